@@ -1,0 +1,167 @@
+"""FP64 CPU oracle for the Eulerian Gaussian beam hot path.
+
+TEST INFRASTRUCTURE ONLY: only ``tests/``, the smoke check and the benchmark's
+CPU-baseline leg may import this package.  It shares no code with the HIP
+library (``paper_2006_11945_amd``) and never imports it.
+
+The arithmetic lives in ``egb_oracle.c`` (plain double-precision loops, built
+with gcc by :func:`build`); this module only marshals numpy arrays.  Plane
+order of the oracle state: phi1, psi, Re C, Im C, Re B, Im B.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "egb_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+PLANES = ("phi1", "psi", "ReC", "ImC", "ReB", "ImB")
+VEL_PLANES = ("Vx", "Vz", "Vt", "A11", "A12", "A21", "A22")
+NFLD, NTAY = 5, 6
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, OpenMP)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+                               "-D_DEFAULT_SOURCE", "-Wall", "-Wno-unused-function",
+                               SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=True)
+        L = ctypes.CDLL(LIB)
+        P = ctypes.POINTER(ctypes.c_double)
+        i, d = ctypes.c_int, ctypes.c_double
+        L.oc_fd1.argtypes = [P, i, i, d]; L.oc_fd1.restype = d
+        L.oc_fd2.argtypes = [P, i, i, d]; L.oc_fd2.restype = d
+        L.oc_medium_table.argtypes = [i, i, d, d, P, P, P, P, d, P]
+        L.oc_vjet.argtypes = [P, d, P]; L.oc_vjet.restype = None
+        L.oc_va.argtypes = [P, d, P, P]; L.oc_va.restype = None
+        L.oc_velocity.argtypes = [i, i, i, d, d, P, P, P, P]
+        L.oc_init_state.argtypes = [i, i, i, d, d, d, d, P, d, d, d, P]
+        L.oc_weno.argtypes = [P, i]; L.oc_weno.restype = d
+        L.oc_march.argtypes = [i, i, i, d, d, d, d, P, d, d, d, P, d, i]
+        L.oc_beam_sum.argtypes = [i, i, i, d, d, d, d, P, P, d, P, P, i, P]
+        L.oc_pick.argtypes = [i, i, i, d, d, d, d, P, P, i, P]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _c(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def fd1(f, i: int, h: float) -> float:
+    f = _c(f)
+    return lib().oc_fd1(_p(f), len(f), i, h)
+
+
+def fd2(f, i: int, h: float) -> float:
+    f = _c(f)
+    return lib().oc_fd2(_p(f), len(f), i, h)
+
+
+def medium_table(grid, medium) -> np.ndarray:
+    """Table [nx][nz][5 fields (a11, a33, b, a55, nu)][6 (f, fx, fz, fxx, fxz, fzz)]."""
+    tab = np.zeros((grid.nx, grid.nz, NFLD, NTAY))
+    rc = lib().oc_medium_table(grid.nx, grid.nz, grid.dx, grid.dz, _p(_c(medium.vp0)), _p(_c(medium.eps)),
+                               _p(_c(medium.delta)), _p(_c(medium.tilt)), float(medium.vs_ratio), _p(tab))
+    if rc != 0:
+        raise ValueError(f"oc_medium_table failed ({rc})")
+    return tab
+
+
+def vjet(t: np.ndarray, theta: float) -> np.ndarray:
+    """Jet of v at one point: v, v_x, v_z, v_t, v_xx, v_xz, v_zz, v_xt, v_zt, v_tt."""
+    t = _c(t).reshape(NFLD * NTAY)
+    o = np.zeros(10)
+    lib().oc_vjet(_p(t), float(theta), _p(o))
+    return o
+
+
+def va(vj: np.ndarray, theta: float):
+    """(V[3], A[4]) from a v-jet."""
+    vj = _c(vj)
+    V, A = np.zeros(3), np.zeros(4)
+    lib().oc_va(_p(vj), float(theta), _p(V), _p(A))
+    return V, A
+
+
+def velocity(grid, tab: np.ndarray):
+    """Returns (vel[7][nth][nx][nz], vaux[4][nth][nx][nz] = v, v_x, v_z, v_t, dt_cfl)."""
+    sh = (grid.nth, grid.nx, grid.nz)
+    vel = np.zeros((7,) + sh)
+    vaux = np.zeros((4,) + sh)
+    dt = np.zeros(1)
+    lib().oc_velocity(grid.nx, grid.nz, grid.nth, grid.dx, grid.dz, _p(_c(tab)), _p(vel), _p(vaux), _p(dt))
+    return vel, vaux, float(dt[0])
+
+
+def init_state(grid, tab: np.ndarray, source) -> np.ndarray:
+    U = np.zeros((6, grid.nth, grid.nx, grid.nz))
+    lib().oc_init_state(grid.nx, grid.nz, grid.nth, grid.x0, grid.z0, grid.dx, grid.dz, _p(_c(tab)),
+                        source.xs, source.zs, source.beta, _p(U))
+    return U
+
+
+def weno(u7, minus: bool) -> float:
+    u7 = _c(u7)
+    return lib().oc_weno(_p(u7), int(bool(minus)))
+
+
+def march(grid, vel: np.ndarray, source, U: np.ndarray, dt: float, nsteps: int) -> np.ndarray:
+    U = _c(U).copy()
+    rc = lib().oc_march(grid.nx, grid.nz, grid.nth, grid.x0, grid.z0, grid.dx, grid.dz, _p(_c(vel)),
+                        source.xs, source.zs, source.r0, _p(U), float(dt), int(nsteps))
+    if rc != 0:
+        raise MemoryError("oc_march")
+    return U
+
+
+def beam_sum(grid, vel, vaux, source, U, omegas) -> np.ndarray:
+    """Complex Green's function [nw][nx][nz]."""
+    om = _c(np.atleast_1d(omegas))
+    out = np.zeros((len(om), grid.nx, grid.nz, 2))
+    rc = lib().oc_beam_sum(grid.nx, grid.nz, grid.nth, grid.x0, grid.z0, grid.dx, grid.dz, _p(_c(vel)),
+                           _p(_c(vaux)), source.beta, _p(_c(U)), _p(om), len(om), _p(out))
+    if rc == -3:
+        raise RuntimeError("oracle beam list overflow")
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def pick(grid, U, receivers) -> np.ndarray:
+    rx = _c(receivers).reshape(-1, 2)
+    out = np.zeros(len(rx))
+    lib().oc_pick(grid.nx, grid.nz, grid.nth, grid.x0, grid.z0, grid.dx, grid.dz, _p(_c(U)), _p(rx),
+                  len(rx), _p(out))
+    return out
+
+
+def solve(problem, nsteps=None):
+    """Full oracle pipeline: table, velocity, data, march.  Returns a dict."""
+    g = problem.grid
+    tab = medium_table(g, problem.medium)
+    vel, vaux, dt = velocity(g, tab)
+    U0 = init_state(g, tab, problem.source)
+    ns = problem.nsteps if nsteps is None else nsteps
+    U = march(g, vel, problem.source, U0, dt, ns) if ns > 0 else U0
+    return {"tab": tab, "vel": vel, "vaux": vaux, "dt": dt, "U0": U0, "U": U, "nsteps": ns}
