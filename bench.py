@@ -1,0 +1,147 @@
+"""Benchmark of the Eulerian Gaussian beam hot path on one MI355X.
+
+One step = one pass of the whole path over the heterogeneous-VTI workload
+(256 x 256 x 256 phase grid, 4 km square, 600 SSP-RK3 steps, beam sum over 32
+frequencies 5-60 Hz, first-arrival pick at 128 receivers), inputs resident
+in HBM:  medium table + velocity/DRT field, point-source data, the march, the
+beam superposition, the pick.
+
+Metric: phase-space cell-updates/s (nx nz nth x RK3 steps / wall time).
+The dominant kernel (the RK3 stage) is timed live with HIP events on the
+launch stream; its roofline entry counts the scheme's floating-point
+operations per cell-stage against the FP32 vector rate.  The oracle (FP64,
+C + OpenMP) is timed on the host on one full-size RK3 step.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Floating-point operations of the scheme per cell and RK stage, counted from
+# its definition (WENO5-JS in Hamilton-Jacobi form on 6 planes x 3 axes,
+# convection, sources, stage combine); see the design notes.
+FLOP_WENO = 80
+FLOP_CELL_STAGE = 18 * FLOP_WENO + 6 * 6 + 3 + 17 + 30
+PEAK_FP32_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 excluded
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256, help="grid size per axis (256 = the quoted workload)")
+    ap.add_argument("--rk-steps", type=int, default=600)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(problem):
+    """Oracle (as it stands) on one full-size RK3 step of the same workload."""
+    import oracle
+
+    oracle.build(force=False)
+    cores = len(os.sched_getaffinity(0))
+    os.environ.setdefault("OMP_NUM_THREADS", str(cores))
+    t0 = time.perf_counter()
+    r = oracle.solve(problem, nsteps=0)
+    t1 = time.perf_counter()
+    oracle.march(problem.grid, r["vel"], problem.source, r["U0"], r["dt"], 1)
+    t2 = time.perf_counter()
+    g = problem.grid
+    return {"value": g.ncell / (t2 - t1), "unit": "cell-updates/s",
+            "cores": int(os.environ.get("OMP_NUM_THREADS", cores)), "kind": "oracle",
+            "sample": f"one SSP-RK3 step of the full {g.nx}x{g.nz}x{g.nth} grid "
+                      f"(FP64; setup {t1 - t0:.1f} s not counted, step {t2 - t1:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is a design "
+              "note, not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2006_11945_amd as egb
+    import workloads as W
+
+    p = W.vti_256(n=args.n, nsteps=args.rk_steps)
+    L = p.grid.nx * p.grid.dx
+    rx = np.stack([np.linspace(0.1 * L, 0.9 * L, 128), np.full(128, 0.9 * L)], axis=1)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    s = egb.Solver(p, dev)
+    s.velocity()
+    dt = s.dt_cfl
+    s.work_beam = egb.alloc_bytes(egb.workspace_size(s.eg, egb.EGB_OP_BEAM), dev)
+    out = torch.empty((len(p.omegas), p.grid.nx, p.grid.nz, 2), dtype=torch.float32, device=dev)
+    rx_d = torch.as_tensor(rx, device=dev)
+    t_pick = torch.empty(128, dtype=torch.float64, device=dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    march_ms = []
+
+    def one_step(timed):
+        s.velocity()
+        s.init()
+        if timed:
+            ev0.record(stream)
+        s.step(p.nsteps, dt=dt)
+        if timed:
+            ev1.record(stream)
+        s.beam(p.omegas, out=out)
+        egb.egb_pick_receivers(s.eg, s.state, rx_d, t_pick)
+        if timed:
+            ev1.synchronize()
+            march_ms.append(ev0.elapsed_time(ev1))
+
+    for _ in range(args.warmup):
+        one_step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    cells = p.grid.ncell
+    value = cells * p.nsteps / (ms * 1e-3)
+    launches = 3 * p.nsteps
+    stage_ms = float(np.mean(march_ms)) / launches
+    achieved = cells * FLOP_CELL_STAGE / (stage_ms * 1e-3) / 1e12
+    res = {
+        "metric": "phase-space cell-updates/s",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"heterogeneous VTI {p.grid.nx}x{p.grid.nz}x{p.grid.nth}, {p.nsteps} RK3 steps, "
+                               f"beam sum {len(p.omegas)} freqs 5-60 Hz, 128 receivers",
+                   "grid": [p.grid.nx, p.grid.nz, p.grid.nth], "rk3_steps": p.nsteps,
+                   "frequencies": len(p.omegas), "receivers": 128, "psi_dtype": "f64"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_stage (one SSP-RK3 stage)", "avg_launch_ms": stage_ms,
+                     "flop_per_cell_stage": FLOP_CELL_STAGE},
+        "march_ms": float(np.mean(march_ms)),
+        "march_cell_updates_per_s": cells * p.nsteps / (float(np.mean(march_ms)) * 1e-3),
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(W.vti_256(n=args.n, nsteps=1))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,161 @@
+/*
+ * egb.h - C ABI of the MI355X Eulerian Gaussian beam library (libegb.so).
+ *
+ * The library marches the stationary phase-space Liouville system of the
+ * anisotropic Eulerian Gaussian beam method (Huang, arXiv 2006.11945) on a
+ * regular (x, z, theta) grid and superposes the beams on the Cartesian grid.
+ *
+ * Conventions for every call:
+ *  - Buffers are caller-owned DEVICE pointers unless marked "host".  The
+ *    library never allocates device memory: scratch space comes from the
+ *    caller, sized by egb_workspace_size().
+ *  - Calls are asynchronous and ordered on `stream` (NULL = default stream)
+ *    unless stated otherwise.
+ *  - Arguments are validated on the host before anything is launched; on an
+ *    error nothing is launched and an egb_status < 0 is returned.  No C++
+ *    exception crosses this interface.
+ *  - Device pointers must be 16-byte aligned.
+ *  - x is horizontal, z is depth (positive down); theta is the phase angle
+ *    measured from +z toward +x, so the slowness is p = (sin, cos)(theta)/v
+ *    (eq. 7).  Cell (i, j, k) sits at x = x0 + (i+1/2) dx, z = z0 + (j+1/2) dz,
+ *    theta = k * 2 pi / nth.  Phase-space planes are stored [theta][x][z],
+ *    z fastest, each plane padded to egb_plane_stride() elements.
+ */
+#ifndef EGB_H
+#define EGB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EGB_OK = 0,
+    EGB_EINVAL = -1,        /* bad argument: null, size, alignment, dtype, range */
+    EGB_ECFL = -2,          /* dt not positive and finite */
+    EGB_EWORKSPACE = -3,    /* workspace too small, or a beam list overflowed it */
+    EGB_EHIP = -4,          /* a HIP launch or runtime call failed */
+    EGB_ENONFINITE = -5,    /* a non-finite value was produced */
+    EGB_EUNSUPPORTED = -6   /* valid request this build does not implement */
+} egb_status;
+
+/* Arithmetic type of the phase-space planes.  EGB_F32: five planes in float,
+ * traveltime psi in double (FP64 traveltime accumulation); EGB_F64: all
+ * planes in double. */
+typedef enum { EGB_F32 = 0, EGB_F64 = 1 } egb_dtype;
+
+/* State planes (order in memory).  phi1: ray-family level set, the signed
+ * miss distance of the ray from the source (X - x_s of eqs. 19-20, 35);
+ * (C, B): complex dynamic ray tracing pair of eq. 21 in the ray-normal frame;
+ * psi: traveltime (tau of eq. 19). */
+enum { EGB_PHI1 = 0, EGB_RE_C = 1, EGB_IM_C = 2, EGB_RE_B = 3, EGB_IM_B = 4, EGB_PSI = 5, EGB_NSTATE = 6 };
+
+/* Velocity planes (order in memory): the Liouville velocity V = (dx/dtau,
+ * dz/dtau, dtheta/dtau) of eqs. 8, 9, 12 and the 2x2 ray-normal dynamic ray
+ * tracing matrix A (row major), all in the grid dtype. */
+enum { EGB_VX = 0, EGB_VZ = 1, EGB_VT = 2, EGB_A11 = 3, EGB_A12 = 4, EGB_A21 = 5, EGB_A22 = 6, EGB_NVEL = 7 };
+
+/* Medium table (coeff2d): float64 [EGB_NFIELD][EGB_NTAYLOR][nx][nz]; fields
+ * a11, a33, b = a13 + a55, a55 (density-normalised moduli, eq. 5) and tilt nu;
+ * Taylor slots f, f_x, f_z, f_xx, f_xz, f_zz (4th-order differences). */
+enum { EGB_NFIELD = 5, EGB_NTAYLOR = 6 };
+
+/* Workspace queries (egb_workspace_size op argument). */
+enum { EGB_OP_VELOCITY = 0, EGB_OP_STEP = 1, EGB_OP_BEAM = 2, EGB_OP_ADJOINT = 3 };
+
+typedef struct {
+    int32_t nx, nz, nth; /* cells in x, z (>= 8) and theta (>= 8) */
+    int32_t dtype;       /* egb_dtype */
+    double x0, z0;       /* domain origin (m) */
+    double dx, dz;       /* cell size (m), > 0 */
+} egb_grid;
+
+/* Thomsen-parameter medium, device float64 arrays [nx][nz]; tilt may be NULL
+ * (VTI).  vs_ratio = vs0/vp0 fixes a55 (0 <= vs_ratio < 1). */
+typedef struct {
+    const double *vp0, *eps, *delta, *tilt;
+    double vs_ratio;
+} egb_medium;
+
+/* Point source at (xs, zs); r0 is the radius of the source ball whose cells
+ * hold the point-source data; beta > 0 the initial beam parameter
+ * (B(0) = i beta C(0), eq. 24). */
+typedef struct {
+    double xs, zs, r0, beta;
+} egb_source;
+
+/* ------------------------------------------------------------------ sizes */
+size_t egb_plane_stride(const egb_grid *g);         /* elements per plane */
+size_t egb_coeff2d_bytes(const egb_grid *g);
+size_t egb_vel3d_bytes(const egb_grid *g);
+size_t egb_state_bytes(const egb_grid *g);
+size_t egb_state_plane_offset(const egb_grid *g, int32_t plane); /* bytes */
+size_t egb_workspace_size(const egb_grid *g, int32_t op);        /* bytes; 0 on bad args */
+
+/* ------------------------------------------------------------------ calls */
+
+/* Medium -> Christoffel table -> Liouville velocity and DRT matrix.
+ * Paper: eqs. 3-5 (qP eigenvalue of Gamma_ik = a_ijkl p_j p_l with
+ * a = c/rho), eqs. 8-9 (dx/dtau, dz/dtau = grad_p G / 2, the group
+ * velocity), eq. 12 (dtheta/dtau, Hamiltonian sign), eq. 21 (the linearised
+ * flow, in the ray-normal frame).
+ * In:  g, m (device float64 [nx][nz] each).
+ * Out: coeff2d (egb_coeff2d_bytes), vel3d (egb_vel3d_bytes, grid dtype),
+ *      *dt_cfl (host) = 0.5 / max(|V_x|/dx + |V_z|/dz + |V_theta|/dtheta).
+ * work: egb_workspace_size(g, EGB_OP_VELOCITY) bytes.
+ * Synchronises `stream` once (to return dt_cfl).  EGB_ENONFINITE if the
+ * medium yields a non-finite velocity. */
+egb_status egb_hamiltonian_velocity(const egb_grid *g, const egb_medium *m, void *coeff2d, void *vel3d,
+                                    double *dt_cfl, void *work, size_t work_bytes, hipStream_t stream);
+
+/* Point-source data (eqs. 20 and 24 read for a point source): with the medium
+ * frozen at the source (bilinear in coeff2d), every cell gets
+ * phi1 = (x - xs).g_perp(theta), psi = p(theta).(x - xs),
+ * C = s (1 + i beta A12 psi), B = i beta s, s = (sqrt(v)/W)^(2/3),
+ * W = a33/v^2 (the beam weight of eqs. 31-33 redone in 2D).
+ * Out: state (egb_state_bytes). */
+egb_status egb_init_state(const egb_grid *g, const void *coeff2d, const egb_source *src, void *state,
+                          hipStream_t stream);
+
+/* nsteps SSP-RK3 pseudo-time steps of U_t + V.grad U = S(U) (eqs. 16, 19, 21
+ * multiplied by dz/dtau): WENO5 Hamilton-Jacobi upwind derivatives, sources
+ * S_psi = 1, S_(C,B) = A (C, B); ghosts: x, z linear extrapolation, theta
+ * periodic; cells within r0 of the source keep their values (Dirichlet data).
+ * In/out: state.  vel3d from egb_hamiltonian_velocity.
+ * work: egb_workspace_size(g, EGB_OP_STEP) bytes (two RK stage buffers).
+ * dt must be positive and finite (EGB_ECFL otherwise); stability needs
+ * dt <= dt_cfl. */
+egb_status egb_liouville_step(const egb_grid *g, const void *vel3d, const egb_source *src, void *state,
+                              void *work, size_t work_bytes, double dt, int32_t nsteps, hipStream_t stream);
+
+/* Eulerian Gaussian beam superposition (eqs. 25-27, 33-35).  For every
+ * output cell (x0, z0) and frequency omega:
+ *   G = (i/4pi) [ sum_row w A dtheta exp(i omega T) + sum_col (1-w) A dtheta exp(i omega T) ]
+ * over the phase cells of the same row / column on Gamma = {phi1 = 0, psi > 0}
+ * (smoothed delta of width 2 dx), T = psi + p1 (x0 - x) + M (x0 - x)^2 / 2.
+ * In: omegas (HOST float64 [nw], rad/s).  Out: out, complex [nw][nx][nz]
+ * interleaved (re, im) in the grid dtype (complex64 / complex128).
+ * work: egb_workspace_size(g, EGB_OP_BEAM).  Synchronises `stream` once;
+ * EGB_EWORKSPACE if a per-row/column beam list overflowed. */
+egb_status egb_beam_sum(const egb_grid *g, const void *coeff2d, const void *vel3d, const egb_source *src,
+                        const void *state, const double *omegas, int32_t nw, void *out, void *work,
+                        size_t work_bytes, hipStream_t stream);
+
+/* First-arrival traveltime at receivers on the level set phi1 = 0 (eq. 35):
+ * bilinear in (x, z) per theta plane, linear root of phi1 in theta, the
+ * smallest interpolated psi > 0 (lowest theta on ties); NaN if no arrival.
+ * In: rx (device float64 [nr][2] = x, z).  Out: t_out (device float64 [nr]). */
+egb_status egb_pick_receivers(const egb_grid *g, const void *state, const double *rx, int32_t nr, double *t_out,
+                              hipStream_t stream);
+
+/* Human-readable text for a status code (static storage). */
+const char *egb_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EGB_H */

@@ -1,0 +1,261 @@
+"""Python binding of libegb, the MI355X Eulerian Gaussian beam library.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C ABI declared in ``include/egb.h``.  PyTorch supplies device
+memory and streams.  Importing this package fails loudly when ``libegb.so``
+has not been built; there is no CPU fallback.
+
+The functions named ``egb_*`` mirror the C entry points one to one.  The
+``Solver`` helper strings them together for one source: medium table and
+velocity, point-source data, the march, the beam sum and the receiver pick.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libegb.so")
+
+EGB_OK, EGB_EINVAL, EGB_ECFL, EGB_EWORKSPACE, EGB_EHIP, EGB_ENONFINITE, EGB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+EGB_F32, EGB_F64 = 0, 1
+EGB_PHI1, EGB_RE_C, EGB_IM_C, EGB_RE_B, EGB_IM_B, EGB_PSI = range(6)
+EGB_OP_VELOCITY, EGB_OP_STEP, EGB_OP_BEAM, EGB_OP_ADJOINT = range(4)
+STATE_PLANES = ("phi1", "ReC", "ImC", "ReB", "ImB", "psi")
+VEL_PLANES = ("Vx", "Vz", "Vt", "A11", "A12", "A21", "A22")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2006_11945_amd/build.py` "
+                      "(or __graft_entry__.build()); there is no CPU fallback")
+
+
+class EgbGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nz", ctypes.c_int32), ("nth", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("x0", ctypes.c_double), ("z0", ctypes.c_double), ("dx", ctypes.c_double), ("dz", ctypes.c_double)]
+
+
+class EgbMedium(ctypes.Structure):
+    _fields_ = [("vp0", ctypes.c_void_p), ("eps", ctypes.c_void_p), ("delta", ctypes.c_void_p),
+                ("tilt", ctypes.c_void_p), ("vs_ratio", ctypes.c_double)]
+
+
+class EgbSource(ctypes.Structure):
+    _fields_ = [("xs", ctypes.c_double), ("zs", ctypes.c_double), ("r0", ctypes.c_double), ("beta", ctypes.c_double)]
+
+
+class EgbError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__(f"{fn} failed: {status} ({_lib.egb_status_string(status).decode()})")
+        self.status = status
+
+
+def _load():
+    L = ctypes.CDLL(LIB_PATH)
+    G, M, S = ctypes.POINTER(EgbGrid), ctypes.POINTER(EgbMedium), ctypes.POINTER(EgbSource)
+    vp, sz, i32, d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double
+    dp = ctypes.POINTER(ctypes.c_double)
+    for name in ("egb_plane_stride", "egb_coeff2d_bytes", "egb_vel3d_bytes", "egb_state_bytes"):
+        getattr(L, name).argtypes = [G]
+        getattr(L, name).restype = sz
+    L.egb_state_plane_offset.argtypes = [G, i32]; L.egb_state_plane_offset.restype = sz
+    L.egb_workspace_size.argtypes = [G, i32]; L.egb_workspace_size.restype = sz
+    L.egb_hamiltonian_velocity.argtypes = [G, M, vp, vp, dp, vp, sz, vp]
+    L.egb_init_state.argtypes = [G, vp, S, vp, vp]
+    L.egb_liouville_step.argtypes = [G, vp, S, vp, vp, sz, d, i32, vp]
+    L.egb_beam_sum.argtypes = [G, vp, vp, S, vp, dp, i32, vp, vp, sz, vp]
+    L.egb_pick_receivers.argtypes = [G, vp, vp, i32, vp, vp]
+    for name in ("egb_hamiltonian_velocity", "egb_init_state", "egb_liouville_step", "egb_beam_sum",
+                 "egb_pick_receivers"):
+        getattr(L, name).restype = ctypes.c_int
+    L.egb_status_string.argtypes = [i32]; L.egb_status_string.restype = ctypes.c_char_p
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(fn: str, rc: int):
+    if rc != EGB_OK:
+        raise EgbError(fn, rc)
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ structs
+def make_grid(g, dtype: str = "f32") -> EgbGrid:
+    """egb_grid from a workloads.Grid-like object (nx, nz, nth, x0, z0, dx, dz)."""
+    return EgbGrid(g.nx, g.nz, g.nth, EGB_F64 if dtype == "f64" else EGB_F32, g.x0, g.z0, g.dx, g.dz)
+
+
+def make_source(s) -> EgbSource:
+    return EgbSource(s.xs, s.zs, s.r0, s.beta)
+
+
+def real_dtype(eg: EgbGrid):
+    return torch.float64 if eg.dtype == EGB_F64 else torch.float32
+
+
+# ------------------------------------------------------------------ sizes
+def plane_stride(eg) -> int: return _lib.egb_plane_stride(ctypes.byref(eg))
+def coeff2d_bytes(eg) -> int: return _lib.egb_coeff2d_bytes(ctypes.byref(eg))
+def vel3d_bytes(eg) -> int: return _lib.egb_vel3d_bytes(ctypes.byref(eg))
+def state_bytes(eg) -> int: return _lib.egb_state_bytes(ctypes.byref(eg))
+def state_plane_offset(eg, p: int) -> int: return _lib.egb_state_plane_offset(ctypes.byref(eg), p)
+def workspace_size(eg, op: int) -> int: return _lib.egb_workspace_size(ctypes.byref(eg), op)
+
+
+def alloc_bytes(n: int, device) -> torch.Tensor:
+    return torch.empty(max(int(n), 16), dtype=torch.uint8, device=device)
+
+
+# ------------------------------------------------------------------ calls
+def egb_hamiltonian_velocity(eg, medium: "DeviceMedium", coeff2d, vel3d, work, stream=None) -> float:
+    dt = ctypes.c_double(0.0)
+    rc = _lib.egb_hamiltonian_velocity(ctypes.byref(eg), ctypes.byref(medium.struct()), _ptr(coeff2d), _ptr(vel3d),
+                                       ctypes.byref(dt), _ptr(work), work.numel(), _stream(stream))
+    _check("egb_hamiltonian_velocity", rc)
+    return dt.value
+
+
+def egb_init_state(eg, coeff2d, src: EgbSource, state, stream=None):
+    _check("egb_init_state", _lib.egb_init_state(ctypes.byref(eg), _ptr(coeff2d), ctypes.byref(src), _ptr(state),
+                                                 _stream(stream)))
+
+
+def egb_liouville_step(eg, vel3d, src: EgbSource, state, work, dt: float, nsteps: int, stream=None):
+    rc = _lib.egb_liouville_step(ctypes.byref(eg), _ptr(vel3d), ctypes.byref(src), _ptr(state), _ptr(work),
+                                 0 if work is None else work.numel(), float(dt), int(nsteps), _stream(stream))
+    _check("egb_liouville_step", rc)
+
+
+def egb_beam_sum(eg, coeff2d, vel3d, src: EgbSource, state, omegas, out, work, stream=None):
+    om = np.ascontiguousarray(np.atleast_1d(np.asarray(omegas, dtype=np.float64)))
+    rc = _lib.egb_beam_sum(ctypes.byref(eg), _ptr(coeff2d), _ptr(vel3d), ctypes.byref(src), _ptr(state),
+                           om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(om), _ptr(out), _ptr(work),
+                           work.numel(), _stream(stream))
+    _check("egb_beam_sum", rc)
+
+
+def egb_pick_receivers(eg, state, rx, t_out, stream=None):
+    n = 0 if rx is None else rx.shape[0]
+    rc = _lib.egb_pick_receivers(ctypes.byref(eg), _ptr(state), _ptr(rx), n, _ptr(t_out), _stream(stream))
+    _check("egb_pick_receivers", rc)
+
+
+# ------------------------------------------------------------------ views
+def state_views(eg, state: torch.Tensor) -> dict:
+    """Named [nth][nx][nz] views of the planes of a state byte buffer."""
+    n = eg.nth * eg.nx * eg.nz
+    out = {}
+    for p, name in enumerate(STATE_PLANES):
+        dt = torch.float64 if p == EGB_PSI else real_dtype(eg)
+        off = state_plane_offset(eg, p)
+        es = torch.empty((), dtype=dt).element_size()
+        out[name] = state[off:off + n * es].view(dt).view(eg.nth, eg.nx, eg.nz)
+    return out
+
+
+def vel_views(eg, vel3d: torch.Tensor) -> dict:
+    n = eg.nth * eg.nx * eg.nz
+    dt = real_dtype(eg)
+    flat = vel3d.view(dt)
+    st = plane_stride(eg)
+    return {name: flat[q * st:q * st + n].view(eg.nth, eg.nx, eg.nz) for q, name in enumerate(VEL_PLANES)}
+
+
+def coeff2d_view(eg, coeff2d: torch.Tensor) -> torch.Tensor:
+    """[field][taylor][nx][nz] float64 view."""
+    return coeff2d.view(torch.float64).view(5, 6, eg.nx, eg.nz)
+
+
+def write_state(eg, state: torch.Tensor, planes: dict):
+    """Copy named host/device arrays into a state buffer (marshalling for tests)."""
+    v = state_views(eg, state)
+    for name, arr in planes.items():
+        v[name].copy_(torch.as_tensor(np.asarray(arr)).to(v[name].dtype))
+
+
+@dataclass
+class DeviceMedium:
+    vp0: torch.Tensor
+    eps: torch.Tensor
+    delta: torch.Tensor
+    tilt: Optional[torch.Tensor]
+    vs_ratio: float
+
+    @staticmethod
+    def from_numpy(m, device) -> "DeviceMedium":
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+        return DeviceMedium(f(m.vp0), f(m.eps), f(m.delta), None if m.tilt is None else f(m.tilt), float(m.vs_ratio))
+
+    def struct(self) -> EgbMedium:
+        return EgbMedium(self.vp0.data_ptr(), self.eps.data_ptr(), self.delta.data_ptr(),
+                         None if self.tilt is None else self.tilt.data_ptr(), self.vs_ratio)
+
+
+class Solver:
+    """Buffers and call sequence for one problem (one source) on one device."""
+
+    def __init__(self, problem, device="cuda", dtype: Optional[str] = None):
+        self.p = problem
+        self.device = torch.device(device)
+        self.eg = make_grid(problem.grid, dtype or problem.dtype)
+        self.src = make_source(problem.source)
+        self.medium = DeviceMedium.from_numpy(problem.medium, self.device)
+        eg = self.eg
+        self.coeff2d = alloc_bytes(coeff2d_bytes(eg), self.device)
+        self.vel3d = alloc_bytes(vel3d_bytes(eg), self.device)
+        self.state = alloc_bytes(state_bytes(eg), self.device)
+        self.work_vel = alloc_bytes(workspace_size(eg, EGB_OP_VELOCITY), self.device)
+        self.work_step = alloc_bytes(workspace_size(eg, EGB_OP_STEP), self.device)
+        self.work_beam = None
+        self.dt_cfl = None
+
+    def velocity(self, stream=None) -> float:
+        self.dt_cfl = egb_hamiltonian_velocity(self.eg, self.medium, self.coeff2d, self.vel3d, self.work_vel, stream)
+        return self.dt_cfl
+
+    def init(self, stream=None):
+        egb_init_state(self.eg, self.coeff2d, self.src, self.state, stream)
+
+    def step(self, nsteps: int, dt: Optional[float] = None, stream=None):
+        egb_liouville_step(self.eg, self.vel3d, self.src, self.state, self.work_step,
+                           self.dt_cfl if dt is None else dt, nsteps, stream)
+
+    def beam(self, omegas, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        om = np.atleast_1d(np.asarray(omegas, dtype=np.float64))
+        if self.work_beam is None:
+            self.work_beam = alloc_bytes(workspace_size(self.eg, EGB_OP_BEAM), self.device)
+        if out is None:
+            out = torch.empty((len(om), self.eg.nx, self.eg.nz, 2), dtype=real_dtype(self.eg), device=self.device)
+        egb_beam_sum(self.eg, self.coeff2d, self.vel3d, self.src, self.state, om, out, self.work_beam, stream)
+        return out
+
+    def pick(self, receivers, stream=None) -> torch.Tensor:
+        rx = torch.as_tensor(np.ascontiguousarray(receivers, dtype=np.float64), device=self.device).reshape(-1, 2)
+        t = torch.empty(rx.shape[0], dtype=torch.float64, device=self.device)
+        egb_pick_receivers(self.eg, self.state, rx, t, stream)
+        return t
+
+    def planes(self) -> dict:
+        return state_views(self.eg, self.state)
+
+    def vel_planes(self) -> dict:
+        return vel_views(self.eg, self.vel3d)

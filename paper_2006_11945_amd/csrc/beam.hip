@@ -1,0 +1,269 @@
+// Eulerian Gaussian beam superposition (eqs. 25-27, 33-35).
+//
+// Pass 1 (k_beam_compact): every phase cell on (near) Gamma = {phi1 = 0,
+// psi > 0} becomes one beam record in the list of its row (z = const) and of
+// its column (x = const).  The take-off-angle measure comes from a smoothed
+// delta of the signed distance d = phi1 / |grad phi1| (theta scaled by
+// lambda = dx / dtheta, width h = 2 dx) and from the imaginary DRT part
+// Im(C, B) = beta s (dn, dth_perp) per unit take-off angle.  Each record holds
+//   pos (x or z of the cell), psi, p (p1 or p3), M (traveltime Hessian along
+//   the line, complex) and amp = w sqrt(v / C) dtheta (complex),
+// w = cos^4 / (cos^4 + sin^4) of the ray angle for rows and 1 - w for columns.
+// Pass 2 (k_beam_line): for every output cell and frequency,
+//   G += amp exp(i omega T),  T = psi + p d + M d^2 / 2,
+// skipping beams with omega Im(M) d^2 / 2 > 16, and G is scaled by i/(4 pi).
+// A wavefront owns one row (or column) and walks its record list with
+// uniform loads; lanes span the output cells of that line.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "egb_device.h"
+#include "egb_internal.h"
+
+namespace egb {
+
+struct BeamRec {
+    double psi, pos, p, Mre, Mim, are, aim, pad;
+};
+
+size_t beam_record_bytes() { return sizeof(BeamRec); }
+
+namespace {
+
+__device__ __forceinline__ long long cidx2(const GridArgs& a, int f, int t, int ix, int iz) {
+    return ((long long)(f * NT + t)) * a.nxz + (long long)ix * a.nz + iz;
+}
+
+template <typename T>
+__device__ __forceinline__ double line_at(const T* base, long long st, int n, int idx) {
+    if (idx < 0) return (1.0 - idx) * (double)base[0] + (double)idx * (double)base[st];
+    if (idx > n - 1) {
+        const int e = idx - (n - 1);
+        return (e + 1.0) * (double)base[(long long)(n - 1) * st] - (double)e * (double)base[(long long)(n - 2) * st];
+    }
+    return (double)base[(long long)idx * st];
+}
+
+// 4th-order central difference of a line (ghosts as in the march)
+template <typename T>
+__device__ __forceinline__ double cd4(const T* base, long long st, int n, int i, double h) {
+    return (line_at(base, st, n, i - 2) - 8.0 * line_at(base, st, n, i - 1) + 8.0 * line_at(base, st, n, i + 1) -
+            line_at(base, st, n, i + 2)) /
+           (12.0 * h);
+}
+
+__device__ __forceinline__ double delta_h(double d, double h) {
+    return fabs(d) < h ? (1.0 + cos(M_PI * d / h)) / (2.0 * h) : 0.0;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_beam_compact(BeamArgs a) {
+    const GridArgs& g = a.g;
+    const int iz = blockIdx.x * 64 + threadIdx.x, ix = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+    if (iz >= g.nz || ix >= g.nx) return;
+    const long long S = g.stride, kb = (long long)k * g.nxz, c = kb + (long long)ix * g.nz + iz;
+    const R* U = reinterpret_cast<const R*>(a.U);
+    const double psi = reinterpret_cast<const double*>(U + 5 * S)[c];
+    if (!(psi > 0.0)) return;
+    const R* phi = U + EGB_PHI1 * S;
+    const double fx = cd4(phi + kb + iz, g.nz, g.nx, ix, g.dx);
+    const double fz = cd4(phi + kb + (long long)ix * g.nz, 1, g.nz, iz, g.dz);
+    double ft;
+    {
+        const R* col = phi + (long long)ix * g.nz + iz;
+        auto at = [&](int m) {
+            int kk = k + m;
+            kk += kk < 0 ? g.nth : 0;
+            kk -= kk >= g.nth ? g.nth : 0;
+            return (double)col[(long long)kk * g.nxz];
+        };
+        ft = (at(-2) - 8.0 * at(-1) + 8.0 * at(1) - at(2)) / (12.0 * g.dth);
+    }
+    const double f0 = (double)phi[c];
+    const double lx = g.dx / g.dth, lz = g.dz / g.dth, hx = 2.0 * g.dx, hz = 2.0 * g.dz;
+    const double drow = f0 / sqrt(fx * fx + (ft / lx) * (ft / lx));
+    const double dcol = f0 / sqrt(fz * fz + (ft / lz) * (ft / lz));
+    const bool arow = fabs(drow) < hx, acol = fabs(dcol) < hz;
+    if (!arow && !acol) return;
+
+    // local Hamiltonian (first derivatives of v are all that is needed)
+    MediumPoint M;
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) M.m[f][t] = a.coeff2d[cidx2(g, f, t, ix, iz)];
+    const double th = k * g.dth;
+    const VJet J = qp_velocity(M, th);
+    const VelA va = velocity_and_drt(J, th);
+    double sn, cs;
+    sincos_d(th, &sn, &cs);
+    const double v = J.v, vx = J.g[0], vz = J.g[1], vt = J.g[2];
+    const double Vt = va.V[2];
+    const double sp = sqrt(va.V[0] * va.V[0] + va.V[1] * va.V[1]);
+    const double hxr = va.V[0] / sp, hzr = va.V[1] / sp;  // ray direction (sin, cos of its angle)
+    const double ex = hzr, ez = -hxr;                     // ray normal
+    const double reC = (double)U[EGB_RE_C * S + c], imC = (double)U[EGB_IM_C * S + c];
+    const double reB = (double)U[EGB_RE_B * S + c], imB = (double)U[EGB_IM_B * S + c];
+    // Hessian of the beam traveltime in the ray frame:
+    //   across the ray  Mn = [(e.p_theta) B + (e^T d_x p e) C] / C,
+    //   mixed / along    from q = (dp/dtau)/|V| = -grad v / (v |V|).
+    const double e_pth = ex * (cs / v - sn * vt / (v * v)) + ez * (-sn / v - cs * vt / (v * v));
+    const double e_dxp_e = -(ex * sn + ez * cs) * (vx * ex + vz * ez) / (v * v);
+    const double qx = -vx / (v * sp), qz = -vz / (v * sp);
+    const double gq = hxr * qx + hzr * qz, eq = ex * qx + ez * qz;
+    // Mn = (e_pth * B) / C + e_dxp_e
+    const double den = reC * reC + imC * imC;
+    const double BCre = (reB * reC + imB * imC) / den, BCim = (imB * reC - reB * imC) / den;
+    const double Mnre = e_pth * BCre + e_dxp_e, Mnim = e_pth * BCim;
+    // sqrt(v / C), principal branch
+    const double vCre = v * reC / den, vCim = -v * imC / den;
+    const double mod = sqrt(vCre * vCre + vCim * vCim);
+    double sqre = sqrt(0.5 * (mod + vCre));
+    double sqim = sqrt(0.5 * fmax(mod - vCre, 0.0));
+    sqim = vCim < 0.0 ? -sqim : sqim;
+    const double c4 = hzr * hzr * hzr * hzr, s4 = hxr * hxr * hxr * hxr, wrow = c4 / (c4 + s4);
+    const double dn = imC, dtp = imB;
+    BeamRec* rows = reinterpret_cast<BeamRec*>(a.rows);
+    BeamRec* cols = reinterpret_cast<BeamRec*>(a.cols);
+    if (arow && fabs(hzr) > 1e-4) {
+        const double ds = dn * hxr / hzr, px = dn / hzr, pt = dtp + ds * Vt / sp;
+        const double dthc = a.beta * delta_h(drow, hx) * lx * g.dx * g.dth / sqrt(px * px + lx * lx * pt * pt);
+        const double w = wrow * dthc;
+        BeamRec r;
+        r.psi = psi;
+        r.pos = g.x0 + (ix + 0.5) * g.dx;
+        r.p = sn / v;
+        r.Mre = Mnre * hzr * hzr + 2.0 * eq * hxr * hzr + gq * hxr * hxr;
+        r.Mim = Mnim * hzr * hzr;
+        r.are = w * sqre;
+        r.aim = w * sqim;
+        r.pad = 0.0;
+        const int slot = atomicAdd(&a.counts[iz], 1);
+        if (slot < a.cap) rows[(long long)iz * a.cap + slot] = r;
+    }
+    if (acol && fabs(hxr) > 1e-4) {
+        const double ds = -dn * hzr / hxr, pz = -dn / hxr, pt = dtp + ds * Vt / sp;
+        const double dthc = a.beta * delta_h(dcol, hz) * lz * g.dz * g.dth / sqrt(pz * pz + lz * lz * pt * pt);
+        const double w = (1.0 - wrow) * dthc;
+        BeamRec r;
+        r.psi = psi;
+        r.pos = g.z0 + (iz + 0.5) * g.dz;
+        r.p = cs / v;
+        r.Mre = Mnre * hxr * hxr - 2.0 * eq * hxr * hzr + gq * hzr * hzr;
+        r.Mim = Mnim * hxr * hxr;
+        r.are = w * sqre;
+        r.aim = w * sqim;
+        r.pad = 0.0;
+        const int slot = atomicAdd(&a.counts[g.nz + ix], 1);
+        if (slot < a.cap) cols[(long long)ix * a.cap + slot] = r;
+    }
+}
+
+constexpr int WCHUNK = 16;
+struct Omegas {
+    double w[WCHUNK];
+    int n, first;
+};
+
+// Sum over one row (ROW) or column list for a chunk of frequencies.
+// block: 64 lanes = 64 consecutive output cells along the line; grid.x: chunks
+// along the line, grid.y: the line index.
+template <typename R, bool ROW>
+__global__ __launch_bounds__(64) void k_beam_line(BeamArgs a, Omegas om, R* out) {
+    const GridArgs& g = a.g;
+    const int line = blockIdx.y;
+    const int j = blockIdx.x * 64 + threadIdx.x;  // position along the line
+    const int nalong = ROW ? g.nx : g.nz;
+    const bool valid = j < nalong;
+    const double pos = ROW ? g.x0 + (j + 0.5) * g.dx : g.z0 + (j + 0.5) * g.dz;
+    const int cnt = min(a.counts[ROW ? line : g.nz + line], a.cap);
+    const BeamRec* recs = reinterpret_cast<const BeamRec*>(ROW ? a.rows : a.cols) + (long long)line * a.cap;
+    R gre[WCHUNK], gim[WCHUNK];
+#pragma unroll
+    for (int w = 0; w < WCHUNK; ++w) gre[w] = gim[w] = (R)0;
+    const double two_pi = 6.283185307179586476925286766559, inv_two_pi = 1.0 / two_pi;
+    for (int r = 0; r < cnt; ++r) {
+        const BeamRec b = recs[r];
+        const double d = pos - b.pos;
+        const double Tre = b.psi + b.p * d + 0.5 * b.Mre * d * d;
+        const double Tim = 0.5 * b.Mim * d * d;
+#pragma unroll
+        for (int w = 0; w < WCHUNK; ++w) {
+            if (w < om.n) {
+                const double o = om.w[w];
+                const double decay = o * Tim;
+                if (decay <= 16.0) {
+                    // exp(i o T) = exp(-o Im T) (cos + i sin)(o Re T); phase reduced mod 2 pi in double
+                    const double ph = o * Tre;
+                    const double red = ph - two_pi * rint(ph * inv_two_pi);
+                    R sph, cph;
+                    if constexpr (sizeof(R) == 4) {
+                        sincosf((float)red, &sph, &cph);
+                        const R mag = __expf(-(float)decay);
+                        const R er = mag * cph, ei = mag * sph;
+                        gre[w] += (R)b.are * er - (R)b.aim * ei;
+                        gim[w] += (R)b.are * ei + (R)b.aim * er;
+                    } else {
+                        sincos(red, &sph, &cph);
+                        const R mag = exp(-decay);
+                        const R er = mag * cph, ei = mag * sph;
+                        gre[w] += b.are * er - b.aim * ei;
+                        gim[w] += b.are * ei + b.aim * er;
+                    }
+                }
+            }
+        }
+    }
+    if (!valid) return;
+    const int ix = ROW ? j : line, iz = ROW ? line : j;
+    // W = i / (4 pi): (gre + i gim) * i / (4 pi) = (-gim + i gre) / (4 pi)
+    const R s = (R)(1.0 / (4.0 * M_PI));
+    for (int w = 0; w < om.n; ++w) {
+        const long long o = (((long long)(om.first + w) * g.nx + ix) * g.nz + iz) * 2;
+        if (ROW) {
+            out[o] = -gim[w] * s;
+            out[o + 1] = gre[w] * s;
+        } else {
+            out[o] += -gim[w] * s;
+            out[o + 1] += gre[w] * s;
+        }
+    }
+}
+
+__global__ void k_fill_i32(int* p, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+}  // namespace
+
+hipError_t launch_beam_compact(const BeamArgs& a, int dtype, hipStream_t s) {
+    const int nl = a.g.nz + a.g.nx;
+    k_fill_i32<<<(nl + 255) / 256, 256, 0, s>>>(a.counts, nl);
+    const dim3 grid((a.g.nz + 63) / 64, (a.g.nx + 3) / 4, a.g.nth), block(64, 4);
+    if (dtype == EGB_F64)
+        k_beam_compact<double><<<grid, block, 0, s>>>(a);
+    else
+        k_beam_compact<float><<<grid, block, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_beam_sum(const BeamArgs& a, int dtype, const double* omegas, int nw, void* out, hipStream_t s) {
+    for (int w0 = 0; w0 < nw; w0 += WCHUNK) {
+        Omegas om;
+        om.n = nw - w0 < WCHUNK ? nw - w0 : WCHUNK;
+        om.first = w0;
+        for (int w = 0; w < WCHUNK; ++w) om.w[w] = w < om.n ? omegas[w0 + w] : 0.0;
+        const dim3 grow((a.g.nx + 63) / 64, a.g.nz), gcol((a.g.nz + 63) / 64, a.g.nx);
+        if (dtype == EGB_F64) {
+            k_beam_line<double, true><<<grow, 64, 0, s>>>(a, om, (double*)out);
+            k_beam_line<double, false><<<gcol, 64, 0, s>>>(a, om, (double*)out);
+        } else {
+            k_beam_line<float, true><<<grow, 64, 0, s>>>(a, om, (float*)out);
+            k_beam_line<float, false><<<gcol, 64, 0, s>>>(a, om, (float*)out);
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace egb

@@ -1,0 +1,196 @@
+// C ABI of libegb: argument validation, workspace carving, launch order.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "egb_internal.h"
+
+using namespace egb;
+
+namespace {
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+bool grid_ok(const egb_grid* g) {
+    if (!g) return false;
+    if (g->nx < 8 || g->nz < 8 || g->nth < 8) return false;
+    if (g->dtype != EGB_F32 && g->dtype != EGB_F64) return false;
+    if (!(g->dx > 0.0) || !(g->dz > 0.0) || !isfinite(g->dx) || !isfinite(g->dz)) return false;
+    if (!isfinite(g->x0) || !isfinite(g->z0)) return false;
+    // keep every plane index below 2^62 bytes and per-axis products in range
+    const double n = (double)g->nx * (double)g->nz * (double)g->nth;
+    return n < 4.0e12;
+}
+
+bool source_ok(const egb_source* s) {
+    return s && isfinite(s->xs) && isfinite(s->zs) && isfinite(s->r0) && s->r0 >= 0.0 && isfinite(s->beta) &&
+           s->beta > 0.0;
+}
+
+egb_status hip_status(hipError_t e) { return e == hipSuccess ? EGB_OK : EGB_EHIP; }
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Default beam-list capacity per row / column.
+int beam_cap_default(const egb_grid& g) { return 16 * ((g.nx > g.nz ? g.nx : g.nz) + g.nth) + 64; }
+
+size_t beam_counts_bytes(const egb_grid& g) { return align256((size_t)(g.nx + g.nz) * sizeof(int)); }
+
+}  // namespace
+
+extern "C" {
+
+size_t egb_plane_stride(const egb_grid* g) { return grid_ok(g) ? plane_stride(*g) : 0; }
+
+size_t egb_coeff2d_bytes(const egb_grid* g) {
+    return grid_ok(g) ? (size_t)EGB_NFIELD * EGB_NTAYLOR * (size_t)g->nx * (size_t)g->nz * sizeof(double) : 0;
+}
+
+size_t egb_vel3d_bytes(const egb_grid* g) { return grid_ok(g) ? (size_t)EGB_NVEL * plane_stride(*g) * real_size(*g) : 0; }
+
+size_t egb_state_bytes(const egb_grid* g) { return grid_ok(g) ? state_bytes(*g) : 0; }
+
+size_t egb_state_plane_offset(const egb_grid* g, int32_t plane) {
+    if (!grid_ok(g) || plane < 0 || plane >= EGB_NSTATE) return 0;
+    return state_plane_offset(*g, plane);
+}
+
+size_t egb_workspace_size(const egb_grid* g, int32_t op) {
+    if (!grid_ok(g)) return 0;
+    switch (op) {
+        case EGB_OP_VELOCITY: return 256;
+        case EGB_OP_STEP: return 2 * align256(state_bytes(*g));
+        case EGB_OP_BEAM:
+            return beam_counts_bytes(*g) + (size_t)(g->nx + g->nz) * beam_cap_default(*g) * beam_record_bytes();
+        default: return 0;
+    }
+}
+
+egb_status egb_hamiltonian_velocity(const egb_grid* g, const egb_medium* m, void* coeff2d, void* vel3d,
+                                    double* dt_cfl, void* work, size_t work_bytes, hipStream_t stream) {
+    if (!grid_ok(g) || !m || !m->vp0 || !m->eps || !m->delta || !coeff2d || !vel3d || !dt_cfl || !work)
+        return EGB_EINVAL;
+    if (!(m->vs_ratio >= 0.0) || !(m->vs_ratio < 1.0)) return EGB_EINVAL;
+    if (!aligned16(coeff2d) || !aligned16(vel3d) || !aligned16(work) || !aligned16(m->vp0) || !aligned16(m->eps) ||
+        !aligned16(m->delta) || (m->tilt && !aligned16(m->tilt)))
+        return EGB_EINVAL;
+    if (work_bytes < egb_workspace_size(g, EGB_OP_VELOCITY)) return EGB_EWORKSPACE;
+    const GridArgs a = grid_args(*g);
+    unsigned long long* rate = static_cast<unsigned long long*>(work);
+    hipError_t e = launch_fill_u64(rate, 1, 0ull, stream);
+    if (e == hipSuccess) e = launch_medium_table(a, *m, static_cast<double*>(coeff2d), stream);
+    if (e == hipSuccess) e = launch_velocity(a, g->dtype, static_cast<const double*>(coeff2d), vel3d, rate, stream);
+    unsigned long long bits = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bits, rate, sizeof(bits), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return EGB_EHIP;
+    double r;
+    memcpy(&r, &bits, sizeof(r));
+    if (!(r > 0.0) || !isfinite(r)) return EGB_ENONFINITE;
+    *dt_cfl = 0.5 / r;
+    return EGB_OK;
+}
+
+egb_status egb_init_state(const egb_grid* g, const void* coeff2d, const egb_source* src, void* state,
+                          hipStream_t stream) {
+    if (!grid_ok(g) || !coeff2d || !state || !source_ok(src)) return EGB_EINVAL;
+    if (!aligned16(coeff2d) || !aligned16(state)) return EGB_EINVAL;
+    return hip_status(launch_init_state(grid_args(*g), g->dtype, static_cast<const double*>(coeff2d), *src, state, stream));
+}
+
+egb_status egb_liouville_step(const egb_grid* g, const void* vel3d, const egb_source* src, void* state, void* work,
+                              size_t work_bytes, double dt, int32_t nsteps, hipStream_t stream) {
+    if (!grid_ok(g) || !vel3d || !state || !source_ok(src) || nsteps < 0) return EGB_EINVAL;
+    if (nsteps > 0 && !work) return EGB_EINVAL;
+    if (!aligned16(vel3d) || !aligned16(state) || (work && !aligned16(work))) return EGB_EINVAL;
+    if (!(dt > 0.0) || !isfinite(dt)) return EGB_ECFL;
+    if (nsteps == 0) return EGB_OK;
+    if (work_bytes < egb_workspace_size(g, EGB_OP_STEP)) return EGB_EWORKSPACE;
+    char* w = static_cast<char*>(work);
+    void* U1 = w;
+    void* U2 = w + align256(state_bytes(*g));
+    StageArgs sa;
+    sa.g = grid_args(*g);
+    sa.vel = vel3d;
+    sa.dt = dt;
+    sa.xs = src->xs;
+    sa.zs = src->zs;
+    sa.r02 = src->r0 * src->r0;
+    for (int n = 0; n < nsteps; ++n) {
+        sa.U0 = state;
+        sa.Uin = state;
+        sa.Uout = U1;
+        hipError_t e = launch_stage(sa, g->dtype, 0, stream);
+        if (e != hipSuccess) return EGB_EHIP;
+        sa.Uin = U1;
+        sa.Uout = U2;
+        e = launch_stage(sa, g->dtype, 1, stream);
+        if (e != hipSuccess) return EGB_EHIP;
+        sa.Uin = U2;
+        sa.Uout = state;
+        e = launch_stage(sa, g->dtype, 2, stream);
+        if (e != hipSuccess) return EGB_EHIP;
+    }
+    return EGB_OK;
+}
+
+egb_status egb_beam_sum(const egb_grid* g, const void* coeff2d, const void* vel3d, const egb_source* src,
+                        const void* state, const double* omegas, int32_t nw, void* out, void* work,
+                        size_t work_bytes, hipStream_t stream) {
+    if (!grid_ok(g) || !coeff2d || !vel3d || !state || !omegas || nw < 1 || !out || !work || !source_ok(src))
+        return EGB_EINVAL;
+    if (!aligned16(coeff2d) || !aligned16(vel3d) || !aligned16(state) || !aligned16(out) || !aligned16(work))
+        return EGB_EINVAL;
+    for (int w = 0; w < nw; ++w)
+        if (!isfinite(omegas[w]) || !(omegas[w] > 0.0)) return EGB_EINVAL;
+    const size_t cb = beam_counts_bytes(*g);
+    const size_t per = (size_t)(g->nx + g->nz) * beam_record_bytes();
+    if (work_bytes < cb + per) return EGB_EWORKSPACE;
+    const size_t capz = (work_bytes - cb) / per;
+    const int cap = capz > (size_t)(1 << 30) ? (1 << 30) : (int)capz;
+    char* w = static_cast<char*>(work);
+    BeamArgs ba;
+    ba.g = grid_args(*g);
+    ba.coeff2d = static_cast<const double*>(coeff2d);
+    ba.vel = vel3d;
+    ba.U = state;
+    ba.beta = src->beta;
+    ba.cap = cap;
+    ba.counts = reinterpret_cast<int*>(w);
+    ba.rows = w + cb;
+    ba.cols = w + cb + (size_t)g->nz * cap * beam_record_bytes();
+    hipError_t e = launch_beam_compact(ba, g->dtype, stream);
+    if (e == hipSuccess) e = launch_beam_sum(ba, g->dtype, omegas, nw, out, stream);
+    std::vector<int> counts(g->nx + g->nz);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(counts.data(), ba.counts, counts.size() * sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return EGB_EHIP;
+    for (int c : counts)
+        if (c > cap) return EGB_EWORKSPACE;
+    return EGB_OK;
+}
+
+egb_status egb_pick_receivers(const egb_grid* g, const void* state, const double* rx, int32_t nr, double* t_out,
+                              hipStream_t stream) {
+    if (!grid_ok(g) || !state || nr < 0 || (nr > 0 && (!rx || !t_out))) return EGB_EINVAL;
+    if (!aligned16(state) || (rx && !aligned16(rx)) || (t_out && !aligned16(t_out))) return EGB_EINVAL;
+    return hip_status(launch_pick(grid_args(*g), g->dtype, state, rx, nr, t_out, stream));
+}
+
+const char* egb_status_string(int32_t s) {
+    switch (s) {
+        case EGB_OK: return "ok";
+        case EGB_EINVAL: return "invalid argument";
+        case EGB_ECFL: return "time step not positive and finite";
+        case EGB_EWORKSPACE: return "workspace too small";
+        case EGB_EHIP: return "HIP runtime or launch error";
+        case EGB_ENONFINITE: return "non-finite value";
+        case EGB_EUNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

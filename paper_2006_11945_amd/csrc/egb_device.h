@@ -1,0 +1,260 @@
+// Device-side building blocks shared by the libegb kernels (gfx950).
+//
+//  * qP phase velocity of a 2D TTI medium and its derivatives up to second
+//    order in (x, z, theta), by an explicit chain rule through the
+//    Christoffel eigenvalue (eqs. 3-5, 7);
+//  * the Liouville velocity (eqs. 8-9, 12) and the ray-normal dynamic ray
+//    tracing matrix (eq. 21 read in the ray-normal frame);
+//  * the WENO5 Hamilton-Jacobi one-sided derivative used by the march.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace egb {
+
+constexpr int NF = 5;  // a11, a33, b = a13 + a55, a55, nu
+constexpr int NT = 6;  // f, f_x, f_z, f_xx, f_xz, f_zz
+
+// Medium values at one (x, z) point: m[field][taylor].
+struct MediumPoint {
+    double m[NF][NT];
+};
+
+// Phase velocity and derivatives: gradient index 0 = x, 1 = z, 2 = theta;
+// Hessian stored symmetric as h[a][b].
+struct VJet {
+    double v;
+    double g[3];
+    double h[3][3];
+};
+
+__device__ __host__ inline void sincos_d(double a, double* s, double* c) {
+#ifdef __HIP_DEVICE_COMPILE__
+    sincos(a, s, c);
+#else
+    *s = __builtin_sin(a);
+    *c = __builtin_cos(a);
+#endif
+}
+
+// Second-order derivatives of F(m(x), phi(x, theta)) = sum_m m * kappa_m(phi),
+// phi = theta - nu(x), given F's phi-derivatives Fp, Fpp and the medium sums
+//   Fm[i]   = sum_m m_i kappa_m,  Fmm[i][j] = sum_m m_ij kappa_m,
+//   Fmp[i]  = sum_m m_i kappa_m'.
+struct Lin2 {
+    double f, g[3], h[3][3];
+};
+
+__device__ inline Lin2 chain_linear(double F, double Fp, double Fpp, const double Fm[2], const double Fmm[2][2],
+                                    const double Fmp[2], const double nu[2], const double nuh[2][2]) {
+    Lin2 r;
+    r.f = F;
+    for (int i = 0; i < 2; ++i) r.g[i] = Fm[i] - Fp * nu[i];
+    r.g[2] = Fp;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            r.h[i][j] = Fmm[i][j] - Fmp[i] * nu[j] - Fmp[j] * nu[i] + Fpp * nu[i] * nu[j] - Fp * nuh[i][j];
+    for (int i = 0; i < 2; ++i) {
+        r.h[i][2] = Fmp[i] - Fpp * nu[i];
+        r.h[2][i] = r.h[i][2];
+    }
+    r.h[2][2] = Fpp;
+    return r;
+}
+
+// sqrt of a positive quantity carried with gradient and Hessian.
+__device__ inline Lin2 sqrt2(const Lin2& E) {
+    Lin2 r;
+    r.f = sqrt(E.f);
+    double i2 = 0.5 / r.f;
+    for (int a = 0; a < 3; ++a) r.g[a] = E.g[a] * i2;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) r.h[a][b] = (E.h[a][b] - 2.0 * r.g[a] * r.g[b]) * i2;
+    return r;
+}
+
+// qP phase velocity v(x, z, theta) = sqrt(G), G the larger eigenvalue of the
+// 2x2 Christoffel matrix for the unit phase direction at angle phi = theta - nu
+// from the symmetry axis:
+//   G = (P + sqrt(Q^2 + R^2)) / 2,
+//   P = (a11 + a55) sin^2 + (a33 + a55) cos^2,  Q = (a11 - a55) sin^2 - (a33 - a55) cos^2,
+//   R = 2 b sin cos.
+// With ms == nullptr-free callers passing only values, derivatives vanish.
+__device__ inline VJet qp_velocity(const MediumPoint& M, double theta) {
+    const double* a11 = M.m[0];
+    const double* a33 = M.m[1];
+    const double* b = M.m[2];
+    const double* a55 = M.m[3];
+    const double* nuT = M.m[4];
+    double sp, cp;
+    sincos_d(theta - nuT[0], &sp, &cp);
+    double S2 = sp * sp, C2 = cp * cp, s2 = 2.0 * sp * cp, c2 = C2 - S2;
+    double nu[2] = {nuT[1], nuT[2]};
+    double nuh[2][2] = {{nuT[3], nuT[4]}, {nuT[4], nuT[5]}};
+    // first / second spatial derivative slots of field f: d[f][i], dd[f][i][j]
+    auto d1 = [&](const double* f, int i) { return f[1 + i]; };
+    auto d2 = [&](const double* f, int i, int j) { return (i == j) ? f[3 + 2 * i] : f[4]; };
+
+    double Pm[2], Pmm[2][2], Pmp[2], Qm[2], Qmm[2][2], Qmp[2], Rm[2], Rmm[2][2], Rmp[2];
+    for (int i = 0; i < 2; ++i) {
+        Pm[i] = d1(a11, i) * S2 + d1(a33, i) * C2 + d1(a55, i);
+        Qm[i] = d1(a11, i) * S2 - d1(a33, i) * C2 + d1(a55, i) * c2;
+        Rm[i] = d1(b, i) * s2;
+        Pmp[i] = (d1(a11, i) - d1(a33, i)) * s2;
+        Qmp[i] = (d1(a11, i) + d1(a33, i) - 2.0 * d1(a55, i)) * s2;
+        Rmp[i] = 2.0 * d1(b, i) * c2;
+        for (int j = 0; j < 2; ++j) {
+            Pmm[i][j] = d2(a11, i, j) * S2 + d2(a33, i, j) * C2 + d2(a55, i, j);
+            Qmm[i][j] = d2(a11, i, j) * S2 - d2(a33, i, j) * C2 + d2(a55, i, j) * c2;
+            Rmm[i][j] = d2(b, i, j) * s2;
+        }
+    }
+    double P = (a11[0] + a55[0]) * S2 + (a33[0] + a55[0]) * C2;
+    double Q = (a11[0] - a55[0]) * S2 - (a33[0] - a55[0]) * C2;
+    double R = b[0] * s2;
+    double Pp = (a11[0] - a33[0]) * s2, Ppp = 2.0 * (a11[0] - a33[0]) * c2;
+    double Qp = (a11[0] + a33[0] - 2.0 * a55[0]) * s2, Qpp = 2.0 * (a11[0] + a33[0] - 2.0 * a55[0]) * c2;
+    double Rp = 2.0 * b[0] * c2, Rpp = -4.0 * b[0] * s2;
+
+    Lin2 LP = chain_linear(P, Pp, Ppp, Pm, Pmm, Pmp, nu, nuh);
+    Lin2 LQ = chain_linear(Q, Qp, Qpp, Qm, Qmm, Qmp, nu, nuh);
+    Lin2 LR = chain_linear(R, Rp, Rpp, Rm, Rmm, Rmp, nu, nuh);
+
+    Lin2 E;  // Q^2 + R^2
+    E.f = LQ.f * LQ.f + LR.f * LR.f;
+    for (int a = 0; a < 3; ++a) E.g[a] = 2.0 * (LQ.f * LQ.g[a] + LR.f * LR.g[a]);
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c)
+            E.h[a][c] = 2.0 * (LQ.g[a] * LQ.g[c] + LQ.f * LQ.h[a][c] + LR.g[a] * LR.g[c] + LR.f * LR.h[a][c]);
+    Lin2 D = sqrt2(E);
+    Lin2 G;
+    G.f = 0.5 * (LP.f + D.f);
+    for (int a = 0; a < 3; ++a) G.g[a] = 0.5 * (LP.g[a] + D.g[a]);
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) G.h[a][c] = 0.5 * (LP.h[a][c] + D.h[a][c]);
+    Lin2 v = sqrt2(G);
+    VJet out;
+    out.v = v.f;
+    for (int a = 0; a < 3; ++a) out.g[a] = v.g[a];
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) out.h[a][c] = v.h[a][c];
+    return out;
+}
+
+// Liouville velocity and ray-normal DRT matrix at phase angle theta.
+//   group velocity  Vg = v n + v_theta m,   n = (sin, cos), m = dn/dtheta = (cos, -sin);
+//   angle rate      V_t = -(grad v . m)      (dp/dtau = -grad_x v / v at fixed theta);
+// Perturbation (dn, dt) normal to the ray: position offset dn along
+// e = (gz, -gx) (unit, perpendicular to Vg) and angle offset dt with the
+// along-ray drift removed.  Writing dV/dy for the phase-space Jacobian,
+//   A11 = e.(Jx e), A12 = e.dVg/dtheta,
+//   A21 = e.grad V_t - (gh.(Jx e) + phidot) V_t/|Vg|,
+//   A22 = dV_t/dtheta - (gh.dVg/dtheta) V_t/|Vg|,
+// gh = Vg/|Vg|, Jx = d Vg / d(x, z), phidot the turning rate of gh.
+struct VelA {
+    double V[3];
+    double A[4];
+};
+
+__device__ inline VelA velocity_and_drt(const VJet& J, double theta) {
+    double sn, cs;
+    sincos_d(theta, &sn, &cs);
+    const double v = J.v, vx = J.g[0], vz = J.g[1], vt = J.g[2];
+    const double vxx = J.h[0][0], vxz = J.h[0][1], vzz = J.h[1][1];
+    const double vxt = J.h[0][2], vzt = J.h[1][2], vtt = J.h[2][2];
+    VelA r;
+    const double gx_ = v * sn + vt * cs, gz_ = v * cs - vt * sn;
+    const double Vt = -(vx * cs - vz * sn);
+    r.V[0] = gx_;
+    r.V[1] = gz_;
+    r.V[2] = Vt;
+    const double speed = sqrt(gx_ * gx_ + gz_ * gz_), inv = 1.0 / speed;
+    const double hx = gx_ * inv, hz = gz_ * inv;  // unit ray direction
+    const double ex = hz, ez = -hx;               // unit normal
+    // d Vg / dx and d Vg / dz at fixed theta
+    const double dVx_dx = vx * sn + vxt * cs, dVx_dz = vz * sn + vzt * cs;
+    const double dVz_dx = vx * cs - vxt * sn, dVz_dz = vz * cs - vzt * sn;
+    // d Vg / dtheta = (v + v_tt) m
+    const double w = v + vtt;
+    const double dVx_dt = w * cs, dVz_dt = -w * sn;
+    // Jx applied to e
+    const double Je_x = dVx_dx * ex + dVx_dz * ez, Je_z = dVz_dx * ex + dVz_dz * ez;
+    // dVg/dtau along the ray = Jx Vg + dVg/dtheta V_t
+    const double dgx = dVx_dx * gx_ + dVx_dz * gz_ + dVx_dt * Vt;
+    const double dgz = dVz_dx * gx_ + dVz_dz * gz_ + dVz_dt * Vt;
+    const double phidot = (ex * dgx + ez * dgz) * inv;
+    // grad of V_t and its theta derivative
+    const double dVt_dx = -(vxx * cs - vxz * sn), dVt_dz = -(vxz * cs - vzz * sn);
+    const double dVt_dt = vx * sn + vz * cs - (vxt * cs - vzt * sn);
+    r.A[0] = ex * Je_x + ez * Je_z;
+    r.A[1] = ex * dVx_dt + ez * dVz_dt;
+    r.A[2] = ex * dVt_dx + ez * dVt_dz - (hx * Je_x + hz * Je_z + phidot) * Vt * inv;
+    r.A[3] = dVt_dt - (hx * dVx_dt + hz * dVz_dt) * Vt * inv;
+    return r;
+}
+
+// ---------------------------------------------------------------- WENO5
+// One-sided WENO5 Hamilton-Jacobi derivative, undivided (derivative times
+// the spacing), from the five differences v1..v5 ordered away from the
+// upwind side.  The differences are first scaled by a power of two so that
+// max|v| lies in [0.5, 1): the weights are scale invariant and this keeps
+// every intermediate in range in float; eps = 1e-6 max v^2.  Returns 0 when
+// all differences vanish.
+template <typename R>
+__device__ __forceinline__ R weno5(R v1, R v2, R v3, R v4, R v5);
+
+template <>
+__device__ __forceinline__ float weno5<float>(float v1, float v2, float v3, float v4, float v5) {
+    float m = fmaxf(fmaxf(fmaxf(fabsf(v1), fabsf(v2)), fmaxf(fabsf(v3), fabsf(v4))), fabsf(v5));
+    int e = __builtin_amdgcn_frexp_expf(m);
+    v1 = __builtin_amdgcn_ldexpf(v1, -e);
+    v2 = __builtin_amdgcn_ldexpf(v2, -e);
+    v3 = __builtin_amdgcn_ldexpf(v3, -e);
+    v4 = __builtin_amdgcn_ldexpf(v4, -e);
+    v5 = __builtin_amdgcn_ldexpf(v5, -e);
+    const float mm = __builtin_amdgcn_ldexpf(m, -e);
+    const float eps = 1e-6f * mm * mm;
+    const float q0 = v1 * (1.0f / 3.0f) - v2 * (7.0f / 6.0f) + v3 * (11.0f / 6.0f);
+    const float q1 = -v2 * (1.0f / 6.0f) + v3 * (5.0f / 6.0f) + v4 * (1.0f / 3.0f);
+    const float q2 = v3 * (1.0f / 3.0f) + v4 * (5.0f / 6.0f) - v5 * (1.0f / 6.0f);
+    const float t0 = v1 - 2.0f * v2 + v3, u0 = v1 - 4.0f * v2 + 3.0f * v3;
+    const float t1 = v2 - 2.0f * v3 + v4, u1 = v2 - v4;
+    const float t2 = v3 - 2.0f * v4 + v5, u2 = 3.0f * v3 - 4.0f * v4 + v5;
+    const float b0 = eps + (13.0f / 12.0f) * t0 * t0 + 0.25f * u0 * u0;
+    const float b1 = eps + (13.0f / 12.0f) * t1 * t1 + 0.25f * u1 * u1;
+    const float b2 = eps + (13.0f / 12.0f) * t2 * t2 + 0.25f * u2 * u2;
+    const float e0 = b0 * b0, e1 = b1 * b1, e2 = b2 * b2;
+    // alpha_k = d_k / e_k with a common denominator e0 e1 e2
+    const float w0 = 0.1f * (e1 * e2), w1 = 0.6f * (e0 * e2), w2 = 0.3f * (e0 * e1);
+    const float num = w0 * q0 + w1 * q1 + w2 * q2;
+    const float r = num * __builtin_amdgcn_rcpf(w0 + w1 + w2);
+    return m > 0.0f ? __builtin_amdgcn_ldexpf(r, e) : 0.0f;
+}
+
+template <>
+__device__ __forceinline__ double weno5<double>(double v1, double v2, double v3, double v4, double v5) {
+    double m = fmax(fmax(fmax(fabs(v1), fabs(v2)), fmax(fabs(v3), fabs(v4))), fabs(v5));
+    if (!(m > 0.0)) return 0.0;
+    int e = __builtin_amdgcn_frexp_exp(m);
+    v1 = __builtin_amdgcn_ldexp(v1, -e);
+    v2 = __builtin_amdgcn_ldexp(v2, -e);
+    v3 = __builtin_amdgcn_ldexp(v3, -e);
+    v4 = __builtin_amdgcn_ldexp(v4, -e);
+    v5 = __builtin_amdgcn_ldexp(v5, -e);
+    const double mm = __builtin_amdgcn_ldexp(m, -e);
+    const double eps = 1e-6 * mm * mm;
+    const double q0 = v1 / 3.0 - 7.0 * v2 / 6.0 + 11.0 * v3 / 6.0;
+    const double q1 = -v2 / 6.0 + 5.0 * v3 / 6.0 + v4 / 3.0;
+    const double q2 = v3 / 3.0 + 5.0 * v4 / 6.0 - v5 / 6.0;
+    const double t0 = v1 - 2.0 * v2 + v3, u0 = v1 - 4.0 * v2 + 3.0 * v3;
+    const double t1 = v2 - 2.0 * v3 + v4, u1 = v2 - v4;
+    const double t2 = v3 - 2.0 * v4 + v5, u2 = 3.0 * v3 - 4.0 * v4 + v5;
+    const double b0 = eps + 13.0 / 12.0 * t0 * t0 + 0.25 * u0 * u0;
+    const double b1 = eps + 13.0 / 12.0 * t1 * t1 + 0.25 * u1 * u1;
+    const double b2 = eps + 13.0 / 12.0 * t2 * t2 + 0.25 * u2 * u2;
+    const double a0 = 0.1 / (b0 * b0), a1 = 0.6 / (b1 * b1), a2 = 0.3 / (b2 * b2);
+    return __builtin_amdgcn_ldexp((a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2), e);
+}
+
+}  // namespace egb

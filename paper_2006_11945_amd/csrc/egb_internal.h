@@ -1,0 +1,85 @@
+// Internal host/device interface of libegb: layouts and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/egb.h"
+
+namespace egb {
+
+// Elements per phase-space plane: nth * nx * nz rounded up to 64.
+inline size_t plane_stride(const egb_grid& g) {
+    size_t n = (size_t)g.nth * (size_t)g.nx * (size_t)g.nz;
+    return (n + 63) / 64 * 64;
+}
+inline size_t real_size(const egb_grid& g) { return g.dtype == EGB_F64 ? 8 : 4; }
+
+// Byte offset of state plane p: planes 0..4 in the grid dtype, psi in double.
+inline size_t state_plane_offset(const egb_grid& g, int p) {
+    return (size_t)p * plane_stride(g) * real_size(g);
+}
+inline size_t state_bytes(const egb_grid& g) { return state_plane_offset(g, EGB_PSI) + plane_stride(g) * 8; }
+
+// Geometry passed to kernels by value.
+struct GridArgs {
+    int nx, nz, nth;
+    long long nxz, stride;
+    double x0, z0, dx, dz, dth;
+};
+
+inline GridArgs grid_args(const egb_grid& g) {
+    GridArgs a;
+    a.nx = g.nx;
+    a.nz = g.nz;
+    a.nth = g.nth;
+    a.nxz = (long long)g.nx * g.nz;
+    a.stride = (long long)plane_stride(g);
+    a.x0 = g.x0;
+    a.z0 = g.z0;
+    a.dx = g.dx;
+    a.dz = g.dz;
+    a.dth = 6.283185307179586476925286766559 / g.nth;
+    return a;
+}
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t launch_medium_table(const GridArgs& a, const egb_medium& m, double* coeff2d, hipStream_t s);
+hipError_t launch_velocity(const GridArgs& a, int dtype, const double* coeff2d, void* vel3d, unsigned long long* rate_bits,
+                           hipStream_t s);
+hipError_t launch_init_state(const GridArgs& a, int dtype, const double* coeff2d, const egb_source& src, void* state,
+                             hipStream_t s);
+hipError_t launch_pick(const GridArgs& a, int dtype, const void* state, const double* rx, int nr, double* t_out,
+                       hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
+
+// One SSP-RK3 stage: Uout = ca U0 + cb (Uin + dt L(Uin)), ball cells copy U0.
+struct StageArgs {
+    GridArgs g;
+    const void* vel;
+    const void* U0;
+    const void* Uin;
+    void* Uout;
+    double dt;
+    double xs, zs, r02;
+};
+hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s);
+
+// Beam superposition.
+struct BeamArgs {
+    GridArgs g;
+    const double* coeff2d;
+    const void* vel;
+    const void* U;
+    double beta;
+    int cap;          // records per row / column list
+    int* counts;      // [nz rows][nx cols]
+    void* rows;       // row records
+    void* cols;       // column records
+};
+hipError_t launch_beam_compact(const BeamArgs& a, int dtype, hipStream_t s);
+hipError_t launch_beam_sum(const BeamArgs& a, int dtype, const double* omegas, int nw, void* out, hipStream_t s);
+size_t beam_record_bytes();
+
+}  // namespace egb

@@ -1,0 +1,75 @@
+"""The C-ABI library loads and exports every symbol include/egb.h declares.
+
+CPU only: only host-side size queries and argument validation are called
+(they return before any HIP call).
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "egb.h")
+LIB = os.path.join(ROOT, "paper_2006_11945_amd", "libegb.so")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(egb_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libegb.so not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 10
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_sizes_and_validation_without_gpu():
+    import numpy as np
+    import paper_2006_11945_amd as egb
+    import workloads as W
+
+    g = W.Grid(nx=40, nz=72, nth=36, dx=10.0, dz=10.0)
+    eg = egb.make_grid(g, "f32")
+    n = 40 * 72 * 36
+    st = egb.plane_stride(eg)
+    assert st >= n and st % 64 == 0
+    assert egb.state_bytes(eg) == 5 * st * 4 + st * 8
+    assert egb.state_plane_offset(eg, egb.EGB_PSI) == 5 * st * 4
+    assert egb.vel3d_bytes(eg) == 7 * st * 4
+    assert egb.coeff2d_bytes(eg) == 30 * 40 * 72 * 8
+    assert egb.workspace_size(eg, egb.EGB_OP_STEP) >= 2 * egb.state_bytes(eg)
+    eg64 = egb.make_grid(g, "f64")
+    assert egb.state_bytes(eg64) == 6 * st * 8
+    # invalid grids give zero sizes and EINVAL before any device work
+    bad = egb.EgbGrid(4, 72, 36, 0, 0.0, 0.0, 10.0, 10.0)
+    assert egb.state_bytes(bad) == 0
+    L = egb.lib()
+    src = egb.EgbSource(1.0, 1.0, 1.0, 1e-4)
+    assert L.egb_init_state(ctypes.byref(bad), None, ctypes.byref(src), None, None) == egb.EGB_EINVAL
+    assert L.egb_init_state(None, None, None, None, None) == egb.EGB_EINVAL
+    assert L.egb_liouville_step(ctypes.byref(eg), ctypes.c_void_p(256), ctypes.byref(src), ctypes.c_void_p(256),
+                                ctypes.c_void_p(256), 1 << 30, -1.0, 1, None) == egb.EGB_ECFL
+    assert L.egb_liouville_step(ctypes.byref(eg), ctypes.c_void_p(256), ctypes.byref(src), ctypes.c_void_p(256),
+                                ctypes.c_void_p(256), 16, 1e-3, 1, None) == egb.EGB_EWORKSPACE
+    assert L.egb_liouville_step(ctypes.byref(eg), ctypes.c_void_p(258), ctypes.byref(src), ctypes.c_void_p(256),
+                                ctypes.c_void_p(256), 1 << 30, 1e-3, 1, None) == egb.EGB_EINVAL
+    nosrc = egb.EgbSource(1.0, 1.0, 1.0, 0.0)  # beta must be > 0
+    assert L.egb_init_state(ctypes.byref(eg), ctypes.c_void_p(256), ctypes.byref(nosrc), ctypes.c_void_p(256),
+                            None) == egb.EGB_EINVAL
+    om = np.array([-1.0])
+    assert L.egb_beam_sum(ctypes.byref(eg), ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.byref(src),
+                          ctypes.c_void_p(256), om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1,
+                          ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 30, None) == egb.EGB_EINVAL
+    assert L.egb_pick_receivers(ctypes.byref(eg), ctypes.c_void_p(256), None, 0, None, None) == egb.EGB_OK
+    assert egb.lib().egb_status_string(-3) == b"workspace too small"

@@ -1,0 +1,207 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances (fixed before measuring, from the arithmetic):
+  * FP64 grids: 1e-10 relative (different summation / FMA order only);
+  * FP32 grids: traveltime psi max relative error <= 1e-5 over active cells
+    (|phi1| / |grad phi1| < 2 dx, psi > 0); the other planes <= 1e-4 of the
+    plane's max magnitude; wavefield relative L2 <= 1e-4;
+  * the medium table and the velocity are computed in FP64 on both sides and
+    only rounded to FP32 at the end (<= 2e-6 of the plane max).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from tests.gpu_helpers import ORACLE_TO_GPU, gpu_planes, log, oracle_planes, rel_err, rounded_oracle_state
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def egb():
+    import paper_2006_11945_amd as m
+    return m
+
+
+def ragged_problem(nx=42, nz=72, nth=36, tilt=False, seed=0, dtype="f32", nsteps=30):
+    """VTI / TTI recipe on a small ragged grid (several 64 x 4 tiles plus tails)."""
+    dx = 15.625
+    g = W.Grid(nx=nx, nz=nz, nth=nth, dx=dx, dz=dx)
+    L = max(nx, nz) * dx
+    rng = W.rng_for(2 if tilt else 1, 100 + seed)
+    med = W.vti_medium(rng, g, L, tilt=tilt)
+    src = W.Source(xs=0.5 * nx * dx, zs=0.5 * nz * dx, r0=4 * dx, beta=1.0 / (2 * L))
+    return W.Problem("ragged", g, med, src, nsteps, W.hz([10.0, 35.0, 60.0]), dtype=dtype)
+
+
+def active_mask(g, U):
+    phi, psi = U[0], U[1]
+    lam = g.dx / g.dth
+    ft = (np.roll(phi, -1, 0) - np.roll(phi, 1, 0)) / (2 * g.dth)
+    fx = np.gradient(phi, g.dx, axis=1)
+    fz = np.gradient(phi, g.dz, axis=2)
+    drow = phi / np.sqrt(fx ** 2 + (ft / lam) ** 2)
+    dcol = phi / np.sqrt(fz ** 2 + (ft / lam) ** 2)
+    return ((np.abs(drow) < 2 * g.dx) | (np.abs(dcol) < 2 * g.dz)) & (psi > 0)
+
+
+def run_gpu(p, dtype, nsteps, dt=None):
+    s = egb().Solver(p, DEV, dtype)
+    s.velocity()
+    s.init()
+    if nsteps:
+        s.step(nsteps, dt=dt)
+    torch.cuda.synchronize()
+    return s
+
+
+@pytest.mark.parametrize("dtype,tilt", [("f32", False), ("f64", False), ("f32", True)])
+def test_table_velocity_init(dtype, tilt):
+    p = ragged_problem(tilt=tilt, dtype=dtype)
+    log(f"table/velocity/init dtype={dtype} tilt={tilt} grid={p.grid.nx}x{p.grid.nz}x{p.grid.nth}")
+    o = oracle.solve(p, nsteps=0)
+    s = run_gpu(p, dtype, 0)
+    tab = egb().coeff2d_view(s.eg, s.coeff2d).cpu().numpy()  # [f][t][x][z]
+    otab = np.transpose(o["tab"], (2, 3, 0, 1))
+    for f in range(5):
+        for t in range(6):
+            sc = max(np.abs(otab[f, t]).max(), 1e-300 if f < 4 else 1e-12)
+            assert rel_err(tab[f, t], otab[f, t], sc) < 1e-10, (f, t)
+    assert s.dt_cfl == pytest.approx(o["dt"], rel=1e-10)
+    vel = {k: v.double().cpu().numpy() for k, v in s.vel_planes().items()}
+    tol = 1e-10 if dtype == "f64" else 2e-6
+    for q, name in enumerate(egb().VEL_PLANES):
+        assert rel_err(vel[name], o["vel"][q]) < tol, name
+    G, O = gpu_planes(s), oracle_planes(o["U0"])
+    for name in ORACLE_TO_GPU:
+        t_ = 1e-12 if (dtype == "f64" or name == "psi") else 2e-6
+        assert rel_err(G[name], O[name], max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())) < t_, name
+
+
+@pytest.mark.parametrize("tilt", [False, True])
+def test_march_parity_f32(tilt):
+    p = ragged_problem(tilt=tilt, nsteps=40)
+    log(f"march f32 tilt={tilt} grid={p.grid.nx}x{p.grid.nz}x{p.grid.nth} steps={p.nsteps}")
+    o = oracle.solve(p)
+    s = run_gpu(p, "f32", p.nsteps, dt=o["dt"])
+    G, O = gpu_planes(s), oracle_planes(o["U"])
+    act = active_mask(p.grid, o["U"])
+    assert act.sum() > 200
+    trel = (np.abs(G["psi"] - O["psi"]) / O["psi"])[act].max()
+    log(f"  psi max rel err over {act.sum()} active cells: {trel:.3e}")
+    assert trel <= 1e-5
+    for name in ("phi1", "ReC", "ImC", "ReB", "ImB"):
+        sc = max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())
+        e = rel_err(G[name], O[name], sc)
+        log(f"  {name}: {e:.3e}")
+        assert e <= 1e-4, name
+
+
+def test_homog_iso_64_fp64_full_workload():
+    """The plain FP64 workload (64^3 homogeneous isotropic, 100 steps, 20 Hz)."""
+    p = W.homog_iso_64()
+    log("homogeneous isotropic fp64 64^3 x 100 steps")
+    o = oracle.solve(p)
+    s = run_gpu(p, "f64", p.nsteps, dt=o["dt"])
+    G, O = gpu_planes(s), oracle_planes(o["U"])
+    for name in ORACLE_TO_GPU:
+        sc = max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())
+        assert rel_err(G[name], O[name], sc) < 1e-10, name
+    out = s.beam(p.omegas).cpu().numpy()
+    Gb = out[..., 0] + 1j * out[..., 1]
+    Ob = oracle.beam_sum(p.grid, o["vel"], o["vaux"], p.source, o["U"], p.omegas)
+    e = np.linalg.norm(Gb - Ob) / np.linalg.norm(Ob)
+    log(f"  beam rel L2 vs oracle: {e:.3e}")
+    assert e < 1e-10
+    from oracle import closed_forms as CF
+    X, Z = np.meshgrid(p.grid.xc(), p.grid.zc(), indexing="ij")
+    H = CF.green_iso(X, Z, 500.0, 500.0, 2000.0, p.omegas[0])
+    R = np.hypot(X - 500.0, Z - 500.0)
+    m = (R >= 200.0) & (R <= 480.0)
+    assert np.linalg.norm((Gb[0] - H)[m]) / np.linalg.norm(H[m]) < 0.03
+
+
+@pytest.mark.parametrize("tilt", [False, True])
+def test_beam_sum_parity_f32(tilt):
+    """Beam sum on identical input: the oracle's marched state, rounded to the
+    FP32 storage, is written into the GPU state buffer."""
+    p = ragged_problem(tilt=tilt, nsteps=40)
+    log(f"beam f32 tilt={tilt}")
+    o = oracle.solve(p)
+    Ur = rounded_oracle_state(o["U"], "f32")
+    s = run_gpu(p, "f32", 0)
+    egb().write_state(s.eg, s.state, oracle_planes(Ur))
+    out = s.beam(p.omegas).cpu().numpy()
+    Gb = out[..., 0] + 1j * out[..., 1]
+    Ob = oracle.beam_sum(p.grid, o["vel"], o["vaux"], p.source, Ur, p.omegas)
+    for w in range(len(p.omegas)):
+        e = np.linalg.norm(Gb[w] - Ob[w]) / np.linalg.norm(Ob[w])
+        log(f"  omega {p.omegas[w]:.1f}: rel L2 {e:.3e}")
+        assert e <= 1e-4
+
+
+def test_pick_parity_and_no_arrival():
+    p = ragged_problem(nsteps=40)
+    o = oracle.solve(p)
+    Ur = rounded_oracle_state(o["U"], "f32")
+    s = run_gpu(p, "f32", 0)
+    egb().write_state(s.eg, s.state, oracle_planes(Ur))
+    rng = np.random.default_rng(3)
+    Lx, Lz = p.grid.nx * p.grid.dx, p.grid.nz * p.grid.dz
+    rx = np.stack([rng.uniform(0, Lx, 64), rng.uniform(0, Lz, 64)], axis=1)
+    rx[0] = (-50.0, -50.0)  # clamped to the corner cell
+    t = s.pick(rx).cpu().numpy()
+    to = oracle.pick(p.grid, Ur, rx)
+    assert np.array_equal(np.isnan(t), np.isnan(to))
+    ok = ~np.isnan(to)
+    assert ok.sum() > 50
+    assert np.abs(t[ok] - to[ok]).max() <= 1e-12 * np.abs(to[ok]).max()
+    # empty receiver set is a no-op
+    s.pick(np.zeros((0, 2)))
+
+
+def test_minimum_grid_and_zero_steps():
+    g = W.Grid(nx=8, nz=8, nth=8, dx=20.0, dz=20.0)
+    med = W.vti_medium(W.rng_for(1, 7), g, 160.0)
+    p = W.Problem("tiny", g, med, W.Source(80.0, 80.0, 40.0, 1.0 / 320.0), 5, W.hz([20.0]), dtype="f64")
+    o = oracle.solve(p)
+    s = run_gpu(p, "f64", 0)
+    before = gpu_planes(s)
+    s.step(0)
+    after = gpu_planes(s)
+    for k in before:
+        assert np.array_equal(before[k], after[k])
+    s.step(p.nsteps, dt=o["dt"])
+    torch.cuda.synchronize()
+    G, O = gpu_planes(s), oracle_planes(o["U"])
+    for name in ORACLE_TO_GPU:
+        sc = max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())
+        assert rel_err(G[name], O[name], sc) < 1e-10, name
+
+
+def test_vti_256_full_size_one_step():
+    """The 256^3 VTI workload in the benchmark's launch configuration: one
+    SSP-RK3 step from the point-source data, every cell compared."""
+    p = W.vti_256()
+    log("VTI 256^3 one step")
+    o = oracle.solve(p, nsteps=1)
+    s = run_gpu(p, "f32", 1, dt=o["dt"])
+    G, O = gpu_planes(s), oracle_planes(o["U"])
+    rel = np.abs(G["psi"] - O["psi"]) / np.maximum(np.abs(O["psi"]), 1e-3)
+    log(f"  psi max rel err (|psi| >= 1e-3 floor): {rel.max():.3e}")
+    assert rel.max() <= 1e-5
+    for name in ("phi1", "ReC", "ImC", "ReB", "ImB"):
+        sc = max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())
+        e = rel_err(G[name], O[name], sc)
+        log(f"  {name}: {e:.3e}")
+        assert e <= 1e-5, name

@@ -261,7 +261,7 @@ def test_drt_symplectic_invariant():
 def test_homogeneous_point_source_data_is_steady(eps, delta, tilt):
     """The local homogeneous data is an exact steady state of the scheme
     (linear in x, z; V_theta = 0), including at extrapolated ghosts."""
-    p = W.c0(n=24, nsteps=0)
+    p = W.homog_iso_64(n=24, nsteps=0)
     p.grid.nth = 20
     p.medium = W.homogeneous(p.grid, 2000.0, eps, delta, tilt)
     r = oracle.solve(p, nsteps=6)
@@ -276,7 +276,7 @@ def _pick_tol(grid, t):
 
 @pytest.mark.parametrize("eps,tilt", [(0.0, 0.0), (0.2, 0.3)])
 def test_pick_matches_straight_and_elliptic_traveltime(eps, tilt):
-    p = W.c0(n=32, nsteps=0)
+    p = W.homog_iso_64(n=32, nsteps=0)
     p.grid.nth = 48
     p.medium = W.homogeneous(p.grid, 2000.0, eps, eps, tilt)
     r = oracle.solve(p, nsteps=2)
@@ -335,7 +335,7 @@ def _beam_err(p, ref):
 
 
 def test_beam_sum_matches_hankel_isotropic():
-    p = W.c0(n=96, nsteps=0)
+    p = W.homog_iso_64(n=96, nsteps=0)
     p.omegas = W.hz([20.0, 40.0])
     err, _ = _beam_err(p, lambda X, Z, om: CF.green_iso(X, Z, 500.0, 500.0, 2000.0, om))
     assert err[0] < 0.03 and err[1] < 0.02, err
@@ -343,7 +343,7 @@ def test_beam_sum_matches_hankel_isotropic():
 
 @pytest.mark.parametrize("tilt", [0.0, 0.4])
 def test_beam_sum_matches_elliptic_green(tilt):
-    p = W.c0(n=96, nsteps=0)
+    p = W.homog_iso_64(n=96, nsteps=0)
     p.omegas = W.hz([20.0, 40.0])
     p.medium = W.homogeneous(p.grid, 2000.0, 0.2, 0.2, tilt)
     err, _ = _beam_err(p, lambda X, Z, om: CF.green_elliptic(X, Z, 500.0, 500.0, 2000.0, 0.2, om, tilt))
@@ -351,12 +351,12 @@ def test_beam_sum_matches_elliptic_green(tilt):
 
 
 def test_beam_sum_nonelliptic_far_field_and_beta_independence():
-    p = W.c0(n=96, nsteps=0)
+    p = W.homog_iso_64(n=96, nsteps=0)
     p.omegas = W.hz([40.0])
     p.medium = W.homogeneous(p.grid, 2000.0, 0.25, 0.05, 0.0)
     r = oracle.solve(p, nsteps=0)
     G = oracle.beam_sum(p.grid, r["vel"], r["vaux"], p.source, r["U"], p.omegas)[0]
-    p2 = W.c0(n=96, nsteps=0)
+    p2 = W.homog_iso_64(n=96, nsteps=0)
     p2.omegas, p2.medium = p.omegas, p.medium
     p2.source.beta *= 0.5
     r2 = oracle.solve(p2, nsteps=0)

@@ -6,19 +6,20 @@ scheme), so both the FP64 oracle and the HIP path can take their inputs from
 here without sharing any computation.
 
 The paper (theory only, Sec. 1) measures nothing, so every workload is
-synthetic.  The recipes follow the workloads the hot path is quoted on:
+synthetic:
 
-* ``c0``: homogeneous isotropic medium, v = 2000 m/s, 1 km square, 64^3 phase
-  grid, 100 SSP-RK3 steps, one frequency (20 Hz), FP64 end to end.
-* ``c1``: heterogeneous VTI, vp0 = 3000 m/s + 8 Gaussian blobs (+-1000 m/s,
-  sigma 100-300 m), smoothed random epsilon in [0, 0.3] and delta in
-  [-0.1, 0.2], 4 km square, 256^3, 600 steps, 32 frequencies 5-60 Hz, FP32.
-* ``c2``: the c1 medium at 512^2 plus a smoothed random tilt in [-45, 45] deg,
-  512^3, 1200 steps, 64 frequencies.
-* ``c3``: 64 independent c1-recipe problems with per-axis sizes drawn
-  uniformly from 128..384, 400 steps each.
-* ``c4``: c1 medium, 16 sources at z = 0.1 L and 128 receivers at z = 0.9 L;
-  observed traveltimes come from a perturbed model (vp0 +-5 %, eps +-0.05).
+* ``homog_iso_64``: homogeneous isotropic medium, v = 2000 m/s, 1 km square,
+  64^3 phase grid, 100 SSP-RK3 steps, one frequency (20 Hz), FP64 end to end.
+* ``vti_256``: heterogeneous VTI, vp0 = 3000 m/s + 8 Gaussian blobs
+  (+-1000 m/s, sigma 100-300 m), smoothed random epsilon in [0, 0.3] and delta
+  in [-0.1, 0.2], 4 km square, 256^3, 600 steps, 32 frequencies 5-60 Hz, FP32.
+* ``tti_512``: the VTI recipe at 512^2 plus a smoothed random tilt in
+  [-45, 45] deg, 512^3, 1200 steps, 64 frequencies.
+* ``batch_uneven``: 64 independent VTI-recipe problems with per-axis sizes
+  drawn uniformly from 128..384, 400 steps each.
+* ``adjoint_sources``: VTI medium, 16 sources at z = 0.1 L and 128 receivers
+  at z = 0.9 L; observed traveltimes come from a perturbed model
+  (vp0 +-5 %, eps +-0.05).
 
 Units: metres, seconds, radians.  Arrays are float64, indexed [ix][iz]
 (z fastest), sampled at cell centres x_i = x0 + (i + 1/2) dx.
@@ -34,9 +35,10 @@ from scipy.ndimage import gaussian_filter
 SEED_BASE = 20061194
 
 
-def rng_for(cfg: int, src: int = 0) -> np.random.Generator:
-    """Seeded generator for workload ``cfg`` and source ``src``."""
-    return np.random.default_rng(SEED_BASE + 1000 * cfg + src)
+def rng_for(kind: int, src: int = 0) -> np.random.Generator:
+    """Seeded generator for workload family ``kind`` (0 homogeneous, 1 VTI,
+    2 TTI, 3 batched, 4 adjoint) and source ``src``."""
+    return np.random.default_rng(SEED_BASE + 1000 * kind + src)
 
 
 @dataclass
@@ -170,37 +172,37 @@ def hz(f) -> np.ndarray:
 
 # ---------------------------------------------------------------- workloads
 
-def c0(n: int = 64, nsteps: int = 100) -> Problem:
+def homog_iso_64(n: int = 64, nsteps: int = 100) -> Problem:
     L = 1000.0
     g = square_grid(n, L)
-    return Problem("c0-homog-iso-64", g, homogeneous(g, 2000.0), centre_source(g, L),
+    return Problem("homog-iso-64", g, homogeneous(g, 2000.0), centre_source(g, L),
                    nsteps, hz([20.0]), dtype="f64")
 
 
-def c1(n: int = 256, nsteps: int = 600, L: Optional[float] = None, nw: int = 32,
-       src: int = 0, nth: Optional[int] = None) -> Problem:
+def vti_256(n: int = 256, nsteps: int = 600, L: Optional[float] = None, nw: int = 32,
+            src: int = 0, nth: Optional[int] = None) -> Problem:
     """Heterogeneous VTI.  ``n``/``L`` can be shrunk for parity-size runs."""
     L = 4000.0 if L is None else L
     g = square_grid(n, L, nth)
     rng = rng_for(1, src)
     med = vti_medium(rng, g, L)
-    return Problem(f"c1-vti-{n}", g, med, centre_source(g, L), nsteps,
+    return Problem(f"vti-{n}", g, med, centre_source(g, L), nsteps,
                    hz(np.linspace(5.0, 60.0, nw)), dtype="f32")
 
 
-def c2(n: int = 512, nsteps: int = 1200, L: Optional[float] = None, nw: int = 64,
-       nth: Optional[int] = None) -> Problem:
+def tti_512(n: int = 512, nsteps: int = 1200, L: Optional[float] = None, nw: int = 64,
+            nth: Optional[int] = None) -> Problem:
     L = 4000.0 if L is None else L
     g = square_grid(n, L, nth)
     rng = rng_for(2, 0)
     med = vti_medium(rng, g, L, tilt=True)
-    return Problem(f"c2-tti-{n}", g, med, centre_source(g, L), nsteps,
+    return Problem(f"tti-{n}", g, med, centre_source(g, L), nsteps,
                    hz(np.linspace(5.0, 60.0, nw)), dtype="f32")
 
 
-def c3(nprob: int = 64, nsteps: int = 400, lo: int = 128, hi: int = 384,
-       L: float = 4000.0) -> List[Problem]:
-    """Independent c1-recipe problems with per-axis sizes drawn from lo..hi."""
+def batch_uneven(nprob: int = 64, nsteps: int = 400, lo: int = 128, hi: int = 384,
+                 L: float = 4000.0) -> List[Problem]:
+    """Independent VTI-recipe problems with per-axis sizes drawn from lo..hi."""
     out = []
     for s in range(nprob):
         rng = rng_for(3, s)
@@ -208,7 +210,7 @@ def c3(nprob: int = 64, nsteps: int = 400, lo: int = 128, hi: int = 384,
         g = Grid(nx=nx, nz=nz, nth=nth, dx=L / nx, dz=L / nz)
         med = vti_medium(rng, g, L)
         src = Source(xs=0.5 * L, zs=0.5 * L, r0=4.0 * max(g.dx, g.dz), beta=1.0 / (2.0 * L))
-        out.append(Problem(f"c3-batch-{s}", g, med, src, nsteps, hz([20.0]), dtype="f32"))
+        out.append(Problem(f"batch-{s}", g, med, src, nsteps, hz([20.0]), dtype="f32"))
     return out
 
 
@@ -217,7 +219,7 @@ def smooth_field(rng: np.random.Generator, g: Grid, sigma_m: float = 300.0) -> n
     return _smoothed_uniform(rng, g, sigma_m, -1.0, 1.0)
 
 
-def c4(n: int = 256, nsteps: int = 600, L: float = 4000.0, nsrc: int = 16, nrec: int = 128,
+def adjoint_sources(n: int = 256, nsteps: int = 600, L: float = 4000.0, nsrc: int = 16, nrec: int = 128,
        nth: Optional[int] = None) -> List[Problem]:
     """Adjoint workload: shared medium, many sources, receivers at depth.
 
@@ -234,6 +236,6 @@ def c4(n: int = 256, nsteps: int = 600, L: float = 4000.0, nsrc: int = 16, nrec:
     out = []
     for s in range(nsrc):
         src = Source(xs=float(xs[s]), zs=0.1 * L, r0=4.0 * g.dx, beta=1.0 / (2.0 * L))
-        out.append(Problem(f"c4-adjoint-{s}", g, med, src, nsteps, hz([20.0]), dtype="f32",
+        out.append(Problem(f"adjoint-src-{s}", g, med, src, nsteps, hz([20.0]), dtype="f32",
                            receivers=rx, extra={"true_medium": true}))
     return out
