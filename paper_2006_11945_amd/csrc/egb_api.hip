@@ -108,6 +108,7 @@ egb_status egb_liouville_step(const egb_grid* g, const void* vel3d, const egb_so
     if (!(dt > 0.0) || !isfinite(dt)) return EGB_ECFL;
     if (nsteps == 0) return EGB_OK;
     if (work_bytes < egb_workspace_size(g, EGB_OP_STEP)) return EGB_EWORKSPACE;
+    if (!stage_fits_32bit(grid_args(*g), g->dtype)) return EGB_EUNSUPPORTED;
     char* w = static_cast<char*>(work);
     void* U1 = w;
     void* U2 = w + align256(state_bytes(*g));

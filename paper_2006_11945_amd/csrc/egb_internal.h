@@ -65,6 +65,8 @@ struct StageArgs {
     double xs, zs, r02;
 };
 hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s);
+// The stage kernel addresses each array with 32-bit byte offsets.
+bool stage_fits_32bit(const GridArgs& g, int dtype);
 
 // Beam superposition.
 struct BeamArgs {
