@@ -37,7 +37,24 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="grid size per axis (256 = the quoted workload)")
     ap.add_argument("--rk-steps", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before the run, copy a device buffer of this size (a plain copy kernel of known "
+                         "size, to scale HBM byte counters)")
     return ap.parse_args()
+
+
+def measured_traffic(n):
+    """HBM bytes per stage launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs, only while the kernel sources are unchanged since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_stage_vti256_traffic.json")
+    if n != 256 or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    csrc = os.path.join(ROOT, "paper_2006_11945_amd", "csrc")
+    src = open(os.path.join(csrc, "liouville.hip"), "rb").read() + open(os.path.join(csrc, "egb_device.h"), "rb").read()
+    return rec["hbm_bytes_per_launch"] if hashlib.sha256(src).hexdigest() == rec["source_sha256"] else None
 
 
 def cpu_baseline(problem):
@@ -71,6 +88,13 @@ def main():
     import paper_2006_11945_amd as egb
     import workloads as W
 
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib << 18  # float32 elements
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     p = W.vti_256(n=args.n, nsteps=args.rk_steps)
     L = p.grid.nx * p.grid.dx
     rx = np.stack([np.linspace(0.1 * L, 0.9 * L, 128), np.full(128, 0.9 * L)], axis=1)
@@ -132,7 +156,7 @@ def main():
                    "grid": [p.grid.nx, p.grid.nz, p.grid.nth], "rk3_steps": p.nsteps,
                    "frequencies": len(p.omegas), "receivers": 128, "psi_dtype": "f64"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(args.n),
                      "kernel": "k_stage (one SSP-RK3 stage)", "avg_launch_ms": stage_ms,
                      "flop_per_cell_stage": FLOP_CELL_STAGE},
         "march_ms": float(np.mean(march_ms)),
