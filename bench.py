@@ -37,10 +37,56 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="grid size per axis (256 = the quoted workload)")
     ap.add_argument("--rk-steps", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=10,
+                    help="RK3 steps for the batched-vs-sequential comparison on the 64-problem uneven workload "
+                         "(0 skips it)")
+    ap.add_argument("--batched-problems", type=int, default=64)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the run, copy a device buffer of this size (a plain copy kernel of known "
                          "size, to scale HBM byte counters)")
     return ap.parse_args()
+
+
+def batched_vs_sequential(nprob, nsteps):
+    """64 independent VTI problems with per-axis sizes uniform in 128..384:
+    one graph-captured persistent march of all of them against marching them
+    one after another with the single-problem call (same GPU, same steps)."""
+    import torch
+
+    import paper_2006_11945_amd as egb
+    import workloads as W
+
+    probs = W.batch_uneven(nprob=nprob, nsteps=nsteps)
+    solvers = []
+    for p in probs:
+        s = egb.Solver(p, "cuda:0")
+        s.velocity()
+        s.init()
+        solvers.append(s)
+    cells = sum(p.grid.ncell for p in probs)
+    arr = egb.make_problem_array(solvers)
+    work = egb.alloc_bytes(egb.workspace_size_batched(arr), "cuda:0")
+    egb.egb_liouville_step_batched(arr, 1, work)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    egb.egb_liouville_step_batched(arr, nsteps, work)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    del work
+    step_work = egb.alloc_bytes(max(egb.workspace_size(s.eg, egb.EGB_OP_STEP) for s in solvers), "cuda:0")
+    for s in solvers:
+        s.work_step = step_work
+    solvers[0].step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.step(nsteps)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    return {"problems": nprob, "cells": cells, "rk3_steps": nsteps,
+            "batched_cell_updates_per_s": cells * nsteps / t_batch,
+            "sequential_cell_updates_per_s": cells * nsteps / t_seq,
+            "batched_over_sequential": t_seq / t_batch}
 
 
 def measured_traffic(n):
@@ -162,6 +208,11 @@ def main():
         "march_ms": float(np.mean(march_ms)),
         "march_cell_updates_per_s": cells * p.nsteps / (float(np.mean(march_ms)) * 1e-3),
     }
+    del s, out
+    torch.cuda.empty_cache()
+    if args.batched_steps > 0:
+        res["batched"] = batched_vs_sequential(args.batched_problems, args.batched_steps)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(W.vti_256(n=args.n, nsteps=1))
     print(json.dumps(res), flush=True)

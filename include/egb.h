@@ -145,6 +145,30 @@ egb_status egb_beam_sum(const egb_grid *g, const void *coeff2d, const void *vel3
                         const void *state, const double *omegas, int32_t nw, void *out, void *work,
                         size_t work_bytes, hipStream_t stream);
 
+/* One problem of a batched march (independent source, own grid and dt). */
+typedef struct {
+    egb_grid grid;
+    const void *vel3d; /* from egb_hamiltonian_velocity for this grid */
+    egb_source src;
+    void *state;       /* in/out */
+    double dt;         /* this problem's pseudo-time step */
+} egb_problem;
+
+/* Workspace for egb_liouville_step_batched: the device problem table plus two
+ * RK stage buffers per problem.  0 on bad arguments. */
+size_t egb_workspace_size_batched(const egb_problem *probs, int32_t nprob);
+
+/* nsteps SSP-RK3 steps of every problem in `probs` (HOST array, nprob >= 1;
+ * same dtype for all), the same scheme as egb_liouville_step.  All problems
+ * advance together: each stage is ONE launch over a single tile queue that
+ * spans all grids (each block walks the queue from its index with a stride of
+ * the grid size; by default the grid covers the queue), and the 3 * nsteps
+ * launches are captured in one hipGraph replayed on `stream`.  Synchronises `stream` before returning
+ * (the graph is destroyed).  Errors as egb_liouville_step; EGB_EINVAL if the
+ * dtypes differ. */
+egb_status egb_liouville_step_batched(const egb_problem *probs, int32_t nprob, int32_t nsteps, void *work,
+                                      size_t work_bytes, hipStream_t stream);
+
 /* First-arrival traveltime at receivers on the level set phi1 = 0 (eq. 35):
  * bilinear in (x, z) per theta plane, linear root of phi1 in theta, the
  * smallest interpolated psi > 0 (lowest theta on ties); NaN if no arrival.

@@ -48,6 +48,11 @@ class EgbSource(ctypes.Structure):
     _fields_ = [("xs", ctypes.c_double), ("zs", ctypes.c_double), ("r0", ctypes.c_double), ("beta", ctypes.c_double)]
 
 
+class EgbProblem(ctypes.Structure):
+    _fields_ = [("grid", EgbGrid), ("vel3d", ctypes.c_void_p), ("src", EgbSource), ("state", ctypes.c_void_p),
+                ("dt", ctypes.c_double)]
+
+
 class EgbError(RuntimeError):
     def __init__(self, fn: str, status: int):
         super().__init__(f"{fn} failed: {status} ({_lib.egb_status_string(status).decode()})")
@@ -69,6 +74,10 @@ def _load():
     L.egb_liouville_step.argtypes = [G, vp, S, vp, vp, sz, d, i32, vp]
     L.egb_beam_sum.argtypes = [G, vp, vp, S, vp, dp, i32, vp, vp, sz, vp]
     L.egb_pick_receivers.argtypes = [G, vp, vp, i32, vp, vp]
+    P = ctypes.POINTER(EgbProblem)
+    L.egb_workspace_size_batched.argtypes = [P, i32]; L.egb_workspace_size_batched.restype = sz
+    L.egb_liouville_step_batched.argtypes = [P, i32, i32, vp, sz, vp]
+    L.egb_liouville_step_batched.restype = ctypes.c_int
     for name in ("egb_hamiltonian_velocity", "egb_init_state", "egb_liouville_step", "egb_beam_sum",
                  "egb_pick_receivers"):
         getattr(L, name).restype = ctypes.c_int
@@ -157,6 +166,24 @@ def egb_pick_receivers(eg, state, rx, t_out, stream=None):
     n = 0 if rx is None else rx.shape[0]
     rc = _lib.egb_pick_receivers(ctypes.byref(eg), _ptr(state), _ptr(rx), n, _ptr(t_out), _stream(stream))
     _check("egb_pick_receivers", rc)
+
+
+def make_problem_array(solvers, dts=None):
+    """ctypes array of egb_problem from Solver objects (their own dt_cfl unless given)."""
+    arr = (EgbProblem * len(solvers))()
+    for i, s in enumerate(solvers):
+        dt = s.dt_cfl if dts is None else dts[i]
+        arr[i] = EgbProblem(s.eg, s.vel3d.data_ptr(), s.src, s.state.data_ptr(), float(dt))
+    return arr
+
+
+def workspace_size_batched(arr) -> int:
+    return _lib.egb_workspace_size_batched(arr, len(arr))
+
+
+def egb_liouville_step_batched(arr, nsteps: int, work, stream=None):
+    rc = _lib.egb_liouville_step_batched(arr, len(arr), int(nsteps), _ptr(work), work.numel(), _stream(stream))
+    _check("egb_liouville_step_batched", rc)
 
 
 # ------------------------------------------------------------------ views

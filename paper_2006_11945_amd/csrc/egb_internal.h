@@ -68,6 +68,15 @@ hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s)
 // The stage kernel addresses each array with 32-bit byte offsets.
 bool stage_fits_32bit(const GridArgs& g, int dtype);
 
+// Batched march (see liouville.hip).
+size_t batch_item_bytes();
+int batch_item_fill(void* item, const GridArgs& g, int dtype, const void* vel, void* state, void* U1, void* U2,
+                    double dt, double xs, double zs, double r02);
+hipError_t launch_stage_batched(const void* items, const int* first, int nprob, int total, int dtype, int stage,
+                                int grid, hipStream_t s);
+int stage_block_threads(int dtype);
+const void* stage_batched_kernel(int dtype, int stage);
+
 // Beam superposition.
 struct BeamArgs {
     GridArgs g;

@@ -112,22 +112,33 @@ struct TileArgs {
     unsigned state_bytes, vel_bytes;
 };
 
+// XCD-aware numbering: hardware block b runs on XCD b % 8; give each XCD a
+// contiguous range of logical tiles (a bijection of [0, n)).
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    const int q8 = n >> 3, r8 = n & 7, xcd = b & 7;
+    return xcd * q8 + min(xcd, r8) + (b >> 3);
+}
+
+template <typename R, int TK>
+struct StageSmem {
+    static constexpr int PLANE = (TK + 6) * PZ;
+    R r[2][5 * PLANE];
+    double p[2][PLANE];
+};
+
+// One (z, theta) tile x one x chunk of an RK stage; `logical` numbers the
+// tile within its problem.
 template <typename R, int STAGE, int TK>
-__global__ __launch_bounds__(64 * TK) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
-void k_stage(StageArgs a, TileArgs t) {
-    constexpr int PK = TK + 6;
-    constexpr int PLANE = PK * PZ;
+__device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t, int logical,
+                                           StageSmem<R, TK>& sm) {
+    constexpr int PLANE = StageSmem<R, TK>::PLANE;
     constexpr int NHALO = 6 * TZ + 6 * TK;
     static_assert(NHALO <= 64 * TK, "one halo slot per thread");
     constexpr unsigned ES = sizeof(R);
-    __shared__ R sR[2][5 * PLANE];
-    __shared__ double sP[2][PLANE];
+    auto& sR = sm.r;
+    auto& sP = sm.p;
 
     const GridArgs& g = a.g;
-    // XCD-aware block numbering: hardware block b runs on XCD b % 8; give each
-    // XCD a contiguous range of logical tiles.
-    const int b = blockIdx.x, q8 = t.nblocks >> 3, r8 = t.nblocks & 7, xcd = b & 7;
-    const int logical = xcd * q8 + min(xcd, r8) + (b >> 3);
     const int tzi = logical % t.ntz;
     const int rest = logical / t.ntz;
     const int tki = rest % t.ntk;
@@ -310,6 +321,40 @@ void k_stage(StageArgs a, TileArgs t) {
     }
 }
 
+template <typename R, int STAGE, int TK>
+__global__ __launch_bounds__(64 * TK) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
+void k_stage(StageArgs a, TileArgs t) {
+    __shared__ StageSmem<R, TK> sm;
+    stage_tile<R, STAGE, TK>(a, t, xcd_remap(blockIdx.x, t.nblocks), sm);
+}
+
+// Batched march: a persistent grid walks one queue of tiles spanning every
+// problem (uneven grids, own buffers and dt).  first[p] is the first queue
+// index of problem p (first[nprob] = total).
+struct BatchItem {
+    StageArgs a[3];  // stage 0, 1, 2 buffers of this problem
+    TileArgs t;
+};
+
+template <typename R, int STAGE, int TK>
+__global__ __launch_bounds__(64 * TK) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
+void k_stage_batched(const BatchItem* __restrict__ items, const int* __restrict__ first, int nprob, int total) {
+    __shared__ StageSmem<R, TK> sm;
+    for (int q = blockIdx.x; q < total; q += gridDim.x) {
+        const int t = xcd_remap(q, total);
+        int lo = 0, hi = nprob;  // first[lo] <= t < first[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (first[mid] <= t) lo = mid; else hi = mid;
+        }
+        // private copies: the stage's stores cannot alias them, so they stay in scalar registers
+        const StageArgs a = items[lo].a[STAGE];
+        const TileArgs ta = items[lo].t;
+        __syncthreads();  // the previous tile's last LDS reads are done
+        stage_tile<R, STAGE, TK>(a, ta, t - first[lo], sm);
+    }
+}
+
 unsigned long long state_bytes_of(const GridArgs& g, size_t es) {
     return (unsigned long long)g.stride * (5ull * es + 8ull);
 }
@@ -347,7 +392,69 @@ int choose_kx(const GridArgs& g, int tk) {
     return kx;
 }
 
+template <typename R, int TK>
+hipError_t launch_batched_t(const void* items, const int* first, int nprob, int total, int stage, int grid,
+                            hipStream_t s) {
+    const dim3 block(TZ, TK);
+    const BatchItem* it = static_cast<const BatchItem*>(items);
+    switch (stage) {
+        case 0: k_stage_batched<R, 0, TK><<<grid, block, 0, s>>>(it, first, nprob, total); break;
+        case 1: k_stage_batched<R, 1, TK><<<grid, block, 0, s>>>(it, first, nprob, total); break;
+        default: k_stage_batched<R, 2, TK><<<grid, block, 0, s>>>(it, first, nprob, total); break;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
+
+size_t batch_item_bytes() { return sizeof(BatchItem); }
+
+// Fill the host-side item for one problem; returns its tile count.
+int batch_item_fill(void* item, const GridArgs& g, int dtype, const void* vel, void* state, void* U1, void* U2,
+                    double dt, double xs, double zs, double r02) {
+    BatchItem& it = *static_cast<BatchItem*>(item);
+    const int tk = dtype == EGB_F64 ? 8 : 12;
+    const size_t es = dtype == EGB_F64 ? 8 : 4;
+    TileArgs t;
+    t.ntz = (g.nz + TZ - 1) / TZ;
+    t.ntk = (g.nth + tk - 1) / tk;
+    t.kx = choose_kx(g, tk);
+    t.nxc = (g.nx + t.kx - 1) / t.kx;
+    t.nblocks = t.ntz * t.ntk * t.nxc;
+    t.state_bytes = (unsigned)state_bytes_of(g, es);
+    t.vel_bytes = (unsigned)(7ull * (unsigned long long)g.stride * es);
+    it.t = t;
+    void* in[3] = {state, U1, U2};
+    void* out[3] = {U1, U2, state};
+    for (int s = 0; s < 3; ++s) {
+        it.a[s].g = g;
+        it.a[s].vel = vel;
+        it.a[s].U0 = state;
+        it.a[s].Uin = in[s];
+        it.a[s].Uout = out[s];
+        it.a[s].dt = dt;
+        it.a[s].xs = xs;
+        it.a[s].zs = zs;
+        it.a[s].r02 = r02;
+    }
+    return t.nblocks;
+}
+
+hipError_t launch_stage_batched(const void* items, const int* first, int nprob, int total, int dtype, int stage,
+                                int grid, hipStream_t s) {
+    if (dtype == EGB_F64) return launch_batched_t<double, 8>(items, first, nprob, total, stage, grid, s);
+    return launch_batched_t<float, 12>(items, first, nprob, total, stage, grid, s);
+}
+
+int stage_block_threads(int dtype) { return dtype == EGB_F64 ? 64 * 8 : 64 * 12; }
+
+const void* stage_batched_kernel(int dtype, int stage) {
+    if (dtype == EGB_F64)
+        return stage == 0 ? (const void*)k_stage_batched<double, 0, 8>
+                          : stage == 1 ? (const void*)k_stage_batched<double, 1, 8> : (const void*)k_stage_batched<double, 2, 8>;
+    return stage == 0 ? (const void*)k_stage_batched<float, 0, 12>
+                      : stage == 1 ? (const void*)k_stage_batched<float, 1, 12> : (const void*)k_stage_batched<float, 2, 12>;
+}
 
 bool stage_fits_32bit(const GridArgs& g, int dtype) {
     const size_t es = dtype == EGB_F64 ? 8 : 4;
