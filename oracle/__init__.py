@@ -156,12 +156,14 @@ def pick(grid, U, receivers) -> np.ndarray:
     return out
 
 
-def solve(problem, nsteps=None):
-    """Full oracle pipeline: table, velocity, data, march.  Returns a dict."""
+def solve(problem, nsteps=None, dt=None):
+    """Full oracle pipeline: table, velocity, data, march (at the CFL step of
+    this medium unless ``dt`` is given).  Returns a dict."""
     g = problem.grid
     tab = medium_table(g, problem.medium)
-    vel, vaux, dt = velocity(g, tab)
+    vel, vaux, dt_cfl = velocity(g, tab)
+    dt = dt_cfl if dt is None else float(dt)
     U0 = init_state(g, tab, problem.source)
     ns = problem.nsteps if nsteps is None else nsteps
     U = march(g, vel, problem.source, U0, dt, ns) if ns > 0 else U0
-    return {"tab": tab, "vel": vel, "vaux": vaux, "dt": dt, "U0": U0, "U": U, "nsteps": ns}
+    return {"tab": tab, "vel": vel, "vaux": vaux, "dt": dt, "dt_cfl": dt_cfl, "U0": U0, "U": U, "nsteps": ns}
