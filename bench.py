@@ -41,6 +41,8 @@ def parse():
                     help="RK3 steps for the batched-vs-sequential comparison on the 64-problem uneven workload "
                          "(0 skips it)")
     ap.add_argument("--batched-problems", type=int, default=64)
+    ap.add_argument("--adjoint-sources", type=int, default=2,
+                    help="sources of the 16-source adjoint workload to time (0 skips it)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the run, copy a device buffer of this size (a plain copy kernel of known "
                          "size, to scale HBM byte counters)")
@@ -87,6 +89,59 @@ def batched_vs_sequential(nprob, nsteps):
             "batched_cell_updates_per_s": cells * nsteps / t_batch,
             "sequential_cell_updates_per_s": cells * nsteps / t_seq,
             "batched_over_sequential": t_seq / t_batch}
+
+
+def adjoint_vs_forward(nsrc, nsteps, n=256):
+    """Traveltime misfit at 128 receivers for `nsrc` of the 16 sources on the
+    VTI medium: forward (kinematic march with checkpoints every 16 steps +
+    pick) and backward (pick adjoint, recomputation, adjoint steps, medium
+    gradient) timed separately, next to the plain full-plane forward march."""
+    import numpy as np
+    import torch
+
+    import paper_2006_11945_amd as egb
+    import workloads as W
+
+    probs = W.adjoint_sources(n=n, nsteps=nsteps)
+    true = probs[0].extra["true_medium"]
+    dev = "cuda:0"
+    mk = lambda m, grad=False: [torch.tensor(np.asarray(a, dtype=np.float64), device=dev, requires_grad=grad)
+                                for a in (m.vp0, m.eps, m.delta, m.tilt)]
+    base = egb.Solver(probs[0], dev)
+    dt = base.velocity()
+    t_fwd = t_bwd = t_plain = 0.0
+    for p in probs[:nsrc]:
+        spec = {"grid": p.grid, "source": p.source, "receivers": p.receivers, "nsteps": nsteps, "vs_ratio": 0.5,
+                "dtype": "f32", "checkpoint_every": 16, "dt": dt}
+        with torch.no_grad():
+            t_obs = egb.traveltime(*mk(true), spec)
+        ts = mk(p.medium, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t = egb.traveltime(*ts, spec)
+        ok = ~(torch.isnan(t) | torch.isnan(t_obs))
+        J = torch.sum((t[ok] - t_obs[ok]) ** 2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t_fwd += t1 - t0
+        t_bwd += t2 - t1
+        s = egb.Solver(p, dev)
+        s.velocity()
+        s.init()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        s.step(nsteps, dt=dt)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t3
+        del s, ts, t, J
+        torch.cuda.empty_cache()
+    cu = probs[0].grid.ncell * nsteps * nsrc
+    return {"sources": nsrc, "rk3_steps": nsteps, "receivers": 128, "checkpoint_every": 16,
+            "forward_s": t_fwd, "backward_s": t_bwd, "plain_forward_s": t_plain,
+            "backward_cell_updates_per_s": cu / t_bwd, "backward_over_plain_forward": t_bwd / t_plain}
 
 
 def measured_traffic(n):
@@ -212,6 +267,9 @@ def main():
     torch.cuda.empty_cache()
     if args.batched_steps > 0:
         res["batched"] = batched_vs_sequential(args.batched_problems, args.batched_steps)
+        torch.cuda.empty_cache()
+    if args.adjoint_sources > 0:
+        res["adjoint"] = adjoint_vs_forward(args.adjoint_sources, args.rk_steps, args.n)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(W.vti_256(n=args.n, nsteps=1))

@@ -176,6 +176,50 @@ egb_status egb_liouville_step_batched(const egb_problem *probs, int32_t nprob, i
 egb_status egb_pick_receivers(const egb_grid *g, const void *state, const double *rx, int32_t nr, double *t_out,
                               hipStream_t stream);
 
+/* ----------------------------------------------- traveltime adjoint
+ * The adjoint covers objectives that depend on the traveltime field, such as
+ * the misfit J = sum_r (t_r - t_obs_r)^2 of egb_pick_receivers.  phi1 and psi
+ * are transported without coupling to (C, B) (eqs. 16, 19), so only those two
+ * planes carry adjoint values and only the Liouville velocity V (eqs. 8-9, 12)
+ * is differentiated.  `lambda` buffers use the state layout
+ * (egb_state_bytes; planes EGB_PHI1 and EGB_PSI are read and written, the
+ * others are left untouched); `gvel` is [3][egb_plane_stride] in the grid
+ * dtype (dJ/dV_x, dJ/dV_z, dJ/dV_theta), egb_gvel_bytes() bytes.  The
+ * caller zero-initialises both before the reverse sweep. */
+size_t egb_gvel_bytes(const egb_grid *g);
+
+/* egb_liouville_step restricted to the planes phi1 and psi (identical
+ * values for them; the DRT planes are left untouched). */
+egb_status egb_liouville_step_kinematic(const egb_grid *g, const void *vel3d, const egb_source *src, void *state,
+                                        void *work, size_t work_bytes, double dt, int32_t nsteps,
+                                        hipStream_t stream);
+
+/* Adjoint of egb_pick_receivers: lambda += sum_r tbar[r] d t_r / d(phi1, psi)
+ * evaluated on `state` (the final state of the march).  rx, tbar: device
+ * float64 [nr][2] and [nr]; receivers without an arrival contribute nothing. */
+egb_status egb_pick_adjoint(const egb_grid *g, const void *state, const double *rx, int32_t nr,
+                            const double *tbar, void *lambda, hipStream_t stream);
+
+/* Exact discrete adjoint of one SSP-RK3 step of the march (WENO5 weights
+ * differentiated, upwind sides frozen, ball cells pass their adjoint to the
+ * step's start, ghosts transposed).  In: state_n = U^n (the step's start),
+ * lambda = dJ/dU^{n+1}.  Out: lambda = dJ/dU^n; gvel += dJ/dV through this
+ * step.  The step's inner stages are recomputed from state_n.
+ * work: egb_workspace_size(g, EGB_OP_ADJOINT). */
+egb_status egb_adjoint_step(const egb_grid *g, const void *vel3d, const egb_source *src, const void *state_n,
+                            void *lambda, void *gvel, void *work, size_t work_bytes, double dt,
+                            hipStream_t stream);
+
+/* Medium gradient from the reverse sweep: dJ/dV (gvel, accumulated over all
+ * steps) through the velocity (eqs. 3-5, 7-12) and the medium table, plus
+ * dJ/dU^0 (lambda0) through the point-source data (medium frozen at the
+ * source), then the Thomsen map.  Out: grad, device float64 [4][nx][nz]
+ * = dJ/d(vp0, eps, delta, tilt).  The time step is held fixed.
+ * work: egb_workspace_size(g, EGB_OP_ADJOINT). */
+egb_status egb_adjoint_medium(const egb_grid *g, const egb_medium *m, const void *coeff2d, const egb_source *src,
+                              const void *gvel, const void *lambda0, double *grad, void *work, size_t work_bytes,
+                              hipStream_t stream);
+
 /* Human-readable text for a status code (static storage). */
 const char *egb_status_string(int32_t status);
 

@@ -74,6 +74,13 @@ def _load():
     L.egb_liouville_step.argtypes = [G, vp, S, vp, vp, sz, d, i32, vp]
     L.egb_beam_sum.argtypes = [G, vp, vp, S, vp, dp, i32, vp, vp, sz, vp]
     L.egb_pick_receivers.argtypes = [G, vp, vp, i32, vp, vp]
+    L.egb_gvel_bytes.argtypes = [G]; L.egb_gvel_bytes.restype = sz
+    L.egb_liouville_step_kinematic.argtypes = [G, vp, S, vp, vp, sz, d, i32, vp]
+    L.egb_pick_adjoint.argtypes = [G, vp, vp, i32, vp, vp, vp]
+    L.egb_adjoint_step.argtypes = [G, vp, S, vp, vp, vp, vp, sz, d, vp]
+    L.egb_adjoint_medium.argtypes = [G, M, vp, S, vp, vp, vp, vp, sz, vp]
+    for name in ("egb_liouville_step_kinematic", "egb_pick_adjoint", "egb_adjoint_step", "egb_adjoint_medium"):
+        getattr(L, name).restype = ctypes.c_int
     P = ctypes.POINTER(EgbProblem)
     L.egb_workspace_size_batched.argtypes = [P, i32]; L.egb_workspace_size_batched.restype = sz
     L.egb_liouville_step_batched.argtypes = [P, i32, i32, vp, sz, vp]
@@ -166,6 +173,33 @@ def egb_pick_receivers(eg, state, rx, t_out, stream=None):
     n = 0 if rx is None else rx.shape[0]
     rc = _lib.egb_pick_receivers(ctypes.byref(eg), _ptr(state), _ptr(rx), n, _ptr(t_out), _stream(stream))
     _check("egb_pick_receivers", rc)
+
+
+def gvel_bytes(eg) -> int: return _lib.egb_gvel_bytes(ctypes.byref(eg))
+
+
+def egb_liouville_step_kinematic(eg, vel3d, src: EgbSource, state, work, dt: float, nsteps: int, stream=None):
+    rc = _lib.egb_liouville_step_kinematic(ctypes.byref(eg), _ptr(vel3d), ctypes.byref(src), _ptr(state), _ptr(work),
+                                           work.numel(), float(dt), int(nsteps), _stream(stream))
+    _check("egb_liouville_step_kinematic", rc)
+
+
+def egb_pick_adjoint(eg, state, rx, tbar, lam, stream=None):
+    rc = _lib.egb_pick_adjoint(ctypes.byref(eg), _ptr(state), _ptr(rx), rx.shape[0], _ptr(tbar), _ptr(lam),
+                               _stream(stream))
+    _check("egb_pick_adjoint", rc)
+
+
+def egb_adjoint_step(eg, vel3d, src: EgbSource, state_n, lam, gvel, work, dt: float, stream=None):
+    rc = _lib.egb_adjoint_step(ctypes.byref(eg), _ptr(vel3d), ctypes.byref(src), _ptr(state_n), _ptr(lam), _ptr(gvel),
+                               _ptr(work), work.numel(), float(dt), _stream(stream))
+    _check("egb_adjoint_step", rc)
+
+
+def egb_adjoint_medium(eg, medium: "DeviceMedium", coeff2d, src: EgbSource, gvel, lam0, grad, work, stream=None):
+    rc = _lib.egb_adjoint_medium(ctypes.byref(eg), ctypes.byref(medium.struct()), _ptr(coeff2d), ctypes.byref(src),
+                                 _ptr(gvel), _ptr(lam0), _ptr(grad), _ptr(work), work.numel(), _stream(stream))
+    _check("egb_adjoint_medium", rc)
 
 
 def make_problem_array(solvers, dts=None):
@@ -286,3 +320,78 @@ class Solver:
 
     def vel_planes(self) -> dict:
         return vel_views(self.eg, self.vel3d)
+
+
+class TravelTime(torch.autograd.Function):
+    """First-arrival traveltimes at receivers as a differentiable function of
+    the gridded medium (vp0, eps, delta, tilt; float64 device tensors [nx][nz]).
+
+    forward: medium table and velocity, point-source data, ``nsteps``
+    kinematic RK3 steps (phi1, psi) keeping a state every ``checkpoint_every``
+    steps, then the pick.  backward: the pick adjoint, then segment by segment
+    in reverse the forward states are recomputed from the checkpoint and the
+    adjoint step is applied, and finally the medium gradient.  The time step
+    is fixed (the CFL step of the forward medium unless ``spec['dt']`` is set).
+
+    spec: grid (nx, nz, nth, x0, z0, dx, dz), source (xs, zs, r0, beta),
+    receivers (numpy [nr][2]), nsteps, vs_ratio, dtype ("f32" / "f64"),
+    checkpoint_every (default 16), dt (optional).
+    """
+
+    @staticmethod
+    def forward(ctx, vp0, eps, delta, tilt, spec):
+        dev = vp0.device
+        eg = make_grid(spec["grid"], spec.get("dtype", "f32"))
+        src = make_source(spec["source"])
+        med = DeviceMedium(vp0.contiguous(), eps.contiguous(), delta.contiguous(), tilt.contiguous(),
+                           float(spec.get("vs_ratio", 0.5)))
+        coeff2d = alloc_bytes(coeff2d_bytes(eg), dev)
+        vel3d = alloc_bytes(vel3d_bytes(eg), dev)
+        wv = alloc_bytes(workspace_size(eg, EGB_OP_VELOCITY), dev)
+        dt = egb_hamiltonian_velocity(eg, med, coeff2d, vel3d, wv)
+        dt = float(spec["dt"]) if spec.get("dt") is not None else dt
+        state = alloc_bytes(state_bytes(eg), dev)
+        egb_init_state(eg, coeff2d, src, state)
+        work = alloc_bytes(workspace_size(eg, EGB_OP_STEP), dev)
+        K = int(spec.get("checkpoint_every", 16))
+        nsteps = int(spec["nsteps"])
+        ckpts = []
+        done = 0
+        while done < nsteps:
+            ckpts.append((done, state.clone()))
+            n = min(K, nsteps - done)
+            egb_liouville_step_kinematic(eg, vel3d, src, state, work, dt, n)
+            done += n
+        rx = torch.as_tensor(np.ascontiguousarray(spec["receivers"], dtype=np.float64), device=dev).reshape(-1, 2)
+        t = torch.empty(rx.shape[0], dtype=torch.float64, device=dev)
+        egb_pick_receivers(eg, state, rx, t)
+        ctx.egb = dict(eg=eg, src=src, med=med, coeff2d=coeff2d, vel3d=vel3d, dt=dt, K=K, nsteps=nsteps,
+                       ckpts=ckpts, final=state, rx=rx, work=work)
+        return t
+
+    @staticmethod
+    def backward(ctx, tbar):
+        d = ctx.egb
+        eg, src, dev = d["eg"], d["src"], d["final"].device
+        lam = torch.zeros(state_bytes(eg), dtype=torch.uint8, device=dev)
+        gvel = torch.zeros(gvel_bytes(eg), dtype=torch.uint8, device=dev)
+        tb = torch.nan_to_num(tbar.detach().to(torch.float64).contiguous(), nan=0.0)
+        egb_pick_adjoint(eg, d["final"], d["rx"], tb, lam)
+        wadj = alloc_bytes(workspace_size(eg, EGB_OP_ADJOINT), dev)
+        for start, ck in reversed(d["ckpts"]):
+            n = min(d["K"], d["nsteps"] - start)
+            states = [ck]
+            cur = ck.clone()
+            for _ in range(n - 1):
+                egb_liouville_step_kinematic(eg, d["vel3d"], src, cur, d["work"], d["dt"], 1)
+                states.append(cur.clone())
+            for st in reversed(states):
+                egb_adjoint_step(eg, d["vel3d"], src, st, lam, gvel, wadj, d["dt"])
+        grad = torch.empty((4, eg.nx, eg.nz), dtype=torch.float64, device=dev)
+        egb_adjoint_medium(eg, d["med"], d["coeff2d"], src, gvel, lam, grad, wadj)
+        return grad[0], grad[1], grad[2], grad[3], None
+
+
+def traveltime(vp0, eps, delta, tilt, spec):
+    """Differentiable first-arrival traveltimes (see TravelTime)."""
+    return TravelTime.apply(vp0, eps, delta, tilt, spec)

@@ -66,6 +66,12 @@ size_t egb_workspace_size(const egb_grid* g, int32_t op) {
         case EGB_OP_STEP: return 2 * align256(state_bytes(*g));
         case EGB_OP_BEAM:
             return beam_counts_bytes(*g) + (size_t)(g->nx + g->nz) * beam_cap_default(*g) * beam_record_bytes();
+        case EGB_OP_ADJOINT: {
+            const size_t step = 4 * align256(state_bytes(*g)) + align256(adjoint_packet_bytes(*g));
+            const size_t med = align256((size_t)15 * g->nx * g->nz * sizeof(double)) +
+                               align256((size_t)g->nth * EGB_NFIELD * sizeof(double));
+            return step > med ? step : med;
+        }
         default: return 0;
     }
 }
@@ -102,8 +108,8 @@ egb_status egb_init_state(const egb_grid* g, const void* coeff2d, const egb_sour
     return hip_status(launch_init_state(grid_args(*g), g->dtype, static_cast<const double*>(coeff2d), *src, state, stream));
 }
 
-egb_status egb_liouville_step(const egb_grid* g, const void* vel3d, const egb_source* src, void* state, void* work,
-                              size_t work_bytes, double dt, int32_t nsteps, hipStream_t stream) {
+static egb_status liouville_steps(const egb_grid* g, const void* vel3d, const egb_source* src, void* state, void* work,
+                                  size_t work_bytes, double dt, int32_t nsteps, hipStream_t stream, bool kin) {
     if (!grid_ok(g) || !vel3d || !state || !source_ok(src) || nsteps < 0) return EGB_EINVAL;
     if (nsteps > 0 && !work) return EGB_EINVAL;
     if (!aligned16(vel3d) || !aligned16(state) || (work && !aligned16(work))) return EGB_EINVAL;
@@ -125,18 +131,103 @@ egb_status egb_liouville_step(const egb_grid* g, const void* vel3d, const egb_so
         sa.U0 = state;
         sa.Uin = state;
         sa.Uout = U1;
-        hipError_t e = launch_stage(sa, g->dtype, 0, stream);
+        hipError_t e = launch_stage(sa, g->dtype, 0, stream, kin);
         if (e != hipSuccess) return EGB_EHIP;
         sa.Uin = U1;
         sa.Uout = U2;
-        e = launch_stage(sa, g->dtype, 1, stream);
+        e = launch_stage(sa, g->dtype, 1, stream, kin);
         if (e != hipSuccess) return EGB_EHIP;
         sa.Uin = U2;
         sa.Uout = state;
-        e = launch_stage(sa, g->dtype, 2, stream);
+        e = launch_stage(sa, g->dtype, 2, stream, kin);
         if (e != hipSuccess) return EGB_EHIP;
     }
     return EGB_OK;
+}
+
+egb_status egb_liouville_step(const egb_grid* g, const void* vel3d, const egb_source* src, void* state, void* work,
+                              size_t work_bytes, double dt, int32_t nsteps, hipStream_t stream) {
+    return liouville_steps(g, vel3d, src, state, work, work_bytes, dt, nsteps, stream, false);
+}
+
+egb_status egb_liouville_step_kinematic(const egb_grid* g, const void* vel3d, const egb_source* src, void* state,
+                                        void* work, size_t work_bytes, double dt, int32_t nsteps,
+                                        hipStream_t stream) {
+    return liouville_steps(g, vel3d, src, state, work, work_bytes, dt, nsteps, stream, true);
+}
+
+size_t egb_gvel_bytes(const egb_grid* g) { return grid_ok(g) ? (size_t)3 * plane_stride(*g) * real_size(*g) : 0; }
+
+egb_status egb_pick_adjoint(const egb_grid* g, const void* state, const double* rx, int32_t nr, const double* tbar,
+                            void* lambda, hipStream_t stream) {
+    if (!grid_ok(g) || !state || !lambda || nr < 0 || (nr > 0 && (!rx || !tbar))) return EGB_EINVAL;
+    if (!aligned16(state) || !aligned16(lambda) || (rx && !aligned16(rx)) || (tbar && ((uintptr_t)tbar & 7u)))
+        return EGB_EINVAL;
+    return hip_status(launch_pick_adjoint(grid_args(*g), g->dtype, state, rx, nr, tbar, lambda, stream));
+}
+
+egb_status egb_adjoint_step(const egb_grid* g, const void* vel3d, const egb_source* src, const void* state_n,
+                            void* lambda, void* gvel, void* work, size_t work_bytes, double dt, hipStream_t stream) {
+    if (!grid_ok(g) || !vel3d || !state_n || !lambda || !gvel || !work || !source_ok(src)) return EGB_EINVAL;
+    if (!aligned16(vel3d) || !aligned16(state_n) || !aligned16(lambda) || !aligned16(gvel) || !aligned16(work))
+        return EGB_EINVAL;
+    if (state_n == lambda) return EGB_EINVAL;
+    if (!(dt > 0.0) || !isfinite(dt)) return EGB_ECFL;
+    if (work_bytes < egb_workspace_size(g, EGB_OP_ADJOINT)) return EGB_EWORKSPACE;
+    if (!stage_fits_32bit(grid_args(*g), g->dtype)) return EGB_EUNSUPPORTED;
+    const size_t sb = align256(state_bytes(*g));
+    char* w = static_cast<char*>(work);
+    void* U1 = w;
+    void* U2 = w + sb;
+    void* L2 = w + 2 * sb;
+    void* L1 = w + 3 * sb;
+    void* pk = w + 4 * sb;
+    const GridArgs a = grid_args(*g);
+    // recompute the inner stages of this step (phi1 and psi only)
+    StageArgs sa;
+    sa.g = a;
+    sa.vel = vel3d;
+    sa.dt = dt;
+    sa.xs = src->xs;
+    sa.zs = src->zs;
+    sa.r02 = src->r0 * src->r0;
+    sa.U0 = state_n;
+    sa.Uin = state_n;
+    sa.Uout = U1;
+    hipError_t e = launch_stage(sa, g->dtype, 0, stream, true);
+    if (e == hipSuccess) {
+        sa.Uin = U1;
+        sa.Uout = U2;
+        e = launch_stage(sa, g->dtype, 1, stream, true);
+    }
+    const double r02 = src->r0 * src->r0;
+    // reverse: stage 2 (input U2), stage 1 (input U1), stage 0 (input U^n)
+    if (e == hipSuccess)
+        e = launch_adjoint_stage(a, g->dtype, 2, vel3d, U2, lambda, L2, lambda, pk, gvel, dt, src->xs, src->zs, r02,
+                                 stream);
+    if (e == hipSuccess)
+        e = launch_adjoint_stage(a, g->dtype, 1, vel3d, U1, L2, L1, lambda, pk, gvel, dt, src->xs, src->zs, r02,
+                                 stream);
+    if (e == hipSuccess)
+        e = launch_adjoint_stage(a, g->dtype, 0, vel3d, state_n, L1, nullptr, lambda, pk, gvel, dt, src->xs, src->zs,
+                                 r02, stream);
+    return hip_status(e);
+}
+
+egb_status egb_adjoint_medium(const egb_grid* g, const egb_medium* m, const void* coeff2d, const egb_source* src,
+                              const void* gvel, const void* lambda0, double* grad, void* work, size_t work_bytes,
+                              hipStream_t stream) {
+    if (!grid_ok(g) || !m || !m->vp0 || !m->eps || !m->delta || !coeff2d || !gvel || !lambda0 || !grad || !work ||
+        !source_ok(src))
+        return EGB_EINVAL;
+    if (!aligned16(coeff2d) || !aligned16(gvel) || !aligned16(lambda0) || !aligned16(grad) || !aligned16(work))
+        return EGB_EINVAL;
+    if (work_bytes < egb_workspace_size(g, EGB_OP_ADJOINT)) return EGB_EWORKSPACE;
+    char* w = static_cast<char*>(work);
+    double* gtab = reinterpret_cast<double*>(w);
+    double* gms = reinterpret_cast<double*>(w + align256((size_t)15 * g->nx * g->nz * sizeof(double)));
+    return hip_status(launch_adjoint_medium(grid_args(*g), g->dtype, *m, static_cast<const double*>(coeff2d), *src,
+                                            gvel, lambda0, grad, gtab, gms, stream));
 }
 
 size_t egb_workspace_size_batched(const egb_problem* probs, int32_t nprob) {

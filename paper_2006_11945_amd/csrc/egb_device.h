@@ -29,14 +29,7 @@ struct VJet {
     double h[3][3];
 };
 
-__device__ __host__ inline void sincos_d(double a, double* s, double* c) {
-#ifdef __HIP_DEVICE_COMPILE__
-    sincos(a, s, c);
-#else
-    *s = __builtin_sin(a);
-    *c = __builtin_cos(a);
-#endif
-}
+__device__ inline void sincos_d(double a, double* s, double* c) { sincos(a, s, c); }
 
 // Second-order derivatives of F(m(x), phi(x, theta)) = sum_m m * kappa_m(phi),
 // phi = theta - nu(x), given F's phi-derivatives Fp, Fpp and the medium sums
@@ -80,7 +73,6 @@ __device__ inline Lin2 sqrt2(const Lin2& E) {
 //   G = (P + sqrt(Q^2 + R^2)) / 2,
 //   P = (a11 + a55) sin^2 + (a33 + a55) cos^2,  Q = (a11 - a55) sin^2 - (a33 - a55) cos^2,
 //   R = 2 b sin cos.
-// With ms == nullptr-free callers passing only values, derivatives vanish.
 __device__ inline VJet qp_velocity(const MediumPoint& M, double theta) {
     const double* a11 = M.m[0];
     const double* a33 = M.m[1];
@@ -255,6 +247,144 @@ __device__ __forceinline__ double weno5<double>(double v1, double v2, double v3,
     const double b2 = eps + 13.0 / 12.0 * t2 * t2 + 0.25 * u2 * u2;
     const double a0 = 0.1 / (b0 * b0), a1 = 0.6 / (b1 * b1), a2 = 0.3 / (b2 * b2);
     return __builtin_amdgcn_ldexp((a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2), e);
+}
+
+// WENO5 value (undivided) and its gradient g[k] = dW/dv_{k+1}, by reverse-mode
+// differentiation of the formula above (alpha_k = d_k/(eps + S_k)^2,
+// omega_k = alpha_k / sum alpha, W = sum omega_k q_k, eps = 1e-6 max v^2).
+// W is positively 1-homogeneous in v, so its gradient is evaluated on the
+// power-of-two normalised differences and needs no rescaling.  When all
+// differences vanish both W and the gradient are 0.
+template <typename R>
+__device__ __forceinline__ R weno5_grad(R v1, R v2, R v3, R v4, R v5, R (&g)[5]) {
+    R v[5] = {v1, v2, v3, v4, v5};
+    R m = (R)0;
+    int J = 0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const R a = v[k] < (R)0 ? -v[k] : v[k];
+        if (a > m) { m = a; J = k; }
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) g[k] = (R)0;
+    if (!(m > (R)0)) return (R)0;
+    int e;
+    if constexpr (sizeof(R) == 4) e = __builtin_amdgcn_frexp_expf(m);
+    else e = __builtin_amdgcn_frexp_exp(m);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        if constexpr (sizeof(R) == 4) v[k] = __builtin_amdgcn_ldexpf(v[k], -e);
+        else v[k] = __builtin_amdgcn_ldexp(v[k], -e);
+    }
+    const R vJ = v[J];
+    const R eps = (R)1e-6 * vJ * vJ;
+    const R q[3] = {v[0] * (R)(1.0 / 3.0) - v[1] * (R)(7.0 / 6.0) + v[2] * (R)(11.0 / 6.0),
+                    -v[1] * (R)(1.0 / 6.0) + v[2] * (R)(5.0 / 6.0) + v[3] * (R)(1.0 / 3.0),
+                    v[2] * (R)(1.0 / 3.0) + v[3] * (R)(5.0 / 6.0) - v[4] * (R)(1.0 / 6.0)};
+    const R t[3] = {v[0] - (R)2 * v[1] + v[2], v[1] - (R)2 * v[2] + v[3], v[2] - (R)2 * v[3] + v[4]};
+    const R u[3] = {v[0] - (R)4 * v[1] + (R)3 * v[2], v[1] - v[3], (R)3 * v[2] - (R)4 * v[3] + v[4]};
+    const R d[3] = {(R)0.1, (R)0.6, (R)0.3};
+    R b[3], al[3], A = (R)0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        b[k] = eps + (R)(13.0 / 12.0) * t[k] * t[k] + (R)0.25 * u[k] * u[k];
+        al[k] = d[k] / (b[k] * b[k]);
+        A += al[k];
+    }
+    const R iA = (R)1 / A;
+    const R w[3] = {al[0] * iA, al[1] * iA, al[2] * iA};
+    const R W = w[0] * q[0] + w[1] * q[1] + w[2] * q[2];
+    // backward
+    R tb[3], ub[3], epsb = (R)0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const R ab = (q[k] - W) * iA;
+        const R bb = (R)(-2) * al[k] * ab / b[k];
+        epsb += bb;
+        tb[k] = bb * (R)(13.0 / 6.0) * t[k];
+        ub[k] = bb * (R)0.5 * u[k];
+    }
+    g[0] = w[0] * (R)(1.0 / 3.0) + tb[0] + ub[0];
+    g[1] = -w[0] * (R)(7.0 / 6.0) - w[1] * (R)(1.0 / 6.0) - (R)2 * tb[0] - (R)4 * ub[0] + tb[1] + ub[1];
+    g[2] = w[0] * (R)(11.0 / 6.0) + w[1] * (R)(5.0 / 6.0) + w[2] * (R)(1.0 / 3.0) + tb[0] + (R)3 * ub[0] -
+           (R)2 * tb[1] + tb[2] + (R)3 * ub[2];
+    g[3] = w[1] * (R)(1.0 / 3.0) + w[2] * (R)(5.0 / 6.0) + tb[1] - ub[1] - (R)2 * tb[2] - (R)4 * ub[2];
+    g[4] = -w[2] * (R)(1.0 / 6.0) + tb[2] + ub[2];
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+        if (k == J) g[k] += epsb * (R)2e-6 * vJ;
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_ldexpf(W, e);
+    else return __builtin_amdgcn_ldexp(W, e);
+}
+
+// ------------------------------------------------------------ dual numbers
+// Forward-mode derivative carrier: value and one directional derivative.
+struct Dual {
+    double v, d;
+};
+__device__ __forceinline__ Dual dual(double v, double d = 0.0) { return Dual{v, d}; }
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a) { return {-a.v, -a.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.v * b.d + a.d * b.v}; }
+__device__ __forceinline__ Dual operator*(double s, Dual a) { return {s * a.v, s * a.d}; }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+    const double r = a.v / b.v;
+    return {r, (a.d - r * b.d) / b.v};
+}
+__device__ __forceinline__ Dual dsqrt(Dual a) {
+    const double r = sqrt(a.v);
+    return {r, 0.5 * a.d / r};
+}
+__device__ __forceinline__ void dsincos(Dual a, Dual* s, Dual* c) {
+    double sv, cv;
+    sincos(a.v, &sv, &cv);
+    *s = {sv, cv * a.d};
+    *c = {cv, -sv * a.d};
+}
+
+// First-order velocity jet for the medium adjoint: from the five fields'
+// values and first derivatives m[f][0..2] = (f, f_x, f_z) (as duals), the qP
+// phase velocity v and v_x, v_z, v_theta, then the Liouville velocity
+// V = (v sin + v_t cos, v cos - v_t sin, -(v_x cos - v_z sin)).
+__device__ inline void liouville_velocity_dual(const Dual (&m)[NF][3], double theta, Dual (&V)[3],
+                                               Dual* vout = nullptr) {
+    Dual sp, cp;
+    dsincos(dual(theta) - m[4][0], &sp, &cp);
+    const Dual S2 = sp * sp, C2 = cp * cp, s2 = 2.0 * (sp * cp), c2 = C2 - S2;
+    const Dual a11 = m[0][0], a33 = m[1][0], b = m[2][0], a55 = m[3][0];
+    const Dual P = (a11 + a55) * S2 + (a33 + a55) * C2;
+    const Dual Q = (a11 - a55) * S2 - (a33 - a55) * C2;
+    const Dual R = b * s2;
+    // phi-derivatives
+    const Dual Pp = (a11 - a33) * s2;
+    const Dual Qp = (a11 + a33 - 2.0 * a55) * s2;
+    const Dual Rp = 2.0 * (b * c2);
+    Dual Fx[3], Fz[3];  // spatial derivatives of P, Q, R at fixed theta
+    for (int i = 0; i < 2; ++i) {
+        const int sl = 1 + i;
+        const Dual nui = m[4][sl];
+        const Dual Pm = m[0][sl] * S2 + m[1][sl] * C2 + m[3][sl];
+        const Dual Qm = m[0][sl] * S2 - m[1][sl] * C2 + m[3][sl] * c2;
+        const Dual Rm = m[2][sl] * s2;
+        Dual* out = i == 0 ? Fx : Fz;
+        out[0] = Pm - Pp * nui;
+        out[1] = Qm - Qp * nui;
+        out[2] = Rm - Rp * nui;
+    }
+    const Dual D = dsqrt(Q * Q + R * R);
+    const Dual v = dsqrt(0.5 * (P + D));
+    // dv = (dP + (Q dQ + R dR)/D) / (4 v)
+    auto dv = [&](Dual dP, Dual dQ, Dual dR) { return (dP + (Q * dQ + R * dR) / D) / (4.0 * v); };
+    const Dual vt = dv(Pp, Qp, Rp);
+    const Dual vx = dv(Fx[0], Fx[1], Fx[2]);
+    const Dual vz = dv(Fz[0], Fz[1], Fz[2]);
+    double sn, cs;
+    sincos(theta, &sn, &cs);
+    V[0] = sn * v + cs * vt;
+    V[1] = cs * v - sn * vt;
+    V[2] = -(cs * vx - sn * vz);
+    if (vout) *vout = v;
 }
 
 }  // namespace egb

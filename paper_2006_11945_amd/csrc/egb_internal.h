@@ -64,7 +64,8 @@ struct StageArgs {
     double dt;
     double xs, zs, r02;
 };
-hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s);
+// kinematic: march phi1 and psi only (the planes a traveltime depends on)
+hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s, bool kinematic = false);
 // The stage kernel addresses each array with 32-bit byte offsets.
 bool stage_fits_32bit(const GridArgs& g, int dtype);
 
@@ -76,6 +77,17 @@ hipError_t launch_stage_batched(const void* items, const int* first, int nprob, 
                                 int grid, hipStream_t s);
 int stage_block_threads(int dtype);
 const void* stage_batched_kernel(int dtype, int stage);
+
+// Adjoint of the kinematic march (see adjoint.hip).
+size_t adjoint_packet_bytes(const egb_grid& g);
+hipError_t launch_adjoint_stage(const GridArgs& g, int dtype, int stage, const void* vel, const void* Uin,
+                                const void* lam_out, void* lam_in, void* lam_acc, void* packets, void* gvel,
+                                double dt, double xs, double zs, double r02, hipStream_t s);
+hipError_t launch_pick_adjoint(const GridArgs& a, int dtype, const void* state, const double* rx, int nr,
+                               const double* tbar, void* lam, hipStream_t s);
+hipError_t launch_adjoint_medium(const GridArgs& a, int dtype, const egb_medium& m, const double* coeff2d,
+                                 const egb_source& src, const void* gvel, const void* lam0, double* grad, double* gtab,
+                                 double* gms, hipStream_t s);
 
 // Beam superposition.
 struct BeamArgs {

@@ -128,13 +128,15 @@ struct StageSmem {
 
 // One (z, theta) tile x one x chunk of an RK stage; `logical` numbers the
 // tile within its problem.
-template <typename R, int STAGE, int TK>
+// KIN: only phi1 and psi (the planes a traveltime depends on).
+template <typename R, int STAGE, int TK, bool KIN>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t, int logical,
                                            StageSmem<R, TK>& sm) {
     constexpr int PLANE = StageSmem<R, TK>::PLANE;
     constexpr int NHALO = 6 * TZ + 6 * TK;
     static_assert(NHALO <= 64 * TK, "one halo slot per thread");
     constexpr unsigned ES = sizeof(R);
+    constexpr int NP = KIN ? 1 : 5;  // R planes marched
     auto& sR = sm.r;
     auto& sP = sm.p;
 
@@ -187,20 +189,20 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
     const int x0 = xc * t.kx;
     const int x1 = min(x0 + t.kx, g.nx);
     // queue of the column's x-neighbours: q[f][j] at x - 3 + j
-    R q[5][7];
+    R q[NP][7];
     double qp[7];
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
         const int x = x0 - 3 + j;
 #pragma unroll
-        for (int f = 0; f < 5; ++f) q[f][j] = fetch<R>(rUi, f * SP, g, kb, x, iz);
+        for (int f = 0; f < NP; ++f) q[f][j] = fetch<R>(rUi, f * SP, g, kb, x, iz);
         qp[j] = fetch<double>(rUi, PSI, g, kb, x, iz);
     }
     // halo values of the first slice
-    R hv[5];
+    R hv[NP];
     double hp = 0.0;
 #pragma unroll
-    for (int f = 0; f < 5; ++f) hv[f] = has_halo ? fetch<R>(rUi, f * SP, g, hkb, x0, hzg) : (R)0;
+    for (int f = 0; f < NP; ++f) hv[f] = has_halo ? fetch<R>(rUi, f * SP, g, hkb, x0, hzg) : (R)0;
     if (has_halo) hp = fetch<double>(rUi, PSI, g, hkb, x0, hzg);
 
     const R inv_dx = (R)(1.0 / g.dx), inv_dz = (R)(1.0 / g.dz), inv_dt = (R)(1.0 / g.dth);
@@ -216,35 +218,35 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
         R* L = sR[buf];
         double* LP = sP[buf];
 #pragma unroll
-        for (int f = 0; f < 5; ++f) L[f * PLANE + me] = q[f][3];
+        for (int f = 0; f < NP; ++f) L[f * PLANE + me] = q[f][3];
         LP[me] = qp[3];
         if (has_halo) {
 #pragma unroll
-            for (int f = 0; f < 5; ++f) L[f * PLANE + hi] = hv[f];
+            for (int f = 0; f < NP; ++f) L[f * PLANE + hi] = hv[f];
             LP[hi] = hp;
         }
         // next queue entry (x + 4) and next halo slice (x + 1)
-        R qn[5];
+        R qn[NP];
         double qpn;
         if (x + 4 < g.nx && iz < g.nz) {
             const unsigned o = kb + (unsigned)((x + 4) * g.nz + iz);
 #pragma unroll
-            for (int f = 0; f < 5; ++f) qn[f] = bload<R>(rUi, o * ES, f * SP);
+            for (int f = 0; f < NP; ++f) qn[f] = bload<R>(rUi, o * ES, f * SP);
             qpn = bload<double>(rUi, o * 8u, PSI);
         } else {
 #pragma unroll
-            for (int f = 0; f < 5; ++f) qn[f] = fetch<R>(rUi, f * SP, g, kb, x + 4, iz);
+            for (int f = 0; f < NP; ++f) qn[f] = fetch<R>(rUi, f * SP, g, kb, x + 4, iz);
             qpn = fetch<double>(rUi, PSI, g, kb, x + 4, iz);
         }
         if (has_halo && x + 1 < x1) {
             if (hzg >= 0 && hzg < g.nz) {
                 const unsigned o = hkb + (unsigned)((x + 1) * g.nz + hzg);
 #pragma unroll
-                for (int f = 0; f < 5; ++f) hv[f] = bload<R>(rUi, o * ES, f * SP);
+                for (int f = 0; f < NP; ++f) hv[f] = bload<R>(rUi, o * ES, f * SP);
                 hp = bload<double>(rUi, o * 8u, PSI);
             } else {
 #pragma unroll
-                for (int f = 0; f < 5; ++f) hv[f] = fetch<R>(rUi, f * SP, g, hkb, x + 1, hzg);
+                for (int f = 0; f < NP; ++f) hv[f] = fetch<R>(rUi, f * SP, g, hkb, x + 1, hzg);
                 hp = fetch<double>(rUi, PSI, g, hkb, x + 1, hzg);
             }
         }
@@ -256,25 +258,30 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
             const double xr = g.x0 + (x + 0.5) * g.dx - a.xs;
             if (xr * xr + zc * zc <= a.r02) {  // source ball: Dirichlet data
 #pragma unroll
-                for (int f = 0; f < 5; ++f) bstore(bload<R>(rU0, cR, f * SP), rUo, cR, f * SP);
+                for (int f = 0; f < NP; ++f) bstore(bload<R>(rU0, cR, f * SP), rUo, cR, f * SP);
                 bstore(bload<double>(rU0, c8, PSI), rUo, c8, PSI);
             } else {
                 const R cx = bload<R>(rV, cR, EGB_VX * SP) * inv_dx;
                 const R cz = bload<R>(rV, cR, EGB_VZ * SP) * inv_dz;
                 const R ct = bload<R>(rV, cR, EGB_VT * SP) * inv_dt;
-                const R A11 = bload<R>(rV, cR, EGB_A11 * SP), A12 = bload<R>(rV, cR, EGB_A12 * SP);
-                const R A21 = bload<R>(rV, cR, EGB_A21 * SP), A22 = bload<R>(rV, cR, EGB_A22 * SP);
-                R u0[5];
+                R A11 = 0, A12 = 0, A21 = 0, A22 = 0;
+                if constexpr (!KIN) {
+                    A11 = bload<R>(rV, cR, EGB_A11 * SP);
+                    A12 = bload<R>(rV, cR, EGB_A12 * SP);
+                    A21 = bload<R>(rV, cR, EGB_A21 * SP);
+                    A22 = bload<R>(rV, cR, EGB_A22 * SP);
+                }
+                R u0[NP];
                 double p0 = 0.0;
                 if (STAGE != 0) {
 #pragma unroll
-                    for (int f = 0; f < 5; ++f) u0[f] = bload<R>(rU0, cR, f * SP);
+                    for (int f = 0; f < NP; ++f) u0[f] = bload<R>(rU0, cR, f * SP);
                     p0 = bload<double>(rU0, c8, PSI);
                 }
                 const bool mx = cx >= (R)0, mz = cz >= (R)0, mt = ct >= (R)0;
-                R Lf[5];
+                R Lf[NP];
 #pragma unroll
-                for (int f = 0; f < 5; ++f) {
+                for (int f = 0; f < NP; ++f) {
                     const R* Lp = L + f * PLANE + me;
                     R uz[7], ut[7];
 #pragma unroll
@@ -284,10 +291,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
                     }
                     Lf[f] = -(cx * weno7<R, R>(q[f], mx) + cz * weno7<R, R>(uz, mz) + ct * weno7<R, R>(ut, mt));
                 }
-                Lf[EGB_RE_C] += A11 * q[EGB_RE_C][3] + A12 * q[EGB_RE_B][3];
-                Lf[EGB_RE_B] += A21 * q[EGB_RE_C][3] + A22 * q[EGB_RE_B][3];
-                Lf[EGB_IM_C] += A11 * q[EGB_IM_C][3] + A12 * q[EGB_IM_B][3];
-                Lf[EGB_IM_B] += A21 * q[EGB_IM_C][3] + A22 * q[EGB_IM_B][3];
+                if constexpr (!KIN) {
+                    Lf[EGB_RE_C] += A11 * q[EGB_RE_C][3] + A12 * q[EGB_RE_B][3];
+                    Lf[EGB_RE_B] += A21 * q[EGB_RE_C][3] + A22 * q[EGB_RE_B][3];
+                    Lf[EGB_IM_C] += A11 * q[EGB_IM_C][3] + A12 * q[EGB_IM_B][3];
+                    Lf[EGB_IM_B] += A21 * q[EGB_IM_C][3] + A22 * q[EGB_IM_B][3];
+                }
                 double pz[7], pt[7];
                 const double* LPp = LP + me;
 #pragma unroll
@@ -300,7 +309,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
                                     (double)ct * (double)weno7<double, R>(pt, mt);
                 const double Lpsi = 1.0 - conv;
 #pragma unroll
-                for (int f = 0; f < 5; ++f) {
+                for (int f = 0; f < NP; ++f) {
                     const R y = q[f][3] + dtR * Lf[f];
                     bstore((STAGE == 0) ? y : (R)ca * u0[f] + (R)cb * y, rUo, cR, f * SP);
                 }
@@ -312,20 +321,20 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
 #pragma unroll
-            for (int f = 0; f < 5; ++f) q[f][j] = q[f][j + 1];
+            for (int f = 0; f < NP; ++f) q[f][j] = q[f][j + 1];
             qp[j] = qp[j + 1];
         }
 #pragma unroll
-        for (int f = 0; f < 5; ++f) q[f][6] = qn[f];
+        for (int f = 0; f < NP; ++f) q[f][6] = qn[f];
         qp[6] = qpn;
     }
 }
 
-template <typename R, int STAGE, int TK>
+template <typename R, int STAGE, int TK, bool KIN>
 __global__ __launch_bounds__(64 * TK) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
 void k_stage(StageArgs a, TileArgs t) {
     __shared__ StageSmem<R, TK> sm;
-    stage_tile<R, STAGE, TK>(a, t, xcd_remap(blockIdx.x, t.nblocks), sm);
+    stage_tile<R, STAGE, TK, KIN>(a, t, xcd_remap(blockIdx.x, t.nblocks), sm);
 }
 
 // Batched march: a persistent grid walks one queue of tiles spanning every
@@ -351,7 +360,7 @@ void k_stage_batched(const BatchItem* __restrict__ items, const int* __restrict_
         const StageArgs a = items[lo].a[STAGE];
         const TileArgs ta = items[lo].t;
         __syncthreads();  // the previous tile's last LDS reads are done
-        stage_tile<R, STAGE, TK>(a, ta, t - first[lo], sm);
+        stage_tile<R, STAGE, TK, false>(a, ta, t - first[lo], sm);
     }
 }
 
@@ -359,7 +368,7 @@ unsigned long long state_bytes_of(const GridArgs& g, size_t es) {
     return (unsigned long long)g.stride * (5ull * es + 8ull);
 }
 
-template <typename R, int TK>
+template <typename R, int TK, bool KIN>
 hipError_t launch_stage_t(const StageArgs& a, int stage, int kx, hipStream_t s) {
     TileArgs t;
     t.ntz = (a.g.nz + TZ - 1) / TZ;
@@ -371,9 +380,9 @@ hipError_t launch_stage_t(const StageArgs& a, int stage, int kx, hipStream_t s) 
     t.vel_bytes = (unsigned)(7ull * (unsigned long long)a.g.stride * sizeof(R));
     const dim3 grid(t.nblocks), block(TZ, TK);
     switch (stage) {
-        case 0: k_stage<R, 0, TK><<<grid, block, 0, s>>>(a, t); break;
-        case 1: k_stage<R, 1, TK><<<grid, block, 0, s>>>(a, t); break;
-        default: k_stage<R, 2, TK><<<grid, block, 0, s>>>(a, t); break;
+        case 0: k_stage<R, 0, TK, KIN><<<grid, block, 0, s>>>(a, t); break;
+        case 1: k_stage<R, 1, TK, KIN><<<grid, block, 0, s>>>(a, t); break;
+        default: k_stage<R, 2, TK, KIN><<<grid, block, 0, s>>>(a, t); break;
     }
     return hipGetLastError();
 }
@@ -461,9 +470,12 @@ bool stage_fits_32bit(const GridArgs& g, int dtype) {
     return state_bytes_of(g, es) < (1ull << 32) && 7ull * (unsigned long long)g.stride * es < (1ull << 32);
 }
 
-hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s) {
-    if (dtype == EGB_F64) return launch_stage_t<double, 8>(a, stage, choose_kx(a.g, 8), s);
-    return launch_stage_t<float, 12>(a, stage, choose_kx(a.g, 12), s);
+hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s, bool kinematic) {
+    if (dtype == EGB_F64)
+        return kinematic ? launch_stage_t<double, 8, true>(a, stage, choose_kx(a.g, 8), s)
+                         : launch_stage_t<double, 8, false>(a, stage, choose_kx(a.g, 8), s);
+    return kinematic ? launch_stage_t<float, 12, true>(a, stage, choose_kx(a.g, 12), s)
+                     : launch_stage_t<float, 12, false>(a, stage, choose_kx(a.g, 12), s);
 }
 
 }  // namespace egb

@@ -1,0 +1,114 @@
+"""Traveltime-misfit gradients from the HIP adjoint (through the C ABI)
+against the oracle's autograd gradient, and a directional-derivative check of
+the full-size adjoint workload."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from oracle import adjoint as AD
+from tests.gpu_helpers import log
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def adjoint_problem(n=24, nth=24, nsteps=14, tilt=True):
+    L = 480.0
+    g = W.Grid(nx=n, nz=n + 4, nth=nth, dx=L / n, dz=L / n)
+    rng = W.rng_for(4, 900)
+    med = W.vti_medium(rng, g, L, tilt=tilt)
+    src = W.Source(xs=0.5 * L + 3.0, zs=0.3 * L, r0=4 * g.dx, beta=1.0 / (2 * L))
+    rx = np.stack([np.linspace(0.25 * L, 0.75 * L, 9), np.full(9, 0.72 * L)], axis=1)
+    return W.Problem("adj", g, med, src, nsteps, W.hz([20.0])), rx
+
+
+def spec_of(p, rx, dtype, dt, K=5):
+    return {"grid": p.grid, "source": p.source, "receivers": rx, "nsteps": p.nsteps,
+            "vs_ratio": p.medium.vs_ratio, "dtype": dtype, "checkpoint_every": K, "dt": dt}
+
+
+def gpu_gradient(p, rx, t_obs, dtype, dt, K=5):
+    import paper_2006_11945_amd as egb
+    ts = [torch.tensor(np.asarray(a, dtype=np.float64), device=DEV, requires_grad=True)
+          for a in (p.medium.vp0, p.medium.eps, p.medium.delta, p.medium.tilt)]
+    t = egb.traveltime(*ts, spec_of(p, rx, dtype, dt, K))
+    ok = ~torch.isnan(t)
+    J = torch.sum((t[ok] - torch.as_tensor(t_obs, device=DEV)[ok]) ** 2)
+    J.backward()
+    return float(J.detach()), [x.grad.cpu().numpy() for x in ts], t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_gradient_matches_oracle(dtype):
+    p, rx = adjoint_problem()
+    r = oracle.solve(p)
+    dt = r["dt"]
+    true = replace(p.medium, vp0=p.medium.vp0 * 1.03, eps=p.medium.eps + 0.02)
+    rt = oracle.solve(replace(p, medium=true), dt=dt)
+    t_obs = oracle.pick(p.grid, rt["U"], rx)
+    Jo, go = AD.gradient(p, rx, t_obs, dt, p.nsteps)
+    Jg, gg, tg = gpu_gradient(p, rx, t_obs, dtype, dt)
+    log(f"adjoint {dtype}: J oracle {Jo:.6e} gpu {Jg:.6e}")
+    tol = 1e-9 if dtype == "f64" else 1e-3
+    assert Jg == pytest.approx(Jo, rel=1e-9 if dtype == "f64" else 1e-4)
+    for name, a, b in zip(("vp0", "eps", "delta", "tilt"), gg, go):
+        e = np.abs(a - b).max() / np.abs(b).max()
+        log(f"  d/d{name}: max rel err {e:.3e} (scale {np.abs(b).max():.3e})")
+        assert e < tol, name
+
+
+def test_adjoint_checkpoint_interval_does_not_change_gradient():
+    p, rx = adjoint_problem(nsteps=11)
+    r = oracle.solve(p)
+    t_obs = oracle.pick(p.grid, oracle.solve(replace(p, medium=replace(p.medium, vp0=p.medium.vp0 * 0.98)),
+                                                 dt=r["dt"])["U"], rx)
+    _, g1, _ = gpu_gradient(p, rx, t_obs, "f64", r["dt"], K=1)
+    _, g2, _ = gpu_gradient(p, rx, t_obs, "f64", r["dt"], K=4)
+    for a, b in zip(g1, g2):
+        assert np.array_equal(a, b)
+
+
+def test_adjoint_full_size_directional_derivative():
+    """256^3 VTI medium, 16 sources' geometry (one source here), 128 receivers:
+    <grad J, d> against a central difference of J along a smooth direction d."""
+    import paper_2006_11945_amd as egb
+    probs = W.adjoint_sources(nsteps=300)
+    p = probs[7]
+    rx = p.receivers
+    true = p.extra["true_medium"]
+    log("adjoint full size 256^3, 300 steps")
+    spec = {"grid": p.grid, "source": p.source, "receivers": rx, "nsteps": p.nsteps, "vs_ratio": 0.5,
+            "dtype": "f32", "checkpoint_every": 16}
+    mk = lambda m: [torch.tensor(np.asarray(a, dtype=np.float64), device=DEV) for a in (m.vp0, m.eps, m.delta, m.tilt)]
+    # every evaluation uses the base medium's CFL step
+    spec["dt"] = egb.Solver(p, DEV).velocity()
+    t_obs = egb.traveltime(*mk(true), spec).cpu().numpy()
+    ts = mk(p.medium)
+    for x in ts:
+        x.requires_grad_(True)
+    t = egb.traveltime(*ts, spec)
+    ok = ~(torch.isnan(t) | torch.isnan(torch.as_tensor(t_obs, device=DEV)))
+    J = torch.sum((t[ok] - torch.as_tensor(t_obs, device=DEV)[ok]) ** 2)
+    J.backward()
+    d = W.smooth_field(np.random.default_rng(11), p.grid, 400.0) * p.medium.vp0
+    gd = float(np.sum(ts[0].grad.cpu().numpy() * d))
+    h = 2e-4
+    Js = []
+    for sgn in (1, -1):
+        m = replace(p.medium, vp0=p.medium.vp0 + sgn * h * d)
+        with torch.no_grad():
+            tt = egb.traveltime(*mk(m), spec)
+        Js.append(float(torch.sum((tt[ok] - torch.as_tensor(t_obs, device=DEV)[ok]) ** 2)))
+    fd = (Js[0] - Js[1]) / (2 * h)
+    log(f"  J {float(J.detach()):.6e}  <g,d> {gd:.6e}  FD {fd:.6e}")
+    assert fd == pytest.approx(gd, rel=2e-2)
