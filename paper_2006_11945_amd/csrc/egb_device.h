@@ -189,64 +189,55 @@ __device__ inline VelA velocity_and_drt(const VJet& J, double theta) {
 // ---------------------------------------------------------------- WENO5
 // One-sided WENO5 Hamilton-Jacobi derivative, undivided (derivative times
 // the spacing), from the five differences v1..v5 ordered away from the
-// upwind side.  The differences are first scaled by a power of two so that
-// max|v| lies in [0.5, 1): the weights are scale invariant and this keeps
-// every intermediate in range in float; eps = 1e-6 max v^2.  Returns 0 when
-// all differences vanish.
+// upwind side, eps = 1e-6 max v^2.  Rewritten with the second differences
+// s_j = v_{j+1} - v_j (j = 1..4):
+//   W = v3 + (1/6) sum_k omega_k r_k,  r = (5 s2 - 2 s1, s2 + 2 s3, 4 s3 - s4),
+//   beta_k = 13/12 t_k^2 + 1/4 u_k^2,  t = (s2 - s1, s3 - s2, s4 - s3),
+//                                      u = (3 s2 - s1, s2 + s3, s4 - 3 s3),
+//   omega_k proportional to d_k / (eps + beta_k)^2,  d = (0.1, 0.6, 0.3),
+// which is the textbook form (q_k - v3 = r_k / 6) with fewer operations.
+// The weights use b_k = 4 (eps + beta_k) 2^(-2e), 2^e ~ max|v|, computed
+// from s_j 2^(-e) (exact power-of-two scaling): every intermediate stays
+// within [1e-6, 1e5] whatever the scale of v, and the weights over the common
+// denominator b0^2 b1^2 b2^2 need a single reciprocal.  All differences zero
+// gives W = 0 (eps is then taken with max|v| 2^(-e) = 1/2, which keeps the
+// denominator positive).
 template <typename R>
-__device__ __forceinline__ R weno5(R v1, R v2, R v3, R v4, R v5);
-
-template <>
-__device__ __forceinline__ float weno5<float>(float v1, float v2, float v3, float v4, float v5) {
-    float m = fmaxf(fmaxf(fmaxf(fabsf(v1), fabsf(v2)), fmaxf(fabsf(v3), fabsf(v4))), fabsf(v5));
-    int e = __builtin_amdgcn_frexp_expf(m);
-    v1 = __builtin_amdgcn_ldexpf(v1, -e);
-    v2 = __builtin_amdgcn_ldexpf(v2, -e);
-    v3 = __builtin_amdgcn_ldexpf(v3, -e);
-    v4 = __builtin_amdgcn_ldexpf(v4, -e);
-    v5 = __builtin_amdgcn_ldexpf(v5, -e);
-    const float mm = __builtin_amdgcn_ldexpf(m, -e);
-    const float eps = 1e-6f * mm * mm;
-    const float q0 = v1 * (1.0f / 3.0f) - v2 * (7.0f / 6.0f) + v3 * (11.0f / 6.0f);
-    const float q1 = -v2 * (1.0f / 6.0f) + v3 * (5.0f / 6.0f) + v4 * (1.0f / 3.0f);
-    const float q2 = v3 * (1.0f / 3.0f) + v4 * (5.0f / 6.0f) - v5 * (1.0f / 6.0f);
-    const float t0 = v1 - 2.0f * v2 + v3, u0 = v1 - 4.0f * v2 + 3.0f * v3;
-    const float t1 = v2 - 2.0f * v3 + v4, u1 = v2 - v4;
-    const float t2 = v3 - 2.0f * v4 + v5, u2 = 3.0f * v3 - 4.0f * v4 + v5;
-    const float b0 = eps + (13.0f / 12.0f) * t0 * t0 + 0.25f * u0 * u0;
-    const float b1 = eps + (13.0f / 12.0f) * t1 * t1 + 0.25f * u1 * u1;
-    const float b2 = eps + (13.0f / 12.0f) * t2 * t2 + 0.25f * u2 * u2;
-    const float e0 = b0 * b0, e1 = b1 * b1, e2 = b2 * b2;
-    // alpha_k = d_k / e_k with a common denominator e0 e1 e2
-    const float w0 = 0.1f * (e1 * e2), w1 = 0.6f * (e0 * e2), w2 = 0.3f * (e0 * e1);
-    const float num = w0 * q0 + w1 * q1 + w2 * q2;
-    const float r = num * __builtin_amdgcn_rcpf(w0 + w1 + w2);
-    return m > 0.0f ? __builtin_amdgcn_ldexpf(r, e) : 0.0f;
-}
-
-template <>
-__device__ __forceinline__ double weno5<double>(double v1, double v2, double v3, double v4, double v5) {
-    double m = fmax(fmax(fmax(fabs(v1), fabs(v2)), fmax(fabs(v3), fabs(v4))), fabs(v5));
-    if (!(m > 0.0)) return 0.0;
-    int e = __builtin_amdgcn_frexp_exp(m);
-    v1 = __builtin_amdgcn_ldexp(v1, -e);
-    v2 = __builtin_amdgcn_ldexp(v2, -e);
-    v3 = __builtin_amdgcn_ldexp(v3, -e);
-    v4 = __builtin_amdgcn_ldexp(v4, -e);
-    v5 = __builtin_amdgcn_ldexp(v5, -e);
-    const double mm = __builtin_amdgcn_ldexp(m, -e);
-    const double eps = 1e-6 * mm * mm;
-    const double q0 = v1 / 3.0 - 7.0 * v2 / 6.0 + 11.0 * v3 / 6.0;
-    const double q1 = -v2 / 6.0 + 5.0 * v3 / 6.0 + v4 / 3.0;
-    const double q2 = v3 / 3.0 + 5.0 * v4 / 6.0 - v5 / 6.0;
-    const double t0 = v1 - 2.0 * v2 + v3, u0 = v1 - 4.0 * v2 + 3.0 * v3;
-    const double t1 = v2 - 2.0 * v3 + v4, u1 = v2 - v4;
-    const double t2 = v3 - 2.0 * v4 + v5, u2 = 3.0 * v3 - 4.0 * v4 + v5;
-    const double b0 = eps + 13.0 / 12.0 * t0 * t0 + 0.25 * u0 * u0;
-    const double b1 = eps + 13.0 / 12.0 * t1 * t1 + 0.25 * u1 * u1;
-    const double b2 = eps + 13.0 / 12.0 * t2 * t2 + 0.25 * u2 * u2;
-    const double a0 = 0.1 / (b0 * b0), a1 = 0.6 / (b1 * b1), a2 = 0.3 / (b2 * b2);
-    return __builtin_amdgcn_ldexp((a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2), e);
+__device__ __forceinline__ R weno5(R v1, R v2, R v3, R v4, R v5) {
+    constexpr bool F = sizeof(R) == 4;
+    const R m = fmax(fmax(fmax(fmax(fabs(v1), fabs(v2)), fabs(v3)), fabs(v4)), fabs(v5));
+    int e;
+    R mm;
+    if constexpr (F) {
+        e = __builtin_amdgcn_frexp_expf(m);
+        mm = fmaxf(__builtin_amdgcn_frexp_mantf(m), 0.5f);
+    } else {
+        e = __builtin_amdgcn_frexp_exp(m);
+        mm = fmax(__builtin_amdgcn_frexp_mant(m), 0.5);
+    }
+    auto sc = [&](R x) {
+        if constexpr (F) return __builtin_amdgcn_ldexpf(x, -e);
+        else return __builtin_amdgcn_ldexp(x, -e);
+    };
+    const R eps4 = ((R)4e-6 * mm) * mm;
+    const R s1 = sc(v2 - v1), s2 = sc(v3 - v2), s3 = sc(v4 - v3), s4 = sc(v5 - v4);
+    const R t0 = s2 - s1, u0 = (R)3 * s2 - s1;
+    const R t1 = s3 - s2, u1 = s2 + s3;
+    const R t2 = s4 - s3, u2 = s4 - (R)3 * s3;
+    constexpr R c13 = (R)(13.0 / 3.0);
+    const R b0 = (c13 * t0) * t0 + (u0 * u0 + eps4);
+    const R b1 = (c13 * t1) * t1 + (u1 * u1 + eps4);
+    const R b2 = (c13 * t2) * t2 + (u2 * u2 + eps4);
+    // weights over the common denominator: (1, 6, 3) x products of the other two b^2
+    const R G = ((R)3 * b0) * b0, E1 = b1 * b1, E2 = b2 * b2;
+    const R w0 = E1 * E2, w2 = G * E1, H = G * E2, w1 = H + H;
+    const R r0 = (R)5 * s2 - (R)2 * s1, r1 = s2 + (R)2 * s3, r2 = (R)4 * s3 - s4;
+    const R num = w0 * r0 + w1 * r1 + w2 * r2;
+    const R den = (w0 + w1) + w2;
+    R r;
+    if constexpr (F) r = __builtin_amdgcn_ldexpf(num * __builtin_amdgcn_rcpf(den), e);
+    else r = __builtin_amdgcn_ldexp(num / den, e);
+    return v3 + r * (R)(1.0 / 6.0);
 }
 
 // WENO5 value (undivided) and its gradient g[k] = dW/dv_{k+1}, by reverse-mode

@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <stdlib.h>
 
+#include <type_traits>
+
 #include "egb_device.h"
 #include "egb_internal.h"
 
@@ -51,16 +53,24 @@ struct RK<2> {
 constexpr int TZ = 64;       // z cells per tile (one wavefront row)
 constexpr int PZ = TZ + 6;   // padded LDS row
 
-// WENO5 on seven values u[0..6] at offsets -3..3 (upwind side chosen by
-// `minus`); differences are formed in T and the derivative in R.
-template <typename T, typename R>
-__device__ __forceinline__ R weno7(const T (&u)[7], bool minus) {
-    // written with scalars: an indexed select would become a computed index
-    const T d0 = u[1] - u[0], d1 = u[2] - u[1], d2 = u[3] - u[2];
-    const T d3 = u[4] - u[3], d4 = u[5] - u[4], d5 = u[6] - u[5];
-    const R v1 = (R)(minus ? d0 : d5), v2 = (R)(minus ? d1 : d4), v3 = (R)(minus ? d2 : d3);
-    const R v4 = (R)(minus ? d3 : d2), v5 = (R)(minus ? d4 : d1);
-    return weno5<R>(v1, v2, v3, v4, v5);
+// WENO5 of six values u0..u5 read in upwind order (u3 is the cell itself,
+// u0..u2 lie on the upwind side): differences u_k - u_{k-1}, formed in T,
+// derivative in R.  Reading the stencil mirrored when the velocity component
+// is negative turns D+ into minus D- of the mirrored values, so
+// V * D(U) = |V| * weno_up(mirrored values) for either sign.
+template <typename R, typename T>
+__device__ __forceinline__ R weno_up(T u0, T u1, T u2, T u3, T u4, T u5) {
+    return weno5<R>((R)(u1 - u0), (R)(u2 - u1), (R)(u3 - u2), (R)(u4 - u3), (R)(u5 - u4));
+}
+
+// Value m of the upwind-ordered x stencil from the column queue q (q[3] is
+// the cell): DIR 0 = every lane upwinds from -x, 1 = every lane from +x,
+// 2 = per lane (`minus`).
+template <int DIR, typename T>
+__device__ __forceinline__ T upw(const T (&q)[7], int m, bool minus) {
+    if constexpr (DIR == 0) return q[m];
+    else if constexpr (DIR == 1) return q[6 - m];
+    else return minus ? q[m] : q[6 - m];
 }
 
 // Raw buffer access: one descriptor per array (base, size < 4 GiB), a 32-bit
@@ -119,26 +129,96 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
     return xcd * q8 + min(xcd, r8) + (b >> 3);
 }
 
-template <typename R, int TK>
-struct StageSmem {
-    static constexpr int PLANE = (TK + 6) * PZ;
-    R r[2][5 * PLANE];
-    double p[2][PLANE];
+// LDS slice layout: NP planes of R (as raw words), then psi as two 32-bit
+// planes (F32) or one 64-bit plane (F64), so that one cell has the same word
+// index in every plane and one per-lane address serves them all (the plane
+// is an immediate offset).
+template <typename R>
+struct LdsWord;
+template <>
+struct LdsWord<float> {
+    using T = unsigned;
+    static constexpr int PSI_WORDS = 2;
 };
+template <>
+struct LdsWord<double> {
+    using T = unsigned long long;
+    static constexpr int PSI_WORDS = 1;
+};
+
+template <typename R, int TK, int NP>
+struct StageSmem {
+    using W = typename LdsWord<R>::T;
+    // words per plane, padded to a multiple of 64 so that two planes at one
+    // address pair up in a single ds_read2st64
+    static constexpr int PLANE = ((TK + 6) * PZ + 63) / 64 * 64;
+    static constexpr int NW = NP + LdsWord<R>::PSI_WORDS;    // planes per slice
+    static constexpr int BUF = NW * PLANE;                   // words per slice
+    static constexpr int PB = PLANE * (int)sizeof(W);        // bytes per plane
+    W w[2 * BUF];
+};
+
+// Store the NP plane values and psi of one cell at word index i.
+template <typename R, int TK, int NP>
+__device__ __forceinline__ void lds_put(StageSmem<R, TK, NP>& sm, int i, const R (&v)[NP], double p) {
+    using S = StageSmem<R, TK, NP>;
+    using W = typename S::W;
+#pragma unroll
+    for (int f = 0; f < NP; ++f) sm.w[i + f * S::PLANE] = __builtin_bit_cast(W, v[f]);
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, p);
+    if constexpr (sizeof(R) == 4) {
+        sm.w[i + NP * S::PLANE] = (unsigned)b;
+        sm.w[i + (NP + 1) * S::PLANE] = (unsigned)(b >> 32);
+    } else {
+        sm.w[i + NP * S::PLANE] = b;
+    }
+}
+
+// Plane f (or psi) of the cell at byte address `byte` of the slice buffers.
+template <typename R, typename S>
+__device__ __forceinline__ R lds_r(const S& sm, int byte, int f) {
+    const char* c = reinterpret_cast<const char*>(sm.w) + byte + f * S::PB;
+    return __builtin_bit_cast(R, *reinterpret_cast<const typename S::W*>(c));
+}
+template <int NP, typename S>
+__device__ __forceinline__ double lds_psi(const S& sm, int byte) {
+    const char* c = reinterpret_cast<const char*>(sm.w) + byte + NP * S::PB;
+    if constexpr (sizeof(typename S::W) == 4) {
+        const unsigned lo = *reinterpret_cast<const unsigned*>(c);
+        const unsigned hi = *reinterpret_cast<const unsigned*>(c + S::PB);
+        return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+    } else {
+        return __builtin_bit_cast(double, *reinterpret_cast<const unsigned long long*>(c));
+    }
+}
 
 // One (z, theta) tile x one x chunk of an RK stage; `logical` numbers the
 // tile within its problem.
 // KIN: only phi1 and psi (the planes a traveltime depends on).
+//
+// Per plane f the cell's new value is
+//   ca U0 + cb Uin + cb dt S_f - sum_a (cb dt |V_a| / h_a) weno_up(stencil_a),
+// the three stencils read in upwind order: x from the register queue (a
+// wave whose lanes all upwind from the same side takes a select-free
+// path), z and theta from LDS at per-lane mirrored addresses.  Cells in the
+// source ball take U0 instead (stage 0 is called with Uin == U0).
+//
+// Memory traffic inside the x loop is straight-line per lane, so that the
+// waits the compiler places before a use cover only the load that use
+// needs: a z ghost is the two-point extrapolation w0 u(z0) + w1 u(z1) of a
+// halo column (w = (1, 0) inside; the second load only in tiles that touch
+// a z end), an x ghost continues the line of the last two queue entries,
+// and lanes past nz load an in-domain column and write nothing.
 template <typename R, int STAGE, int TK, bool KIN>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t, int logical,
-                                           StageSmem<R, TK>& sm) {
-    constexpr int PLANE = StageSmem<R, TK>::PLANE;
+                                           StageSmem<R, TK, KIN ? 1 : 5>& sm) {
+    constexpr int NP = KIN ? 1 : 5;  // R planes marched
+    using S = StageSmem<R, TK, NP>;
+    constexpr int WS = (int)sizeof(typename S::W);
     constexpr int NHALO = 6 * TZ + 6 * TK;
     static_assert(NHALO <= 64 * TK, "one halo slot per thread");
+    static_assert(S::PB * (S::NW - 1) < 65536, "plane offsets fit the LDS immediate");
     constexpr unsigned ES = sizeof(R);
-    constexpr int NP = KIN ? 1 : 5;  // R planes marched
-    auto& sR = sm.r;
-    auto& sP = sm.p;
 
     const GridArgs& g = a.g;
     const int tzi = logical % t.ntz;
@@ -148,43 +228,56 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
 
     const int tz = threadIdx.x, tk = threadIdx.y, tid = tk * TZ + tz;
     const int iz = tzi * TZ + tz;
+    const int nv = min(TZ, g.nz - tzi * TZ);  // z columns of this tile inside the grid
     const int kraw = tki * TK + tk;
-    const int k = kraw < g.nth ? kraw : kraw - g.nth;  // ragged theta tiles wrap (never written)
-    const bool valid = iz < g.nz && kraw < g.nth;
-    const unsigned nxz = (unsigned)g.nxz, S = (unsigned)g.stride;
+    const int k = kraw < g.nth ? kraw : kraw - g.nth;  // ragged theta tiles wrap (periodic rows, never written)
+    const bool zin = tz < nv;
+    const bool valid = zin && kraw < g.nth;
+    const int izc = min(iz, g.nz - 1);  // in-domain column for the loads of lanes past nz
+    const unsigned nxz = (unsigned)g.nxz, SS = (unsigned)g.stride;
     const unsigned kb = (unsigned)k * nxz;
     const auto rUi = make_rsrc(a.Uin, t.state_bytes);
     const auto rU0 = make_rsrc(a.U0, t.state_bytes);
     const auto rUo = make_rsrc(a.Uout, t.state_bytes);
     const auto rV = make_rsrc(a.vel, t.vel_bytes);
-    const unsigned SP = S * ES;          // bytes per R plane
+    const unsigned SP = SS * ES;         // bytes per R plane
     const unsigned PSI = 5u * SP;        // byte offset of the psi plane
 
-    // halo slot of this thread (if any): theta rows first, then z columns
-    bool has_halo = tid < NHALO;
-    int hk = 0, hz = 0;  // LDS coordinates (0-based, padded)
-    unsigned hkb = 0;
-    int hzg = 0;         // global z of the halo cell
-    if (has_halo) {
-        if (tid < 6 * TZ) {
-            const int r = tid / TZ;
-            hz = tid % TZ + 3;
-            hk = r < 3 ? r : TK + r;
-            int kk = tki * TK + hk - 3;
-            kk = ((kk % g.nth) + g.nth) % g.nth;
-            hkb = (unsigned)kk * nxz;
-            hzg = min(tzi * TZ + hz - 3, g.nz - 1);  // columns beyond nz are never read
-        } else {
-            const int h = tid - 6 * TZ, r = h / TK;
-            hk = h % TK + 3;
-            hz = r < 3 ? r : TZ + r;
-            int kk = tki * TK + hk - 3;
-            kk = kk < g.nth ? kk : kk - g.nth;
-            hkb = (unsigned)kk * nxz;
-            hzg = tzi * TZ + hz - 3;
-            if (hzg > g.nz + 2) has_halo = false;  // beyond the last ghost: never read
+    // Halo slot of this thread (if any): theta rows first (whole waves; z
+    // clamped into the grid, columns past nz are never read), then z
+    // columns: three on each side of the tile's nv inside columns, so that
+    // in the last tile the right ones are the ghosts nz, nz + 1, nz + 2.
+    const bool has_halo = tid < NHALO;
+    int hk = 0, hz = 0;    // LDS coordinates (0-based, padded)
+    unsigned hkb = kb;     // threads without a slot load their own column (unused)
+    int hz0 = izc, hz1 = izc;  // the two global z read for the halo cell
+    R hw0 = (R)1, hw1 = (R)0;
+    if (tid < 6 * TZ) {
+        const int r = tid / TZ;
+        hz = tid % TZ + 3;
+        hk = r < 3 ? r : TK + r;
+        int kk = tki * TK + hk - 3;
+        kk = ((kk % g.nth) + g.nth) % g.nth;
+        hkb = (unsigned)kk * nxz;
+        hz0 = hz1 = min(tzi * TZ + hz - 3, g.nz - 1);
+    } else if (has_halo) {
+        const int h = tid - 6 * TZ, r = h / TK;
+        hk = h % TK + 3;
+        hz = r < 3 ? r : nv + r;
+        int kk = tki * TK + hk - 3;
+        kk = kk < g.nth ? kk : kk - g.nth;
+        hkb = (unsigned)kk * nxz;
+        const int hzg = tzi * TZ + hz - 3;  // a ghost outside [0, nz)
+        hz0 = hz1 = hzg;
+        if (hzg < 0 || hzg >= g.nz) {
+            const int e = hzg < 0 ? -hzg : hzg - (g.nz - 1);
+            hz0 = hzg < 0 ? 0 : g.nz - 1;
+            hz1 = hzg < 0 ? 1 : g.nz - 2;
+            hw0 = (R)(e + 1);
+            hw1 = (R)(-e);
         }
     }
+    const bool z_end = tzi == 0 || tzi == t.ntz - 1 || (tzi + 1) * TZ + 3 > g.nz;  // block-uniform
 
     const int x0 = xc * t.kx;
     const int x1 = min(x0 + t.kx, g.nx);
@@ -195,129 +288,171 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
     for (int j = 0; j < 7; ++j) {
         const int x = x0 - 3 + j;
 #pragma unroll
-        for (int f = 0; f < NP; ++f) q[f][j] = fetch<R>(rUi, f * SP, g, kb, x, iz);
-        qp[j] = fetch<double>(rUi, PSI, g, kb, x, iz);
+        for (int f = 0; f < NP; ++f) q[f][j] = fetch<R>(rUi, f * SP, g, kb, x, izc);
+        qp[j] = fetch<double>(rUi, PSI, g, kb, x, izc);
     }
-    // halo values of the first slice
-    R hv[NP];
-    double hp = 0.0;
+    // halo loads of slice xs: the two points of every thread (the second
+    // only where the tile touches a z end), combined when written to LDS
+    R hr0[NP], hr1[NP];
+    double hq0, hq1 = 0.0;
+    auto halo_load = [&](int xs) {
+        const unsigned xo = hkb + (unsigned)(xs * g.nz);
+        const unsigned o0 = xo + (unsigned)hz0;
 #pragma unroll
-    for (int f = 0; f < NP; ++f) hv[f] = has_halo ? fetch<R>(rUi, f * SP, g, hkb, x0, hzg) : (R)0;
-    if (has_halo) hp = fetch<double>(rUi, PSI, g, hkb, x0, hzg);
+        for (int f = 0; f < NP; ++f) hr0[f] = bload<R>(rUi, o0 * ES, f * SP);
+        hq0 = bload<double>(rUi, o0 * 8u, PSI);
+        if (z_end) {
+            const unsigned o1 = xo + (unsigned)hz1;
+#pragma unroll
+            for (int f = 0; f < NP; ++f) hr1[f] = bload<R>(rUi, o1 * ES, f * SP);
+            hq1 = bload<double>(rUi, o1 * 8u, PSI);
+        }
+    };
+    halo_load(x0);
 
-    const R inv_dx = (R)(1.0 / g.dx), inv_dz = (R)(1.0 / g.dz), inv_dt = (R)(1.0 / g.dth);
-    const R dtR = (R)a.dt;
+    // RK-weighted coefficients: cb dt / h per axis (R planes and psi)
     constexpr double ca = RK<STAGE>::ca, cb = RK<STAGE>::cb;
+    const double cdt = cb * a.dt;
+    const double kxd = cdt / g.dx, kzd = cdt / g.dz, ktd = cdt / g.dth;
+    const R kxr = (R)kxd, kzr = (R)kzd, ktr = (R)ktd, cdtr = (R)cdt;
     const double zc = g.z0 + (iz + 0.5) * g.dz - a.zs;
     const int me = (tk + 3) * PZ + tz + 3;
     const int hi = hk * PZ + hz;
 
+    // velocity components of the cell, fetched one x step ahead
+    R cvx = (R)0, cvz = (R)0, cvt = (R)0;
+    if (x0 < x1) {
+        const unsigned cR = (kb + (unsigned)(x0 * g.nz + izc)) * ES;
+        cvx = bload<R>(rV, cR, EGB_VX * SP);
+        cvz = bload<R>(rV, cR, EGB_VZ * SP);
+        cvt = bload<R>(rV, cR, EGB_VT * SP);
+    }
+
     int buf = 0;
     for (int x = x0; x < x1; ++x, buf ^= 1) {
-        // slice x into LDS: own column from the queue, halo from registers
-        R* L = sR[buf];
-        double* LP = sP[buf];
+        const int wb = buf * S::BUF;
+        // slice x into LDS: own column from the queue, halo from its loads
+        if (zin) {
+            R own[NP];
 #pragma unroll
-        for (int f = 0; f < NP; ++f) L[f * PLANE + me] = q[f][3];
-        LP[me] = qp[3];
-        if (has_halo) {
-#pragma unroll
-            for (int f = 0; f < NP; ++f) L[f * PLANE + hi] = hv[f];
-            LP[hi] = hp;
+            for (int f = 0; f < NP; ++f) own[f] = q[f][3];
+            lds_put(sm, wb + me, own, qp[3]);
         }
-        // next queue entry (x + 4) and next halo slice (x + 1)
+        if (has_halo) {
+            R hv[NP];
+            double hp;
+            if (z_end) {
+#pragma unroll
+                for (int f = 0; f < NP; ++f) hv[f] = hw0 * hr0[f] + hw1 * hr1[f];
+                hp = (double)hw0 * hq0 + (double)hw1 * hq1;
+            } else {
+#pragma unroll
+                for (int f = 0; f < NP; ++f) hv[f] = hr0[f];
+                hp = hq0;
+            }
+            lds_put(sm, wb + hi, hv, hp);
+        }
+        // next queue entry (x + 4; clamped, replaced by the extrapolation past nx)
         R qn[NP];
         double qpn;
-        if (x + 4 < g.nx && iz < g.nz) {
-            const unsigned o = kb + (unsigned)((x + 4) * g.nz + iz);
+        {
+            const unsigned o = kb + (unsigned)(min(x + 4, g.nx - 1) * g.nz + izc);
 #pragma unroll
             for (int f = 0; f < NP; ++f) qn[f] = bload<R>(rUi, o * ES, f * SP);
             qpn = bload<double>(rUi, o * 8u, PSI);
-        } else {
-#pragma unroll
-            for (int f = 0; f < NP; ++f) qn[f] = fetch<R>(rUi, f * SP, g, kb, x + 4, iz);
-            qpn = fetch<double>(rUi, PSI, g, kb, x + 4, iz);
         }
-        if (has_halo && x + 1 < x1) {
-            if (hzg >= 0 && hzg < g.nz) {
-                const unsigned o = hkb + (unsigned)((x + 1) * g.nz + hzg);
-#pragma unroll
-                for (int f = 0; f < NP; ++f) hv[f] = bload<R>(rUi, o * ES, f * SP);
-                hp = bload<double>(rUi, o * 8u, PSI);
-            } else {
-#pragma unroll
-                for (int f = 0; f < NP; ++f) hv[f] = fetch<R>(rUi, f * SP, g, hkb, x + 1, hzg);
-                hp = fetch<double>(rUi, PSI, g, hkb, x + 1, hzg);
-            }
+        // next halo slice and the next cell's velocity (clamped at the chunk end)
+        const int xn = min(x + 1, x1 - 1);
+        halo_load(xn);
+        R nvx, nvz, nvt;
+        {
+            const unsigned cR = (kb + (unsigned)(xn * g.nz + izc)) * ES;
+            nvx = bload<R>(rV, cR, EGB_VX * SP);
+            nvz = bload<R>(rV, cR, EGB_VZ * SP);
+            nvt = bload<R>(rV, cR, EGB_VT * SP);
         }
         __syncthreads();
 
-        if (valid) {
-            const unsigned c = kb + (unsigned)(x * g.nz + iz);
-            const unsigned cR = c * ES, c8 = c * 8u;
+        {
+            const unsigned cR = (kb + (unsigned)(x * g.nz + izc)) * ES;
+            const unsigned c8 = cR / ES * 8u;
             const double xr = g.x0 + (x + 0.5) * g.dx - a.xs;
-            if (xr * xr + zc * zc <= a.r02) {  // source ball: Dirichlet data
+            const bool ball = xr * xr + zc * zc <= a.r02;  // source ball: Dirichlet data
+            const R vx = cvx, vz = cvz, vt = cvt;
+            const bool mx = vx >= (R)0, mz = vz >= (R)0, mt = vt >= (R)0;
+            const R gx = fabs(vx) * kxr, gz = fabs(vz) * kzr, gt = fabs(vt) * ktr;
+            const double gpx = (double)fabs(vx) * kxd, gpz = (double)fabs(vz) * kzd, gpt = (double)fabs(vt) * ktd;
+            // loads consumed after the stencils (their latency hides behind them)
+            R u0[NP], Am[4];
+            double p0;
+            if constexpr (STAGE != 0) {
 #pragma unroll
-                for (int f = 0; f < NP; ++f) bstore(bload<R>(rU0, cR, f * SP), rUo, cR, f * SP);
-                bstore(bload<double>(rU0, c8, PSI), rUo, c8, PSI);
+                for (int f = 0; f < NP; ++f) u0[f] = bload<R>(rU0, cR, f * SP);
+                p0 = bload<double>(rU0, c8, PSI);
             } else {
-                const R cx = bload<R>(rV, cR, EGB_VX * SP) * inv_dx;
-                const R cz = bload<R>(rV, cR, EGB_VZ * SP) * inv_dz;
-                const R ct = bload<R>(rV, cR, EGB_VT * SP) * inv_dt;
-                R A11 = 0, A12 = 0, A21 = 0, A22 = 0;
-                if constexpr (!KIN) {
-                    A11 = bload<R>(rV, cR, EGB_A11 * SP);
-                    A12 = bload<R>(rV, cR, EGB_A12 * SP);
-                    A21 = bload<R>(rV, cR, EGB_A21 * SP);
-                    A22 = bload<R>(rV, cR, EGB_A22 * SP);
-                }
-                R u0[NP];
-                double p0 = 0.0;
-                if (STAGE != 0) {
 #pragma unroll
-                    for (int f = 0; f < NP; ++f) u0[f] = bload<R>(rU0, cR, f * SP);
-                    p0 = bload<double>(rU0, c8, PSI);
-                }
-                const bool mx = cx >= (R)0, mz = cz >= (R)0, mt = ct >= (R)0;
-                R Lf[NP];
+                for (int f = 0; f < NP; ++f) u0[f] = q[f][3];
+                p0 = qp[3];
+            }
+            if constexpr (!KIN) {
 #pragma unroll
-                for (int f = 0; f < NP; ++f) {
-                    const R* Lp = L + f * PLANE + me;
-                    R uz[7], ut[7];
+                for (int j = 0; j < 4; ++j) Am[j] = bload<R>(rV, cR, (EGB_A11 + j) * SP);
+            }
+            // cb (Uin + dt S) - sum_a g_a W_a, then + ca U0
+            R acc[NP];
 #pragma unroll
-                    for (int m = 0; m < 7; ++m) {
-                        uz[m] = Lp[m - 3];
-                        ut[m] = Lp[(m - 3) * PZ];
-                    }
-                    Lf[f] = -(cx * weno7<R, R>(q[f], mx) + cz * weno7<R, R>(uz, mz) + ct * weno7<R, R>(ut, mt));
-                }
-                if constexpr (!KIN) {
-                    Lf[EGB_RE_C] += A11 * q[EGB_RE_C][3] + A12 * q[EGB_RE_B][3];
-                    Lf[EGB_RE_B] += A21 * q[EGB_RE_C][3] + A22 * q[EGB_RE_B][3];
-                    Lf[EGB_IM_C] += A11 * q[EGB_IM_C][3] + A12 * q[EGB_IM_B][3];
-                    Lf[EGB_IM_B] += A21 * q[EGB_IM_C][3] + A22 * q[EGB_IM_B][3];
-                }
-                double pz[7], pt[7];
-                const double* LPp = LP + me;
+            for (int f = 0; f < NP; ++f) acc[f] = (R)cb * q[f][3];
+            double accp = cb * qp[3] + cdt;
+            // x: upwind stencil from the register queue
+            auto xpart = [&](auto dir) {
+                constexpr int D = decltype(dir)::value;
 #pragma unroll
-                for (int m = 0; m < 7; ++m) {
-                    pz[m] = LPp[m - 3];
-                    pt[m] = LPp[(m - 3) * PZ];
-                }
-                const double conv = (double)cx * (double)weno7<double, R>(qp, mx) +
-                                    (double)cz * (double)weno7<double, R>(pz, mz) +
-                                    (double)ct * (double)weno7<double, R>(pt, mt);
-                const double Lpsi = 1.0 - conv;
+                for (int f = 0; f < NP; ++f)
+                    acc[f] -= gx * weno_up<R>(upw<D>(q[f], 0, mx), upw<D>(q[f], 1, mx), upw<D>(q[f], 2, mx),
+                                              q[f][3], upw<D>(q[f], 4, mx), upw<D>(q[f], 5, mx));
+                accp -= gpx * (double)weno_up<R>(upw<D>(qp, 0, mx), upw<D>(qp, 1, mx), upw<D>(qp, 2, mx), qp[3],
+                                                 upw<D>(qp, 4, mx), upw<D>(qp, 5, mx));
+            };
+            if (__all(mx)) xpart(std::integral_constant<int, 0>{});
+            else if (!__any(mx)) xpart(std::integral_constant<int, 1>{});
+            else xpart(std::integral_constant<int, 2>{});
+            // z and theta: upwind stencils from LDS at mirrored addresses
+            const int meB = (wb + me) * WS;
+            auto lpart = [&](int step, R gR, double gP) {
+                const int a0 = meB - 3 * step, a1 = meB - 2 * step, a2 = meB - step;
+                const int a4 = meB + step, a5 = meB + 2 * step;
 #pragma unroll
-                for (int f = 0; f < NP; ++f) {
-                    const R y = q[f][3] + dtR * Lf[f];
-                    bstore((STAGE == 0) ? y : (R)ca * u0[f] + (R)cb * y, rUo, cR, f * SP);
-                }
-                const double yp = qp[3] + a.dt * Lpsi;
-                bstore((STAGE == 0) ? yp : ca * p0 + cb * yp, rUo, c8, PSI);
+                for (int f = 0; f < NP; ++f)
+                    acc[f] -= gR * weno_up<R>(lds_r<R>(sm, a0, f), lds_r<R>(sm, a1, f), lds_r<R>(sm, a2, f), q[f][3],
+                                              lds_r<R>(sm, a4, f), lds_r<R>(sm, a5, f));
+                accp -= gP * (double)weno_up<R>(lds_psi<NP>(sm, a0), lds_psi<NP>(sm, a1), lds_psi<NP>(sm, a2), qp[3],
+                                                lds_psi<NP>(sm, a4), lds_psi<NP>(sm, a5));
+            };
+            lpart(mz ? WS : -WS, gz, gpz);
+            lpart(mt ? PZ * WS : -PZ * WS, gt, gpt);
+            if constexpr (!KIN) {
+                const R A11 = cdtr * Am[0], A12 = cdtr * Am[1], A21 = cdtr * Am[2], A22 = cdtr * Am[3];
+                acc[EGB_RE_C] += A11 * q[EGB_RE_C][3] + A12 * q[EGB_RE_B][3];
+                acc[EGB_RE_B] += A21 * q[EGB_RE_C][3] + A22 * q[EGB_RE_B][3];
+                acc[EGB_IM_C] += A11 * q[EGB_IM_C][3] + A12 * q[EGB_IM_B][3];
+                acc[EGB_IM_B] += A21 * q[EGB_IM_C][3] + A22 * q[EGB_IM_B][3];
+            }
+            if constexpr (STAGE != 0) {
+#pragma unroll
+                for (int f = 0; f < NP; ++f) acc[f] += (R)ca * u0[f];
+                accp += ca * p0;
+            }
+            if (valid) {
+#pragma unroll
+                for (int f = 0; f < NP; ++f) bstore(ball ? u0[f] : acc[f], rUo, cR, f * SP);
+                bstore(ball ? p0 : accp, rUo, c8, PSI);
             }
         }
         // shift the queue
+        const bool xin = x + 4 < g.nx;
+#pragma unroll
+        for (int f = 0; f < NP; ++f) qn[f] = xin ? qn[f] : (R)2 * q[f][6] - q[f][5];
+        qpn = xin ? qpn : 2.0 * qp[6] - qp[5];
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
 #pragma unroll
@@ -327,13 +462,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
 #pragma unroll
         for (int f = 0; f < NP; ++f) q[f][6] = qn[f];
         qp[6] = qpn;
+        cvx = nvx;
+        cvz = nvz;
+        cvt = nvt;
     }
 }
 
 template <typename R, int STAGE, int TK, bool KIN>
 __global__ __launch_bounds__(64 * TK) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
 void k_stage(StageArgs a, TileArgs t) {
-    __shared__ StageSmem<R, TK> sm;
+    __shared__ StageSmem<R, TK, KIN ? 1 : 5> sm;
     stage_tile<R, STAGE, TK, KIN>(a, t, xcd_remap(blockIdx.x, t.nblocks), sm);
 }
 
@@ -348,7 +486,7 @@ struct BatchItem {
 template <typename R, int STAGE, int TK>
 __global__ __launch_bounds__(64 * TK) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
 void k_stage_batched(const BatchItem* __restrict__ items, const int* __restrict__ first, int nprob, int total) {
-    __shared__ StageSmem<R, TK> sm;
+    __shared__ StageSmem<R, TK, 5> sm;
     for (int q = blockIdx.x; q < total; q += gridDim.x) {
         const int t = xcd_remap(q, total);
         int lo = 0, hi = nprob;  // first[lo] <= t < first[hi]
