@@ -24,7 +24,11 @@
 #include <hip/hip_runtime.h>
 #include <stdlib.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 
 #include "egb_device.h"
 #include "egb_internal.h"
@@ -96,27 +100,8 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsig
                                           (int)voff, (int)soff, 0);
 }
 
-// Value of one plane at (slice kb, x, z) with the ghost rules: x or z outside
-// the domain -> linear extrapolation from the two nearest cells along that
-// axis; both outside (a corner, never read) -> 0.  `soff` is the plane's
-// byte offset in the array.
-template <typename T>
-__device__ __forceinline__ T fetch(__amdgpu_buffer_rsrc_t r, unsigned soff, const GridArgs& g, unsigned kb, int x,
-                                   int z) {
-    const bool xo = x < 0 || x >= g.nx, zo = z >= g.nz || z < 0;
-    if (!xo && !zo) return bload<T>(r, (kb + (unsigned)(x * g.nz + z)) * (unsigned)sizeof(T), soff);
-    if (xo && zo) return (T)0;
-    if (xo) {
-        const int b0 = x < 0 ? 0 : g.nx - 1, b1 = x < 0 ? 1 : g.nx - 2, e = x < 0 ? -x : x - (g.nx - 1);
-        return (T)(e + 1) * bload<T>(r, (kb + (unsigned)(b0 * g.nz + z)) * (unsigned)sizeof(T), soff) -
-               (T)e * bload<T>(r, (kb + (unsigned)(b1 * g.nz + z)) * (unsigned)sizeof(T), soff);
-    }
-    const int b0 = z < 0 ? 0 : g.nz - 1, b1 = z < 0 ? 1 : g.nz - 2, e = z < 0 ? -z : z - (g.nz - 1);
-    const unsigned xb = kb + (unsigned)(x * g.nz);
-    return (T)(e + 1) * bload<T>(r, (xb + b0) * (unsigned)sizeof(T), soff) -
-           (T)e * bload<T>(r, (xb + b1) * (unsigned)sizeof(T), soff);
-}
-
+// Tiles of one problem: ntz x ntk (z, theta) tiles; the batched queue also
+// splits x into nxc chunks of kx; nblocks is the launch's block count.
 struct TileArgs {
     int ntz, ntk, nxc, kx, nblocks;
     unsigned state_bytes, vel_bytes;
@@ -192,8 +177,8 @@ __device__ __forceinline__ double lds_psi(const S& sm, int byte) {
     }
 }
 
-// One (z, theta) tile x one x chunk of an RK stage; `logical` numbers the
-// tile within its problem.
+// One (z, theta) tile (number `tile`, z fastest) over the x range [x0, x1)
+// of an RK stage.
 // KIN: only phi1 and psi (the planes a traveltime depends on).
 //
 // Per plane f the cell's new value is
@@ -210,7 +195,7 @@ __device__ __forceinline__ double lds_psi(const S& sm, int byte) {
 // a z end), an x ghost continues the line of the last two queue entries,
 // and lanes past nz load an in-domain column and write nothing.
 template <typename R, int STAGE, int TK, bool KIN>
-__device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t, int logical,
+__device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t, int tile, int x0, int x1,
                                            StageSmem<R, TK, KIN ? 1 : 5>& sm) {
     constexpr int NP = KIN ? 1 : 5;  // R planes marched
     using S = StageSmem<R, TK, NP>;
@@ -221,10 +206,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
     constexpr unsigned ES = sizeof(R);
 
     const GridArgs& g = a.g;
-    const int tzi = logical % t.ntz;
-    const int rest = logical / t.ntz;
-    const int tki = rest % t.ntk;
-    const int xc = rest / t.ntk;
+    const int tzi = tile % t.ntz;
+    const int tki = tile / t.ntz;
 
     const int tz = threadIdx.x, tk = threadIdx.y, tid = tk * TZ + tz;
     const int iz = tzi * TZ + tz;
@@ -279,18 +262,33 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
     }
     const bool z_end = tzi == 0 || tzi == t.ntz - 1 || (tzi + 1) * TZ + 3 > g.nz;  // block-uniform
 
-    const int x0 = xc * t.kx;
-    const int x1 = min(x0 + t.kx, g.nx);
-    // queue of the column's x-neighbours: q[f][j] at x - 3 + j
+    // queue of the column's x-neighbours: q[f][j] at x - 3 + j.  x ghosts
+    // continue the line of the two entries next to them, one at a time (the
+    // same recurrence as inside the loop, so the values do not depend on
+    // where a segment starts).
     R q[NP][7];
     double qp[7];
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
-        const int x = x0 - 3 + j;
+        const unsigned o = kb + (unsigned)(min(max(x0 - 3 + j, 0), g.nx - 1) * g.nz + izc);
 #pragma unroll
-        for (int f = 0; f < NP; ++f) q[f][j] = fetch<R>(rUi, f * SP, g, kb, x, izc);
-        qp[j] = fetch<double>(rUi, PSI, g, kb, x, izc);
+        for (int f = 0; f < NP; ++f) q[f][j] = bload<R>(rUi, o * ES, f * SP);
+        qp[j] = bload<double>(rUi, o * 8u, PSI);
     }
+#pragma unroll
+    for (int j = 2; j >= 0; --j)
+        if (x0 - 3 + j < 0) {
+#pragma unroll
+            for (int f = 0; f < NP; ++f) q[f][j] = (R)2 * q[f][j + 1] - q[f][j + 2];
+            qp[j] = 2.0 * qp[j + 1] - qp[j + 2];
+        }
+#pragma unroll
+    for (int j = 4; j < 7; ++j)
+        if (x0 - 3 + j >= g.nx) {
+#pragma unroll
+            for (int f = 0; f < NP; ++f) q[f][j] = (R)2 * q[f][j - 1] - q[f][j - 2];
+            qp[j] = 2.0 * qp[j - 1] - qp[j - 2];
+        }
     // halo loads of slice xs: the two points of every thread (the second
     // only where the tile touches a z end), combined when written to LDS
     R hr0[NP], hr1[NP];
@@ -313,8 +311,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
     // RK-weighted coefficients: cb dt / h per axis (R planes and psi)
     constexpr double ca = RK<STAGE>::ca, cb = RK<STAGE>::cb;
     const double cdt = cb * a.dt;
-    const double kxd = cdt / g.dx, kzd = cdt / g.dz, ktd = cdt / g.dth;
-    const R kxr = (R)kxd, kzr = (R)kzd, ktr = (R)ktd, cdtr = (R)cdt;
+    const R kxr = (R)(cdt / g.dx), kzr = (R)(cdt / g.dz), ktr = (R)(cdt / g.dth), cdtr = (R)cdt;
     const double zc = g.z0 + (iz + 0.5) * g.dz - a.zs;
     const int me = (tk + 3) * PZ + tz + 3;
     const int hi = hk * PZ + hz;
@@ -381,7 +378,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
             const R vx = cvx, vz = cvz, vt = cvt;
             const bool mx = vx >= (R)0, mz = vz >= (R)0, mt = vt >= (R)0;
             const R gx = fabs(vx) * kxr, gz = fabs(vz) * kzr, gt = fabs(vt) * ktr;
-            const double gpx = (double)fabs(vx) * kxd, gpz = (double)fabs(vz) * kzd, gpt = (double)fabs(vt) * ktd;
             // loads consumed after the stencils (their latency hides behind them)
             R u0[NP], Am[4];
             double p0;
@@ -398,8 +394,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
 #pragma unroll
                 for (int j = 0; j < 4; ++j) Am[j] = bload<R>(rV, cR, (EGB_A11 + j) * SP);
             }
-            // cb (Uin + dt S) - sum_a g_a W_a, then + ca U0
-            R acc[NP];
+            // cb (Uin + dt S) - sum_a g_a W_a, then + ca U0; the psi stencil
+            // terms (each already rounded to R) are summed in R and added to
+            // the double psi once
+            R acc[NP], convp;
 #pragma unroll
             for (int f = 0; f < NP; ++f) acc[f] = (R)cb * q[f][3];
             double accp = cb * qp[3] + cdt;
@@ -410,26 +408,27 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
                 for (int f = 0; f < NP; ++f)
                     acc[f] -= gx * weno_up<R>(upw<D>(q[f], 0, mx), upw<D>(q[f], 1, mx), upw<D>(q[f], 2, mx),
                                               q[f][3], upw<D>(q[f], 4, mx), upw<D>(q[f], 5, mx));
-                accp -= gpx * (double)weno_up<R>(upw<D>(qp, 0, mx), upw<D>(qp, 1, mx), upw<D>(qp, 2, mx), qp[3],
-                                                 upw<D>(qp, 4, mx), upw<D>(qp, 5, mx));
+                convp = gx * weno_up<R>(upw<D>(qp, 0, mx), upw<D>(qp, 1, mx), upw<D>(qp, 2, mx), qp[3],
+                                        upw<D>(qp, 4, mx), upw<D>(qp, 5, mx));
             };
             if (__all(mx)) xpart(std::integral_constant<int, 0>{});
             else if (!__any(mx)) xpart(std::integral_constant<int, 1>{});
             else xpart(std::integral_constant<int, 2>{});
             // z and theta: upwind stencils from LDS at mirrored addresses
             const int meB = (wb + me) * WS;
-            auto lpart = [&](int step, R gR, double gP) {
+            auto lpart = [&](int step, R gR) {
                 const int a0 = meB - 3 * step, a1 = meB - 2 * step, a2 = meB - step;
                 const int a4 = meB + step, a5 = meB + 2 * step;
 #pragma unroll
                 for (int f = 0; f < NP; ++f)
                     acc[f] -= gR * weno_up<R>(lds_r<R>(sm, a0, f), lds_r<R>(sm, a1, f), lds_r<R>(sm, a2, f), q[f][3],
                                               lds_r<R>(sm, a4, f), lds_r<R>(sm, a5, f));
-                accp -= gP * (double)weno_up<R>(lds_psi<NP>(sm, a0), lds_psi<NP>(sm, a1), lds_psi<NP>(sm, a2), qp[3],
-                                                lds_psi<NP>(sm, a4), lds_psi<NP>(sm, a5));
+                convp += gR * weno_up<R>(lds_psi<NP>(sm, a0), lds_psi<NP>(sm, a1), lds_psi<NP>(sm, a2), qp[3],
+                                         lds_psi<NP>(sm, a4), lds_psi<NP>(sm, a5));
             };
-            lpart(mz ? WS : -WS, gz, gpz);
-            lpart(mt ? PZ * WS : -PZ * WS, gt, gpt);
+            lpart(mz ? WS : -WS, gz);
+            lpart(mt ? PZ * WS : -PZ * WS, gt);
+            accp -= (double)convp;
             if constexpr (!KIN) {
                 const R A11 = cdtr * Am[0], A12 = cdtr * Am[1], A21 = cdtr * Am[2], A22 = cdtr * Am[3];
                 acc[EGB_RE_C] += A11 * q[EGB_RE_C][3] + A12 * q[EGB_RE_B][3];
@@ -472,7 +471,20 @@ template <typename R, int STAGE, int TK, bool KIN>
 __global__ __launch_bounds__(64 * TK) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
 void k_stage(StageArgs a, TileArgs t) {
     __shared__ StageSmem<R, TK, KIN ? 1 : 5> sm;
-    stage_tile<R, STAGE, TK, KIN>(a, t, xcd_remap(blockIdx.x, t.nblocks), sm);
+    // The (tile, x) steps, x fastest, split into gridDim.x equal contiguous
+    // ranges (the grid is what the chip holds at once, so every block runs in
+    // one round); a range crossing a tile boundary is two segments.
+    const long long W = (long long)t.ntz * t.ntk * a.g.nx;
+    const long long b = xcd_remap(blockIdx.x, gridDim.x);
+    long long w = W * b / gridDim.x;
+    const long long w1 = W * (b + 1) / gridDim.x;
+    while (w < w1) {
+        const int tile = (int)(w / a.g.nx), xa = (int)(w % a.g.nx);
+        const int xb = (int)min((long long)a.g.nx, xa + (w1 - w));
+        stage_tile<R, STAGE, TK, KIN>(a, t, tile, xa, xb, sm);
+        w += xb - xa;
+        if (w < w1) __syncthreads();  // the segment's last LDS reads are done
+    }
 }
 
 // Batched march: a persistent grid walks one queue of tiles spanning every
@@ -498,7 +510,9 @@ void k_stage_batched(const BatchItem* __restrict__ items, const int* __restrict_
         const StageArgs a = items[lo].a[STAGE];
         const TileArgs ta = items[lo].t;
         __syncthreads();  // the previous tile's last LDS reads are done
-        stage_tile<R, STAGE, TK, false>(a, ta, t - first[lo], sm);
+        const int l = t - first[lo], ntile = ta.ntz * ta.ntk;
+        const int x0 = (l / ntile) * ta.kx;
+        stage_tile<R, STAGE, TK, false>(a, ta, l % ntile, x0, min(x0 + ta.kx, a.g.nx), sm);
     }
 }
 
@@ -506,17 +520,50 @@ unsigned long long state_bytes_of(const GridArgs& g, size_t es) {
     return (unsigned long long)g.stride * (5ull * es + 8ull);
 }
 
+// Blocks of a kernel that the device holds at once (cached per kernel and device).
+int resident_blocks(const void* kernel, int threads) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(kernel, dev);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    const int n = std::max(1, per_cu) * std::max(1, ncu);
+    cache[key] = n;
+    return n;
+}
+
 template <typename R, int TK, bool KIN>
-hipError_t launch_stage_t(const StageArgs& a, int stage, int kx, hipStream_t s) {
+hipError_t launch_stage_t(const StageArgs& a, int stage, hipStream_t s) {
     TileArgs t;
     t.ntz = (a.g.nz + TZ - 1) / TZ;
     t.ntk = (a.g.nth + TK - 1) / TK;
-    t.kx = kx;
-    t.nxc = (a.g.nx + kx - 1) / kx;
-    t.nblocks = t.ntz * t.ntk * t.nxc;
+    t.kx = a.g.nx;
+    t.nxc = 1;
     t.state_bytes = (unsigned)state_bytes_of(a.g, sizeof(R));
     t.vel_bytes = (unsigned)(7ull * (unsigned long long)a.g.stride * sizeof(R));
-    const dim3 grid(t.nblocks), block(TZ, TK);
+    const void* k = stage == 0 ? (const void*)k_stage<R, 0, TK, KIN>
+                  : stage == 1 ? (const void*)k_stage<R, 1, TK, KIN> : (const void*)k_stage<R, 2, TK, KIN>;
+    // one round of resident blocks, each with at least MIN_STEPS x steps
+    // (EGB_STAGE_GRID overrides, for tuning sweeps)
+    constexpr long long MIN_STEPS = 16;
+    static const int forced = [] {
+        const char* e = getenv("EGB_STAGE_GRID");
+        return e ? atoi(e) : 0;
+    }();
+    const long long W = (long long)t.ntz * t.ntk * a.g.nx;
+    long long G = forced > 0 ? forced : resident_blocks(k, 64 * TK);
+    if (G <= 0) return hipErrorInvalidDeviceFunction;
+    if (forced <= 0) G = std::min(G, std::max(1LL, W / MIN_STEPS));
+    G = std::min(G, W);
+    t.nblocks = (int)G;
+    const dim3 grid((unsigned)G), block(TZ, TK);
     switch (stage) {
         case 0: k_stage<R, 0, TK, KIN><<<grid, block, 0, s>>>(a, t); break;
         case 1: k_stage<R, 1, TK, KIN><<<grid, block, 0, s>>>(a, t); break;
@@ -525,8 +572,8 @@ hipError_t launch_stage_t(const StageArgs& a, int stage, int kx, hipStream_t s) 
     return hipGetLastError();
 }
 
-// x-chunk length: enough blocks to fill the chip several times over
-// (EGB_STAGE_KX overrides, for tuning sweeps).
+// x-chunk length of the batched tile queue: enough tiles to fill the chip
+// several times over (EGB_STAGE_KX overrides, for tuning sweeps).
 int choose_kx(const GridArgs& g, int tk) {
     static const int forced = [] {
         const char* e = getenv("EGB_STAGE_KX");
@@ -610,10 +657,8 @@ bool stage_fits_32bit(const GridArgs& g, int dtype) {
 
 hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s, bool kinematic) {
     if (dtype == EGB_F64)
-        return kinematic ? launch_stage_t<double, 8, true>(a, stage, choose_kx(a.g, 8), s)
-                         : launch_stage_t<double, 8, false>(a, stage, choose_kx(a.g, 8), s);
-    return kinematic ? launch_stage_t<float, 12, true>(a, stage, choose_kx(a.g, 12), s)
-                     : launch_stage_t<float, 12, false>(a, stage, choose_kx(a.g, 12), s);
+        return kinematic ? launch_stage_t<double, 8, true>(a, stage, s) : launch_stage_t<double, 8, false>(a, stage, s);
+    return kinematic ? launch_stage_t<float, 12, true>(a, stage, s) : launch_stage_t<float, 12, false>(a, stage, s);
 }
 
 }  // namespace egb
