@@ -232,7 +232,7 @@ egb_status egb_adjoint_medium(const egb_grid* g, const egb_medium* m, const void
 
 size_t egb_workspace_size_batched(const egb_problem* probs, int32_t nprob) {
     if (!probs || nprob < 1) return 0;
-    size_t b = align256((size_t)nprob * batch_item_bytes()) + align256((size_t)(nprob + 1) * sizeof(int));
+    size_t b = align256((size_t)nprob * batch_item_bytes()) + align256((size_t)(nprob + 1) * sizeof(long long));
     for (int p = 0; p < nprob; ++p) {
         if (!grid_ok(&probs[p].grid)) return 0;
         b += 2 * align256(state_bytes(probs[p].grid));
@@ -254,33 +254,31 @@ egb_status egb_liouville_step_batched(const egb_problem* probs, int32_t nprob, i
     if (nsteps == 0) return EGB_OK;
     if (!work || !aligned16(work)) return EGB_EINVAL;
     if (work_bytes < egb_workspace_size_batched(probs, nprob)) return EGB_EWORKSPACE;
-    // workspace: item table | first[] | per-problem U1, U2
+    // workspace: item table | wfirst[] | per-problem U1, U2
     char* w = static_cast<char*>(work);
     char* d_items = w;
-    int* d_first = reinterpret_cast<int*>(w + align256((size_t)nprob * batch_item_bytes()));
-    char* bufs = reinterpret_cast<char*>(d_first) + align256((size_t)(nprob + 1) * sizeof(int));
+    long long* d_first = reinterpret_cast<long long*>(w + align256((size_t)nprob * batch_item_bytes()));
+    char* bufs = reinterpret_cast<char*>(d_first) + align256((size_t)(nprob + 1) * sizeof(long long));
     std::vector<char> items((size_t)nprob * batch_item_bytes());
-    std::vector<int> first(nprob + 1, 0);
+    std::vector<long long> first(nprob + 1, 0);
     for (int p = 0; p < nprob; ++p) {
         const egb_problem& q = probs[p];
         const size_t sb = align256(state_bytes(q.grid));
         void* U1 = bufs;
         void* U2 = bufs + sb;
         bufs += 2 * sb;
-        const int n = batch_item_fill(items.data() + (size_t)p * batch_item_bytes(), grid_args(q.grid), dtype, q.vel3d,
+        const long long n = batch_item_fill(items.data() + (size_t)p * batch_item_bytes(), grid_args(q.grid), dtype, q.vel3d,
                                       q.state, U1, U2, q.dt, q.src.xs, q.src.zs, q.src.r0 * q.src.r0);
         first[p + 1] = first[p] + n;
     }
-    const int total = first[nprob];
+    const long long total = first[nprob];
     hipError_t e = hipMemcpy(d_items, items.data(), items.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(d_first, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_first, first.data(), first.size() * sizeof(long long), hipMemcpyHostToDevice);
     if (e != hipSuccess) return EGB_EHIP;
-    // One block per queue entry: measured ~10 % faster on MI355X than a
-    // persistent grid of resident blocks walking the same queue (one block per
-    // CU fits, and the hardware dispatcher balances the uneven tiles better).
-    // EGB_BATCH_GRID=<blocks> selects the persistent walk (tuning sweeps).
-    int grid = total;
-    if (const char* ge = getenv("EGB_BATCH_GRID")) grid = std::max(1, std::min(total, atoi(ge)));
+    // one round of resident blocks over all problems' steps
+    // (EGB_BATCH_GRID=<blocks> overrides, for tuning sweeps)
+    int grid = 0;
+    if (const char* ge = getenv("EGB_BATCH_GRID")) grid = std::max(1, atoi(ge));
     // capture the whole march in one graph on a private stream, replay on `stream`
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;

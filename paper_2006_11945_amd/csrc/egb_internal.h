@@ -71,12 +71,11 @@ bool stage_fits_32bit(const GridArgs& g, int dtype);
 
 // Batched march (see liouville.hip).
 size_t batch_item_bytes();
-int batch_item_fill(void* item, const GridArgs& g, int dtype, const void* vel, void* state, void* U1, void* U2,
-                    double dt, double xs, double zs, double r02);
-hipError_t launch_stage_batched(const void* items, const int* first, int nprob, int total, int dtype, int stage,
-                                int grid, hipStream_t s);
-int stage_block_threads(int dtype);
-const void* stage_batched_kernel(int dtype, int stage);
+long long batch_item_fill(void* item, const GridArgs& g, int dtype, const void* vel, void* state, void* U1,
+                          void* U2, double dt, double xs, double zs, double r02);
+// grid <= 0: one round of resident blocks
+hipError_t launch_stage_batched(const void* items, const long long* wfirst, int nprob, long long total, int dtype,
+                                int stage, int grid, hipStream_t s);
 
 // Adjoint of the kinematic march (see adjoint.hip).
 size_t adjoint_packet_bytes(const egb_grid& g);

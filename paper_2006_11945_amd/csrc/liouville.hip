@@ -487,32 +487,42 @@ void k_stage(StageArgs a, TileArgs t) {
     }
 }
 
-// Batched march: a persistent grid walks one queue of tiles spanning every
-// problem (uneven grids, own buffers and dt).  first[p] is the first queue
-// index of problem p (first[nprob] = total).
+// Batched march: one launch walks the problems in order (uneven grids, own
+// buffers and dt); within problem p every block takes its equal contiguous
+// share of the (tile, x) steps, x fastest, exactly like k_stage, so that the
+// blocks running at any moment work on the same problem (its arrays stay in
+// the L2 and TLB).  wfirst[p + 1] - wfirst[p] is the step count of problem p.
 struct BatchItem {
     StageArgs a[3];  // stage 0, 1, 2 buffers of this problem
     TileArgs t;
 };
 
+constexpr long long MIN_STEPS = 16;  // fewest x steps worth a block's prologue
+
 template <typename R, int STAGE, int TK>
 __global__ __launch_bounds__(64 * TK) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
-void k_stage_batched(const BatchItem* __restrict__ items, const int* __restrict__ first, int nprob, int total) {
+void k_stage_batched(const BatchItem* __restrict__ items, const long long* __restrict__ wfirst, int nprob) {
     __shared__ StageSmem<R, TK, 5> sm;
-    for (int q = blockIdx.x; q < total; q += gridDim.x) {
-        const int t = xcd_remap(q, total);
-        int lo = 0, hi = nprob;  // first[lo] <= t < first[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (first[mid] <= t) lo = mid; else hi = mid;
-        }
+    const long long b = xcd_remap(blockIdx.x, gridDim.x);
+    bool first_seg = true;
+    for (int p = 0; p < nprob; ++p) {
         // private copies: the stage's stores cannot alias them, so they stay in scalar registers
-        const StageArgs a = items[lo].a[STAGE];
-        const TileArgs ta = items[lo].t;
-        __syncthreads();  // the previous tile's last LDS reads are done
-        const int l = t - first[lo], ntile = ta.ntz * ta.ntk;
-        const int x0 = (l / ntile) * ta.kx;
-        stage_tile<R, STAGE, TK, false>(a, ta, l % ntile, x0, min(x0 + ta.kx, a.g.nx), sm);
+        const StageArgs a = items[p].a[STAGE];
+        const TileArgs ta = items[p].t;
+        // as k_stage: at most one block per MIN_STEPS steps of this problem
+        const long long W = wfirst[p + 1] - wfirst[p];
+        const long long G = min((long long)gridDim.x, max(1LL, W / MIN_STEPS));
+        if (b >= G) continue;
+        long long w = W * b / G;
+        const long long w1 = W * (b + 1) / G;
+        while (w < w1) {
+            const int tile = (int)(w / a.g.nx), xa = (int)(w % a.g.nx);
+            const int xb = (int)min((long long)a.g.nx, xa + (w1 - w));
+            if (!first_seg) __syncthreads();  // the previous segment's last LDS reads are done
+            first_seg = false;
+            stage_tile<R, STAGE, TK, false>(a, ta, tile, xa, xb, sm);
+            w += xb - xa;
+        }
     }
 }
 
@@ -552,7 +562,6 @@ hipError_t launch_stage_t(const StageArgs& a, int stage, hipStream_t s) {
                   : stage == 1 ? (const void*)k_stage<R, 1, TK, KIN> : (const void*)k_stage<R, 2, TK, KIN>;
     // one round of resident blocks, each with at least MIN_STEPS x steps
     // (EGB_STAGE_GRID overrides, for tuning sweeps)
-    constexpr long long MIN_STEPS = 16;
     static const int forced = [] {
         const char* e = getenv("EGB_STAGE_GRID");
         return e ? atoi(e) : 0;
@@ -572,29 +581,21 @@ hipError_t launch_stage_t(const StageArgs& a, int stage, hipStream_t s) {
     return hipGetLastError();
 }
 
-// x-chunk length of the batched tile queue: enough tiles to fill the chip
-// several times over (EGB_STAGE_KX overrides, for tuning sweeps).
-int choose_kx(const GridArgs& g, int tk) {
-    static const int forced = [] {
-        const char* e = getenv("EGB_STAGE_KX");
-        return e ? atoi(e) : 0;
-    }();
-    if (forced > 0) return forced < g.nx ? forced : g.nx;
-    const long long tiles = (long long)((g.nz + TZ - 1) / TZ) * ((g.nth + tk - 1) / tk);
-    int kx = g.nx;
-    while (kx > 8 && tiles * ((g.nx + kx - 1) / kx) < 512) kx = (kx + 1) / 2;
-    return kx;
-}
-
 template <typename R, int TK>
-hipError_t launch_batched_t(const void* items, const int* first, int nprob, int total, int stage, int grid,
-                            hipStream_t s) {
+hipError_t launch_batched_t(const void* items, const long long* wfirst, int nprob, long long total, int stage,
+                            int grid, hipStream_t s) {
+    const void* k = stage == 0 ? (const void*)k_stage_batched<R, 0, TK>
+                  : stage == 1 ? (const void*)k_stage_batched<R, 1, TK> : (const void*)k_stage_batched<R, 2, TK>;
+    // one round of resident blocks (each problem uses at most one per MIN_STEPS steps)
+    long long G = grid > 0 ? grid : resident_blocks(k, 64 * TK);
+    if (G <= 0) return hipErrorInvalidDeviceFunction;
+    G = std::max(1LL, std::min(G, total));
     const dim3 block(TZ, TK);
     const BatchItem* it = static_cast<const BatchItem*>(items);
     switch (stage) {
-        case 0: k_stage_batched<R, 0, TK><<<grid, block, 0, s>>>(it, first, nprob, total); break;
-        case 1: k_stage_batched<R, 1, TK><<<grid, block, 0, s>>>(it, first, nprob, total); break;
-        default: k_stage_batched<R, 2, TK><<<grid, block, 0, s>>>(it, first, nprob, total); break;
+        case 0: k_stage_batched<R, 0, TK><<<(unsigned)G, block, 0, s>>>(it, wfirst, nprob); break;
+        case 1: k_stage_batched<R, 1, TK><<<(unsigned)G, block, 0, s>>>(it, wfirst, nprob); break;
+        default: k_stage_batched<R, 2, TK><<<(unsigned)G, block, 0, s>>>(it, wfirst, nprob); break;
     }
     return hipGetLastError();
 }
@@ -603,8 +604,8 @@ hipError_t launch_batched_t(const void* items, const int* first, int nprob, int 
 
 size_t batch_item_bytes() { return sizeof(BatchItem); }
 
-// Fill the host-side item for one problem; returns its tile count.
-int batch_item_fill(void* item, const GridArgs& g, int dtype, const void* vel, void* state, void* U1, void* U2,
+// Fill the host-side item for one problem; returns its (tile, x) step count.
+long long batch_item_fill(void* item, const GridArgs& g, int dtype, const void* vel, void* state, void* U1, void* U2,
                     double dt, double xs, double zs, double r02) {
     BatchItem& it = *static_cast<BatchItem*>(item);
     const int tk = dtype == EGB_F64 ? 8 : 12;
@@ -612,9 +613,9 @@ int batch_item_fill(void* item, const GridArgs& g, int dtype, const void* vel, v
     TileArgs t;
     t.ntz = (g.nz + TZ - 1) / TZ;
     t.ntk = (g.nth + tk - 1) / tk;
-    t.kx = choose_kx(g, tk);
-    t.nxc = (g.nx + t.kx - 1) / t.kx;
-    t.nblocks = t.ntz * t.ntk * t.nxc;
+    t.kx = g.nx;
+    t.nxc = 1;
+    t.nblocks = 0;
     t.state_bytes = (unsigned)state_bytes_of(g, es);
     t.vel_bytes = (unsigned)(7ull * (unsigned long long)g.stride * es);
     it.t = t;
@@ -631,23 +632,13 @@ int batch_item_fill(void* item, const GridArgs& g, int dtype, const void* vel, v
         it.a[s].zs = zs;
         it.a[s].r02 = r02;
     }
-    return t.nblocks;
+    return (long long)t.ntz * t.ntk * g.nx;
 }
 
-hipError_t launch_stage_batched(const void* items, const int* first, int nprob, int total, int dtype, int stage,
-                                int grid, hipStream_t s) {
-    if (dtype == EGB_F64) return launch_batched_t<double, 8>(items, first, nprob, total, stage, grid, s);
-    return launch_batched_t<float, 12>(items, first, nprob, total, stage, grid, s);
-}
-
-int stage_block_threads(int dtype) { return dtype == EGB_F64 ? 64 * 8 : 64 * 12; }
-
-const void* stage_batched_kernel(int dtype, int stage) {
-    if (dtype == EGB_F64)
-        return stage == 0 ? (const void*)k_stage_batched<double, 0, 8>
-                          : stage == 1 ? (const void*)k_stage_batched<double, 1, 8> : (const void*)k_stage_batched<double, 2, 8>;
-    return stage == 0 ? (const void*)k_stage_batched<float, 0, 12>
-                      : stage == 1 ? (const void*)k_stage_batched<float, 1, 12> : (const void*)k_stage_batched<float, 2, 12>;
+hipError_t launch_stage_batched(const void* items, const long long* wfirst, int nprob, long long total, int dtype,
+                                int stage, int grid, hipStream_t s) {
+    if (dtype == EGB_F64) return launch_batched_t<double, 8>(items, wfirst, nprob, total, stage, grid, s);
+    return launch_batched_t<float, 12>(items, wfirst, nprob, total, stage, grid, s);
 }
 
 bool stage_fits_32bit(const GridArgs& g, int dtype) {
