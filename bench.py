@@ -49,16 +49,16 @@ def parse():
     return ap.parse_args()
 
 
-def batched_vs_sequential(nprob, nsteps):
-    """64 independent VTI problems with per-axis sizes uniform in 128..384:
-    one graph-captured persistent march of all of them against marching them
+def batched_vs_sequential(nprob, nsteps, lo=128, hi=384):
+    """`nprob` independent VTI problems with per-axis sizes uniform in lo..hi:
+    one graph-captured batched march of all of them against marching them
     one after another with the single-problem call (same GPU, same steps)."""
     import torch
 
     import paper_2006_11945_amd as egb
     import workloads as W
 
-    probs = W.batch_uneven(nprob=nprob, nsteps=nsteps)
+    probs = W.batch_uneven(nprob=nprob, nsteps=nsteps, lo=lo, hi=hi)
     solvers = []
     for p in probs:
         s = egb.Solver(p, "cuda:0")
@@ -85,7 +85,7 @@ def batched_vs_sequential(nprob, nsteps):
         s.step(nsteps)
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
-    return {"problems": nprob, "cells": cells, "rk3_steps": nsteps,
+    return {"problems": nprob, "sizes": [lo, hi], "cells": cells, "rk3_steps": nsteps,
             "batched_cell_updates_per_s": cells * nsteps / t_batch,
             "sequential_cell_updates_per_s": cells * nsteps / t_seq,
             "batched_over_sequential": t_seq / t_batch}
@@ -267,6 +267,8 @@ def main():
     torch.cuda.empty_cache()
     if args.batched_steps > 0:
         res["batched"] = batched_vs_sequential(args.batched_problems, args.batched_steps)
+        # many small problems: one problem alone cannot fill the chip
+        res["batched_small"] = batched_vs_sequential(256, 4 * args.batched_steps, lo=32, hi=96)
         torch.cuda.empty_cache()
     if args.adjoint_sources > 0:
         res["adjoint"] = adjoint_vs_forward(args.adjoint_sources, args.rk_steps, args.n)

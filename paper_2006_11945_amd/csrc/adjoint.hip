@@ -25,6 +25,15 @@ namespace egb {
 namespace {
 
 constexpr int NSLOT = 7;
+constexpr int NQ = 2 * 3 * NSLOT;  // packets per cell: plane x axis x slot
+
+// Packet layout: per (theta, x, 64-cell z strip) the NQ packets of the strip
+// are contiguous (NQ rows of 64), so a wave reads or writes whole 256-byte
+// rows that sit next to each other.
+__device__ __forceinline__ long long pk_idx(const GridArgs& g, int q, int k, int x, int z) {
+    const int ntz = (g.nz + 63) >> 6;
+    return ((((long long)k * g.nx + x) * ntz + (z >> 6)) * NQ + q) * 64 + (z & 63);
+}
 
 // value of a line at index idx with linear-extrapolation ghosts
 template <typename T>
@@ -112,7 +121,7 @@ __global__ __launch_bounds__(256) void k_adj_packets(AdjArgs a) {
     const bool ball = in_ball(g, ix, iz, a.xs, a.zs, a.r02);
     const R mu[2] = {ball ? (R)0 : lamR[c], ball ? (R)0 : (R)lamP[c]};
     if (mu[0] == (R)0 && mu[1] == (R)0) {
-        for (int q = 0; q < 2 * 3 * NSLOT; ++q) pk[q * S + c] = (R)0;
+        for (int q = 0; q < NQ; ++q) pk[pk_idx(g, q, k, ix, iz)] = (R)0;
         return;
     }
     const R* V = static_cast<const R*>(a.vel);
@@ -129,7 +138,7 @@ __global__ __launch_bounds__(256) void k_adj_packets(AdjArgs a) {
             stencil7<R>(phi, g, k, ix, iz, axis, u);
             const R W = weno_row<R, R>(u, minus, row);
             const R coef = (R)(-a.cbdt) * cvel[axis] * mu[0];
-            for (int j = 0; j < NSLOT; ++j) pk[((0 * 3 + axis) * NSLOT + j) * S + c] = coef * row[j];
+            for (int j = 0; j < NSLOT; ++j) pk[pk_idx(g, (0 * 3 + axis) * NSLOT + j, k, ix, iz)] = coef * row[j];
             Wsum += mu[0] * W;
         }
         {
@@ -137,7 +146,7 @@ __global__ __launch_bounds__(256) void k_adj_packets(AdjArgs a) {
             stencil7<double>(psi, g, k, ix, iz, axis, u);
             const R W = weno_row<double, R>(u, minus, row);
             const R coef = (R)(-a.cbdt) * cvel[axis] * mu[1];
-            for (int j = 0; j < NSLOT; ++j) pk[((1 * 3 + axis) * NSLOT + j) * S + c] = coef * row[j];
+            for (int j = 0; j < NSLOT; ++j) pk[pk_idx(g, (1 * 3 + axis) * NSLOT + j, k, ix, iz)] = coef * row[j];
             Wsum += mu[1] * W;
         }
         gv[axis * S + c] += (R)(-a.cbdt * inv[axis]) * Wsum;
@@ -147,15 +156,19 @@ __global__ __launch_bounds__(256) void k_adj_packets(AdjArgs a) {
 // Sum of the packets of plane f aimed at cell (k, ix, iz).
 template <typename R>
 __device__ __forceinline__ double gather_plane(const R* pk, const GridArgs& g, int f, int k, int ix, int iz) {
-    const long long S = g.stride, kb = (long long)k * g.nxz;
     double acc = 0.0;
     // x: source ix - j, slot j
     {
-        const R* P = pk + (long long)((f * 3 + 0) * NSLOT) * S;
-        for (int j = -3; j <= 3; ++j) {
+        const int q0 = (f * 3 + 0) * NSLOT + 3;
+        R v[7];
+#pragma unroll
+        for (int j = -3; j <= 3; ++j) {  // branch-free: clamped source, weight 0 outside
             const int xs = ix - j;
-            if (xs >= 0 && xs < g.nx) acc += (double)P[(j + 3) * S + kb + (long long)xs * g.nz + iz];
+            const R r = pk[pk_idx(g, q0 + j, k, min(max(xs, 0), g.nx - 1), iz)];
+            v[j + 3] = (xs >= 0 && xs < g.nx) ? r : (R)0;
         }
+#pragma unroll
+        for (int j = 0; j < 7; ++j) acc += (double)v[j];
         if (ix <= 1 || ix >= g.nx - 2) {
             for (int m = 1; m <= 3; ++m) {
                 const bool lo = ix <= 1;
@@ -163,19 +176,23 @@ __device__ __forceinline__ double gather_plane(const R* pk, const GridArgs& g, i
                 const int gpos = lo ? -m : g.nx - 1 + m;
                 for (int j = -3; j <= 3; ++j) {
                     const int xs = gpos - j;
-                    if (xs >= 0 && xs < g.nx) acc += w * (double)P[(j + 3) * S + kb + (long long)xs * g.nz + iz];
+                    if (xs >= 0 && xs < g.nx) acc += w * (double)pk[pk_idx(g, q0 + j, k, xs, iz)];
                 }
             }
         }
     }
     // z
     {
-        const R* P = pk + (long long)((f * 3 + 1) * NSLOT) * S;
-        const long long xb = kb + (long long)ix * g.nz;
+        const int q0 = (f * 3 + 1) * NSLOT + 3;
+        R v[7];
+#pragma unroll
         for (int j = -3; j <= 3; ++j) {
             const int zs = iz - j;
-            if (zs >= 0 && zs < g.nz) acc += (double)P[(j + 3) * S + xb + zs];
+            const R r = pk[pk_idx(g, q0 + j, k, ix, min(max(zs, 0), g.nz - 1))];
+            v[j + 3] = (zs >= 0 && zs < g.nz) ? r : (R)0;
         }
+#pragma unroll
+        for (int j = 0; j < 7; ++j) acc += (double)v[j];
         if (iz <= 1 || iz >= g.nz - 2) {
             for (int m = 1; m <= 3; ++m) {
                 const bool lo = iz <= 1;
@@ -183,21 +200,24 @@ __device__ __forceinline__ double gather_plane(const R* pk, const GridArgs& g, i
                 const int gpos = lo ? -m : g.nz - 1 + m;
                 for (int j = -3; j <= 3; ++j) {
                     const int zs = gpos - j;
-                    if (zs >= 0 && zs < g.nz) acc += w * (double)P[(j + 3) * S + xb + zs];
+                    if (zs >= 0 && zs < g.nz) acc += w * (double)pk[pk_idx(g, q0 + j, k, ix, zs)];
                 }
             }
         }
     }
     // theta (periodic)
     {
-        const R* P = pk + (long long)((f * 3 + 2) * NSLOT) * S;
-        const long long o = (long long)ix * g.nz + iz;
+        const int q0 = (f * 3 + 2) * NSLOT + 3;
+        R v[7];
+#pragma unroll
         for (int j = -3; j <= 3; ++j) {
             int ks = k - j;
             ks += ks < 0 ? g.nth : 0;
             ks -= ks >= g.nth ? g.nth : 0;
-            acc += (double)P[(j + 3) * S + (long long)ks * g.nxz + o];
+            v[j + 3] = pk[pk_idx(g, q0 + j, ks, ix, iz)];
         }
+#pragma unroll
+        for (int j = 0; j < 7; ++j) acc += (double)v[j];
     }
     return acc;
 }
@@ -501,7 +521,9 @@ hipError_t adj_stage_t(const AdjArgs& a, int stage, void* lam_in, void* lam_acc,
 
 }  // namespace
 
-size_t adjoint_packet_bytes(const egb_grid& g) { return (size_t)2 * 3 * NSLOT * plane_stride(g) * real_size(g); }
+size_t adjoint_packet_bytes(const egb_grid& g) {
+    return (size_t)NQ * 64 * (size_t)((g.nz + 63) / 64) * (size_t)g.nx * (size_t)g.nth * real_size(g);
+}
 
 hipError_t launch_adjoint_stage(const GridArgs& g, int dtype, int stage, const void* vel, const void* Uin,
                                 const void* lam_out, void* lam_in, void* lam_acc, void* packets, void* gvel,
