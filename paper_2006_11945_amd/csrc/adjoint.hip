@@ -10,254 +10,510 @@
 //   lambda_Uin  = cb mu + cb dt (dL/dUin)^T mu
 //   g_V        += cb dt (dL/dV)^T mu,  dL/dV_d = -W_d / Delta_d,
 // where W_d is the upwind WENO5 derivative (upwind side frozen).  The
-// transposed stencil is applied in two passes: every cell writes its seven
-// Jacobian coefficients per plane and axis scaled by -cb dt c_d mu ("packets",
-// slot j for the target at offset j), then every cell gathers the packets aimed
-// at it; packets aimed at extrapolated ghosts go to the two cells the ghost is
-// extrapolated from (weights m + 1 and -m), theta wraps.
+// transposed stencil (dL/dUin)^T is applied by the fused stage kernel below:
+// every source cell forms its Jacobian rows and the rows are summed per
+// target, x through a register queue and z, theta through LDS; slots aimed
+// at extrapolated ghosts go to the two cells the ghost is extrapolated from
+// (weights m + 1 and -m), theta wraps.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "egb_device.h"
 #include "egb_internal.h"
+#include "stage_common.h"
 
 namespace egb {
 namespace {
 
-constexpr int NSLOT = 7;
-constexpr int NQ = 2 * 3 * NSLOT;  // packets per cell: plane x axis x slot
+constexpr int NSLOT = 7;  // stencil positions -3..3
 
-// Packet layout: per (theta, x, 64-cell z strip) the NQ packets of the strip
-// are contiguous (NQ rows of 64), so a wave reads or writes whole 256-byte
-// rows that sit next to each other.
-__device__ __forceinline__ long long pk_idx(const GridArgs& g, int q, int k, int x, int z) {
-    const int ntz = (g.nz + 63) >> 6;
-    return ((((long long)k * g.nx + x) * ntz + (z >> 6)) * NQ + q) * 64 + (z & 63);
-}
+// ------------------------------------------------------------ fused stage
+// One adjoint stage in one pass.  A block owns a (z, theta) tile of
+// TZ x TK cells and an x range [x0, x1) of targets; it walks the source
+// slices x0 - 3 .. x1 + 2 (the three extra on each side contribute through
+// their x rows only).  Per source slice:
+//  * x rows of the tile's own cells go into a register queue of seven
+//    accumulators per plane (targets xs - 3 .. xs + 3); target xs - 3 is
+//    complete afterwards and is written out;
+//  * z and theta rows of the own cells, plus the theta rows of the three
+//    theta rows on either side of the tile and the z rows of the three z
+//    columns on either side (the only halo rows that reach into the tile),
+//    are written to LDS as seven slots per source ("slot j" = coefficient of
+//    the target at offset j - 3), then every own cell sums the seven slots
+//    aimed at it per axis;
+//  * rows are formed in upwind order (mirrored reads for a negative
+//    velocity component) and folded at x and z ends: a slot aimed at the
+//    ghost m cells outside goes to the edge cell with weight m + 1 and to
+//    its neighbour with weight -m; theta wraps.
+// The stencil values of the slice sit in LDS with a 6-cell halo (the halo
+// sources' own stencils); the own column's x stencil is a register queue.
+template <typename R, int TK>
+struct AdjSmem {
+    using W = typename LdsWord<R>::T;
+    static constexpr int VZ = TZ + 12;                             // z positions -6 .. TZ + 5
+    static constexpr int PLANE = ((TK + 12) * VZ + 63) / 64 * 64;  // words per value plane
+    static constexpr int NW = 1 + LdsWord<R>::PSI_WORDS;           // phi1, psi
+    static constexpr int PB = PLANE * (int)sizeof(W);              // bytes per value plane
+    static constexpr int CZW = TZ + 6;                             // z sources -3 .. TZ + 2
+    static constexpr int ZPL = TK * CZW;                           // z slots per (plane, slot)
+    static constexpr int TPL = (TK + 6) * TZ;                      // theta sources -3 .. TK + 2
+    W w[NW * PLANE];
+    R cz[2 * NSLOT * ZPL];
+    R ct[2 * NSLOT * TPL];
+};
 
-// value of a line at index idx with linear-extrapolation ghosts
-template <typename T>
-__device__ __forceinline__ T line_at(const T* base, long long st, int n, int idx) {
-    if (idx < 0) return (T)(1 - idx) * base[0] + (T)idx * base[st];
-    if (idx > n - 1) {
-        const int e = idx - (n - 1);
-        return (T)(e + 1) * base[(long long)(n - 1) * st] - (T)e * base[(long long)(n - 2) * st];
-    }
-    return base[(long long)idx * st];
-}
+struct AdjStageArgs {
+    GridArgs g;
+    const void* vel;     // vel3d
+    const void* Uin;     // stage input state (phi1 and psi are read)
+    const void* lam;     // lambda of the stage output
+    const void* acc_in;  // stages 0, 1: accumulated lambda of U0 so far (may alias acc_out)
+    void* acc_out;
+    void* lam_in;        // stages 1, 2: lambda of the stage input
+    void* gvel;          // [3][stride] of R, accumulated
+    double dt, xs, zs, r02;
+    unsigned state_bytes, vel_bytes, gvel_bytes;
+    int ntz, ntk;
+};
 
-// the seven stencil values along axis (0 x, 1 z, 2 theta) at offsets -3..3
-template <typename T>
-__device__ __forceinline__ void stencil7(const T* P, const GridArgs& g, int k, int ix, int iz, int axis, T (&u)[7]) {
-    const long long kb = (long long)k * g.nxz;
-    if (axis == 0) {
-        for (int m = 0; m < 7; ++m) u[m] = line_at(P + kb + iz, g.nz, g.nx, ix + m - 3);
-    } else if (axis == 1) {
-        for (int m = 0; m < 7; ++m) u[m] = line_at(P + kb + (long long)ix * g.nz, 1, g.nz, iz + m - 3);
-    } else {
-        for (int m = 0; m < 7; ++m) {
-            int kk = k + m - 3;
-            kk += kk < 0 ? g.nth : 0;
-            kk -= kk >= g.nth ? g.nth : 0;
-            u[m] = P[(long long)kk * g.nxz + (long long)ix * g.nz + iz];
-        }
-    }
-}
-
-// Upwind WENO5 derivative W and its Jacobian row dW/du[m] (m = 0..6 at
-// offsets -3..3); differences formed in T, the derivative in R.
-template <typename T, typename R>
-__device__ __forceinline__ R weno_row(const T (&u)[7], bool minus, R (&row)[7]) {
-    R d[6];
-    for (int m = 0; m < 6; ++m) d[m] = (R)(u[m + 1] - u[m]);
+// Gradient of the upwind WENO5 value with respect to the six upwind-ordered
+// values u0..u5 (differences formed in T); returns the value.
+template <typename R, typename T>
+__device__ __forceinline__ R wgrad_up(T u0, T u1, T u2, T u3, T u4, T u5, R (&du)[6]) {
     R gr[5];
-    if (minus) {
-        const R W = weno5_grad<R>(d[0], d[1], d[2], d[3], d[4], gr);
-        row[0] = -gr[0];
-        row[1] = gr[0] - gr[1];
-        row[2] = gr[1] - gr[2];
-        row[3] = gr[2] - gr[3];
-        row[4] = gr[3] - gr[4];
-        row[5] = gr[4];
-        row[6] = (R)0;
-        return W;
-    }
-    const R W = weno5_grad<R>(d[5], d[4], d[3], d[2], d[1], gr);
-    row[6] = gr[0];
-    row[5] = gr[1] - gr[0];
-    row[4] = gr[2] - gr[1];
-    row[3] = gr[3] - gr[2];
-    row[2] = gr[4] - gr[3];
-    row[1] = -gr[4];
-    row[0] = (R)0;
+    const R W = weno5_grad<R>((R)(u1 - u0), (R)(u2 - u1), (R)(u3 - u2), (R)(u4 - u3), (R)(u5 - u4), gr);
+    du[0] = -gr[0];
+    du[1] = gr[0] - gr[1];
+    du[2] = gr[1] - gr[2];
+    du[3] = gr[2] - gr[3];
+    du[4] = gr[3] - gr[4];
+    du[5] = gr[4];
     return W;
 }
 
-struct AdjArgs {
-    GridArgs g;
-    const void* vel;    // vel3d
-    const void* Uin;    // stage input state
-    const void* lam;    // lambda of the stage output (state layout)
-    void* pk;           // packets [2][3][7][stride] in R
-    void* gvel;         // [3][stride] in R, accumulated
-    double cbdt;        // cb * dt
-    double xs, zs, r02;
-};
-
-__device__ __forceinline__ bool in_ball(const GridArgs& g, int ix, int iz, double xs, double zs, double r02) {
-    const double ddx = g.x0 + (ix + 0.5) * g.dx - xs, ddz = g.z0 + (iz + 0.5) * g.dz - zs;
-    return ddx * ddx + ddz * ddz <= r02;
+// Slots (target offset j - 3) from an upwind-ordered row scaled by c: value m
+// sits at offset (m - 3) for a non-negative velocity component, 3 - m else.
+template <typename R, typename C>
+__device__ __forceinline__ void to_slots(const R (&du)[6], bool plus, C c, C (&d)[NSLOT]) {
+#pragma unroll
+    for (int j = 0; j < NSLOT; ++j) {
+        const R v = plus ? (j < 6 ? du[j] : (R)0) : (j > 0 ? du[6 - j] : (R)0);
+        d[j] = c * (C)v;
+    }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_adj_packets(AdjArgs a) {
+// Fold the slots of a source at index s of a line of n cells whose targets
+// leave the line: the ghost m cells outside goes to the edge cell (m + 1)
+// and its neighbour (-m).
+template <typename C>
+__device__ __forceinline__ void fold_ends(C (&d)[NSLOT], int s, int n) {
+    const bool lo = s < 3;
+    const int e0 = lo ? 0 : n - 1, e1 = lo ? 1 : n - 2;
+    C f0 = (C)0, f1 = (C)0;
+#pragma unroll
+    for (int j = 0; j < NSLOT; ++j) {
+        const int t = s + j - 3;
+        const int m = t < 0 ? -t : (t > n - 1 ? t - (n - 1) : 0);
+        if (m > 0) {
+            f0 += (C)(m + 1) * d[j];
+            f1 -= (C)m * d[j];
+            d[j] = (C)0;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NSLOT; ++j) {
+        const int t = s + j - 3;
+        d[j] += t == e0 ? f0 : (t == e1 ? f1 : (C)0);
+    }
+}
+
+template <typename R, int STAGE, int TK>
+__device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0, int x1, AdjSmem<R, TK>& sm) {
+    using S = AdjSmem<R, TK>;
+    using Wd = typename S::W;
+    constexpr int WS = (int)sizeof(Wd);
+    constexpr int NT = TZ * TK;
+    constexpr int NV = (TK + 12) * S::VZ;       // value cells per slice
+    constexpr int NVI = (NV + NT - 1) / NT;     // value cells per thread
+    constexpr int NH = 6 * TZ + 6 * TK;         // halo sources per slice
+    constexpr int NHI = (NH + NT - 1) / NT;     // halo sources per thread
+    constexpr unsigned ES = sizeof(R);
+    constexpr double ca = RK<STAGE>::ca, cb = RK<STAGE>::cb;
+    static_assert(S::PB * (S::NW - 1) < 65536, "plane offsets fit the LDS immediate");
+
     const GridArgs& g = a.g;
-    const int iz = blockIdx.x * 64 + threadIdx.x, ix = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
-    if (iz >= g.nz || ix >= g.nx) return;
-    const long long S = g.stride, c = (long long)k * g.nxz + (long long)ix * g.nz + iz;
-    R* pk = static_cast<R*>(a.pk);
-    const R* lamR = static_cast<const R*>(a.lam);
-    const double* lamP = reinterpret_cast<const double*>(lamR + 5 * S);
-    const bool ball = in_ball(g, ix, iz, a.xs, a.zs, a.r02);
-    const R mu[2] = {ball ? (R)0 : lamR[c], ball ? (R)0 : (R)lamP[c]};
-    if (mu[0] == (R)0 && mu[1] == (R)0) {
-        for (int q = 0; q < NQ; ++q) pk[pk_idx(g, q, k, ix, iz)] = (R)0;
-        return;
-    }
-    const R* V = static_cast<const R*>(a.vel);
-    const double inv[3] = {1.0 / g.dx, 1.0 / g.dz, 1.0 / g.dth};
-    const R cvel[3] = {V[EGB_VX * S + c] * (R)inv[0], V[EGB_VZ * S + c] * (R)inv[1], V[EGB_VT * S + c] * (R)inv[2]};
-    const R* phi = static_cast<const R*>(a.Uin);
-    const double* psi = reinterpret_cast<const double*>(phi + 5 * S);
-    R* gv = static_cast<R*>(a.gvel);
-    for (int axis = 0; axis < 3; ++axis) {
-        const bool minus = cvel[axis] >= (R)0;
-        R row[7], Wsum = (R)0;
-        {
-            R u[7];
-            stencil7<R>(phi, g, k, ix, iz, axis, u);
-            const R W = weno_row<R, R>(u, minus, row);
-            const R coef = (R)(-a.cbdt) * cvel[axis] * mu[0];
-            for (int j = 0; j < NSLOT; ++j) pk[pk_idx(g, (0 * 3 + axis) * NSLOT + j, k, ix, iz)] = coef * row[j];
-            Wsum += mu[0] * W;
-        }
-        {
-            double u[7];
-            stencil7<double>(psi, g, k, ix, iz, axis, u);
-            const R W = weno_row<double, R>(u, minus, row);
-            const R coef = (R)(-a.cbdt) * cvel[axis] * mu[1];
-            for (int j = 0; j < NSLOT; ++j) pk[pk_idx(g, (1 * 3 + axis) * NSLOT + j, k, ix, iz)] = coef * row[j];
-            Wsum += mu[1] * W;
-        }
-        gv[axis * S + c] += (R)(-a.cbdt * inv[axis]) * Wsum;
-    }
-}
+    const int tzi = tile % a.ntz, tki = tile / a.ntz;
+    const int tz = threadIdx.x, tk = threadIdx.y, tid = tk * TZ + tz;
+    const int iz = tzi * TZ + tz;
+    const int kraw = tki * TK + tk;
+    const int k = kraw < g.nth ? kraw : kraw - g.nth;  // ragged theta tiles wrap
+    const bool zin = iz < g.nz;
+    const bool valid = zin && kraw < g.nth;  // own cell written by this tile
+    const int izc = min(iz, g.nz - 1);
+    const unsigned nxz = (unsigned)g.nxz, SP = (unsigned)g.stride * ES, PSI = 5u * SP;
+    const unsigned kb = (unsigned)k * nxz;
+    const auto rUi = make_rsrc(a.Uin, a.state_bytes);
+    const auto rL = make_rsrc(a.lam, a.state_bytes);
+    const auto rV = make_rsrc(a.vel, a.vel_bytes);
+    const auto rG = make_rsrc(a.gvel, a.gvel_bytes);
+    const double cbdt = cb * a.dt;
+    const double kx = cbdt / g.dx, kz = cbdt / g.dz, kt = cbdt / g.dth;
+    auto wrapk = [&](int kk) { return ((kk % g.nth) + g.nth) % g.nth; };
+    auto in_ball = [&](int ix, int izz) {
+        const double xr = g.x0 + (ix + 0.5) * g.dx - a.xs, zr = g.z0 + (izz + 0.5) * g.dz - a.zs;
+        return xr * xr + zr * zr <= a.r02;
+    };
 
-// Sum of the packets of plane f aimed at cell (k, ix, iz).
-template <typename R>
-__device__ __forceinline__ double gather_plane(const R* pk, const GridArgs& g, int f, int k, int ix, int iz) {
-    double acc = 0.0;
-    // x: source ix - j, slot j
+    // value cell i of the LDS slice: base (theta row, clamped z) and the
+    // ghost distance (0 inside, +-m within 3 of an end, 100 beyond: never
+    // read by a source inside the grid)
+    auto vcell = [&](int i, unsigned& vb, int& vm) {
+        const int tl = i / S::VZ - 6, zl = i % S::VZ - 6;
+        const int z = tzi * TZ + zl;
+        vb = (unsigned)wrapk(tki * TK + tl) * nxz + (unsigned)min(max(z, 0), g.nz - 1);
+        vm = z < 0 ? (z >= -3 ? z : 100) : (z >= g.nz ? (z <= g.nz + 2 ? z - (g.nz - 1) : 100) : 0);
+    };
+    const bool z_end = tzi == 0 || (tzi + 1) * TZ + 6 > g.nz;  // block-uniform: some value cell is a ghost
+    // halo source h: theta rows (h < 6 TZ) then z columns; LDS row, z position,
+    // whether it is a cell of the grid, and its (clamped) cell index
+    auto hcell = [&](int h, int& tl, int& zl, bool& real, unsigned& c) {
+        tl = 0;
+        zl = 0;
+        if (h < 6 * TZ) {
+            const int rr = h / TZ;
+            zl = h % TZ;
+            tl = rr < 3 ? rr - 3 : TK + rr - 3;
+        } else if (h < NH) {
+            const int cc = (h - 6 * TZ) / TK;
+            tl = (h - 6 * TZ) % TK;
+            zl = cc < 3 ? cc - 3 : TZ + cc - 3;
+        }
+        const int z = tzi * TZ + zl;
+        real = h < NH && z >= 0 && z < g.nz;
+        c = (unsigned)wrapk(tki * TK + tl) * nxz + (unsigned)min(max(z, 0), g.nz - 1);
+    };
+
+    // own column's x stencil: values at xs - 3 .. xs + 3 (x ghosts continue
+    // the line of the two entries next to them)
+    R qv[7];
+    double qp[7];
+    const int xa = x0 - 3, xb = x1 + 3;  // source slices
     {
-        const int q0 = (f * 3 + 0) * NSLOT + 3;
-        R v[7];
+        // eight entries (x0 - 6 .. x0 + 1): the line through x = 0, 1 reaches
+        // every left ghost among the first seven
+        R tv[8];
+        double tp[8];
 #pragma unroll
-        for (int j = -3; j <= 3; ++j) {  // branch-free: clamped source, weight 0 outside
-            const int xs = ix - j;
-            const R r = pk[pk_idx(g, q0 + j, k, min(max(xs, 0), g.nx - 1), iz)];
-            v[j + 3] = (xs >= 0 && xs < g.nx) ? r : (R)0;
+        for (int j = 0; j < 8; ++j) {
+            const unsigned o = kb + (unsigned)(min(max(xa - 3 + j, 0), g.nx - 1) * g.nz + izc);
+            tv[j] = bload<R>(rUi, o * ES, 0);
+            tp[j] = bload<double>(rUi, o * 8u, PSI);
         }
 #pragma unroll
-        for (int j = 0; j < 7; ++j) acc += (double)v[j];
-        if (ix <= 1 || ix >= g.nx - 2) {
-            for (int m = 1; m <= 3; ++m) {
-                const bool lo = ix <= 1;
-                const double w = (ix == 0 || ix == g.nx - 1) ? (double)(m + 1) : (double)(-m);
-                const int gpos = lo ? -m : g.nx - 1 + m;
-                for (int j = -3; j <= 3; ++j) {
-                    const int xs = gpos - j;
-                    if (xs >= 0 && xs < g.nx) acc += w * (double)pk[pk_idx(g, q0 + j, k, xs, iz)];
+        for (int j = 5; j >= 0; --j)
+            if (xa - 3 + j < 0) {
+                tv[j] = (R)2 * tv[j + 1] - tv[j + 2];
+                tp[j] = 2.0 * tp[j + 1] - tp[j + 2];
+            }
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            qv[j] = tv[j];
+            qp[j] = tp[j];
+        }
+    }
+    // accumulators of targets xs - 3 .. xs + 3 (phi1, psi)
+    R a0[7], a1[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        a0[j] = (R)0;
+        a1[j] = (R)0;
+    }
+    // mu (lambda of the output, 0 in the source ball and outside the grid)
+    // and V of the own cell, fetched one slice ahead
+    auto own_mu_v = [&](int x, R& m0, double& m1, R& vx, R& vz, R& vt) {
+        const int xc = min(max(x, 0), g.nx - 1);
+        const unsigned c = kb + (unsigned)(xc * g.nz + izc);
+        const R l0 = bload<R>(rL, c * ES, 0);
+        const double l1 = bload<double>(rL, c * 8u, PSI);
+        vx = bload<R>(rV, c * ES, EGB_VX * SP);
+        vz = bload<R>(rV, c * ES, EGB_VZ * SP);
+        vt = bload<R>(rV, c * ES, EGB_VT * SP);
+        const bool live = zin && !in_ball(xc, izc);
+        m0 = live ? l0 : (R)0;
+        m1 = live ? l1 : 0.0;
+    };
+    R cm0, cvx, cvz, cvt;
+    double cm1;
+    own_mu_v(xa, cm0, cm1, cvx, cvz, cvt);
+
+    const int me = (tk + 6) * S::VZ + tz + 6;  // own cell in the value slice
+
+    for (int xs = xa; xs < xb; ++xs) {
+        const bool src = xs >= 0 && xs < g.nx;  // block-uniform
+        const bool core = xs >= x0 && xs < x1;
+        // prefetch: queue entry xs + 4, own mu and V of slice xs + 1
+        R qn;
+        double qpn;
+        {
+            const unsigned o = kb + (unsigned)(min(max(xs + 4, 0), g.nx - 1) * g.nz + izc);
+            qn = bload<R>(rUi, o * ES, 0);
+            qpn = bload<double>(rUi, o * 8u, PSI);
+        }
+        R nm0, nvx, nvz, nvt;
+        double nm1;
+        own_mu_v(xs + 1, nm0, nm1, nvx, nvz, nvt);
+        // slice loads of a core step: value cells, halo sources' mu and V, own gvel
+        R vv[NVI], vv1[NVI];
+        double vp[NVI], vp1[NVI];
+        R hm0[NHI], hvel[NHI];
+        double hm1[NHI];
+        const unsigned xo = (unsigned)(min(max(xs, 0), g.nx - 1) * g.nz);
+        const unsigned cR = (kb + xo + (unsigned)izc) * ES;
+        if (core) {
+#pragma unroll
+            for (int r = 0; r < NVI; ++r) {
+                unsigned vb;
+                int vm;
+                vcell(tid + r * NT, vb, vm);
+                const unsigned o = vb + xo;
+                vv[r] = bload<R>(rUi, o * ES, 0);
+                vp[r] = bload<double>(rUi, o * 8u, PSI);
+                if (z_end) {  // second point of a ghost: the cell next to the edge
+                    const unsigned o1 = vm < 0 ? o + 1u : (vm > 0 && vm < 100 ? o - 1u : o);
+                    vv1[r] = bload<R>(rUi, o1 * ES, 0);
+                    vp1[r] = bload<double>(rUi, o1 * 8u, PSI);
                 }
             }
-        }
-    }
-    // z
-    {
-        const int q0 = (f * 3 + 1) * NSLOT + 3;
-        R v[7];
 #pragma unroll
-        for (int j = -3; j <= 3; ++j) {
-            const int zs = iz - j;
-            const R r = pk[pk_idx(g, q0 + j, k, ix, min(max(zs, 0), g.nz - 1))];
-            v[j + 3] = (zs >= 0 && zs < g.nz) ? r : (R)0;
-        }
-#pragma unroll
-        for (int j = 0; j < 7; ++j) acc += (double)v[j];
-        if (iz <= 1 || iz >= g.nz - 2) {
-            for (int m = 1; m <= 3; ++m) {
-                const bool lo = iz <= 1;
-                const double w = (iz == 0 || iz == g.nz - 1) ? (double)(m + 1) : (double)(-m);
-                const int gpos = lo ? -m : g.nz - 1 + m;
-                for (int j = -3; j <= 3; ++j) {
-                    const int zs = gpos - j;
-                    if (zs >= 0 && zs < g.nz) acc += w * (double)pk[pk_idx(g, q0 + j, k, ix, zs)];
-                }
+            for (int r = 0; r < NHI; ++r) {
+                int tl, zl;
+                bool real;
+                unsigned hc;
+                hcell(tid + r * NT, tl, zl, real, hc);
+                const unsigned c = (hc + xo) * ES, c8 = (hc + xo) * 8u;
+                const R l0 = bload<R>(rL, c, 0);
+                const double l1 = bload<double>(rL, c8, PSI);
+                hvel[r] = bload<R>(rV, c, (tid + r * NT < 6 * TZ ? EGB_VT : EGB_VZ) * SP);
+                const bool live = real && !in_ball(xs, tzi * TZ + zl);
+                hm0[r] = live ? l0 : (R)0;
+                hm1[r] = live ? l1 : 0.0;
             }
         }
-    }
-    // theta (periodic)
-    {
-        const int q0 = (f * 3 + 2) * NSLOT + 3;
-        R v[7];
+        R gsx = (R)0;  // this step's x term of gvel
+        // x rows of the own column
+        if (src && __any(cm0 != (R)0 || cm1 != 0.0)) {
+            const bool plus = cvx >= (R)0;
+            R du[6];
+            R d0[NSLOT], d1[NSLOT];
+            auto u = [&](const auto& q, int m) { return plus ? q[m] : q[6 - m]; };
+            const R W0 = wgrad_up<R>(u(qv, 0), u(qv, 1), u(qv, 2), qv[3], u(qv, 4), u(qv, 5), du);
+            const R c0 = (R)(-kx) * fabs(cvx) * cm0;
+            to_slots(du, plus, c0, d0);
+            const R W1 = wgrad_up<R>(u(qp, 0), u(qp, 1), u(qp, 2), qp[3], u(qp, 4), u(qp, 5), du);
+            const R c1 = (R)(-kx * (double)fabs(cvx) * cm1);
+            to_slots(du, plus, c1, d1);
+            if (xs < 3 || xs > g.nx - 4) {
+                fold_ends(d0, xs, g.nx);
+                fold_ends(d1, xs, g.nx);
+            }
 #pragma unroll
-        for (int j = -3; j <= 3; ++j) {
-            int ks = k - j;
-            ks += ks < 0 ? g.nth : 0;
-            ks -= ks >= g.nth ? g.nth : 0;
-            v[j + 3] = pk[pk_idx(g, q0 + j, ks, ix, iz)];
+            for (int j = 0; j < NSLOT; ++j) {
+                a0[j] += d0[j];
+                a1[j] += d1[j];
+            }
+            // d(-cb dt V_x D_x U / dx)/dV_x with D_x U = sign * W_up / dx
+            gsx = (R)(plus ? -kx : kx) * (cm0 * W0 + (R)cm1 * W1);
         }
+        if (core) {
+            // value slice into LDS
 #pragma unroll
-        for (int j = 0; j < 7; ++j) acc += (double)v[j];
+            for (int r = 0; r < NVI; ++r) {
+                const int i = tid + r * NT;
+                if (i < NV) {
+                    R v0 = vv[r];
+                    double v1 = vp[r];
+                    unsigned vb;
+                    int vm;
+                    vcell(i, vb, vm);
+                    if (z_end && vm != 0) {
+                        const int m = vm < 0 ? -vm : vm;
+                        v0 = m < 100 ? (R)(m + 1) * vv[r] - (R)m * vv1[r] : (R)0;
+                        v1 = m < 100 ? (double)(m + 1) * vp[r] - (double)m * vp1[r] : 0.0;
+                    }
+                    sm.w[i] = __builtin_bit_cast(Wd, v0);
+                    const unsigned long long b = __builtin_bit_cast(unsigned long long, v1);
+                    if constexpr (sizeof(R) == 4) {
+                        sm.w[i + S::PLANE] = (unsigned)b;
+                        sm.w[i + 2 * S::PLANE] = (unsigned)(b >> 32);
+                    } else {
+                        sm.w[i + S::PLANE] = b;
+                    }
+                }
+            }
+            __syncthreads();
+            // z and theta rows of a source at LDS (tl, zl): slots scaled by
+            // -cb dt |V| mu / h, stored at the source position
+            auto row = [&](int tl, int zl, bool zaxis, R vel, R m0, double m1, int zg, R& Wsum) {
+                const int base = ((tl + 6) * S::VZ + zl + 6) * WS;
+                const bool plus = vel >= (R)0;
+                const int step = (zaxis ? WS : S::VZ * WS) * (plus ? 1 : -1);
+                const int b0 = base - 3 * step, b1 = base - 2 * step, b2 = base - step;
+                const int b4 = base + step, b5 = base + 2 * step;
+                R du[6];
+                R d0[NSLOT];
+                R d1[NSLOT];
+                const R W0 = wgrad_up<R>(lds_r<R>(sm, b0, 0), lds_r<R>(sm, b1, 0), lds_r<R>(sm, b2, 0),
+                                         lds_r<R>(sm, base, 0), lds_r<R>(sm, b4, 0), lds_r<R>(sm, b5, 0), du);
+                const double kk = zaxis ? kz : kt;
+                const R c0 = (R)(-kk) * fabs(vel) * m0;
+                to_slots(du, plus, c0, d0);
+                const R W1 = wgrad_up<R>(lds_psi<1>(sm, b0), lds_psi<1>(sm, b1), lds_psi<1>(sm, b2),
+                                         lds_psi<1>(sm, base), lds_psi<1>(sm, b4), lds_psi<1>(sm, b5), du);
+                const R c1 = (R)(-kk * (double)fabs(vel) * m1);
+                to_slots(du, plus, c1, d1);
+                if (zaxis && (zg < 3 || zg > g.nz - 4)) {
+                    fold_ends(d0, zg, g.nz);
+                    fold_ends(d1, zg, g.nz);
+                }
+                R* dst0;
+                R* dst1;
+                int stride;
+                if (zaxis) {
+                    dst0 = sm.cz + tl * S::CZW + zl + 3;
+                    dst1 = dst0 + NSLOT * S::ZPL;
+                    stride = S::ZPL;
+                } else {
+                    dst0 = sm.ct + (tl + 3) * TZ + zl;
+                    dst1 = dst0 + NSLOT * S::TPL;
+                    stride = S::TPL;
+                }
+#pragma unroll
+                for (int j = 0; j < NSLOT; ++j) {
+                    dst0[j * stride] = d0[j];
+                    dst1[j * stride] = d1[j];
+                }
+                Wsum = (plus ? (R)1 : (R)-1) * (m0 * W0 + (R)m1 * W1);
+            };
+            auto zero_row = [&](int tl, int zl, bool zaxis) {
+                R* dst0 = zaxis ? sm.cz + tl * S::CZW + zl + 3 : sm.ct + (tl + 3) * TZ + zl;
+                const int stride = zaxis ? S::ZPL : S::TPL;
+#pragma unroll
+                for (int j = 0; j < 2 * NSLOT; ++j) dst0[j * stride] = (R)0;
+            };
+            const bool live = cm0 != (R)0 || cm1 != 0.0;
+            R Wz = (R)0, Wt = (R)0;
+            if (__any(live)) {
+                row(tk, tz, true, cvz, cm0, cm1, izc, Wz);
+                row(tk, tz, false, cvt, cm0, cm1, izc, Wt);
+            } else {
+                zero_row(tk, tz, true);
+                zero_row(tk, tz, false);
+            }
+#pragma unroll
+            for (int r = 0; r < NHI; ++r) {
+                const int h = tid + r * NT;
+                if (h < NH) {
+                    int tl, zl;
+                    bool real;
+                    unsigned hc;
+                    hcell(h, tl, zl, real, hc);
+                    const bool zaxis = h >= 6 * TZ;
+                    R wh;  // a halo source's V term belongs to another tile
+                    if (__any(hm0[r] != (R)0 || hm1[r] != 0.0))
+                        row(tl, zl, zaxis, hvel[r], hm0[r], hm1[r], tzi * TZ + zl, wh);
+                    else zero_row(tl, zl, zaxis);
+                }
+            }
+            if (valid) {
+                const R gv0 = bload<R>(rG, cR, 0);
+                const R gv1 = bload<R>(rG, cR, SP);
+                const R gv2 = bload<R>(rG, cR, 2u * SP);
+                bstore(gv0 + gsx, rG, cR, 0);
+                bstore(gv1 + (R)(-kz) * Wz, rG, cR, SP);
+                bstore(gv2 + (R)(-kt) * Wt, rG, cR, 2u * SP);
+            }
+            __syncthreads();
+            // sum the slots aimed at the own cell
+            double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+            for (int j = 0; j < NSLOT; ++j) {
+                const int zsrc = tz - (j - 3), tsrc = tk - (j - 3);
+                t0 += (double)sm.cz[j * S::ZPL + tk * S::CZW + zsrc + 3] +
+                      (double)sm.ct[j * S::TPL + (tsrc + 3) * TZ + tz];
+                t1 += (double)sm.cz[(NSLOT + j) * S::ZPL + tk * S::CZW + zsrc + 3] +
+                      (double)sm.ct[(NSLOT + j) * S::TPL + (tsrc + 3) * TZ + tz];
+            }
+            a0[3] += (R)(t0 + cb * (double)cm0);
+            a1[3] += (R)(t1 + cb * cm1);
+        }
+        // target xs - 3 is complete
+        const int xt = xs - 3;
+        if (valid && xt >= x0 && xt < x1) {
+            const unsigned c = kb + (unsigned)(xt * g.nz + iz);
+            const R l0 = bload<R>(rL, c * ES, 0);
+            const double l1 = bload<double>(rL, c * 8u, PSI);
+            const bool ball = in_ball(xt, iz);
+            const R add0 = ball ? l0 : (R)ca * l0;
+            const double add1 = ball ? l1 : ca * l1;
+            const auto rAo = make_rsrc(a.acc_out, a.state_bytes);
+            if constexpr (STAGE == 2) {
+                bstore(add0, rAo, c * ES, 0);
+                bstore(add1, rAo, c * 8u, PSI);
+            } else {
+                const auto rAi = make_rsrc(a.acc_in, a.state_bytes);
+                R o0 = bload<R>(rAi, c * ES, 0) + add0;
+                double o1 = bload<double>(rAi, c * 8u, PSI) + add1;
+                if constexpr (STAGE == 0) {
+                    o0 += a0[0];
+                    o1 += (double)a1[0];
+                }
+                bstore(o0, rAo, c * ES, 0);
+                bstore(o1, rAo, c * 8u, PSI);
+            }
+            if constexpr (STAGE != 0) {
+                const auto rLi = make_rsrc(a.lam_in, a.state_bytes);
+                bstore(a0[0], rLi, c * ES, 0);
+                bstore((double)a1[0], rLi, c * 8u, PSI);
+            }
+        }
+        // shift
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            qv[j] = qv[j + 1];
+            qp[j] = qp[j + 1];
+            a0[j] = a0[j + 1];
+            a1[j] = a1[j + 1];
+        }
+        const bool xin = xs + 4 < g.nx;
+        qv[6] = xin ? qn : (R)2 * qv[5] - qv[4];
+        qp[6] = xin ? qpn : 2.0 * qp[5] - qp[4];
+        a0[6] = (R)0;
+        a1[6] = (R)0;
+        cm0 = nm0;
+        cm1 = nm1;
+        cvx = nvx;
+        cvz = nvz;
+        cvt = nvt;
     }
-    return acc;
 }
 
-// STAGE 2: lam_acc = ca mu + [ball] lam (may alias lam), lam_in = cb mu + T^T mu
-// STAGE 1: lam_acc += ca mu + [ball] lam,               lam_in = cb mu + T^T mu
-// STAGE 0: lam_acc += [ball] lam + cb mu + T^T mu       (Uin is U0)
-template <typename R, int STAGE>
-__global__ __launch_bounds__(256) void k_adj_gather(AdjArgs a, void* lam_in, void* lam_acc, double ca, double cb) {
-    const GridArgs& g = a.g;
-    const int iz = blockIdx.x * 64 + threadIdx.x, ix = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
-    if (iz >= g.nz || ix >= g.nx) return;
-    const long long S = g.stride, c = (long long)k * g.nxz + (long long)ix * g.nz + iz;
-    const R* lamR = static_cast<const R*>(a.lam);
-    const double* lamP = reinterpret_cast<const double*>(lamR + 5 * S);
-    const bool ball = in_ball(g, ix, iz, a.xs, a.zs, a.r02);
-    const double lo[2] = {(double)lamR[c], lamP[c]};
-    const double mu[2] = {ball ? 0.0 : lo[0], ball ? 0.0 : lo[1]};
-    const R* pk = static_cast<const R*>(a.pk);
-    double lin[2];
-    for (int f = 0; f < 2; ++f) lin[f] = cb * mu[f] + gather_plane<R>(pk, g, f, k, ix, iz);
-    R* accR = static_cast<R*>(lam_acc);
-    double* accP = reinterpret_cast<double*>(accR + 5 * S);
-    double add[2];
-    for (int f = 0; f < 2; ++f) add[f] = ball ? lo[f] : ca * mu[f];
-    if (STAGE == 2) {
-        accR[c] = (R)add[0];
-        accP[c] = add[1];
-    } else if (STAGE == 1) {
-        accR[c] = (R)((double)accR[c] + add[0]);
-        accP[c] += add[1];
-    } else {
-        accR[c] = (R)((double)accR[c] + add[0] + lin[0]);
-        accP[c] += add[1] + lin[1];
-    }
-    if (STAGE != 0) {
-        R* inR = static_cast<R*>(lam_in);
-        double* inP = reinterpret_cast<double*>(inR + 5 * S);
-        inR[c] = (R)lin[0];
-        inP[c] = lin[1];
+template <typename R, int STAGE, int TK>
+__global__ __launch_bounds__(64 * TK) void k_adj_stage(AdjStageArgs a) {
+    __shared__ AdjSmem<R, TK> sm;
+    // the (tile, x) targets, x fastest, split into gridDim.x equal contiguous
+    // ranges (one round of resident blocks), as in the forward stage
+    const long long W = (long long)a.ntz * a.ntk * a.g.nx;
+    const long long b = xcd_remap(blockIdx.x, gridDim.x);
+    long long w = W * b / gridDim.x;
+    const long long w1 = W * (b + 1) / gridDim.x;
+    while (w < w1) {
+        const int tile = (int)(w / a.g.nx), xa = (int)(w % a.g.nx);
+        const int xb = (int)min((long long)a.g.nx, xa + (w1 - w));
+        adj_tile<R, STAGE, TK>(a, tile, xa, xb, sm);
+        w += xb - xa;
+        if (w < w1) __syncthreads();  // the segment's last LDS reads are done
     }
 }
 
@@ -505,43 +761,49 @@ __global__ void k_adj_fields(GridArgs a, egb_medium med, const double* gtab, con
     grad[3 * a.nxz + cz] = gF[4];
 }
 
-inline dim3 cells(const GridArgs& a) { return dim3((a.nz + 63) / 64, (a.nx + 3) / 4, a.nth); }
-
-template <typename R>
-hipError_t adj_stage_t(const AdjArgs& a, int stage, void* lam_in, void* lam_acc, hipStream_t s) {
-    static const double CA[3] = {0.0, 0.75, 1.0 / 3.0}, CB[3] = {1.0, 0.25, 2.0 / 3.0};
-    k_adj_packets<R><<<cells(a.g), dim3(64, 4), 0, s>>>(a);
+template <typename R, int TK>
+hipError_t adj_stage_t(AdjStageArgs a, int stage, hipStream_t s) {
+    a.ntz = (a.g.nz + TZ - 1) / TZ;
+    a.ntk = (a.g.nth + TK - 1) / TK;
+    const void* k = stage == 0 ? (const void*)k_adj_stage<R, 0, TK>
+                  : stage == 1 ? (const void*)k_adj_stage<R, 1, TK> : (const void*)k_adj_stage<R, 2, TK>;
+    const long long W = (long long)a.ntz * a.ntk * a.g.nx;
+    long long G = resident_blocks(k, 64 * TK);
+    if (G <= 0) return hipErrorInvalidDeviceFunction;
+    G = std::max(1LL, std::min(G, W / 16));
+    const dim3 grid((unsigned)G), block(TZ, TK);
     switch (stage) {
-        case 2: k_adj_gather<R, 2><<<cells(a.g), dim3(64, 4), 0, s>>>(a, lam_in, lam_acc, CA[2], CB[2]); break;
-        case 1: k_adj_gather<R, 1><<<cells(a.g), dim3(64, 4), 0, s>>>(a, lam_in, lam_acc, CA[1], CB[1]); break;
-        default: k_adj_gather<R, 0><<<cells(a.g), dim3(64, 4), 0, s>>>(a, lam_in, lam_acc, CA[0], CB[0]); break;
+        case 0: k_adj_stage<R, 0, TK><<<grid, block, 0, s>>>(a); break;
+        case 1: k_adj_stage<R, 1, TK><<<grid, block, 0, s>>>(a); break;
+        default: k_adj_stage<R, 2, TK><<<grid, block, 0, s>>>(a); break;
     }
     return hipGetLastError();
 }
 
 }  // namespace
 
-size_t adjoint_packet_bytes(const egb_grid& g) {
-    return (size_t)NQ * 64 * (size_t)((g.nz + 63) / 64) * (size_t)g.nx * (size_t)g.nth * real_size(g);
-}
-
 hipError_t launch_adjoint_stage(const GridArgs& g, int dtype, int stage, const void* vel, const void* Uin,
-                                const void* lam_out, void* lam_in, void* lam_acc, void* packets, void* gvel,
+                                const void* lam_out, void* lam_in, const void* acc_in, void* acc_out, void* gvel,
                                 double dt, double xs, double zs, double r02, hipStream_t s) {
-    static const double CB[3] = {1.0, 0.25, 2.0 / 3.0};
-    AdjArgs a;
+    const unsigned long long es = dtype == EGB_F64 ? 8 : 4, S = (unsigned long long)g.stride;
+    AdjStageArgs a;
     a.g = g;
     a.vel = vel;
     a.Uin = Uin;
     a.lam = lam_out;
-    a.pk = packets;
+    a.acc_in = acc_in;
+    a.acc_out = acc_out;
+    a.lam_in = lam_in;
     a.gvel = gvel;
-    a.cbdt = CB[stage] * dt;
+    a.dt = dt;
     a.xs = xs;
     a.zs = zs;
     a.r02 = r02;
-    return dtype == EGB_F64 ? adj_stage_t<double>(a, stage, lam_in, lam_acc, s)
-                            : adj_stage_t<float>(a, stage, lam_in, lam_acc, s);
+    a.state_bytes = (unsigned)(S * (5 * es + 8));
+    a.vel_bytes = (unsigned)(7 * S * es);
+    a.gvel_bytes = (unsigned)(3 * S * es);
+    a.ntz = a.ntk = 0;
+    return dtype == EGB_F64 ? adj_stage_t<double, 4>(a, stage, s) : adj_stage_t<float, 8>(a, stage, s);
 }
 
 hipError_t launch_pick_adjoint(const GridArgs& a, int dtype, const void* state, const double* rx, int nr,

@@ -67,7 +67,7 @@ size_t egb_workspace_size(const egb_grid* g, int32_t op) {
         case EGB_OP_BEAM:
             return beam_counts_bytes(*g) + (size_t)(g->nx + g->nz) * beam_cap_default(*g) * beam_record_bytes();
         case EGB_OP_ADJOINT: {
-            const size_t step = 4 * align256(state_bytes(*g)) + align256(adjoint_packet_bytes(*g));
+            const size_t step = 5 * align256(state_bytes(*g));
             const size_t med = align256((size_t)15 * g->nx * g->nz * sizeof(double)) +
                                align256((size_t)g->nth * EGB_NFIELD * sizeof(double));
             return step > med ? step : med;
@@ -181,7 +181,7 @@ egb_status egb_adjoint_step(const egb_grid* g, const void* vel3d, const egb_sour
     void* U2 = w + sb;
     void* L2 = w + 2 * sb;
     void* L1 = w + 3 * sb;
-    void* pk = w + 4 * sb;
+    void* L3 = w + 4 * sb;
     const GridArgs a = grid_args(*g);
     // recompute the inner stages of this step (phi1 and psi only)
     StageArgs sa;
@@ -201,15 +201,17 @@ egb_status egb_adjoint_step(const egb_grid* g, const void* vel3d, const egb_sour
         e = launch_stage(sa, g->dtype, 1, stream, true);
     }
     const double r02 = src->r0 * src->r0;
-    // reverse: stage 2 (input U2), stage 1 (input U1), stage 0 (input U^n)
-    if (e == hipSuccess)
-        e = launch_adjoint_stage(a, g->dtype, 2, vel3d, U2, lambda, L2, lambda, pk, gvel, dt, src->xs, src->zs, r02,
+    // Reverse: stage 2 (input U2), stage 1 (input U1), stage 0 (input U^n).
+    // A stage reads the lambda of its output around every cell, so no output
+    // may overwrite it: the accumulated lambda of U^n lives in L1 until stage
+    // 0 writes the result back into `lambda`.
+    if (e == hipSuccess)  // lambda -> L2 (of U2), acc L1 = (ca mu + ball) part
+        e = launch_adjoint_stage(a, g->dtype, 2, vel3d, U2, lambda, L2, nullptr, L1, gvel, dt, src->xs, src->zs, r02,
                                  stream);
-    if (e == hipSuccess)
-        e = launch_adjoint_stage(a, g->dtype, 1, vel3d, U1, L2, L1, lambda, pk, gvel, dt, src->xs, src->zs, r02,
-                                 stream);
-    if (e == hipSuccess)
-        e = launch_adjoint_stage(a, g->dtype, 0, vel3d, state_n, L1, nullptr, lambda, pk, gvel, dt, src->xs, src->zs,
+    if (e == hipSuccess)  // L2 -> L3 (of U1), acc L1 +=
+        e = launch_adjoint_stage(a, g->dtype, 1, vel3d, U1, L2, L3, L1, L1, gvel, dt, src->xs, src->zs, r02, stream);
+    if (e == hipSuccess)  // L3 -> lambda = L1 + stage 0 terms
+        e = launch_adjoint_stage(a, g->dtype, 0, vel3d, state_n, L3, nullptr, L1, lambda, gvel, dt, src->xs, src->zs,
                                  r02, stream);
     return hip_status(e);
 }

@@ -241,71 +241,70 @@ __device__ __forceinline__ R weno5(R v1, R v2, R v3, R v4, R v5) {
 }
 
 // WENO5 value (undivided) and its gradient g[k] = dW/dv_{k+1}, by reverse-mode
-// differentiation of the formula above (alpha_k = d_k/(eps + S_k)^2,
-// omega_k = alpha_k / sum alpha, W = sum omega_k q_k, eps = 1e-6 max v^2).
-// W is positively 1-homogeneous in v, so its gradient is evaluated on the
-// power-of-two normalised differences and needs no rescaling.  When all
-// differences vanish both W and the gradient are 0.
+// differentiation of the formula above.  W is positively 1-homogeneous in v,
+// so the gradient is that of the power-of-two normalised differences a:
+// with omega_k = w_k / D, Rb = sum omega_k r_k and W' = a3 + Rb / 6,
+//   dW'/db_k = -omega_k (r_k - Rb) / (3 b_k)   (b_k enters squared in w),
+//   dW'/dr_k = omega_k / 6,  dW'/deps4 = sum_k dW'/db_k,
+// then back through t, u, r, s to a; eps4 = 4e-6 a_J^2 for the first entry J
+// of largest magnitude.  When all differences vanish W and the gradient are 0.
 template <typename R>
 __device__ __forceinline__ R weno5_grad(R v1, R v2, R v3, R v4, R v5, R (&g)[5]) {
-    R v[5] = {v1, v2, v3, v4, v5};
-    R m = (R)0;
-    int J = 0;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        const R a = v[k] < (R)0 ? -v[k] : v[k];
-        if (a > m) { m = a; J = k; }
-    }
-#pragma unroll
-    for (int k = 0; k < 5; ++k) g[k] = (R)0;
-    if (!(m > (R)0)) return (R)0;
+    constexpr bool F = sizeof(R) == 4;
+    const R m1 = fabs(v1), m2 = fabs(v2), m3 = fabs(v3), m4 = fabs(v4), m5 = fabs(v5);
+    const R m = fmax(fmax(fmax(fmax(m1, m2), m3), m4), m5);
+    // first entry of largest magnitude
+    const bool j0 = m1 == m, j1 = !j0 && m2 == m, j2 = !j0 && !j1 && m3 == m;
+    const bool j3 = !j0 && !j1 && !j2 && m4 == m, j4 = !j0 && !j1 && !j2 && !j3;
+    const R vJ = j0 ? v1 : j1 ? v2 : j2 ? v3 : j3 ? v4 : v5;
     int e;
-    if constexpr (sizeof(R) == 4) e = __builtin_amdgcn_frexp_expf(m);
+    if constexpr (F) e = __builtin_amdgcn_frexp_expf(m);
     else e = __builtin_amdgcn_frexp_exp(m);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        if constexpr (sizeof(R) == 4) v[k] = __builtin_amdgcn_ldexpf(v[k], -e);
-        else v[k] = __builtin_amdgcn_ldexp(v[k], -e);
-    }
-    const R vJ = v[J];
-    const R eps = (R)1e-6 * vJ * vJ;
-    const R q[3] = {v[0] * (R)(1.0 / 3.0) - v[1] * (R)(7.0 / 6.0) + v[2] * (R)(11.0 / 6.0),
-                    -v[1] * (R)(1.0 / 6.0) + v[2] * (R)(5.0 / 6.0) + v[3] * (R)(1.0 / 3.0),
-                    v[2] * (R)(1.0 / 3.0) + v[3] * (R)(5.0 / 6.0) - v[4] * (R)(1.0 / 6.0)};
-    const R t[3] = {v[0] - (R)2 * v[1] + v[2], v[1] - (R)2 * v[2] + v[3], v[2] - (R)2 * v[3] + v[4]};
-    const R u[3] = {v[0] - (R)4 * v[1] + (R)3 * v[2], v[1] - v[3], (R)3 * v[2] - (R)4 * v[3] + v[4]};
-    const R d[3] = {(R)0.1, (R)0.6, (R)0.3};
-    R b[3], al[3], A = (R)0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        b[k] = eps + (R)(13.0 / 12.0) * t[k] * t[k] + (R)0.25 * u[k] * u[k];
-        al[k] = d[k] / (b[k] * b[k]);
-        A += al[k];
-    }
-    const R iA = (R)1 / A;
-    const R w[3] = {al[0] * iA, al[1] * iA, al[2] * iA};
-    const R W = w[0] * q[0] + w[1] * q[1] + w[2] * q[2];
-    // backward
-    R tb[3], ub[3], epsb = (R)0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const R ab = (q[k] - W) * iA;
-        const R bb = (R)(-2) * al[k] * ab / b[k];
-        epsb += bb;
-        tb[k] = bb * (R)(13.0 / 6.0) * t[k];
-        ub[k] = bb * (R)0.5 * u[k];
-    }
-    g[0] = w[0] * (R)(1.0 / 3.0) + tb[0] + ub[0];
-    g[1] = -w[0] * (R)(7.0 / 6.0) - w[1] * (R)(1.0 / 6.0) - (R)2 * tb[0] - (R)4 * ub[0] + tb[1] + ub[1];
-    g[2] = w[0] * (R)(11.0 / 6.0) + w[1] * (R)(5.0 / 6.0) + w[2] * (R)(1.0 / 3.0) + tb[0] + (R)3 * ub[0] -
-           (R)2 * tb[1] + tb[2] + (R)3 * ub[2];
-    g[3] = w[1] * (R)(1.0 / 3.0) + w[2] * (R)(5.0 / 6.0) + tb[1] - ub[1] - (R)2 * tb[2] - (R)4 * ub[2];
-    g[4] = -w[2] * (R)(1.0 / 6.0) + tb[2] + ub[2];
-#pragma unroll
-    for (int k = 0; k < 5; ++k)
-        if (k == J) g[k] += epsb * (R)2e-6 * vJ;
-    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_ldexpf(W, e);
-    else return __builtin_amdgcn_ldexp(W, e);
+    auto sc = [&](R x) {
+        if constexpr (F) return __builtin_amdgcn_ldexpf(x, -e);
+        else return __builtin_amdgcn_ldexp(x, -e);
+    };
+    auto rcp = [](R x) {
+        if constexpr (F) return __builtin_amdgcn_rcpf(x);
+        else return (R)1 / x;
+    };
+    const R a1 = sc(v1), a2 = sc(v2), a3 = sc(v3), a4 = sc(v4), a5 = sc(v5), aJ = sc(vJ);
+    // aJ^2 lies in [1/4, 1) unless all differences vanish (then 1/4 keeps D > 0)
+    const R eps4 = (R)4e-6 * fmax(aJ * aJ, (R)0.25);
+    const R s1 = a2 - a1, s2 = a3 - a2, s3 = a4 - a3, s4 = a5 - a4;
+    const R t0 = s2 - s1, u0 = (R)3 * s2 - s1;
+    const R t1 = s3 - s2, u1 = s2 + s3;
+    const R t2 = s4 - s3, u2 = s4 - (R)3 * s3;
+    constexpr R c13 = (R)(13.0 / 3.0);
+    const R b0 = (c13 * t0) * t0 + (u0 * u0 + eps4);
+    const R b1 = (c13 * t1) * t1 + (u1 * u1 + eps4);
+    const R b2 = (c13 * t2) * t2 + (u2 * u2 + eps4);
+    const R G = ((R)3 * b0) * b0, E1 = b1 * b1, E2 = b2 * b2;
+    const R w0 = E1 * E2, w2 = G * E1, H = G * E2, w1 = H + H;
+    const R rD = rcp((w0 + w1) + w2);
+    const R o0 = w0 * rD, o1 = w1 * rD, o2 = w2 * rD;
+    const R r0 = (R)5 * s2 - (R)2 * s1, r1 = s2 + (R)2 * s3, r2 = (R)4 * s3 - s4;
+    const R Rb = o0 * r0 + o1 * r1 + o2 * r2;
+    const R W = a3 + Rb * (R)(1.0 / 6.0);
+    // backward: beta_k = omega_k (r_k - Rb) / b_k, dW'/db_k = -beta_k / 3
+    const R be0 = o0 * (r0 - Rb) * rcp(b0), be1 = o1 * (r1 - Rb) * rcp(b1), be2 = o2 * (r2 - Rb) * rcp(b2);
+    constexpr R kt = (R)(-2.0 * 13.0 / 9.0), ku = (R)(-2.0 / 3.0);  // d b / d t = 2 c t, d b / d u = 2 u
+    const R tb0 = kt * t0 * be0, tb1 = kt * t1 * be1, tb2 = kt * t2 * be2;
+    const R ub0 = ku * u0 * be0, ub1 = ku * u1 * be1, ub2 = ku * u2 * be2;
+    const R epsb = (be0 + be1 + be2) * (R)(-1.0 / 3.0);
+    const R s1b = -tb0 - ub0 - o0 * (R)(1.0 / 3.0);
+    const R s2b = tb0 + (R)3 * ub0 - tb1 + ub1 + (o0 * (R)5 + o1) * (R)(1.0 / 6.0);
+    const R s3b = tb1 + ub1 - tb2 - (R)3 * ub2 + (o1 + o2 * (R)2) * (R)(1.0 / 3.0);
+    const R s4b = tb2 + ub2 - o2 * (R)(1.0 / 6.0);
+    const R ej = epsb * (R)8e-6 * aJ;
+    const bool ok = m > (R)0;
+    g[0] = ok ? -s1b + (j0 ? ej : (R)0) : (R)0;
+    g[1] = ok ? s1b - s2b + (j1 ? ej : (R)0) : (R)0;
+    g[2] = ok ? (R)1 + s2b - s3b + (j2 ? ej : (R)0) : (R)0;
+    g[3] = ok ? s3b - s4b + (j3 ? ej : (R)0) : (R)0;
+    g[4] = ok ? s4b + (j4 ? ej : (R)0) : (R)0;
+    if constexpr (F) return ok ? __builtin_amdgcn_ldexpf(W, e) : (R)0;
+    else return ok ? __builtin_amdgcn_ldexp(W, e) : (R)0;
 }
 
 // ------------------------------------------------------------ dual numbers

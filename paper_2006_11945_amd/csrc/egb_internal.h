@@ -64,6 +64,9 @@ struct StageArgs {
     double dt;
     double xs, zs, r02;
 };
+// Blocks of `kernel` (launched with `threads` threads) that the current device
+// holds at once; 0 on a HIP error.
+int resident_blocks(const void* kernel, int threads);
 // kinematic: march phi1 and psi only (the planes a traveltime depends on)
 hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s, bool kinematic = false);
 // The stage kernel addresses each array with 32-bit byte offsets.
@@ -78,9 +81,10 @@ hipError_t launch_stage_batched(const void* items, const long long* wfirst, int 
                                 int stage, int grid, hipStream_t s);
 
 // Adjoint of the kinematic march (see adjoint.hip).
-size_t adjoint_packet_bytes(const egb_grid& g);
+// One reverse stage: lam_in (stages 1, 2) and acc_out = acc_in + ... (see
+// adjoint.hip); lam_out must not alias any output.
 hipError_t launch_adjoint_stage(const GridArgs& g, int dtype, int stage, const void* vel, const void* Uin,
-                                const void* lam_out, void* lam_in, void* lam_acc, void* packets, void* gvel,
+                                const void* lam_out, void* lam_in, const void* acc_in, void* acc_out, void* gvel,
                                 double dt, double xs, double zs, double r02, hipStream_t s);
 hipError_t launch_pick_adjoint(const GridArgs& a, int dtype, const void* state, const double* rx, int nr,
                                const double* tbar, void* lam, hipStream_t s);

@@ -32,103 +32,21 @@
 
 #include "egb_device.h"
 #include "egb_internal.h"
+#include "stage_common.h"
 
 namespace egb {
 namespace {
 
-template <int STAGE>
-struct RK;
-template <>
-struct RK<0> {
-    static constexpr double ca = 0.0, cb = 1.0;
-};
-template <>
-struct RK<1> {
-    static constexpr double ca = 0.75, cb = 0.25;
-};
-template <>
-struct RK<2> {
-    static constexpr double ca = 1.0 / 3.0, cb = 2.0 / 3.0;
-};
-
 #ifndef WAVES_PER_EU
 #define WAVES_PER_EU 3
 #endif
-constexpr int TZ = 64;       // z cells per tile (one wavefront row)
 constexpr int PZ = TZ + 6;   // padded LDS row
-
-// WENO5 of six values u0..u5 read in upwind order (u3 is the cell itself,
-// u0..u2 lie on the upwind side): differences u_k - u_{k-1}, formed in T,
-// derivative in R.  Reading the stencil mirrored when the velocity component
-// is negative turns D+ into minus D- of the mirrored values, so
-// V * D(U) = |V| * weno_up(mirrored values) for either sign.
-template <typename R, typename T>
-__device__ __forceinline__ R weno_up(T u0, T u1, T u2, T u3, T u4, T u5) {
-    return weno5<R>((R)(u1 - u0), (R)(u2 - u1), (R)(u3 - u2), (R)(u4 - u3), (R)(u5 - u4));
-}
-
-// Value m of the upwind-ordered x stencil from the column queue q (q[3] is
-// the cell): DIR 0 = every lane upwinds from -x, 1 = every lane from +x,
-// 2 = per lane (`minus`).
-template <int DIR, typename T>
-__device__ __forceinline__ T upw(const T (&q)[7], int m, bool minus) {
-    if constexpr (DIR == 0) return q[m];
-    else if constexpr (DIR == 1) return q[6 - m];
-    else return minus ? q[m] : q[6 - m];
-}
-
-// Raw buffer access: one descriptor per array (base, size < 4 GiB), a 32-bit
-// per-lane byte offset and the plane offset in the scalar offset register.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
-}
-template <typename T>
-__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
-template <>
-__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
-}
-template <>
-__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
-}
-__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
-}
-__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
-                                          (int)voff, (int)soff, 0);
-}
 
 // Tiles of one problem: ntz x ntk (z, theta) tiles; the batched queue also
 // splits x into nxc chunks of kx; nblocks is the launch's block count.
 struct TileArgs {
     int ntz, ntk, nxc, kx, nblocks;
     unsigned state_bytes, vel_bytes;
-};
-
-// XCD-aware numbering: hardware block b runs on XCD b % 8; give each XCD a
-// contiguous range of logical tiles (a bijection of [0, n)).
-__device__ __forceinline__ int xcd_remap(int b, int n) {
-    const int q8 = n >> 3, r8 = n & 7, xcd = b & 7;
-    return xcd * q8 + min(xcd, r8) + (b >> 3);
-}
-
-// LDS slice layout: NP planes of R (as raw words), then psi as two 32-bit
-// planes (F32) or one 64-bit plane (F64), so that one cell has the same word
-// index in every plane and one per-lane address serves them all (the plane
-// is an immediate offset).
-template <typename R>
-struct LdsWord;
-template <>
-struct LdsWord<float> {
-    using T = unsigned;
-    static constexpr int PSI_WORDS = 2;
-};
-template <>
-struct LdsWord<double> {
-    using T = unsigned long long;
-    static constexpr int PSI_WORDS = 1;
 };
 
 template <typename R, int TK, int NP>
@@ -156,24 +74,6 @@ __device__ __forceinline__ void lds_put(StageSmem<R, TK, NP>& sm, int i, const R
         sm.w[i + (NP + 1) * S::PLANE] = (unsigned)(b >> 32);
     } else {
         sm.w[i + NP * S::PLANE] = b;
-    }
-}
-
-// Plane f (or psi) of the cell at byte address `byte` of the slice buffers.
-template <typename R, typename S>
-__device__ __forceinline__ R lds_r(const S& sm, int byte, int f) {
-    const char* c = reinterpret_cast<const char*>(sm.w) + byte + f * S::PB;
-    return __builtin_bit_cast(R, *reinterpret_cast<const typename S::W*>(c));
-}
-template <int NP, typename S>
-__device__ __forceinline__ double lds_psi(const S& sm, int byte) {
-    const char* c = reinterpret_cast<const char*>(sm.w) + byte + NP * S::PB;
-    if constexpr (sizeof(typename S::W) == 4) {
-        const unsigned lo = *reinterpret_cast<const unsigned*>(c);
-        const unsigned hi = *reinterpret_cast<const unsigned*>(c + S::PB);
-        return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-    } else {
-        return __builtin_bit_cast(double, *reinterpret_cast<const unsigned long long*>(c));
     }
 }
 
@@ -530,25 +430,6 @@ unsigned long long state_bytes_of(const GridArgs& g, size_t es) {
     return (unsigned long long)g.stride * (5ull * es + 8ull);
 }
 
-// Blocks of a kernel that the device holds at once (cached per kernel and device).
-int resident_blocks(const void* kernel, int threads) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    static std::mutex mu;
-    static std::map<std::pair<const void*, int>, int> cache;
-    std::lock_guard<std::mutex> lock(mu);
-    const auto key = std::make_pair(kernel, dev);
-    auto it = cache.find(key);
-    if (it != cache.end()) return it->second;
-    int per_cu = 0, ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return 0;
-    const int n = std::max(1, per_cu) * std::max(1, ncu);
-    cache[key] = n;
-    return n;
-}
-
 template <typename R, int TK, bool KIN>
 hipError_t launch_stage_t(const StageArgs& a, int stage, hipStream_t s) {
     TileArgs t;
@@ -601,6 +482,25 @@ hipError_t launch_batched_t(const void* items, const long long* wfirst, int npro
 }
 
 }  // namespace
+
+// Blocks of a kernel that the device holds at once (cached per kernel and device).
+int resident_blocks(const void* kernel, int threads) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(kernel, dev);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    const int n = std::max(1, per_cu) * std::max(1, ncu);
+    cache[key] = n;
+    return n;
+}
 
 size_t batch_item_bytes() { return sizeof(BatchItem); }
 
