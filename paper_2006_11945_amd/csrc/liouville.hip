@@ -387,11 +387,11 @@ void k_stage(StageArgs a, TileArgs t) {
     }
 }
 
-// Batched march: one launch walks the problems in order (uneven grids, own
-// buffers and dt); within problem p every block takes its equal contiguous
-// share of the (tile, x) steps, x fastest, exactly like k_stage, so that the
-// blocks running at any moment work on the same problem (its arrays stay in
-// the L2 and TLB).  wfirst[p + 1] - wfirst[p] is the step count of problem p.
+// Batched march: the (problem, tile, x) steps of every problem (uneven
+// grids, own buffers and dt), x fastest, split into gridDim.x equal
+// contiguous ranges like k_stage, so that many small problems fill the chip
+// together; a range crossing a tile or problem boundary is several segments.
+// wfirst[p] is the first step of problem p (wfirst[nprob] = total).
 struct BatchItem {
     StageArgs a[3];  // stage 0, 1, 2 buffers of this problem
     TileArgs t;
@@ -403,26 +403,27 @@ template <typename R, int STAGE, int TK>
 __global__ __launch_bounds__(64 * TK) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
 void k_stage_batched(const BatchItem* __restrict__ items, const long long* __restrict__ wfirst, int nprob) {
     __shared__ StageSmem<R, TK, 5> sm;
+    const long long W = wfirst[nprob];
     const long long b = xcd_remap(blockIdx.x, gridDim.x);
+    long long w = W * b / gridDim.x;
+    const long long w1 = W * (b + 1) / gridDim.x;
     bool first_seg = true;
-    for (int p = 0; p < nprob; ++p) {
-        // private copies: the stage's stores cannot alias them, so they stay in scalar registers
-        const StageArgs a = items[p].a[STAGE];
-        const TileArgs ta = items[p].t;
-        // as k_stage: at most one block per MIN_STEPS steps of this problem
-        const long long W = wfirst[p + 1] - wfirst[p];
-        const long long G = min((long long)gridDim.x, max(1LL, W / MIN_STEPS));
-        if (b >= G) continue;
-        long long w = W * b / G;
-        const long long w1 = W * (b + 1) / G;
-        while (w < w1) {
-            const int tile = (int)(w / a.g.nx), xa = (int)(w % a.g.nx);
-            const int xb = (int)min((long long)a.g.nx, xa + (w1 - w));
-            if (!first_seg) __syncthreads();  // the previous segment's last LDS reads are done
-            first_seg = false;
-            stage_tile<R, STAGE, TK, false>(a, ta, tile, xa, xb, sm);
-            w += xb - xa;
+    while (w < w1) {
+        int lo = 0, hi = nprob;  // wfirst[lo] <= w < wfirst[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (wfirst[mid] <= w) lo = mid; else hi = mid;
         }
+        // private copies: the stage's stores cannot alias them, so they stay in scalar registers
+        const StageArgs a = items[lo].a[STAGE];
+        const TileArgs ta = items[lo].t;
+        const long long l = w - wfirst[lo];
+        const int tile = (int)(l / a.g.nx), xa = (int)(l % a.g.nx);
+        const int xb = (int)min((long long)a.g.nx, xa + (w1 - w));
+        if (!first_seg) __syncthreads();  // the previous segment's last LDS reads are done
+        first_seg = false;
+        stage_tile<R, STAGE, TK, false>(a, ta, tile, xa, xb, sm);
+        w += xb - xa;
     }
 }
 
@@ -467,9 +468,10 @@ hipError_t launch_batched_t(const void* items, const long long* wfirst, int npro
                             int grid, hipStream_t s) {
     const void* k = stage == 0 ? (const void*)k_stage_batched<R, 0, TK>
                   : stage == 1 ? (const void*)k_stage_batched<R, 1, TK> : (const void*)k_stage_batched<R, 2, TK>;
-    // one round of resident blocks (each problem uses at most one per MIN_STEPS steps)
+    // one round of resident blocks, each with at least MIN_STEPS x steps
     long long G = grid > 0 ? grid : resident_blocks(k, 64 * TK);
     if (G <= 0) return hipErrorInvalidDeviceFunction;
+    if (grid <= 0) G = std::min(G, std::max(1LL, total / MIN_STEPS));
     G = std::max(1LL, std::min(G, total));
     const dim3 block(TZ, TK);
     const BatchItem* it = static_cast<const BatchItem*>(items);
