@@ -248,86 +248,54 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
     double cm1;
     own_mu_v(xa, cm0, cm1, cvx, cvz, cvt);
 
-    const int me = (tk + 6) * S::VZ + tz + 6;  // own cell in the value slice
+    // value cells of the next core slice, loaded at the end of the step before
+    R vv[NVI], vv1[NVI];
+    double vp[NVI], vp1[NVI];
+    auto load_values = [&](int x) {
+        const unsigned xo = (unsigned)(x * g.nz);
+#pragma unroll
+        for (int r = 0; r < NVI; ++r) {
+            unsigned vb;
+            int vm;
+            vcell(tid + r * NT, vb, vm);
+            const unsigned o = vb + xo;
+            vv[r] = bload<R>(rUi, o * ES, 0);
+            vp[r] = bload<double>(rUi, o * 8u, PSI);
+            if (z_end) {  // second point of a ghost: the cell next to the edge
+                const unsigned o1 = vm < 0 ? o + 1u : (vm > 0 && vm < 100 ? o - 1u : o);
+                vv1[r] = bload<R>(rUi, o1 * ES, 0);
+                vp1[r] = bload<double>(rUi, o1 * 8u, PSI);
+            }
+        }
+    };
+
+    // halo sources' mu and V of the next core slice, loaded with the values
+    R hm0[NHI], hvel[NHI];
+    double hm1[NHI];
+    auto load_halo = [&](int x) {
+        const unsigned xo = (unsigned)(x * g.nz);
+#pragma unroll
+        for (int r = 0; r < NHI; ++r) {
+            int tl, zl;
+            bool real;
+            unsigned hc;
+            hcell(tid + r * NT, tl, zl, real, hc);
+            const unsigned c = (hc + xo) * ES, c8 = (hc + xo) * 8u;
+            const R l0 = bload<R>(rL, c, 0);
+            const double l1 = bload<double>(rL, c8, PSI);
+            hvel[r] = bload<R>(rV, c, (tid + r * NT < 6 * TZ ? EGB_VT : EGB_VZ) * SP);
+            const bool live = real && !in_ball(x, tzi * TZ + zl);
+            hm0[r] = live ? l0 : (R)0;
+            hm1[r] = live ? l1 : 0.0;
+        }
+    };
 
     for (int xs = xa; xs < xb; ++xs) {
         const bool src = xs >= 0 && xs < g.nx;  // block-uniform
         const bool core = xs >= x0 && xs < x1;
-        // prefetch: queue entry xs + 4, own mu and V of slice xs + 1
-        R qn;
-        double qpn;
-        {
-            const unsigned o = kb + (unsigned)(min(max(xs + 4, 0), g.nx - 1) * g.nz + izc);
-            qn = bload<R>(rUi, o * ES, 0);
-            qpn = bload<double>(rUi, o * 8u, PSI);
-        }
-        R nm0, nvx, nvz, nvt;
-        double nm1;
-        own_mu_v(xs + 1, nm0, nm1, nvx, nvz, nvt);
-        // slice loads of a core step: value cells, halo sources' mu and V, own gvel
-        R vv[NVI], vv1[NVI];
-        double vp[NVI], vp1[NVI];
-        R hm0[NHI], hvel[NHI];
-        double hm1[NHI];
-        const unsigned xo = (unsigned)(min(max(xs, 0), g.nx - 1) * g.nz);
-        const unsigned cR = (kb + xo + (unsigned)izc) * ES;
         if (core) {
-#pragma unroll
-            for (int r = 0; r < NVI; ++r) {
-                unsigned vb;
-                int vm;
-                vcell(tid + r * NT, vb, vm);
-                const unsigned o = vb + xo;
-                vv[r] = bload<R>(rUi, o * ES, 0);
-                vp[r] = bload<double>(rUi, o * 8u, PSI);
-                if (z_end) {  // second point of a ghost: the cell next to the edge
-                    const unsigned o1 = vm < 0 ? o + 1u : (vm > 0 && vm < 100 ? o - 1u : o);
-                    vv1[r] = bload<R>(rUi, o1 * ES, 0);
-                    vp1[r] = bload<double>(rUi, o1 * 8u, PSI);
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < NHI; ++r) {
-                int tl, zl;
-                bool real;
-                unsigned hc;
-                hcell(tid + r * NT, tl, zl, real, hc);
-                const unsigned c = (hc + xo) * ES, c8 = (hc + xo) * 8u;
-                const R l0 = bload<R>(rL, c, 0);
-                const double l1 = bload<double>(rL, c8, PSI);
-                hvel[r] = bload<R>(rV, c, (tid + r * NT < 6 * TZ ? EGB_VT : EGB_VZ) * SP);
-                const bool live = real && !in_ball(xs, tzi * TZ + zl);
-                hm0[r] = live ? l0 : (R)0;
-                hm1[r] = live ? l1 : 0.0;
-            }
-        }
-        R gsx = (R)0;  // this step's x term of gvel
-        // x rows of the own column
-        if (src && __any(cm0 != (R)0 || cm1 != 0.0)) {
-            const bool plus = cvx >= (R)0;
-            R du[6];
-            R d0[NSLOT], d1[NSLOT];
-            auto u = [&](const auto& q, int m) { return plus ? q[m] : q[6 - m]; };
-            const R W0 = wgrad_up<R>(u(qv, 0), u(qv, 1), u(qv, 2), qv[3], u(qv, 4), u(qv, 5), du);
-            const R c0 = (R)(-kx) * fabs(cvx) * cm0;
-            to_slots(du, plus, c0, d0);
-            const R W1 = wgrad_up<R>(u(qp, 0), u(qp, 1), u(qp, 2), qp[3], u(qp, 4), u(qp, 5), du);
-            const R c1 = (R)(-kx * (double)fabs(cvx) * cm1);
-            to_slots(du, plus, c1, d1);
-            if (xs < 3 || xs > g.nx - 4) {
-                fold_ends(d0, xs, g.nx);
-                fold_ends(d1, xs, g.nx);
-            }
-#pragma unroll
-            for (int j = 0; j < NSLOT; ++j) {
-                a0[j] += d0[j];
-                a1[j] += d1[j];
-            }
-            // d(-cb dt V_x D_x U / dx)/dV_x with D_x U = sign * W_up / dx
-            gsx = (R)(plus ? -kx : kx) * (cm0 * W0 + (R)cm1 * W1);
-        }
-        if (core) {
-            // value slice into LDS
+            // value slice into LDS (every read of the previous slice ended
+            // before the previous step's second barrier)
 #pragma unroll
             for (int r = 0; r < NVI; ++r) {
                 const int i = tid + r * NT;
@@ -352,6 +320,76 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
                     }
                 }
             }
+        }
+        // prefetch: queue entry xs + 4, own mu and V of slice xs + 1
+        R qn;
+        double qpn;
+        {
+            const unsigned o = kb + (unsigned)(min(max(xs + 4, 0), g.nx - 1) * g.nz + izc);
+            qn = bload<R>(rUi, o * ES, 0);
+            qpn = bload<double>(rUi, o * 8u, PSI);
+        }
+        R nm0, nvx, nvz, nvt;
+        double nm1;
+        own_mu_v(xs + 1, nm0, nm1, nvx, nvz, nvt);
+        // this step's halo mu and V, then the next core slice's values and halo
+        // mu and V (a whole step of cover)
+        R chm0[NHI], chvel[NHI];
+        double chm1[NHI];
+#pragma unroll
+        for (int r = 0; r < NHI; ++r) {
+            chm0[r] = hm0[r];
+            chm1[r] = hm1[r];
+            chvel[r] = hvel[r];
+        }
+        if (xs + 1 >= x0 && xs + 1 < x1) {
+            load_values(xs + 1);
+            load_halo(xs + 1);
+        }
+        const unsigned xo = (unsigned)(min(max(xs, 0), g.nx - 1) * g.nz);
+        const unsigned cR = (kb + xo + (unsigned)izc) * ES;
+        // loads consumed later in the step: the output target's lambda and
+        // accumulated lambda (clamped, used only when written), own gvel
+        const int xt = xs - 3;
+        const bool out = valid && xt >= x0 && xt < x1;
+        const unsigned co = kb + (unsigned)(min(max(xt, 0), g.nx - 1) * g.nz + izc);
+        const R ol0 = bload<R>(rL, co * ES, 0);
+        const double ol1 = bload<double>(rL, co * 8u, PSI);
+        R oa0 = (R)0;
+        double oa1 = 0.0;
+        if constexpr (STAGE != 2) {
+            const auto rAi = make_rsrc(a.acc_in, a.state_bytes);
+            oa0 = bload<R>(rAi, co * ES, 0);
+            oa1 = bload<double>(rAi, co * 8u, PSI);
+        }
+        const bool wlive = __any(cm0 != (R)0 || cm1 != 0.0);  // wave-uniform
+        R gv0 = (R)0, gv1 = (R)0, gv2 = (R)0;
+        if (core && wlive) {
+            gv0 = bload<R>(rG, cR, 0);
+            gv1 = bload<R>(rG, cR, SP);
+            gv2 = bload<R>(rG, cR, 2u * SP);
+        }
+        R gsx = (R)0;  // this step's x term of gvel
+        // x rows of the own column
+        if (src && wlive) {
+            const bool plus = cvx >= (R)0;
+            R du[6], d[NSLOT];
+            auto u = [&](const auto& q, int m) { return plus ? q[m] : q[6 - m]; };
+            const bool xend = xs < 3 || xs > g.nx - 4;
+            const R W0 = wgrad_up<R>(u(qv, 0), u(qv, 1), u(qv, 2), qv[3], u(qv, 4), u(qv, 5), du);
+            to_slots(du, plus, (R)(-kx) * fabs(cvx) * cm0, d);
+            if (xend) fold_ends(d, xs, g.nx);
+#pragma unroll
+            for (int j = 0; j < NSLOT; ++j) a0[j] += d[j];
+            const R W1 = wgrad_up<R>(u(qp, 0), u(qp, 1), u(qp, 2), qp[3], u(qp, 4), u(qp, 5), du);
+            to_slots(du, plus, (R)(-kx * (double)fabs(cvx) * cm1), d);
+            if (xend) fold_ends(d, xs, g.nx);
+#pragma unroll
+            for (int j = 0; j < NSLOT; ++j) a1[j] += d[j];
+            // d(-cb dt V_x D_x U / dx)/dV_x with D_x U = sign * W_up / dx
+            gsx = (R)(plus ? -kx : kx) * (cm0 * W0 + (R)cm1 * W1);
+        }
+        if (core) {
             __syncthreads();
             // z and theta rows of a source at LDS (tl, zl): slots scaled by
             // -cb dt |V| mu / h, stored at the source position
@@ -361,39 +399,23 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
                 const int step = (zaxis ? WS : S::VZ * WS) * (plus ? 1 : -1);
                 const int b0 = base - 3 * step, b1 = base - 2 * step, b2 = base - step;
                 const int b4 = base + step, b5 = base + 2 * step;
-                R du[6];
-                R d0[NSLOT];
-                R d1[NSLOT];
+                R du[6], d[NSLOT];
+                const double kk = zaxis ? kz : kt;
+                const int stride = zaxis ? S::ZPL : S::TPL;
+                R* dst = zaxis ? sm.cz + tl * S::CZW + zl + 3 : sm.ct + (tl + 3) * TZ + zl;
+                const bool fold = zaxis && (zg < 3 || zg > g.nz - 4);
                 const R W0 = wgrad_up<R>(lds_r<R>(sm, b0, 0), lds_r<R>(sm, b1, 0), lds_r<R>(sm, b2, 0),
                                          lds_r<R>(sm, base, 0), lds_r<R>(sm, b4, 0), lds_r<R>(sm, b5, 0), du);
-                const double kk = zaxis ? kz : kt;
-                const R c0 = (R)(-kk) * fabs(vel) * m0;
-                to_slots(du, plus, c0, d0);
+                to_slots(du, plus, (R)(-kk) * fabs(vel) * m0, d);
+                if (fold) fold_ends(d, zg, g.nz);
+#pragma unroll
+                for (int j = 0; j < NSLOT; ++j) dst[j * stride] = d[j];
                 const R W1 = wgrad_up<R>(lds_psi<1>(sm, b0), lds_psi<1>(sm, b1), lds_psi<1>(sm, b2),
                                          lds_psi<1>(sm, base), lds_psi<1>(sm, b4), lds_psi<1>(sm, b5), du);
-                const R c1 = (R)(-kk * (double)fabs(vel) * m1);
-                to_slots(du, plus, c1, d1);
-                if (zaxis && (zg < 3 || zg > g.nz - 4)) {
-                    fold_ends(d0, zg, g.nz);
-                    fold_ends(d1, zg, g.nz);
-                }
-                R* dst0;
-                R* dst1;
-                int stride;
-                if (zaxis) {
-                    dst0 = sm.cz + tl * S::CZW + zl + 3;
-                    dst1 = dst0 + NSLOT * S::ZPL;
-                    stride = S::ZPL;
-                } else {
-                    dst0 = sm.ct + (tl + 3) * TZ + zl;
-                    dst1 = dst0 + NSLOT * S::TPL;
-                    stride = S::TPL;
-                }
+                to_slots(du, plus, (R)(-kk * (double)fabs(vel) * m1), d);
+                if (fold) fold_ends(d, zg, g.nz);
 #pragma unroll
-                for (int j = 0; j < NSLOT; ++j) {
-                    dst0[j * stride] = d0[j];
-                    dst1[j * stride] = d1[j];
-                }
+                for (int j = 0; j < NSLOT; ++j) dst[(NSLOT + j) * stride] = d[j];
                 Wsum = (plus ? (R)1 : (R)-1) * (m0 * W0 + (R)m1 * W1);
             };
             auto zero_row = [&](int tl, int zl, bool zaxis) {
@@ -402,9 +424,8 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
 #pragma unroll
                 for (int j = 0; j < 2 * NSLOT; ++j) dst0[j * stride] = (R)0;
             };
-            const bool live = cm0 != (R)0 || cm1 != 0.0;
             R Wz = (R)0, Wt = (R)0;
-            if (__any(live)) {
+            if (wlive) {
                 row(tk, tz, true, cvz, cm0, cm1, izc, Wz);
                 row(tk, tz, false, cvt, cm0, cm1, izc, Wt);
             } else {
@@ -421,15 +442,12 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
                     hcell(h, tl, zl, real, hc);
                     const bool zaxis = h >= 6 * TZ;
                     R wh;  // a halo source's V term belongs to another tile
-                    if (__any(hm0[r] != (R)0 || hm1[r] != 0.0))
-                        row(tl, zl, zaxis, hvel[r], hm0[r], hm1[r], tzi * TZ + zl, wh);
+                    if (__any(chm0[r] != (R)0 || chm1[r] != 0.0))
+                        row(tl, zl, zaxis, chvel[r], chm0[r], chm1[r], tzi * TZ + zl, wh);
                     else zero_row(tl, zl, zaxis);
                 }
             }
-            if (valid) {
-                const R gv0 = bload<R>(rG, cR, 0);
-                const R gv1 = bload<R>(rG, cR, SP);
-                const R gv2 = bload<R>(rG, cR, 2u * SP);
+            if (valid && wlive) {
                 bstore(gv0 + gsx, rG, cR, 0);
                 bstore(gv1 + (R)(-kz) * Wz, rG, cR, SP);
                 bstore(gv2 + (R)(-kt) * Wt, rG, cR, 2u * SP);
@@ -449,11 +467,10 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
             a1[3] += (R)(t1 + cb * cm1);
         }
         // target xs - 3 is complete
-        const int xt = xs - 3;
-        if (valid && xt >= x0 && xt < x1) {
-            const unsigned c = kb + (unsigned)(xt * g.nz + iz);
-            const R l0 = bload<R>(rL, c * ES, 0);
-            const double l1 = bload<double>(rL, c * 8u, PSI);
+        if (out) {
+            const unsigned c = co;
+            const R l0 = ol0;
+            const double l1 = ol1;
             const bool ball = in_ball(xt, iz);
             const R add0 = ball ? l0 : (R)ca * l0;
             const double add1 = ball ? l1 : ca * l1;
@@ -462,9 +479,8 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
                 bstore(add0, rAo, c * ES, 0);
                 bstore(add1, rAo, c * 8u, PSI);
             } else {
-                const auto rAi = make_rsrc(a.acc_in, a.state_bytes);
-                R o0 = bload<R>(rAi, c * ES, 0) + add0;
-                double o1 = bload<double>(rAi, c * 8u, PSI) + add1;
+                R o0 = oa0 + add0;
+                double o1 = oa1 + add1;
                 if constexpr (STAGE == 0) {
                     o0 += a0[0];
                     o1 += (double)a1[0];
@@ -496,6 +512,7 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
         cvx = nvx;
         cvz = nvz;
         cvt = nvt;
+
     }
 }
 

@@ -251,12 +251,10 @@ __device__ __forceinline__ R weno5(R v1, R v2, R v3, R v4, R v5) {
 template <typename R>
 __device__ __forceinline__ R weno5_grad(R v1, R v2, R v3, R v4, R v5, R (&g)[5]) {
     constexpr bool F = sizeof(R) == 4;
-    const R m1 = fabs(v1), m2 = fabs(v2), m3 = fabs(v3), m4 = fabs(v4), m5 = fabs(v5);
-    const R m = fmax(fmax(fmax(fmax(m1, m2), m3), m4), m5);
-    // first entry of largest magnitude
-    const bool j0 = m1 == m, j1 = !j0 && m2 == m, j2 = !j0 && !j1 && m3 == m;
-    const bool j3 = !j0 && !j1 && !j2 && m4 == m, j4 = !j0 && !j1 && !j2 && !j3;
-    const R vJ = j0 ? v1 : j1 ? v2 : j2 ? v3 : j3 ? v4 : v5;
+    const R m = fmax(fmax(fmax(fmax(fabs(v1), fabs(v2)), fabs(v3)), fabs(v4)), fabs(v5));
+    // first entry of largest magnitude (its index and value)
+    const int J = fabs(v1) == m ? 0 : fabs(v2) == m ? 1 : fabs(v3) == m ? 2 : fabs(v4) == m ? 3 : 4;
+    const R vJ = J == 0 ? v1 : J == 1 ? v2 : J == 2 ? v3 : J == 3 ? v4 : v5;
     int e;
     if constexpr (F) e = __builtin_amdgcn_frexp_expf(m);
     else e = __builtin_amdgcn_frexp_exp(m);
@@ -298,11 +296,11 @@ __device__ __forceinline__ R weno5_grad(R v1, R v2, R v3, R v4, R v5, R (&g)[5])
     const R s4b = tb2 + ub2 - o2 * (R)(1.0 / 6.0);
     const R ej = epsb * (R)8e-6 * aJ;
     const bool ok = m > (R)0;
-    g[0] = ok ? -s1b + (j0 ? ej : (R)0) : (R)0;
-    g[1] = ok ? s1b - s2b + (j1 ? ej : (R)0) : (R)0;
-    g[2] = ok ? (R)1 + s2b - s3b + (j2 ? ej : (R)0) : (R)0;
-    g[3] = ok ? s3b - s4b + (j3 ? ej : (R)0) : (R)0;
-    g[4] = ok ? s4b + (j4 ? ej : (R)0) : (R)0;
+    g[0] = ok ? -s1b + (J == 0 ? ej : (R)0) : (R)0;
+    g[1] = ok ? s1b - s2b + (J == 1 ? ej : (R)0) : (R)0;
+    g[2] = ok ? (R)1 + s2b - s3b + (J == 2 ? ej : (R)0) : (R)0;
+    g[3] = ok ? s3b - s4b + (J == 3 ? ej : (R)0) : (R)0;
+    g[4] = ok ? s4b + (J == 4 ? ej : (R)0) : (R)0;
     if constexpr (F) return ok ? __builtin_amdgcn_ldexpf(W, e) : (R)0;
     else return ok ? __builtin_amdgcn_ldexp(W, e) : (R)0;
 }
