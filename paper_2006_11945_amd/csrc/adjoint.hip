@@ -332,20 +332,6 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
         R nm0, nvx, nvz, nvt;
         double nm1;
         own_mu_v(xs + 1, nm0, nm1, nvx, nvz, nvt);
-        // this step's halo mu and V, then the next core slice's values and halo
-        // mu and V (a whole step of cover)
-        R chm0[NHI], chvel[NHI];
-        double chm1[NHI];
-#pragma unroll
-        for (int r = 0; r < NHI; ++r) {
-            chm0[r] = hm0[r];
-            chm1[r] = hm1[r];
-            chvel[r] = hvel[r];
-        }
-        if (xs + 1 >= x0 && xs + 1 < x1) {
-            load_values(xs + 1);
-            load_halo(xs + 1);
-        }
         const unsigned xo = (unsigned)(min(max(xs, 0), g.nx - 1) * g.nz);
         const unsigned cR = (kb + xo + (unsigned)izc) * ES;
         // loads consumed later in the step: the output target's lambda and
@@ -442,8 +428,8 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
                     hcell(h, tl, zl, real, hc);
                     const bool zaxis = h >= 6 * TZ;
                     R wh;  // a halo source's V term belongs to another tile
-                    if (__any(chm0[r] != (R)0 || chm1[r] != 0.0))
-                        row(tl, zl, zaxis, chvel[r], chm0[r], chm1[r], tzi * TZ + zl, wh);
+                    if (__any(hm0[r] != (R)0 || hm1[r] != 0.0))
+                        row(tl, zl, zaxis, hvel[r], hm0[r], hm1[r], tzi * TZ + zl, wh);
                     else zero_row(tl, zl, zaxis);
                 }
             }
@@ -512,6 +498,10 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
         cvx = nvx;
         cvz = nvz;
         cvt = nvt;
+        if (xs + 1 >= x0 && xs + 1 < x1) {  // the next core slice
+            load_values(xs + 1);
+            load_halo(xs + 1);
+        }
 
     }
 }
