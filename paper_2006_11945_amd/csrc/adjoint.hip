@@ -17,6 +17,7 @@
 // (weights m + 1 and -m), theta wraps.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdlib.h>
 
 #include <algorithm>
 
@@ -775,9 +776,14 @@ hipError_t adj_stage_t(AdjStageArgs a, int stage, hipStream_t s) {
     const void* k = stage == 0 ? (const void*)k_adj_stage<R, 0, TK>
                   : stage == 1 ? (const void*)k_adj_stage<R, 1, TK> : (const void*)k_adj_stage<R, 2, TK>;
     const long long W = (long long)a.ntz * a.ntk * a.g.nx;
-    long long G = resident_blocks(k, 64 * TK);
+    // one round of resident blocks, each with at least 16 target steps
+    // (EGB_ADJ_GRID=<blocks> overrides: tuning sweeps, segmentation tests)
+    const char* fe = getenv("EGB_ADJ_GRID");
+    const int forced = fe ? atoi(fe) : 0;
+    long long G = forced > 0 ? forced : resident_blocks(k, 64 * TK);
     if (G <= 0) return hipErrorInvalidDeviceFunction;
-    G = std::max(1LL, std::min(G, W / 16));
+    if (forced <= 0) G = std::min(G, W / 16);
+    G = std::max(1LL, std::min(G, W));
     const dim3 grid((unsigned)G), block(TZ, TK);
     switch (stage) {
         case 0: k_adj_stage<R, 0, TK><<<grid, block, 0, s>>>(a); break;

@@ -443,11 +443,9 @@ hipError_t launch_stage_t(const StageArgs& a, int stage, hipStream_t s) {
     const void* k = stage == 0 ? (const void*)k_stage<R, 0, TK, KIN>
                   : stage == 1 ? (const void*)k_stage<R, 1, TK, KIN> : (const void*)k_stage<R, 2, TK, KIN>;
     // one round of resident blocks, each with at least MIN_STEPS x steps
-    // (EGB_STAGE_GRID overrides, for tuning sweeps)
-    static const int forced = [] {
-        const char* e = getenv("EGB_STAGE_GRID");
-        return e ? atoi(e) : 0;
-    }();
+    // (EGB_STAGE_GRID=<blocks> overrides: tuning sweeps, segmentation tests)
+    const char* fe = getenv("EGB_STAGE_GRID");
+    const int forced = fe ? atoi(fe) : 0;
     const long long W = (long long)t.ntz * t.ntk * a.g.nx;
     long long G = forced > 0 ? forced : resident_blocks(k, 64 * TK);
     if (G <= 0) return hipErrorInvalidDeviceFunction;
