@@ -144,6 +144,10 @@ def adjoint_vs_forward(nsrc, nsteps, n=256):
             "backward_cell_updates_per_s": cu / t_bwd, "backward_over_plain_forward": t_bwd / t_plain}
 
 
+# sources the stage kernel is built from (the traffic record names their hash)
+STAGE_SOURCES = ("liouville.hip", "stage_common.h", "egb_device.h")
+
+
 def measured_traffic(n):
     """HBM bytes per stage launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE runs, only while the kernel sources are unchanged since."""
@@ -154,7 +158,7 @@ def measured_traffic(n):
         return None
     rec = json.load(open(path))
     csrc = os.path.join(ROOT, "paper_2006_11945_amd", "csrc")
-    src = open(os.path.join(csrc, "liouville.hip"), "rb").read() + open(os.path.join(csrc, "egb_device.h"), "rb").read()
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in STAGE_SOURCES)
     return rec["hbm_bytes_per_launch"] if hashlib.sha256(src).hexdigest() == rec["source_sha256"] else None
 
 
