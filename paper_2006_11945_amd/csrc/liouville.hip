@@ -347,11 +347,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
                 bstore(ball ? p0 : accp, rUo, c8, PSI);
             }
         }
-        // shift the queue
-        const bool xin = x + 4 < g.nx;
+        // shift the queue (past nx the entry continues the line; block-uniform)
+        if (x + 4 >= g.nx) {
 #pragma unroll
-        for (int f = 0; f < NP; ++f) qn[f] = xin ? qn[f] : (R)2 * q[f][6] - q[f][5];
-        qpn = xin ? qpn : 2.0 * qp[6] - qp[5];
+            for (int f = 0; f < NP; ++f) qn[f] = (R)2 * q[f][6] - q[f][5];
+            qpn = 2.0 * qp[6] - qp[5];
+        }
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
 #pragma unroll
@@ -549,7 +550,7 @@ bool stage_fits_32bit(const GridArgs& g, int dtype) {
 hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s, bool kinematic) {
     if (dtype == EGB_F64)
         return kinematic ? launch_stage_t<double, 8, true>(a, stage, s) : launch_stage_t<double, 8, false>(a, stage, s);
-    return kinematic ? launch_stage_t<float, 12, true>(a, stage, s) : launch_stage_t<float, 12, false>(a, stage, s);
+    return kinematic ? launch_stage_t<float, 16, true>(a, stage, s) : launch_stage_t<float, 12, false>(a, stage, s);
 }
 
 }  // namespace egb
