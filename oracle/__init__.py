@@ -21,6 +21,7 @@ SRC = os.path.join(HERE, "egb_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 PLANES = ("phi1", "psi", "ReC", "ImC", "ReB", "ImB")
+PAR_PLANES = ("X", "vt", "tau", "ReC", "ImC", "ReB", "ImB")  # paraxial depth march
 VEL_PLANES = ("Vx", "Vz", "Vt", "A11", "A12", "A21", "A22")
 NFLD, NTAY = 5, 6
 
@@ -54,9 +55,13 @@ def lib():
         L.oc_velocity.argtypes = [i, i, i, d, d, P, P, P, P]
         L.oc_init_state.argtypes = [i, i, i, d, d, d, d, P, d, d, d, P]
         L.oc_weno.argtypes = [P, i]; L.oc_weno.restype = d
-        L.oc_march.argtypes = [i, i, i, d, d, d, d, P, d, d, d, P, d, i]
+        L.oc_march.argtypes = [i, i, i, d, d, d, d, P, d, d, d, P, P, d, i]
         L.oc_beam_sum.argtypes = [i, i, i, d, d, d, d, P, P, d, P, P, i, P]
         L.oc_pick.argtypes = [i, i, i, d, d, d, d, P, P, i, P]
+        L.oc_pvelocity.argtypes = [i, i, i, d, d, d, P, P, P]
+        L.oc_pinit.argtypes = [i, i, d, d, d, P, d, P]
+        L.oc_pmarch.argtypes = [i, i, i, d, d, d, P, i, P]
+        L.oc_ppick.argtypes = [i, i, i, P, P, i, P]
         _lib = L
     return _lib
 
@@ -128,10 +133,13 @@ def weno(u7, minus: bool) -> float:
     return lib().oc_weno(_p(u7), int(bool(minus)))
 
 
-def march(grid, vel: np.ndarray, source, U: np.ndarray, dt: float, nsteps: int) -> np.ndarray:
+def march(grid, vel: np.ndarray, source, U: np.ndarray, dt: float, nsteps: int, Ub=None) -> np.ndarray:
+    """nsteps SSP-RK3 steps from U.  Ub: the point-source data (boundary
+    values outside the grid and in the ball); U itself when None."""
     U = _c(U).copy()
+    Ub = U.copy() if Ub is None else _c(Ub)
     rc = lib().oc_march(grid.nx, grid.nz, grid.nth, grid.x0, grid.z0, grid.dx, grid.dz, _p(_c(vel)),
-                        source.xs, source.zs, source.r0, _p(U), float(dt), int(nsteps))
+                        source.xs, source.zs, source.r0, _p(Ub), _p(U), float(dt), int(nsteps))
     if rc != 0:
         raise MemoryError("oc_march")
     return U
@@ -167,3 +175,63 @@ def solve(problem, nsteps=None, dt=None):
     ns = problem.nsteps if nsteps is None else nsteps
     U = march(g, vel, problem.source, U0, dt, ns) if ns > 0 else U0
     return {"tab": tab, "vel": vel, "vaux": vaux, "dt": dt, "dt_cfl": dt_cfl, "U0": U0, "U": U, "nsteps": ns}
+
+
+# ---------------------------------------------------------------- paraxial
+# Depth march on (x, theta) slices, theta in (-theta_max, theta_max); see the
+# paraxial section of egb_oracle.c.  Arrays: pvel[nz][7][nth][nx],
+# states [nz][7][nth][nx] (planes PAR_PLANES), T[source][nz][nx].
+
+def ptheta(grid, theta_max: float) -> np.ndarray:
+    dth = 2.0 * theta_max / grid.nth
+    return -theta_max + (np.arange(grid.nth) + 0.5) * dth
+
+
+def pvelocity(grid, tab: np.ndarray, theta_max: float):
+    """(pvel, rate) with rate = max(|u|/dx + |w|/dtheta); raises if V_z <= 0."""
+    pvel = np.zeros((grid.nz, 7, grid.nth, grid.nx))
+    rate = np.zeros(1)
+    rc = lib().oc_pvelocity(grid.nx, grid.nz, grid.nth, grid.dx, grid.dz, float(theta_max), _p(_c(tab)),
+                            _p(pvel), _p(rate))
+    if rc != 0:
+        raise ValueError("paraxial velocity: V_z <= 0 inside (-theta_max, theta_max)")
+    return pvel, float(rate[0])
+
+
+def psubsteps(grid, rate: float, cfl: float = 0.5) -> int:
+    """SSP-RK3 steps per depth interval dz: dz / nsub * rate <= cfl."""
+    return max(1, int(np.ceil(grid.dz * rate / cfl - 1e-12)))
+
+
+def pinit(grid, pvel: np.ndarray, theta_max: float, beta: float) -> np.ndarray:
+    U = np.zeros((7, grid.nth, grid.nx))
+    lib().oc_pinit(grid.nx, grid.nth, grid.x0, grid.dx, float(theta_max), _p(_c(pvel[0, 0])), float(beta), _p(U))
+    return U
+
+
+def pmarch(grid, pvel: np.ndarray, theta_max: float, U0: np.ndarray, nsub: int) -> np.ndarray:
+    Uall = np.zeros((grid.nz, 7, grid.nth, grid.nx))
+    Uall[0] = U0
+    rc = lib().oc_pmarch(grid.nx, grid.nz, grid.nth, grid.dx, grid.dz, float(theta_max), _p(_c(pvel)), int(nsub),
+                         _p(Uall))
+    if rc != 0:
+        raise MemoryError("oc_pmarch")
+    return Uall
+
+
+def ppick(grid, Uall: np.ndarray, xs) -> np.ndarray:
+    xs = _c(np.atleast_1d(xs))
+    T = np.zeros((len(xs), grid.nz, grid.nx))
+    lib().oc_ppick(grid.nx, grid.nz, grid.nth, _p(_c(Uall)), _p(xs), len(xs), _p(T))
+    return T
+
+
+def psolve(grid, medium, theta_max: float, beta: float, xs=(), cfl: float = 0.5):
+    """Table, paraxial velocity, surface data, depth march, picks."""
+    tab = medium_table(grid, medium)
+    pvel, rate = pvelocity(grid, tab, theta_max)
+    nsub = psubsteps(grid, rate, cfl)
+    U0 = pinit(grid, pvel, theta_max, beta)
+    Uall = pmarch(grid, pvel, theta_max, U0, nsub)
+    T = ppick(grid, Uall, xs) if len(np.atleast_1d(xs)) else None
+    return {"tab": tab, "pvel": pvel, "rate": rate, "nsub": nsub, "U": Uall, "T": T}

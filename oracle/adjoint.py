@@ -153,11 +153,14 @@ def weno(u7, minus):
     dm = [u7[m + 1] - u7[m] for m in range(5)]          # D- differences v1..v5
     dp = [u7[6 - m] - u7[5 - m] for m in range(5)]      # D+ differences v1..v5
     v = [torch.where(minus, a, b) for a, b in zip(dm, dp)]
-    mx = torch.stack([x * x for x in v]).amax(0)
-    ok = mx > 0
-    safe = [torch.where(ok, x, torch.ones_like(x)) for x in v]
-    v1, v2, v3, v4, v5 = safe
-    mxs = torch.where(ok, mx, torch.ones_like(mx))
+    # evaluated on v / max|v| and scaled back (W is 1-homogeneous): the same
+    # value without overflow of 1 / (e + s)^2 for tiny differences
+    am = torch.stack([x.abs() for x in v]).amax(0)
+    ok = am > 0
+    ams = torch.where(ok, am, torch.ones_like(am))
+    v = [torch.where(ok, x / ams, torch.ones_like(x)) for x in v]
+    v1, v2, v3, v4, v5 = v
+    mxs = torch.stack([x * x for x in v]).amax(0)
     q0 = v1 / 3 - 7 * v2 / 6 + 11 * v3 / 6
     q1 = -v2 / 6 + 5 * v3 / 6 + v4 / 3
     q2 = v3 / 3 + 5 * v4 / 6 - v5 / 6
@@ -166,15 +169,16 @@ def weno(u7, minus):
     s2 = 13 / 12 * (v3 - 2 * v4 + v5) ** 2 + 0.25 * (3 * v3 - 4 * v4 + v5) ** 2
     e = 1e-6 * mxs
     a0, a1, a2 = 0.1 / (e + s0) ** 2, 0.6 / (e + s1) ** 2, 0.3 / (e + s2) ** 2
-    w = (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2)
+    w = ams * ((a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2))
     return torch.where(ok, w, torch.zeros_like(w))
 
 
-def _stencil_xz(u, axis):
-    """[7, ...] values at offsets -3..3 along axis 1 (x) or 2 (z) with linear
-    extrapolation ghosts u_{-m} = (m+1) u_0 - m u_1."""
+def _stencil_xz(u, b, axis):
+    """[7, ...] values at offsets -3..3 along axis 1 (x) or 2 (z); ghosts are
+    the point-source data b of the plane extended by linear extrapolation
+    b_{-m} = (m+1) b_0 - m b_1 (fixed in time)."""
     n = u.shape[axis]
-    sl = lambda i: u.narrow(axis, i, 1)
+    sl = lambda i: b.narrow(axis, i, 1)
     lo = [(m + 1) * sl(0) - m * sl(1) for m in (3, 2, 1)]
     hi = [(m + 1) * sl(n - 1) - m * sl(n - 2) for m in (1, 2, 3)]
     ext = torch.cat(lo + [u] + hi, dim=axis)
@@ -185,19 +189,22 @@ def _stencil_t(u):
     return torch.stack([torch.roll(u, -o, dims=0) for o in range(-3, 4)])
 
 
-def rhs(phi, psi, V, g):
+def rhs(phi, psi, V, g, bc):
     Vx, Vz, Vt = V
     cx, cz, ct = Vx / g.dx, Vz / g.dz, Vt / g.dth
     out = []
-    for u in (phi, psi):
-        L = -(cx * weno(_stencil_xz(u, 1), cx >= 0) + cz * weno(_stencil_xz(u, 2), cz >= 0)
+    for u, b in zip((phi, psi), bc):
+        L = -(cx * weno(_stencil_xz(u, b, 1), cx >= 0) + cz * weno(_stencil_xz(u, b, 2), cz >= 0)
               + ct * weno(_stencil_t(u), ct >= 0))
         out.append(L)
     out[1] = out[1] + 1.0
     return out
 
 
-def march(phi, psi, V, g, src, dt, nsteps):
+def march(phi, psi, V, g, src, dt, nsteps, bc=None):
+    """bc: the point-source data (phi1, psi) that the ghosts extend; the
+    starting state when None."""
+    bc = (phi, psi) if bc is None else bc
     X = torch.as_tensor(g.xc() - src.xs, dtype=T)[:, None]
     Z = torch.as_tensor(g.zc() - src.zs, dtype=T)[None, :]
     ball = (X * X + Z * Z <= src.r0 ** 2)[None, :, :]
@@ -206,7 +213,7 @@ def march(phi, psi, V, g, src, dt, nsteps):
         u0 = (phi, psi)
         ui = u0
         for st in range(3):
-            L = rhs(ui[0], ui[1], V, g)
+            L = rhs(ui[0], ui[1], V, g, bc)
             new = []
             for f in range(2):
                 y = ca[st] * u0[f] + cb[st] * (ui[f] + dt * L[f])

@@ -378,10 +378,17 @@ double oc_weno(const double *u, int minus)
     double v[5];
     for (int m = 0; m < 5; ++m)
         v[m] = minus ? u[m + 1] - u[m] : u[6 - m] - u[5 - m];
+    /* W is positively 1-homogeneous in v (eps scales with max v^2), so it is
+     * evaluated on v / max|v| and scaled back: the textbook formula as
+     * written, without overflow of 1 / (eps + beta)^2 for tiny differences */
+    double am = 0.0;
+    for (int m = 0; m < 5; ++m)
+        if (fabs(v[m]) > am) am = fabs(v[m]);
+    if (am == 0.0) return 0.0;
+    for (int m = 0; m < 5; ++m) v[m] /= am;
     double mx = 0.0;
     for (int m = 0; m < 5; ++m)
         if (v[m] * v[m] > mx) mx = v[m] * v[m];
-    if (mx == 0.0) return 0.0;
     double q0 = v[0] / 3.0 - 7.0 * v[1] / 6.0 + 11.0 * v[2] / 6.0;
     double q1 = -v[1] / 6.0 + 5.0 * v[2] / 6.0 + v[3] / 3.0;
     double q2 = v[2] / 3.0 + 5.0 * v[3] / 6.0 - v[4] / 6.0;
@@ -390,29 +397,31 @@ double oc_weno(const double *u, int minus)
     double s2 = 13.0 / 12.0 * pow(v[2] - 2.0 * v[3] + v[4], 2) + 0.25 * pow(3.0 * v[2] - 4.0 * v[3] + v[4], 2);
     double e = 1e-6 * mx;
     double a0 = 0.1 / pow(e + s0, 2), a1 = 0.6 / pow(e + s1, 2), a2 = 0.3 / pow(e + s2, 2);
-    return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+    return am * ((a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2));
 }
 
-/* Value of plane u at (k, ix + m, iz) / (k, ix, iz + m) / (k + m, ix, iz)
- * with ghosts: x and z by linear extrapolation u_{-m} = (m+1) u_0 - m u_1,
- * theta periodic.                                                          */
-static double at_x(const double *u, int nx, int nz, long base_k, int ix, int iz, int m)
+/* Value of plane u at (k, ix + m, iz) / (k, ix, iz + m) with ghosts: outside
+ * the grid in x or z the point-source data b of the same plane, extended by
+ * linear extrapolation b_{-m} = (m+1) b_0 - m b_1 (exact for that data, which
+ * is affine in position per theta): a Dirichlet condition fixed in time, like
+ * the source ball.  theta is periodic.                                      */
+static double at_x(const double *u, const double *b, int nx, int nz, long base_k, int ix, int iz, int m)
 {
     int i = ix + m;
-    if (i < 0) return (1 - i) * u[base_k + (long)0 * nz + iz] + i * u[base_k + (long)1 * nz + iz];
+    if (i < 0) return (1 - i) * b[base_k + (long)0 * nz + iz] + i * b[base_k + (long)1 * nz + iz];
     if (i > nx - 1) {
         int e = i - (nx - 1);
-        return (e + 1) * u[base_k + (long)(nx - 1) * nz + iz] - e * u[base_k + (long)(nx - 2) * nz + iz];
+        return (e + 1) * b[base_k + (long)(nx - 1) * nz + iz] - e * b[base_k + (long)(nx - 2) * nz + iz];
     }
     return u[base_k + (long)i * nz + iz];
 }
-static double at_z(const double *u, int nz, long base_kx, int iz, int m)
+static double at_z(const double *u, const double *b, int nz, long base_kx, int iz, int m)
 {
     int j = iz + m;
-    if (j < 0) return (1 - j) * u[base_kx] + j * u[base_kx + 1];
+    if (j < 0) return (1 - j) * b[base_kx] + j * b[base_kx + 1];
     if (j > nz - 1) {
         int e = j - (nz - 1);
-        return (e + 1) * u[base_kx + nz - 1] - e * u[base_kx + nz - 2];
+        return (e + 1) * b[base_kx + nz - 1] - e * b[base_kx + nz - 2];
     }
     return u[base_kx + j];
 }
@@ -423,7 +432,7 @@ static double at_z(const double *u, int nz, long base_kx, int iz, int m)
  * Upwinding: D- where the velocity component is >= 0... precisely D- when
  * V_d > 0 or V_d == 0, D+ when V_d < 0.                                    */
 static void rhs(int nx, int nz, int nth, double dx, double dz, const double *vel, const double *U,
-                double *L)
+                const double *Ub, double *L)
 {
     long n = (long)nth * nx * nz, nxz = (long)nx * nz;
     double dth = 2.0 * M_PI / nth;
@@ -435,11 +444,11 @@ static void rhs(int nx, int nz, int nth, double dx, double dz, const double *vel
                 double cx = vel[0 * n + c] / dx, cz = vel[1 * n + c] / dz, ct = vel[2 * n + c] / dth;
                 double Lf[NSTATE];
                 for (int f = 0; f < NSTATE; ++f) {
-                    const double *u = U + f * n;
+                    const double *u = U + f * n, *ub = Ub + f * n;
                     double w[7];
-                    for (int m = -3; m <= 3; ++m) w[m + 3] = at_x(u, nx, nz, (long)k * nxz, ix, iz, m);
+                    for (int m = -3; m <= 3; ++m) w[m + 3] = at_x(u, ub, nx, nz, (long)k * nxz, ix, iz, m);
                     double Dx = oc_weno(w, cx >= 0.0);
-                    for (int m = -3; m <= 3; ++m) w[m + 3] = at_z(u, nz, (long)k * nxz + (long)ix * nz, iz, m);
+                    for (int m = -3; m <= 3; ++m) w[m + 3] = at_z(u, ub, nz, (long)k * nxz + (long)ix * nz, iz, m);
                     double Dz = oc_weno(w, cz >= 0.0);
                     for (int m = -3; m <= 3; ++m) {
                         int kk = ((k + m) % nth + nth) % nth;
@@ -470,7 +479,7 @@ static int in_ball(double x0, double z0, double dx, double dz, int ix, int iz, d
  *   U  = 1/3 U + 2/3 (U2 + dt L(U2)),
  * ball cells copying U after every stage (Dirichlet point-source data).   */
 int oc_march(int nx, int nz, int nth, double x0, double z0, double dx, double dz, const double *vel,
-             double xs, double zs, double r0, double *U, double dt, int nsteps)
+             double xs, double zs, double r0, const double *Ub, double *U, double dt, int nsteps)
 {
     long n = (long)nth * nx * nz, nxz = (long)nx * nz;
     double *U1 = (double *)malloc(sizeof(double) * n * NSTATE);
@@ -485,7 +494,7 @@ int oc_march(int nx, int nz, int nth, double x0, double z0, double dx, double dz
         const double *in[3] = {U, U1, U2};
         double *out[3] = {U1, U2, U};
         for (int st = 0; st < 3; ++st) {
-            rhs(nx, nz, nth, dx, dz, vel, in[st], L);
+            rhs(nx, nz, nth, dx, dz, vel, in[st], Ub, L);
 #pragma omp parallel for schedule(static)
             for (long c = 0; c < n; ++c) {
                 int b = ball[c % nxz];
@@ -542,11 +551,11 @@ int oc_beam_sum(int nx, int nz, int nth, double x0, double z0, double dx, double
                 double psi = U[S_PSI * n + c];
                 if (!(psi > 0.0)) continue;
                 /* 4th-order central differences of phi1 (ghost rules as in the march) */
-                double fx = (at_x(phi, nx, nz, kb, ix, iz, -2) - 8.0 * at_x(phi, nx, nz, kb, ix, iz, -1) +
-                             8.0 * at_x(phi, nx, nz, kb, ix, iz, 1) - at_x(phi, nx, nz, kb, ix, iz, 2)) / (12.0 * dx);
+                double fx = (at_x(phi, phi, nx, nz, kb, ix, iz, -2) - 8.0 * at_x(phi, phi, nx, nz, kb, ix, iz, -1) +
+                             8.0 * at_x(phi, phi, nx, nz, kb, ix, iz, 1) - at_x(phi, phi, nx, nz, kb, ix, iz, 2)) / (12.0 * dx);
                 long kx = kb + (long)ix * nz;
-                double fz = (at_z(phi, nz, kx, iz, -2) - 8.0 * at_z(phi, nz, kx, iz, -1) + 8.0 * at_z(phi, nz, kx, iz, 1) -
-                             at_z(phi, nz, kx, iz, 2)) / (12.0 * dz);
+                double fz = (at_z(phi, phi, nz, kx, iz, -2) - 8.0 * at_z(phi, phi, nz, kx, iz, -1) + 8.0 * at_z(phi, phi, nz, kx, iz, 1) -
+                             at_z(phi, phi, nz, kx, iz, 2)) / (12.0 * dz);
                 int km2 = (k + nth - 2) % nth, km1 = (k + nth - 1) % nth, kp1 = (k + 1) % nth, kp2 = (k + 2) % nth;
                 long o = (long)ix * nz + iz;
                 double ft = (phi[km2 * nxz + o] - 8.0 * phi[km1 * nxz + o] + 8.0 * phi[kp1 * nxz + o] - phi[kp2 * nxz + o]) /
@@ -668,5 +677,190 @@ int oc_pick(int nx, int nz, int nth, double x0, double z0, double dx, double dz,
         }
         tout[r] = best;
     }
+    return 0;
+}
+
+/* ======================================================================== */
+/* Paraxial depth march (section 3 eqs. 13-15, section 4 eqs. 16-24, the
+ * level set of eq. 35).
+ *
+ * Depth z is the evolution variable and the phase space is (x, theta), with
+ * theta restricted to (-theta_max, theta_max) where rays go down (eq. 13).
+ * With the stationary Liouville velocity V = d(x, z, theta)/dtau (eqs. 7-12):
+ *   u = dx/dz = V_x / V_z,   w = dtheta/dz = V_theta / V_z   (eqs. 14, 15, 17, 18)
+ * and every field U of (X, vartheta, tau, C, B) obeys
+ *   U_z + u U_x + w U_theta = S                                (eqs. 16, 19, 21)
+ *   S_X = S_vartheta = 0,  S_tau = 1 / V_z  (= p . dx/dz of eq. 19, since p . V = 1),
+ *   S_(C,B) = (A / V_z) (C, B)  (the ray-normal dynamic ray tracing of the
+ *                                 stationary system, per unit depth)
+ * with data on the first depth row (eqs. 20, 24):
+ *   X = x, vartheta = theta, tau = 0, C = cos(theta) + sin(theta) u = v / V_z,
+ *   B = i beta C.
+ * Grid: x_i = x0 + (i + 1/2) dx, z_n = z0 + (n + 1/2) dz,
+ *       theta_k = -theta_max + (k + 1/2) dtheta, dtheta = 2 theta_max / nth.
+ * Plane order of the oracle state: X, vartheta, tau, Re C, Im C, Re B, Im B.
+ * Velocity table pvel[n][7][k][i]: u, w, 1/V_z, A11/V_z, A12/V_z, A21/V_z, A22/V_z.
+ */
+#define P_X 0
+#define P_VT 1
+#define P_TAU 2
+#define P_RC 3
+#define P_IC 4
+#define P_RB 5
+#define P_IB 6
+#define NPAR 7
+
+int oc_pvelocity(int nx, int nz, int nth, double dx, double dz, double theta_max, const double *tab,
+                 double *pvel, double *rate_out)
+{
+    (void)dz;
+    double dth = 2.0 * theta_max / nth;
+    long plane = (long)nth * nx;
+    double rate = 0.0;
+    int bad = 0;
+#pragma omp parallel for reduction(max : rate) reduction(| : bad) schedule(static)
+    for (int n = 0; n < nz; ++n)
+        for (int k = 0; k < nth; ++k) {
+            double th = -theta_max + (k + 0.5) * dth;
+            for (int i = 0; i < nx; ++i) {
+                long c2 = (long)i * nz + n;
+                double vj[10], V[3], A[4];
+                vjet_flat(phase_velocity_jet(tab + c2 * NFLD * NTAY, th), vj);
+                oc_va(vj, th, V, A);
+                if (!(V[1] > 0.0)) {
+                    bad = 1;
+                    continue;
+                }
+                double *o = pvel + (long)n * 7 * plane + (long)k * nx + i;
+                o[0] = V[0] / V[1];
+                o[plane] = V[2] / V[1];
+                o[2 * plane] = 1.0 / V[1];
+                for (int q = 0; q < 4; ++q) o[(3 + q) * plane] = A[q] / V[1];
+                double r = fabs(o[0]) / dx + fabs(o[plane]) / dth;
+                if (r > rate) rate = r;
+            }
+        }
+    *rate_out = rate; /* max (|u| / dx + |w| / dtheta) over the table */
+    return bad ? -1 : 0;
+}
+
+int oc_pinit(int nx, int nth, double x0, double dx, double theta_max, const double *pvel0, double beta, double *U)
+{
+    double dth = 2.0 * theta_max / nth;
+    long plane = (long)nth * nx;
+    for (int k = 0; k < nth; ++k) {
+        double th = -theta_max + (k + 0.5) * dth;
+        for (int i = 0; i < nx; ++i) {
+            long c = (long)k * nx + i;
+            double c0 = cos(th) + sin(th) * pvel0[c];
+            U[P_X * plane + c] = x0 + (i + 0.5) * dx;
+            U[P_VT * plane + c] = th;
+            U[P_TAU * plane + c] = 0.0;
+            U[P_RC * plane + c] = c0;
+            U[P_IC * plane + c] = 0.0;
+            U[P_RB * plane + c] = 0.0;
+            U[P_IB * plane + c] = beta * c0;
+        }
+    }
+    return 0;
+}
+
+/* value of a line of n values (stride st) at index idx, ghosts by linear
+ * extrapolation u_{-m} = (m+1) u_0 - m u_1 at either end */
+static double pline(const double *u, long st, int n, int idx)
+{
+    if (idx < 0) return (1 - idx) * u[0] + idx * u[st];
+    if (idx > n - 1) {
+        int e = idx - (n - 1);
+        return (e + 1) * u[(long)(n - 1) * st] - e * u[(long)(n - 2) * st];
+    }
+    return u[(long)idx * st];
+}
+
+/* L = -(u D_x U + w D_theta U) + S at fractional depth s of the level
+ * interval (velocity table (1 - s) pv0 + s pv1); WENO5 upwind on both axes,
+ * D- where the coefficient is >= 0. */
+static void prhs(int nx, int nth, double dx, double dth, const double *pv0, const double *pv1, double s,
+                 const double *U, double *L)
+{
+    long plane = (long)nth * nx;
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nth; ++k)
+        for (int i = 0; i < nx; ++i) {
+            long c = (long)k * nx + i;
+            double cv[7];
+            for (int q = 0; q < 7; ++q) cv[q] = (1.0 - s) * pv0[q * plane + c] + s * pv1[q * plane + c];
+            double cx = cv[0] / dx, ct = cv[1] / dth;
+            double Lf[NPAR];
+            for (int f = 0; f < NPAR; ++f) {
+                const double *u = U + f * plane;
+                double w7[7];
+                for (int m = -3; m <= 3; ++m) w7[m + 3] = pline(u + (long)k * nx, 1, nx, i + m);
+                double Dx = oc_weno(w7, cx >= 0.0);
+                for (int m = -3; m <= 3; ++m) w7[m + 3] = pline(u + i, nx, nth, k + m);
+                double Dt = oc_weno(w7, ct >= 0.0);
+                Lf[f] = -(cx * Dx + ct * Dt);
+            }
+            Lf[P_TAU] += cv[2];
+            Lf[P_RC] += cv[3] * U[P_RC * plane + c] + cv[4] * U[P_RB * plane + c];
+            Lf[P_RB] += cv[5] * U[P_RC * plane + c] + cv[6] * U[P_RB * plane + c];
+            Lf[P_IC] += cv[3] * U[P_IC * plane + c] + cv[4] * U[P_IB * plane + c];
+            Lf[P_IB] += cv[5] * U[P_IC * plane + c] + cv[6] * U[P_IB * plane + c];
+            for (int f = 0; f < NPAR; ++f) L[f * plane + c] = Lf[f];
+        }
+}
+
+/* March from level 0 (Uall[0] holds the data) to level nz - 1: each level
+ * interval dz is nsub SSP-RK3 steps of dz / nsub, stage depths s, s + h,
+ * s + h / 2 (h = 1 / nsub).  Every level is kept: Uall[n][7][k][i]. */
+int oc_pmarch(int nx, int nz, int nth, double dx, double dz, double theta_max, const double *pvel, int nsub,
+              double *Uall)
+{
+    double dth = 2.0 * theta_max / nth, h = 1.0 / nsub, dl = dz * h;
+    long plane = (long)nth * nx, lev = NPAR * plane;
+    double *U = (double *)malloc(sizeof(double) * lev), *U1 = (double *)malloc(sizeof(double) * lev);
+    double *U2 = (double *)malloc(sizeof(double) * lev), *L = (double *)malloc(sizeof(double) * lev);
+    if (!U || !U1 || !U2 || !L) { free(U); free(U1); free(U2); free(L); return -2; }
+    memcpy(U, Uall, sizeof(double) * lev);
+    for (int n = 0; n + 1 < nz; ++n) {
+        const double *pv0 = pvel + (long)n * 7 * plane, *pv1 = pv0 + 7 * plane;
+        for (int j = 0; j < nsub; ++j) {
+            double s = j * h;
+            prhs(nx, nth, dx, dth, pv0, pv1, s, U, L);
+            for (long q = 0; q < lev; ++q) U1[q] = U[q] + dl * L[q];
+            prhs(nx, nth, dx, dth, pv0, pv1, s + h, U1, L);
+            for (long q = 0; q < lev; ++q) U2[q] = 0.75 * U[q] + 0.25 * (U1[q] + dl * L[q]);
+            prhs(nx, nth, dx, dth, pv0, pv1, s + 0.5 * h, U2, L);
+            for (long q = 0; q < lev; ++q) U[q] = U[q] / 3.0 + 2.0 / 3.0 * (U2[q] + dl * L[q]);
+        }
+        memcpy(Uall + (long)(n + 1) * lev, U, sizeof(double) * lev);
+    }
+    free(U); free(U1); free(U2); free(L);
+    return 0;
+}
+
+/* First arrival at every (x_i, z_n) from a source at x = xs on the first
+ * depth row: roots in theta of X(z_n, x_i, .) - xs between adjacent theta
+ * nodes (eq. 35's Gamma = {X = x_s}; linear interpolation of X and tau), the
+ * smallest tau > 0 among them; NaN where there is none.  T[s][n][i]. */
+int oc_ppick(int nx, int nz, int nth, const double *Uall, const double *xs, int nsrc, double *T)
+{
+    long plane = (long)nth * nx, lev = NPAR * plane;
+#pragma omp parallel for schedule(static)
+    for (int n = 0; n < nz; ++n)
+        for (int s = 0; s < nsrc; ++s)
+            for (int i = 0; i < nx; ++i) {
+                const double *X = Uall + (long)n * lev + P_X * plane + i;
+                const double *tau = Uall + (long)n * lev + P_TAU * plane + i;
+                double best = NAN;
+                for (int k = 0; k + 1 < nth; ++k) {
+                    double f0 = X[(long)k * nx] - xs[s], f1 = X[(long)(k + 1) * nx] - xs[s];
+                    if (!(f0 == 0.0 || f0 * f1 < 0.0)) continue;
+                    double t = f0 / (f0 - f1);
+                    double v = tau[(long)k * nx] + t * (tau[(long)(k + 1) * nx] - tau[(long)k * nx]);
+                    if (v > 0.0 && (isnan(best) || v < best)) best = v;
+                }
+                T[((long)s * nz + n) * nx + i] = best;
+            }
     return 0;
 }

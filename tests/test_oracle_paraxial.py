@@ -1,0 +1,63 @@
+"""Pins of the paraxial depth-march oracle (section 3 eqs. 13-15, section 4
+eqs. 16-24, the level set X = x_s of eq. 35) against closed forms."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import closed_forms as CF
+
+TMAX = np.pi / 3
+
+
+def test_homogeneous_isotropic_is_exact():
+    # straight rays: X = x - tan(theta) dz, tau = dz / (v cos theta); the
+    # depth DRT with A12 / V_z = 1 / cos(theta): C = 1/cos + i beta dz / cos^2,
+    # B = i beta / cos, all exact for the scheme (linear in x, constant w = 0)
+    n, L, v = 32, 640.0, 2000.0
+    beta = 1.0 / (2 * L)
+    g = W.Grid(nx=n, nz=n, nth=40, dx=L / n, dz=L / n)
+    r = oracle.psolve(g, W.homogeneous(g, v), TMAX, beta)
+    U, th = r["U"], oracle.ptheta(g, TMAX)
+    dz = (g.zc() - g.zc()[0])[:, None, None]
+    x = g.xc()[None, None, :]
+    t = th[None, :, None]
+    assert np.abs(U[:, 0] - (x - np.tan(t) * dz)).max() < 1e-10 * L
+    assert np.abs(U[:, 1] - t).max() < 1e-13
+    assert np.abs(U[:, 2] - dz / (v * np.cos(t))).max() < 1e-14
+    assert np.abs(U[:, 3] - 1 / np.cos(t)).max() < 1e-12
+    assert np.abs(U[:, 4] - beta * dz / np.cos(t) ** 2).max() < 1e-12
+    assert np.abs(U[:, 5]).max() < 1e-12
+    assert np.abs(U[:, 6] - beta / np.cos(t)).max() < 1e-14
+
+
+@pytest.mark.parametrize("eps,tilt", [(0.0, 0.0), (0.2, 0.0), (0.2, 0.3)])
+def test_surface_source_traveltime_straight_and_elliptic(eps, tilt):
+    # first arrivals from a surface source through the level set X = x_s,
+    # within the bound of linear interpolation between theta nodes
+    n, L, v = 40, 800.0, 2500.0
+    g = W.Grid(nx=n, nz=n, nth=48, dx=L / n, dz=L / n)
+    xs = 0.5 * L
+    r = oracle.psolve(g, W.homogeneous(g, v, eps=eps, delta=eps, tilt=tilt), TMAX, 1 / (2 * L), xs=[xs])
+    T = r["T"][0]
+    Z, X = np.meshgrid(g.zc(), g.xc(), indexing="ij")
+    te = CF.t_elliptic(X, Z, xs, g.zc()[0], v, eps, tilt)
+    ok = np.isfinite(T) & (te > 0)
+    assert ok.mean() > 0.7
+    dth = 2 * TMAX / g.nth
+    assert np.max(np.abs(T - te)[ok] / te[ok]) < dth ** 2 / 4
+
+
+def test_gradient_medium_second_order():
+    # v(z) = v0 + g z: the arccosh traveltime, errors falling ~4x per halving
+    L, errs = 800.0, []
+    for n in (32, 64):
+        g = W.Grid(nx=n, nz=n, nth=n, dx=L / n, dz=L / n)
+        r = oracle.psolve(g, W.gradient_medium(g, 1500.0, 1.0, 0.0), TMAX, 1 / (2 * L), xs=[0.5 * L])
+        T = r["T"][0]
+        Z, X = np.meshgrid(g.zc(), g.xc(), indexing="ij")
+        te = CF.t_gradient(X, Z, 0.5 * L, g.zc()[0], 1500.0, 1.0, 0.0)
+        ok = np.isfinite(T) & (te > 0)
+        errs.append(np.sqrt(np.mean(((T - te) / te)[ok] ** 2)))
+    assert errs[1] < errs[0] / 3.0
+    assert errs[1] < 2e-4
