@@ -95,6 +95,7 @@ size_t egb_vel3d_bytes(const egb_grid *g);
 size_t egb_state_bytes(const egb_grid *g);
 size_t egb_state_plane_offset(const egb_grid *g, int32_t plane); /* bytes */
 size_t egb_workspace_size(const egb_grid *g, int32_t op);        /* bytes; 0 on bad args */
+size_t egb_bdata_bytes(const egb_grid *g);          /* boundary data of the march */
 
 /* ------------------------------------------------------------------ calls */
 
@@ -121,16 +122,32 @@ egb_status egb_hamiltonian_velocity(const egb_grid *g, const egb_medium *m, void
 egb_status egb_init_state(const egb_grid *g, const void *coeff2d, const egb_source *src, void *state,
                           hipStream_t stream);
 
+/* Boundary data of the march: the values of the six ghost cells beyond each
+ * end of every x line and z line, per state plane, taken from the point-source
+ * data and extended linearly, u(-m) = (m+1) u(0) - m u(1) for m = 1, 2, 3 (and
+ * the mirror image at the far end).  The march holds these values fixed, a
+ * Dirichlet condition like the source ball (the reading of the boundary that
+ * eqs. 16-21 leave open: the point-source data is the solution of the
+ * homogeneous problem, so it is what enters through the edges).
+ * In: state holding the point-source data (egb_init_state).
+ * Out: bdata, egb_bdata_bytes(g) bytes.  Layout per plane (five planes in the
+ * grid dtype, then psi in double, each padded to egb_bdata_plane_stride()
+ * elements): x ghosts [theta][6][nz], then z ghosts [theta][nx][6], ghost
+ * slots 0..2 at positions -3..-1 and 3..5 at n, n+1, n+2 of the line. */
+size_t egb_bdata_plane_stride(const egb_grid *g);
+egb_status egb_boundary_data(const egb_grid *g, const void *state, void *bdata, hipStream_t stream);
+
 /* nsteps SSP-RK3 pseudo-time steps of U_t + V.grad U = S(U) (eqs. 16, 19, 21
  * multiplied by dz/dtau): WENO5 Hamilton-Jacobi upwind derivatives, sources
- * S_psi = 1, S_(C,B) = A (C, B); ghosts: x, z linear extrapolation, theta
- * periodic; cells within r0 of the source keep their values (Dirichlet data).
- * In/out: state.  vel3d from egb_hamiltonian_velocity.
+ * S_psi = 1, S_(C,B) = A (C, B); ghosts: x, z from bdata (egb_boundary_data),
+ * theta periodic; cells within r0 of the source keep their values (Dirichlet
+ * data).  In/out: state.  vel3d from egb_hamiltonian_velocity.
  * work: egb_workspace_size(g, EGB_OP_STEP) bytes (two RK stage buffers).
  * dt must be positive and finite (EGB_ECFL otherwise); stability needs
  * dt <= dt_cfl. */
-egb_status egb_liouville_step(const egb_grid *g, const void *vel3d, const egb_source *src, void *state,
-                              void *work, size_t work_bytes, double dt, int32_t nsteps, hipStream_t stream);
+egb_status egb_liouville_step(const egb_grid *g, const void *vel3d, const egb_source *src, const void *bdata,
+                              void *state, void *work, size_t work_bytes, double dt, int32_t nsteps,
+                              hipStream_t stream);
 
 /* Eulerian Gaussian beam superposition (eqs. 25-27, 33-35).  For every
  * output cell (x0, z0) and frequency omega:
@@ -150,6 +167,7 @@ typedef struct {
     egb_grid grid;
     const void *vel3d; /* from egb_hamiltonian_velocity for this grid */
     egb_source src;
+    const void *bdata; /* egb_boundary_data of this problem */
     void *state;       /* in/out */
     double dt;         /* this problem's pseudo-time step */
 } egb_problem;
@@ -184,15 +202,21 @@ egb_status egb_pick_receivers(const egb_grid *g, const void *state, const double
  * is differentiated.  `lambda` buffers use the state layout
  * (egb_state_bytes; planes EGB_PHI1 and EGB_PSI are read and written, the
  * others are left untouched); `gvel` is [3][egb_plane_stride] in the grid
- * dtype (dJ/dV_x, dJ/dV_z, dJ/dV_theta), egb_gvel_bytes() bytes.  The
- * caller zero-initialises both before the reverse sweep. */
+ * dtype (dJ/dV_x, dJ/dV_z, dJ/dV_theta), egb_gvel_bytes() bytes.  `bfold`
+ * accumulates the sensitivity to the boundary data (the ghosts are fixed
+ * extensions of the point-source data, so it reaches the medium through the
+ * source): float64, egb_bfold_bytes() bytes, per line end and per source
+ * cell within three cells of it, the weights of the two cells the ghosts are
+ * extrapolated from.  The caller zero-initialises lambda, gvel and bfold
+ * before the reverse sweep. */
 size_t egb_gvel_bytes(const egb_grid *g);
+size_t egb_bfold_bytes(const egb_grid *g);
 
 /* egb_liouville_step restricted to the planes phi1 and psi (identical
  * values for them; the DRT planes are left untouched). */
-egb_status egb_liouville_step_kinematic(const egb_grid *g, const void *vel3d, const egb_source *src, void *state,
-                                        void *work, size_t work_bytes, double dt, int32_t nsteps,
-                                        hipStream_t stream);
+egb_status egb_liouville_step_kinematic(const egb_grid *g, const void *vel3d, const egb_source *src,
+                                        const void *bdata, void *state, void *work, size_t work_bytes, double dt,
+                                        int32_t nsteps, hipStream_t stream);
 
 /* Adjoint of egb_pick_receivers: lambda += sum_r tbar[r] d t_r / d(phi1, psi)
  * evaluated on `state` (the final state of the march).  rx, tbar: device
@@ -202,23 +226,24 @@ egb_status egb_pick_adjoint(const egb_grid *g, const void *state, const double *
 
 /* Exact discrete adjoint of one SSP-RK3 step of the march (WENO5 weights
  * differentiated, upwind sides frozen, ball cells pass their adjoint to the
- * step's start, ghosts transposed).  In: state_n = U^n (the step's start),
- * lambda = dJ/dU^{n+1}.  Out: lambda = dJ/dU^n; gvel += dJ/dV through this
- * step.  The step's inner stages are recomputed from state_n.
+ * step's start).  In: state_n = U^n (the step's start), lambda = dJ/dU^{n+1},
+ * bdata as given to the forward march.  Out: lambda = dJ/dU^n; gvel += dJ/dV
+ * and bfold += dJ/d(boundary data) through this step.  The step's inner
+ * stages are recomputed from state_n.
  * work: egb_workspace_size(g, EGB_OP_ADJOINT). */
-egb_status egb_adjoint_step(const egb_grid *g, const void *vel3d, const egb_source *src, const void *state_n,
-                            void *lambda, void *gvel, void *work, size_t work_bytes, double dt,
-                            hipStream_t stream);
+egb_status egb_adjoint_step(const egb_grid *g, const void *vel3d, const egb_source *src, const void *bdata,
+                            const void *state_n, void *lambda, void *gvel, void *bfold, void *work,
+                            size_t work_bytes, double dt, hipStream_t stream);
 
 /* Medium gradient from the reverse sweep: dJ/dV (gvel, accumulated over all
  * steps) through the velocity (eqs. 3-5, 7-12) and the medium table, plus
- * dJ/dU^0 (lambda0) through the point-source data (medium frozen at the
- * source), then the Thomsen map.  Out: grad, device float64 [4][nx][nz]
- * = dJ/d(vp0, eps, delta, tilt).  The time step is held fixed.
- * work: egb_workspace_size(g, EGB_OP_ADJOINT). */
+ * dJ/dU^0 (lambda0) and the boundary-data sensitivity (bfold) through the
+ * point-source data (medium frozen at the source), then the Thomsen map.
+ * Out: grad, device float64 [4][nx][nz] = dJ/d(vp0, eps, delta, tilt).  The
+ * time step is held fixed.  work: egb_workspace_size(g, EGB_OP_ADJOINT). */
 egb_status egb_adjoint_medium(const egb_grid *g, const egb_medium *m, const void *coeff2d, const egb_source *src,
-                              const void *gvel, const void *lambda0, double *grad, void *work, size_t work_bytes,
-                              hipStream_t stream);
+                              const void *gvel, const void *lambda0, const void *bfold, double *grad, void *work,
+                              size_t work_bytes, hipStream_t stream);
 
 /* Human-readable text for a status code (static storage). */
 const char *egb_status_string(int32_t status);

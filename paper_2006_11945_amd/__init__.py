@@ -49,8 +49,8 @@ class EgbSource(ctypes.Structure):
 
 
 class EgbProblem(ctypes.Structure):
-    _fields_ = [("grid", EgbGrid), ("vel3d", ctypes.c_void_p), ("src", EgbSource), ("state", ctypes.c_void_p),
-                ("dt", ctypes.c_double)]
+    _fields_ = [("grid", EgbGrid), ("vel3d", ctypes.c_void_p), ("src", EgbSource), ("bdata", ctypes.c_void_p),
+                ("state", ctypes.c_void_p), ("dt", ctypes.c_double)]
 
 
 class EgbError(RuntimeError):
@@ -64,29 +64,31 @@ def _load():
     G, M, S = ctypes.POINTER(EgbGrid), ctypes.POINTER(EgbMedium), ctypes.POINTER(EgbSource)
     vp, sz, i32, d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double
     dp = ctypes.POINTER(ctypes.c_double)
-    for name in ("egb_plane_stride", "egb_coeff2d_bytes", "egb_vel3d_bytes", "egb_state_bytes"):
+    for name in ("egb_plane_stride", "egb_coeff2d_bytes", "egb_vel3d_bytes", "egb_state_bytes", "egb_bdata_bytes",
+                 "egb_bdata_plane_stride", "egb_bfold_bytes"):
         getattr(L, name).argtypes = [G]
         getattr(L, name).restype = sz
     L.egb_state_plane_offset.argtypes = [G, i32]; L.egb_state_plane_offset.restype = sz
     L.egb_workspace_size.argtypes = [G, i32]; L.egb_workspace_size.restype = sz
     L.egb_hamiltonian_velocity.argtypes = [G, M, vp, vp, dp, vp, sz, vp]
     L.egb_init_state.argtypes = [G, vp, S, vp, vp]
-    L.egb_liouville_step.argtypes = [G, vp, S, vp, vp, sz, d, i32, vp]
+    L.egb_boundary_data.argtypes = [G, vp, vp, vp]
+    L.egb_liouville_step.argtypes = [G, vp, S, vp, vp, vp, sz, d, i32, vp]
     L.egb_beam_sum.argtypes = [G, vp, vp, S, vp, dp, i32, vp, vp, sz, vp]
     L.egb_pick_receivers.argtypes = [G, vp, vp, i32, vp, vp]
     L.egb_gvel_bytes.argtypes = [G]; L.egb_gvel_bytes.restype = sz
-    L.egb_liouville_step_kinematic.argtypes = [G, vp, S, vp, vp, sz, d, i32, vp]
+    L.egb_liouville_step_kinematic.argtypes = [G, vp, S, vp, vp, vp, sz, d, i32, vp]
     L.egb_pick_adjoint.argtypes = [G, vp, vp, i32, vp, vp, vp]
-    L.egb_adjoint_step.argtypes = [G, vp, S, vp, vp, vp, vp, sz, d, vp]
-    L.egb_adjoint_medium.argtypes = [G, M, vp, S, vp, vp, vp, vp, sz, vp]
+    L.egb_adjoint_step.argtypes = [G, vp, S, vp, vp, vp, vp, vp, vp, sz, d, vp]
+    L.egb_adjoint_medium.argtypes = [G, M, vp, S, vp, vp, vp, vp, vp, sz, vp]
     for name in ("egb_liouville_step_kinematic", "egb_pick_adjoint", "egb_adjoint_step", "egb_adjoint_medium"):
         getattr(L, name).restype = ctypes.c_int
     P = ctypes.POINTER(EgbProblem)
     L.egb_workspace_size_batched.argtypes = [P, i32]; L.egb_workspace_size_batched.restype = sz
     L.egb_liouville_step_batched.argtypes = [P, i32, i32, vp, sz, vp]
     L.egb_liouville_step_batched.restype = ctypes.c_int
-    for name in ("egb_hamiltonian_velocity", "egb_init_state", "egb_liouville_step", "egb_beam_sum",
-                 "egb_pick_receivers"):
+    for name in ("egb_hamiltonian_velocity", "egb_init_state", "egb_boundary_data", "egb_liouville_step",
+                 "egb_beam_sum", "egb_pick_receivers"):
         getattr(L, name).restype = ctypes.c_int
     L.egb_status_string.argtypes = [i32]; L.egb_status_string.restype = ctypes.c_char_p
     return L
@@ -135,6 +137,9 @@ def vel3d_bytes(eg) -> int: return _lib.egb_vel3d_bytes(ctypes.byref(eg))
 def state_bytes(eg) -> int: return _lib.egb_state_bytes(ctypes.byref(eg))
 def state_plane_offset(eg, p: int) -> int: return _lib.egb_state_plane_offset(ctypes.byref(eg), p)
 def workspace_size(eg, op: int) -> int: return _lib.egb_workspace_size(ctypes.byref(eg), op)
+def bdata_bytes(eg) -> int: return _lib.egb_bdata_bytes(ctypes.byref(eg))
+def bdata_plane_stride(eg) -> int: return _lib.egb_bdata_plane_stride(ctypes.byref(eg))
+def bfold_bytes(eg) -> int: return _lib.egb_bfold_bytes(ctypes.byref(eg))
 
 
 def alloc_bytes(n: int, device) -> torch.Tensor:
@@ -155,9 +160,14 @@ def egb_init_state(eg, coeff2d, src: EgbSource, state, stream=None):
                                                  _stream(stream)))
 
 
-def egb_liouville_step(eg, vel3d, src: EgbSource, state, work, dt: float, nsteps: int, stream=None):
-    rc = _lib.egb_liouville_step(ctypes.byref(eg), _ptr(vel3d), ctypes.byref(src), _ptr(state), _ptr(work),
-                                 0 if work is None else work.numel(), float(dt), int(nsteps), _stream(stream))
+def egb_boundary_data(eg, state, bdata, stream=None):
+    _check("egb_boundary_data", _lib.egb_boundary_data(ctypes.byref(eg), _ptr(state), _ptr(bdata), _stream(stream)))
+
+
+def egb_liouville_step(eg, vel3d, src: EgbSource, bdata, state, work, dt: float, nsteps: int, stream=None):
+    rc = _lib.egb_liouville_step(ctypes.byref(eg), _ptr(vel3d), ctypes.byref(src), _ptr(bdata), _ptr(state),
+                                 _ptr(work), 0 if work is None else work.numel(), float(dt), int(nsteps),
+                                 _stream(stream))
     _check("egb_liouville_step", rc)
 
 
@@ -178,9 +188,11 @@ def egb_pick_receivers(eg, state, rx, t_out, stream=None):
 def gvel_bytes(eg) -> int: return _lib.egb_gvel_bytes(ctypes.byref(eg))
 
 
-def egb_liouville_step_kinematic(eg, vel3d, src: EgbSource, state, work, dt: float, nsteps: int, stream=None):
-    rc = _lib.egb_liouville_step_kinematic(ctypes.byref(eg), _ptr(vel3d), ctypes.byref(src), _ptr(state), _ptr(work),
-                                           work.numel(), float(dt), int(nsteps), _stream(stream))
+def egb_liouville_step_kinematic(eg, vel3d, src: EgbSource, bdata, state, work, dt: float, nsteps: int,
+                                 stream=None):
+    rc = _lib.egb_liouville_step_kinematic(ctypes.byref(eg), _ptr(vel3d), ctypes.byref(src), _ptr(bdata),
+                                           _ptr(state), _ptr(work), work.numel(), float(dt), int(nsteps),
+                                           _stream(stream))
     _check("egb_liouville_step_kinematic", rc)
 
 
@@ -190,15 +202,18 @@ def egb_pick_adjoint(eg, state, rx, tbar, lam, stream=None):
     _check("egb_pick_adjoint", rc)
 
 
-def egb_adjoint_step(eg, vel3d, src: EgbSource, state_n, lam, gvel, work, dt: float, stream=None):
-    rc = _lib.egb_adjoint_step(ctypes.byref(eg), _ptr(vel3d), ctypes.byref(src), _ptr(state_n), _ptr(lam), _ptr(gvel),
-                               _ptr(work), work.numel(), float(dt), _stream(stream))
+def egb_adjoint_step(eg, vel3d, src: EgbSource, bdata, state_n, lam, gvel, bfold, work, dt: float, stream=None):
+    rc = _lib.egb_adjoint_step(ctypes.byref(eg), _ptr(vel3d), ctypes.byref(src), _ptr(bdata), _ptr(state_n),
+                               _ptr(lam), _ptr(gvel), _ptr(bfold), _ptr(work), work.numel(), float(dt),
+                               _stream(stream))
     _check("egb_adjoint_step", rc)
 
 
-def egb_adjoint_medium(eg, medium: "DeviceMedium", coeff2d, src: EgbSource, gvel, lam0, grad, work, stream=None):
+def egb_adjoint_medium(eg, medium: "DeviceMedium", coeff2d, src: EgbSource, gvel, lam0, bfold, grad, work,
+                       stream=None):
     rc = _lib.egb_adjoint_medium(ctypes.byref(eg), ctypes.byref(medium.struct()), _ptr(coeff2d), ctypes.byref(src),
-                                 _ptr(gvel), _ptr(lam0), _ptr(grad), _ptr(work), work.numel(), _stream(stream))
+                                 _ptr(gvel), _ptr(lam0), _ptr(bfold), _ptr(grad), _ptr(work), work.numel(),
+                                 _stream(stream))
     _check("egb_adjoint_medium", rc)
 
 
@@ -207,7 +222,7 @@ def make_problem_array(solvers, dts=None):
     arr = (EgbProblem * len(solvers))()
     for i, s in enumerate(solvers):
         dt = s.dt_cfl if dts is None else dts[i]
-        arr[i] = EgbProblem(s.eg, s.vel3d.data_ptr(), s.src, s.state.data_ptr(), float(dt))
+        arr[i] = EgbProblem(s.eg, s.vel3d.data_ptr(), s.src, s.bdata.data_ptr(), s.state.data_ptr(), float(dt))
     return arr
 
 
@@ -284,6 +299,7 @@ class Solver:
         self.coeff2d = alloc_bytes(coeff2d_bytes(eg), self.device)
         self.vel3d = alloc_bytes(vel3d_bytes(eg), self.device)
         self.state = alloc_bytes(state_bytes(eg), self.device)
+        self.bdata = alloc_bytes(bdata_bytes(eg), self.device)
         self.work_vel = alloc_bytes(workspace_size(eg, EGB_OP_VELOCITY), self.device)
         self.work_step = alloc_bytes(workspace_size(eg, EGB_OP_STEP), self.device)
         self.work_beam = None
@@ -294,10 +310,12 @@ class Solver:
         return self.dt_cfl
 
     def init(self, stream=None):
+        """Point-source data, and the boundary data of the march taken from it."""
         egb_init_state(self.eg, self.coeff2d, self.src, self.state, stream)
+        egb_boundary_data(self.eg, self.state, self.bdata, stream)
 
     def step(self, nsteps: int, dt: Optional[float] = None, stream=None):
-        egb_liouville_step(self.eg, self.vel3d, self.src, self.state, self.work_step,
+        egb_liouville_step(self.eg, self.vel3d, self.src, self.bdata, self.state, self.work_step,
                            self.dt_cfl if dt is None else dt, nsteps, stream)
 
     def beam(self, omegas, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
@@ -352,6 +370,8 @@ class TravelTime(torch.autograd.Function):
         dt = float(spec["dt"]) if spec.get("dt") is not None else dt
         state = alloc_bytes(state_bytes(eg), dev)
         egb_init_state(eg, coeff2d, src, state)
+        bdata = alloc_bytes(bdata_bytes(eg), dev)
+        egb_boundary_data(eg, state, bdata)
         work = alloc_bytes(workspace_size(eg, EGB_OP_STEP), dev)
         K = int(spec.get("checkpoint_every", 16))
         nsteps = int(spec["nsteps"])
@@ -360,12 +380,12 @@ class TravelTime(torch.autograd.Function):
         while done < nsteps:
             ckpts.append((done, state.clone()))
             n = min(K, nsteps - done)
-            egb_liouville_step_kinematic(eg, vel3d, src, state, work, dt, n)
+            egb_liouville_step_kinematic(eg, vel3d, src, bdata, state, work, dt, n)
             done += n
         rx = torch.as_tensor(np.ascontiguousarray(spec["receivers"], dtype=np.float64), device=dev).reshape(-1, 2)
         t = torch.empty(rx.shape[0], dtype=torch.float64, device=dev)
         egb_pick_receivers(eg, state, rx, t)
-        ctx.egb = dict(eg=eg, src=src, med=med, coeff2d=coeff2d, vel3d=vel3d, dt=dt, K=K, nsteps=nsteps,
+        ctx.egb = dict(eg=eg, src=src, med=med, coeff2d=coeff2d, vel3d=vel3d, bdata=bdata, dt=dt, K=K, nsteps=nsteps,
                        ckpts=ckpts, final=state, rx=rx, work=work)
         return t
 
@@ -375,6 +395,7 @@ class TravelTime(torch.autograd.Function):
         eg, src, dev = d["eg"], d["src"], d["final"].device
         lam = torch.zeros(state_bytes(eg), dtype=torch.uint8, device=dev)
         gvel = torch.zeros(gvel_bytes(eg), dtype=torch.uint8, device=dev)
+        bfold = torch.zeros(bfold_bytes(eg), dtype=torch.uint8, device=dev)
         tb = torch.nan_to_num(tbar.detach().to(torch.float64).contiguous(), nan=0.0)
         egb_pick_adjoint(eg, d["final"], d["rx"], tb, lam)
         wadj = alloc_bytes(workspace_size(eg, EGB_OP_ADJOINT), dev)
@@ -383,12 +404,12 @@ class TravelTime(torch.autograd.Function):
             states = [ck]
             cur = ck.clone()
             for _ in range(n - 1):
-                egb_liouville_step_kinematic(eg, d["vel3d"], src, cur, d["work"], d["dt"], 1)
+                egb_liouville_step_kinematic(eg, d["vel3d"], src, d["bdata"], cur, d["work"], d["dt"], 1)
                 states.append(cur.clone())
             for st in reversed(states):
-                egb_adjoint_step(eg, d["vel3d"], src, st, lam, gvel, wadj, d["dt"])
+                egb_adjoint_step(eg, d["vel3d"], src, d["bdata"], st, lam, gvel, bfold, wadj, d["dt"])
         grad = torch.empty((4, eg.nx, eg.nz), dtype=torch.float64, device=dev)
-        egb_adjoint_medium(eg, d["med"], d["coeff2d"], src, gvel, lam, grad, wadj)
+        egb_adjoint_medium(eg, d["med"], d["coeff2d"], src, gvel, lam, bfold, grad, wadj)
         return grad[0], grad[1], grad[2], grad[3], None
 
 

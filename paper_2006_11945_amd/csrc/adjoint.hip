@@ -12,9 +12,12 @@
 // where W_d is the upwind WENO5 derivative (upwind side frozen).  The
 // transposed stencil (dL/dUin)^T is applied by the fused stage kernel below:
 // every source cell forms its Jacobian rows and the rows are summed per
-// target, x through a register queue and z, theta through LDS; slots aimed
-// at extrapolated ghosts go to the two cells the ghost is extrapolated from
-// (weights m + 1 and -m), theta wraps.
+// target, x through a register queue and z, theta through LDS; theta wraps.
+// The x and z ghosts hold boundary data, fixed extensions of the point-source
+// data: slots aimed at them are sensitivities to that data.  Folded onto the
+// two end cells the ghost extends (weights m + 1 and -m), they accumulate per
+// source cell in a boundary buffer that the source gradient contracts like
+// lambda of the initial state.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdlib.h>
@@ -45,9 +48,10 @@ constexpr int NSLOT = 7;  // stencil positions -3..3
 //    the target at offset j - 3), then every own cell sums the seven slots
 //    aimed at it per axis;
 //  * rows are formed in upwind order (mirrored reads for a negative
-//    velocity component) and folded at x and z ends: a slot aimed at the
-//    ghost m cells outside goes to the edge cell with weight m + 1 and to
-//    its neighbour with weight -m; theta wraps.
+//    velocity component); a slot aimed at a ghost is never summed into a
+//    target: the block that owns the source adds its fold (weight m + 1 on
+//    the end cell, -m on its neighbour, for the ghost m cells outside) to
+//    the boundary buffer, one (source, weight) entry per thread.
 // The stencil values of the slice sit in LDS with a 6-cell halo (the halo
 // sources' own stencils); the own column's x stencil is a register queue.
 template <typename R, int TK>
@@ -68,6 +72,8 @@ struct AdjSmem {
 struct AdjStageArgs {
     GridArgs g;
     const void* vel;     // vel3d
+    const void* bd;      // boundary data (ghost values)
+    double* bfold;       // boundary sensitivity, accumulated
     const void* Uin;     // stage input state (phi1 and psi are read)
     const void* lam;     // lambda of the stage output
     const void* acc_in;  // stages 0, 1: accumulated lambda of U0 so far (may alias acc_out)
@@ -75,7 +81,7 @@ struct AdjStageArgs {
     void* lam_in;        // stages 1, 2: lambda of the stage input
     void* gvel;          // [3][stride] of R, accumulated
     double dt, xs, zs, r02;
-    unsigned state_bytes, vel_bytes, gvel_bytes;
+    unsigned state_bytes, vel_bytes, gvel_bytes, bd_bytes;
     int ntz, ntk;
 };
 
@@ -105,29 +111,33 @@ __device__ __forceinline__ void to_slots(const R (&du)[6], bool plus, C c, C (&d
     }
 }
 
-// Fold the slots of a source at index s of a line of n cells whose targets
-// leave the line: the ghost m cells outside goes to the edge cell (m + 1)
-// and its neighbour (-m).
+// Fold of the slots of a source at index s of a line of n cells that aim
+// beyond an end: the ghost m cells outside extends the end cell (weight
+// m + 1) and its neighbour (weight -m).
 template <typename C>
-__device__ __forceinline__ void fold_ends(C (&d)[NSLOT], int s, int n) {
-    const bool lo = s < 3;
-    const int e0 = lo ? 0 : n - 1, e1 = lo ? 1 : n - 2;
-    C f0 = (C)0, f1 = (C)0;
+__device__ __forceinline__ void fold_weights(const C (&d)[NSLOT], int s, int n, double& f0, double& f1) {
+    f0 = 0.0;
+    f1 = 0.0;
 #pragma unroll
     for (int j = 0; j < NSLOT; ++j) {
         const int t = s + j - 3;
         const int m = t < 0 ? -t : (t > n - 1 ? t - (n - 1) : 0);
         if (m > 0) {
-            f0 += (C)(m + 1) * d[j];
-            f1 -= (C)m * d[j];
-            d[j] = (C)0;
+            f0 += (double)(m + 1) * (double)d[j];
+            f1 -= (double)m * (double)d[j];
         }
     }
-#pragma unroll
-    for (int j = 0; j < NSLOT; ++j) {
-        const int t = s + j - 3;
-        d[j] += t == e0 ? f0 : (t == e1 ? f1 : (C)0);
-    }
+}
+
+// Index of a boundary-sensitivity entry: plane p (0 phi1, 1 psi), theta k,
+// line end e (0 near, 1 far), source s (0..2 counted from that end, inward),
+// weight w (0 end cell, 1 its neighbour); x lines by z, z lines by x.
+__device__ __forceinline__ long long bfold_x(const GridArgs& g, int p, int k, int e, int s, int w, int z) {
+    return (long long)p * g.nth * 12 * (g.nx + g.nz) + ((((long long)k * 2 + e) * 3 + s) * 2 + w) * g.nz + z;
+}
+__device__ __forceinline__ long long bfold_z(const GridArgs& g, int p, int k, int x, int e, int s, int w) {
+    return (long long)p * g.nth * 12 * (g.nx + g.nz) + (long long)g.nth * 12 * g.nz +
+           (((long long)k * g.nx + x) * 2 + e) * 6 + s * 2 + w;
 }
 
 template <typename R, int STAGE, int TK>
@@ -159,6 +169,10 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
     const auto rL = make_rsrc(a.lam, a.state_bytes);
     const auto rV = make_rsrc(a.vel, a.vel_bytes);
     const auto rG = make_rsrc(a.gvel, a.gvel_bytes);
+    const auto rB = make_rsrc(a.bd, a.bd_bytes);
+    const unsigned BSP = (unsigned)g.bstride * ES;  // boundary data: bytes per R plane
+    const unsigned XG = (unsigned)k * 6u * (unsigned)g.nz + (unsigned)izc;  // x ghost slot 0 of the column
+    const unsigned ZG = (unsigned)g.nth * 6u * (unsigned)g.nz;            // first z ghost
     const double cbdt = cb * a.dt;
     const double kx = cbdt / g.dx, kz = cbdt / g.dz, kt = cbdt / g.dth;
     auto wrapk = [&](int kk) { return ((kk % g.nth) + g.nth) % g.nth; };
@@ -167,14 +181,18 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
         return xr * xr + zr * zr <= a.r02;
     };
 
-    // value cell i of the LDS slice: base (theta row, clamped z) and the
-    // ghost distance (0 inside, +-m within 3 of an end, 100 beyond: never
-    // read by a source inside the grid)
-    auto vcell = [&](int i, unsigned& vb, int& vm) {
+    // value cell i of the LDS slice: base (theta row, clamped z), the ghost
+    // distance (0 inside, +-m within 3 of an end, 100 beyond: never read by
+    // a source inside the grid) and the boundary-data index at x = 0 of a
+    // ghost (step 6 per x; a valid index for the other cells)
+    auto vcell = [&](int i, unsigned& vb, int& vm, unsigned& vbd) {
         const int tl = i / S::VZ - 6, zl = i % S::VZ - 6;
         const int z = tzi * TZ + zl;
-        vb = (unsigned)wrapk(tki * TK + tl) * nxz + (unsigned)min(max(z, 0), g.nz - 1);
+        const int kk = wrapk(tki * TK + tl);
+        vb = (unsigned)kk * nxz + (unsigned)min(max(z, 0), g.nz - 1);
         vm = z < 0 ? (z >= -3 ? z : 100) : (z >= g.nz ? (z <= g.nz + 2 ? z - (g.nz - 1) : 100) : 0);
+        const int gi = (vm < 0 ? vm + 3 : (vm < 100 ? vm + 2 : 0));
+        vbd = ZG + (unsigned)kk * 6u * (unsigned)g.nx + (unsigned)gi;
     };
     const bool z_end = tzi == 0 || (tzi + 1) * TZ + 6 > g.nz;  // block-uniform: some value cell is a ghost
     // halo source h: theta rows (h < 6 TZ) then z columns; LDS row, z position,
@@ -196,34 +214,24 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
         c = (unsigned)wrapk(tki * TK + tl) * nxz + (unsigned)min(max(z, 0), g.nz - 1);
     };
 
-    // own column's x stencil: values at xs - 3 .. xs + 3 (x ghosts continue
-    // the line of the two entries next to them)
+    // own column's x stencil: values at xs - 3 .. xs + 3, from the state
+    // inside the grid and from the boundary data beyond either end (the
+    // buffer is chosen per block; slots beyond the three ghosts on either
+    // side are only in stencils of sources outside the grid and clamped)
+    auto x_value = [&](int p, R& v, double& vp) {
+        const bool gh = p < 0 || p >= g.nx;  // block-uniform
+        const auto r = gh ? rB : rUi;
+        const unsigned sp = gh ? BSP : SP;
+        const unsigned o = gh ? XG + (unsigned)(min(max(p < 0 ? p + 3 : p - g.nx + 3, 0), 5) * g.nz)
+                              : kb + (unsigned)(p * g.nz + izc);
+        v = bload<R>(r, o * ES, 0);
+        vp = bload<double>(r, o * 8u, 5u * sp);
+    };
     R qv[7];
     double qp[7];
     const int xa = x0 - 3, xb = x1 + 3;  // source slices
-    {
-        // eight entries (x0 - 6 .. x0 + 1): the line through x = 0, 1 reaches
-        // every left ghost among the first seven
-        R tv[8];
-        double tp[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const unsigned o = kb + (unsigned)(min(max(xa - 3 + j, 0), g.nx - 1) * g.nz + izc);
-            tv[j] = bload<R>(rUi, o * ES, 0);
-            tp[j] = bload<double>(rUi, o * 8u, PSI);
-        }
-#pragma unroll
-        for (int j = 5; j >= 0; --j)
-            if (xa - 3 + j < 0) {
-                tv[j] = (R)2 * tv[j + 1] - tv[j + 2];
-                tp[j] = 2.0 * tp[j + 1] - tp[j + 2];
-            }
-#pragma unroll
-        for (int j = 0; j < 7; ++j) {
-            qv[j] = tv[j];
-            qp[j] = tp[j];
-        }
-    }
+    for (int j = 0; j < 7; ++j) x_value(xa - 3 + j, qv[j], qp[j]);
     // accumulators of targets xs - 3 .. xs + 3 (phi1, psi)
     R a0[7], a1[7];
 #pragma unroll
@@ -256,16 +264,16 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
         const unsigned xo = (unsigned)(x * g.nz);
 #pragma unroll
         for (int r = 0; r < NVI; ++r) {
-            unsigned vb;
+            unsigned vb, vbd;
             int vm;
-            vcell(tid + r * NT, vb, vm);
+            vcell(tid + r * NT, vb, vm, vbd);
             const unsigned o = vb + xo;
             vv[r] = bload<R>(rUi, o * ES, 0);
             vp[r] = bload<double>(rUi, o * 8u, PSI);
-            if (z_end) {  // second point of a ghost: the cell next to the edge
-                const unsigned o1 = vm < 0 ? o + 1u : (vm > 0 && vm < 100 ? o - 1u : o);
-                vv1[r] = bload<R>(rUi, o1 * ES, 0);
-                vp1[r] = bload<double>(rUi, o1 * 8u, PSI);
+            if (z_end) {  // the boundary-data value, kept by ghost cells
+                const unsigned o1 = vbd + (unsigned)(x * 6);
+                vv1[r] = bload<R>(rB, o1 * ES, 0);
+                vp1[r] = bload<double>(rB, o1 * 8u, 5u * BSP);
             }
         }
     };
@@ -303,13 +311,12 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
                 if (i < NV) {
                     R v0 = vv[r];
                     double v1 = vp[r];
-                    unsigned vb;
+                    unsigned vb, vbd;
                     int vm;
-                    vcell(i, vb, vm);
+                    vcell(i, vb, vm, vbd);
                     if (z_end && vm != 0) {
-                        const int m = vm < 0 ? -vm : vm;
-                        v0 = m < 100 ? (R)(m + 1) * vv[r] - (R)m * vv1[r] : (R)0;
-                        v1 = m < 100 ? (double)(m + 1) * vp[r] - (double)m * vp1[r] : 0.0;
+                        v0 = vm != 100 ? vv1[r] : (R)0;
+                        v1 = vm != 100 ? vp1[r] : 0.0;
                     }
                     sm.w[i] = __builtin_bit_cast(Wd, v0);
                     const unsigned long long b = __builtin_bit_cast(unsigned long long, v1);
@@ -325,11 +332,7 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
         // prefetch: queue entry xs + 4, own mu and V of slice xs + 1
         R qn;
         double qpn;
-        {
-            const unsigned o = kb + (unsigned)(min(max(xs + 4, 0), g.nx - 1) * g.nz + izc);
-            qn = bload<R>(rUi, o * ES, 0);
-            qpn = bload<double>(rUi, o * 8u, PSI);
-        }
+        x_value(xs + 4, qn, qpn);
         R nm0, nvx, nvz, nvt;
         double nm1;
         own_mu_v(xs + 1, nm0, nm1, nvx, nvz, nvt);
@@ -362,25 +365,33 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
             const bool plus = cvx >= (R)0;
             R du[6], d[NSLOT];
             auto u = [&](const auto& q, int m) { return plus ? q[m] : q[6 - m]; };
-            const bool xend = xs < 3 || xs > g.nx - 4;
+            // the block owning a source within 3 of an x end folds its ghost slots
+            const bool xfold = (xs < 3 || xs > g.nx - 4) && core;  // block-uniform
+            double f[4];
             const R W0 = wgrad_up<R>(u(qv, 0), u(qv, 1), u(qv, 2), qv[3], u(qv, 4), u(qv, 5), du);
             to_slots(du, plus, (R)(-kx) * fabs(cvx) * cm0, d);
-            if (xend) fold_ends(d, xs, g.nx);
+            if (xfold) fold_weights(d, xs, g.nx, f[0], f[1]);
 #pragma unroll
             for (int j = 0; j < NSLOT; ++j) a0[j] += d[j];
             const R W1 = wgrad_up<R>(u(qp, 0), u(qp, 1), u(qp, 2), qp[3], u(qp, 4), u(qp, 5), du);
             to_slots(du, plus, (R)(-kx * (double)fabs(cvx) * cm1), d);
-            if (xend) fold_ends(d, xs, g.nx);
+            if (xfold) fold_weights(d, xs, g.nx, f[2], f[3]);
 #pragma unroll
             for (int j = 0; j < NSLOT; ++j) a1[j] += d[j];
+            if (xfold && valid) {
+                const int e = xs < 3 ? 0 : 1, sidx = e == 0 ? xs : g.nx - 1 - xs;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a.bfold[bfold_x(g, q >> 1, k, e, sidx, q & 1, iz)] += f[q];
+            }
             // d(-cb dt V_x D_x U / dx)/dV_x with D_x U = sign * W_up / dx
             gsx = (R)(plus ? -kx : kx) * (cm0 * W0 + (R)cm1 * W1);
         }
         if (core) {
             __syncthreads();
             // z and theta rows of a source at LDS (tl, zl): slots scaled by
-            // -cb dt |V| mu / h, stored at the source position
-            auto row = [&](int tl, int zl, bool zaxis, R vel, R m0, double m1, int zg, R& Wsum) {
+            // -cb dt |V| mu / h, stored at the source position; the own cell
+            // of a valid lane within 3 of a z end folds its ghost slots
+            auto row = [&](int tl, int zl, bool zaxis, R vel, R m0, double m1, int zg, R& Wsum, bool own) {
                 const int base = ((tl + 6) * S::VZ + zl + 6) * WS;
                 const bool plus = vel >= (R)0;
                 const int step = (zaxis ? WS : S::VZ * WS) * (plus ? 1 : -1);
@@ -390,17 +401,23 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
                 const double kk = zaxis ? kz : kt;
                 const int stride = zaxis ? S::ZPL : S::TPL;
                 R* dst = zaxis ? sm.cz + tl * S::CZW + zl + 3 : sm.ct + (tl + 3) * TZ + zl;
-                const bool fold = zaxis && (zg < 3 || zg > g.nz - 4);
+                const bool fold = own && zaxis && (zg < 3 || zg > g.nz - 4);
+                double f[4];
                 const R W0 = wgrad_up<R>(lds_r<R>(sm, b0, 0), lds_r<R>(sm, b1, 0), lds_r<R>(sm, b2, 0),
                                          lds_r<R>(sm, base, 0), lds_r<R>(sm, b4, 0), lds_r<R>(sm, b5, 0), du);
                 to_slots(du, plus, (R)(-kk) * fabs(vel) * m0, d);
-                if (fold) fold_ends(d, zg, g.nz);
+                if (fold) fold_weights(d, zg, g.nz, f[0], f[1]);
 #pragma unroll
                 for (int j = 0; j < NSLOT; ++j) dst[j * stride] = d[j];
                 const R W1 = wgrad_up<R>(lds_psi<1>(sm, b0), lds_psi<1>(sm, b1), lds_psi<1>(sm, b2),
                                          lds_psi<1>(sm, base), lds_psi<1>(sm, b4), lds_psi<1>(sm, b5), du);
                 to_slots(du, plus, (R)(-kk * (double)fabs(vel) * m1), d);
-                if (fold) fold_ends(d, zg, g.nz);
+                if (fold) {
+                    fold_weights(d, zg, g.nz, f[2], f[3]);
+                    const int e = zg < 3 ? 0 : 1, sidx = e == 0 ? zg : g.nz - 1 - zg;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) a.bfold[bfold_z(g, q >> 1, k, xs, e, sidx, q & 1)] += f[q];
+                }
 #pragma unroll
                 for (int j = 0; j < NSLOT; ++j) dst[(NSLOT + j) * stride] = d[j];
                 Wsum = (plus ? (R)1 : (R)-1) * (m0 * W0 + (R)m1 * W1);
@@ -413,8 +430,8 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
             };
             R Wz = (R)0, Wt = (R)0;
             if (wlive) {
-                row(tk, tz, true, cvz, cm0, cm1, izc, Wz);
-                row(tk, tz, false, cvt, cm0, cm1, izc, Wt);
+                row(tk, tz, true, cvz, cm0, cm1, izc, Wz, valid);
+                row(tk, tz, false, cvt, cm0, cm1, izc, Wt, false);
             } else {
                 zero_row(tk, tz, true);
                 zero_row(tk, tz, false);
@@ -430,7 +447,7 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
                     const bool zaxis = h >= 6 * TZ;
                     R wh;  // a halo source's V term belongs to another tile
                     if (__any(hm0[r] != (R)0 || hm1[r] != 0.0))
-                        row(tl, zl, zaxis, hvel[r], hm0[r], hm1[r], tzi * TZ + zl, wh);
+                        row(tl, zl, zaxis, hvel[r], hm0[r], hm1[r], tzi * TZ + zl, wh, false);
                     else zero_row(tl, zl, zaxis);
                 }
             }
@@ -489,9 +506,8 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
             a0[j] = a0[j + 1];
             a1[j] = a1[j + 1];
         }
-        const bool xin = xs + 4 < g.nx;
-        qv[6] = xin ? qn : (R)2 * qv[5] - qv[4];
-        qp[6] = xin ? qpn : 2.0 * qp[5] - qp[4];
+        qv[6] = qn;
+        qp[6] = qpn;
         a0[6] = (R)0;
         a1[6] = (R)0;
         cm0 = nm0;
@@ -656,12 +672,14 @@ __device__ double source_weight(const GridArgs& a, double xs, double zs, int ix,
 }
 
 // Point-source data phi1 = (x - xs).g_perp(theta; m_s), psi = p(theta; m_s).(x - xs):
-// per theta slice, contract lambda0 with (x - xs, z - zs), then differentiate
-// g_perp and p with respect to the five source values (dual numbers); the
-// slice's five partial derivatives go to gms[k][5] (summed in order later).
+// per theta slice, contract lambda0 and the boundary sensitivity (its
+// entries sit on the end cells of the lines) with (x - xs, z - zs), then
+// differentiate g_perp and p with respect to the five source values (dual
+// numbers); the slice's five partial derivatives go to gms[k][5] (summed in
+// order later).
 template <typename R>
 __global__ __launch_bounds__(256) void k_adj_source(GridArgs a, const double* C, egb_source src, const char* lam0,
-                                                    double* gms) {
+                                                    const double* bfold, double* gms) {
     const int k = blockIdx.x;
     const R* lphi = reinterpret_cast<const R*>(lam0);
     const double* lpsi = reinterpret_cast<const double*>(lphi + 5 * a.stride);
@@ -675,6 +693,28 @@ __global__ __launch_bounds__(256) void k_adj_source(GridArgs a, const double* C,
         s[1] += lf * Z;
         s[2] += lp * X;
         s[3] += lp * Z;
+    }
+    // x lines: entry (end e, source, weight w, z) sits at x = 0, 1 / nx-1, nx-2
+    for (int i = threadIdx.x; i < 12 * a.nz; i += blockDim.x) {
+        const int z = i % a.nz, w = (i / a.nz) & 1, e = i / (6 * a.nz), sidx = (i / (2 * a.nz)) % 3;
+        const int ix = e == 0 ? w : a.nx - 1 - w;
+        const double X = a.x0 + (ix + 0.5) * a.dx - src.xs, Z = a.z0 + (z + 0.5) * a.dz - src.zs;
+        for (int p = 0; p < 2; ++p) {
+            const double v = bfold[bfold_x(a, p, k, e, sidx, w, z)];
+            s[2 * p] += v * X;
+            s[2 * p + 1] += v * Z;
+        }
+    }
+    // z lines: entry (x, end e, source, weight w) sits at z = 0, 1 / nz-1, nz-2
+    for (int i = threadIdx.x; i < 12 * a.nx; i += blockDim.x) {
+        const int x = i / 12, e = (i / 6) & 1, sidx = (i / 2) % 3, w = i & 1;
+        const int iz = e == 0 ? w : a.nz - 1 - w;
+        const double X = a.x0 + (x + 0.5) * a.dx - src.xs, Z = a.z0 + (iz + 0.5) * a.dz - src.zs;
+        for (int p = 0; p < 2; ++p) {
+            const double v = bfold[bfold_z(a, p, k, x, e, sidx, w)];
+            s[2 * p] += v * X;
+            s[2 * p + 1] += v * Z;
+        }
     }
     __shared__ double red[4][256];
     for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = s[q];
@@ -795,13 +835,15 @@ hipError_t adj_stage_t(AdjStageArgs a, int stage, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_adjoint_stage(const GridArgs& g, int dtype, int stage, const void* vel, const void* Uin,
-                                const void* lam_out, void* lam_in, const void* acc_in, void* acc_out, void* gvel,
-                                double dt, double xs, double zs, double r02, hipStream_t s) {
+hipError_t launch_adjoint_stage(const GridArgs& g, int dtype, int stage, const void* vel, const void* bd,
+                                const void* Uin, const void* lam_out, void* lam_in, const void* acc_in, void* acc_out,
+                                void* gvel, void* bfold, double dt, double xs, double zs, double r02, hipStream_t s) {
     const unsigned long long es = dtype == EGB_F64 ? 8 : 4, S = (unsigned long long)g.stride;
     AdjStageArgs a;
     a.g = g;
     a.vel = vel;
+    a.bd = bd;
+    a.bfold = static_cast<double*>(bfold);
     a.Uin = Uin;
     a.lam = lam_out;
     a.acc_in = acc_in;
@@ -815,6 +857,7 @@ hipError_t launch_adjoint_stage(const GridArgs& g, int dtype, int stage, const v
     a.state_bytes = (unsigned)(S * (5 * es + 8));
     a.vel_bytes = (unsigned)(7 * S * es);
     a.gvel_bytes = (unsigned)(3 * S * es);
+    a.bd_bytes = (unsigned)((unsigned long long)g.bstride * (5 * es + 8));
     a.ntz = a.ntk = 0;
     return dtype == EGB_F64 ? adj_stage_t<double, 4>(a, stage, s) : adj_stage_t<float, 8>(a, stage, s);
 }
@@ -830,15 +873,15 @@ hipError_t launch_pick_adjoint(const GridArgs& a, int dtype, const void* state, 
 }
 
 hipError_t launch_adjoint_medium(const GridArgs& a, int dtype, const egb_medium& m, const double* coeff2d,
-                                 const egb_source& src, const void* gvel, const void* lam0, double* grad, double* gtab,
-                                 double* gms, hipStream_t s) {
+                                 const egb_source& src, const void* gvel, const void* lam0, const double* bfold,
+                                 double* grad, double* gtab, double* gms, hipStream_t s) {
     const long long nt = 15 * a.nxz;
     if (dtype == EGB_F64) {
         k_adj_vtable<double><<<(unsigned)((nt + 255) / 256), 256, 0, s>>>(a, coeff2d, (const double*)gvel, gtab);
-        k_adj_source<double><<<a.nth, 256, 0, s>>>(a, coeff2d, src, (const char*)lam0, gms);
+        k_adj_source<double><<<a.nth, 256, 0, s>>>(a, coeff2d, src, (const char*)lam0, bfold, gms);
     } else {
         k_adj_vtable<float><<<(unsigned)((nt + 255) / 256), 256, 0, s>>>(a, coeff2d, (const float*)gvel, gtab);
-        k_adj_source<float><<<a.nth, 256, 0, s>>>(a, coeff2d, src, (const char*)lam0, gms);
+        k_adj_source<float><<<a.nth, 256, 0, s>>>(a, coeff2d, src, (const char*)lam0, bfold, gms);
     }
     k_adj_fields<<<(unsigned)((a.nxz + 255) / 256), 256, 0, s>>>(a, m, gtab, gms, src, grad);
     return hipGetLastError();

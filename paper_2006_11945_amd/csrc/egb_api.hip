@@ -59,6 +59,10 @@ size_t egb_state_plane_offset(const egb_grid* g, int32_t plane) {
     return state_plane_offset(*g, plane);
 }
 
+size_t egb_bdata_bytes(const egb_grid* g) { return grid_ok(g) ? bdata_bytes(*g) : 0; }
+size_t egb_bdata_plane_stride(const egb_grid* g) { return grid_ok(g) ? bdata_stride(*g) : 0; }
+size_t egb_bfold_bytes(const egb_grid* g) { return grid_ok(g) ? bfold_bytes(*g) : 0; }
+
 size_t egb_workspace_size(const egb_grid* g, int32_t op) {
     if (!grid_ok(g)) return 0;
     switch (op) {
@@ -108,11 +112,18 @@ egb_status egb_init_state(const egb_grid* g, const void* coeff2d, const egb_sour
     return hip_status(launch_init_state(grid_args(*g), g->dtype, static_cast<const double*>(coeff2d), *src, state, stream));
 }
 
-static egb_status liouville_steps(const egb_grid* g, const void* vel3d, const egb_source* src, void* state, void* work,
-                                  size_t work_bytes, double dt, int32_t nsteps, hipStream_t stream, bool kin) {
-    if (!grid_ok(g) || !vel3d || !state || !source_ok(src) || nsteps < 0) return EGB_EINVAL;
+egb_status egb_boundary_data(const egb_grid* g, const void* state, void* bdata, hipStream_t stream) {
+    if (!grid_ok(g) || !state || !bdata) return EGB_EINVAL;
+    if (!aligned16(state) || !aligned16(bdata)) return EGB_EINVAL;
+    return hip_status(launch_boundary_data(grid_args(*g), g->dtype, state, bdata, stream));
+}
+
+static egb_status liouville_steps(const egb_grid* g, const void* vel3d, const egb_source* src, const void* bdata,
+                                  void* state, void* work, size_t work_bytes, double dt, int32_t nsteps,
+                                  hipStream_t stream, bool kin) {
+    if (!grid_ok(g) || !vel3d || !bdata || !state || !source_ok(src) || nsteps < 0) return EGB_EINVAL;
     if (nsteps > 0 && !work) return EGB_EINVAL;
-    if (!aligned16(vel3d) || !aligned16(state) || (work && !aligned16(work))) return EGB_EINVAL;
+    if (!aligned16(vel3d) || !aligned16(bdata) || !aligned16(state) || (work && !aligned16(work))) return EGB_EINVAL;
     if (!(dt > 0.0) || !isfinite(dt)) return EGB_ECFL;
     if (nsteps == 0) return EGB_OK;
     if (work_bytes < egb_workspace_size(g, EGB_OP_STEP)) return EGB_EWORKSPACE;
@@ -123,6 +134,7 @@ static egb_status liouville_steps(const egb_grid* g, const void* vel3d, const eg
     StageArgs sa;
     sa.g = grid_args(*g);
     sa.vel = vel3d;
+    sa.bd = bdata;
     sa.dt = dt;
     sa.xs = src->xs;
     sa.zs = src->zs;
@@ -145,15 +157,16 @@ static egb_status liouville_steps(const egb_grid* g, const void* vel3d, const eg
     return EGB_OK;
 }
 
-egb_status egb_liouville_step(const egb_grid* g, const void* vel3d, const egb_source* src, void* state, void* work,
-                              size_t work_bytes, double dt, int32_t nsteps, hipStream_t stream) {
-    return liouville_steps(g, vel3d, src, state, work, work_bytes, dt, nsteps, stream, false);
+egb_status egb_liouville_step(const egb_grid* g, const void* vel3d, const egb_source* src, const void* bdata,
+                              void* state, void* work, size_t work_bytes, double dt, int32_t nsteps,
+                              hipStream_t stream) {
+    return liouville_steps(g, vel3d, src, bdata, state, work, work_bytes, dt, nsteps, stream, false);
 }
 
-egb_status egb_liouville_step_kinematic(const egb_grid* g, const void* vel3d, const egb_source* src, void* state,
-                                        void* work, size_t work_bytes, double dt, int32_t nsteps,
-                                        hipStream_t stream) {
-    return liouville_steps(g, vel3d, src, state, work, work_bytes, dt, nsteps, stream, true);
+egb_status egb_liouville_step_kinematic(const egb_grid* g, const void* vel3d, const egb_source* src,
+                                        const void* bdata, void* state, void* work, size_t work_bytes, double dt,
+                                        int32_t nsteps, hipStream_t stream) {
+    return liouville_steps(g, vel3d, src, bdata, state, work, work_bytes, dt, nsteps, stream, true);
 }
 
 size_t egb_gvel_bytes(const egb_grid* g) { return grid_ok(g) ? (size_t)3 * plane_stride(*g) * real_size(*g) : 0; }
@@ -166,10 +179,13 @@ egb_status egb_pick_adjoint(const egb_grid* g, const void* state, const double* 
     return hip_status(launch_pick_adjoint(grid_args(*g), g->dtype, state, rx, nr, tbar, lambda, stream));
 }
 
-egb_status egb_adjoint_step(const egb_grid* g, const void* vel3d, const egb_source* src, const void* state_n,
-                            void* lambda, void* gvel, void* work, size_t work_bytes, double dt, hipStream_t stream) {
-    if (!grid_ok(g) || !vel3d || !state_n || !lambda || !gvel || !work || !source_ok(src)) return EGB_EINVAL;
-    if (!aligned16(vel3d) || !aligned16(state_n) || !aligned16(lambda) || !aligned16(gvel) || !aligned16(work))
+egb_status egb_adjoint_step(const egb_grid* g, const void* vel3d, const egb_source* src, const void* bdata,
+                            const void* state_n, void* lambda, void* gvel, void* bfold, void* work, size_t work_bytes,
+                            double dt, hipStream_t stream) {
+    if (!grid_ok(g) || !vel3d || !bdata || !state_n || !lambda || !gvel || !bfold || !work || !source_ok(src))
+        return EGB_EINVAL;
+    if (!aligned16(vel3d) || !aligned16(bdata) || !aligned16(state_n) || !aligned16(lambda) || !aligned16(gvel) ||
+        !aligned16(bfold) || !aligned16(work))
         return EGB_EINVAL;
     if (state_n == lambda) return EGB_EINVAL;
     if (!(dt > 0.0) || !isfinite(dt)) return EGB_ECFL;
@@ -187,6 +203,7 @@ egb_status egb_adjoint_step(const egb_grid* g, const void* vel3d, const egb_sour
     StageArgs sa;
     sa.g = a;
     sa.vel = vel3d;
+    sa.bd = bdata;
     sa.dt = dt;
     sa.xs = src->xs;
     sa.zs = src->zs;
@@ -206,30 +223,33 @@ egb_status egb_adjoint_step(const egb_grid* g, const void* vel3d, const egb_sour
     // may overwrite it: the accumulated lambda of U^n lives in L1 until stage
     // 0 writes the result back into `lambda`.
     if (e == hipSuccess)  // lambda -> L2 (of U2), acc L1 = (ca mu + ball) part
-        e = launch_adjoint_stage(a, g->dtype, 2, vel3d, U2, lambda, L2, nullptr, L1, gvel, dt, src->xs, src->zs, r02,
-                                 stream);
+        e = launch_adjoint_stage(a, g->dtype, 2, vel3d, bdata, U2, lambda, L2, nullptr, L1, gvel, bfold, dt, src->xs,
+                                 src->zs, r02, stream);
     if (e == hipSuccess)  // L2 -> L3 (of U1), acc L1 +=
-        e = launch_adjoint_stage(a, g->dtype, 1, vel3d, U1, L2, L3, L1, L1, gvel, dt, src->xs, src->zs, r02, stream);
-    if (e == hipSuccess)  // L3 -> lambda = L1 + stage 0 terms
-        e = launch_adjoint_stage(a, g->dtype, 0, vel3d, state_n, L3, nullptr, L1, lambda, gvel, dt, src->xs, src->zs,
+        e = launch_adjoint_stage(a, g->dtype, 1, vel3d, bdata, U1, L2, L3, L1, L1, gvel, bfold, dt, src->xs, src->zs,
                                  r02, stream);
+    if (e == hipSuccess)  // L3 -> lambda = L1 + stage 0 terms
+        e = launch_adjoint_stage(a, g->dtype, 0, vel3d, bdata, state_n, L3, nullptr, L1, lambda, gvel, bfold, dt,
+                                 src->xs, src->zs, r02, stream);
     return hip_status(e);
 }
 
 egb_status egb_adjoint_medium(const egb_grid* g, const egb_medium* m, const void* coeff2d, const egb_source* src,
-                              const void* gvel, const void* lambda0, double* grad, void* work, size_t work_bytes,
-                              hipStream_t stream) {
-    if (!grid_ok(g) || !m || !m->vp0 || !m->eps || !m->delta || !coeff2d || !gvel || !lambda0 || !grad || !work ||
-        !source_ok(src))
+                              const void* gvel, const void* lambda0, const void* bfold, double* grad, void* work,
+                              size_t work_bytes, hipStream_t stream) {
+    if (!grid_ok(g) || !m || !m->vp0 || !m->eps || !m->delta || !coeff2d || !gvel || !lambda0 || !bfold || !grad ||
+        !work || !source_ok(src))
         return EGB_EINVAL;
-    if (!aligned16(coeff2d) || !aligned16(gvel) || !aligned16(lambda0) || !aligned16(grad) || !aligned16(work))
+    if (!aligned16(coeff2d) || !aligned16(gvel) || !aligned16(lambda0) || !aligned16(bfold) || !aligned16(grad) ||
+        !aligned16(work))
         return EGB_EINVAL;
     if (work_bytes < egb_workspace_size(g, EGB_OP_ADJOINT)) return EGB_EWORKSPACE;
     char* w = static_cast<char*>(work);
     double* gtab = reinterpret_cast<double*>(w);
     double* gms = reinterpret_cast<double*>(w + align256((size_t)15 * g->nx * g->nz * sizeof(double)));
     return hip_status(launch_adjoint_medium(grid_args(*g), g->dtype, *m, static_cast<const double*>(coeff2d), *src,
-                                            gvel, lambda0, grad, gtab, gms, stream));
+                                            gvel, lambda0, static_cast<const double*>(bfold), grad, gtab, gms,
+                                            stream));
 }
 
 size_t egb_workspace_size_batched(const egb_problem* probs, int32_t nprob) {
@@ -248,8 +268,9 @@ egb_status egb_liouville_step_batched(const egb_problem* probs, int32_t nprob, i
     const int dtype = probs[0].grid.dtype;
     for (int p = 0; p < nprob; ++p) {
         const egb_problem& q = probs[p];
-        if (!grid_ok(&q.grid) || q.grid.dtype != dtype || !q.vel3d || !q.state || !source_ok(&q.src)) return EGB_EINVAL;
-        if (!aligned16(q.vel3d) || !aligned16(q.state)) return EGB_EINVAL;
+        if (!grid_ok(&q.grid) || q.grid.dtype != dtype || !q.vel3d || !q.bdata || !q.state || !source_ok(&q.src))
+            return EGB_EINVAL;
+        if (!aligned16(q.vel3d) || !aligned16(q.bdata) || !aligned16(q.state)) return EGB_EINVAL;
         if (!(q.dt > 0.0) || !isfinite(q.dt)) return EGB_ECFL;
         if (!stage_fits_32bit(grid_args(q.grid), dtype)) return EGB_EUNSUPPORTED;
     }
@@ -269,8 +290,9 @@ egb_status egb_liouville_step_batched(const egb_problem* probs, int32_t nprob, i
         void* U1 = bufs;
         void* U2 = bufs + sb;
         bufs += 2 * sb;
-        const long long n = batch_item_fill(items.data() + (size_t)p * batch_item_bytes(), grid_args(q.grid), dtype, q.vel3d,
-                                      q.state, U1, U2, q.dt, q.src.xs, q.src.zs, q.src.r0 * q.src.r0);
+        const long long n = batch_item_fill(items.data() + (size_t)p * batch_item_bytes(), grid_args(q.grid), dtype,
+                                            q.vel3d, q.bdata, q.state, U1, U2, q.dt, q.src.xs, q.src.zs,
+                                            q.src.r0 * q.src.r0);
         first[p + 1] = first[p] + n;
     }
     const long long total = first[nprob];

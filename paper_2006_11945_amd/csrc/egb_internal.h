@@ -22,10 +22,22 @@ inline size_t state_plane_offset(const egb_grid& g, int p) {
 }
 inline size_t state_bytes(const egb_grid& g) { return state_plane_offset(g, EGB_PSI) + plane_stride(g) * 8; }
 
+// Boundary data: per plane, x ghosts [theta][6][nz] then z ghosts
+// [theta][nx][6], padded to 64 elements; five planes in the grid dtype, psi
+// in double.
+inline size_t bdata_stride(const egb_grid& g) {
+    size_t n = (size_t)g.nth * 6 * ((size_t)g.nx + (size_t)g.nz);
+    return (n + 63) / 64 * 64;
+}
+inline size_t bdata_bytes(const egb_grid& g) { return bdata_stride(g) * (5 * real_size(g) + 8); }
+// Adjoint boundary accumulator (float64): [2 planes: phi1, psi][theta] x
+// ([2 ends][3 sources][2 weights][nz] then [nx][2 ends][3 sources][2 weights]).
+inline size_t bfold_bytes(const egb_grid& g) { return (size_t)2 * g.nth * 12 * ((size_t)g.nx + g.nz) * 8; }
+
 // Geometry passed to kernels by value.
 struct GridArgs {
     int nx, nz, nth;
-    long long nxz, stride;
+    long long nxz, stride, bstride;  // cells per theta slice; plane strides of state and boundary data
     double x0, z0, dx, dz, dth;
 };
 
@@ -36,6 +48,7 @@ inline GridArgs grid_args(const egb_grid& g) {
     a.nth = g.nth;
     a.nxz = (long long)g.nx * g.nz;
     a.stride = (long long)plane_stride(g);
+    a.bstride = (long long)bdata_stride(g);
     a.x0 = g.x0;
     a.z0 = g.z0;
     a.dx = g.dx;
@@ -50,6 +63,7 @@ hipError_t launch_velocity(const GridArgs& a, int dtype, const double* coeff2d, 
                            hipStream_t s);
 hipError_t launch_init_state(const GridArgs& a, int dtype, const double* coeff2d, const egb_source& src, void* state,
                              hipStream_t s);
+hipError_t launch_boundary_data(const GridArgs& a, int dtype, const void* state, void* bdata, hipStream_t s);
 hipError_t launch_pick(const GridArgs& a, int dtype, const void* state, const double* rx, int nr, double* t_out,
                        hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
@@ -58,6 +72,7 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
 struct StageArgs {
     GridArgs g;
     const void* vel;
+    const void* bd;  // boundary data (ghost values)
     const void* U0;
     const void* Uin;
     void* Uout;
@@ -74,8 +89,8 @@ bool stage_fits_32bit(const GridArgs& g, int dtype);
 
 // Batched march (see liouville.hip).
 size_t batch_item_bytes();
-long long batch_item_fill(void* item, const GridArgs& g, int dtype, const void* vel, void* state, void* U1,
-                          void* U2, double dt, double xs, double zs, double r02);
+long long batch_item_fill(void* item, const GridArgs& g, int dtype, const void* vel, const void* bd, void* state,
+                          void* U1, void* U2, double dt, double xs, double zs, double r02);
 // grid <= 0: one round of resident blocks
 hipError_t launch_stage_batched(const void* items, const long long* wfirst, int nprob, long long total, int dtype,
                                 int stage, int grid, hipStream_t s);
@@ -83,14 +98,14 @@ hipError_t launch_stage_batched(const void* items, const long long* wfirst, int 
 // Adjoint of the kinematic march (see adjoint.hip).
 // One reverse stage: lam_in (stages 1, 2) and acc_out = acc_in + ... (see
 // adjoint.hip); lam_out must not alias any output.
-hipError_t launch_adjoint_stage(const GridArgs& g, int dtype, int stage, const void* vel, const void* Uin,
-                                const void* lam_out, void* lam_in, const void* acc_in, void* acc_out, void* gvel,
-                                double dt, double xs, double zs, double r02, hipStream_t s);
+hipError_t launch_adjoint_stage(const GridArgs& g, int dtype, int stage, const void* vel, const void* bd,
+                                const void* Uin, const void* lam_out, void* lam_in, const void* acc_in, void* acc_out,
+                                void* gvel, void* bfold, double dt, double xs, double zs, double r02, hipStream_t s);
 hipError_t launch_pick_adjoint(const GridArgs& a, int dtype, const void* state, const double* rx, int nr,
                                const double* tbar, void* lam, hipStream_t s);
 hipError_t launch_adjoint_medium(const GridArgs& a, int dtype, const egb_medium& m, const double* coeff2d,
-                                 const egb_source& src, const void* gvel, const void* lam0, double* grad, double* gtab,
-                                 double* gms, hipStream_t s);
+                                 const egb_source& src, const void* gvel, const void* lam0, const double* bfold,
+                                 double* grad, double* gtab, double* gms, hipStream_t s);
 
 // Beam superposition.
 struct BeamArgs {

@@ -6,8 +6,9 @@
 // with D the WENO5 Hamilton-Jacobi derivative on the upwind side (D- for a
 // velocity component >= 0, D+ otherwise), then
 //   Uout = ca U0 + cb (Uin + dt L(Uin)),  (ca, cb) = (0,1), (3/4,1/4), (1/3,2/3),
-// and cells inside the source ball copy U0.  Ghosts: x, z by linear
-// extrapolation u_{-m} = (m+1) u_0 - m u_1, theta periodic.
+// and cells inside the source ball copy U0.  Ghosts: x, z from the boundary
+// data (fixed values: the point-source data extended linearly beyond each
+// end), theta periodic.
 //
 // Precision: planes phi1, C, B in R (float or double); psi is stored and
 // combined in double, its WENO differences are formed in double and the
@@ -16,8 +17,8 @@
 // Work decomposition.  A block owns a (z, theta) tile of 64 x TK cells and
 // walks a chunk of x.  Each thread keeps the seven x-neighbours of its own
 // (theta, z) column in registers (a queue shifted once per x step), so the
-// x-stencil and the x-ghosts cost no memory traffic.  The current x slice of
-// the tile, with a 3-cell halo in z (ghosts by extrapolation) and in theta
+// x-stencil costs no extra memory traffic.  The current x slice of the
+// tile, with a 3-cell halo in z (ghosts from the boundary data) and in theta
 // (periodic), sits in LDS (double buffered, one barrier per x step); the z-
 // and theta-stencils read it at immediate offsets.  Blocks are numbered so
 // that consecutive tiles land on the same XCD (shared L2 for the theta halo).
@@ -46,7 +47,7 @@ constexpr int PZ = TZ + 6;   // padded LDS row
 // splits x into nxc chunks of kx; nblocks is the launch's block count.
 struct TileArgs {
     int ntz, ntk, nxc, kx, nblocks;
-    unsigned state_bytes, vel_bytes;
+    unsigned state_bytes, vel_bytes, bd_bytes;
 };
 
 template <typename R, int TK, int NP>
@@ -90,10 +91,11 @@ __device__ __forceinline__ void lds_put(StageSmem<R, TK, NP>& sm, int i, const R
 //
 // Memory traffic inside the x loop is straight-line per lane, so that the
 // waits the compiler places before a use cover only the load that use
-// needs: a z ghost is the two-point extrapolation w0 u(z0) + w1 u(z1) of a
-// halo column (w = (1, 0) inside; the second load only in tiles that touch
-// a z end), an x ghost continues the line of the last two queue entries,
-// and lanes past nz load an in-domain column and write nothing.
+// needs: in tiles that touch a z end every halo lane loads both its state
+// cell (clamped) and a boundary-data value and keeps one of them; the next
+// x queue entry comes from the state or, past nx, from the boundary data
+// (the buffer is chosen per block, the load is the same); lanes past nz
+// load an in-domain column and write nothing.
 template <typename R, int STAGE, int TK, bool KIN>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t, int tile, int x0, int x1,
                                            StageSmem<R, TK, KIN ? 1 : 5>& sm) {
@@ -123,8 +125,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
     const auto rU0 = make_rsrc(a.U0, t.state_bytes);
     const auto rUo = make_rsrc(a.Uout, t.state_bytes);
     const auto rV = make_rsrc(a.vel, t.vel_bytes);
+    const auto rB = make_rsrc(a.bd, t.bd_bytes);
     const unsigned SP = SS * ES;         // bytes per R plane
     const unsigned PSI = 5u * SP;        // byte offset of the psi plane
+    const unsigned BSP = (unsigned)g.bstride * ES;  // boundary data: bytes per R plane
+    const unsigned XG = (unsigned)k * 6u * (unsigned)g.nz + (unsigned)izc;  // x ghost slot 0 of the column
+    const unsigned ZG = (unsigned)g.nth * 6u * (unsigned)g.nz;            // first z ghost
 
     // Halo slot of this thread (if any): theta rows first (whole waves; z
     // clamped into the grid, columns past nz are never read), then z
@@ -133,8 +139,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
     const bool has_halo = tid < NHALO;
     int hk = 0, hz = 0;    // LDS coordinates (0-based, padded)
     unsigned hkb = kb;     // threads without a slot load their own column (unused)
-    int hz0 = izc, hz1 = izc;  // the two global z read for the halo cell
-    R hw0 = (R)1, hw1 = (R)0;
+    int hz0 = izc;         // global z of the halo cell (clamped)
+    bool hgh = false;      // the halo cell is a z ghost
+    unsigned hbo = ZG;     // its boundary-data index at x = 0 (step 6 per x)
     if (tid < 6 * TZ) {
         const int r = tid / TZ;
         hz = tid % TZ + 3;
@@ -142,7 +149,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
         int kk = tki * TK + hk - 3;
         kk = ((kk % g.nth) + g.nth) % g.nth;
         hkb = (unsigned)kk * nxz;
-        hz0 = hz1 = min(tzi * TZ + hz - 3, g.nz - 1);
+        hz0 = min(tzi * TZ + hz - 3, g.nz - 1);
     } else if (has_halo) {
         const int h = tid - 6 * TZ, r = h / TK;
         hk = h % TK + 3;
@@ -151,59 +158,49 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
         kk = kk < g.nth ? kk : kk - g.nth;
         hkb = (unsigned)kk * nxz;
         const int hzg = tzi * TZ + hz - 3;  // a ghost outside [0, nz)
-        hz0 = hz1 = hzg;
-        if (hzg < 0 || hzg >= g.nz) {
-            const int e = hzg < 0 ? -hzg : hzg - (g.nz - 1);
-            hz0 = hzg < 0 ? 0 : g.nz - 1;
-            hz1 = hzg < 0 ? 1 : g.nz - 2;
-            hw0 = (R)(e + 1);
-            hw1 = (R)(-e);
-        }
+        hz0 = min(max(hzg, 0), g.nz - 1);
+        hgh = hzg < 0 || hzg >= g.nz;
+        if (hgh) hbo = ZG + (unsigned)kk * 6u * (unsigned)g.nx + (unsigned)(hzg < 0 ? hzg + 3 : hzg - g.nz + 3);
     }
     const bool z_end = tzi == 0 || tzi == t.ntz - 1 || (tzi + 1) * TZ + 3 > g.nz;  // block-uniform
 
-    // queue of the column's x-neighbours: q[f][j] at x - 3 + j.  x ghosts
-    // continue the line of the two entries next to them, one at a time (the
-    // same recurrence as inside the loop, so the values do not depend on
-    // where a segment starts).
+    // queue of the column's x-neighbours: q[f][j] at x - 3 + j, from the
+    // state inside the grid and from the boundary data beyond either end
+    // (position p: slot p + 3 before x = 0, p - nx + 3 past nx - 1; a slot
+    // past nx + 2 is never used and clamped)
+    auto x_entry = [&](int p, R (&v)[NP], double& vp) {
+        const bool gh = p < 0 || p >= g.nx;  // block-uniform
+        const auto r = gh ? rB : rUi;
+        const unsigned sp = gh ? BSP : SP;
+        const unsigned o = gh ? XG + (unsigned)(min(p < 0 ? p + 3 : p - g.nx + 3, 5) * g.nz)
+                              : kb + (unsigned)(p * g.nz + izc);
+#pragma unroll
+        for (int f = 0; f < NP; ++f) v[f] = bload<R>(r, o * ES, f * sp);
+        vp = bload<double>(r, o * 8u, 5u * sp);
+    };
     R q[NP][7];
     double qp[7];
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
-        const unsigned o = kb + (unsigned)(min(max(x0 - 3 + j, 0), g.nx - 1) * g.nz + izc);
+        R v[NP];
+        x_entry(x0 - 3 + j, v, qp[j]);
 #pragma unroll
-        for (int f = 0; f < NP; ++f) q[f][j] = bload<R>(rUi, o * ES, f * SP);
-        qp[j] = bload<double>(rUi, o * 8u, PSI);
+        for (int f = 0; f < NP; ++f) q[f][j] = v[f];
     }
-#pragma unroll
-    for (int j = 2; j >= 0; --j)
-        if (x0 - 3 + j < 0) {
-#pragma unroll
-            for (int f = 0; f < NP; ++f) q[f][j] = (R)2 * q[f][j + 1] - q[f][j + 2];
-            qp[j] = 2.0 * qp[j + 1] - qp[j + 2];
-        }
-#pragma unroll
-    for (int j = 4; j < 7; ++j)
-        if (x0 - 3 + j >= g.nx) {
-#pragma unroll
-            for (int f = 0; f < NP; ++f) q[f][j] = (R)2 * q[f][j - 1] - q[f][j - 2];
-            qp[j] = 2.0 * qp[j - 1] - qp[j - 2];
-        }
-    // halo loads of slice xs: the two points of every thread (the second
-    // only where the tile touches a z end), combined when written to LDS
+    // halo loads of slice xs: the state cell of every thread and, where the
+    // tile touches a z end, the boundary-data value (kept by ghost lanes)
     R hr0[NP], hr1[NP];
     double hq0, hq1 = 0.0;
     auto halo_load = [&](int xs) {
-        const unsigned xo = hkb + (unsigned)(xs * g.nz);
-        const unsigned o0 = xo + (unsigned)hz0;
+        const unsigned o0 = hkb + (unsigned)(xs * g.nz) + (unsigned)hz0;
 #pragma unroll
         for (int f = 0; f < NP; ++f) hr0[f] = bload<R>(rUi, o0 * ES, f * SP);
         hq0 = bload<double>(rUi, o0 * 8u, PSI);
         if (z_end) {
-            const unsigned o1 = xo + (unsigned)hz1;
+            const unsigned o1 = hbo + (unsigned)(xs * 6);
 #pragma unroll
-            for (int f = 0; f < NP; ++f) hr1[f] = bload<R>(rUi, o1 * ES, f * SP);
-            hq1 = bload<double>(rUi, o1 * 8u, PSI);
+            for (int f = 0; f < NP; ++f) hr1[f] = bload<R>(rB, o1 * ES, f * BSP);
+            hq1 = bload<double>(rB, o1 * 8u, 5u * BSP);
         }
     };
     halo_load(x0);
@@ -240,8 +237,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
             double hp;
             if (z_end) {
 #pragma unroll
-                for (int f = 0; f < NP; ++f) hv[f] = hw0 * hr0[f] + hw1 * hr1[f];
-                hp = (double)hw0 * hq0 + (double)hw1 * hq1;
+                for (int f = 0; f < NP; ++f) hv[f] = hgh ? hr1[f] : hr0[f];
+                hp = hgh ? hq1 : hq0;
             } else {
 #pragma unroll
                 for (int f = 0; f < NP; ++f) hv[f] = hr0[f];
@@ -249,15 +246,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
             }
             lds_put(sm, wb + hi, hv, hp);
         }
-        // next queue entry (x + 4; clamped, replaced by the extrapolation past nx)
+        // next queue entry (x + 4)
         R qn[NP];
         double qpn;
-        {
-            const unsigned o = kb + (unsigned)(min(x + 4, g.nx - 1) * g.nz + izc);
-#pragma unroll
-            for (int f = 0; f < NP; ++f) qn[f] = bload<R>(rUi, o * ES, f * SP);
-            qpn = bload<double>(rUi, o * 8u, PSI);
-        }
+        x_entry(x + 4, qn, qpn);
         // next halo slice and the next cell's velocity (clamped at the chunk end)
         const int xn = min(x + 1, x1 - 1);
         halo_load(xn);
@@ -347,12 +339,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
                 bstore(ball ? p0 : accp, rUo, c8, PSI);
             }
         }
-        // shift the queue (past nx the entry continues the line; block-uniform)
-        if (x + 4 >= g.nx) {
-#pragma unroll
-            for (int f = 0; f < NP; ++f) qn[f] = (R)2 * q[f][6] - q[f][5];
-            qpn = 2.0 * qp[6] - qp[5];
-        }
+        // shift the queue
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
 #pragma unroll
@@ -431,6 +418,9 @@ void k_stage_batched(const BatchItem* __restrict__ items, const long long* __res
 unsigned long long state_bytes_of(const GridArgs& g, size_t es) {
     return (unsigned long long)g.stride * (5ull * es + 8ull);
 }
+unsigned long long bd_bytes_of(const GridArgs& g, size_t es) {
+    return (unsigned long long)g.bstride * (5ull * es + 8ull);
+}
 
 template <typename R, int TK, bool KIN>
 hipError_t launch_stage_t(const StageArgs& a, int stage, hipStream_t s) {
@@ -441,6 +431,7 @@ hipError_t launch_stage_t(const StageArgs& a, int stage, hipStream_t s) {
     t.nxc = 1;
     t.state_bytes = (unsigned)state_bytes_of(a.g, sizeof(R));
     t.vel_bytes = (unsigned)(7ull * (unsigned long long)a.g.stride * sizeof(R));
+    t.bd_bytes = (unsigned)bd_bytes_of(a.g, sizeof(R));
     const void* k = stage == 0 ? (const void*)k_stage<R, 0, TK, KIN>
                   : stage == 1 ? (const void*)k_stage<R, 1, TK, KIN> : (const void*)k_stage<R, 2, TK, KIN>;
     // one round of resident blocks, each with at least MIN_STEPS x steps
@@ -506,8 +497,8 @@ int resident_blocks(const void* kernel, int threads) {
 size_t batch_item_bytes() { return sizeof(BatchItem); }
 
 // Fill the host-side item for one problem; returns its (tile, x) step count.
-long long batch_item_fill(void* item, const GridArgs& g, int dtype, const void* vel, void* state, void* U1, void* U2,
-                    double dt, double xs, double zs, double r02) {
+long long batch_item_fill(void* item, const GridArgs& g, int dtype, const void* vel, const void* bd, void* state,
+                          void* U1, void* U2, double dt, double xs, double zs, double r02) {
     BatchItem& it = *static_cast<BatchItem*>(item);
     const int tk = dtype == EGB_F64 ? 8 : 12;
     const size_t es = dtype == EGB_F64 ? 8 : 4;
@@ -519,12 +510,14 @@ long long batch_item_fill(void* item, const GridArgs& g, int dtype, const void* 
     t.nblocks = 0;
     t.state_bytes = (unsigned)state_bytes_of(g, es);
     t.vel_bytes = (unsigned)(7ull * (unsigned long long)g.stride * es);
+    t.bd_bytes = (unsigned)bd_bytes_of(g, es);
     it.t = t;
     void* in[3] = {state, U1, U2};
     void* out[3] = {U1, U2, state};
     for (int s = 0; s < 3; ++s) {
         it.a[s].g = g;
         it.a[s].vel = vel;
+        it.a[s].bd = bd;
         it.a[s].U0 = state;
         it.a[s].Uin = in[s];
         it.a[s].Uout = out[s];

@@ -166,6 +166,43 @@ __global__ __launch_bounds__(256) void k_init_state(GridArgs a, const double* C,
     Ps[c] = psi;
 }
 
+// Boundary data: thread i < nth*6*nz is x ghost (theta, slot, z), the rest z
+// ghosts (theta, x, slot); slot 0..2 = position -3..-1, 3..5 = n..n+2 of the
+// line; the value continues the line through the two end cells.
+template <typename R>
+__global__ __launch_bounds__(256) void k_boundary_data(GridArgs a, const char* state, char* bd) {
+    const long long nxg = (long long)a.nth * 6 * a.nz, n = (long long)a.nth * 6 * (a.nx + a.nz);
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int gi, len;
+    long long c0, step;  // cell at line position 0 and the stride along the line
+    if (i < nxg) {
+        const int k = (int)(i / (6 * a.nz)), z = (int)(i % a.nz);
+        gi = (int)((i / a.nz) % 6);
+        c0 = (long long)k * a.nxz + z;
+        step = a.nz;
+        len = a.nx;
+    } else {
+        const long long j = i - nxg;
+        const int k = (int)(j / (6 * a.nx)), x = (int)((j / 6) % a.nx);
+        gi = (int)(j % 6);
+        c0 = (long long)k * a.nxz + (long long)x * a.nz;
+        step = 1;
+        len = a.nz;
+    }
+    // ghost at distance m beyond the end cell e, e1 the cell next to e
+    const int m = gi < 3 ? 3 - gi : gi - 2;
+    const long long e = gi < 3 ? c0 : c0 + (long long)(len - 1) * step;
+    const long long e1 = gi < 3 ? c0 + step : c0 + (long long)(len - 2) * step;
+    const R* P = reinterpret_cast<const R*>(state);
+    const double* Ps = reinterpret_cast<const double*>(P + 5 * a.stride);
+    R* B = reinterpret_cast<R*>(bd);
+    double* Bs = reinterpret_cast<double*>(B + 5 * a.bstride);
+    for (int f = 0; f < 5; ++f)
+        B[f * a.bstride + i] = (R)((m + 1) * (double)P[f * a.stride + e] - m * (double)P[f * a.stride + e1]);
+    Bs[i] = (m + 1) * Ps[e] - m * Ps[e1];
+}
+
 // One thread per receiver; see egb_pick_receivers.
 template <typename R>
 __global__ void k_pick(GridArgs a, const char* state, const double* rx, int nr, double* t_out) {
@@ -238,6 +275,16 @@ hipError_t launch_init_state(const GridArgs& a, int dtype, const double* C, cons
         k_init_state<double><<<cell_grid(a), dim3(64, 4), 0, s>>>(a, C, src, (char*)state);
     else
         k_init_state<float><<<cell_grid(a), dim3(64, 4), 0, s>>>(a, C, src, (char*)state);
+    return hipGetLastError();
+}
+
+hipError_t launch_boundary_data(const GridArgs& a, int dtype, const void* state, void* bdata, hipStream_t s) {
+    const long long n = (long long)a.nth * 6 * (a.nx + a.nz);
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (dtype == EGB_F64)
+        k_boundary_data<double><<<blocks, 256, 0, s>>>(a, (const char*)state, (char*)bdata);
+    else
+        k_boundary_data<float><<<blocks, 256, 0, s>>>(a, (const char*)state, (char*)bdata);
     return hipGetLastError();
 }
 

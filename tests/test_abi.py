@@ -58,12 +58,24 @@ def test_sizes_and_validation_without_gpu():
     src = egb.EgbSource(1.0, 1.0, 1.0, 1e-4)
     assert L.egb_init_state(ctypes.byref(bad), None, ctypes.byref(src), None, None) == egb.EGB_EINVAL
     assert L.egb_init_state(None, None, None, None, None) == egb.EGB_EINVAL
-    assert L.egb_liouville_step(ctypes.byref(eg), ctypes.c_void_p(256), ctypes.byref(src), ctypes.c_void_p(256),
-                                ctypes.c_void_p(256), 1 << 30, -1.0, 1, None) == egb.EGB_ECFL
-    assert L.egb_liouville_step(ctypes.byref(eg), ctypes.c_void_p(256), ctypes.byref(src), ctypes.c_void_p(256),
-                                ctypes.c_void_p(256), 16, 1e-3, 1, None) == egb.EGB_EWORKSPACE
-    assert L.egb_liouville_step(ctypes.byref(eg), ctypes.c_void_p(258), ctypes.byref(src), ctypes.c_void_p(256),
-                                ctypes.c_void_p(256), 1 << 30, 1e-3, 1, None) == egb.EGB_EINVAL
+    P = ctypes.c_void_p
+    assert L.egb_liouville_step(ctypes.byref(eg), P(256), ctypes.byref(src), P(256), P(256), P(256), 1 << 30, -1.0,
+                                1, None) == egb.EGB_ECFL
+    assert L.egb_liouville_step(ctypes.byref(eg), P(256), ctypes.byref(src), P(256), P(256), P(256), 16, 1e-3, 1,
+                                None) == egb.EGB_EWORKSPACE
+    assert L.egb_liouville_step(ctypes.byref(eg), P(258), ctypes.byref(src), P(256), P(256), P(256), 1 << 30, 1e-3,
+                                1, None) == egb.EGB_EINVAL
+    # the boundary data is required and aligned
+    assert L.egb_liouville_step(ctypes.byref(eg), P(256), ctypes.byref(src), None, P(256), P(256), 1 << 30, 1e-3, 1,
+                                None) == egb.EGB_EINVAL
+    assert L.egb_liouville_step(ctypes.byref(eg), P(256), ctypes.byref(src), P(264), P(256), P(256), 1 << 30, 1e-3,
+                                1, None) == egb.EGB_EINVAL
+    assert L.egb_boundary_data(ctypes.byref(eg), None, P(256), None) == egb.EGB_EINVAL
+    bs = egb.bdata_plane_stride(eg)
+    assert bs >= 36 * 6 * (40 + 72) and bs % 64 == 0
+    assert egb.bdata_bytes(eg) == 5 * bs * 4 + bs * 8
+    assert egb.bdata_bytes(eg64) == 6 * bs * 8
+    assert egb.bfold_bytes(eg) == 2 * 36 * 12 * (40 + 72) * 8
     nosrc = egb.EgbSource(1.0, 1.0, 1.0, 0.0)  # beta must be > 0
     assert L.egb_init_state(ctypes.byref(eg), ctypes.c_void_p(256), ctypes.byref(nosrc), ctypes.c_void_p(256),
                             None) == egb.EGB_EINVAL

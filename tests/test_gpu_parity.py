@@ -88,6 +88,45 @@ def test_table_velocity_init(dtype, tilt):
         assert rel_err(G[name], O[name], max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())) < t_, name
 
 
+def boundary_views(eg, bdata):
+    """Named (x ghosts [nth][6][nz], z ghosts [nth][nx][6]) views of the
+    boundary data, in float64."""
+    e = egb()
+    bs = e.bdata_plane_stride(eg)
+    nxg, nzg = eg.nth * 6 * eg.nz, eg.nth * eg.nx * 6
+    rd = e.real_dtype(eg)
+    es = torch.empty((), dtype=rd).element_size()
+    out = {}
+    for p, name in enumerate(e.STATE_PLANES):
+        dt, off = (torch.float64, 5 * bs * es) if p == e.EGB_PSI else (rd, p * bs * es)
+        flat = bdata[off:off + bs * torch.empty((), dtype=dt).element_size()].view(dt).double().cpu().numpy()
+        out[name] = (flat[:nxg].reshape(eg.nth, 6, eg.nz), flat[nxg:nxg + nzg].reshape(eg.nth, eg.nx, 6))
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_boundary_data(dtype):
+    """Ghost values: the oracle's point-source data continued linearly past
+    both ends of every x and z line (three cells each side)."""
+    p = ragged_problem(dtype=dtype, tilt=True)
+    o = oracle.solve(p, nsteps=0)
+    s = run_gpu(p, dtype, 0)
+    B = boundary_views(s.eg, s.bdata)
+    O = oracle_planes(rounded_oracle_state(o["U0"], dtype))
+    for name, u in O.items():
+        ex = np.empty((p.grid.nth, 6, p.grid.nz))
+        ez = np.empty((p.grid.nth, p.grid.nx, 6))
+        for m in (1, 2, 3):
+            ex[:, 3 - m] = (m + 1) * u[:, 0, :] - m * u[:, 1, :]
+            ex[:, 2 + m] = (m + 1) * u[:, -1, :] - m * u[:, -2, :]
+            ez[:, :, 3 - m] = (m + 1) * u[:, :, 0] - m * u[:, :, 1]
+            ez[:, :, 2 + m] = (m + 1) * u[:, :, -1] - m * u[:, :, -2]
+        tol = 1e-13 if (dtype == "f64" or name == "psi") else 2e-7
+        sc = max(np.abs(ex).max(), np.abs(ez).max(), 1e-300)
+        assert rel_err(B[name][0], ex, sc) < tol, name
+        assert rel_err(B[name][1], ez, sc) < tol, name
+
+
 @pytest.mark.parametrize("tilt", [False, True])
 def test_march_parity_f32(tilt):
     p = ragged_problem(tilt=tilt, nsteps=40)
