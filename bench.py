@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--batched-problems", type=int, default=64)
     ap.add_argument("--adjoint-sources", type=int, default=2,
                     help="sources of the 16-source adjoint workload to time (0 skips it)")
+    ap.add_argument("--paraxial-sources", type=int, default=16,
+                    help="surface sources picked from the paraxial depth march of the same medium (0 skips it)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the run, copy a device buffer of this size (a plain copy kernel of known "
                          "size, to scale HBM byte counters)")
@@ -142,6 +144,57 @@ def adjoint_vs_forward(nsrc, nsteps, n=256):
     return {"sources": nsrc, "rk3_steps": nsteps, "receivers": 128, "checkpoint_every": 16,
             "forward_s": t_fwd, "backward_s": t_bwd, "plain_forward_s": t_plain,
             "backward_cell_updates_per_s": cu / t_bwd, "backward_over_plain_forward": t_bwd / t_plain}
+
+
+# Paraxial stage: 7 planes x 2 axes of WENO5, convection, sources, the
+# stage combine and the coefficient interpolation, per cell and RK stage.
+FLOP_PCELL_STAGE = 14 * FLOP_WENO + 7 * 2 * 2 + 17 + 7 * 4 + 7 * 3
+
+
+def paraxial_leg(n, nsrc, nth=256, theta_max=None):
+    """The paraxial depth march (the paper's own formulation) on the same
+    medium: 256 x 256 slice of 256 theta nodes in (-60, 60) degrees, all 256
+    depth levels, first arrivals of `nsrc` surface sources from the one march."""
+    from dataclasses import replace
+
+    import numpy as np
+    import torch
+
+    import paper_2006_11945_amd as egb
+    import workloads as W
+
+    theta_max = np.pi / 3 if theta_max is None else theta_max
+    p = W.vti_256(n=n, nsteps=1)
+    g = replace(p.grid, nth=nth)
+    L = g.nx * g.dx
+    P = egb.Paraxial(g, p.medium, theta_max, "cuda:0", "f32")
+    P.velocity()
+    nsub = P.substeps()
+    xs = np.linspace(0.1 * L, 0.9 * L, nsrc)
+    P.init(1.0 / (2 * L))
+    P.march(nsub)  # warm-up
+    P.init(1.0 / (2 * L))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.march(nsub)
+    t1 = time.perf_counter()
+    T = P.pick(xs)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    launches = 3 * nsub * (g.nz - 1)
+    cells = g.nx * nth
+    stage_ms = (t1 - t0) * 1e3 / launches
+    achieved = cells * FLOP_PCELL_STAGE / (stage_ms * 1e-3) / 1e12
+    return {"grid": [g.nx, g.nz, nth], "theta_max_deg": float(np.degrees(theta_max)), "substeps_per_level": nsub,
+            "stage_launches": launches, "march_s": t1 - t0, "pick_s": t2 - t1, "sources": nsrc,
+            "arrival_fraction": float(torch.isfinite(T).float().mean()),
+            "cell_updates_per_s": cells * nsub * (g.nz - 1) / (t1 - t0),
+            "roofline": {"bound": "alu", "kernel": "k_pstage (one depth-substep RK3 stage)",
+                         "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                         "avg_launch_ms": stage_ms, "flop_per_cell_stage": FLOP_PCELL_STAGE,
+                         "note": "march wall time (graph capture, instantiation and launch gaps included) "
+                                 "divided by the stage launches"}}
 
 
 # sources the stage kernel is built from (the traffic record names their hash)
@@ -276,6 +329,9 @@ def main():
         torch.cuda.empty_cache()
     if args.adjoint_sources > 0:
         res["adjoint"] = adjoint_vs_forward(args.adjoint_sources, args.rk_steps, args.n)
+        torch.cuda.empty_cache()
+    if args.paraxial_sources > 0:
+        res["paraxial"] = paraxial_leg(args.n, args.paraxial_sources)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(W.vti_256(n=args.n, nsteps=1))

@@ -65,7 +65,7 @@ enum { EGB_VX = 0, EGB_VZ = 1, EGB_VT = 2, EGB_A11 = 3, EGB_A12 = 4, EGB_A21 = 5
 enum { EGB_NFIELD = 5, EGB_NTAYLOR = 6 };
 
 /* Workspace queries (egb_workspace_size op argument). */
-enum { EGB_OP_VELOCITY = 0, EGB_OP_STEP = 1, EGB_OP_BEAM = 2, EGB_OP_ADJOINT = 3 };
+enum { EGB_OP_VELOCITY = 0, EGB_OP_STEP = 1, EGB_OP_BEAM = 2, EGB_OP_ADJOINT = 3, EGB_OP_PARAXIAL = 4 };
 
 typedef struct {
     int32_t nx, nz, nth; /* cells in x, z (>= 8) and theta (>= 8) */
@@ -244,6 +244,61 @@ egb_status egb_adjoint_step(const egb_grid *g, const void *vel3d, const egb_sour
 egb_status egb_adjoint_medium(const egb_grid *g, const egb_medium *m, const void *coeff2d, const egb_source *src,
                               const void *gvel, const void *lambda0, const void *bfold, double *grad, void *work,
                               size_t work_bytes, hipStream_t stream);
+
+/* ------------------------------------------------ paraxial depth march
+ * The paper's own formulation (eqs. 13-15, 16-24): the Liouville equations
+ * divided by dz/dtau, marched in depth on (x, theta) slices with theta in
+ * (-theta_max, theta_max), dtheta = 2 theta_max / nth, theta_k = -theta_max +
+ * (k + 1/2) dtheta.  Level state (one per depth z_n, n = 0 .. nz-1): X (the
+ * surface position of the ray, eqs. 17, 19), vartheta (its take-off angle),
+ * C, B (eqs. 21-24) and tau (traveltime, eq. 19).  One march serves every
+ * surface source: the first arrival from a source at x_s is read on the level
+ * set X = x_s (eq. 35).  Layout of one level: planes X, vartheta, Re C, Im C,
+ * Re B, Im B in the grid dtype, then tau in float64, each [theta][x] (x
+ * fastest) padded to egb_paraxial_plane_stride() elements; `levels` holds nz
+ * levels of egb_paraxial_level_bytes() each.  The grid's nth counts the
+ * theta nodes of the aperture; z0 is the depth of level 0 (the surface).
+ * Coefficients `pvel`: [nz][7][stride] in the grid dtype, planes
+ * u = V_x/V_z, w = V_theta/V_z, S_tau = 1/V_z, A11..A22 / V_z. */
+size_t egb_paraxial_plane_stride(const egb_grid *g);
+size_t egb_paraxial_level_bytes(const egb_grid *g);
+size_t egb_paraxial_vel_bytes(const egb_grid *g);
+
+/* Medium table alone (the first part of egb_hamiltonian_velocity, eqs. 4-5).
+ * Out: coeff2d (egb_coeff2d_bytes). */
+egb_status egb_medium_table(const egb_grid *g, const egb_medium *m, void *coeff2d, hipStream_t stream);
+
+/* Depth-march coefficients (eqs. 8-9, 12 and 21 divided by dz/dtau, eq. 13)
+ * at every level and theta node from the medium table.  Out: pvel
+ * (egb_paraxial_vel_bytes); *rate (host) = max(|u|/dx + |w|/dtheta), so that
+ * nsub >= dz rate / 0.5 substeps per level keep the march stable.
+ * 0 < theta_max <= pi/2; EGB_EINVAL if V_z <= 0 at some node (rays that do
+ * not go down: beyond the paraxial range of this medium).  work:
+ * egb_workspace_size(g, EGB_OP_VELOCITY).  Synchronises `stream` once. */
+egb_status egb_paraxial_velocity(const egb_grid *g, const void *coeff2d, double theta_max, void *pvel,
+                                 double *rate, void *work, size_t work_bytes, hipStream_t stream);
+
+/* Surface data on level 0 (eqs. 20, 24 on the surface line): X = x,
+ * vartheta = theta, tau = 0, C = cos(theta) + sin(theta) u, B = i beta C. */
+egb_status egb_paraxial_init(const egb_grid *g, const void *pvel, double theta_max, double beta, void *levels,
+                             hipStream_t stream);
+
+/* March levels 0 -> nz-1: each depth interval is nsub SSP-RK3 steps of
+ * dz/nsub of U_z + u U_x + w U_theta = S (S_tau = 1/V_z, S_(C,B) = A/V_z (C,
+ * B), the rest zero) with WENO5 upwind x and theta derivatives, the
+ * coefficients linear in z between the two levels; x and theta ghosts
+ * continue the line of the two cells next to them.  In: level 0 of levels.
+ * Out: levels 1 .. nz-1.  work: egb_workspace_size(g, EGB_OP_PARAXIAL).  The
+ * 3 nsub (nz - 1) stage launches run as one hipGraph; synchronises `stream`. */
+egb_status egb_paraxial_march(const egb_grid *g, const void *pvel, double theta_max, int32_t nsub, void *levels,
+                              void *work, size_t work_bytes, hipStream_t stream);
+
+/* First arrivals of nsrc surface sources at every (x_i, z_n): roots in theta
+ * of X - x_s between adjacent nodes (linear interpolation of X and tau), the
+ * smallest tau > 0; NaN where there is none.  In: xs (device float64 [nsrc]).
+ * Out: T (device float64 [nsrc][nz][nx]). */
+egb_status egb_paraxial_pick(const egb_grid *g, const void *levels, const double *xs, int32_t nsrc, double *T,
+                             hipStream_t stream);
 
 /* Human-readable text for a status code (static storage). */
 const char *egb_status_string(int32_t status);

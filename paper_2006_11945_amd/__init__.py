@@ -25,9 +25,11 @@ LIB_PATH = os.path.join(HERE, "libegb.so")
 EGB_OK, EGB_EINVAL, EGB_ECFL, EGB_EWORKSPACE, EGB_EHIP, EGB_ENONFINITE, EGB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 EGB_F32, EGB_F64 = 0, 1
 EGB_PHI1, EGB_RE_C, EGB_IM_C, EGB_RE_B, EGB_IM_B, EGB_PSI = range(6)
-EGB_OP_VELOCITY, EGB_OP_STEP, EGB_OP_BEAM, EGB_OP_ADJOINT = range(4)
+EGB_OP_VELOCITY, EGB_OP_STEP, EGB_OP_BEAM, EGB_OP_ADJOINT, EGB_OP_PARAXIAL = range(5)
 STATE_PLANES = ("phi1", "ReC", "ImC", "ReB", "ImB", "psi")
 VEL_PLANES = ("Vx", "Vz", "Vt", "A11", "A12", "A21", "A22")
+PAR_PLANES = ("X", "vartheta", "ReC", "ImC", "ReB", "ImB", "tau")   # paraxial level planes, in memory order
+PVEL_PLANES = ("u", "w", "Stau", "A11", "A12", "A21", "A22")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2006_11945_amd/build.py` "
@@ -65,7 +67,8 @@ def _load():
     vp, sz, i32, d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double
     dp = ctypes.POINTER(ctypes.c_double)
     for name in ("egb_plane_stride", "egb_coeff2d_bytes", "egb_vel3d_bytes", "egb_state_bytes", "egb_bdata_bytes",
-                 "egb_bdata_plane_stride", "egb_bfold_bytes"):
+                 "egb_bdata_plane_stride", "egb_bfold_bytes", "egb_paraxial_plane_stride", "egb_paraxial_level_bytes",
+                 "egb_paraxial_vel_bytes"):
         getattr(L, name).argtypes = [G]
         getattr(L, name).restype = sz
     L.egb_state_plane_offset.argtypes = [G, i32]; L.egb_state_plane_offset.restype = sz
@@ -89,6 +92,14 @@ def _load():
     L.egb_liouville_step_batched.restype = ctypes.c_int
     for name in ("egb_hamiltonian_velocity", "egb_init_state", "egb_boundary_data", "egb_liouville_step",
                  "egb_beam_sum", "egb_pick_receivers"):
+        getattr(L, name).restype = ctypes.c_int
+    L.egb_medium_table.argtypes = [G, M, vp, vp]
+    L.egb_paraxial_velocity.argtypes = [G, vp, d, vp, dp, vp, sz, vp]
+    L.egb_paraxial_init.argtypes = [G, vp, d, d, vp, vp]
+    L.egb_paraxial_march.argtypes = [G, vp, d, i32, vp, vp, sz, vp]
+    L.egb_paraxial_pick.argtypes = [G, vp, vp, i32, vp, vp]
+    for name in ("egb_medium_table", "egb_paraxial_velocity", "egb_paraxial_init", "egb_paraxial_march",
+                 "egb_paraxial_pick"):
         getattr(L, name).restype = ctypes.c_int
     L.egb_status_string.argtypes = [i32]; L.egb_status_string.restype = ctypes.c_char_p
     return L
@@ -217,6 +228,41 @@ def egb_adjoint_medium(eg, medium: "DeviceMedium", coeff2d, src: EgbSource, gvel
     _check("egb_adjoint_medium", rc)
 
 
+def paraxial_plane_stride(eg) -> int: return _lib.egb_paraxial_plane_stride(ctypes.byref(eg))
+def paraxial_level_bytes(eg) -> int: return _lib.egb_paraxial_level_bytes(ctypes.byref(eg))
+def paraxial_vel_bytes(eg) -> int: return _lib.egb_paraxial_vel_bytes(ctypes.byref(eg))
+
+
+def egb_medium_table(eg, medium: "DeviceMedium", coeff2d, stream=None):
+    _check("egb_medium_table", _lib.egb_medium_table(ctypes.byref(eg), ctypes.byref(medium.struct()), _ptr(coeff2d),
+                                                     _stream(stream)))
+
+
+def egb_paraxial_velocity(eg, coeff2d, theta_max: float, pvel, work, stream=None) -> float:
+    rate = ctypes.c_double(0.0)
+    rc = _lib.egb_paraxial_velocity(ctypes.byref(eg), _ptr(coeff2d), float(theta_max), _ptr(pvel), ctypes.byref(rate),
+                                    _ptr(work), work.numel(), _stream(stream))
+    _check("egb_paraxial_velocity", rc)
+    return rate.value
+
+
+def egb_paraxial_init(eg, pvel, theta_max: float, beta: float, levels, stream=None):
+    _check("egb_paraxial_init", _lib.egb_paraxial_init(ctypes.byref(eg), _ptr(pvel), float(theta_max), float(beta),
+                                                       _ptr(levels), _stream(stream)))
+
+
+def egb_paraxial_march(eg, pvel, theta_max: float, nsub: int, levels, work, stream=None):
+    rc = _lib.egb_paraxial_march(ctypes.byref(eg), _ptr(pvel), float(theta_max), int(nsub), _ptr(levels), _ptr(work),
+                                 work.numel(), _stream(stream))
+    _check("egb_paraxial_march", rc)
+
+
+def egb_paraxial_pick(eg, levels, xs, T, stream=None):
+    n = 0 if xs is None else xs.numel()
+    _check("egb_paraxial_pick", _lib.egb_paraxial_pick(ctypes.byref(eg), _ptr(levels), _ptr(xs), n, _ptr(T),
+                                                       _stream(stream)))
+
+
 def make_problem_array(solvers, dts=None):
     """ctypes array of egb_problem from Solver objects (their own dt_cfl unless given)."""
     arr = (EgbProblem * len(solvers))()
@@ -338,6 +384,71 @@ class Solver:
 
     def vel_planes(self) -> dict:
         return vel_views(self.eg, self.vel3d)
+
+
+def paraxial_level_views(eg, levels: torch.Tensor, n: int) -> dict:
+    """Named [nth][nx] views of level n of a paraxial levels buffer."""
+    lb, st = paraxial_level_bytes(eg), paraxial_plane_stride(eg)
+    rd = real_dtype(eg)
+    es = torch.empty((), dtype=rd).element_size()
+    base = levels[n * lb:(n + 1) * lb]
+    out = {}
+    for q, name in enumerate(PAR_PLANES):
+        dt, off = (torch.float64, 6 * st * es) if name == "tau" else (rd, q * st * es)
+        e = torch.empty((), dtype=dt).element_size()
+        out[name] = base[off:off + eg.nth * eg.nx * e].view(dt).view(eg.nth, eg.nx)
+    return out
+
+
+class Paraxial:
+    """Buffers and call sequence of the paraxial depth march for one medium:
+    medium table, coefficients, surface data, march, first-arrival picks of
+    any number of surface sources.  theta_max: half aperture (rad)."""
+
+    def __init__(self, grid, medium, theta_max: float, device="cuda", dtype: str = "f32"):
+        self.device = torch.device(device)
+        self.eg = make_grid(grid, dtype)
+        self.theta_max = float(theta_max)
+        self.medium = DeviceMedium.from_numpy(medium, self.device)
+        eg = self.eg
+        self.coeff2d = alloc_bytes(coeff2d_bytes(eg), self.device)
+        self.pvel = alloc_bytes(paraxial_vel_bytes(eg), self.device)
+        self.levels = alloc_bytes(eg.nz * paraxial_level_bytes(eg), self.device)
+        self.work_vel = alloc_bytes(workspace_size(eg, EGB_OP_VELOCITY), self.device)
+        self.work = alloc_bytes(workspace_size(eg, EGB_OP_PARAXIAL), self.device)
+        self.rate = None
+
+    def velocity(self, stream=None) -> float:
+        egb_medium_table(self.eg, self.medium, self.coeff2d, stream)
+        self.rate = egb_paraxial_velocity(self.eg, self.coeff2d, self.theta_max, self.pvel, self.work_vel, stream)
+        return self.rate
+
+    def substeps(self, cfl: float = 0.5) -> int:
+        """RK3 substeps per depth interval: dz / nsub * rate <= cfl."""
+        return max(1, int(np.ceil(self.eg.dz * self.rate / cfl - 1e-12)))
+
+    def init(self, beta: float, stream=None):
+        egb_paraxial_init(self.eg, self.pvel, self.theta_max, beta, self.levels, stream)
+
+    def march(self, nsub: Optional[int] = None, stream=None):
+        egb_paraxial_march(self.eg, self.pvel, self.theta_max, self.substeps() if nsub is None else nsub,
+                           self.levels, self.work, stream)
+
+    def pick(self, xs, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        x = torch.as_tensor(np.ascontiguousarray(np.atleast_1d(xs), dtype=np.float64), device=self.device)
+        if out is None:
+            out = torch.empty((x.numel(), self.eg.nz, self.eg.nx), dtype=torch.float64, device=self.device)
+        egb_paraxial_pick(self.eg, self.levels, x, out, stream)
+        return out
+
+    def level(self, n: int) -> dict:
+        return paraxial_level_views(self.eg, self.levels, n)
+
+    def pvel_level(self, n: int) -> dict:
+        st = paraxial_plane_stride(self.eg)
+        flat = self.pvel.view(real_dtype(self.eg))[n * 7 * st:(n + 1) * 7 * st]
+        m = self.eg.nth * self.eg.nx
+        return {name: flat[q * st:q * st + m].view(self.eg.nth, self.eg.nx) for q, name in enumerate(PVEL_PLANES)}
 
 
 class TravelTime(torch.autograd.Function):

@@ -70,6 +70,7 @@ size_t egb_workspace_size(const egb_grid* g, int32_t op) {
         case EGB_OP_STEP: return 2 * align256(state_bytes(*g));
         case EGB_OP_BEAM:
             return beam_counts_bytes(*g) + (size_t)(g->nx + g->nz) * beam_cap_default(*g) * beam_record_bytes();
+        case EGB_OP_PARAXIAL: return 2 * align256(paraxial_level_bytes(*g));
         case EGB_OP_ADJOINT: {
             const size_t step = 5 * align256(state_bytes(*g));
             const size_t med = align256((size_t)15 * g->nx * g->nz * sizeof(double)) +
@@ -103,6 +104,15 @@ egb_status egb_hamiltonian_velocity(const egb_grid* g, const egb_medium* m, void
     if (!(r > 0.0) || !isfinite(r)) return EGB_ENONFINITE;
     *dt_cfl = 0.5 / r;
     return EGB_OK;
+}
+
+egb_status egb_medium_table(const egb_grid* g, const egb_medium* m, void* coeff2d, hipStream_t stream) {
+    if (!grid_ok(g) || !m || !m->vp0 || !m->eps || !m->delta || !coeff2d) return EGB_EINVAL;
+    if (!(m->vs_ratio >= 0.0) || !(m->vs_ratio < 1.0)) return EGB_EINVAL;
+    if (!aligned16(coeff2d) || !aligned16(m->vp0) || !aligned16(m->eps) || !aligned16(m->delta) ||
+        (m->tilt && !aligned16(m->tilt)))
+        return EGB_EINVAL;
+    return hip_status(launch_medium_table(grid_args(*g), *m, static_cast<double*>(coeff2d), stream));
 }
 
 egb_status egb_init_state(const egb_grid* g, const void* coeff2d, const egb_source* src, void* state,
@@ -250,6 +260,113 @@ egb_status egb_adjoint_medium(const egb_grid* g, const egb_medium* m, const void
     return hip_status(launch_adjoint_medium(grid_args(*g), g->dtype, *m, static_cast<const double*>(coeff2d), *src,
                                             gvel, lambda0, static_cast<const double*>(bfold), grad, gtab, gms,
                                             stream));
+}
+
+size_t egb_paraxial_plane_stride(const egb_grid* g) { return grid_ok(g) ? paraxial_stride(*g) : 0; }
+size_t egb_paraxial_level_bytes(const egb_grid* g) { return grid_ok(g) ? paraxial_level_bytes(*g) : 0; }
+size_t egb_paraxial_vel_bytes(const egb_grid* g) { return grid_ok(g) ? paraxial_vel_bytes(*g) : 0; }
+
+static bool theta_max_ok(double t) { return isfinite(t) && t > 0.0 && t <= 1.5707963267948966; }
+
+egb_status egb_paraxial_velocity(const egb_grid* g, const void* coeff2d, double theta_max, void* pvel,
+                                 double* rate_out, void* work, size_t work_bytes, hipStream_t stream) {
+    if (!grid_ok(g) || !coeff2d || !pvel || !rate_out || !work || !theta_max_ok(theta_max)) return EGB_EINVAL;
+    if (!aligned16(coeff2d) || !aligned16(pvel) || !aligned16(work)) return EGB_EINVAL;
+    if (work_bytes < egb_workspace_size(g, EGB_OP_VELOCITY)) return EGB_EWORKSPACE;
+    unsigned long long* rate = static_cast<unsigned long long*>(work);
+    hipError_t e = launch_fill_u64(rate, 1, 0ull, stream);
+    if (e == hipSuccess)
+        e = launch_pvelocity(grid_args(*g), g->dtype, theta_max, static_cast<const double*>(coeff2d), pvel,
+                             (long long)paraxial_stride(*g), rate, stream);
+    unsigned long long bits = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bits, rate, sizeof(bits), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return EGB_EHIP;
+    double r;
+    memcpy(&r, &bits, sizeof(r));
+    if (!isfinite(r)) return EGB_EINVAL;  // V_z <= 0 inside (-theta_max, theta_max): beyond the paraxial range
+    *rate_out = r;
+    return EGB_OK;
+}
+
+egb_status egb_paraxial_init(const egb_grid* g, const void* pvel, double theta_max, double beta, void* levels,
+                             hipStream_t stream) {
+    if (!grid_ok(g) || !pvel || !levels || !theta_max_ok(theta_max) || !isfinite(beta) || !(beta > 0.0))
+        return EGB_EINVAL;
+    if (!aligned16(pvel) || !aligned16(levels)) return EGB_EINVAL;
+    return hip_status(launch_pinit(g->nx, g->nth, (long long)paraxial_stride(*g), g->x0, g->dx, theta_max, beta,
+                                   g->dtype, pvel, levels, stream));
+}
+
+egb_status egb_paraxial_march(const egb_grid* g, const void* pvel, double theta_max, int32_t nsub, void* levels,
+                              void* work, size_t work_bytes, hipStream_t stream) {
+    if (!grid_ok(g) || !pvel || !levels || !work || !theta_max_ok(theta_max) || nsub < 1) return EGB_EINVAL;
+    if (!aligned16(pvel) || !aligned16(levels) || !aligned16(work)) return EGB_EINVAL;
+    if (work_bytes < egb_workspace_size(g, EGB_OP_PARAXIAL)) return EGB_EWORKSPACE;
+    const size_t lb = paraxial_level_bytes(*g);
+    const long long P = (long long)paraxial_stride(*g);
+    const size_t vb = (size_t)7 * P * real_size(*g);  // coefficient bytes per level
+    char* lev = static_cast<char*>(levels);
+    const char* pv = static_cast<const char*>(pvel);
+    void* U1 = work;
+    void* U2 = static_cast<char*>(work) + align256(lb);
+    PStageArgs a;
+    a.nx = g->nx;
+    a.nth = g->nth;
+    a.P = P;
+    a.dx = g->dx;
+    a.dth = 2.0 * theta_max / g->nth;
+    const double h = 1.0 / nsub;
+    a.dl = g->dz * h;
+    // the whole march (3 nsub (nz - 1) stage launches) as one graph replayed on `stream`
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = hipSuccess;
+        for (int n = 0; n + 1 < g->nz && le == hipSuccess; ++n) {
+            a.pv0 = pv + (size_t)n * vb;
+            a.pv1 = pv + (size_t)(n + 1) * vb;
+            void* next = lev + (size_t)(n + 1) * lb;
+            for (int j = 0; j < nsub && le == hipSuccess; ++j) {
+                const double s0 = j * h;
+                a.U0 = j == 0 ? lev + (size_t)n * lb : next;  // the substep's start
+                a.Uin = a.U0;
+                a.Uout = U1;
+                a.s = s0;
+                le = launch_pstage(a, g->dtype, 0, cs);
+                if (le != hipSuccess) break;
+                a.Uin = U1;
+                a.Uout = U2;
+                a.s = s0 + h;
+                le = launch_pstage(a, g->dtype, 1, cs);
+                if (le != hipSuccess) break;
+                a.Uin = U2;
+                a.Uout = next;  // in place for j > 0: each cell reads the start only at itself
+                a.s = s0 + 0.5 * h;
+                le = launch_pstage(a, g->dtype, 2, cs);
+            }
+        }
+        e = hipStreamEndCapture(cs, &graph);
+        if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    if (cs) hipStreamDestroy(cs);
+    return hip_status(e);
+}
+
+egb_status egb_paraxial_pick(const egb_grid* g, const void* levels, const double* xs, int32_t nsrc, double* T,
+                             hipStream_t stream) {
+    if (!grid_ok(g) || !levels || nsrc < 0 || (nsrc > 0 && (!xs || !T))) return EGB_EINVAL;
+    if (!aligned16(levels) || (xs && ((uintptr_t)xs & 7u)) || (T && ((uintptr_t)T & 7u))) return EGB_EINVAL;
+    return hip_status(launch_ppick(g->nx, g->nz, g->nth, (long long)paraxial_stride(*g), g->dtype, levels,
+                                   paraxial_level_bytes(*g), xs, nsrc, T, stream));
 }
 
 size_t egb_workspace_size_batched(const egb_problem* probs, int32_t nprob) {

@@ -107,6 +107,32 @@ hipError_t launch_adjoint_medium(const GridArgs& a, int dtype, const egb_medium&
                                  const egb_source& src, const void* gvel, const void* lam0, const double* bfold,
                                  double* grad, double* gtab, double* gms, hipStream_t s);
 
+// Paraxial depth march (see paraxial.hip).  Level planes: six in the grid
+// dtype, then tau in double, each of paraxial_stride() elements.
+inline size_t paraxial_stride(const egb_grid& g) {
+    size_t n = (size_t)g.nth * (size_t)g.nx;
+    return (n + 63) / 64 * 64;
+}
+inline size_t paraxial_level_bytes(const egb_grid& g) { return paraxial_stride(g) * (6 * real_size(g) + 8); }
+inline size_t paraxial_vel_bytes(const egb_grid& g) { return (size_t)g.nz * 7 * paraxial_stride(g) * real_size(g); }
+struct PStageArgs {
+    int nx, nth;
+    long long P;               // plane stride (elements)
+    double dx, dth, dl, s;     // dl: the substep in z; s: stage depth as a fraction of the level interval
+    const void* pv0;           // coefficients at the interval's two levels
+    const void* pv1;
+    const void* U0;            // the substep's starting state
+    const void* Uin;
+    void* Uout;
+};
+hipError_t launch_pvelocity(const GridArgs& a, int dtype, double theta_max, const double* coeff2d, void* pvel,
+                            long long P, unsigned long long* rate_bits, hipStream_t s);
+hipError_t launch_pinit(int nx, int nth, long long P, double x0, double dx, double theta_max, double beta, int dtype,
+                        const void* pvel, void* level0, hipStream_t s);
+hipError_t launch_pstage(const PStageArgs& a, int dtype, int stage, hipStream_t s);
+hipError_t launch_ppick(int nx, int nz, int nth, long long P, int dtype, const void* levels, size_t level_bytes,
+                        const double* xs, int nsrc, double* T, hipStream_t s);
+
 // Beam superposition.
 struct BeamArgs {
     GridArgs g;

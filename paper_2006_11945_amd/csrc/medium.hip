@@ -123,6 +123,37 @@ __global__ __launch_bounds__(256) void k_velocity(GridArgs a, const double* C, R
     if ((threadIdx.x & 63) == 0) atomic_max_pos(rate_bits, rate);
 }
 
+// Coefficients of the paraxial depth march at theta_k = -theta_max +
+// (k + 1/2) dtheta, dtheta = 2 theta_max / nth: the Liouville velocity and
+// DRT matrix divided by V_z (eqs. 13-15), planes u, w, S_tau, A11..A22 / V_z,
+// layout [nz][7][P] with index k nx + x.  rate: max |u|/dx + |w|/dtheta, +inf
+// where V_z <= 0 (beyond the paraxial range) or not finite.
+template <typename R>
+__global__ __launch_bounds__(256) void k_pvelocity(GridArgs a, double theta_max, const double* C, R* pvel,
+                                                   long long P, unsigned long long* rate_bits) {
+    const int ix = blockIdx.x * 64 + threadIdx.x, k = blockIdx.y * 4 + threadIdx.y, n = blockIdx.z;
+    double rate = 0.0;
+    if (ix < a.nx && k < a.nth) {
+        MediumPoint M;
+        load_point(a, C, ix, n, M);
+        const double dth = 2.0 * theta_max / a.nth;
+        const double th = -theta_max + (k + 0.5) * dth;
+        const VJet J = qp_velocity(M, th);
+        const VelA r = velocity_and_drt(J, th);
+        const long long c = (long long)n * 7 * P + (long long)k * a.nx + ix;
+        const double vz = r.V[1];
+        const double u = r.V[0] / vz, w = r.V[2] / vz;
+        pvel[c] = (R)u;
+        pvel[P + c] = (R)w;
+        pvel[2 * P + c] = (R)(1.0 / vz);
+        for (int q = 0; q < 4; ++q) pvel[(3 + q) * P + c] = (R)(r.A[q] / vz);
+        rate = fabs(u) / a.dx + fabs(w) / dth;
+        if (!(vz > 0.0) || !isfinite(rate)) rate = __longlong_as_double(0x7ff0000000000000LL);
+    }
+    for (int o = 32; o > 0; o >>= 1) rate = fmax(rate, __shfl_xor(rate, o, 64));
+    if ((threadIdx.x & 63) == 0) atomic_max_pos(rate_bits, rate);
+}
+
 // Bilinear interpolation of the table values at (xs, zs) (medium frozen at the source).
 __device__ void source_medium(const GridArgs& a, const double* C, double xs, double zs, MediumPoint& M) {
     double fx = (xs - a.x0) / a.dx - 0.5, fz = (zs - a.z0) / a.dz - 0.5;
@@ -266,6 +297,16 @@ hipError_t launch_velocity(const GridArgs& a, int dtype, const double* C, void* 
         k_velocity<double><<<cell_grid(a), dim3(64, 4), 0, s>>>(a, C, (double*)vel, rate_bits);
     else
         k_velocity<float><<<cell_grid(a), dim3(64, 4), 0, s>>>(a, C, (float*)vel, rate_bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_pvelocity(const GridArgs& a, int dtype, double theta_max, const double* C, void* pvel, long long P,
+                            unsigned long long* rate_bits, hipStream_t s) {
+    const dim3 grid((a.nx + 63) / 64, (a.nth + 3) / 4, a.nz), block(64, 4);
+    if (dtype == EGB_F64)
+        k_pvelocity<double><<<grid, block, 0, s>>>(a, theta_max, C, (double*)pvel, P, rate_bits);
+    else
+        k_pvelocity<float><<<grid, block, 0, s>>>(a, theta_max, C, (float*)pvel, P, rate_bits);
     return hipGetLastError();
 }
 
