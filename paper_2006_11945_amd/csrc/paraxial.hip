@@ -14,12 +14,14 @@
 // Level layout: planes X, vartheta, Re C, Im C, Re B, Im B in R, then tau in
 // double, each [theta][x] (x fastest) padded to a multiple of 64 elements.
 //
-// Work decomposition: a block owns a tile of 64 x by 4 theta cells of one
-// slice; the slice with a 3-cell halo (ghosts filled while loading) goes to
-// LDS once, then every cell reads its x and theta stencils there at per-lane
-// mirrored addresses (V D(U) = |V| W(values in upwind order), as in the
-// phase-space stage kernel).  A slice is small (nx nth cells), so the march
-// is a long chain of short launches, captured once into a hipGraph.
+// Work decomposition: a block owns a tile of 64 x by 2 theta cells of one
+// slice and has one wave per (plane, theta row), so that a slice of nx nth
+// cells still gives every SIMD several waves; the tile with a 3-cell halo
+// (ghosts filled while loading) goes to LDS once, then every thread reads its
+// plane's x and theta stencils there at per-lane mirrored addresses
+// (V D(U) = |V| W(values in upwind order), as in the phase-space stage
+// kernel).  The march is a long chain of short launches, captured once into
+// a hipGraph.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -32,12 +34,14 @@
 namespace egb {
 namespace {
 
-constexpr int PTX = 64, PTT = 4;         // tile: x cells, theta rows
+constexpr int PTX = 64, PTT = 2;         // tile: x cells, theta rows
+constexpr int NPL = 7;                   // planes, one wave each per theta row
 constexpr int PRX = PTX + 6;             // LDS row (3-cell halo each side)
 constexpr int PROWS = PTT + 6;
 constexpr int PCELLS = PROWS * PRX;      // LDS cells per plane
-constexpr int NPR = 6;                   // R planes: X, vartheta, ReC, ImC, ReB, ImB
-enum { Q_X = 0, Q_VT = 1, Q_RC = 2, Q_IC = 3, Q_RB = 4, Q_IB = 5 };
+constexpr int NT = PTX * PTT * NPL;      // threads per block
+constexpr int NPR = 6;                   // R planes: X, vartheta, ReC, ImC, ReB, ImB (then tau)
+enum { Q_X = 0, Q_VT = 1, Q_RC = 2, Q_IC = 3, Q_RB = 4, Q_IB = 5, Q_TAU = 6 };
 // velocity planes: u, w, S_tau, A11/Vz, A12/Vz, A21/Vz, A22/Vz
 
 template <typename R>
@@ -48,109 +52,147 @@ struct PSmem {
     W w[(NPR + LdsWord<R>::PSI_WORDS) * PLANE];
 };
 
-// Value of a line through (x, k): inside the slice the stored value, beyond
-// an x end or a theta end the line of the two cells next to it
-// (u_{-m} = (m+1) u_0 - m u_1); cells beyond both are never read.
-template <typename T>
-__device__ __forceinline__ T pline_val(const T* u, int nx, int nth, int x, int k) {
-    if (x >= 0 && x < nx && k >= 0 && k < nth) return u[(long long)k * nx + x];
-    if (k >= 0 && k < nth) {
-        const T* r = u + (long long)k * nx;
-        if (x < 0) return (T)(1 - x) * r[0] + (T)x * r[1];
-        const int e = x - (nx - 1);
-        return (T)(e + 1) * r[nx - 1] - (T)e * r[nx - 2];
+// LDS cell i of a tile (x0, k0): the two slice cells whose combination
+// w0 u[i0] + w1 u[i1] gives its value.  Inside the slice (w0, w1) = (1, 0);
+// beyond an x end or a theta end the line of the two cells next to it,
+// u_{-m} = (m+1) u_0 - m u_1; cells beyond both are never read (weights 0).
+__device__ __forceinline__ void pline_src(int nx, int nth, int x, int k, int& i0, int& i1, int& w0, int& w1) {
+    const bool xin = x >= 0 && x < nx, kin = k >= 0 && k < nth;
+    if (xin && kin) {
+        i0 = i1 = k * nx + x;
+        w0 = 1;
+        w1 = 0;
+    } else if (kin) {
+        const bool lo = x < 0;
+        const int m = lo ? -x : x - (nx - 1);
+        i0 = k * nx + (lo ? 0 : nx - 1);
+        i1 = k * nx + (lo ? 1 : nx - 2);
+        w0 = m + 1;
+        w1 = -m;
+    } else if (xin) {
+        const bool lo = k < 0;
+        const int m = lo ? -k : k - (nth - 1);
+        i0 = (lo ? 0 : nth - 1) * nx + x;
+        i1 = (lo ? 1 : nth - 2) * nx + x;
+        w0 = m + 1;
+        w1 = -m;
+    } else {
+        i0 = i1 = 0;
+        w0 = w1 = 0;
     }
-    if (x >= 0 && x < nx) {
-        if (k < 0) return (T)(1 - k) * u[x] + (T)k * u[nx + x];
-        const int e = k - (nth - 1);
-        return (T)(e + 1) * u[(long long)(nth - 1) * nx + x] - (T)e * u[(long long)(nth - 2) * nx + x];
-    }
-    return (T)0;
 }
 
+// One RK stage on a 64 x 2 (x, theta) tile: thread (x, row, plane), so
+// every wave holds one plane of one theta row and all branches on the plane
+// are wave-uniform.  The tile of every plane with its halo is loaded to LDS
+// by the waves of that plane (all loads of a thread issued together; the
+// second point of a ghost only in tiles that touch an edge); the x and theta
+// stencils are then read at per-lane mirrored addresses.  The cell's
+// coefficients and stage-start value are fetched before the barrier.
 template <typename R, int STAGE>
-__global__ __launch_bounds__(PTX * PTT) void k_pstage(PStageArgs a) {
+__global__ __launch_bounds__(NT) void k_pstage(PStageArgs a) {
     using S = PSmem<R>;
     using Wd = typename S::W;
     constexpr int WS = (int)sizeof(Wd);
+    constexpr int NLD = (PCELLS + PTX * PTT - 1) / (PTX * PTT);  // LDS cells per thread
     __shared__ S sm;
     const int ntx = (a.nx + PTX - 1) / PTX;
     const int tx0 = (blockIdx.x % ntx) * PTX, tk0 = (blockIdx.x / ntx) * PTT;
-    const int tid = threadIdx.y * PTX + threadIdx.x;
-    const R* Ui = static_cast<const R*>(a.Uin);
-    const double* Tin = reinterpret_cast<const double*>(Ui + NPR * a.P);
+    const int p = threadIdx.z;  // plane (wave-uniform)
+    const int pt = threadIdx.y * PTX + threadIdx.x;
+    const bool edge = tx0 < 3 || tx0 + PTX + 3 > a.nx || tk0 < 3 || tk0 + PTT + 3 > a.nth;  // block-uniform
 
-    // slice tile + halo into LDS (ghosts by extrapolation)
-    for (int i = tid; i < PCELLS; i += PTX * PTT) {
-        const int x = tx0 + i % PRX - 3, k = tk0 + i / PRX - 3;
-#pragma unroll
-        for (int f = 0; f < NPR; ++f)
-            sm.w[f * S::PLANE + i] = __builtin_bit_cast(Wd, pline_val<R>(Ui + f * a.P, a.nx, a.nth, x, k));
-        const unsigned long long b = __builtin_bit_cast(unsigned long long, pline_val<double>(Tin, a.nx, a.nth, x, k));
-        if constexpr (sizeof(R) == 4) {
-            sm.w[NPR * S::PLANE + i] = (unsigned)b;
-            sm.w[(NPR + 1) * S::PLANE + i] = (unsigned)(b >> 32);
-        } else {
-            sm.w[NPR * S::PLANE + i] = b;
-        }
-    }
-    __syncthreads();
-
+    // own cell (clamped for threads past the slice) and its prefetched inputs
     const int x = tx0 + (int)threadIdx.x, k = tk0 + (int)threadIdx.y;
-    if (x >= a.nx || k >= a.nth) return;
-    const long long c = (long long)k * a.nx + x;
-    // coefficients at this stage's depth
+    const bool valid = x < a.nx && k < a.nth;
+    const long long c = (long long)min(k, a.nth - 1) * a.nx + min(x, a.nx - 1);
     const R* p0 = static_cast<const R*>(a.pv0);
     const R* p1 = static_cast<const R*>(a.pv1);
-    const R s1 = (R)a.s, s0 = (R)(1.0 - a.s);
-    R cv[7];
-#pragma unroll
-    for (int q = 0; q < 7; ++q) cv[q] = s0 * p0[q * a.P + c] + s1 * p1[q * a.P + c];
-    constexpr double ca = RK<STAGE>::ca, cb = RK<STAGE>::cb;
-    const double cdl = cb * a.dl;
-    const R gx = fabs(cv[0]) * (R)(cdl / a.dx), gt = fabs(cv[1]) * (R)(cdl / a.dth), cdr = (R)cdl;
-    const bool mx = cv[0] >= (R)0, mt = cv[1] >= (R)0;
-
-    const int me = ((int)threadIdx.y + 3) * PRX + (int)threadIdx.x + 3;
-    const int meB = me * WS;
-    R own[NPR];
-#pragma unroll
-    for (int f = 0; f < NPR; ++f) own[f] = lds_r<R>(sm, meB, f);
-    const double ownp = lds_psi<NPR>(sm, meB);
-    R acc[NPR];
-#pragma unroll
-    for (int f = 0; f < NPR; ++f) acc[f] = (R)cb * own[f];
-    double accp = cb * ownp + cdl * (double)cv[2];
-    R convp = (R)0;
-    auto axis = [&](int step, R g) {
-        const int a0 = meB - 3 * step, a1 = meB - 2 * step, a2 = meB - step, a4 = meB + step, a5 = meB + 2 * step;
-#pragma unroll
-        for (int f = 0; f < NPR; ++f)
-            acc[f] -= g * weno_up<R>(lds_r<R>(sm, a0, f), lds_r<R>(sm, a1, f), lds_r<R>(sm, a2, f), own[f],
-                                     lds_r<R>(sm, a4, f), lds_r<R>(sm, a5, f));
-        convp += g * weno_up<R>(lds_psi<NPR>(sm, a0), lds_psi<NPR>(sm, a1), lds_psi<NPR>(sm, a2), ownp,
-                                lds_psi<NPR>(sm, a4), lds_psi<NPR>(sm, a5));
-    };
-    axis(mx ? WS : -WS, gx);
-    axis(mt ? PRX * WS : -PRX * WS, gt);
-    accp -= (double)convp;
-    const R A11 = cdr * cv[3], A12 = cdr * cv[4], A21 = cdr * cv[5], A22 = cdr * cv[6];
-    acc[Q_RC] += A11 * own[Q_RC] + A12 * own[Q_RB];
-    acc[Q_RB] += A21 * own[Q_RC] + A22 * own[Q_RB];
-    acc[Q_IC] += A11 * own[Q_IC] + A12 * own[Q_IB];
-    acc[Q_IB] += A21 * own[Q_IC] + A22 * own[Q_IB];
-    R* Uo = static_cast<R*>(a.Uout);
-    double* To = reinterpret_cast<double*>(Uo + NPR * a.P);
+    const bool isC = p == Q_RC || p == Q_IC;
+    const int qa = p == Q_TAU ? 2 : (isC ? 3 : 5);  // this plane's source coefficients
+    const R u0 = p0[c], u1 = p1[c], w0 = p0[a.P + c], w1 = p1[a.P + c];
+    const R a0 = p0[qa * a.P + c], a1 = p1[qa * a.P + c];
+    const R b0 = p0[(qa + 1) * a.P + c], b1 = p1[(qa + 1) * a.P + c];
+    const R* Ui = static_cast<const R*>(a.Uin);
+    R r0 = (R)0;
+    double t0 = 0.0;
     if constexpr (STAGE != 0) {
         const R* U0 = static_cast<const R*>(a.U0);
-        const double* T0 = reinterpret_cast<const double*>(U0 + NPR * a.P);
-#pragma unroll
-        for (int f = 0; f < NPR; ++f) acc[f] += (R)ca * U0[f * a.P + c];
-        accp += ca * T0[c];
+        if (p == Q_TAU) t0 = reinterpret_cast<const double*>(U0 + NPR * a.P)[c];
+        else r0 = U0[p * a.P + c];
     }
+
+    // this plane's tile + halo into LDS
+    auto fill = [&](auto tag) {
+        using T = decltype(tag);
+        const T* u = p == Q_TAU ? reinterpret_cast<const T*>(Ui + NPR * a.P) : reinterpret_cast<const T*>(Ui + p * a.P);
+        T v0[NLD], v1[NLD];
+        int wa[NLD], wb[NLD];
 #pragma unroll
-    for (int f = 0; f < NPR; ++f) Uo[f * a.P + c] = acc[f];
-    To[c] = accp;
+        for (int r = 0; r < NLD; ++r) {
+            const int i = min(pt + r * PTX * PTT, PCELLS - 1);
+            int i0, i1;
+            pline_src(a.nx, a.nth, tx0 + i % PRX - 3, tk0 + i / PRX - 3, i0, i1, wa[r], wb[r]);
+            v0[r] = u[i0];
+            v1[r] = edge ? u[i1] : (T)0;
+        }
+#pragma unroll
+        for (int r = 0; r < NLD; ++r) {
+            const int i = pt + r * PTX * PTT;
+            if (i < PCELLS) {
+                const T v = edge ? (T)wa[r] * v0[r] + (T)wb[r] * v1[r] : v0[r];
+                if constexpr (sizeof(T) == sizeof(Wd)) {
+                    sm.w[(p == Q_TAU ? NPR : p) * S::PLANE + i] = __builtin_bit_cast(Wd, v);
+                } else {  // tau of an FP32 slice: two 32-bit planes
+                    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+                    sm.w[NPR * S::PLANE + i] = (Wd)(unsigned)b;
+                    sm.w[(NPR + 1) * S::PLANE + i] = (Wd)(unsigned)(b >> 32);
+                }
+            }
+        }
+    };
+    if (p == Q_TAU) fill(0.0);
+    else fill((R)0);
+    __syncthreads();
+
+    if (!valid) return;
+    // coefficients at this stage's depth: u and w, then this plane's source
+    const R s1 = (R)a.s, s0 = (R)(1.0 - a.s);
+    const R cu = s0 * u0 + s1 * u1, cw = s0 * w0 + s1 * w1;
+    const R ca_ = s0 * a0 + s1 * a1, cb_ = s0 * b0 + s1 * b1;
+    constexpr double ca = RK<STAGE>::ca, cb = RK<STAGE>::cb;
+    const double cdl = cb * a.dl;
+    const R gx = fabs(cu) * (R)(cdl / a.dx), gt = fabs(cw) * (R)(cdl / a.dth), cdr = (R)cdl;
+    const int meB = (((int)threadIdx.y + 3) * PRX + (int)threadIdx.x + 3) * WS;
+    const int sx = cu >= (R)0 ? WS : -WS, st = cw >= (R)0 ? PRX * WS : -PRX * WS;
+    R* Uo = static_cast<R*>(a.Uout);
+    if (p == Q_TAU) {
+        const double own = lds_psi<NPR>(sm, meB);
+        auto wup = [&](int step) {
+            return weno_up<R>(lds_psi<NPR>(sm, meB - 3 * step), lds_psi<NPR>(sm, meB - 2 * step),
+                              lds_psi<NPR>(sm, meB - step), own, lds_psi<NPR>(sm, meB + step),
+                              lds_psi<NPR>(sm, meB + 2 * step));
+        };
+        const R conv = gx * wup(sx) + gt * wup(st);
+        double acc = cb * own + cdl * (double)ca_ - (double)conv;
+        if constexpr (STAGE != 0) acc += ca * t0;
+        reinterpret_cast<double*>(Uo + NPR * a.P)[c] = acc;
+        return;
+    }
+    const R own = lds_r<R>(sm, meB, p);
+    auto wup = [&](int step) {
+        return weno_up<R>(lds_r<R>(sm, meB - 3 * step, p), lds_r<R>(sm, meB - 2 * step, p),
+                          lds_r<R>(sm, meB - step, p), own, lds_r<R>(sm, meB + step, p),
+                          lds_r<R>(sm, meB + 2 * step, p));
+    };
+    R acc = (R)cb * own - gx * wup(sx) - gt * wup(st);
+    if (p >= Q_RC) {
+        // (C, B) pairs (Re C, Re B) and (Im C, Im B): C' = A11 C + A12 B, B' = A21 C + A22 B
+        const R cC = lds_r<R>(sm, meB, isC ? p : p - 2), cB = lds_r<R>(sm, meB, isC ? p + 2 : p);
+        acc += cdr * (ca_ * cC + cb_ * cB);
+    }
+    if constexpr (STAGE != 0) acc += (R)ca * r0;
+    Uo[p * a.P + c] = acc;
 }
 
 // Surface data on level 0: X = x, vartheta = theta, tau = 0,
@@ -207,7 +249,7 @@ __global__ __launch_bounds__(256) void k_ppick(int nx, int nz, int nth, long lon
 template <typename R>
 hipError_t pstage_t(const PStageArgs& a, int stage, hipStream_t s) {
     const int blocks = ((a.nx + PTX - 1) / PTX) * ((a.nth + PTT - 1) / PTT);
-    const dim3 block(PTX, PTT);
+    const dim3 block(PTX, PTT, NPL);
     switch (stage) {
         case 0: k_pstage<R, 0><<<blocks, block, 0, s>>>(a); break;
         case 1: k_pstage<R, 1><<<blocks, block, 0, s>>>(a); break;
