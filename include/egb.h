@@ -83,9 +83,16 @@ typedef struct {
 
 /* Point source at (xs, zs); r0 is the radius of the source ball whose cells
  * hold the point-source data; beta > 0 the initial beam parameter
- * (B(0) = i beta C(0), eq. 24). */
+ * (B(0) = i beta C(0), eq. 24).  lin_variant selects the linear phase
+ * coefficient of the beam sum (read by egb_beam_sum only):
+ * EGB_LIN_EXACT, p1 = sin(theta)/v of eq. 7, or EGB_LIN_PAPER28, eq. 28's
+ * coefficient sqrt(s (s u^2 + 2 c u - s)) / (v (c + s u)), u = V_x/V_z
+ * (s, c = sin, cos theta; the sign of p1 restored, a negative radicand
+ * counted as 0; columns mirrored), an approximation away from isotropy. */
+enum { EGB_LIN_EXACT = 0, EGB_LIN_PAPER28 = 1 };
 typedef struct {
     double xs, zs, r0, beta;
+    int32_t lin_variant;
 } egb_source;
 
 /* ------------------------------------------------------------------ sizes */

@@ -56,7 +56,9 @@ def lib():
         L.oc_init_state.argtypes = [i, i, i, d, d, d, d, P, d, d, d, P]
         L.oc_weno.argtypes = [P, i]; L.oc_weno.restype = d
         L.oc_march.argtypes = [i, i, i, d, d, d, d, P, d, d, d, P, P, d, i]
-        L.oc_beam_sum.argtypes = [i, i, i, d, d, d, d, P, P, d, P, P, i, P]
+        L.oc_beam_sum.argtypes = [i, i, i, d, d, d, d, P, P, d, i, P, P, i, P]
+        L.oc_lin28.argtypes = [d, d, d, d]
+        L.oc_lin28.restype = d
         L.oc_pick.argtypes = [i, i, i, d, d, d, d, P, P, i, P]
         L.oc_pvelocity.argtypes = [i, i, i, d, d, d, P, P, P]
         L.oc_pinit.argtypes = [i, i, d, d, d, P, d, P]
@@ -145,12 +147,13 @@ def march(grid, vel: np.ndarray, source, U: np.ndarray, dt: float, nsteps: int, 
     return U
 
 
-def beam_sum(grid, vel, vaux, source, U, omegas) -> np.ndarray:
-    """Complex Green's function [nw][nx][nz]."""
+def beam_sum(grid, vel, vaux, source, U, omegas, lin: int = 0) -> np.ndarray:
+    """Complex Green's function [nw][nx][nz]; lin = 1: eq. 28's linear
+    phase coefficient instead of eq. 7's p1."""
     om = _c(np.atleast_1d(omegas))
     out = np.zeros((len(om), grid.nx, grid.nz, 2))
     rc = lib().oc_beam_sum(grid.nx, grid.nz, grid.nth, grid.x0, grid.z0, grid.dx, grid.dz, _p(_c(vel)),
-                           _p(_c(vaux)), source.beta, _p(_c(U)), _p(om), len(om), _p(out))
+                           _p(_c(vaux)), source.beta, int(lin), _p(_c(U)), _p(om), len(om), _p(out))
     if rc == -3:
         raise RuntimeError("oracle beam list overflow")
     return out[..., 0] + 1j * out[..., 1]
@@ -217,6 +220,11 @@ def pmarch(grid, pvel: np.ndarray, theta_max: float, U0: np.ndarray, nsub: int) 
     if rc != 0:
         raise MemoryError("oc_pmarch")
     return Uall
+
+
+def lin28(s: float, c: float, u: float, v: float) -> float:
+    """Eq. 28's linear phase coefficient (see oc_lin28)."""
+    return lib().oc_lin28(float(s), float(c), float(u), float(v))
 
 
 def ppick(grid, Uall: np.ndarray, xs) -> np.ndarray:

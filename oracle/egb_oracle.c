@@ -524,14 +524,29 @@ int oc_march(int nx, int nz, int nth, double x0, double z0, double dx, double dz
  * with M the complex traveltime Hessian restricted to the line (M = B C^-1 in
  * the ray-normal frame, eq. 25), w = cos^4/(cos^4 + sin^4) of the ray angle
  * for rows and 1 - w for columns, and the total scaled by W = i / (4 pi).
- * Beams with 1/2 omega Im(M) dist^2 > 16 are skipped.  Output layout
- * out[w][ix][iz][re/im].                                                   */
+ * Beams with 1/2 omega Im(M) dist^2 > 16 are skipped.  lin != 0 takes the
+ * linear coefficient p1 (p3) from eq. 28 (oc_lin28) instead of eq. 7.
+ * Output layout out[w][ix][iz][re/im].                                     */
 typedef struct { double pos, psi, p; double complex M, amp; } beamrec;
+
+/* Linear phase coefficient of eq. 28 (the lin=paper28 variant): for a ray
+ * with phase angle th (sin s, cos c) and direction u = dx/dz, phase velocity
+ * v, sqrt(s (s u^2 + 2 c u - s)) / (v (c + s u)).  Reading: the square root
+ * drops the sign of p1, which is restored from sin th, and a negative
+ * radicand (no real value) counts as 0.  In isotropic media (u = tan th) it
+ * is sin th / v, eq. 7's p1.  Column quadrature: the mirror image (s <-> c,
+ * u -> dz/dx).                                                             */
+double oc_lin28(double s, double c, double u, double v)
+{
+    double rad = s * (s * u * u + 2.0 * c * u - s);
+    double L = sqrt(rad > 0.0 ? rad : 0.0) / (v * (c + s * u));
+    return copysign(fabs(L), s);
+}
 
 static double delta_h(double d, double h) { return fabs(d) < h ? (1.0 + cos(M_PI * d / h)) / (2.0 * h) : 0.0; }
 
 int oc_beam_sum(int nx, int nz, int nth, double x0, double z0, double dx, double dz, const double *vel,
-                const double *vaux, double beta, const double *U, const double *omegas, int nw, double *out)
+                const double *vaux, double beta, int lin, const double *U, const double *omegas, int nw, double *out)
 {
     long n = (long)nth * nx * nz, nxz = (long)nx * nz;
     double dth = 2.0 * M_PI / nth, lx = dx / dth, lz = dz / dth, hx = 2.0 * dx, hz = 2.0 * dz;
@@ -587,7 +602,7 @@ int oc_beam_sum(int nx, int nz, int nth, double x0, double z0, double dx, double
                     beamrec r;
                     r.pos = x0 + (ix + 0.5) * dx;
                     r.psi = psi;
-                    r.p = sn / v;
+                    r.p = lin ? oc_lin28(sn, cs, Vx / Vz, v) : sn / v;
                     r.M = Mn * gz * gz + 2.0 * gpq * gx * gz + gq * gx * gx;
                     r.amp = wrow * amp0 * dth_c;
                     if (nrow[iz] < cap) rows[(long)iz * cap + nrow[iz]++] = r; else overflow = 1;
@@ -598,7 +613,7 @@ int oc_beam_sum(int nx, int nz, int nth, double x0, double z0, double dx, double
                     beamrec r;
                     r.pos = z0 + (iz + 0.5) * dz;
                     r.psi = psi;
-                    r.p = cs / v;
+                    r.p = lin ? oc_lin28(cs, sn, Vz / Vx, v) : cs / v;
                     r.M = Mn * gx * gx - 2.0 * gpq * gx * gz + gq * gz * gz;
                     r.amp = (1.0 - wrow) * amp0 * dth_c;
                     if (ncol[ix] < cap) cols[(long)ix * cap + ncol[ix]++] = r; else overflow = 1;

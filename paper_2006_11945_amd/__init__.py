@@ -47,7 +47,8 @@ class EgbMedium(ctypes.Structure):
 
 
 class EgbSource(ctypes.Structure):
-    _fields_ = [("xs", ctypes.c_double), ("zs", ctypes.c_double), ("r0", ctypes.c_double), ("beta", ctypes.c_double)]
+    _fields_ = [("xs", ctypes.c_double), ("zs", ctypes.c_double), ("r0", ctypes.c_double), ("beta", ctypes.c_double),
+                ("lin_variant", ctypes.c_int32)]
 
 
 class EgbProblem(ctypes.Structure):
@@ -133,8 +134,11 @@ def make_grid(g, dtype: str = "f32") -> EgbGrid:
     return EgbGrid(g.nx, g.nz, g.nth, EGB_F64 if dtype == "f64" else EGB_F32, g.x0, g.z0, g.dx, g.dz)
 
 
-def make_source(s) -> EgbSource:
-    return EgbSource(s.xs, s.zs, s.r0, s.beta)
+EGB_LIN_EXACT, EGB_LIN_PAPER28 = 0, 1
+
+
+def make_source(s, lin_variant: int = EGB_LIN_EXACT) -> EgbSource:
+    return EgbSource(s.xs, s.zs, s.r0, s.beta, int(lin_variant))
 
 
 def real_dtype(eg: EgbGrid):
@@ -364,13 +368,16 @@ class Solver:
         egb_liouville_step(self.eg, self.vel3d, self.src, self.bdata, self.state, self.work_step,
                            self.dt_cfl if dt is None else dt, nsteps, stream)
 
-    def beam(self, omegas, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    def beam(self, omegas, out: Optional[torch.Tensor] = None, stream=None, lin: int = EGB_LIN_EXACT) -> torch.Tensor:
+        """Green's function [nw][nx][nz][re, im]; lin selects the linear phase
+        coefficient (EGB_LIN_EXACT or EGB_LIN_PAPER28)."""
         om = np.atleast_1d(np.asarray(omegas, dtype=np.float64))
         if self.work_beam is None:
             self.work_beam = alloc_bytes(workspace_size(self.eg, EGB_OP_BEAM), self.device)
         if out is None:
             out = torch.empty((len(om), self.eg.nx, self.eg.nz, 2), dtype=real_dtype(self.eg), device=self.device)
-        egb_beam_sum(self.eg, self.coeff2d, self.vel3d, self.src, self.state, om, out, self.work_beam, stream)
+        src = self.src if lin == EGB_LIN_EXACT else make_source(self.p.source, lin)
+        egb_beam_sum(self.eg, self.coeff2d, self.vel3d, src, self.state, om, out, self.work_beam, stream)
         return out
 
     def pick(self, receivers, stream=None) -> torch.Tensor:

@@ -6,7 +6,8 @@
 // delta of the signed distance d = phi1 / |grad phi1| (theta scaled by
 // lambda = dx / dtheta, width h = 2 dx) and from the imaginary DRT part
 // Im(C, B) = beta s (dn, dth_perp) per unit take-off angle.  Each record holds
-//   pos (x or z of the cell), psi, p (p1 or p3), M (traveltime Hessian along
+//   pos (x or z of the cell), psi, p (p1 or p3 of eq. 7, or eq. 28's
+//   coefficient for the lin=paper28 variant), M (traveltime Hessian along
 //   the line, complex) and amp = w sqrt(v / C) dtheta (complex),
 // w = cos^4 / (cos^4 + sin^4) of the ray angle for rows and 1 - w for columns.
 // Pass 2 (k_beam_line): for every output cell and frequency,
@@ -50,6 +51,16 @@ __device__ __forceinline__ double cd4(const T* base, long long st, int n, int i,
     return (line_at(base, st, n, i - 2) - 8.0 * line_at(base, st, n, i - 1) + 8.0 * line_at(base, st, n, i + 1) -
             line_at(base, st, n, i + 2)) /
            (12.0 * h);
+}
+
+// Eq. 28's linear phase coefficient for phase angle (s, c) = (sin, cos) and
+// ray direction u = dx/dz: sqrt(s (s u^2 + 2 c u - s)) / (v (c + s u)), with
+// the sign of p1 (that of s) restored and a negative radicand taken as 0;
+// sin / v in isotropic media.  Columns use the mirror image.
+__device__ __forceinline__ double lin28(double s, double c, double u, double v) {
+    const double rad = s * (s * u * u + 2.0 * c * u - s);
+    const double L = sqrt(fmax(rad, 0.0)) / (v * (c + s * u));
+    return copysign(fabs(L), s);
 }
 
 __device__ __forceinline__ double delta_h(double d, double h) {
@@ -132,7 +143,7 @@ __global__ __launch_bounds__(256) void k_beam_compact(BeamArgs a) {
         BeamRec r;
         r.psi = psi;
         r.pos = g.x0 + (ix + 0.5) * g.dx;
-        r.p = sn / v;
+        r.p = a.lin == EGB_LIN_PAPER28 ? lin28(sn, cs, va.V[0] / va.V[1], v) : sn / v;
         r.Mre = Mnre * hzr * hzr + 2.0 * eq * hxr * hzr + gq * hxr * hxr;
         r.Mim = Mnim * hzr * hzr;
         r.are = w * sqre;
@@ -148,7 +159,7 @@ __global__ __launch_bounds__(256) void k_beam_compact(BeamArgs a) {
         BeamRec r;
         r.psi = psi;
         r.pos = g.z0 + (iz + 0.5) * g.dz;
-        r.p = cs / v;
+        r.p = a.lin == EGB_LIN_PAPER28 ? lin28(cs, sn, va.V[1] / va.V[0], v) : cs / v;
         r.Mre = Mnre * hxr * hxr - 2.0 * eq * hxr * hzr + gq * hzr * hzr;
         r.Mim = Mnim * hxr * hxr;
         r.are = w * sqre;

@@ -28,7 +28,7 @@ bool grid_ok(const egb_grid* g) {
 
 bool source_ok(const egb_source* s) {
     return s && isfinite(s->xs) && isfinite(s->zs) && isfinite(s->r0) && s->r0 >= 0.0 && isfinite(s->beta) &&
-           s->beta > 0.0;
+           s->beta > 0.0 && (s->lin_variant == EGB_LIN_EXACT || s->lin_variant == EGB_LIN_PAPER28);
 }
 
 egb_status hip_status(hipError_t e) { return e == hipSuccess ? EGB_OK : EGB_EHIP; }
@@ -464,6 +464,7 @@ egb_status egb_beam_sum(const egb_grid* g, const void* coeff2d, const void* vel3
     ba.vel = vel3d;
     ba.U = state;
     ba.beta = src->beta;
+    ba.lin = src->lin_variant;
     ba.cap = cap;
     ba.counts = reinterpret_cast<int*>(w);
     ba.rows = w + cb;

@@ -140,6 +140,7 @@ struct BeamArgs {
     const void* vel;
     const void* U;
     double beta;
+    int lin;          // EGB_LIN_EXACT or EGB_LIN_PAPER28
     int cap;          // records per row / column list
     int* counts;      // [nz rows][nx cols]
     void* rows;       // row records

@@ -76,6 +76,9 @@ def test_sizes_and_validation_without_gpu():
     assert egb.bdata_bytes(eg) == 5 * bs * 4 + bs * 8
     assert egb.bdata_bytes(eg64) == 6 * bs * 8
     assert egb.bfold_bytes(eg) == 2 * 36 * 12 * (40 + 72) * 8
+    badlin = egb.EgbSource(1.0, 1.0, 1.0, 1e-4, 7)  # no such linear-phase variant
+    assert L.egb_init_state(ctypes.byref(eg), ctypes.c_void_p(256), ctypes.byref(badlin), ctypes.c_void_p(256),
+                            None) == egb.EGB_EINVAL
     nosrc = egb.EgbSource(1.0, 1.0, 1.0, 0.0)  # beta must be > 0
     assert L.egb_init_state(ctypes.byref(eg), ctypes.c_void_p(256), ctypes.byref(nosrc), ctypes.c_void_p(256),
                             None) == egb.EGB_EINVAL

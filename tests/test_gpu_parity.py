@@ -170,19 +170,20 @@ def test_homog_iso_64_fp64_full_workload():
     assert np.linalg.norm((Gb[0] - H)[m]) / np.linalg.norm(H[m]) < 0.03
 
 
-@pytest.mark.parametrize("tilt", [False, True])
-def test_beam_sum_parity_f32(tilt):
+@pytest.mark.parametrize("tilt,lin", [(False, 0), (True, 0), (True, 1)])
+def test_beam_sum_parity_f32(tilt, lin):
     """Beam sum on identical input: the oracle's marched state, rounded to the
-    FP32 storage, is written into the GPU state buffer."""
+    FP32 storage, is written into the GPU state buffer.  lin = 1: eq. 28's
+    linear phase coefficient (the medium is anisotropic, so it differs)."""
     p = ragged_problem(tilt=tilt, nsteps=40)
-    log(f"beam f32 tilt={tilt}")
+    log(f"beam f32 tilt={tilt} lin={lin}")
     o = oracle.solve(p)
     Ur = rounded_oracle_state(o["U"], "f32")
     s = run_gpu(p, "f32", 0)
     egb().write_state(s.eg, s.state, oracle_planes(Ur))
-    out = s.beam(p.omegas).cpu().numpy()
+    out = s.beam(p.omegas, lin=lin).cpu().numpy()
     Gb = out[..., 0] + 1j * out[..., 1]
-    Ob = oracle.beam_sum(p.grid, o["vel"], o["vaux"], p.source, Ur, p.omegas)
+    Ob = oracle.beam_sum(p.grid, o["vel"], o["vaux"], p.source, Ur, p.omegas, lin=lin)
     for w in range(len(p.omegas)):
         e = np.linalg.norm(Gb[w] - Ob[w]) / np.linalg.norm(Ob[w])
         log(f"  omega {p.omegas[w]:.1f}: rel L2 {e:.3e}")

@@ -418,3 +418,52 @@ def test_beam_sum_nonelliptic_far_field_and_beta_independence():
         val = ip_r(pt)[0] + 1j * ip_i(pt)[0]
         errs.append(abs(val - ref) / abs(ref))
     assert max(errs) < 0.05, errs
+
+
+# --------------------------------------------- eq. 28 linear phase variant
+def test_lin28_is_eq7_p1_in_isotropic_media():
+    # u = dx/dz = tan(theta): the eq. 28 coefficient is sin(theta) / v for
+    # every direction, up- and down-going
+    for th in np.linspace(-3.1, 3.1, 63):
+        if abs(np.cos(th)) < 1e-3:
+            continue
+        got = oracle.lin28(np.sin(th), np.cos(th), np.tan(th), 2500.0)
+        assert got == pytest.approx(np.sin(th) / 2500.0, rel=1e-13, abs=1e-19), th
+
+
+def test_lin28_elliptic_closed_form():
+    # elliptic medium: u = r tan(theta), r = a11 / a33, so that the coefficient
+    # is |sin| sqrt(r^2 t^2 + 2 r - 1) / (v cos (1 + r t^2)) for cos > 0, which
+    # differs from eq. 7's sin / v by that factor (not 1 unless r = 1)
+    r, v = 1.4, 2000.0
+    for th in np.linspace(-1.2, 1.2, 25):
+        t = np.tan(th)
+        ref = np.sin(th) * np.sqrt(r * r * t * t + 2 * r - 1) / (v * np.cos(th) * (1 + r * t * t))
+        assert oracle.lin28(np.sin(th), np.cos(th), r * t, v) == pytest.approx(ref, rel=1e-13, abs=1e-19)
+    assert abs(np.sqrt(2 * r - 1) - 1) > 0.1  # even at normal incidence the two differ
+
+
+def test_beam_sum_lin28_variant_ab():
+    """A/B of the paper's eq. 28 linear phase coefficient against eq. 7's
+    exact p1: identical in an isotropic medium; in the elliptic medium
+    (eps = delta = 0.2) the eq. 28 coefficient is off by up to
+    sqrt(2r - 1) ~ 1.18 at normal incidence and the Green's function error
+    against the closed form grows well beyond the exact variant's."""
+    p = W.homog_iso_64(n=96, nsteps=0)
+    p.omegas = W.hz([20.0])
+    r = oracle.solve(p, nsteps=0)
+    G0 = oracle.beam_sum(p.grid, r["vel"], r["vaux"], p.source, r["U"], p.omegas)
+    G1 = oracle.beam_sum(p.grid, r["vel"], r["vaux"], p.source, r["U"], p.omegas, lin=1)
+    assert np.linalg.norm(G1 - G0) <= 1e-10 * np.linalg.norm(G0)
+    p.medium = W.homogeneous(p.grid, 2000.0, 0.2, 0.2, 0.0)
+    r = oracle.solve(p, nsteps=0)
+    X, Z = np.meshgrid(p.grid.xc(), p.grid.zc(), indexing="ij")
+    H = CF.green_elliptic(X, Z, 500.0, 500.0, 2000.0, 0.2, p.omegas[0], 0.0)
+    R = np.hypot(X - 500.0, Z - 500.0)
+    m = (R >= 200.0) & (R <= 460.0)
+    errs = []
+    for lin in (0, 1):
+        G = oracle.beam_sum(p.grid, r["vel"], r["vaux"], p.source, r["U"], p.omegas, lin=lin)[0]
+        errs.append(np.linalg.norm((G - H)[m]) / np.linalg.norm(H[m]))
+    assert errs[0] < 0.03, errs
+    assert errs[1] > 5 * errs[0], errs
