@@ -88,3 +88,20 @@ def test_sizes_and_validation_without_gpu():
                           ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 30, None) == egb.EGB_EINVAL
     assert L.egb_pick_receivers(ctypes.byref(eg), ctypes.c_void_p(256), None, 0, None, None) == egb.EGB_OK
     assert egb.lib().egb_status_string(-3) == b"workspace too small"
+
+
+def test_grids_beyond_32_bit_offsets_are_refused_before_any_launch():
+    """The stage kernels address every array with 32-bit byte offsets: a
+    1024^3 FP32 grid (a 30 GB state) is a valid request this build does not
+    implement.  Host-side validation only (fake aligned device pointers)."""
+    import paper_2006_11945_amd as egb
+    import workloads as W
+
+    g = W.Grid(nx=1024, nz=1024, nth=1024, dx=10.0, dz=10.0)
+    eg = egb.make_grid(g, "f32")
+    assert egb.state_bytes(eg) > 1 << 32
+    src = egb.EgbSource(5000.0, 5000.0, 40.0, 1e-4)
+    P = ctypes.c_void_p
+    rc = egb.lib().egb_liouville_step(ctypes.byref(eg), P(256), ctypes.byref(src), P(256), P(256), P(256),
+                                      1 << 62, 1e-3, 1, None)
+    assert rc == egb.EGB_EUNSUPPORTED
