@@ -854,6 +854,119 @@ int oc_pmarch(int nx, int nz, int nth, double dx, double dz, double theta_max, c
     return 0;
 }
 
+/* Gaussian-beam superposition from the depth march (eqs. 25-27, 33-35 in
+ * the paper's own setting): for a surface source at x_s on level 0, the
+ * Green's function on depth row n is the integral over take-off angle of the
+ * beams on Gamma(z_n) = {X = x_s} (eq. 35).  On the (x, theta) slice the
+ * take-off-angle measure of a cell is
+ *   d vartheta = delta_h(d) |det d(X, vartheta)/d(x, theta)| / |grad X| dx dtheta,
+ * d = (X - x_s) / |grad X| the signed distance to Gamma with theta scaled by
+ * lambda = dx / dtheta (width h = 2 dx), derivatives by 4th-order central
+ * differences (ghosts as in the march).  Each beam contributes, as a row of
+ * the phase-space superposition,
+ *   sqrt(v / C) sqrt(u1 / s) s^-1 d vartheta exp(i omega T),
+ *   T = tau + p_s (X - x_s) + p1 (x0 - x) + 1/2 M_row (x0 - x)^2,
+ * with the traveltime Hessian of the phase-space beam sum (M = B C^-1 in the
+ * ray-normal frame), and the whole scaled by i / (4 pi).  Reading: the depth
+ * march starts the beam of take-off angle vartheta with C(0) = u1 =
+ * cos + sin u (eq. 24), the point-source data with C(0) = s (the 2D beam
+ * weight); both solve the same linear transport, so sqrt(u1 / s) (medium
+ * frozen at the source, level 0) turns one normalisation into the other,
+ * and s^-1 is the weight the phase-space sum's take-off-angle measure
+ * carries (its Im(C, B) = beta s (dn, dtheta_perp) per unit angle).
+ * A cell within the smoothed delta but off Gamma carries the ray from X, not
+ * from x_s: its traveltime is moved to the source to first order by the
+ * take-off slowness p_s = sin(vartheta) / v_s (the point-source data of the
+ * phase-space march carries this term in psi itself).  lin != 0: eq. 28's
+ * linear coefficient.  Row 0 (the source row) is left 0.
+ * Output out[w][ix][n][re/im].                                             */
+int oc_pbeam_sum(int nx, int nz, int nth, double x0, double z0, double dx, double dz, double theta_max,
+                 const double *tab, const double *Uall, double xs, int lin, const double *omegas, int nw,
+                 double *out)
+{
+    double dth = 2.0 * theta_max / nth, lam = dx / dth, h = 2.0 * dx;
+    long plane = (long)nth * nx, lev = NPAR * plane;
+    double ms[NFLD];
+    for (int m = 0; m < NFLD; ++m) ms[m] = bilin(tab, nx, nz, dx, dz, x0, z0, xs, z0 + 0.5 * dz, m);
+    int cap = 8 * (nx + nth) + 64, overflow = 0;
+    beamrec *rows = (beamrec *)malloc(sizeof(beamrec) * (long)nz * cap);
+    int *nrow = (int *)calloc(nz, sizeof(int));
+    if (!rows || !nrow) { free(rows); free(nrow); return -2; }
+#pragma omp parallel for schedule(dynamic) reduction(| : overflow)
+    for (int n = 1; n < nz; ++n) {
+        const double *U = Uall + (long)n * lev;
+        const double *X = U + P_X * plane, *T = U + P_VT * plane;
+        for (int k = 0; k < nth; ++k)
+            for (int i = 0; i < nx; ++i) {
+                long c = (long)k * nx + i;
+                double tau = U[P_TAU * plane + c];
+                if (!(tau > 0.0)) continue;
+#define DX(f) ((pline((f) + (long)k * nx, 1, nx, i - 2) - 8.0 * pline((f) + (long)k * nx, 1, nx, i - 1) + \
+                8.0 * pline((f) + (long)k * nx, 1, nx, i + 1) - pline((f) + (long)k * nx, 1, nx, i + 2)) / (12.0 * dx))
+#define DT(f) ((pline((f) + i, nx, nth, k - 2) - 8.0 * pline((f) + i, nx, nth, k - 1) + \
+                8.0 * pline((f) + i, nx, nth, k + 1) - pline((f) + i, nx, nth, k + 2)) / (12.0 * dth))
+                double Xx = DX(X), Xt = DT(X), Tx = DX(T), Tt = DT(T);
+#undef DX
+#undef DT
+                double gX = sqrt(Xx * Xx + (Xt / lam) * (Xt / lam));
+                double d = (X[c] - xs) / gX;
+                if (!(fabs(d) < h)) continue;
+                double meas = delta_h(d, h) * fabs(Xx * Tt - Xt * Tx) / gX * dx * dth;
+                double th = -theta_max + (k + 0.5) * dth, sn = sin(th), cs = cos(th);
+                double vj[10], V[3], A[4];
+                vjet_flat(phase_velocity_jet(tab + ((long)i * nz + n) * NFLD * NTAY, th), vj);
+                oc_va(vj, th, V, A);
+                double v = vj[0], vx = vj[1], vz = vj[2], vt = vj[3];
+                double nv = sqrt(V[0] * V[0] + V[1] * V[1]), gx = V[0] / nv, gz = V[1] / nv;
+                double gp[2] = {gz, -gx};
+                double complex C = U[P_RC * plane + c] + I * U[P_IC * plane + c];
+                double complex B = U[P_RB * plane + c] + I * U[P_IB * plane + c];
+                double pth[2] = {cs / v - sn * vt / (v * v), -sn / v - cs * vt / (v * v)};
+                double gp_pth = gp[0] * pth[0] + gp[1] * pth[1];
+                double gp_dxp_gp = -(gp[0] * sn + gp[1] * cs) * (vx * gp[0] + vz * gp[1]) / (v * v);
+                double q[2] = {-vx / (v * nv), -vz / (v * nv)};
+                double gq = gx * q[0] + gz * q[1], gpq = gp[0] * q[0] + gp[1] * q[1];
+                double complex Mn = (gp_pth * B + gp_dxp_gp * C) / C;
+                /* source normalisation at the take-off angle */
+                double vs, gps[2], ps[2], A12s, ss;
+                double vt0 = T[c];
+                source_data(ms, vt0, &vs, gps, ps, &A12s, &ss);
+                double u1 = cos(vt0) - sin(vt0) * gps[1] / gps[0];
+                beamrec r;
+                r.pos = x0 + (i + 0.5) * dx;
+                r.psi = tau + ps[0] * (X[c] - xs);
+                r.p = lin ? oc_lin28(sn, cs, gx / gz, v) : sn / v;
+                r.M = Mn * gz * gz + 2.0 * gpq * gx * gz + gq * gx * gx;
+                r.amp = csqrt(v / C) * sqrt(u1 / ss) / ss * meas;
+                if (nrow[n] < cap) rows[(long)n * cap + nrow[n]++] = r; else overflow = 1;
+            }
+    }
+    const double complex W = I / (4.0 * M_PI);
+    memset(out, 0, sizeof(double) * 2 * (long)nw * nx * nz);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int w = 0; w < nw; ++w)
+        for (int n = 1; n < nz; ++n) {
+            double om = omegas[w];
+            for (int ix = 0; ix < nx; ++ix) {
+                double xo = x0 + (ix + 0.5) * dx;
+                double complex G = 0.0;
+                for (int r = 0; r < nrow[n]; ++r) {
+                    const beamrec *b = &rows[(long)n * cap + r];
+                    double dd = xo - b->pos;
+                    double complex Tc = b->psi + b->p * dd + 0.5 * b->M * dd * dd;
+                    if (0.5 * om * cimag(b->M) * dd * dd > 16.0) continue;
+                    G += b->amp * cexp(I * om * Tc);
+                }
+                G *= W;
+                long o = (((long)w * nx + ix) * nz + n) * 2;
+                out[o] = creal(G);
+                out[o + 1] = cimag(G);
+            }
+        }
+    free(rows); free(nrow);
+    return overflow ? -3 : 0;
+}
+
 /* First arrival at every (x_i, z_n) from a source at x = xs on the first
  * depth row: roots in theta of X(z_n, x_i, .) - xs between adjacent theta
  * nodes (eq. 35's Gamma = {X = x_s}; linear interpolation of X and tau), the

@@ -93,3 +93,32 @@ def test_rounding_sensitivity_at_the_aperture_edges():
                for q in (0, 1, 3, 4, 5, 6))
     assert 3e-5 < e_all < 1e-3
     assert e_in < 1e-4
+
+
+@pytest.mark.parametrize("eps,tilt", [(0.0, 0.0), (0.2, 0.0), (0.2, 0.3)])
+def test_paraxial_beam_sum_matches_green(eps, tilt):
+    """The beam superposition of the depth march (eq. 34 over Gamma =
+    {X = x_s}, eq. 35) reproduces (i/4) H0 (isotropic) and the elliptic
+    closed form for a surface source, below the source within 20 degrees and
+    beyond three wavelengths.  The domain is twice as wide as deep: the beams
+    (about 250 m wide at 20 Hz for beta = 1/(2 L)) are cut where they leave
+    the domain sideways, which no quadrature inside it can restore."""
+    n, L, v = 96, 1000.0, 2000.0
+    g = W.Grid(nx=2 * n, nz=n, nth=n, dx=L / n, dz=L / n)
+    xs = n * g.dx
+    r = oracle.psolve(g, W.homogeneous(g, v, eps, eps, tilt), TMAX, 1 / (2 * L))
+    om = W.hz([20.0, 40.0])
+    G = oracle.pbeam_sum(g, r["tab"], r["U"], TMAX, xs, om)
+    zs = g.zc()[0]
+    X, Z = np.meshgrid(g.xc(), g.zc(), indexing="ij")
+    R = np.hypot(X - xs, Z - zs)
+    ang = np.arctan2(np.abs(X - xs), Z - zs)
+    for w, o in enumerate(om):
+        H = CF.green_elliptic(X, Z, xs, zs, v, eps, o, tilt)
+        m = (R >= 3 * 2 * np.pi * v / o) & (ang < np.radians(20)) & (np.abs(X - xs) < 300.0)
+        e = np.linalg.norm((G[w] - H)[m]) / np.linalg.norm(H[m])
+        assert e < 0.04, (o, e)
+    # the linear-phase variant of eq. 28 changes nothing in isotropic media
+    if eps == 0.0:
+        G1 = oracle.pbeam_sum(g, r["tab"], r["U"], TMAX, xs, om, lin=1)
+        assert np.linalg.norm(G1 - G) <= 1e-10 * np.linalg.norm(G)
