@@ -154,7 +154,9 @@ FLOP_PCELL_STAGE = 14 * FLOP_WENO + 7 * 2 * 2 + 17 + 7 * 4 + 7 * 3
 def paraxial_leg(n, nsrc, nth=256, theta_max=None):
     """The paraxial depth march (the paper's own formulation) on the same
     medium: 256 x 256 slice of 256 theta nodes in (-60, 60) degrees, all 256
-    depth levels, first arrivals of `nsrc` surface sources from the one march."""
+    depth levels, first arrivals of `nsrc` surface sources from the one march,
+    and the Green's function of the central surface source (eq. 34, the
+    benchmark's 32 frequencies)."""
     from dataclasses import replace
 
     import numpy as np
@@ -181,12 +183,16 @@ def paraxial_leg(n, nsrc, nth=256, theta_max=None):
     T = P.pick(xs)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    G = P.beam(0.5 * L, p.omegas)  # Green's function of the central source, all frequencies
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
     launches = 3 * nsub * (g.nz - 1)
     cells = g.nx * nth
     stage_ms = (t1 - t0) * 1e3 / launches
     achieved = cells * FLOP_PCELL_STAGE / (stage_ms * 1e-3) / 1e12
     return {"grid": [g.nx, g.nz, nth], "theta_max_deg": float(np.degrees(theta_max)), "substeps_per_level": nsub,
             "stage_launches": launches, "march_s": t1 - t0, "pick_s": t2 - t1, "sources": nsrc,
+            "beam_sum_s": t3 - t2, "beam_frequencies": len(p.omegas), "beam_finite": bool(torch.isfinite(G).all()),
             "arrival_fraction": float(torch.isfinite(T).float().mean()),
             "cell_updates_per_s": cells * nsub * (g.nz - 1) / (t1 - t0),
             "roofline": {"bound": "alu", "kernel": "k_pstage (one depth-substep RK3 stage)",

@@ -65,7 +65,8 @@ enum { EGB_VX = 0, EGB_VZ = 1, EGB_VT = 2, EGB_A11 = 3, EGB_A12 = 4, EGB_A21 = 5
 enum { EGB_NFIELD = 5, EGB_NTAYLOR = 6 };
 
 /* Workspace queries (egb_workspace_size op argument). */
-enum { EGB_OP_VELOCITY = 0, EGB_OP_STEP = 1, EGB_OP_BEAM = 2, EGB_OP_ADJOINT = 3, EGB_OP_PARAXIAL = 4 };
+enum { EGB_OP_VELOCITY = 0, EGB_OP_STEP = 1, EGB_OP_BEAM = 2, EGB_OP_ADJOINT = 3, EGB_OP_PARAXIAL = 4,
+       EGB_OP_PBEAM = 5 };
 
 typedef struct {
     int32_t nx, nz, nth; /* cells in x, z (>= 8) and theta (>= 8) */
@@ -299,6 +300,26 @@ egb_status egb_paraxial_init(const egb_grid *g, const void *pvel, double theta_m
  * 3 nsub (nz - 1) stage launches run as one hipGraph; synchronises `stream`. */
 egb_status egb_paraxial_march(const egb_grid *g, const void *pvel, double theta_max, int32_t nsub, void *levels,
                               void *work, size_t work_bytes, hipStream_t stream);
+
+/* Green's function of a surface source at xs (on level 0) from the depth
+ * march: eq. 34 summed over Gamma(z_n) = {X = xs} (eq. 35) on every level.
+ * Per cell of the (x, theta) slice, the take-off-angle measure is the smoothed
+ * delta (width 2 dx) of the signed distance d = (X - xs)/|grad X| (theta
+ * scaled by dx/dtheta) times |det d(X, vartheta)/d(x, theta)| / |grad X|; the
+ * beam is sqrt(v/C) sqrt(u1/s)/s exp(i omega T), T = tau + p_s (X - xs) +
+ * p1 (x0 - x) + M (x0 - x)^2 / 2, with M the traveltime Hessian along the
+ * row (M = B C^-1 across the ray), u1 = cos + sin u and s the 2D beam weight
+ * at the take-off angle for the medium frozen at the source, p_s the
+ * take-off slowness (the ray through a cell off Gamma starts at X), p1 as
+ * chosen by lin_variant (see egb_source); the sum is scaled by i/(4 pi).
+ * In: coeff2d (egb_medium_table), levels (egb_paraxial_march), omegas (HOST
+ * float64 [nw], rad/s).  Out: out, complex [nw][nx][nz] (re, im) in the grid
+ * dtype, row n = level n (row 0 is 0).  work: egb_workspace_size(g,
+ * EGB_OP_PBEAM).  Synchronises `stream` once; EGB_EWORKSPACE if a level's
+ * beam list overflowed. */
+egb_status egb_paraxial_beam_sum(const egb_grid *g, const void *coeff2d, const void *levels, double theta_max,
+                                 double xs, int32_t lin_variant, const double *omegas, int32_t nw, void *out,
+                                 void *work, size_t work_bytes, hipStream_t stream);
 
 /* First arrivals of nsrc surface sources at every (x_i, z_n): roots in theta
  * of X - x_s between adjacent nodes (linear interpolation of X and tau), the

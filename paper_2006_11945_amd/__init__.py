@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(HERE, "libegb.so")
 EGB_OK, EGB_EINVAL, EGB_ECFL, EGB_EWORKSPACE, EGB_EHIP, EGB_ENONFINITE, EGB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 EGB_F32, EGB_F64 = 0, 1
 EGB_PHI1, EGB_RE_C, EGB_IM_C, EGB_RE_B, EGB_IM_B, EGB_PSI = range(6)
-EGB_OP_VELOCITY, EGB_OP_STEP, EGB_OP_BEAM, EGB_OP_ADJOINT, EGB_OP_PARAXIAL = range(5)
+EGB_OP_VELOCITY, EGB_OP_STEP, EGB_OP_BEAM, EGB_OP_ADJOINT, EGB_OP_PARAXIAL, EGB_OP_PBEAM = range(6)
 STATE_PLANES = ("phi1", "ReC", "ImC", "ReB", "ImB", "psi")
 VEL_PLANES = ("Vx", "Vz", "Vt", "A11", "A12", "A21", "A22")
 PAR_PLANES = ("X", "vartheta", "ReC", "ImC", "ReB", "ImB", "tau")   # paraxial level planes, in memory order
@@ -99,8 +99,9 @@ def _load():
     L.egb_paraxial_init.argtypes = [G, vp, d, d, vp, vp]
     L.egb_paraxial_march.argtypes = [G, vp, d, i32, vp, vp, sz, vp]
     L.egb_paraxial_pick.argtypes = [G, vp, vp, i32, vp, vp]
+    L.egb_paraxial_beam_sum.argtypes = [G, vp, vp, d, d, i32, dp, i32, vp, vp, sz, vp]
     for name in ("egb_medium_table", "egb_paraxial_velocity", "egb_paraxial_init", "egb_paraxial_march",
-                 "egb_paraxial_pick"):
+                 "egb_paraxial_pick", "egb_paraxial_beam_sum"):
         getattr(L, name).restype = ctypes.c_int
     L.egb_status_string.argtypes = [i32]; L.egb_status_string.restype = ctypes.c_char_p
     return L
@@ -267,6 +268,15 @@ def egb_paraxial_pick(eg, levels, xs, T, stream=None):
                                                        _stream(stream)))
 
 
+def egb_paraxial_beam_sum(eg, coeff2d, levels, theta_max: float, xs: float, lin: int, omegas, out, work,
+                          stream=None):
+    om = np.ascontiguousarray(np.atleast_1d(np.asarray(omegas, dtype=np.float64)))
+    rc = _lib.egb_paraxial_beam_sum(ctypes.byref(eg), _ptr(coeff2d), _ptr(levels), float(theta_max), float(xs),
+                                    int(lin), om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(om), _ptr(out),
+                                    _ptr(work), work.numel(), _stream(stream))
+    _check("egb_paraxial_beam_sum", rc)
+
+
 def make_problem_array(solvers, dts=None):
     """ctypes array of egb_problem from Solver objects (their own dt_cfl unless given)."""
     arr = (EgbProblem * len(solvers))()
@@ -423,6 +433,7 @@ class Paraxial:
         self.levels = alloc_bytes(eg.nz * paraxial_level_bytes(eg), self.device)
         self.work_vel = alloc_bytes(workspace_size(eg, EGB_OP_VELOCITY), self.device)
         self.work = alloc_bytes(workspace_size(eg, EGB_OP_PARAXIAL), self.device)
+        self.work_beam = None
         self.rate = None
 
     def velocity(self, stream=None) -> float:
@@ -446,6 +457,19 @@ class Paraxial:
         if out is None:
             out = torch.empty((x.numel(), self.eg.nz, self.eg.nx), dtype=torch.float64, device=self.device)
         egb_paraxial_pick(self.eg, self.levels, x, out, stream)
+        return out
+
+    def beam(self, xs: float, omegas, lin: int = EGB_LIN_EXACT, out: Optional[torch.Tensor] = None,
+             stream=None) -> torch.Tensor:
+        """Green's function [nw][nx][nz][re, im] of a surface source at xs
+        (row n = depth level n)."""
+        om = np.atleast_1d(np.asarray(omegas, dtype=np.float64))
+        if self.work_beam is None:
+            self.work_beam = alloc_bytes(workspace_size(self.eg, EGB_OP_PBEAM), self.device)
+        if out is None:
+            out = torch.empty((len(om), self.eg.nx, self.eg.nz, 2), dtype=real_dtype(self.eg), device=self.device)
+        egb_paraxial_beam_sum(self.eg, self.coeff2d, self.levels, self.theta_max, xs, lin, om, out, self.work_beam,
+                              stream)
         return out
 
     def level(self, n: int) -> dict:

@@ -246,7 +246,113 @@ __global__ void k_fill_i32(int* p, int n) {
     if (i < n) p[i] = 0;
 }
 
+// Beam records of the depth march for a surface source at xs: thread
+// (x, theta, level n >= 1).  A cell near Gamma = {X = xs} (signed distance d
+// = (X - xs) / |grad X|, theta scaled by lambda = dx / dtheta, |d| < 2 dx)
+// becomes a row-n record with the take-off-angle measure
+// delta_h(d) |det d(X, vartheta)/d(x, theta)| / |grad X| dx dtheta, the row
+// Hessian of the phase-space beam sum, traveltime tau + p_s (X - xs) (the ray
+// through the cell starts at X) and amplitude sqrt(v / C) sqrt(u1 / s) / s:
+// the depth march starts a beam with C(0) = u1 = cos + sin u, the point-source
+// data with C(0) = s, both for the medium frozen at the source.
+template <typename R>
+__global__ __launch_bounds__(256) void k_pbeam_compact(PBeamArgs a) {
+    const int ix = blockIdx.x * 64 + threadIdx.x, k = blockIdx.y * 4 + threadIdx.y, n = blockIdx.z + 1;
+    if (ix >= a.nx || k >= a.nth || n >= a.nz) return;
+    const long long P = a.P, c = (long long)k * a.nx + ix;
+    const R* L = reinterpret_cast<const R*>(static_cast<const char*>(a.levels) + (size_t)n * a.level_bytes);
+    const double tau = reinterpret_cast<const double*>(L + 6 * P)[c];
+    if (!(tau > 0.0)) return;
+    const R* X = L;           // plane 0
+    const R* T = L + P;       // plane 1: vartheta
+    const double Xx = cd4(X + (long long)k * a.nx, 1, a.nx, ix, a.dx);
+    const double Xt = cd4(X + ix, a.nx, a.nth, k, a.dth);
+    const double Tx = cd4(T + (long long)k * a.nx, 1, a.nx, ix, a.dx);
+    const double Tt = cd4(T + ix, a.nx, a.nth, k, a.dth);
+    const double lam = a.dx / a.dth, h = 2.0 * a.dx;
+    const double gX = sqrt(Xx * Xx + (Xt / lam) * (Xt / lam));
+    const double Xc = (double)X[c];
+    const double d = (Xc - a.xs) / gX;
+    if (!(fabs(d) < h)) return;
+    const double meas = delta_h(d, h) * fabs(Xx * Tt - Xt * Tx) / gX * a.dx * a.dth;
+    // local phase-velocity jet and ray direction at (x, z_n, theta)
+    MediumPoint M;
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) M.m[f][t] = a.coeff2d[cidx2(a.g, f, t, ix, n)];
+    const double th = -a.theta_max + (k + 0.5) * a.dth;
+    const VJet J = qp_velocity(M, th);
+    const VelA va = velocity_and_drt(J, th);
+    double sn, cs;
+    sincos_d(th, &sn, &cs);
+    const double v = J.v, vx = J.g[0], vz = J.g[1], vt = J.g[2];
+    const double sp = sqrt(va.V[0] * va.V[0] + va.V[1] * va.V[1]);
+    const double hxr = va.V[0] / sp, hzr = va.V[1] / sp;
+    const double ex = hzr, ez = -hxr;
+    const double reC = (double)L[2 * P + c], imC = (double)L[3 * P + c];
+    const double reB = (double)L[4 * P + c], imB = (double)L[5 * P + c];
+    const double e_pth = ex * (cs / v - sn * vt / (v * v)) + ez * (-sn / v - cs * vt / (v * v));
+    const double e_dxp_e = -(ex * sn + ez * cs) * (vx * ex + vz * ez) / (v * v);
+    const double qx = -vx / (v * sp), qz = -vz / (v * sp);
+    const double gq = hxr * qx + hzr * qz, eq = ex * qx + ez * qz;
+    const double den = reC * reC + imC * imC;
+    const double BCre = (reB * reC + imB * imC) / den, BCim = (imB * reC - reB * imC) / den;
+    const double Mnre = e_pth * BCre + e_dxp_e, Mnim = e_pth * BCim;
+    const double vCre = v * reC / den, vCim = -v * imC / den;
+    const double mod = sqrt(vCre * vCre + vCim * vCim);
+    double sqre = sqrt(0.5 * (mod + vCre));
+    double sqim = sqrt(0.5 * fmax(mod - vCre, 0.0));
+    sqim = vCim < 0.0 ? -sqim : sqim;
+    // source normalisation at the take-off angle (medium frozen at the source)
+    const double vt0 = (double)T[c];
+    MediumPoint Ms;
+    {
+        // bilinear in the table at (xs, depth of level 0)
+        const double fx = (a.xs - a.g.x0) / a.dx - 0.5;
+        const int sx = min(max((int)floor(fx), 0), a.nx - 2);
+        const double tx = fmin(fmax(fx - sx, 0.0), 1.0);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) Ms.m[f][t] = 0.0;
+            Ms.m[f][0] = (1.0 - tx) * a.coeff2d[cidx2(a.g, f, 0, sx, 0)] + tx * a.coeff2d[cidx2(a.g, f, 0, sx + 1, 0)];
+        }
+    }
+    const VJet Js = qp_velocity(Ms, vt0);
+    const VelA vs = velocity_and_drt(Js, vt0);
+    double s0, c0;
+    sincos_d(vt0, &s0, &c0);
+    const double u1 = c0 + s0 * vs.V[0] / vs.V[1];
+    const double Wt = Ms.m[1][0] / (Js.v * Js.v);
+    const double ssrc = cbrt((sqrt(Js.v) / Wt) * (sqrt(Js.v) / Wt));
+    const double w = sqrt(u1 / ssrc) / ssrc * meas;
+    BeamRec r;
+    r.psi = tau + s0 / Js.v * (Xc - a.xs);
+    r.pos = a.g.x0 + (ix + 0.5) * a.dx;
+    r.p = a.lin == EGB_LIN_PAPER28 ? lin28(sn, cs, va.V[0] / va.V[1], v) : sn / v;
+    r.Mre = Mnre * hzr * hzr + 2.0 * eq * hxr * hzr + gq * hxr * hxr;
+    r.Mim = Mnim * hzr * hzr;
+    r.are = w * sqre;
+    r.aim = w * sqim;
+    r.pad = 0.0;
+    const int slot = atomicAdd(&a.counts[n], 1);
+    if (slot < a.cap) reinterpret_cast<BeamRec*>(a.rows)[(long long)n * a.cap + slot] = r;
+}
+
 }  // namespace
+
+hipError_t launch_pbeam_compact(const PBeamArgs& a, int dtype, hipStream_t s) {
+    const int nl = a.g.nz + a.g.nx;
+    k_fill_i32<<<(nl + 255) / 256, 256, 0, s>>>(a.counts, nl);
+    if (a.nz < 2) return hipGetLastError();
+    const dim3 grid((a.nx + 63) / 64, (a.nth + 3) / 4, a.nz - 1), block(64, 4);
+    if (dtype == EGB_F64)
+        k_pbeam_compact<double><<<grid, block, 0, s>>>(a);
+    else
+        k_pbeam_compact<float><<<grid, block, 0, s>>>(a);
+    return hipGetLastError();
+}
 
 hipError_t launch_beam_compact(const BeamArgs& a, int dtype, hipStream_t s) {
     const int nl = a.g.nz + a.g.nx;

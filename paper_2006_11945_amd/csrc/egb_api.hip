@@ -37,6 +37,8 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 // Default beam-list capacity per row / column.
 int beam_cap_default(const egb_grid& g) { return 16 * ((g.nx > g.nz ? g.nx : g.nz) + g.nth) + 64; }
+// ... per depth level of the paraxial beam sum.
+int pbeam_cap_default(const egb_grid& g) { return 16 * (g.nx + g.nth) + 64; }
 
 size_t beam_counts_bytes(const egb_grid& g) { return align256((size_t)(g.nx + g.nz) * sizeof(int)); }
 
@@ -71,6 +73,7 @@ size_t egb_workspace_size(const egb_grid* g, int32_t op) {
         case EGB_OP_BEAM:
             return beam_counts_bytes(*g) + (size_t)(g->nx + g->nz) * beam_cap_default(*g) * beam_record_bytes();
         case EGB_OP_PARAXIAL: return 2 * align256(paraxial_level_bytes(*g));
+        case EGB_OP_PBEAM: return beam_counts_bytes(*g) + (size_t)g->nz * pbeam_cap_default(*g) * beam_record_bytes();
         case EGB_OP_ADJOINT: {
             const size_t step = 5 * align256(state_bytes(*g));
             const size_t med = align256((size_t)15 * g->nx * g->nz * sizeof(double)) +
@@ -359,6 +362,62 @@ egb_status egb_paraxial_march(const egb_grid* g, const void* pvel, double theta_
     if (graph) hipGraphDestroy(graph);
     if (cs) hipStreamDestroy(cs);
     return hip_status(e);
+}
+
+egb_status egb_paraxial_beam_sum(const egb_grid* g, const void* coeff2d, const void* levels, double theta_max,
+                                 double xs, int32_t lin_variant, const double* omegas, int32_t nw, void* out,
+                                 void* work, size_t work_bytes, hipStream_t stream) {
+    if (!grid_ok(g) || !coeff2d || !levels || !theta_max_ok(theta_max) || !isfinite(xs) || !omegas || nw < 1 ||
+        !out || !work || (lin_variant != EGB_LIN_EXACT && lin_variant != EGB_LIN_PAPER28))
+        return EGB_EINVAL;
+    if (!aligned16(coeff2d) || !aligned16(levels) || !aligned16(out) || !aligned16(work)) return EGB_EINVAL;
+    for (int w = 0; w < nw; ++w)
+        if (!isfinite(omegas[w]) || !(omegas[w] > 0.0)) return EGB_EINVAL;
+    const size_t cb = beam_counts_bytes(*g);
+    const size_t per = (size_t)g->nz * beam_record_bytes();
+    if (work_bytes < cb + per) return EGB_EWORKSPACE;
+    const size_t capz = (work_bytes - cb) / per;
+    const int cap = capz > (size_t)(1 << 30) ? (1 << 30) : (int)capz;
+    char* w = static_cast<char*>(work);
+    PBeamArgs pa;
+    pa.g = grid_args(*g);
+    pa.coeff2d = static_cast<const double*>(coeff2d);
+    pa.levels = levels;
+    pa.level_bytes = paraxial_level_bytes(*g);
+    pa.P = (long long)paraxial_stride(*g);
+    pa.nx = g->nx;
+    pa.nz = g->nz;
+    pa.nth = g->nth;
+    pa.lin = lin_variant;
+    pa.cap = cap;
+    pa.dx = g->dx;
+    pa.dth = 2.0 * theta_max / g->nth;
+    pa.theta_max = theta_max;
+    pa.xs = xs;
+    pa.counts = reinterpret_cast<int*>(w);
+    pa.rows = w + cb;
+    // the line sums of the phase-space beam sum, rows only (column lists empty)
+    BeamArgs ba;
+    ba.g = pa.g;
+    ba.coeff2d = pa.coeff2d;
+    ba.vel = nullptr;
+    ba.U = levels;
+    ba.beta = 0.0;
+    ba.lin = lin_variant;
+    ba.cap = cap;
+    ba.counts = pa.counts;
+    ba.rows = pa.rows;
+    ba.cols = pa.rows;
+    hipError_t e = launch_pbeam_compact(pa, g->dtype, stream);
+    if (e == hipSuccess) e = launch_beam_sum(ba, g->dtype, omegas, nw, out, stream);
+    std::vector<int> counts(g->nz);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(counts.data(), pa.counts, counts.size() * sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return EGB_EHIP;
+    for (int c : counts)
+        if (c > cap) return EGB_EWORKSPACE;
+    return EGB_OK;
 }
 
 egb_status egb_paraxial_pick(const egb_grid* g, const void* levels, const double* xs, int32_t nsrc, double* T,

@@ -147,6 +147,19 @@ struct BeamArgs {
     void* cols;       // column records
 };
 hipError_t launch_beam_compact(const BeamArgs& a, int dtype, hipStream_t s);
+// Beam records of the depth march (rows = levels; see beam.hip).
+struct PBeamArgs {
+    GridArgs g;               // output geometry (rows: levels, columns: x)
+    const double* coeff2d;
+    const void* levels;
+    size_t level_bytes;
+    long long P;              // level plane stride (elements)
+    int nx, nz, nth, lin, cap;
+    double dx, dth, theta_max, xs;
+    int* counts;              // [nz rows][nx columns] (columns stay 0)
+    void* rows;
+};
+hipError_t launch_pbeam_compact(const PBeamArgs& a, int dtype, hipStream_t s);
 hipError_t launch_beam_sum(const BeamArgs& a, int dtype, const double* omegas, int nw, void* out, hipStream_t s);
 size_t beam_record_bytes();
 
