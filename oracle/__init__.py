@@ -57,7 +57,9 @@ def lib():
         L.oc_weno.argtypes = [P, i]; L.oc_weno.restype = d
         L.oc_march.argtypes = [i, i, i, d, d, d, d, P, d, d, d, P, P, d, i]
         L.oc_beam_sum.argtypes = [i, i, i, d, d, d, d, P, P, d, i, P, P, i, P]
-        L.oc_pbeam_sum.argtypes = [i, i, i, d, d, d, d, d, P, P, d, i, P, i, P]
+        L.oc_pbeam_sum.argtypes = [i, i, i, d, d, d, d, d, P, P, d, i, i, P, i, P]
+        L.oc_qp_polarization.argtypes = [P, d, P]
+        L.oc_qp_polarization.restype = None
         L.oc_lin28.argtypes = [d, d, d, d]
         L.oc_lin28.restype = d
         L.oc_pick.argtypes = [i, i, i, d, d, d, d, P, P, i, P]
@@ -223,18 +225,26 @@ def pmarch(grid, pvel: np.ndarray, theta_max: float, U0: np.ndarray, nsub: int) 
     return Uall
 
 
-def pbeam_sum(grid, tab, Uall, theta_max: float, xs: float, omegas, lin: int = 0) -> np.ndarray:
+def pbeam_sum(grid, tab, Uall, theta_max: float, xs: float, omegas, lin: int = 0, comp: int = -1) -> np.ndarray:
     """Green's function [nw][nx][nz] of a surface source at xs from the
-    depth-march levels (row n = depth level n; row 0 left zero)."""
+    depth-march levels (row n = depth level n; row 0 left zero); comp =
+    2 i + k >= 0: the (i, k) component of the qP Green's tensor (x = 0, z = 1)."""
     om = _c(np.atleast_1d(omegas))
     out = np.zeros((len(om), grid.nx, grid.nz, 2))
     rc = lib().oc_pbeam_sum(grid.nx, grid.nz, grid.nth, grid.x0, grid.z0, grid.dx, grid.dz, float(theta_max),
-                            _p(_c(tab)), _p(_c(Uall)), float(xs), int(lin), _p(om), len(om), _p(out))
+                            _p(_c(tab)), _p(_c(Uall)), float(xs), int(lin), int(comp), _p(om), len(om), _p(out))
     if rc == -3:
         raise RuntimeError("oracle beam list overflow")
     if rc != 0:
         raise MemoryError("oc_pbeam_sum")
     return out[..., 0] + 1j * out[..., 1]
+
+
+def qp_polarization(ms, theta: float) -> np.ndarray:
+    """qP polarisation (g_x, g_z) for medium values (a11, a33, a13 + a55, a55, nu)."""
+    g = np.zeros(2)
+    lib().oc_qp_polarization(_p(_c(ms)), float(theta), _p(g))
+    return g
 
 
 def lin28(s: float, c: float, u: float, v: float) -> float:

@@ -99,3 +99,24 @@ def green_aniso_far(R_dir_theta, R, omega, vp0, eps, delta, fs=0.5, tilt=0.0, h=
     a33 = vp0 ** 2
     amp = a33 / (4 * np.pi) * np.sqrt(2 * np.pi / (omega * R * dphig * v * v * nV))
     return x, 1j * amp * np.exp(1j * (omega * T - np.pi / 4))
+
+
+def qp_polarization(theta, vp0, eps, delta, fs=0.5, tilt=0.0):
+    """qP polarisation vector (g_x, g_z) of a 2D TTI medium: the eigenvector of
+    the lab-frame Christoffel matrix Gamma_ik = c_ijkl n_j n_l for its largest
+    eigenvalue (numpy's symmetric eigen-solver), the stiffness rotated from
+    the symmetry frame by the tilt, signed along the phase direction n."""
+    a33 = vp0 ** 2
+    a55 = (fs * vp0) ** 2
+    a11 = a33 * (1 + 2 * eps)
+    a13 = np.sqrt((a33 - a55) * (a33 * (1 + 2 * delta) - a55)) - a55
+    n = np.array([np.sin(theta), np.cos(theta)])
+    # rotation taking symmetry-frame vectors (angle from z toward x) to the lab frame
+    c, s = np.cos(tilt), np.sin(tilt)
+    Rm = np.array([[c, s], [-s, c]])
+    npr = Rm.T @ n
+    G = np.array([[a11 * npr[0] ** 2 + a55 * npr[1] ** 2, (a13 + a55) * npr[0] * npr[1]],
+                  [(a13 + a55) * npr[0] * npr[1], a55 * npr[0] ** 2 + a33 * npr[1] ** 2]])
+    w, V = np.linalg.eigh(Rm @ G @ Rm.T)
+    g = V[:, -1]
+    return g if g @ n >= 0 else -g

@@ -291,6 +291,30 @@ int oc_velocity(int nx, int nz, int nth, double dx, double dz, const double *tab
 }
 
 /* ------------------------------------------------------------------------ */
+/* qP polarisation (eqs. 4, 31-32): the unit eigenvector of the 2x2
+ * Christoffel matrix for its larger eigenvalue, phase angle theta, medium
+ * values ms = (a11, a33, b = a13 + a55, a55, nu).  Built in the symmetry
+ * frame (phase angle theta - nu), turned back by nu, and signed so that it
+ * points along the phase direction (g . n > 0).                            */
+void oc_qp_polarization(const double *ms, double theta, double g[2])
+{
+    double ph = theta - ms[4], n1 = sin(ph), n3 = cos(ph);
+    double g11 = ms[0] * n1 * n1 + ms[3] * n3 * n3, g33 = ms[3] * n1 * n1 + ms[1] * n3 * n3, g13 = ms[2] * n1 * n3;
+    double G = 0.5 * (g11 + g33 + sqrt((g11 - g33) * (g11 - g33) + 4.0 * g13 * g13));
+    /* (G - g33, g13) and (g13, G - g11) both solve the system; take the longer */
+    double a1 = G - g33, a3 = g13, b1 = g13, b3 = G - g11;
+    double vx, vz;
+    if (a1 * a1 + a3 * a3 >= b1 * b1 + b3 * b3) { vx = a1; vz = a3; } else { vx = b1; vz = b3; }
+    double nv = sqrt(vx * vx + vz * vz);
+    if (nv == 0.0) { vx = n1; vz = n3; nv = 1.0; } /* isotropic: any vector; the phase direction */
+    vx /= nv;
+    vz /= nv;
+    if (vx * n1 + vz * n3 < 0.0) { vx = -vx; vz = -vz; }
+    double cn = cos(ms[4]), sn = sin(ms[4]);
+    g[0] = vx * cn + vz * sn;
+    g[1] = -vx * sn + vz * cn;
+}
+
 /* Point-source data (reading of eqs. 20 and 24 for a point source).  The
  * medium is frozen at the source: the table fields are bilinearly
  * interpolated there.  For each theta the homogeneous solution is
@@ -878,10 +902,13 @@ int oc_pmarch(int nx, int nz, int nth, double dx, double dz, double theta_max, c
  * from x_s: its traveltime is moved to the source to first order by the
  * take-off slowness p_s = sin(vartheta) / v_s (the point-source data of the
  * phase-space march carries this term in psi itself).  lin != 0: eq. 28's
- * linear coefficient.  Row 0 (the source row) is left 0.
+ * linear coefficient.  comp >= 0: component (i, k) = (comp / 2, comp % 2)
+ * (0 = x, 1 = z) of the Green's tensor, each beam weighted by the qP
+ * polarisations g_i at the cell and g_k at the source for the take-off angle
+ * (eqs. 31-32); comp < 0: the scalar sum.  Row 0 (the source row) is 0.
  * Output out[w][ix][n][re/im].                                             */
 int oc_pbeam_sum(int nx, int nz, int nth, double x0, double z0, double dx, double dz, double theta_max,
-                 const double *tab, const double *Uall, double xs, int lin, const double *omegas, int nw,
+                 const double *tab, const double *Uall, double xs, int lin, int comp, const double *omegas, int nw,
                  double *out)
 {
     double dth = 2.0 * theta_max / nth, lam = dx / dth, h = 2.0 * dx;
@@ -938,6 +965,13 @@ int oc_pbeam_sum(int nx, int nz, int nth, double x0, double z0, double dx, doubl
                 r.p = lin ? oc_lin28(sn, cs, gx / gz, v) : sn / v;
                 r.M = Mn * gz * gz + 2.0 * gpq * gx * gz + gq * gx * gx;
                 r.amp = csqrt(v / C) * sqrt(u1 / ss) / ss * meas;
+                if (comp >= 0) { /* g_i at the cell (phase angle theta) times g_k at the source (vartheta) */
+                    double mr[NFLD], gr[2], gs[2];
+                    for (int m = 0; m < NFLD; ++m) mr[m] = tab[(((long)i * nz + n) * NFLD + m) * NTAY];
+                    oc_qp_polarization(mr, th, gr);
+                    oc_qp_polarization(ms, vt0, gs);
+                    r.amp *= gr[comp / 2] * gs[comp % 2];
+                }
                 if (nrow[n] < cap) rows[(long)n * cap + nrow[n]++] = r; else overflow = 1;
             }
     }

@@ -122,3 +122,51 @@ def test_paraxial_beam_sum_matches_green(eps, tilt):
     if eps == 0.0:
         G1 = oracle.pbeam_sum(g, r["tab"], r["U"], TMAX, xs, om, lin=1)
         assert np.linalg.norm(G1 - G) <= 1e-10 * np.linalg.norm(G)
+
+
+def test_qp_polarization_matches_library_eigenvectors():
+    """Eqs. 31-32's g: the oracle's qP eigenvector against numpy's symmetric
+    eigen-solver on the lab-frame Christoffel matrix (TTI, any direction)."""
+    vp0, eps, dl, fs = 2500.0, 0.25, 0.05, 0.5
+    for tilt in (0.0, 0.4, -0.7):
+        a33, a55 = vp0 ** 2, (fs * vp0) ** 2
+        a11 = a33 * (1 + 2 * eps)
+        b = np.sqrt((a33 - a55) * (a33 * (1 + 2 * dl) - a55))
+        ms = np.array([a11, a33, b, a55, tilt])
+        for th in np.linspace(-3.1, 3.1, 40):
+            g = oracle.qp_polarization(ms, th)
+            assert np.abs(g - CF.qp_polarization(th, vp0, eps, dl, fs, tilt)).max() < 1e-12
+
+
+@pytest.mark.parametrize("eps,tilt", [(0.0, 0.0), (0.2, 0.3)])
+def test_paraxial_green_tensor(eps, tilt):
+    """Components G_ik of the qP Green's tensor from the depth march (each
+    beam weighted by g_i at the cell and g_k at the source, eqs. 31-32)
+    against g_i g_k of the stationary ray times the scalar closed form:
+    r_i r_k H in isotropic media, the elliptic polarisation of the phase
+    angle whose group direction reaches the receiver otherwise."""
+    n, L, v = 96, 1000.0, 2000.0
+    g = W.Grid(nx=2 * n, nz=n, nth=n, dx=L / n, dz=L / n)
+    xs = n * g.dx
+    r = oracle.psolve(g, W.homogeneous(g, v, eps, eps, tilt), TMAX, 1 / (2 * L))
+    om = W.hz([30.0])
+    zs = g.zc()[0]
+    X, Z = np.meshgrid(g.xc(), g.zc(), indexing="ij")
+    R = np.hypot(X - xs, Z - zs)
+    m = (R >= 3 * 2 * np.pi * v / om[0]) & (np.arctan2(np.abs(X - xs), Z - zs) < np.radians(20)) \
+        & (np.abs(X - xs) < 300.0)
+    H = CF.green_elliptic(X, Z, xs, zs, v, eps, om[0], tilt)
+    # phase angle of the ray to each receiver: elliptic, in the symmetry frame
+    dx_, dz_ = X - xs, Z - zs
+    xr = dx_ * np.cos(tilt) - dz_ * np.sin(tilt)
+    zr = dx_ * np.sin(tilt) + dz_ * np.cos(tilt)
+    th = np.arctan2(xr / (1 + 2 * eps), zr) + tilt
+    gpol = np.stack([np.vectorize(lambda t: CF.qp_polarization(t, v, eps, eps, 0.5, tilt)[c])(th[m])
+                     for c in (0, 1)])
+    num = den = 0.0
+    for comp in range(4):
+        G = oracle.pbeam_sum(g, r["tab"], r["U"], TMAX, xs, om, comp=comp)[0][m]
+        ref = gpol[comp // 2] * gpol[comp % 2] * H[m]
+        num += np.linalg.norm(G - ref) ** 2
+        den += np.linalg.norm(ref) ** 2
+    assert np.sqrt(num / den) < 0.05, np.sqrt(num / den)
