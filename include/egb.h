@@ -312,14 +312,19 @@ egb_status egb_paraxial_march(const egb_grid *g, const void *pvel, double theta_
  * at the take-off angle for the medium frozen at the source, p_s the
  * take-off slowness (the ray through a cell off Gamma starts at X), p1 as
  * chosen by lin_variant (see egb_source); the sum is scaled by i/(4 pi).
+ * component = -1 gives this scalar sum; component = 2 i + k (0 = x, 1 = z)
+ * gives G_ik of the qP Green's tensor (eqs. 31-32): every beam weighted by
+ * g_i, the qP polarisation (unit eigenvector of the Christoffel matrix, eq. 4,
+ * along the phase direction) at the cell, times g_k at the source for the
+ * take-off angle.
  * In: coeff2d (egb_medium_table), levels (egb_paraxial_march), omegas (HOST
  * float64 [nw], rad/s).  Out: out, complex [nw][nx][nz] (re, im) in the grid
  * dtype, row n = level n (row 0 is 0).  work: egb_workspace_size(g,
  * EGB_OP_PBEAM).  Synchronises `stream` once; EGB_EWORKSPACE if a level's
  * beam list overflowed. */
 egb_status egb_paraxial_beam_sum(const egb_grid *g, const void *coeff2d, const void *levels, double theta_max,
-                                 double xs, int32_t lin_variant, const double *omegas, int32_t nw, void *out,
-                                 void *work, size_t work_bytes, hipStream_t stream);
+                                 double xs, int32_t lin_variant, int32_t component, const double *omegas, int32_t nw,
+                                 void *out, void *work, size_t work_bytes, hipStream_t stream);
 
 /* First arrivals of nsrc surface sources at every (x_i, z_n): roots in theta
  * of X - x_s between adjacent nodes (linear interpolation of X and tau), the

@@ -99,7 +99,7 @@ def _load():
     L.egb_paraxial_init.argtypes = [G, vp, d, d, vp, vp]
     L.egb_paraxial_march.argtypes = [G, vp, d, i32, vp, vp, sz, vp]
     L.egb_paraxial_pick.argtypes = [G, vp, vp, i32, vp, vp]
-    L.egb_paraxial_beam_sum.argtypes = [G, vp, vp, d, d, i32, dp, i32, vp, vp, sz, vp]
+    L.egb_paraxial_beam_sum.argtypes = [G, vp, vp, d, d, i32, i32, dp, i32, vp, vp, sz, vp]
     for name in ("egb_medium_table", "egb_paraxial_velocity", "egb_paraxial_init", "egb_paraxial_march",
                  "egb_paraxial_pick", "egb_paraxial_beam_sum"):
         getattr(L, name).restype = ctypes.c_int
@@ -268,12 +268,12 @@ def egb_paraxial_pick(eg, levels, xs, T, stream=None):
                                                        _stream(stream)))
 
 
-def egb_paraxial_beam_sum(eg, coeff2d, levels, theta_max: float, xs: float, lin: int, omegas, out, work,
+def egb_paraxial_beam_sum(eg, coeff2d, levels, theta_max: float, xs: float, lin: int, comp: int, omegas, out, work,
                           stream=None):
     om = np.ascontiguousarray(np.atleast_1d(np.asarray(omegas, dtype=np.float64)))
     rc = _lib.egb_paraxial_beam_sum(ctypes.byref(eg), _ptr(coeff2d), _ptr(levels), float(theta_max), float(xs),
-                                    int(lin), om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(om), _ptr(out),
-                                    _ptr(work), work.numel(), _stream(stream))
+                                    int(lin), int(comp), om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(om),
+                                    _ptr(out), _ptr(work), work.numel(), _stream(stream))
     _check("egb_paraxial_beam_sum", rc)
 
 
@@ -460,16 +460,17 @@ class Paraxial:
         return out
 
     def beam(self, xs: float, omegas, lin: int = EGB_LIN_EXACT, out: Optional[torch.Tensor] = None,
-             stream=None) -> torch.Tensor:
+             stream=None, comp: int = -1) -> torch.Tensor:
         """Green's function [nw][nx][nz][re, im] of a surface source at xs
-        (row n = depth level n)."""
+        (row n = depth level n); comp = 2 i + k: component G_ik of the qP
+        Green's tensor (x = 0, z = 1), -1: the scalar sum."""
         om = np.atleast_1d(np.asarray(omegas, dtype=np.float64))
         if self.work_beam is None:
             self.work_beam = alloc_bytes(workspace_size(self.eg, EGB_OP_PBEAM), self.device)
         if out is None:
             out = torch.empty((len(om), self.eg.nx, self.eg.nz, 2), dtype=real_dtype(self.eg), device=self.device)
-        egb_paraxial_beam_sum(self.eg, self.coeff2d, self.levels, self.theta_max, xs, lin, om, out, self.work_beam,
-                              stream)
+        egb_paraxial_beam_sum(self.eg, self.coeff2d, self.levels, self.theta_max, xs, lin, comp, om, out,
+                              self.work_beam, stream)
         return out
 
     def level(self, n: int) -> dict:

@@ -246,6 +246,38 @@ __global__ void k_fill_i32(int* p, int n) {
     if (i < n) p[i] = 0;
 }
 
+// qP polarisation (eqs. 4, 31-32) for table values m = (a11, a33, a13 + a55,
+// a55, nu) and phase angle theta: the unit eigenvector of the 2x2
+// Christoffel matrix for the larger eigenvalue, found in the symmetry frame
+// (phase angle theta - nu) from the longer of its two null-space forms,
+// turned back by nu and signed along the phase direction.
+__device__ __forceinline__ void qp_polarization(const double (&m)[NF], double theta, double& gx, double& gz) {
+    double n1, n3;
+    sincos_d(theta - m[4], &n1, &n3);
+    const double g11 = m[0] * n1 * n1 + m[3] * n3 * n3, g33 = m[3] * n1 * n1 + m[1] * n3 * n3;
+    const double g13 = m[2] * n1 * n3;
+    const double G = 0.5 * (g11 + g33 + sqrt((g11 - g33) * (g11 - g33) + 4.0 * g13 * g13));
+    const double a1 = G - g33, a3 = g13, b1 = g13, b3 = G - g11;
+    const bool first = a1 * a1 + a3 * a3 >= b1 * b1 + b3 * b3;
+    double vx = first ? a1 : b1, vz = first ? a3 : b3;
+    double nv = sqrt(vx * vx + vz * vz);
+    if (nv == 0.0) {
+        vx = n1;
+        vz = n3;
+        nv = 1.0;
+    }
+    vx /= nv;
+    vz /= nv;
+    if (vx * n1 + vz * n3 < 0.0) {
+        vx = -vx;
+        vz = -vz;
+    }
+    double sn, cn;
+    sincos_d(m[4], &sn, &cn);
+    gx = vx * cn + vz * sn;
+    gz = -vx * sn + vz * cn;
+}
+
 // Beam records of the depth march for a surface source at xs: thread
 // (x, theta, level n >= 1).  A cell near Gamma = {X = xs} (signed distance d
 // = (X - xs) / |grad X|, theta scaled by lambda = dx / dtheta, |d| < 2 dx)
@@ -326,7 +358,18 @@ __global__ __launch_bounds__(256) void k_pbeam_compact(PBeamArgs a) {
     const double u1 = c0 + s0 * vs.V[0] / vs.V[1];
     const double Wt = Ms.m[1][0] / (Js.v * Js.v);
     const double ssrc = cbrt((sqrt(Js.v) / Wt) * (sqrt(Js.v) / Wt));
-    const double w = sqrt(u1 / ssrc) / ssrc * meas;
+    double w = sqrt(u1 / ssrc) / ssrc * meas;
+    if (a.comp >= 0) {  // Green's tensor component (i, k): g_i at the cell, g_k at the source
+        double mr[NF], ms[NF], grx, grz, gsx, gsz;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            mr[f] = M.m[f][0];
+            ms[f] = Ms.m[f][0];
+        }
+        qp_polarization(mr, th, grx, grz);
+        qp_polarization(ms, vt0, gsx, gsz);
+        w *= ((a.comp >> 1) ? grz : grx) * ((a.comp & 1) ? gsz : gsx);
+    }
     BeamRec r;
     r.psi = tau + s0 / Js.v * (Xc - a.xs);
     r.pos = a.g.x0 + (ix + 0.5) * a.dx;

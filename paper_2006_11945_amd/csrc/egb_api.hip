@@ -365,10 +365,11 @@ egb_status egb_paraxial_march(const egb_grid* g, const void* pvel, double theta_
 }
 
 egb_status egb_paraxial_beam_sum(const egb_grid* g, const void* coeff2d, const void* levels, double theta_max,
-                                 double xs, int32_t lin_variant, const double* omegas, int32_t nw, void* out,
-                                 void* work, size_t work_bytes, hipStream_t stream) {
+                                 double xs, int32_t lin_variant, int32_t component, const double* omegas, int32_t nw,
+                                 void* out, void* work, size_t work_bytes, hipStream_t stream) {
     if (!grid_ok(g) || !coeff2d || !levels || !theta_max_ok(theta_max) || !isfinite(xs) || !omegas || nw < 1 ||
-        !out || !work || (lin_variant != EGB_LIN_EXACT && lin_variant != EGB_LIN_PAPER28))
+        !out || !work || (lin_variant != EGB_LIN_EXACT && lin_variant != EGB_LIN_PAPER28) || component < -1 ||
+        component > 3)
         return EGB_EINVAL;
     if (!aligned16(coeff2d) || !aligned16(levels) || !aligned16(out) || !aligned16(work)) return EGB_EINVAL;
     for (int w = 0; w < nw; ++w)
@@ -389,6 +390,7 @@ egb_status egb_paraxial_beam_sum(const egb_grid* g, const void* coeff2d, const v
     pa.nz = g->nz;
     pa.nth = g->nth;
     pa.lin = lin_variant;
+    pa.comp = component;
     pa.cap = cap;
     pa.dx = g->dx;
     pa.dth = 2.0 * theta_max / g->nth;

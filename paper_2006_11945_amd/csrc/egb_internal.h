@@ -154,7 +154,7 @@ struct PBeamArgs {
     const void* levels;
     size_t level_bytes;
     long long P;              // level plane stride (elements)
-    int nx, nz, nth, lin, cap;
+    int nx, nz, nth, lin, comp, cap;  // comp: -1 scalar, else 2 i + k of the Green's tensor
     double dx, dth, theta_max, xs;
     int* counts;              // [nz rows][nx columns] (columns stay 0)
     void* rows;

@@ -206,12 +206,14 @@ def test_paraxial_full_size_first_levels():
         assert all(np.isfinite(v).all() for v in G.values()), n
 
 
-@pytest.mark.parametrize("dtype,lin", [("f64", 0), ("f32", 0), ("f32", 1)])
-def test_paraxial_beam_sum_parity(dtype, lin):
-    """Green's function from the depth march (eq. 34 over Gamma = {X = x_s})
-    on identical input: the oracle's levels, rounded to the storage, written
-    into the GPU buffer; relative L2 per frequency 1e-10 (FP64) and 1e-4
-    (FP32 planes: single-precision phase factors)."""
+@pytest.mark.parametrize("dtype,lin,comp", [("f64", 0, -1), ("f32", 0, -1), ("f32", 1, -1), ("f64", 0, 1),
+                                            ("f32", 0, 0), ("f32", 0, 2), ("f32", 0, 3)])
+def test_paraxial_beam_sum_parity(dtype, lin, comp):
+    """Green's function from the depth march (eq. 34 over Gamma = {X = x_s}),
+    scalar (comp = -1) or a component of the qP Green's tensor, on identical
+    input: the oracle's levels, rounded to the storage, written into the GPU
+    buffer; relative L2 per frequency 1e-10 (FP64) and 1e-4 (FP32 planes:
+    single-precision phase factors)."""
     g, med, beta = par_problem(tilt=True)
     o = oracle.psolve(g, med, TMAX, beta)
     U = o["U"].copy()
@@ -223,11 +225,11 @@ def test_paraxial_beam_sum_parity(dtype, lin):
     write_levels(P, U)
     xs = 0.45 * g.nx * g.dx + 2.0
     om = W.hz([15.0, 40.0])
-    out = P.beam(xs, om, lin=lin).cpu().numpy()
+    out = P.beam(xs, om, lin=lin, comp=comp).cpu().numpy()
     G = out[..., 0] + 1j * out[..., 1]
-    Go = oracle.pbeam_sum(g, o["tab"], U, TMAX, xs, om, lin=lin)
+    Go = oracle.pbeam_sum(g, o["tab"], U, TMAX, xs, om, lin=lin, comp=comp)
     for w in range(len(om)):
         e = np.linalg.norm(G[w] - Go[w]) / np.linalg.norm(Go[w])
-        log(f"  paraxial beam {dtype} lin={lin} omega {om[w]:.1f}: rel L2 {e:.2e}")
+        log(f"  paraxial beam {dtype} lin={lin} comp={comp} omega {om[w]:.1f}: rel L2 {e:.2e}")
         assert e < (1e-10 if dtype == "f64" else 1e-4)
     assert np.linalg.norm(Go[0]) > 0
