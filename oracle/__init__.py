@@ -65,8 +65,8 @@ def lib():
         L.oc_pick.argtypes = [i, i, i, d, d, d, d, P, P, i, P]
         L.oc_pvelocity.argtypes = [i, i, i, d, d, d, P, P, P]
         L.oc_pinit.argtypes = [i, i, d, d, d, P, d, P]
-        L.oc_pmarch.argtypes = [i, i, i, d, d, d, P, i, P]
-        L.oc_ppick.argtypes = [i, i, i, P, P, i, P]
+        L.oc_pmarch.argtypes = [i, i, i, d, d, d, P, i, P, P]
+        L.oc_ppick.argtypes = [i, i, i, d, P, P, i, P]
         _lib = L
     return _lib
 
@@ -215,11 +215,14 @@ def pinit(grid, pvel: np.ndarray, theta_max: float, beta: float) -> np.ndarray:
     return U
 
 
-def pmarch(grid, pvel: np.ndarray, theta_max: float, U0: np.ndarray, nsub: int) -> np.ndarray:
+def pmarch(grid, pvel: np.ndarray, theta_max: float, U0: np.ndarray, nsub: int, Ub=None) -> np.ndarray:
+    """Levels [nz][7][nth][nx] from U0 on level 0; Ub: the surface data held
+    in the ghosts (U0 itself when None)."""
     Uall = np.zeros((grid.nz, 7, grid.nth, grid.nx))
     Uall[0] = U0
+    Ub = _c(U0 if Ub is None else Ub)
     rc = lib().oc_pmarch(grid.nx, grid.nz, grid.nth, grid.dx, grid.dz, float(theta_max), _p(_c(pvel)), int(nsub),
-                         _p(Uall))
+                         _p(Ub), _p(Uall))
     if rc != 0:
         raise MemoryError("oc_pmarch")
     return Uall
@@ -252,10 +255,10 @@ def lin28(s: float, c: float, u: float, v: float) -> float:
     return lib().oc_lin28(float(s), float(c), float(u), float(v))
 
 
-def ppick(grid, Uall: np.ndarray, xs) -> np.ndarray:
+def ppick(grid, Uall: np.ndarray, xs, theta_max: float) -> np.ndarray:
     xs = _c(np.atleast_1d(xs))
     T = np.zeros((len(xs), grid.nz, grid.nx))
-    lib().oc_ppick(grid.nx, grid.nz, grid.nth, _p(_c(Uall)), _p(xs), len(xs), _p(T))
+    lib().oc_ppick(grid.nx, grid.nz, grid.nth, float(theta_max), _p(_c(Uall)), _p(xs), len(xs), _p(T))
     return T
 
 
@@ -266,5 +269,5 @@ def psolve(grid, medium, theta_max: float, beta: float, xs=(), cfl: float = 0.5)
     nsub = psubsteps(grid, rate, cfl)
     U0 = pinit(grid, pvel, theta_max, beta)
     Uall = pmarch(grid, pvel, theta_max, U0, nsub)
-    T = ppick(grid, Uall, xs) if len(np.atleast_1d(xs)) else None
+    T = ppick(grid, Uall, xs, theta_max) if len(np.atleast_1d(xs)) else None
     return {"tab": tab, "pvel": pvel, "rate": rate, "nsub": nsub, "U": Uall, "T": T}

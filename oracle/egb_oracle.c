@@ -816,11 +816,28 @@ static double pline(const double *u, long st, int n, int idx)
     return u[(long)idx * st];
 }
 
+/* value at index idx of a line whose in-range values are u and whose ghosts
+ * extend the line of the fixed data b (linear, from the two end values) */
+static double pline_b(const double *u, const double *b, long st, int n, int idx)
+{
+    if (idx < 0) return (1 - idx) * b[0] + idx * b[st];
+    if (idx > n - 1) {
+        int e = idx - (n - 1);
+        return (e + 1) * b[(long)(n - 1) * st] - e * b[(long)(n - 2) * st];
+    }
+    return u[(long)idx * st];
+}
+
 /* L = -(u D_x U + w D_theta U) + S at fractional depth s of the level
  * interval (velocity table (1 - s) pv0 + s pv1); WENO5 upwind on both axes,
- * D- where the coefficient is >= 0. */
+ * D- where the coefficient is >= 0.  Ghosts beyond the x ends and the
+ * aperture ends hold the surface data Ub extended linearly, fixed in depth:
+ * a ray entering through a side or an aperture edge carries that data (its
+ * take-off angle lies outside the aperture at the aperture edges), the
+ * reading that keeps the march bounded at inflow edges where extending the
+ * marched state grows without bound. */
 static void prhs(int nx, int nth, double dx, double dth, const double *pv0, const double *pv1, double s,
-                 const double *U, double *L)
+                 const double *U, const double *Ub, double *L)
 {
     long plane = (long)nth * nx;
 #pragma omp parallel for schedule(static)
@@ -834,9 +851,10 @@ static void prhs(int nx, int nth, double dx, double dth, const double *pv0, cons
             for (int f = 0; f < NPAR; ++f) {
                 const double *u = U + f * plane;
                 double w7[7];
-                for (int m = -3; m <= 3; ++m) w7[m + 3] = pline(u + (long)k * nx, 1, nx, i + m);
+                for (int m = -3; m <= 3; ++m)
+                    w7[m + 3] = pline_b(u + (long)k * nx, Ub + f * plane + (long)k * nx, 1, nx, i + m);
                 double Dx = oc_weno(w7, cx >= 0.0);
-                for (int m = -3; m <= 3; ++m) w7[m + 3] = pline(u + i, nx, nth, k + m);
+                for (int m = -3; m <= 3; ++m) w7[m + 3] = pline_b(u + i, Ub + f * plane + i, nx, nth, k + m);
                 double Dt = oc_weno(w7, ct >= 0.0);
                 Lf[f] = -(cx * Dx + ct * Dt);
             }
@@ -849,11 +867,12 @@ static void prhs(int nx, int nth, double dx, double dth, const double *pv0, cons
         }
 }
 
-/* March from level 0 (Uall[0] holds the data) to level nz - 1: each level
+/* March from level 0 (Uall[0] holds the start) to level nz - 1: each level
  * interval dz is nsub SSP-RK3 steps of dz / nsub, stage depths s, s + h,
- * s + h / 2 (h = 1 / nsub).  Every level is kept: Uall[n][7][k][i]. */
+ * s + h / 2 (h = 1 / nsub); Ub: the surface data the ghosts extend.  Every
+ * level is kept: Uall[n][7][k][i]. */
 int oc_pmarch(int nx, int nz, int nth, double dx, double dz, double theta_max, const double *pvel, int nsub,
-              double *Uall)
+              const double *Ub, double *Uall)
 {
     double dth = 2.0 * theta_max / nth, h = 1.0 / nsub, dl = dz * h;
     long plane = (long)nth * nx, lev = NPAR * plane;
@@ -865,11 +884,11 @@ int oc_pmarch(int nx, int nz, int nth, double dx, double dz, double theta_max, c
         const double *pv0 = pvel + (long)n * 7 * plane, *pv1 = pv0 + 7 * plane;
         for (int j = 0; j < nsub; ++j) {
             double s = j * h;
-            prhs(nx, nth, dx, dth, pv0, pv1, s, U, L);
+            prhs(nx, nth, dx, dth, pv0, pv1, s, U, Ub, L);
             for (long q = 0; q < lev; ++q) U1[q] = U[q] + dl * L[q];
-            prhs(nx, nth, dx, dth, pv0, pv1, s + h, U1, L);
+            prhs(nx, nth, dx, dth, pv0, pv1, s + h, U1, Ub, L);
             for (long q = 0; q < lev; ++q) U2[q] = 0.75 * U[q] + 0.25 * (U1[q] + dl * L[q]);
-            prhs(nx, nth, dx, dth, pv0, pv1, s + 0.5 * h, U2, L);
+            prhs(nx, nth, dx, dth, pv0, pv1, s + 0.5 * h, U2, Ub, L);
             for (long q = 0; q < lev; ++q) U[q] = U[q] / 3.0 + 2.0 / 3.0 * (U2[q] + dl * L[q]);
         }
         memcpy(Uall + (long)(n + 1) * lev, U, sizeof(double) * lev);
@@ -898,7 +917,9 @@ int oc_pmarch(int nx, int nz, int nth, double dx, double dz, double theta_max, c
  * frozen at the source, level 0) turns one normalisation into the other,
  * and s^-1 is the weight the phase-space sum's take-off-angle measure
  * carries (its Im(C, B) = beta s (dn, dtheta_perp) per unit angle).
- * A cell within the smoothed delta but off Gamma carries the ray from X, not
+ * Only cells whose transported take-off angle lies inside the aperture are
+ * beams: the others hold data the aperture edges extrapolated, not a ray
+ * from the source.  A cell within the smoothed delta but off Gamma carries the ray from X, not
  * from x_s: its traveltime is moved to the source to first order by the
  * take-off slowness p_s = sin(vartheta) / v_s (the point-source data of the
  * phase-space march carries this term in psi itself).  lin != 0: eq. 28's
@@ -938,6 +959,8 @@ int oc_pbeam_sum(int nx, int nz, int nth, double x0, double z0, double dx, doubl
                 double gX = sqrt(Xx * Xx + (Xt / lam) * (Xt / lam));
                 double d = (X[c] - xs) / gX;
                 if (!(fabs(d) < h)) continue;
+                double vt0 = T[c];
+                if (!(fabs(vt0) < theta_max)) continue; /* not a ray that left the source inside the aperture */
                 double meas = delta_h(d, h) * fabs(Xx * Tt - Xt * Tx) / gX * dx * dth;
                 double th = -theta_max + (k + 0.5) * dth, sn = sin(th), cs = cos(th);
                 double vj[10], V[3], A[4];
@@ -956,7 +979,6 @@ int oc_pbeam_sum(int nx, int nz, int nth, double x0, double z0, double dx, doubl
                 double complex Mn = (gp_pth * B + gp_dxp_gp * C) / C;
                 /* source normalisation at the take-off angle */
                 double vs, gps[2], ps[2], A12s, ss;
-                double vt0 = T[c];
                 source_data(ms, vt0, &vs, gps, ps, &A12s, &ss);
                 double u1 = cos(vt0) - sin(vt0) * gps[1] / gps[0];
                 beamrec r;
@@ -1003,9 +1025,11 @@ int oc_pbeam_sum(int nx, int nz, int nth, double x0, double z0, double dx, doubl
 
 /* First arrival at every (x_i, z_n) from a source at x = xs on the first
  * depth row: roots in theta of X(z_n, x_i, .) - xs between adjacent theta
- * nodes (eq. 35's Gamma = {X = x_s}; linear interpolation of X and tau), the
- * smallest tau > 0 among them; NaN where there is none.  T[s][n][i]. */
-int oc_ppick(int nx, int nz, int nth, const double *Uall, const double *xs, int nsrc, double *T)
+ * nodes (eq. 35's Gamma = {X = x_s}; linear interpolation of X and tau)
+ * whose two nodes carry take-off angles inside the aperture (rays from the
+ * source, not data entering at an aperture edge), the smallest tau > 0
+ * among them; NaN where there is none.  T[s][n][i]. */
+int oc_ppick(int nx, int nz, int nth, double theta_max, const double *Uall, const double *xs, int nsrc, double *T)
 {
     long plane = (long)nth * nx, lev = NPAR * plane;
 #pragma omp parallel for schedule(static)
@@ -1014,10 +1038,12 @@ int oc_ppick(int nx, int nz, int nth, const double *Uall, const double *xs, int 
             for (int i = 0; i < nx; ++i) {
                 const double *X = Uall + (long)n * lev + P_X * plane + i;
                 const double *tau = Uall + (long)n * lev + P_TAU * plane + i;
+                const double *vt = Uall + (long)n * lev + P_VT * plane + i;
                 double best = NAN;
                 for (int k = 0; k + 1 < nth; ++k) {
                     double f0 = X[(long)k * nx] - xs[s], f1 = X[(long)(k + 1) * nx] - xs[s];
                     if (!(f0 == 0.0 || f0 * f1 < 0.0)) continue;
+                    if (!(fabs(vt[(long)k * nx]) < theta_max && fabs(vt[(long)(k + 1) * nx]) < theta_max)) continue;
                     double t = f0 / (f0 - f1);
                     double v = tau[(long)k * nx] + t * (tau[(long)(k + 1) * nx] - tau[(long)k * nx]);
                     if (v > 0.0 && (isnan(best) || v < best)) best = v;

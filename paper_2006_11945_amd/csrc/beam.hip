@@ -279,7 +279,8 @@ __device__ __forceinline__ void qp_polarization(const double (&m)[NF], double th
 }
 
 // Beam records of the depth march for a surface source at xs: thread
-// (x, theta, level n >= 1).  A cell near Gamma = {X = xs} (signed distance d
+// (x, theta, level n >= 1).  A cell whose transported take-off angle lies
+// inside the aperture and that is near Gamma = {X = xs} (signed distance d
 // = (X - xs) / |grad X|, theta scaled by lambda = dx / dtheta, |d| < 2 dx)
 // becomes a row-n record with the take-off-angle measure
 // delta_h(d) |det d(X, vartheta)/d(x, theta)| / |grad X| dx dtheta, the row
@@ -306,6 +307,8 @@ __global__ __launch_bounds__(256) void k_pbeam_compact(PBeamArgs a) {
     const double Xc = (double)X[c];
     const double d = (Xc - a.xs) / gX;
     if (!(fabs(d) < h)) return;
+    const double vt0 = (double)T[c];  // take-off angle; outside the aperture: edge data, not a ray
+    if (!(fabs(vt0) < a.theta_max)) return;
     const double meas = delta_h(d, h) * fabs(Xx * Tt - Xt * Tx) / gX * a.dx * a.dth;
     // local phase-velocity jet and ray direction at (x, z_n, theta)
     MediumPoint M;
@@ -337,7 +340,6 @@ __global__ __launch_bounds__(256) void k_pbeam_compact(PBeamArgs a) {
     double sqim = sqrt(0.5 * fmax(mod - vCre, 0.0));
     sqim = vCim < 0.0 ? -sqim : sqim;
     // source normalisation at the take-off angle (medium frozen at the source)
-    const double vt0 = (double)T[c];
     MediumPoint Ms;
     {
         // bilinear in the table at (xs, depth of level 0)

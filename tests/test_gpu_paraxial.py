@@ -9,10 +9,8 @@ Tolerances (fixed from the arithmetic before measuring):
   * FP32 (tau kept in double): coefficients and surface data 2e-6 of the
     plane maximum (computed in double, rounded once); marched levels: tau
     1e-5 of the level's maximum, the other planes 1e-4 of the plane maximum
-    six or more theta nodes inside the aperture and 1e-3 next to its edges,
-    where the extrapolated ghosts amplify rounding (the oracle marched with
-    one FP32 ulp of noise per stage reaches 1-2e-4 there and stays below
-    4e-5 six nodes inside; test_oracle_paraxial pins that sensitivity);
+    (the oracle marched with one FP32 ulp of noise per stage stays below
+    3e-5; test_oracle_paraxial pins that sensitivity);
   * picks on identical (oracle) levels: 1e-12 relative, the same NaN cells.
 """
 from dataclasses import replace
@@ -101,8 +99,7 @@ def test_paraxial_march_parity(dtype, tilt):
     P.march(o["nsub"])
     torch.cuda.synchronize()
     U = o["U"]
-    inner = slice(6, g.nth - 6)
-    worst, worst_in = {}, {}
+    worst = {}
     for n in range(g.nz):
         G = gpu_levels(P, n)
         for name, q in OR.items():
@@ -110,17 +107,14 @@ def test_paraxial_march_parity(dtype, tilt):
             if name == "tau":
                 sc = max(np.abs(U[n, q]).max(), 1e-30)
             worst[name] = max(worst.get(name, 0.0), rel_err(G[name], U[n, q], sc))
-            worst_in[name] = max(worst_in.get(name, 0.0), rel_err(G[name][inner], U[n, q][inner], sc))
-    log("  all: " + " ".join(f"{k}: {v:.2e}" for k, v in worst.items()))
-    log("  inner: " + " ".join(f"{k}: {v:.2e}" for k, v in worst_in.items()))
+    log("  " + " ".join(f"{k}: {v:.2e}" for k, v in worst.items()))
     for name in worst:
         if dtype == "f64":
             assert worst[name] < 1e-10, name
         elif name == "tau":
             assert worst[name] < 1e-5, name
         else:
-            assert worst_in[name] < 1e-4, name
-            assert worst[name] < 1e-3, name
+            assert worst[name] < 1e-4, name
 
 
 def test_paraxial_pick_parity_and_edge_cases():
@@ -191,7 +185,6 @@ def test_paraxial_full_size_first_levels():
     tab = oracle.medium_table(gc, mc)
     pv, _ = oracle.pvelocity(gc, tab, TMAX)
     U = oracle.pmarch(gc, pv, TMAX, oracle.pinit(gc, pv, TMAX, beta), nsub)
-    inner = slice(6, g.nth - 6)
     for n in range(6):
         G = gpu_levels(P, n)
         for name, q in OR.items():
@@ -199,11 +192,15 @@ def test_paraxial_full_size_first_levels():
                 assert rel_err(G[name], U[n, q], max(np.abs(U[n, q]).max(), 1e-30)) < 1e-5, n
                 continue
             sc = max(np.abs(U[:6, q]).max(), 1e-30)
-            assert rel_err(G[name][inner], U[n, q][inner], sc) < 1e-4, (n, name)
-            assert rel_err(G[name], U[n, q], sc) < 1e-3, (n, name)
+            assert rel_err(G[name], U[n, q], sc) < 1e-4, (n, name)
+    # every level stays in its physical range (bounded march)
+    dth = 2 * TMAX / g.nth
     for n in range(0, g.nz, 15):
         G = gpu_levels(P, n)
         assert all(np.isfinite(v).all() for v in G.values()), n
+        assert G["X"].min() > -0.05 * L and G["X"].max() < 1.05 * L, n
+        assert np.abs(G["vartheta"]).max() < TMAX + 4 * dth, n
+        assert G["tau"].min() >= 0.0 and G["tau"].max() < 2 * L / 1000.0, n
 
 
 @pytest.mark.parametrize("dtype,lin,comp", [("f64", 0, -1), ("f32", 0, -1), ("f32", 1, -1), ("f64", 0, 1),

@@ -14,21 +14,48 @@ def test_homogeneous_isotropic_is_exact():
     # straight rays: X = x - tan(theta) dz, tau = dz / (v cos theta); the
     # depth DRT with A12 / V_z = 1 / cos(theta): C = 1/cos + i beta dz / cos^2,
     # B = i beta / cos, all exact for the scheme (linear in x, constant w = 0)
+    # where the surface data decide the solution
     n, L, v = 32, 640.0, 2000.0
     beta = 1.0 / (2 * L)
-    g = W.Grid(nx=n, nz=n, nth=40, dx=L / n, dz=L / n)
+    g = W.Grid(nx=3 * n, nz=n, nth=40, dx=L / n, dz=L / n)
     r = oracle.psolve(g, W.homogeneous(g, v), TMAX, beta)
     U, th = r["U"], oracle.ptheta(g, TMAX)
     dz = (g.zc() - g.zc()[0])[:, None, None]
     x = g.xc()[None, None, :]
     t = th[None, :, None]
-    assert np.abs(U[:, 0] - (x - np.tan(t) * dz)).max() < 1e-10 * L
+    Xe = x - np.tan(t) * dz
+    # the surface data decide the cells whose ray leaves the surface inside the
+    # domain; rays entering through a side carry the fixed side data instead,
+    # and the WENO weights let that edge reach a few cells further (1e-5 of a
+    # cell 12 cells away)
+    m = (Xe > g.xc()[0] + 12 * g.dx) & (Xe < g.xc()[-1] - 12 * g.dx)
+    m = np.broadcast_to(m, U[:, 0].shape)
+    assert m.mean() > 0.4
+    assert np.abs(U[:, 0] - Xe)[m].max() < 1e-5 * g.dx
     assert np.abs(U[:, 1] - t).max() < 1e-13
-    assert np.abs(U[:, 2] - dz / (v * np.cos(t))).max() < 1e-14
+    assert np.abs(U[:, 2] - dz / (v * np.cos(t)))[m].max() < 1e-5 * g.dx / v
     assert np.abs(U[:, 3] - 1 / np.cos(t)).max() < 1e-12
-    assert np.abs(U[:, 4] - beta * dz / np.cos(t) ** 2).max() < 1e-12
+    assert np.abs(U[:, 4] - beta * dz / np.cos(t) ** 2)[m].max() < 1e-5 * beta * g.dx
     assert np.abs(U[:, 5]).max() < 1e-12
     assert np.abs(U[:, 6] - beta / np.cos(t)).max() < 1e-14
+
+
+def test_long_march_stays_bounded_in_heterogeneous_medium():
+    # 96 levels of the heterogeneous VTI workload (25 substeps each): with the
+    # surface data held fixed in the side and aperture ghosts every field
+    # stays in its physical range (extrapolating the marched state there let
+    # the inflow corners grow without bound after about 35 levels)
+    from dataclasses import replace
+    p = W.vti_256(n=96, nsteps=1)
+    g = replace(p.grid, nth=96)
+    L = g.nx * g.dx
+    r = oracle.psolve(g, p.medium, TMAX, 1 / (2 * L))
+    U = r["U"]
+    dth = 2 * TMAX / g.nth
+    assert np.isfinite(U).all()
+    assert U[:, 0].min() > -0.05 * L and U[:, 0].max() < 1.05 * L
+    assert np.abs(U[:, 1]).max() < TMAX + 4 * dth
+    assert U[:, 2].min() >= 0.0 and U[:, 2].max() < 2 * L / 1000.0
 
 
 @pytest.mark.parametrize("eps,tilt", [(0.0, 0.0), (0.2, 0.0), (0.2, 0.3)])
@@ -63,12 +90,11 @@ def test_gradient_medium_second_order():
     assert errs[1] < 2e-4
 
 
-def test_rounding_sensitivity_at_the_aperture_edges():
-    """The extrapolated theta ghosts at the aperture edges amplify small
-    perturbations: one FP32 ulp of relative noise per RK stage (applied once
-    per level, scaled by sqrt(3 nsub)) grows to about 1e-4 of a plane's
-    maximum next to the edges but stays below 1e-4 six nodes inside.  This
-    fixes the FP32 tolerances of the GPU parity test of the depth march."""
+def test_rounding_sensitivity_of_the_depth_march():
+    """One FP32 ulp of relative noise per RK stage (applied once per level,
+    scaled by sqrt(3 nsub)) stays at the rounding level of every plane, next
+    to the edges too (the fixed ghost data do not feed it back): this fixes
+    the FP32 tolerances of the GPU parity test of the depth march."""
     from dataclasses import replace
     g = W.Grid(nx=42, nz=30, nth=36, dx=15.625, dz=15.625)
     L = 42 * 15.625
@@ -82,17 +108,13 @@ def test_rounding_sensitivity_at_the_aperture_edges():
     g2 = replace(g, nz=2)
     U, Ub = U0.copy(), [U0.copy()]
     for n in range(g.nz - 1):
-        U = oracle.pmarch(g2, np.ascontiguousarray(pv[n:n + 2]), TMAX, U, nsub)[1]
+        U = oracle.pmarch(g2, np.ascontiguousarray(pv[n:n + 2]), TMAX, U, nsub, Ub=U0)[1]
         for q in (0, 1, 3, 4, 5, 6):
             U[q] = U[q] * (1 + rng.uniform(-6e-8, 6e-8, U[q].shape) * np.sqrt(3 * nsub))
         Ub.append(U.copy())
     Ub = np.array(Ub)
-    inner = slice(6, g.nth - 6)
     e_all = max(np.abs(Ub[:, q] - Ua[:, q]).max() / np.abs(Ua[:, q]).max() for q in (0, 1, 3, 4, 5, 6))
-    e_in = max(np.abs(Ub[:, q][:, inner] - Ua[:, q][:, inner]).max() / np.abs(Ua[:, q]).max()
-               for q in (0, 1, 3, 4, 5, 6))
-    assert 3e-5 < e_all < 1e-3
-    assert e_in < 1e-4
+    assert e_all < 3e-5
 
 
 @pytest.mark.parametrize("eps,tilt", [(0.0, 0.0), (0.2, 0.0), (0.2, 0.3)])
