@@ -294,9 +294,11 @@ egb_status egb_paraxial_init(const egb_grid *g, const void *pvel, double theta_m
 /* March levels 0 -> nz-1: each depth interval is nsub SSP-RK3 steps of
  * dz/nsub of U_z + u U_x + w U_theta = S (S_tau = 1/V_z, S_(C,B) = A/V_z (C,
  * B), the rest zero) with WENO5 upwind x and theta derivatives, the
- * coefficients linear in z between the two levels; x and theta ghosts
- * continue the line of the two cells next to them.  In: level 0 of levels.
- * Out: levels 1 .. nz-1.  work: egb_workspace_size(g, EGB_OP_PARAXIAL).  The
+ * coefficients linear in z between the two levels; x and theta ghosts hold
+ * the surface data of level 0 extended linearly, fixed in depth (rays
+ * entering through a side or an aperture edge carry it: their take-off
+ * angle lies outside the aperture at the aperture edges).  In: level 0 of
+ * levels (kept).  Out: levels 1 .. nz-1.  work: egb_workspace_size(g, EGB_OP_PARAXIAL).  The
  * 3 nsub (nz - 1) stage launches run as one hipGraph; synchronises `stream`. */
 egb_status egb_paraxial_march(const egb_grid *g, const void *pvel, double theta_max, int32_t nsub, void *levels,
                               void *work, size_t work_bytes, hipStream_t stream);
@@ -327,11 +329,12 @@ egb_status egb_paraxial_beam_sum(const egb_grid *g, const void *coeff2d, const v
                                  void *out, void *work, size_t work_bytes, hipStream_t stream);
 
 /* First arrivals of nsrc surface sources at every (x_i, z_n): roots in theta
- * of X - x_s between adjacent nodes (linear interpolation of X and tau), the
- * smallest tau > 0; NaN where there is none.  In: xs (device float64 [nsrc]).
+ * of X - x_s between adjacent nodes whose take-off angles vartheta lie inside
+ * (-theta_max, theta_max) (linear interpolation of X and tau), the smallest
+ * tau > 0; NaN where there is none.  In: xs (device float64 [nsrc]).
  * Out: T (device float64 [nsrc][nz][nx]). */
-egb_status egb_paraxial_pick(const egb_grid *g, const void *levels, const double *xs, int32_t nsrc, double *T,
-                             hipStream_t stream);
+egb_status egb_paraxial_pick(const egb_grid *g, const void *levels, double theta_max, const double *xs, int32_t nsrc,
+                             double *T, hipStream_t stream);
 
 /* Human-readable text for a status code (static storage). */
 const char *egb_status_string(int32_t status);

@@ -548,7 +548,10 @@ int oc_march(int nx, int nz, int nth, double x0, double z0, double dx, double dz
  * with M the complex traveltime Hessian restricted to the line (M = B C^-1 in
  * the ray-normal frame, eq. 25), w = cos^4/(cos^4 + sin^4) of the ray angle
  * for rows and 1 - w for columns, and the total scaled by W = i / (4 pi).
- * Beams with 1/2 omega Im(M) dist^2 > 16 are skipped.  lin != 0 takes the
+ * Beams with 1/2 omega Im(M) dist^2 > 16 are skipped, and cells whose line
+ * Hessian has Im(M) <= 0 are no beams: a Gaussian beam decays away from its
+ * centre (the exact transport keeps Im(B conj(C)) > 0; a discrete field can
+ * lose it, and such a cell would grow without bound).  lin != 0 takes the
  * linear coefficient p1 (p3) from eq. 28 (oc_lin28) instead of eq. 7.
  * Output layout out[w][ix][iz][re/im].                                     */
 typedef struct { double pos, psi, p; double complex M, amp; } beamrec;
@@ -629,7 +632,9 @@ int oc_beam_sum(int nx, int nz, int nth, double x0, double z0, double dx, double
                     r.p = lin ? oc_lin28(sn, cs, Vx / Vz, v) : sn / v;
                     r.M = Mn * gz * gz + 2.0 * gpq * gx * gz + gq * gx * gx;
                     r.amp = wrow * amp0 * dth_c;
-                    if (nrow[iz] < cap) rows[(long)iz * cap + nrow[iz]++] = r; else overflow = 1;
+                    if (cimag(r.M) > 0.0) {
+                        if (nrow[iz] < cap) rows[(long)iz * cap + nrow[iz]++] = r; else overflow = 1;
+                    }
                 }
                 if (acol && fabs(gx) > 1e-4) {
                     double ds = -dn * gz / gx, pz = -dn / gx, pt = dtp + ds * Vt / nv;
@@ -640,7 +645,9 @@ int oc_beam_sum(int nx, int nz, int nth, double x0, double z0, double dx, double
                     r.p = lin ? oc_lin28(cs, sn, Vz / Vx, v) : cs / v;
                     r.M = Mn * gx * gx - 2.0 * gpq * gx * gz + gq * gz * gz;
                     r.amp = (1.0 - wrow) * amp0 * dth_c;
-                    if (ncol[ix] < cap) cols[(long)ix * cap + ncol[ix]++] = r; else overflow = 1;
+                    if (cimag(r.M) > 0.0) {
+                        if (ncol[ix] < cap) cols[(long)ix * cap + ncol[ix]++] = r; else overflow = 1;
+                    }
                 }
             }
     }
@@ -918,9 +925,11 @@ int oc_pmarch(int nx, int nz, int nth, double dx, double dz, double theta_max, c
  * and s^-1 is the weight the phase-space sum's take-off-angle measure
  * carries (its Im(C, B) = beta s (dn, dtheta_perp) per unit angle).
  * Only cells whose transported take-off angle lies inside the aperture are
- * beams: the others hold data the aperture edges extrapolated, not a ray
- * from the source.  A cell within the smoothed delta but off Gamma carries the ray from X, not
- * from x_s: its traveltime is moved to the source to first order by the
+ * beams (the others hold data that entered at an aperture edge, not a ray
+ * from the source), and, as in the phase-space sum, only those with
+ * Im(M_row) > 0.  A cell within the smoothed delta but off Gamma carries the
+ * ray from X, not from x_s: its traveltime is moved to the source to first
+ * order by the
  * take-off slowness p_s = sin(vartheta) / v_s (the point-source data of the
  * phase-space march carries this term in psi itself).  lin != 0: eq. 28's
  * linear coefficient.  comp >= 0: component (i, k) = (comp / 2, comp % 2)
@@ -994,6 +1003,7 @@ int oc_pbeam_sum(int nx, int nz, int nth, double x0, double z0, double dx, doubl
                     oc_qp_polarization(ms, vt0, gs);
                     r.amp *= gr[comp / 2] * gs[comp % 2];
                 }
+                if (!(cimag(r.M) > 0.0)) continue;
                 if (nrow[n] < cap) rows[(long)n * cap + nrow[n]++] = r; else overflow = 1;
             }
     }

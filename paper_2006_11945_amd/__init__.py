@@ -98,7 +98,7 @@ def _load():
     L.egb_paraxial_velocity.argtypes = [G, vp, d, vp, dp, vp, sz, vp]
     L.egb_paraxial_init.argtypes = [G, vp, d, d, vp, vp]
     L.egb_paraxial_march.argtypes = [G, vp, d, i32, vp, vp, sz, vp]
-    L.egb_paraxial_pick.argtypes = [G, vp, vp, i32, vp, vp]
+    L.egb_paraxial_pick.argtypes = [G, vp, d, vp, i32, vp, vp]
     L.egb_paraxial_beam_sum.argtypes = [G, vp, vp, d, d, i32, i32, dp, i32, vp, vp, sz, vp]
     for name in ("egb_medium_table", "egb_paraxial_velocity", "egb_paraxial_init", "egb_paraxial_march",
                  "egb_paraxial_pick", "egb_paraxial_beam_sum"):
@@ -262,10 +262,10 @@ def egb_paraxial_march(eg, pvel, theta_max: float, nsub: int, levels, work, stre
     _check("egb_paraxial_march", rc)
 
 
-def egb_paraxial_pick(eg, levels, xs, T, stream=None):
+def egb_paraxial_pick(eg, levels, theta_max: float, xs, T, stream=None):
     n = 0 if xs is None else xs.numel()
-    _check("egb_paraxial_pick", _lib.egb_paraxial_pick(ctypes.byref(eg), _ptr(levels), _ptr(xs), n, _ptr(T),
-                                                       _stream(stream)))
+    _check("egb_paraxial_pick", _lib.egb_paraxial_pick(ctypes.byref(eg), _ptr(levels), float(theta_max), _ptr(xs), n,
+                                                       _ptr(T), _stream(stream)))
 
 
 def egb_paraxial_beam_sum(eg, coeff2d, levels, theta_max: float, xs: float, lin: int, comp: int, omegas, out, work,
@@ -456,7 +456,7 @@ class Paraxial:
         x = torch.as_tensor(np.ascontiguousarray(np.atleast_1d(xs), dtype=np.float64), device=self.device)
         if out is None:
             out = torch.empty((x.numel(), self.eg.nz, self.eg.nx), dtype=torch.float64, device=self.device)
-        egb_paraxial_pick(self.eg, self.levels, x, out, stream)
+        egb_paraxial_pick(self.eg, self.levels, self.theta_max, x, out, stream)
         return out
 
     def beam(self, xs: float, omegas, lin: int = EGB_LIN_EXACT, out: Optional[torch.Tensor] = None,

@@ -10,6 +10,9 @@
 //   coefficient for the lin=paper28 variant), M (traveltime Hessian along
 //   the line, complex) and amp = w sqrt(v / C) dtheta (complex),
 // w = cos^4 / (cos^4 + sin^4) of the ray angle for rows and 1 - w for columns.
+// Cells whose line Hessian has Im(M) <= 0 give no record: a Gaussian beam
+// decays away from its centre (the exact transport keeps Im(B conj(C)) > 0,
+// a discrete field can lose it).
 // Pass 2 (k_beam_line): for every output cell and frequency,
 //   G += amp exp(i omega T),  T = psi + p d + M d^2 / 2,
 // skipping beams with omega Im(M) d^2 / 2 > 16, and G is scaled by i/(4 pi).
@@ -149,8 +152,10 @@ __global__ __launch_bounds__(256) void k_beam_compact(BeamArgs a) {
         r.are = w * sqre;
         r.aim = w * sqim;
         r.pad = 0.0;
-        const int slot = atomicAdd(&a.counts[iz], 1);
-        if (slot < a.cap) rows[(long long)iz * a.cap + slot] = r;
+        if (r.Mim > 0.0) {  // a Gaussian beam decays away from its centre
+            const int slot = atomicAdd(&a.counts[iz], 1);
+            if (slot < a.cap) rows[(long long)iz * a.cap + slot] = r;
+        }
     }
     if (acol && fabs(hxr) > 1e-4) {
         const double ds = -dn * hzr / hxr, pz = -dn / hxr, pt = dtp + ds * Vt / sp;
@@ -165,8 +170,10 @@ __global__ __launch_bounds__(256) void k_beam_compact(BeamArgs a) {
         r.are = w * sqre;
         r.aim = w * sqim;
         r.pad = 0.0;
-        const int slot = atomicAdd(&a.counts[g.nz + ix], 1);
-        if (slot < a.cap) cols[(long long)ix * a.cap + slot] = r;
+        if (r.Mim > 0.0) {
+            const int slot = atomicAdd(&a.counts[g.nz + ix], 1);
+            if (slot < a.cap) cols[(long long)ix * a.cap + slot] = r;
+        }
     }
 }
 
@@ -381,6 +388,7 @@ __global__ __launch_bounds__(256) void k_pbeam_compact(PBeamArgs a) {
     r.are = w * sqre;
     r.aim = w * sqim;
     r.pad = 0.0;
+    if (!(r.Mim > 0.0)) return;  // not a Gaussian beam (grows away from its centre)
     const int slot = atomicAdd(&a.counts[n], 1);
     if (slot < a.cap) reinterpret_cast<BeamRec*>(a.rows)[(long long)n * a.cap + slot] = r;
 }

@@ -319,6 +319,7 @@ egb_status egb_paraxial_march(const egb_grid* g, const void* pvel, double theta_
     a.P = P;
     a.dx = g->dx;
     a.dth = 2.0 * theta_max / g->nth;
+    a.Ub = levels;  // level 0 keeps the surface data
     const double h = 1.0 / nsub;
     a.dl = g->dz * h;
     // the whole march (3 nsub (nz - 1) stage launches) as one graph replayed on `stream`
@@ -422,11 +423,12 @@ egb_status egb_paraxial_beam_sum(const egb_grid* g, const void* coeff2d, const v
     return EGB_OK;
 }
 
-egb_status egb_paraxial_pick(const egb_grid* g, const void* levels, const double* xs, int32_t nsrc, double* T,
-                             hipStream_t stream) {
-    if (!grid_ok(g) || !levels || nsrc < 0 || (nsrc > 0 && (!xs || !T))) return EGB_EINVAL;
+egb_status egb_paraxial_pick(const egb_grid* g, const void* levels, double theta_max, const double* xs, int32_t nsrc,
+                             double* T, hipStream_t stream) {
+    if (!grid_ok(g) || !levels || !theta_max_ok(theta_max) || nsrc < 0 || (nsrc > 0 && (!xs || !T)))
+        return EGB_EINVAL;
     if (!aligned16(levels) || (xs && ((uintptr_t)xs & 7u)) || (T && ((uintptr_t)T & 7u))) return EGB_EINVAL;
-    return hip_status(launch_ppick(g->nx, g->nz, g->nth, (long long)paraxial_stride(*g), g->dtype, levels,
+    return hip_status(launch_ppick(g->nx, g->nz, g->nth, theta_max, (long long)paraxial_stride(*g), g->dtype, levels,
                                    paraxial_level_bytes(*g), xs, nsrc, T, stream));
 }
 

@@ -121,6 +121,7 @@ struct PStageArgs {
     double dx, dth, dl, s;     // dl: the substep in z; s: stage depth as a fraction of the level interval
     const void* pv0;           // coefficients at the interval's two levels
     const void* pv1;
+    const void* Ub;            // surface data (level 0): the ghost values
     const void* U0;            // the substep's starting state
     const void* Uin;
     void* Uout;
@@ -130,8 +131,8 @@ hipError_t launch_pvelocity(const GridArgs& a, int dtype, double theta_max, cons
 hipError_t launch_pinit(int nx, int nth, long long P, double x0, double dx, double theta_max, double beta, int dtype,
                         const void* pvel, void* level0, hipStream_t s);
 hipError_t launch_pstage(const PStageArgs& a, int dtype, int stage, hipStream_t s);
-hipError_t launch_ppick(int nx, int nz, int nth, long long P, int dtype, const void* levels, size_t level_bytes,
-                        const double* xs, int nsrc, double* T, hipStream_t s);
+hipError_t launch_ppick(int nx, int nz, int nth, double theta_max, long long P, int dtype, const void* levels,
+                        size_t level_bytes, const double* xs, int nsrc, double* T, hipStream_t s);
 
 // Beam superposition.
 struct BeamArgs {

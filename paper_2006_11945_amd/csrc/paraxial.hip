@@ -7,9 +7,11 @@
 // S_tau = 1 / V_z, S_(C,B) = (A / V_z)(C, B), the other sources zero.  Each
 // depth interval dz is nsub SSP-RK3 steps of dz / nsub in z, the
 // coefficients linear in z between the two levels (stage depths s, s + h,
-// s + h / 2 of the interval, h = 1 / nsub); x and theta ghosts continue the
-// line of the two cells next to them.  Every level is kept; first arrivals
-// for a surface source at x_s follow from the level set X = x_s (eq. 35).
+// s + h / 2 of the interval, h = 1 / nsub); x and theta ghosts hold the
+// surface data extended linearly, fixed in depth (a ray entering through a
+// side or an aperture edge carries it).  Every level is kept; first arrivals
+// for a surface source at x_s follow from the level set X = x_s (eq. 35),
+// over the nodes whose take-off angle lies inside the aperture.
 //
 // Level layout: planes X, vartheta, Re C, Im C, Re B, Im B in R, then tau in
 // double, each [theta][x] (x fastest) padded to a multiple of 64 elements.
@@ -52,10 +54,11 @@ struct PSmem {
     W w[(NPR + LdsWord<R>::PSI_WORDS) * PLANE];
 };
 
-// LDS cell i of a tile (x0, k0): the two slice cells whose combination
-// w0 u[i0] + w1 u[i1] gives its value.  Inside the slice (w0, w1) = (1, 0);
-// beyond an x end or a theta end the line of the two cells next to it,
-// u_{-m} = (m+1) u_0 - m u_1; cells beyond both are never read (weights 0).
+// LDS cell i of a tile (x0, k0): inside the slice the marched value u[i0]
+// ((w0, w1) = (1, 0)); beyond an x end or a theta end (a ghost) the surface
+// data b extended linearly from the two cells next to that end,
+// w0 b[i0] + w1 b[i1] with (w0, w1) = (m + 1, -m); cells beyond both are
+// never read (weights 0).
 __device__ __forceinline__ void pline_src(int nx, int nth, int x, int k, int& i0, int& i1, int& w0, int& w1) {
     const bool xin = x >= 0 && x < nx, kin = k >= 0 && k < nth;
     if (xin && kin) {
@@ -114,6 +117,7 @@ __global__ __launch_bounds__(NT) void k_pstage(PStageArgs a) {
     const R a0 = p0[qa * a.P + c], a1 = p1[qa * a.P + c];
     const R b0 = p0[(qa + 1) * a.P + c], b1 = p1[(qa + 1) * a.P + c];
     const R* Ui = static_cast<const R*>(a.Uin);
+    const R* Ub = static_cast<const R*>(a.Ub);  // surface data (level 0): the ghosts
     R r0 = (R)0;
     double t0 = 0.0;
     if constexpr (STAGE != 0) {
@@ -126,7 +130,8 @@ __global__ __launch_bounds__(NT) void k_pstage(PStageArgs a) {
     auto fill = [&](auto tag) {
         using T = decltype(tag);
         const T* u = p == Q_TAU ? reinterpret_cast<const T*>(Ui + NPR * a.P) : reinterpret_cast<const T*>(Ui + p * a.P);
-        T v0[NLD], v1[NLD];
+        const T* ub = p == Q_TAU ? reinterpret_cast<const T*>(Ub + NPR * a.P) : reinterpret_cast<const T*>(Ub + p * a.P);
+        T v0[NLD], b0[NLD], b1[NLD];
         int wa[NLD], wb[NLD];
 #pragma unroll
         for (int r = 0; r < NLD; ++r) {
@@ -134,13 +139,15 @@ __global__ __launch_bounds__(NT) void k_pstage(PStageArgs a) {
             int i0, i1;
             pline_src(a.nx, a.nth, tx0 + i % PRX - 3, tk0 + i / PRX - 3, i0, i1, wa[r], wb[r]);
             v0[r] = u[i0];
-            v1[r] = edge ? u[i1] : (T)0;
+            b0[r] = edge ? ub[i0] : (T)0;
+            b1[r] = edge ? ub[i1] : (T)0;
         }
 #pragma unroll
         for (int r = 0; r < NLD; ++r) {
             const int i = pt + r * PTX * PTT;
             if (i < PCELLS) {
-                const T v = edge ? (T)wa[r] * v0[r] + (T)wb[r] * v1[r] : v0[r];
+                const bool ghost = wa[r] != 1 || wb[r] != 0;
+                const T v = edge && ghost ? (T)wa[r] * b0[r] + (T)wb[r] * b1[r] : v0[r];
                 if constexpr (sizeof(T) == sizeof(Wd)) {
                     sm.w[(p == Q_TAU ? NPR : p) * S::PLANE + i] = __builtin_bit_cast(Wd, v);
                 } else {  // tau of an FP32 slice: two 32-bit planes
@@ -218,11 +225,13 @@ __global__ __launch_bounds__(256) void k_pinit(int nx, int nth, long long P, dou
 }
 
 // First arrival at (x_i, level n) for surface source s: roots in theta of
-// X - x_s between adjacent nodes, tau interpolated linearly, the smallest
-// tau > 0 (NaN when there is none).  T[s][n][i].
+// X - x_s between adjacent nodes whose take-off angles lie inside the
+// aperture, tau interpolated linearly, the smallest tau > 0 (NaN when there
+// is none).  T[s][n][i].
 template <typename R>
-__global__ __launch_bounds__(256) void k_ppick(int nx, int nz, int nth, long long P, const char* levels,
-                                               size_t level_bytes, const double* xs, int nsrc, double* T) {
+__global__ __launch_bounds__(256) void k_ppick(int nx, int nz, int nth, double theta_max, long long P,
+                                               const char* levels, size_t level_bytes, const double* xs, int nsrc,
+                                               double* T) {
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long total = (long long)nsrc * nz * nx;
     if (id >= total) return;
@@ -230,18 +239,22 @@ __global__ __launch_bounds__(256) void k_ppick(int nx, int nz, int nth, long lon
     const R* X = reinterpret_cast<const R*>(levels + (size_t)n * level_bytes) + i;
     const double* tau = reinterpret_cast<const double*>(reinterpret_cast<const R*>(levels + (size_t)n * level_bytes) +
                                                         NPR * P) + i;
+    const R* VT = X + P;  // take-off angle
     const double x_s = xs[s];
     double best = __longlong_as_double(0x7ff8000000000000LL);
     double f0 = (double)X[0] - x_s, t0 = tau[0];
+    bool in0 = fabs((double)VT[0]) < theta_max;
     for (int k = 0; k + 1 < nth; ++k) {
         const double f1 = (double)X[(long long)(k + 1) * nx] - x_s, t1 = tau[(long long)(k + 1) * nx];
-        if (f0 == 0.0 || f0 * f1 < 0.0) {
+        const bool in1 = fabs((double)VT[(long long)(k + 1) * nx]) < theta_max;
+        if ((f0 == 0.0 || f0 * f1 < 0.0) && in0 && in1) {
             const double t = f0 / (f0 - f1);
             const double v = t0 + t * (t1 - t0);
             if (v > 0.0 && (isnan(best) || v < best)) best = v;
         }
         f0 = f1;
         t0 = t1;
+        in0 = in1;
     }
     T[id] = best;
 }
@@ -275,15 +288,15 @@ hipError_t launch_pinit(int nx, int nth, long long P, double x0, double dx, doub
     return hipGetLastError();
 }
 
-hipError_t launch_ppick(int nx, int nz, int nth, long long P, int dtype, const void* levels, size_t level_bytes,
-                        const double* xs, int nsrc, double* T, hipStream_t s) {
+hipError_t launch_ppick(int nx, int nz, int nth, double theta_max, long long P, int dtype, const void* levels,
+                        size_t level_bytes, const double* xs, int nsrc, double* T, hipStream_t s) {
     const long long total = (long long)nsrc * nz * nx;
     if (total == 0) return hipSuccess;
     const unsigned blocks = (unsigned)((total + 255) / 256);
     if (dtype == EGB_F64)
-        k_ppick<double><<<blocks, 256, 0, s>>>(nx, nz, nth, P, (const char*)levels, level_bytes, xs, nsrc, T);
+        k_ppick<double><<<blocks, 256, 0, s>>>(nx, nz, nth, theta_max, P, (const char*)levels, level_bytes, xs, nsrc, T);
     else
-        k_ppick<float><<<blocks, 256, 0, s>>>(nx, nz, nth, P, (const char*)levels, level_bytes, xs, nsrc, T);
+        k_ppick<float><<<blocks, 256, 0, s>>>(nx, nz, nth, theta_max, P, (const char*)levels, level_bytes, xs, nsrc, T);
     return hipGetLastError();
 }
 

@@ -128,7 +128,7 @@ def test_paraxial_pick_parity_and_edge_cases():
         U[:, q] = U[:, q].astype(np.float32).astype(np.float64)
     write_levels(P, U)
     T = P.pick(xs).cpu().numpy()
-    To = oracle.ppick(g, U, xs)
+    To = oracle.ppick(g, U, xs, TMAX)
     assert np.array_equal(np.isnan(T), np.isnan(To))
     assert np.isnan(T[-1]).all()
     ok = ~np.isnan(To)
@@ -201,6 +201,9 @@ def test_paraxial_full_size_first_levels():
         assert G["X"].min() > -0.05 * L and G["X"].max() < 1.05 * L, n
         assert np.abs(G["vartheta"]).max() < TMAX + 4 * dth, n
         assert G["tau"].min() >= 0.0 and G["tau"].max() < 2 * L / 1000.0, n
+    # the Green's function of the central source is finite at every depth
+    out = P.beam(0.5 * L, W.hz([5.0, 60.0]))
+    assert torch.isfinite(out).all()
 
 
 @pytest.mark.parametrize("dtype,lin,comp", [("f64", 0, -1), ("f32", 0, -1), ("f32", 1, -1), ("f64", 0, 1),

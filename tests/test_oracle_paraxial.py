@@ -56,6 +56,12 @@ def test_long_march_stays_bounded_in_heterogeneous_medium():
     assert U[:, 0].min() > -0.05 * L and U[:, 0].max() < 1.05 * L
     assert np.abs(U[:, 1]).max() < TMAX + 4 * dth
     assert U[:, 2].min() >= 0.0 and U[:, 2].max() < 2 * L / 1000.0
+    # and its beam sum is finite: cells that lost Im(B/C) > 0 are no beams
+    C = U[:, 3] + 1j * U[:, 4]
+    B = U[:, 5] + 1j * U[:, 6]
+    assert (B / C).imag.min() < 0.0  # the discrete field does lose it somewhere
+    G = oracle.pbeam_sum(g, r["tab"], U, TMAX, 0.5 * L, W.hz([10.0, 60.0]))
+    assert np.isfinite(G).all() and np.abs(G).max() < 1.0
 
 
 @pytest.mark.parametrize("eps,tilt", [(0.0, 0.0), (0.2, 0.0), (0.2, 0.3)])
