@@ -21,7 +21,7 @@ SRC = os.path.join(HERE, "egb_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 PLANES = ("phi1", "psi", "ReC", "ImC", "ReB", "ImB")
-PAR_PLANES = ("X", "vt", "tau", "ReC", "ImC", "ReB", "ImB")  # paraxial depth march
+PAR_PLANES = ("X", "vt", "tau", "ReC", "ImC", "ReB", "ImB", "phase")  # paraxial depth march
 VEL_PLANES = ("Vx", "Vz", "Vt", "A11", "A12", "A21", "A22")
 NFLD, NTAY = 5, 6
 
@@ -186,7 +186,7 @@ def solve(problem, nsteps=None, dt=None):
 # ---------------------------------------------------------------- paraxial
 # Depth march on (x, theta) slices, theta in (-theta_max, theta_max); see the
 # paraxial section of egb_oracle.c.  Arrays: pvel[nz][7][nth][nx],
-# states [nz][7][nth][nx] (planes PAR_PLANES), T[source][nz][nx].
+# states [nz][8][nth][nx] (planes PAR_PLANES), T[source][nz][nx].
 
 def ptheta(grid, theta_max: float) -> np.ndarray:
     dth = 2.0 * theta_max / grid.nth
@@ -210,15 +210,15 @@ def psubsteps(grid, rate: float, cfl: float = 0.5) -> int:
 
 
 def pinit(grid, pvel: np.ndarray, theta_max: float, beta: float) -> np.ndarray:
-    U = np.zeros((7, grid.nth, grid.nx))
+    U = np.zeros((len(PAR_PLANES), grid.nth, grid.nx))
     lib().oc_pinit(grid.nx, grid.nth, grid.x0, grid.dx, float(theta_max), _p(_c(pvel[0, 0])), float(beta), _p(U))
     return U
 
 
 def pmarch(grid, pvel: np.ndarray, theta_max: float, U0: np.ndarray, nsub: int, Ub=None) -> np.ndarray:
-    """Levels [nz][7][nth][nx] from U0 on level 0; Ub: the surface data held
+    """Levels [nz][8][nth][nx] from U0 on level 0; Ub: the surface data held
     in the ghosts (U0 itself when None)."""
-    Uall = np.zeros((grid.nz, 7, grid.nth, grid.nx))
+    Uall = np.zeros((grid.nz, len(PAR_PLANES), grid.nth, grid.nx))
     Uall[0] = U0
     Ub = _c(U0 if Ub is None else Ub)
     rc = lib().oc_pmarch(grid.nx, grid.nz, grid.nth, grid.dx, grid.dz, float(theta_max), _p(_c(pvel)), int(nsub),

@@ -744,7 +744,12 @@ int oc_pick(int nx, int nz, int nth, double x0, double z0, double dx, double dz,
  *   B = i beta C.
  * Grid: x_i = x0 + (i + 1/2) dx, z_n = z0 + (n + 1/2) dz,
  *       theta_k = -theta_max + (k + 1/2) dtheta, dtheta = 2 theta_max / nth.
- * Plane order of the oracle state: X, vartheta, tau, Re C, Im C, Re B, Im B.
+ * Plane order of the oracle state: X, vartheta, tau, Re C, Im C, Re B, Im B,
+ * Phi.  Phi is the continuous phase of C along the ray (the KMAH phase):
+ * with C' = (A11 C + A12 B) / V_z and A real, d(log C)/dz has the imaginary
+ * part (A12 / V_z) Im(B / C), so Phi_z + u Phi_x + w Phi_theta =
+ * (A12 / V_z) Im(B / C), Phi = 0 on the surface (C(0) > 0); exp(i Phi) =
+ * C / |C| while Phi keeps counting past +-pi where the ray crosses caustics.
  * Velocity table pvel[n][7][k][i]: u, w, 1/V_z, A11/V_z, A12/V_z, A21/V_z, A22/V_z.
  */
 #define P_X 0
@@ -754,7 +759,8 @@ int oc_pick(int nx, int nz, int nth, double x0, double z0, double dx, double dz,
 #define P_IC 4
 #define P_RB 5
 #define P_IB 6
-#define NPAR 7
+#define P_PH 7
+#define NPAR 8
 
 int oc_pvelocity(int nx, int nz, int nth, double dx, double dz, double theta_max, const double *tab,
                  double *pvel, double *rate_out)
@@ -806,6 +812,7 @@ int oc_pinit(int nx, int nth, double x0, double dx, double theta_max, const doub
             U[P_IC * plane + c] = 0.0;
             U[P_RB * plane + c] = 0.0;
             U[P_IB * plane + c] = beta * c0;
+            U[P_PH * plane + c] = 0.0;
         }
     }
     return 0;
@@ -870,6 +877,11 @@ static void prhs(int nx, int nth, double dx, double dth, const double *pv0, cons
             Lf[P_RB] += cv[5] * U[P_RC * plane + c] + cv[6] * U[P_RB * plane + c];
             Lf[P_IC] += cv[3] * U[P_IC * plane + c] + cv[4] * U[P_IB * plane + c];
             Lf[P_IB] += cv[5] * U[P_IC * plane + c] + cv[6] * U[P_IB * plane + c];
+            {
+                double rc = U[P_RC * plane + c], ic = U[P_IC * plane + c];
+                double rb = U[P_RB * plane + c], ib = U[P_IB * plane + c];
+                Lf[P_PH] += cv[4] * (ib * rc - rb * ic) / (rc * rc + ic * ic);
+            }
             for (int f = 0; f < NPAR; ++f) L[f * plane + c] = Lf[f];
         }
 }
@@ -915,6 +927,10 @@ int oc_pmarch(int nx, int nz, int nth, double dx, double dz, double theta_max, c
  * differences (ghosts as in the march).  Each beam contributes, as a row of
  * the phase-space superposition,
  *   sqrt(v / C) sqrt(u1 / s) s^-1 d vartheta exp(i omega T),
+ * sqrt(v / C) on the branch the ray carries: the principal root times
+ * (-1)^k, k = round((Phi - arg C) / 2 pi) full turns of the continuous phase
+ * Phi (the KMAH phase: the principal root alone is wrong past a second
+ * caustic; arg C keeps the phase consistent with M = B / C),
  *   T = tau + p_s (X - x_s) + p1 (x0 - x) + 1/2 M_row (x0 - x)^2,
  * with the traveltime Hessian of the phase-space beam sum (M = B C^-1 in the
  * ray-normal frame), and the whole scaled by i / (4 pi).  Reading: the depth
@@ -995,7 +1011,11 @@ int oc_pbeam_sum(int nx, int nz, int nth, double x0, double z0, double dx, doubl
                 r.psi = tau + ps[0] * (X[c] - xs);
                 r.p = lin ? oc_lin28(sn, cs, gx / gz, v) : sn / v;
                 r.M = Mn * gz * gz + 2.0 * gpq * gx * gz + gq * gx * gx;
-                r.amp = csqrt(v / C) * sqrt(u1 / ss) / ss * meas;
+                /* sqrt(v / C) on the branch the ray carries: the principal root turned by
+                 * the number of full turns between the continuous phase Phi and arg C */
+                double turns = nearbyint((U[P_PH * plane + c] - carg(C)) / (2.0 * M_PI));
+                double sgn = fmod(fabs(turns), 2.0) == 1.0 ? -1.0 : 1.0;
+                r.amp = sgn * csqrt(v / C) * sqrt(u1 / ss) / ss * meas;
                 if (comp >= 0) { /* g_i at the cell (phase angle theta) times g_k at the source (vartheta) */
                     double mr[NFLD], gr[2], gs[2];
                     for (int m = 0; m < NFLD; ++m) mr[m] = tab[(((long)i * nz + n) * NFLD + m) * NTAY];

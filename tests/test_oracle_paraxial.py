@@ -38,6 +38,9 @@ def test_homogeneous_isotropic_is_exact():
     assert np.abs(U[:, 4] - beta * dz / np.cos(t) ** 2)[m].max() < 1e-5 * beta * g.dx
     assert np.abs(U[:, 5]).max() < 1e-12
     assert np.abs(U[:, 6] - beta / np.cos(t)).max() < 1e-14
+    # the continuous phase of C: arctan(beta dz / cos) (no caustic), = arg C
+    assert np.abs(U[:, 7] - np.arctan(beta * dz / np.cos(t)))[m].max() < 1e-7
+    assert np.abs(U[:, 7] - np.angle(U[:, 3] + 1j * U[:, 4]))[m].max() < 1e-9
 
 
 def test_long_march_stays_bounded_in_heterogeneous_medium():
@@ -60,6 +63,14 @@ def test_long_march_stays_bounded_in_heterogeneous_medium():
     C = U[:, 3] + 1j * U[:, 4]
     B = U[:, 5] + 1j * U[:, 6]
     assert (B / C).imag.min() < 0.0  # the discrete field does lose it somewhere
+    # the continuous phase Phi of C follows arg C (mod 2 pi) in the cells of
+    # rays from the source, and past caustics it has turned by more than pi
+    # (the principal root of 1/C has the wrong sign there: the KMAH phase)
+    ok = np.abs(U[:, 1]) < TMAX
+    d = np.abs(np.exp(1j * U[:, 7]) - C / np.abs(C))[ok]
+    assert np.median(d) < 1e-3 and np.percentile(d, 99.9) < 2.0
+    turns = np.rint((U[:, 7] - np.angle(C)) / (2 * np.pi))[ok]
+    assert (np.abs(turns) % 2 == 1).sum() > 1000
     G = oracle.pbeam_sum(g, r["tab"], U, TMAX, 0.5 * L, W.hz([10.0, 60.0]))
     assert np.isfinite(G).all() and np.abs(G).max() < 1.0
 
