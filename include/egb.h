@@ -259,10 +259,12 @@ egb_status egb_adjoint_medium(const egb_grid *g, const egb_medium *m, const void
  * (-theta_max, theta_max), dtheta = 2 theta_max / nth, theta_k = -theta_max +
  * (k + 1/2) dtheta.  Level state (one per depth z_n, n = 0 .. nz-1): X (the
  * surface position of the ray, eqs. 17, 19), vartheta (its take-off angle),
- * C, B (eqs. 21-24) and tau (traveltime, eq. 19).  One march serves every
- * surface source: the first arrival from a source at x_s is read on the level
- * set X = x_s (eq. 35).  Layout of one level: planes X, vartheta, Re C, Im C,
- * Re B, Im B in the grid dtype, then tau in float64, each [theta][x] (x
+ * C, B (eqs. 21-24), Phi (the continuous phase of C along the ray, the KMAH
+ * phase: Phi_z + u Phi_x + w Phi_theta = (A12/V_z) Im(B/C), 0 on the
+ * surface) and tau (traveltime, eq. 19).  One march serves every surface
+ * source: the first arrival from a source at x_s is read on the level set
+ * X = x_s (eq. 35).  Layout of one level: planes X, vartheta, Re C, Im C,
+ * Re B, Im B, Phi in the grid dtype, then tau in float64, each [theta][x] (x
  * fastest) padded to egb_paraxial_plane_stride() elements; `levels` holds nz
  * levels of egb_paraxial_level_bytes() each.  The grid's nth counts the
  * theta nodes of the aperture; z0 is the depth of level 0 (the surface).
@@ -287,7 +289,8 @@ egb_status egb_paraxial_velocity(const egb_grid *g, const void *coeff2d, double 
                                  double *rate, void *work, size_t work_bytes, hipStream_t stream);
 
 /* Surface data on level 0 (eqs. 20, 24 on the surface line): X = x,
- * vartheta = theta, tau = 0, C = cos(theta) + sin(theta) u, B = i beta C. */
+ * vartheta = theta, tau = 0, C = cos(theta) + sin(theta) u, B = i beta C,
+ * Phi = 0. */
 egb_status egb_paraxial_init(const egb_grid *g, const void *pvel, double theta_max, double beta, void *levels,
                              hipStream_t stream);
 
@@ -308,7 +311,9 @@ egb_status egb_paraxial_march(const egb_grid *g, const void *pvel, double theta_
  * Per cell of the (x, theta) slice, the take-off-angle measure is the smoothed
  * delta (width 2 dx) of the signed distance d = (X - xs)/|grad X| (theta
  * scaled by dx/dtheta) times |det d(X, vartheta)/d(x, theta)| / |grad X|; the
- * beam is sqrt(v/C) sqrt(u1/s)/s exp(i omega T), T = tau + p_s (X - xs) +
+ * beam is sqrt(v/C) sqrt(u1/s)/s exp(i omega T) (sqrt(v/C) on the branch
+ * of the ray: the principal root times (-1)^k, k the full turns between Phi
+ * and arg C), T = tau + p_s (X - xs) +
  * p1 (x0 - x) + M (x0 - x)^2 / 2, with M the traveltime Hessian along the
  * row (M = B C^-1 across the ray), u1 = cos + sin u and s the 2D beam weight
  * at the take-off angle for the medium frozen at the source, p_s the

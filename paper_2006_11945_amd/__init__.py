@@ -28,7 +28,7 @@ EGB_PHI1, EGB_RE_C, EGB_IM_C, EGB_RE_B, EGB_IM_B, EGB_PSI = range(6)
 EGB_OP_VELOCITY, EGB_OP_STEP, EGB_OP_BEAM, EGB_OP_ADJOINT, EGB_OP_PARAXIAL, EGB_OP_PBEAM = range(6)
 STATE_PLANES = ("phi1", "ReC", "ImC", "ReB", "ImB", "psi")
 VEL_PLANES = ("Vx", "Vz", "Vt", "A11", "A12", "A21", "A22")
-PAR_PLANES = ("X", "vartheta", "ReC", "ImC", "ReB", "ImB", "tau")   # paraxial level planes, in memory order
+PAR_PLANES = ("X", "vartheta", "ReC", "ImC", "ReB", "ImB", "phase", "tau")   # paraxial level planes, in memory order
 PVEL_PLANES = ("u", "w", "Stau", "A11", "A12", "A21", "A22")
 
 if not os.path.exists(LIB_PATH):
@@ -411,7 +411,7 @@ def paraxial_level_views(eg, levels: torch.Tensor, n: int) -> dict:
     base = levels[n * lb:(n + 1) * lb]
     out = {}
     for q, name in enumerate(PAR_PLANES):
-        dt, off = (torch.float64, 6 * st * es) if name == "tau" else (rd, q * st * es)
+        dt, off = (torch.float64, 7 * st * es) if name == "tau" else (rd, q * st * es)
         e = torch.empty((), dtype=dt).element_size()
         out[name] = base[off:off + eg.nth * eg.nx * e].view(dt).view(eg.nth, eg.nx)
     return out

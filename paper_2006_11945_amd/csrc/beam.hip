@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) void k_pbeam_compact(PBeamArgs a) {
     if (ix >= a.nx || k >= a.nth || n >= a.nz) return;
     const long long P = a.P, c = (long long)k * a.nx + ix;
     const R* L = reinterpret_cast<const R*>(static_cast<const char*>(a.levels) + (size_t)n * a.level_bytes);
-    const double tau = reinterpret_cast<const double*>(L + 6 * P)[c];
+    const double tau = reinterpret_cast<const double*>(L + 7 * P)[c];
     if (!(tau > 0.0)) return;
     const R* X = L;           // plane 0
     const R* T = L + P;       // plane 1: vartheta
@@ -346,6 +346,15 @@ __global__ __launch_bounds__(256) void k_pbeam_compact(PBeamArgs a) {
     double sqre = sqrt(0.5 * (mod + vCre));
     double sqim = sqrt(0.5 * fmax(mod - vCre, 0.0));
     sqim = vCim < 0.0 ? -sqim : sqim;
+    {
+        // the branch the ray carries: (-1)^k, k full turns between the continuous
+        // phase Phi of C and arg C (the KMAH phase)
+        const double turns = rint(((double)L[6 * P + c] - atan2(imC, reC)) / 6.283185307179586476925286766559);
+        if (fmod(fabs(turns), 2.0) == 1.0) {
+            sqre = -sqre;
+            sqim = -sqim;
+        }
+    }
     // source normalisation at the take-off angle (medium frozen at the source)
     MediumPoint Ms;
     {

@@ -107,13 +107,13 @@ hipError_t launch_adjoint_medium(const GridArgs& a, int dtype, const egb_medium&
                                  const egb_source& src, const void* gvel, const void* lam0, const double* bfold,
                                  double* grad, double* gtab, double* gms, hipStream_t s);
 
-// Paraxial depth march (see paraxial.hip).  Level planes: six in the grid
+// Paraxial depth march (see paraxial.hip).  Level planes: seven in the grid
 // dtype, then tau in double, each of paraxial_stride() elements.
 inline size_t paraxial_stride(const egb_grid& g) {
     size_t n = (size_t)g.nth * (size_t)g.nx;
     return (n + 63) / 64 * 64;
 }
-inline size_t paraxial_level_bytes(const egb_grid& g) { return paraxial_stride(g) * (6 * real_size(g) + 8); }
+inline size_t paraxial_level_bytes(const egb_grid& g) { return paraxial_stride(g) * (7 * real_size(g) + 8); }
 inline size_t paraxial_vel_bytes(const egb_grid& g) { return (size_t)g.nz * 7 * paraxial_stride(g) * real_size(g); }
 struct PStageArgs {
     int nx, nth;

@@ -13,8 +13,10 @@
 // for a surface source at x_s follow from the level set X = x_s (eq. 35),
 // over the nodes whose take-off angle lies inside the aperture.
 //
-// Level layout: planes X, vartheta, Re C, Im C, Re B, Im B in R, then tau in
-// double, each [theta][x] (x fastest) padded to a multiple of 64 elements.
+// Level layout: planes X, vartheta, Re C, Im C, Re B, Im B, Phi in R, then
+// tau in double, each [theta][x] (x fastest) padded to a multiple of 64
+// elements.  Phi is the continuous phase of C along the ray (the KMAH phase):
+// Phi_z + u Phi_x + w Phi_theta = (A12 / V_z) Im(B / C), 0 on the surface.
 //
 // Work decomposition: a block owns a tile of 64 x by 2 theta cells of one
 // slice and has one wave per (plane, theta row), so that a slice of nx nth
@@ -37,13 +39,13 @@ namespace egb {
 namespace {
 
 constexpr int PTX = 64, PTT = 2;         // tile: x cells, theta rows
-constexpr int NPL = 7;                   // planes, one wave each per theta row
+constexpr int NPL = 8;                   // planes, one wave each per theta row
 constexpr int PRX = PTX + 6;             // LDS row (3-cell halo each side)
 constexpr int PROWS = PTT + 6;
 constexpr int PCELLS = PROWS * PRX;      // LDS cells per plane
 constexpr int NT = PTX * PTT * NPL;      // threads per block
-constexpr int NPR = 6;                   // R planes: X, vartheta, ReC, ImC, ReB, ImB (then tau)
-enum { Q_X = 0, Q_VT = 1, Q_RC = 2, Q_IC = 3, Q_RB = 4, Q_IB = 5, Q_TAU = 6 };
+constexpr int NPR = 7;                   // R planes: X, vartheta, ReC, ImC, ReB, ImB, Phi (then tau)
+enum { Q_X = 0, Q_VT = 1, Q_RC = 2, Q_IC = 3, Q_RB = 4, Q_IB = 5, Q_PH = 6, Q_TAU = 7 };
 // velocity planes: u, w, S_tau, A11/Vz, A12/Vz, A21/Vz, A22/Vz
 
 template <typename R>
@@ -112,7 +114,7 @@ __global__ __launch_bounds__(NT) void k_pstage(PStageArgs a) {
     const R* p0 = static_cast<const R*>(a.pv0);
     const R* p1 = static_cast<const R*>(a.pv1);
     const bool isC = p == Q_RC || p == Q_IC;
-    const int qa = p == Q_TAU ? 2 : (isC ? 3 : 5);  // this plane's source coefficients
+    const int qa = p == Q_TAU ? 2 : (p == Q_PH ? 4 : (isC ? 3 : 5));  // this plane's source coefficients
     const R u0 = p0[c], u1 = p1[c], w0 = p0[a.P + c], w1 = p1[a.P + c];
     const R a0 = p0[qa * a.P + c], a1 = p1[qa * a.P + c];
     const R b0 = p0[(qa + 1) * a.P + c], b1 = p1[(qa + 1) * a.P + c];
@@ -193,7 +195,12 @@ __global__ __launch_bounds__(NT) void k_pstage(PStageArgs a) {
                           lds_r<R>(sm, meB + 2 * step, p));
     };
     R acc = (R)cb * own - gx * wup(sx) - gt * wup(st);
-    if (p >= Q_RC) {
+    if (p == Q_PH) {
+        // continuous phase of C: (A12 / V_z) Im(B / C)
+        const R rc = lds_r<R>(sm, meB, Q_RC), ic = lds_r<R>(sm, meB, Q_IC);
+        const R rb = lds_r<R>(sm, meB, Q_RB), ib = lds_r<R>(sm, meB, Q_IB);
+        acc += cdr * ca_ * ((ib * rc - rb * ic) / (rc * rc + ic * ic));
+    } else if (p >= Q_RC) {
         // (C, B) pairs (Re C, Re B) and (Im C, Im B): C' = A11 C + A12 B, B' = A21 C + A22 B
         const R cC = lds_r<R>(sm, meB, isC ? p : p - 2), cB = lds_r<R>(sm, meB, isC ? p + 2 : p);
         acc += cdr * (ca_ * cC + cb_ * cB);
@@ -203,7 +210,7 @@ __global__ __launch_bounds__(NT) void k_pstage(PStageArgs a) {
 }
 
 // Surface data on level 0: X = x, vartheta = theta, tau = 0,
-// C = cos(theta) + sin(theta) u, B = i beta C.
+// C = cos(theta) + sin(theta) u, B = i beta C, Phi = 0.
 template <typename R>
 __global__ __launch_bounds__(256) void k_pinit(int nx, int nth, long long P, double x0, double dx, double theta_max,
                                                double beta, const R* pv, R* U) {
@@ -221,6 +228,7 @@ __global__ __launch_bounds__(256) void k_pinit(int nx, int nth, long long P, dou
     U[Q_IC * P + c] = (R)0;
     U[Q_RB * P + c] = (R)0;
     U[Q_IB * P + c] = (R)(beta * c0);
+    U[Q_PH * P + c] = (R)0;
     reinterpret_cast<double*>(U + NPR * P)[c] = 0.0;
 }
 

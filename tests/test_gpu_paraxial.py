@@ -27,7 +27,7 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 TMAX = np.pi / 3
 # oracle plane index of each GPU level plane
-OR = {"X": 0, "vartheta": 1, "tau": 2, "ReC": 3, "ImC": 4, "ReB": 5, "ImB": 6}
+OR = {"X": 0, "vartheta": 1, "tau": 2, "ReC": 3, "ImC": 4, "ReB": 5, "ImB": 6, "phase": 7}
 PV = ("u", "w", "Stau", "A11", "A12", "A21", "A22")
 
 
@@ -124,7 +124,7 @@ def test_paraxial_pick_parity_and_edge_cases():
     xs = np.array([0.31 * L, 0.5 * L + 3.0, 0.77 * L, g.xc()[5], -10.0 * L])  # the last: outside, no arrivals
     P = egb().Paraxial(g, med, TMAX, DEV, "f32")
     U = o["U"].copy()
-    for q in (0, 1, 3, 4, 5, 6):  # the storage of an FP32 march (tau stays double)
+    for q in (0, 1, 3, 4, 5, 6, 7):  # the storage of an FP32 march (tau stays double)
         U[:, q] = U[:, q].astype(np.float32).astype(np.float64)
     write_levels(P, U)
     T = P.pick(xs).cpu().numpy()
@@ -218,7 +218,7 @@ def test_paraxial_beam_sum_parity(dtype, lin, comp):
     o = oracle.psolve(g, med, TMAX, beta)
     U = o["U"].copy()
     if dtype == "f32":
-        for q in (0, 1, 3, 4, 5, 6):
+        for q in (0, 1, 3, 4, 5, 6, 7):
             U[:, q] = U[:, q].astype(np.float32).astype(np.float64)
     P = egb().Paraxial(g, med, TMAX, DEV, dtype)
     P.velocity()
