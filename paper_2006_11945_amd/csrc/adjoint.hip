@@ -240,22 +240,26 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
         a1[j] = (R)0;
     }
     // mu (lambda of the output, 0 in the source ball and outside the grid)
-    // and V of the own cell, fetched one slice ahead
-    auto own_mu_v = [&](int x, R& m0, double& m1, R& vx, R& vz, R& vt) {
+    // and V of the own cell, fetched one slice ahead: the raw lambda and the
+    // live flag (the select waits for the load, so it is made at the shift)
+    auto own_mu_v = [&](int x, R& l0, double& l1, bool& live, R& vx, R& vz, R& vt) {
         const int xc = min(max(x, 0), g.nx - 1);
         const unsigned c = kb + (unsigned)(xc * g.nz + izc);
-        const R l0 = bload<R>(rL, c * ES, 0);
-        const double l1 = bload<double>(rL, c * 8u, PSI);
+        l0 = bload<R>(rL, c * ES, 0);
+        l1 = bload<double>(rL, c * 8u, PSI);
         vx = bload<R>(rV, c * ES, EGB_VX * SP);
         vz = bload<R>(rV, c * ES, EGB_VZ * SP);
         vt = bload<R>(rV, c * ES, EGB_VT * SP);
-        const bool live = zin && !in_ball(xc, izc);
-        m0 = live ? l0 : (R)0;
-        m1 = live ? l1 : 0.0;
+        live = zin && !in_ball(xc, izc);
     };
     R cm0, cvx, cvz, cvt;
     double cm1;
-    own_mu_v(xa, cm0, cm1, cvx, cvz, cvt);
+    {
+        bool live;
+        own_mu_v(xa, cm0, cm1, live, cvx, cvz, cvt);
+        cm0 = live ? cm0 : (R)0;
+        cm1 = live ? cm1 : 0.0;
+    }
 
     // value cells of the next core slice, loaded at the end of the step before
     R vv[NVI], vv1[NVI];
@@ -278,9 +282,13 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
         }
     };
 
-    // halo sources' mu and V of the next core slice, loaded with the values
-    R hm0[NHI], hvel[NHI];
-    double hm1[NHI];
+    // halo sources' mu and V of this core slice (h) and of the next (nh: raw
+    // lambda and the live flag, selected at the shift), loaded with the
+    // values one step ahead; the V plane goes into the per-lane offset (a
+    // per-lane scalar offset would make the load a loop over its values)
+    R hm0[NHI], hvel[NHI], nhm0[NHI], nhvel[NHI];
+    double hm1[NHI], nhm1[NHI];
+    bool nhlive[NHI];
     auto load_halo = [&](int x) {
         const unsigned xo = (unsigned)(x * g.nz);
 #pragma unroll
@@ -290,12 +298,10 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
             unsigned hc;
             hcell(tid + r * NT, tl, zl, real, hc);
             const unsigned c = (hc + xo) * ES, c8 = (hc + xo) * 8u;
-            const R l0 = bload<R>(rL, c, 0);
-            const double l1 = bload<double>(rL, c8, PSI);
-            hvel[r] = bload<R>(rV, c, (tid + r * NT < 6 * TZ ? EGB_VT : EGB_VZ) * SP);
-            const bool live = real && !in_ball(x, tzi * TZ + zl);
-            hm0[r] = live ? l0 : (R)0;
-            hm1[r] = live ? l1 : 0.0;
+            nhm0[r] = bload<R>(rL, c, 0);
+            nhm1[r] = bload<double>(rL, c8, PSI);
+            nhvel[r] = bload<R>(rV, c + (unsigned)(tid + r * NT < 6 * TZ ? EGB_VT : EGB_VZ) * SP, 0);
+            nhlive[r] = real && !in_ball(x, tzi * TZ + zl);
         }
     };
 
@@ -335,7 +341,8 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
         x_value(xs + 4, qn, qpn);
         R nm0, nvx, nvz, nvt;
         double nm1;
-        own_mu_v(xs + 1, nm0, nm1, nvx, nvz, nvt);
+        bool nlive;
+        own_mu_v(xs + 1, nm0, nm1, nlive, nvx, nvz, nvt);
         const unsigned xo = (unsigned)(min(max(xs, 0), g.nx - 1) * g.nz);
         const unsigned cR = (kb + xo + (unsigned)izc) * ES;
         // loads consumed later in the step: the output target's lambda and
@@ -353,11 +360,14 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
             oa1 = bload<double>(rAi, co * 8u, PSI);
         }
         const bool wlive = __any(cm0 != (R)0 || cm1 != 0.0);  // wave-uniform
-        R gv0 = (R)0, gv1 = (R)0, gv2 = (R)0;
-        if (core && wlive) {
-            gv0 = bload<R>(rG, cR, 0);
-            gv1 = bload<R>(rG, cR, SP);
-            gv2 = bload<R>(rG, cR, 2u * SP);
+        // (straight-line: the store is guarded, the address is clamped)
+        const R gv0 = bload<R>(rG, cR, 0), gv1 = bload<R>(rG, cR, SP), gv2 = bload<R>(rG, cR, 2u * SP);
+        // the next core slice's values and halo, one step ahead: their latency
+        // hides behind this step's rows (the registers of this slice's values
+        // are free once it is in LDS)
+        if (xs + 1 >= x0 && xs + 1 < x1) {  // block-uniform
+            load_values(xs + 1);
+            load_halo(xs + 1);
         }
         R gsx = (R)0;  // this step's x term of gvel
         // x rows of the own column
@@ -510,16 +520,17 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
         qp[6] = qpn;
         a0[6] = (R)0;
         a1[6] = (R)0;
-        cm0 = nm0;
-        cm1 = nm1;
+        cm0 = nlive ? nm0 : (R)0;
+        cm1 = nlive ? nm1 : 0.0;
         cvx = nvx;
         cvz = nvz;
         cvt = nvt;
-        if (xs + 1 >= x0 && xs + 1 < x1) {  // the next core slice
-            load_values(xs + 1);
-            load_halo(xs + 1);
+#pragma unroll
+        for (int r = 0; r < NHI; ++r) {
+            hm0[r] = nhlive[r] ? nhm0[r] : (R)0;
+            hm1[r] = nhlive[r] ? nhm1[r] : 0.0;
+            hvel[r] = nhvel[r];
         }
-
     }
 }
 
