@@ -199,8 +199,7 @@ def paraxial_leg(n, nsrc, nth=256, theta_max=None):
                          "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                          "avg_launch_ms": stage_ms, "flop_per_cell_stage": FLOP_PCELL_STAGE,
-                         "note": "march wall time (graph capture, instantiation and launch gaps included) "
-                                 "divided by the stage launches"}}
+                         "note": "march wall time (launch gaps included) divided by the stage launches"}}
 
 
 # sources the stage kernel is built from (the traffic record names their hash)

@@ -302,7 +302,9 @@ egb_status egb_paraxial_init(const egb_grid *g, const void *pvel, double theta_m
  * entering through a side or an aperture edge carry it: their take-off
  * angle lies outside the aperture at the aperture edges).  In: level 0 of
  * levels (kept).  Out: levels 1 .. nz-1.  work: egb_workspace_size(g, EGB_OP_PARAXIAL).  The
- * 3 nsub (nz - 1) stage launches run as one hipGraph; synchronises `stream`. */
+ * 3 nsub (nz - 1) stage launches are queued in order on `stream` (the call
+ * returns without waiting for them).
+ * EGB_EUNSUPPORTED if one level (egb_paraxial_level_bytes) reaches 2 GiB. */
 egb_status egb_paraxial_march(const egb_grid *g, const void *pvel, double theta_max, int32_t nsub, void *levels,
                               void *work, size_t work_bytes, hipStream_t stream);
 

@@ -307,6 +307,7 @@ egb_status egb_paraxial_march(const egb_grid* g, const void* pvel, double theta_
     if (!aligned16(pvel) || !aligned16(levels) || !aligned16(work)) return EGB_EINVAL;
     if (work_bytes < egb_workspace_size(g, EGB_OP_PARAXIAL)) return EGB_EWORKSPACE;
     const size_t lb = paraxial_level_bytes(*g);
+    if (lb >= ((size_t)1 << 31)) return EGB_EUNSUPPORTED;  // the stage kernel's 32-bit offsets
     const long long P = (long long)paraxial_stride(*g);
     const size_t vb = (size_t)7 * P * real_size(*g);  // coefficient bytes per level
     char* lev = static_cast<char*>(levels);
@@ -322,47 +323,31 @@ egb_status egb_paraxial_march(const egb_grid* g, const void* pvel, double theta_
     a.Ub = levels;  // level 0 keeps the surface data
     const double h = 1.0 / nsub;
     a.dl = g->dz * h;
-    // the whole march (3 nsub (nz - 1) stage launches) as one graph replayed on `stream`
-    hipStream_t cs = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        hipError_t le = hipSuccess;
-        for (int n = 0; n + 1 < g->nz && le == hipSuccess; ++n) {
-            a.pv0 = pv + (size_t)n * vb;
-            a.pv1 = pv + (size_t)(n + 1) * vb;
-            void* next = lev + (size_t)(n + 1) * lb;
-            for (int j = 0; j < nsub && le == hipSuccess; ++j) {
-                const double s0 = j * h;
-                a.U0 = j == 0 ? lev + (size_t)n * lb : next;  // the substep's start
-                a.Uin = a.U0;
-                a.Uout = U1;
-                a.s = s0;
-                le = launch_pstage(a, g->dtype, 0, cs);
-                if (le != hipSuccess) break;
-                a.Uin = U1;
-                a.Uout = U2;
-                a.s = s0 + h;
-                le = launch_pstage(a, g->dtype, 1, cs);
-                if (le != hipSuccess) break;
-                a.Uin = U2;
-                a.Uout = next;  // in place for j > 0: each cell reads the start only at itself
-                a.s = s0 + 0.5 * h;
-                le = launch_pstage(a, g->dtype, 2, cs);
-            }
+    // 3 nsub (nz - 1) stage launches in order on `stream`: the host enqueues
+    // a stage faster than the GPU runs one, so the queue never drains
+    for (int n = 0; n + 1 < g->nz; ++n) {
+        a.pv0 = pv + (size_t)n * vb;
+        a.pv1 = pv + (size_t)(n + 1) * vb;
+        void* next = lev + (size_t)(n + 1) * lb;
+        for (int j = 0; j < nsub; ++j) {
+            const double s0 = j * h;
+            a.U0 = j == 0 ? lev + (size_t)n * lb : next;  // the substep's start
+            a.Uin = a.U0;
+            a.Uout = U1;
+            a.s = s0;
+            hipError_t e = launch_pstage(a, g->dtype, 0, stream);
+            a.Uin = U1;
+            a.Uout = U2;
+            a.s = s0 + h;
+            if (e == hipSuccess) e = launch_pstage(a, g->dtype, 1, stream);
+            a.Uin = U2;
+            a.Uout = next;  // in place for j > 0: each cell reads the start only at itself
+            a.s = s0 + 0.5 * h;
+            if (e == hipSuccess) e = launch_pstage(a, g->dtype, 2, stream);
+            if (e != hipSuccess) return hip_status(e);
         }
-        e = hipStreamEndCapture(cs, &graph);
-        if (e == hipSuccess) e = le;
     }
-    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e == hipSuccess) e = hipGraphLaunch(exec, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
-    if (cs) hipStreamDestroy(cs);
-    return hip_status(e);
+    return EGB_OK;
 }
 
 egb_status egb_paraxial_beam_sum(const egb_grid* g, const void* coeff2d, const void* levels, double theta_max,

@@ -24,8 +24,8 @@
 // (ghosts filled while loading) goes to LDS once, then every thread reads its
 // plane's x and theta stencils there at per-lane mirrored addresses
 // (V D(U) = |V| W(values in upwind order), as in the phase-space stage
-// kernel).  The march is a long chain of short launches, captured once into
-// a hipGraph.
+// kernel).  The march is a long chain of short launches queued in order on
+// one stream.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -56,107 +56,119 @@ struct PSmem {
     W w[(NPR + LdsWord<R>::PSI_WORDS) * PLANE];
 };
 
-// LDS cell i of a tile (x0, k0): inside the slice the marched value u[i0]
-// ((w0, w1) = (1, 0)); beyond an x end or a theta end (a ghost) the surface
-// data b extended linearly from the two cells next to that end,
-// w0 b[i0] + w1 b[i1] with (w0, w1) = (m + 1, -m); cells beyond both are
-// never read (weights 0).
-__device__ __forceinline__ void pline_src(int nx, int nth, int x, int k, int& i0, int& i1, int& w0, int& w1) {
-    const bool xin = x >= 0 && x < nx, kin = k >= 0 && k < nth;
-    if (xin && kin) {
-        i0 = i1 = k * nx + x;
-        w0 = 1;
-        w1 = 0;
-    } else if (kin) {
-        const bool lo = x < 0;
-        const int m = lo ? -x : x - (nx - 1);
-        i0 = k * nx + (lo ? 0 : nx - 1);
-        i1 = k * nx + (lo ? 1 : nx - 2);
-        w0 = m + 1;
-        w1 = -m;
-    } else if (xin) {
-        const bool lo = k < 0;
-        const int m = lo ? -k : k - (nth - 1);
-        i0 = (lo ? 0 : nth - 1) * nx + x;
-        i1 = (lo ? 1 : nth - 2) * nx + x;
-        w0 = m + 1;
-        w1 = -m;
-    } else {
-        i0 = i1 = 0;
-        w0 = w1 = 0;
-    }
+// Source of the LDS cell at slice position (x, k) in a tile that touches an
+// end: inside the slice the marched value u[i0] (no ghost); beyond an x end
+// or a theta end the surface data b extended linearly from the two cells
+// next to that end, w0 b[i0] + w1 b[i1] with (w0, w1) = (m + 1, -m) for the
+// ghost m cells outside; cells beyond both ends are never read (weights 0).
+// Branch-free: every lane of a wave takes the same instructions.
+__device__ __forceinline__ void pghost_src(int nx, int nth, int x, int k, int& i0, int& i1, int& w0, int& w1,
+                                           bool& ghost) {
+    const int mx = x < 0 ? -x : max(x - (nx - 1), 0);
+    const int mk = k < 0 ? -k : max(k - (nth - 1), 0);
+    const int xa = mx ? (x < 0 ? 0 : nx - 1) : x, xb = mx ? (x < 0 ? 1 : nx - 2) : x;
+    const int ka = mk ? (k < 0 ? 0 : nth - 1) : k, kb = mk ? (k < 0 ? 1 : nth - 2) : k;
+    const int m = mx + mk;
+    const bool both = mx != 0 && mk != 0;
+    i0 = ka * nx + xa;
+    i1 = kb * nx + xb;
+    ghost = m != 0;
+    w0 = both ? 0 : m + 1;
+    w1 = both ? 0 : -m;
 }
 
 // One RK stage on a 64 x 2 (x, theta) tile: thread (x, row, plane), so
 // every wave holds one plane of one theta row and all branches on the plane
 // are wave-uniform.  The tile of every plane with its halo is loaded to LDS
-// by the waves of that plane (all loads of a thread issued together; the
-// second point of a ghost only in tiles that touch an edge); the x and theta
-// stencils are then read at per-lane mirrored addresses.  The cell's
-// coefficients and stage-start value are fetched before the barrier.
+// by the waves of that plane: each thread takes the rows y, y + 2, y + 4,
+// y + 6 at its own column and the first 48 threads one of the six halo
+// columns of a row (all loads of a thread issued together; the ghost logic
+// only in tiles that touch an end).  The x and theta stencils are then read
+// at per-lane mirrored addresses.  The cell's coefficients and stage-start
+// value are fetched before the barrier.  Offsets are 32-bit (one level
+// stays below 2 GiB).
 template <typename R, int STAGE>
 __global__ __launch_bounds__(NT) void k_pstage(PStageArgs a) {
     using S = PSmem<R>;
     using Wd = typename S::W;
     constexpr int WS = (int)sizeof(Wd);
-    constexpr int NLD = (PCELLS + PTX * PTT - 1) / (PTX * PTT);  // LDS cells per thread
+    constexpr int NMAIN = PROWS / PTT;  // tile rows per thread
+    static_assert(PROWS % PTT == 0 && 6 * PROWS <= PTX * PTT, "fill mapping");
     __shared__ S sm;
-    const int ntx = (a.nx + PTX - 1) / PTX;
+    const int nx = a.nx, nth = a.nth, P = (int)a.P;
+    const int ntx = (nx + PTX - 1) / PTX;
     const int tx0 = (blockIdx.x % ntx) * PTX, tk0 = (blockIdx.x / ntx) * PTT;
     const int p = threadIdx.z;  // plane (wave-uniform)
-    const int pt = threadIdx.y * PTX + threadIdx.x;
-    const bool edge = tx0 < 3 || tx0 + PTX + 3 > a.nx || tk0 < 3 || tk0 + PTT + 3 > a.nth;  // block-uniform
+    const int ty = threadIdx.y, tx = threadIdx.x;
+    const int pt = ty * PTX + tx;
+    const bool edge = tx0 < 3 || tx0 + PTX + 3 > nx || tk0 < 3 || tk0 + PTT + 3 > nth;  // block-uniform
 
     // own cell (clamped for threads past the slice) and its prefetched inputs
-    const int x = tx0 + (int)threadIdx.x, k = tk0 + (int)threadIdx.y;
-    const bool valid = x < a.nx && k < a.nth;
-    const long long c = (long long)min(k, a.nth - 1) * a.nx + min(x, a.nx - 1);
+    const int x = tx0 + tx, k = tk0 + ty;
+    const bool valid = x < nx && k < nth;
+    const int c = min(k, nth - 1) * nx + min(x, nx - 1);
     const R* p0 = static_cast<const R*>(a.pv0);
     const R* p1 = static_cast<const R*>(a.pv1);
     const bool isC = p == Q_RC || p == Q_IC;
     const int qa = p == Q_TAU ? 2 : (p == Q_PH ? 4 : (isC ? 3 : 5));  // this plane's source coefficients
-    const R u0 = p0[c], u1 = p1[c], w0 = p0[a.P + c], w1 = p1[a.P + c];
-    const R a0 = p0[qa * a.P + c], a1 = p1[qa * a.P + c];
-    const R b0 = p0[(qa + 1) * a.P + c], b1 = p1[(qa + 1) * a.P + c];
+    const R u0 = p0[c], u1 = p1[c], w0 = p0[P + c], w1 = p1[P + c];
+    const R a0 = p0[qa * P + c], a1 = p1[qa * P + c];
+    const R b0 = p0[(qa + 1) * P + c], b1 = p1[(qa + 1) * P + c];
     const R* Ui = static_cast<const R*>(a.Uin);
     const R* Ub = static_cast<const R*>(a.Ub);  // surface data (level 0): the ghosts
     R r0 = (R)0;
     double t0 = 0.0;
     if constexpr (STAGE != 0) {
         const R* U0 = static_cast<const R*>(a.U0);
-        if (p == Q_TAU) t0 = reinterpret_cast<const double*>(U0 + NPR * a.P)[c];
-        else r0 = U0[p * a.P + c];
+        if (p == Q_TAU) t0 = reinterpret_cast<const double*>(U0 + NPR * P)[c];
+        else r0 = U0[p * P + c];
     }
 
     // this plane's tile + halo into LDS
+    const bool hal = pt < 6 * PROWS;  // a halo-column cell: row pt / 6, column 0..2 or 67..69
+    const int er = pt / 6, ej = pt - 6 * er;
+    const int ec = ej < 3 ? ej : ej + PTX;
     auto fill = [&](auto tag) {
         using T = decltype(tag);
-        const T* u = p == Q_TAU ? reinterpret_cast<const T*>(Ui + NPR * a.P) : reinterpret_cast<const T*>(Ui + p * a.P);
-        const T* ub = p == Q_TAU ? reinterpret_cast<const T*>(Ub + NPR * a.P) : reinterpret_cast<const T*>(Ub + p * a.P);
-        T v0[NLD], b0[NLD], b1[NLD];
-        int wa[NLD], wb[NLD];
+        const int po = p == Q_TAU ? NPR * P : p * P;
+        const T* u = reinterpret_cast<const T*>(Ui + po);
+        const T* ub = reinterpret_cast<const T*>(Ub + po);
+        T v[NMAIN + 1];
+        if (!edge) {
+            const int base = (tk0 - 3 + ty) * nx + x;
 #pragma unroll
-        for (int r = 0; r < NLD; ++r) {
-            const int i = min(pt + r * PTX * PTT, PCELLS - 1);
-            int i0, i1;
-            pline_src(a.nx, a.nth, tx0 + i % PRX - 3, tk0 + i / PRX - 3, i0, i1, wa[r], wb[r]);
-            v0[r] = u[i0];
-            b0[r] = edge ? ub[i0] : (T)0;
-            b1[r] = edge ? ub[i1] : (T)0;
+            for (int j = 0; j < NMAIN; ++j) v[j] = u[base + j * PTT * nx];
+            if (hal) v[NMAIN] = u[(tk0 - 3 + er) * nx + tx0 - 3 + ec];
+        } else {
+            T f[NMAIN + 1], g[NMAIN + 1];
+            int wa[NMAIN + 1], wb[NMAIN + 1];
+            bool gh[NMAIN + 1];
+#pragma unroll
+            for (int j = 0; j <= NMAIN; ++j) {
+                if (j == NMAIN && !hal) break;
+                const int gx = j < NMAIN ? x : tx0 - 3 + ec;
+                const int gk = tk0 - 3 + (j < NMAIN ? ty + j * PTT : er);
+                int i0, i1;
+                pghost_src(nx, nth, gx, gk, i0, i1, wa[j], wb[j], gh[j]);
+                f[j] = (gh[j] ? ub : u)[i0];
+                g[j] = ub[i1];
+            }
+#pragma unroll
+            for (int j = 0; j <= NMAIN; ++j) {
+                if (j == NMAIN && !hal) break;
+                v[j] = gh[j] ? (T)wa[j] * f[j] + (T)wb[j] * g[j] : f[j];
+            }
         }
 #pragma unroll
-        for (int r = 0; r < NLD; ++r) {
-            const int i = pt + r * PTX * PTT;
-            if (i < PCELLS) {
-                const bool ghost = wa[r] != 1 || wb[r] != 0;
-                const T v = edge && ghost ? (T)wa[r] * b0[r] + (T)wb[r] * b1[r] : v0[r];
-                if constexpr (sizeof(T) == sizeof(Wd)) {
-                    sm.w[(p == Q_TAU ? NPR : p) * S::PLANE + i] = __builtin_bit_cast(Wd, v);
-                } else {  // tau of an FP32 slice: two 32-bit planes
-                    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-                    sm.w[NPR * S::PLANE + i] = (Wd)(unsigned)b;
-                    sm.w[(NPR + 1) * S::PLANE + i] = (Wd)(unsigned)(b >> 32);
-                }
+        for (int j = 0; j <= NMAIN; ++j) {
+            if (j == NMAIN && !hal) break;
+            const int i = j < NMAIN ? (ty + j * PTT) * PRX + tx + 3 : er * PRX + ec;
+            if constexpr (sizeof(T) == sizeof(Wd)) {
+                sm.w[(p == Q_TAU ? NPR : p) * S::PLANE + i] = __builtin_bit_cast(Wd, v[j]);
+            } else {  // tau of an FP32 slice: two 32-bit planes
+                const unsigned long long bits = __builtin_bit_cast(unsigned long long, v[j]);
+                sm.w[NPR * S::PLANE + i] = (Wd)(unsigned)bits;
+                sm.w[(NPR + 1) * S::PLANE + i] = (Wd)(unsigned)(bits >> 32);
             }
         }
     };
@@ -172,7 +184,7 @@ __global__ __launch_bounds__(NT) void k_pstage(PStageArgs a) {
     constexpr double ca = RK<STAGE>::ca, cb = RK<STAGE>::cb;
     const double cdl = cb * a.dl;
     const R gx = fabs(cu) * (R)(cdl / a.dx), gt = fabs(cw) * (R)(cdl / a.dth), cdr = (R)cdl;
-    const int meB = (((int)threadIdx.y + 3) * PRX + (int)threadIdx.x + 3) * WS;
+    const int meB = ((ty + 3) * PRX + tx + 3) * WS;
     const int sx = cu >= (R)0 ? WS : -WS, st = cw >= (R)0 ? PRX * WS : -PRX * WS;
     R* Uo = static_cast<R*>(a.Uout);
     if (p == Q_TAU) {
@@ -185,7 +197,7 @@ __global__ __launch_bounds__(NT) void k_pstage(PStageArgs a) {
         const R conv = gx * wup(sx) + gt * wup(st);
         double acc = cb * own + cdl * (double)ca_ - (double)conv;
         if constexpr (STAGE != 0) acc += ca * t0;
-        reinterpret_cast<double*>(Uo + NPR * a.P)[c] = acc;
+        reinterpret_cast<double*>(Uo + NPR * P)[c] = acc;
         return;
     }
     const R own = lds_r<R>(sm, meB, p);
@@ -206,7 +218,7 @@ __global__ __launch_bounds__(NT) void k_pstage(PStageArgs a) {
         acc += cdr * (ca_ * cC + cb_ * cB);
     }
     if constexpr (STAGE != 0) acc += (R)ca * r0;
-    Uo[p * a.P + c] = acc;
+    Uo[p * P + c] = acc;
 }
 
 // Surface data on level 0: X = x, vartheta = theta, tau = 0,
