@@ -122,6 +122,30 @@ def test_long_march_stays_bounded_in_heterogeneous_medium():
     assert np.abs(t2 - t1).max() < 1e-3 * t1.min()
 
 
+def test_one_step_on_a_window_equals_the_whole_grid():
+    # One SSP-RK3 step reads cells within 9 of a cell (three stages of a
+    # 3-cell stencil): a window of the medium around the source, stepped on
+    # its own, reproduces the whole grid's step exactly on cells 9 or more
+    # from its edges and differs nearer to them (its ghosts are the source
+    # data, not marched cells).  The full-size GPU parity test compares such
+    # windows.
+    p = W.tti_512(n=64, nth=48)
+    g = p.grid
+    o = oracle.solve(p, nsteps=1)
+    n = 36
+    i0, k0 = int(p.source.xs / g.dx) - n // 2, int(p.source.zs / g.dz) - n // 2 + 3
+    gw = W.Grid(nx=n, nz=n, nth=g.nth, dx=g.dx, dz=g.dz, x0=g.x0 + i0 * g.dx, z0=g.z0 + k0 * g.dz)
+    cut = lambda a: np.ascontiguousarray(a[i0:i0 + n, k0:k0 + n])
+    mw = W.Medium(vp0=cut(p.medium.vp0), eps=cut(p.medium.eps), delta=cut(p.medium.delta),
+                  tilt=cut(p.medium.tilt), vs_ratio=p.medium.vs_ratio)
+    ow = oracle.solve(W.Problem("window", gw, mw, p.source, 1, p.omegas), nsteps=1, dt=o["dt"])
+    A = o["U"][:, :, i0:i0 + n, k0:k0 + n]
+    inner = (slice(None), slice(None), slice(9, n - 9), slice(9, n - 9))
+    assert np.array_equal(A[inner], ow["U"][inner])
+    near = (slice(None), slice(None), slice(6, n - 6), slice(6, n - 6))
+    assert not np.array_equal(A[near], ow["U"][near])
+
+
 def test_medium_table_thomsen_and_quadratic_derivatives():
     g = W.Grid(nx=9, nz=11, nth=8, dx=10.0, dz=12.0)
     X, Z = np.meshgrid(g.xc(), g.zc(), indexing="ij")
