@@ -70,6 +70,7 @@ def batched_vs_sequential(nprob, nsteps, lo=128, hi=384):
     cells = sum(p.grid.ncell for p in probs)
     arr = egb.make_problem_array(solvers)
     work = egb.alloc_bytes(egb.workspace_size_batched(arr), "cuda:0")
+    blocks = egb.egb_tune_batched(arr, work)  # launch shape for this batch (results do not depend on it)
     egb.egb_liouville_step_batched(arr, 1, work)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -87,7 +88,7 @@ def batched_vs_sequential(nprob, nsteps, lo=128, hi=384):
         s.step(nsteps)
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
-    return {"problems": nprob, "sizes": [lo, hi], "cells": cells, "rk3_steps": nsteps,
+    return {"problems": nprob, "sizes": [lo, hi], "cells": cells, "rk3_steps": nsteps, "tuned_blocks": blocks,
             "batched_cell_updates_per_s": cells * nsteps / t_batch,
             "sequential_cell_updates_per_s": cells * nsteps / t_seq,
             "batched_over_sequential": t_seq / t_batch}
@@ -266,6 +267,8 @@ def main():
     s = egb.Solver(p, dev)
     s.velocity()
     dt = s.dt_cfl
+    s.init()
+    blocks = s.tune()  # stage launch shape for this grid (results do not depend on it)
     s.work_beam = egb.alloc_bytes(egb.workspace_size(s.eg, egb.EGB_OP_BEAM), dev)
     out = torch.empty((len(p.omegas), p.grid.nx, p.grid.nz, 2), dtype=torch.float32, device=dev)
     rx_d = torch.as_tensor(rx, device=dev)
@@ -320,7 +323,7 @@ def main():
                    "frequencies": len(p.omegas), "receivers": 128, "psi_dtype": "f64"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(args.n),
-                     "kernel": "k_stage (one SSP-RK3 stage)", "avg_launch_ms": stage_ms,
+                     "kernel": "k_stage (one SSP-RK3 stage)", "avg_launch_ms": stage_ms, "blocks_per_launch": blocks,
                      "flop_per_cell_stage": FLOP_CELL_STAGE},
         "march_ms": float(np.mean(march_ms)),
         "march_cell_updates_per_s": cells * p.nsteps / (float(np.mean(march_ms)) * 1e-3),

@@ -186,9 +186,9 @@ size_t egb_workspace_size_batched(const egb_problem *probs, int32_t nprob);
 
 /* nsteps SSP-RK3 steps of every problem in `probs` (HOST array, nprob >= 1;
  * same dtype for all), the same scheme as egb_liouville_step.  All problems
- * advance together: each stage is ONE launch over a single tile queue that
- * spans all grids (each block walks the queue from its index with a stride of
- * the grid size; by default the grid covers the queue), and the 3 * nsteps
+ * advance together: each stage is ONE launch over the (tile, x) steps of all
+ * grids, split into one contiguous range per block (by default one round of
+ * resident blocks; see launch tuning), and the 3 * nsteps
  * launches are captured in one hipGraph replayed on `stream`.  Synchronises `stream` before returning
  * (the graph is destroyed).  Errors as egb_liouville_step; EGB_EINVAL if the
  * dtypes differ. */
@@ -342,6 +342,46 @@ egb_status egb_paraxial_beam_sum(const egb_grid *g, const void *coeff2d, const v
  * Out: T (device float64 [nsrc][nz][nx]). */
 egb_status egb_paraxial_pick(const egb_grid *g, const void *levels, double theta_max, const double *xs, int32_t nsrc,
                              double *T, hipStream_t stream);
+
+/* ------------------------------------------------------ launch tuning
+ * Not a step of the method: the stage kernels of egb_liouville_step, its
+ * kinematic variant, the reverse stages of egb_adjoint_step and
+ * egb_liouville_step_batched split the (tile, x) steps of their grids into
+ * one contiguous range per block, and the number of blocks per launch
+ * decides only how that work is spread over the chip; every count gives
+ * bit-identical results.  By default a launch uses one round of resident
+ * blocks.  The library keeps a count per (operation, grid shape(s), dtype,
+ * current device), process-wide behind a mutex; these calls read it, fix it
+ * or measure it.  They allocate nothing on the device. */
+#define EGB_TUNE_STEP 0      /* egb_liouville_step */
+#define EGB_TUNE_KINEMATIC 1 /* egb_liouville_step_kinematic, and the stages egb_adjoint_step recomputes */
+#define EGB_TUNE_ADJOINT 2   /* the reverse stages of egb_adjoint_step */
+
+/* The count in use for `op` on grids of g's shape and dtype (0 = the
+ * default); 0 also for bad arguments. */
+int32_t egb_get_blocks(const egb_grid *g, int32_t op);
+
+/* Fix the count (blocks >= 1) or restore the default (blocks = 0).
+ * EGB_EINVAL for a bad grid, op or count; EGB_EHIP without a device. */
+egb_status egb_set_blocks(const egb_grid *g, int32_t op, int32_t blocks);
+
+/* The autotuner for op = EGB_TUNE_STEP or EGB_TUNE_KINEMATIC: times `reps`
+ * (>= 1) launches of RK stage 0 at each candidate count (the default and
+ * 1/2 to 3 rounds of resident blocks) with HIP events on `stream`, keeps the
+ * fastest for this shape and returns it in *blocks.  Arguments as
+ * egb_liouville_step (one step); stage 0 reads `state` and writes only
+ * `work`, so no buffer of the caller changes.  Synchronises `stream`. */
+egb_status egb_tune_step(const egb_grid *g, const void *vel3d, const egb_source *src, const void *bdata,
+                         const void *state, void *work, size_t work_bytes, double dt, int32_t op, int32_t reps,
+                         hipStream_t stream, int32_t *blocks);
+
+/* The same for a batch (egb_liouville_step_batched's arguments), keyed by
+ * the shapes of all its grids in order.  Synchronises `stream`. */
+egb_status egb_tune_batched(const egb_problem *probs, int32_t nprob, void *work, size_t work_bytes, int32_t reps,
+                            hipStream_t stream, int32_t *blocks);
+
+/* Fix (blocks >= 1) or restore (0) the count of a batch of this shape. */
+egb_status egb_set_blocks_batched(const egb_problem *probs, int32_t nprob, int32_t blocks);
 
 /* Human-readable text for a status code (static storage). */
 const char *egb_status_string(int32_t status);

@@ -103,6 +103,13 @@ def _load():
     for name in ("egb_medium_table", "egb_paraxial_velocity", "egb_paraxial_init", "egb_paraxial_march",
                  "egb_paraxial_pick", "egb_paraxial_beam_sum"):
         getattr(L, name).restype = ctypes.c_int
+    L.egb_get_blocks.argtypes = [G, i32]; L.egb_get_blocks.restype = i32
+    L.egb_set_blocks.argtypes = [G, i32, i32]
+    L.egb_tune_step.argtypes = [G, vp, S, vp, vp, vp, sz, d, i32, i32, vp, ctypes.POINTER(i32)]
+    L.egb_tune_batched.argtypes = [P, i32, vp, sz, i32, vp, ctypes.POINTER(i32)]
+    L.egb_set_blocks_batched.argtypes = [P, i32, i32]
+    for name in ("egb_set_blocks", "egb_tune_step", "egb_tune_batched", "egb_set_blocks_batched"):
+        getattr(L, name).restype = ctypes.c_int
     L.egb_status_string.argtypes = [i32]; L.egb_status_string.restype = ctypes.c_char_p
     return L
 
@@ -295,6 +302,38 @@ def egb_liouville_step_batched(arr, nsteps: int, work, stream=None):
     _check("egb_liouville_step_batched", rc)
 
 
+# ----------------------------------------------------------- launch tuning
+EGB_TUNE_STEP, EGB_TUNE_KINEMATIC, EGB_TUNE_ADJOINT = 0, 1, 2
+
+
+def egb_get_blocks(eg, op: int) -> int:
+    return int(_lib.egb_get_blocks(ctypes.byref(eg), int(op)))
+
+
+def egb_set_blocks(eg, op: int, blocks: int):
+    _check("egb_set_blocks", _lib.egb_set_blocks(ctypes.byref(eg), int(op), int(blocks)))
+
+
+def egb_tune_step(eg, vel3d, src: EgbSource, bdata, state, work, dt: float, op: int = EGB_TUNE_STEP, reps: int = 3,
+                  stream=None) -> int:
+    b = ctypes.c_int32(0)
+    rc = _lib.egb_tune_step(ctypes.byref(eg), _ptr(vel3d), ctypes.byref(src), _ptr(bdata), _ptr(state), _ptr(work),
+                            work.numel(), float(dt), int(op), int(reps), _stream(stream), ctypes.byref(b))
+    _check("egb_tune_step", rc)
+    return b.value
+
+
+def egb_tune_batched(arr, work, reps: int = 3, stream=None) -> int:
+    b = ctypes.c_int32(0)
+    rc = _lib.egb_tune_batched(arr, len(arr), _ptr(work), work.numel(), int(reps), _stream(stream), ctypes.byref(b))
+    _check("egb_tune_batched", rc)
+    return b.value
+
+
+def egb_set_blocks_batched(arr, blocks: int):
+    _check("egb_set_blocks_batched", _lib.egb_set_blocks_batched(arr, len(arr), int(blocks)))
+
+
 # ------------------------------------------------------------------ views
 def state_views(eg, state: torch.Tensor) -> dict:
     """Named [nth][nx][nz] views of the planes of a state byte buffer."""
@@ -365,6 +404,12 @@ class Solver:
         self.work_beam = None
         self.dt_cfl = None
 
+    def tune(self, op: int = EGB_TUNE_STEP, reps: int = 3, dt: Optional[float] = None, stream=None) -> int:
+        """Autotune the stage launch shape for this grid (after velocity() and
+        init()); the state is left unchanged."""
+        return egb_tune_step(self.eg, self.vel3d, self.src, self.bdata, self.state, self.work_step,
+                             self.dt_cfl if dt is None else dt, op, reps, stream)
+
     def velocity(self, stream=None) -> float:
         self.dt_cfl = egb_hamiltonian_velocity(self.eg, self.medium, self.coeff2d, self.vel3d, self.work_vel, stream)
         return self.dt_cfl
@@ -377,6 +422,11 @@ class Solver:
     def step(self, nsteps: int, dt: Optional[float] = None, stream=None):
         egb_liouville_step(self.eg, self.vel3d, self.src, self.bdata, self.state, self.work_step,
                            self.dt_cfl if dt is None else dt, nsteps, stream)
+
+    def step_kinematic(self, nsteps: int, dt: Optional[float] = None, stream=None):
+        """March phi1 and psi only (the other planes are left as they are)."""
+        egb_liouville_step_kinematic(self.eg, self.vel3d, self.src, self.bdata, self.state, self.work_step,
+                                     self.dt_cfl if dt is None else dt, nsteps, stream)
 
     def beam(self, omegas, out: Optional[torch.Tensor] = None, stream=None, lin: int = EGB_LIN_EXACT) -> torch.Tensor:
         """Green's function [nw][nx][nz][re, im]; lin selects the linear phase

@@ -821,19 +821,17 @@ __global__ void k_adj_fields(GridArgs a, egb_medium med, const double* gtab, con
 }
 
 template <typename R, int TK>
-hipError_t adj_stage_t(AdjStageArgs a, int stage, hipStream_t s) {
+hipError_t adj_stage_t(AdjStageArgs a, int stage, hipStream_t s, int blocks) {
     a.ntz = (a.g.nz + TZ - 1) / TZ;
     a.ntk = (a.g.nth + TK - 1) / TK;
     const void* k = stage == 0 ? (const void*)k_adj_stage<R, 0, TK>
                   : stage == 1 ? (const void*)k_adj_stage<R, 1, TK> : (const void*)k_adj_stage<R, 2, TK>;
     const long long W = (long long)a.ntz * a.ntk * a.g.nx;
-    // one round of resident blocks, each with at least 16 target steps
-    // (EGB_ADJ_GRID=<blocks> overrides: tuning sweeps, segmentation tests)
-    const char* fe = getenv("EGB_ADJ_GRID");
-    const int forced = fe ? atoi(fe) : 0;
-    long long G = forced > 0 ? forced : resident_blocks(k, 64 * TK);
+    // by default one round of resident blocks, each with at least 16 target
+    // steps; `blocks` > 0 splits the steps over that many blocks instead
+    long long G = blocks > 0 ? blocks : resident_blocks(k, 64 * TK);
     if (G <= 0) return hipErrorInvalidDeviceFunction;
-    if (forced <= 0) G = std::min(G, W / 16);
+    if (blocks <= 0) G = std::min(G, W / 16);
     G = std::max(1LL, std::min(G, W));
     const dim3 grid((unsigned)G), block(TZ, TK);
     switch (stage) {
@@ -848,7 +846,8 @@ hipError_t adj_stage_t(AdjStageArgs a, int stage, hipStream_t s) {
 
 hipError_t launch_adjoint_stage(const GridArgs& g, int dtype, int stage, const void* vel, const void* bd,
                                 const void* Uin, const void* lam_out, void* lam_in, const void* acc_in, void* acc_out,
-                                void* gvel, void* bfold, double dt, double xs, double zs, double r02, hipStream_t s) {
+                                void* gvel, void* bfold, double dt, double xs, double zs, double r02, hipStream_t s,
+                                int blocks) {
     const unsigned long long es = dtype == EGB_F64 ? 8 : 4, S = (unsigned long long)g.stride;
     AdjStageArgs a;
     a.g = g;
@@ -870,7 +869,7 @@ hipError_t launch_adjoint_stage(const GridArgs& g, int dtype, int stage, const v
     a.gvel_bytes = (unsigned)(3 * S * es);
     a.bd_bytes = (unsigned)((unsigned long long)g.bstride * (5 * es + 8));
     a.ntz = a.ntk = 0;
-    return dtype == EGB_F64 ? adj_stage_t<double, 4>(a, stage, s) : adj_stage_t<float, 8>(a, stage, s);
+    return dtype == EGB_F64 ? adj_stage_t<double, 4>(a, stage, s, blocks) : adj_stage_t<float, 8>(a, stage, s, blocks);
 }
 
 hipError_t launch_pick_adjoint(const GridArgs& a, int dtype, const void* state, const double* rx, int nr,

@@ -152,19 +152,20 @@ static egb_status liouville_steps(const egb_grid* g, const void* vel3d, const eg
     sa.xs = src->xs;
     sa.zs = src->zs;
     sa.r02 = src->r0 * src->r0;
+    const int blocks = tuned_blocks(kin ? EGB_TUNE_KINEMATIC : EGB_TUNE_STEP, grid_shape_key(*g), g->dtype);
     for (int n = 0; n < nsteps; ++n) {
         sa.U0 = state;
         sa.Uin = state;
         sa.Uout = U1;
-        hipError_t e = launch_stage(sa, g->dtype, 0, stream, kin);
+        hipError_t e = launch_stage(sa, g->dtype, 0, stream, kin, blocks);
         if (e != hipSuccess) return EGB_EHIP;
         sa.Uin = U1;
         sa.Uout = U2;
-        e = launch_stage(sa, g->dtype, 1, stream, kin);
+        e = launch_stage(sa, g->dtype, 1, stream, kin, blocks);
         if (e != hipSuccess) return EGB_EHIP;
         sa.Uin = U2;
         sa.Uout = state;
-        e = launch_stage(sa, g->dtype, 2, stream, kin);
+        e = launch_stage(sa, g->dtype, 2, stream, kin, blocks);
         if (e != hipSuccess) return EGB_EHIP;
     }
     return EGB_OK;
@@ -224,11 +225,13 @@ egb_status egb_adjoint_step(const egb_grid* g, const void* vel3d, const egb_sour
     sa.U0 = state_n;
     sa.Uin = state_n;
     sa.Uout = U1;
-    hipError_t e = launch_stage(sa, g->dtype, 0, stream, true);
+    const unsigned long long key = grid_shape_key(*g);
+    const int kb = tuned_blocks(EGB_TUNE_KINEMATIC, key, g->dtype), ab = tuned_blocks(EGB_TUNE_ADJOINT, key, g->dtype);
+    hipError_t e = launch_stage(sa, g->dtype, 0, stream, true, kb);
     if (e == hipSuccess) {
         sa.Uin = U1;
         sa.Uout = U2;
-        e = launch_stage(sa, g->dtype, 1, stream, true);
+        e = launch_stage(sa, g->dtype, 1, stream, true, kb);
     }
     const double r02 = src->r0 * src->r0;
     // Reverse: stage 2 (input U2), stage 1 (input U1), stage 0 (input U^n).
@@ -237,13 +240,13 @@ egb_status egb_adjoint_step(const egb_grid* g, const void* vel3d, const egb_sour
     // 0 writes the result back into `lambda`.
     if (e == hipSuccess)  // lambda -> L2 (of U2), acc L1 = (ca mu + ball) part
         e = launch_adjoint_stage(a, g->dtype, 2, vel3d, bdata, U2, lambda, L2, nullptr, L1, gvel, bfold, dt, src->xs,
-                                 src->zs, r02, stream);
+                                 src->zs, r02, stream, ab);
     if (e == hipSuccess)  // L2 -> L3 (of U1), acc L1 +=
         e = launch_adjoint_stage(a, g->dtype, 1, vel3d, bdata, U1, L2, L3, L1, L1, gvel, bfold, dt, src->xs, src->zs,
-                                 r02, stream);
+                                 r02, stream, ab);
     if (e == hipSuccess)  // L3 -> lambda = L1 + stage 0 terms
         e = launch_adjoint_stage(a, g->dtype, 0, vel3d, bdata, state_n, L3, nullptr, L1, lambda, gvel, bfold, dt,
-                                 src->xs, src->zs, r02, stream);
+                                 src->xs, src->zs, r02, stream, ab);
     return hip_status(e);
 }
 
@@ -427,25 +430,16 @@ size_t egb_workspace_size_batched(const egb_problem* probs, int32_t nprob) {
     return b;
 }
 
-egb_status egb_liouville_step_batched(const egb_problem* probs, int32_t nprob, int32_t nsteps, void* work,
-                                      size_t work_bytes, hipStream_t stream) {
-    if (!probs || nprob < 1 || nsteps < 0) return EGB_EINVAL;
+// Validate a batch and write its item table and step offsets into the
+// workspace (item table | wfirst[] | per-problem U1, U2).
+static egb_status prepare_batch(const egb_problem* probs, int32_t nprob, void* work, size_t work_bytes,
+                                char*& d_items, long long*& d_first, long long& total) {
     const int dtype = probs[0].grid.dtype;
-    for (int p = 0; p < nprob; ++p) {
-        const egb_problem& q = probs[p];
-        if (!grid_ok(&q.grid) || q.grid.dtype != dtype || !q.vel3d || !q.bdata || !q.state || !source_ok(&q.src))
-            return EGB_EINVAL;
-        if (!aligned16(q.vel3d) || !aligned16(q.bdata) || !aligned16(q.state)) return EGB_EINVAL;
-        if (!(q.dt > 0.0) || !isfinite(q.dt)) return EGB_ECFL;
-        if (!stage_fits_32bit(grid_args(q.grid), dtype)) return EGB_EUNSUPPORTED;
-    }
-    if (nsteps == 0) return EGB_OK;
     if (!work || !aligned16(work)) return EGB_EINVAL;
     if (work_bytes < egb_workspace_size_batched(probs, nprob)) return EGB_EWORKSPACE;
-    // workspace: item table | wfirst[] | per-problem U1, U2
     char* w = static_cast<char*>(work);
-    char* d_items = w;
-    long long* d_first = reinterpret_cast<long long*>(w + align256((size_t)nprob * batch_item_bytes()));
+    d_items = w;
+    d_first = reinterpret_cast<long long*>(w + align256((size_t)nprob * batch_item_bytes()));
     char* bufs = reinterpret_cast<char*>(d_first) + align256((size_t)(nprob + 1) * sizeof(long long));
     std::vector<char> items((size_t)nprob * batch_item_bytes());
     std::vector<long long> first(nprob + 1, 0);
@@ -460,25 +454,52 @@ egb_status egb_liouville_step_batched(const egb_problem* probs, int32_t nprob, i
                                             q.src.r0 * q.src.r0);
         first[p + 1] = first[p] + n;
     }
-    const long long total = first[nprob];
+    total = first[nprob];
     hipError_t e = hipMemcpy(d_items, items.data(), items.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_first, first.data(), first.size() * sizeof(long long), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return EGB_EHIP;
-    // one round of resident blocks over all problems' steps
-    // (EGB_BATCH_GRID=<blocks> overrides, for tuning sweeps)
-    int grid = 0;
-    if (const char* ge = getenv("EGB_BATCH_GRID")) grid = std::max(1, atoi(ge));
+    return e == hipSuccess ? EGB_OK : EGB_EHIP;
+}
+
+static egb_status batch_ok(const egb_problem* probs, int32_t nprob) {
+    if (!probs || nprob < 1) return EGB_EINVAL;
+    const int dtype = probs[0].grid.dtype;
+    for (int p = 0; p < nprob; ++p) {
+        const egb_problem& q = probs[p];
+        if (!grid_ok(&q.grid) || q.grid.dtype != dtype || !q.vel3d || !q.bdata || !q.state || !source_ok(&q.src))
+            return EGB_EINVAL;
+        if (!aligned16(q.vel3d) || !aligned16(q.bdata) || !aligned16(q.state)) return EGB_EINVAL;
+        if (!(q.dt > 0.0) || !isfinite(q.dt)) return EGB_ECFL;
+        if (!stage_fits_32bit(grid_args(q.grid), dtype)) return EGB_EUNSUPPORTED;
+    }
+    return EGB_OK;
+}
+
+egb_status egb_liouville_step_batched(const egb_problem* probs, int32_t nprob, int32_t nsteps, void* work,
+                                      size_t work_bytes, hipStream_t stream) {
+    egb_status st = batch_ok(probs, nprob);
+    if (st != EGB_OK) return st;
+    if (nsteps < 0) return EGB_EINVAL;
+    if (nsteps == 0) return EGB_OK;
+    const int dtype = probs[0].grid.dtype;
+    char* d_items = nullptr;
+    long long* d_first = nullptr;
+    long long total = 0;
+    st = prepare_batch(probs, nprob, work, work_bytes, d_items, d_first, total);
+    if (st != EGB_OK) return st;
+    // one round of resident blocks over all problems' steps unless a count
+    // is tuned or fixed for this batch shape
+    const int grid = tuned_blocks(TUNE_BATCHED, batch_shape_key(probs, nprob), dtype);
     // capture the whole march in one graph on a private stream, replay on `stream`
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t le = hipSuccess;
         for (int n = 0; n < nsteps && le == hipSuccess; ++n)
-            for (int st = 0; st < 3 && le == hipSuccess; ++st)
-                le = launch_stage_batched(d_items, d_first, nprob, total, dtype, st, grid, cs);
+            for (int s = 0; s < 3 && le == hipSuccess; ++s)
+                le = launch_stage_batched(d_items, d_first, nprob, total, dtype, s, grid, cs);
         e = hipStreamEndCapture(cs, &graph);
         if (e == hipSuccess) e = le;
     }
@@ -489,6 +510,75 @@ egb_status egb_liouville_step_batched(const egb_problem* probs, int32_t nprob, i
     if (graph) hipGraphDestroy(graph);
     if (cs) hipStreamDestroy(cs);
     return hip_status(e);
+}
+
+// ------------------------------------------------------------ launch tuning
+static bool tune_op_ok(int32_t op) { return op == EGB_TUNE_STEP || op == EGB_TUNE_KINEMATIC || op == EGB_TUNE_ADJOINT; }
+
+int32_t egb_get_blocks(const egb_grid* g, int32_t op) {
+    if (!grid_ok(g) || !tune_op_ok(op)) return 0;
+    return tuned_blocks(op, grid_shape_key(*g), g->dtype);
+}
+
+egb_status egb_set_blocks(const egb_grid* g, int32_t op, int32_t blocks) {
+    if (!grid_ok(g) || !tune_op_ok(op) || blocks < 0) return EGB_EINVAL;
+    return set_tuned_blocks(op, grid_shape_key(*g), g->dtype, blocks) == hipSuccess ? EGB_OK : EGB_EHIP;
+}
+
+egb_status egb_tune_step(const egb_grid* g, const void* vel3d, const egb_source* src, const void* bdata,
+                         const void* state, void* work, size_t work_bytes, double dt, int32_t op, int32_t reps,
+                         hipStream_t stream, int32_t* blocks) {
+    if (!grid_ok(g) || !vel3d || !bdata || !state || !work || !source_ok(src) || !blocks || reps < 1) return EGB_EINVAL;
+    if (op != EGB_TUNE_STEP && op != EGB_TUNE_KINEMATIC) return EGB_EINVAL;
+    if (!aligned16(vel3d) || !aligned16(bdata) || !aligned16(state) || !aligned16(work)) return EGB_EINVAL;
+    if (!(dt > 0.0) || !isfinite(dt)) return EGB_ECFL;
+    if (work_bytes < egb_workspace_size(g, EGB_OP_STEP)) return EGB_EWORKSPACE;
+    if (!stage_fits_32bit(grid_args(*g), g->dtype)) return EGB_EUNSUPPORTED;
+    StageArgs sa;
+    sa.g = grid_args(*g);
+    sa.vel = vel3d;
+    sa.bd = bdata;
+    sa.dt = dt;
+    sa.xs = src->xs;
+    sa.zs = src->zs;
+    sa.r02 = src->r0 * src->r0;
+    sa.U0 = state;
+    sa.Uin = state;
+    sa.Uout = work;  // stage 0 writes only its output
+    int best = 0;
+    hipError_t e = tune_stage(sa, g->dtype, op == EGB_TUNE_KINEMATIC, reps, stream, best);
+    if (e == hipSuccess) e = set_tuned_blocks(op, grid_shape_key(*g), g->dtype, best);
+    if (e != hipSuccess) return hip_status(e);
+    *blocks = best;
+    return EGB_OK;
+}
+
+egb_status egb_tune_batched(const egb_problem* probs, int32_t nprob, void* work, size_t work_bytes, int32_t reps,
+                            hipStream_t stream, int32_t* blocks) {
+    egb_status st = batch_ok(probs, nprob);
+    if (st != EGB_OK) return st;
+    if (!blocks || reps < 1) return EGB_EINVAL;
+    const int dtype = probs[0].grid.dtype;
+    char* d_items = nullptr;
+    long long* d_first = nullptr;
+    long long total = 0;
+    st = prepare_batch(probs, nprob, work, work_bytes, d_items, d_first, total);
+    if (st != EGB_OK) return st;
+    int best = 0;
+    hipError_t e = tune_batched(d_items, d_first, nprob, total, dtype, reps, stream, best);
+    if (e == hipSuccess) e = set_tuned_blocks(TUNE_BATCHED, batch_shape_key(probs, nprob), dtype, best);
+    if (e != hipSuccess) return hip_status(e);
+    *blocks = best;
+    return EGB_OK;
+}
+
+egb_status egb_set_blocks_batched(const egb_problem* probs, int32_t nprob, int32_t blocks) {
+    egb_status st = batch_ok(probs, nprob);
+    if (st != EGB_OK) return st;
+    if (blocks < 0) return EGB_EINVAL;
+    return set_tuned_blocks(TUNE_BATCHED, batch_shape_key(probs, nprob), probs[0].grid.dtype, blocks) == hipSuccess
+               ? EGB_OK
+               : EGB_EHIP;
 }
 
 egb_status egb_beam_sum(const egb_grid* g, const void* coeff2d, const void* vel3d, const egb_source* src,

@@ -83,7 +83,24 @@ struct StageArgs {
 // holds at once; 0 on a HIP error.
 int resident_blocks(const void* kernel, int threads);
 // kinematic: march phi1 and psi only (the planes a traveltime depends on)
-hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s, bool kinematic = false);
+// blocks <= 0: one round of resident blocks; > 0: the steps split over that many
+hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s, bool kinematic = false,
+                        int blocks = 0);
+// resident blocks of the stage kernel (one round) and its (tile, x) steps on grid g
+void stage_limits(const GridArgs& g, int dtype, bool kinematic, long long& resident, long long& work);
+long long batched_resident(int dtype);
+
+// Launch-shape cache and autotuner (tune.hip).  Operation ids: the public
+// EGB_TUNE_* values, and TUNE_BATCHED for a batch keyed by all its grids.
+constexpr int TUNE_BATCHED = 3;
+unsigned long long grid_shape_key(const egb_grid& g);
+unsigned long long batch_shape_key(const egb_problem* p, int n);
+int tuned_blocks(int op, unsigned long long shape, int dtype);  // 0: none (the default)
+hipError_t set_tuned_blocks(int op, unsigned long long shape, int dtype, int blocks);  // blocks <= 0: forget
+// the fastest block count for stage 0 of `a` (reads a.Uin / a.U0, writes a.Uout)
+hipError_t tune_stage(const StageArgs& a, int dtype, bool kinematic, int reps, hipStream_t s, int& best);
+hipError_t tune_batched(const void* items, const long long* wfirst, int nprob, long long total, int dtype, int reps,
+                        hipStream_t s, int& best);
 // The stage kernel addresses each array with 32-bit byte offsets.
 bool stage_fits_32bit(const GridArgs& g, int dtype);
 
@@ -100,7 +117,8 @@ hipError_t launch_stage_batched(const void* items, const long long* wfirst, int 
 // adjoint.hip); lam_out must not alias any output.
 hipError_t launch_adjoint_stage(const GridArgs& g, int dtype, int stage, const void* vel, const void* bd,
                                 const void* Uin, const void* lam_out, void* lam_in, const void* acc_in, void* acc_out,
-                                void* gvel, void* bfold, double dt, double xs, double zs, double r02, hipStream_t s);
+                                void* gvel, void* bfold, double dt, double xs, double zs, double r02, hipStream_t s,
+                                int blocks = 0);
 hipError_t launch_pick_adjoint(const GridArgs& a, int dtype, const void* state, const double* rx, int nr,
                                const double* tbar, void* lam, hipStream_t s);
 hipError_t launch_adjoint_medium(const GridArgs& a, int dtype, const egb_medium& m, const double* coeff2d,

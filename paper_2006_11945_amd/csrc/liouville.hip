@@ -423,7 +423,7 @@ unsigned long long bd_bytes_of(const GridArgs& g, size_t es) {
 }
 
 template <typename R, int TK, bool KIN>
-hipError_t launch_stage_t(const StageArgs& a, int stage, hipStream_t s) {
+hipError_t launch_stage_t(const StageArgs& a, int stage, hipStream_t s, int blocks) {
     TileArgs t;
     t.ntz = (a.g.nz + TZ - 1) / TZ;
     t.ntk = (a.g.nth + TK - 1) / TK;
@@ -434,14 +434,13 @@ hipError_t launch_stage_t(const StageArgs& a, int stage, hipStream_t s) {
     t.bd_bytes = (unsigned)bd_bytes_of(a.g, sizeof(R));
     const void* k = stage == 0 ? (const void*)k_stage<R, 0, TK, KIN>
                   : stage == 1 ? (const void*)k_stage<R, 1, TK, KIN> : (const void*)k_stage<R, 2, TK, KIN>;
-    // one round of resident blocks, each with at least MIN_STEPS x steps
-    // (EGB_STAGE_GRID=<blocks> overrides: tuning sweeps, segmentation tests)
-    const char* fe = getenv("EGB_STAGE_GRID");
-    const int forced = fe ? atoi(fe) : 0;
+    // by default one round of resident blocks, each with at least MIN_STEPS
+    // x steps; `blocks` > 0 (a tuned or fixed count) splits the steps over
+    // that many blocks instead (the results do not depend on the split)
     const long long W = (long long)t.ntz * t.ntk * a.g.nx;
-    long long G = forced > 0 ? forced : resident_blocks(k, 64 * TK);
+    long long G = blocks > 0 ? blocks : resident_blocks(k, 64 * TK);
     if (G <= 0) return hipErrorInvalidDeviceFunction;
-    if (forced <= 0) G = std::min(G, std::max(1LL, W / MIN_STEPS));
+    if (blocks <= 0) G = std::min(G, std::max(1LL, W / MIN_STEPS));
     G = std::min(G, W);
     t.nblocks = (int)G;
     const dim3 grid((unsigned)G), block(TZ, TK);
@@ -540,10 +539,33 @@ bool stage_fits_32bit(const GridArgs& g, int dtype) {
     return state_bytes_of(g, es) < (1ull << 32) && 7ull * (unsigned long long)g.stride * es < (1ull << 32);
 }
 
-hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s, bool kinematic) {
+hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s, bool kinematic, int blocks) {
     if (dtype == EGB_F64)
-        return kinematic ? launch_stage_t<double, 8, true>(a, stage, s) : launch_stage_t<double, 8, false>(a, stage, s);
-    return kinematic ? launch_stage_t<float, 16, true>(a, stage, s) : launch_stage_t<float, 12, false>(a, stage, s);
+        return kinematic ? launch_stage_t<double, 8, true>(a, stage, s, blocks)
+                         : launch_stage_t<double, 8, false>(a, stage, s, blocks);
+    return kinematic ? launch_stage_t<float, 16, true>(a, stage, s, blocks)
+                     : launch_stage_t<float, 12, false>(a, stage, s, blocks);
+}
+
+template <typename R, int TK, bool KIN>
+void stage_limits_t(const GridArgs& g, long long& resident, long long& work) {
+    resident = resident_blocks((const void*)k_stage<R, 0, TK, KIN>, 64 * TK);
+    work = (long long)((g.nz + TZ - 1) / TZ) * ((g.nth + TK - 1) / TK) * g.nx;
+}
+
+void stage_limits(const GridArgs& g, int dtype, bool kinematic, long long& resident, long long& work) {
+    if (dtype == EGB_F64) {
+        if (kinematic) stage_limits_t<double, 8, true>(g, resident, work);
+        else stage_limits_t<double, 8, false>(g, resident, work);
+    } else {
+        if (kinematic) stage_limits_t<float, 16, true>(g, resident, work);
+        else stage_limits_t<float, 12, false>(g, resident, work);
+    }
+}
+
+long long batched_resident(int dtype) {
+    return dtype == EGB_F64 ? resident_blocks((const void*)k_stage_batched<double, 0, 8>, 64 * 8)
+                            : resident_blocks((const void*)k_stage_batched<float, 0, 12>, 64 * 12);
 }
 
 }  // namespace egb

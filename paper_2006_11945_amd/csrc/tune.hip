@@ -1,0 +1,137 @@
+// Launch-shape tuning.  The stage kernels (forward, kinematic, reverse and
+// batched) split the (tile, x) steps of their grids into one contiguous
+// range per block, so the number of blocks decides only how the work is
+// spread over the chip: every count gives bit-identical results.  The
+// default is one round of resident blocks; a process-wide cache keyed by
+// (operation, grid shape(s), dtype, device) holds a count fixed by the
+// caller or found by the autotuner, which times stage-0 launches (they read
+// the state and write only the workspace) at a few counts around one round.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "egb_internal.h"
+
+namespace egb {
+namespace {
+
+struct TuneKey {
+    int op, dtype, dev;
+    unsigned long long shape;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(op, dtype, dev, shape) < std::tie(o.op, o.dtype, o.dev, o.shape);
+    }
+};
+
+std::mutex tune_mu;
+std::map<TuneKey, int>& tune_table() {
+    static std::map<TuneKey, int> t;
+    return t;
+}
+
+// FNV-1a over the 8 bytes of v
+unsigned long long fnv_mix(unsigned long long h, unsigned long long v) {
+    for (int i = 0; i < 8; ++i) {
+        h ^= (v >> (8 * i)) & 0xffull;
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+constexpr unsigned long long FNV0 = 0xcbf29ce484222325ull;
+
+// The default count and 1/2, 3/4, 5/4, 3/2, 2 and 3 rounds of resident
+// blocks, within [1, work], each once.
+std::vector<int> block_candidates(long long resident, long long work, long long dflt) {
+    std::vector<int> c;
+    auto add = [&](long long b) {
+        b = std::max(1LL, std::min(b, work));
+        if (std::find(c.begin(), c.end(), (int)b) == c.end()) c.push_back((int)b);
+    };
+    add(dflt);
+    for (int q : {2, 3, 4, 5, 6, 8, 12}) add(resident * q / 4);
+    return c;
+}
+
+// Average time of `reps` launches of `launch(blocks)` on `s` after one
+// untimed launch, for every candidate; the fastest candidate.
+template <typename F>
+hipError_t pick_fastest(const std::vector<int>& cand, int reps, hipStream_t s, F launch, int& best) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best_ms = 0.0f;
+    best = 0;
+    for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
+        e = launch(cand[i]);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch(cand[i]);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && (best == 0 || ms < best_ms)) {
+            best = cand[i];
+            best_ms = ms;
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    return e;
+}
+
+}  // namespace
+
+unsigned long long grid_shape_key(const egb_grid& g) {
+    return fnv_mix(fnv_mix(fnv_mix(FNV0, (unsigned)g.nx), (unsigned)g.nz), (unsigned)g.nth);
+}
+
+unsigned long long batch_shape_key(const egb_problem* p, int n) {
+    unsigned long long h = fnv_mix(FNV0, (unsigned)n);
+    for (int i = 0; i < n; ++i) h = fnv_mix(h, grid_shape_key(p[i].grid));
+    return h;
+}
+
+int tuned_blocks(int op, unsigned long long shape, int dtype) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lock(tune_mu);
+    const auto it = tune_table().find(TuneKey{op, dtype, dev, shape});
+    return it == tune_table().end() ? 0 : it->second;
+}
+
+hipError_t set_tuned_blocks(int op, unsigned long long shape, int dtype, int blocks) {
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(tune_mu);
+    const TuneKey k{op, dtype, dev, shape};
+    if (blocks <= 0) tune_table().erase(k);
+    else tune_table()[k] = blocks;
+    return hipSuccess;
+}
+
+hipError_t tune_stage(const StageArgs& a, int dtype, bool kinematic, int reps, hipStream_t s, int& best) {
+    long long resident = 0, work = 0;
+    stage_limits(a.g, dtype, kinematic, resident, work);
+    if (resident <= 0) return hipErrorInvalidDeviceFunction;
+    const long long dflt = std::min(resident, std::max(1LL, work / 16));
+    const auto cand = block_candidates(resident, work, dflt);
+    return pick_fastest(cand, reps, s, [&](int b) { return launch_stage(a, dtype, 0, s, kinematic, b); }, best);
+}
+
+hipError_t tune_batched(const void* items, const long long* wfirst, int nprob, long long total, int dtype, int reps,
+                        hipStream_t s, int& best) {
+    const long long resident = batched_resident(dtype);
+    if (resident <= 0) return hipErrorInvalidDeviceFunction;
+    const long long dflt = std::min(resident, std::max(1LL, total / 16));
+    const auto cand = block_candidates(resident, total, dflt);
+    return pick_fastest(cand, reps, s,
+                        [&](int b) { return launch_stage_batched(items, wfirst, nprob, total, dtype, 0, b, s); },
+                        best);
+}
+
+}  // namespace egb

@@ -2,9 +2,9 @@
 of a grid into one contiguous range per block, and a range may start or end
 anywhere inside a tile.  The results must not depend on that split: the same
 march and the same misfit gradient computed with different block counts are
-bit-identical (block counts forced through the tuning overrides)."""
-import os
-
+bit-identical (block counts fixed through egb_set_blocks).  The autotuner
+picks one of those counts by timing: tuning leaves the state unchanged and
+a tuned march equals the default one bit for bit."""
 import numpy as np
 import pytest
 import torch
@@ -24,16 +24,19 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def with_env(name, value, fn):
-    old = os.environ.get(name)
-    os.environ[name] = str(value)
+def with_blocks(grid, dtype, ops, blocks, fn):
+    """Run fn with `blocks` per launch for the given operations on grids of
+    this shape, then restore the default."""
+    import paper_2006_11945_amd as egb
+    eg = egb.make_grid(grid, dtype)
+    for op in ops:
+        egb.egb_set_blocks(eg, op, blocks)
+        assert egb.egb_get_blocks(eg, op) == blocks
     try:
         return fn()
     finally:
-        if old is None:
-            del os.environ[name]
-        else:
-            os.environ[name] = old
+        for op in ops:
+            egb.egb_set_blocks(eg, op, 0)
 
 
 def forward_planes(p, dtype, nsteps):
@@ -53,7 +56,7 @@ def test_forward_independent_of_block_split(dtype):
     ref = forward_planes(p, dtype, 6)
     for G in (1, 3, 17, 64, 10000):
         log(f"forward {dtype}: {G} blocks")
-        got = with_env("EGB_STAGE_GRID", G, lambda: forward_planes(p, dtype, 6))
+        got = with_blocks(p.grid, dtype, (0,), G, lambda: forward_planes(p, dtype, 6))
         for k in ref:
             assert np.array_equal(ref[k], got[k]), (G, k)
 
@@ -67,7 +70,69 @@ def test_adjoint_independent_of_block_split(dtype):
     assert J0 > 0
     for G in (1, 5, 144, 10000):
         log(f"adjoint {dtype}: {G} blocks")
-        J, g, _ = with_env("EGB_ADJ_GRID", G, lambda: gpu_gradient(p, rx, t_obs, dtype, r["dt"]))
+        J, g, _ = with_blocks(p.grid, dtype, (1, 2), G, lambda: gpu_gradient(p, rx, t_obs, dtype, r["dt"]))
         assert J == J0
         for a, b in zip(g0, g):
             assert np.array_equal(a, b), G
+
+
+@pytest.mark.parametrize("dtype,op", [("f32", 0), ("f64", 0), ("f32", 1)])
+def test_autotuned_march_equals_default(dtype, op):
+    import paper_2006_11945_amd as egb
+    p = ragged_problem(dtype=dtype, tilt=True)
+    ref = egb.Solver(p, DEV, dtype)
+    ref.velocity()
+    ref.init()
+    s = egb.Solver(p, DEV, dtype)
+    s.velocity()
+    s.init()
+    before = {k: v.clone() for k, v in s.planes().items()}
+    try:
+        b = s.tune(op=op, reps=2)
+        torch.cuda.synchronize()
+        log(f"tuned {dtype} op {op}: {b} blocks")
+        assert b >= 1 and egb.egb_get_blocks(s.eg, op) == b
+        for k, v in s.planes().items():  # tuning leaves the state as it was
+            assert torch.equal(v, before[k]), k
+        step = s.step if op == 0 else s.step_kinematic
+        step(5)
+    finally:
+        egb.egb_set_blocks(s.eg, op, 0)
+    (ref.step if op == 0 else ref.step_kinematic)(5)
+    torch.cuda.synchronize()
+    A, B = gpu_planes(ref), gpu_planes(s)
+    for k in A:
+        assert np.array_equal(A[k], B[k]), k
+
+
+def test_autotuned_batch_equals_default():
+    import paper_2006_11945_amd as egb
+    from tests.test_gpu_batched import small_batch
+    probs = small_batch("f32", seeds=(4, 5, 6))
+    runs = []
+    for tuned in (False, True):
+        ss = []
+        for p in probs:
+            s = egb.Solver(p, DEV, "f32")
+            s.velocity()
+            s.init()
+            ss.append(s)
+        arr = egb.make_problem_array(ss)
+        work = egb.alloc_bytes(egb.workspace_size_batched(arr), DEV)
+        if tuned:
+            before = [gpu_planes(s) for s in ss]
+            b = egb.egb_tune_batched(arr, work, reps=2)
+            log(f"tuned batch: {b} blocks")
+            assert b >= 1
+            for s, bp in zip(ss, before):
+                after = gpu_planes(s)
+                assert all(np.array_equal(after[k], bp[k]) for k in bp)
+        try:
+            egb.egb_liouville_step_batched(arr, 6, work)
+        finally:
+            egb.egb_set_blocks_batched(arr, 0)
+        torch.cuda.synchronize()
+        runs.append([gpu_planes(s) for s in ss])
+    for A, B in zip(*runs):
+        for k in A:
+            assert np.array_equal(A[k], B[k]), k
