@@ -70,7 +70,7 @@ def batched_vs_sequential(nprob, nsteps, lo=128, hi=384):
     cells = sum(p.grid.ncell for p in probs)
     arr = egb.make_problem_array(solvers)
     work = egb.alloc_bytes(egb.workspace_size_batched(arr), "cuda:0")
-    blocks = egb.egb_tune_batched(arr, work)  # launch shape for this batch (results do not depend on it)
+    blocks = egb.egb_tune_batched(arr, work, reps=6)  # launch shape for this batch (results do not depend on it)
     egb.egb_liouville_step_batched(arr, 1, work)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -180,6 +180,7 @@ def paraxial_leg(n, nsrc, nth=256, theta_max=None):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     P.march(nsub)
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
     T = P.pick(xs)
     torch.cuda.synchronize()
@@ -268,7 +269,7 @@ def main():
     s.velocity()
     dt = s.dt_cfl
     s.init()
-    blocks = s.tune()  # stage launch shape for this grid (results do not depend on it)
+    blocks = s.tune(reps=6)  # stage launch shape for this grid (results do not depend on it)
     s.work_beam = egb.alloc_bytes(egb.workspace_size(s.eg, egb.EGB_OP_BEAM), dev)
     out = torch.empty((len(p.omegas), p.grid.nx, p.grid.nz, 2), dtype=torch.float32, device=dev)
     rx_d = torch.as_tensor(rx, device=dev)

@@ -366,17 +366,19 @@ int32_t egb_get_blocks(const egb_grid *g, int32_t op);
 egb_status egb_set_blocks(const egb_grid *g, int32_t op, int32_t blocks);
 
 /* The autotuner for op = EGB_TUNE_STEP or EGB_TUNE_KINEMATIC: times `reps`
- * (>= 1) launches of RK stage 0 at each candidate count (the default and
- * 1/2 to 3 rounds of resident blocks) with HIP events on `stream`, keeps the
- * fastest for this shape and returns it in *blocks.  Arguments as
- * egb_liouville_step (one step); stage 0 reads `state` and writes only
- * `work`, so no buffer of the caller changes.  Synchronises `stream`. */
+ * (>= 1) RK3 steps at each candidate count (the default and 1/2 to 3 rounds
+ * of resident blocks) with HIP events on `stream`, and keeps the fastest for
+ * this shape (the default unless another is faster by more than 1 %),
+ * returned in *blocks.  Arguments as egb_liouville_step; the timed steps
+ * read `state` and write only `work` (the last stage too), so no buffer of
+ * the caller changes.  Synchronises `stream`. */
 egb_status egb_tune_step(const egb_grid *g, const void *vel3d, const egb_source *src, const void *bdata,
                          const void *state, void *work, size_t work_bytes, double dt, int32_t op, int32_t reps,
                          hipStream_t stream, int32_t *blocks);
 
 /* The same for a batch (egb_liouville_step_batched's arguments), keyed by
- * the shapes of all its grids in order.  Synchronises `stream`. */
+ * the shapes of all its grids in order; the timed steps write only `work`.
+ * Synchronises `stream`. */
 egb_status egb_tune_batched(const egb_problem *probs, int32_t nprob, void *work, size_t work_bytes, int32_t reps,
                             hipStream_t stream, int32_t *blocks);
 

@@ -433,7 +433,7 @@ size_t egb_workspace_size_batched(const egb_problem* probs, int32_t nprob) {
 // Validate a batch and write its item table and step offsets into the
 // workspace (item table | wfirst[] | per-problem U1, U2).
 static egb_status prepare_batch(const egb_problem* probs, int32_t nprob, void* work, size_t work_bytes,
-                                char*& d_items, long long*& d_first, long long& total) {
+                                char*& d_items, long long*& d_first, long long& total, bool last_to_work = false) {
     const int dtype = probs[0].grid.dtype;
     if (!work || !aligned16(work)) return EGB_EINVAL;
     if (work_bytes < egb_workspace_size_batched(probs, nprob)) return EGB_EWORKSPACE;
@@ -451,7 +451,7 @@ static egb_status prepare_batch(const egb_problem* probs, int32_t nprob, void* w
         bufs += 2 * sb;
         const long long n = batch_item_fill(items.data() + (size_t)p * batch_item_bytes(), grid_args(q.grid), dtype,
                                             q.vel3d, q.bdata, q.state, U1, U2, q.dt, q.src.xs, q.src.zs,
-                                            q.src.r0 * q.src.r0);
+                                            q.src.r0 * q.src.r0, last_to_work);
         first[p + 1] = first[p] + n;
     }
     total = first[nprob];
@@ -543,10 +543,19 @@ egb_status egb_tune_step(const egb_grid* g, const void* vel3d, const egb_source*
     sa.zs = src->zs;
     sa.r02 = src->r0 * src->r0;
     sa.U0 = state;
-    sa.Uin = state;
-    sa.Uout = work;  // stage 0 writes only its output
+    // one step whose stages write only the workspace: state -> U1 -> U2, and
+    // the last stage (from U2 and the state) into U1 instead of the state
+    void* U1 = work;
+    void* U2 = static_cast<char*>(work) + align256(state_bytes(*g));
+    StageArgs st[3] = {sa, sa, sa};
+    st[0].Uin = state;
+    st[0].Uout = U1;
+    st[1].Uin = U1;
+    st[1].Uout = U2;
+    st[2].Uin = U2;
+    st[2].Uout = U1;
     int best = 0;
-    hipError_t e = tune_stage(sa, g->dtype, op == EGB_TUNE_KINEMATIC, reps, stream, best);
+    hipError_t e = tune_stage(st, g->dtype, op == EGB_TUNE_KINEMATIC, reps, stream, best);
     if (e == hipSuccess) e = set_tuned_blocks(op, grid_shape_key(*g), g->dtype, best);
     if (e != hipSuccess) return hip_status(e);
     *blocks = best;
@@ -562,7 +571,7 @@ egb_status egb_tune_batched(const egb_problem* probs, int32_t nprob, void* work,
     char* d_items = nullptr;
     long long* d_first = nullptr;
     long long total = 0;
-    st = prepare_batch(probs, nprob, work, work_bytes, d_items, d_first, total);
+    st = prepare_batch(probs, nprob, work, work_bytes, d_items, d_first, total, true);
     if (st != EGB_OK) return st;
     int best = 0;
     hipError_t e = tune_batched(d_items, d_first, nprob, total, dtype, reps, stream, best);

@@ -97,8 +97,9 @@ unsigned long long grid_shape_key(const egb_grid& g);
 unsigned long long batch_shape_key(const egb_problem* p, int n);
 int tuned_blocks(int op, unsigned long long shape, int dtype);  // 0: none (the default)
 hipError_t set_tuned_blocks(int op, unsigned long long shape, int dtype, int blocks);  // blocks <= 0: forget
-// the fastest block count for stage 0 of `a` (reads a.Uin / a.U0, writes a.Uout)
-hipError_t tune_stage(const StageArgs& a, int dtype, bool kinematic, int reps, hipStream_t s, int& best);
+// the fastest block count for the three stages a[0..2] of one RK3 step
+// (each writes only its Uout)
+hipError_t tune_stage(const StageArgs (&a)[3], int dtype, bool kinematic, int reps, hipStream_t s, int& best);
 hipError_t tune_batched(const void* items, const long long* wfirst, int nprob, long long total, int dtype, int reps,
                         hipStream_t s, int& best);
 // The stage kernel addresses each array with 32-bit byte offsets.
@@ -106,8 +107,9 @@ bool stage_fits_32bit(const GridArgs& g, int dtype);
 
 // Batched march (see liouville.hip).
 size_t batch_item_bytes();
+// last_to_work: the last stage writes U1 instead of the state (timing runs)
 long long batch_item_fill(void* item, const GridArgs& g, int dtype, const void* vel, const void* bd, void* state,
-                          void* U1, void* U2, double dt, double xs, double zs, double r02);
+                          void* U1, void* U2, double dt, double xs, double zs, double r02, bool last_to_work = false);
 // grid <= 0: one round of resident blocks
 hipError_t launch_stage_batched(const void* items, const long long* wfirst, int nprob, long long total, int dtype,
                                 int stage, int grid, hipStream_t s);

@@ -497,7 +497,7 @@ size_t batch_item_bytes() { return sizeof(BatchItem); }
 
 // Fill the host-side item for one problem; returns its (tile, x) step count.
 long long batch_item_fill(void* item, const GridArgs& g, int dtype, const void* vel, const void* bd, void* state,
-                          void* U1, void* U2, double dt, double xs, double zs, double r02) {
+                          void* U1, void* U2, double dt, double xs, double zs, double r02, bool last_to_work) {
     BatchItem& it = *static_cast<BatchItem*>(item);
     const int tk = dtype == EGB_F64 ? 8 : 12;
     const size_t es = dtype == EGB_F64 ? 8 : 4;
@@ -512,7 +512,7 @@ long long batch_item_fill(void* item, const GridArgs& g, int dtype, const void* 
     t.bd_bytes = (unsigned)bd_bytes_of(g, es);
     it.t = t;
     void* in[3] = {state, U1, U2};
-    void* out[3] = {U1, U2, state};
+    void* out[3] = {U1, U2, last_to_work ? U1 : state};  // U1 is free again in the last stage
     for (int s = 0; s < 3; ++s) {
         it.a[s].g = g;
         it.a[s].vel = vel;

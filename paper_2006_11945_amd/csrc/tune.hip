@@ -4,8 +4,8 @@
 // spread over the chip: every count gives bit-identical results.  The
 // default is one round of resident blocks; a process-wide cache keyed by
 // (operation, grid shape(s), dtype, device) holds a count fixed by the
-// caller or found by the autotuner, which times stage-0 launches (they read
-// the state and write only the workspace) at a few counts around one round.
+// caller or found by the autotuner, which times RK steps whose stages write
+// only the workspace at a few counts around one round.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -56,27 +56,35 @@ std::vector<int> block_candidates(long long resident, long long work, long long 
     return c;
 }
 
-// Average time of `reps` launches of `launch(blocks)` on `s` after one
-// untimed launch, for every candidate; the fastest candidate.
+// Time of `reps` launches of `launch(blocks)` on `s` for every candidate:
+// after 4 reps of the default (clocks and caches settle), two passes over
+// the candidates, in order and then in reverse, each timing summed over
+// both so that a drift during the search favours none.  The first
+// candidate (the default) is kept unless another is faster by more than
+// 1 %, so that timing noise does not move the count.
 template <typename F>
 hipError_t pick_fastest(const std::vector<int>& cand, int reps, hipStream_t s, F launch, int& best) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    float best_ms = 0.0f;
-    best = 0;
-    for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
-        e = launch(cand[i]);
-        if (e == hipSuccess) e = hipEventRecord(e0, s);
-        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch(cand[i]);
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e == hipSuccess && (best == 0 || ms < best_ms)) {
-            best = cand[i];
-            best_ms = ms;
+    const int nc = (int)cand.size();
+    std::vector<float> total(nc, 0.0f);
+    for (int r = 0; r < 4 * reps && e == hipSuccess; ++r) e = launch(cand[0]);
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass)
+        for (int j = 0; j < nc && e == hipSuccess; ++j) {
+            const int i = pass == 0 ? j : nc - 1 - j;
+            e = hipEventRecord(e0, s);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch(cand[i]);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            total[i] += ms;
         }
+    best = cand[0];
+    if (e == hipSuccess) {
+        const int k = (int)(std::min_element(total.begin(), total.end()) - total.begin());
+        if (total[k] < 0.99f * total[0]) best = cand[k];
     }
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
@@ -114,15 +122,25 @@ hipError_t set_tuned_blocks(int op, unsigned long long shape, int dtype, int blo
     return hipSuccess;
 }
 
-hipError_t tune_stage(const StageArgs& a, int dtype, bool kinematic, int reps, hipStream_t s, int& best) {
+hipError_t tune_stage(const StageArgs (&a)[3], int dtype, bool kinematic, int reps, hipStream_t s, int& best) {
     long long resident = 0, work = 0;
-    stage_limits(a.g, dtype, kinematic, resident, work);
+    stage_limits(a[0].g, dtype, kinematic, resident, work);
     if (resident <= 0) return hipErrorInvalidDeviceFunction;
     const long long dflt = std::min(resident, std::max(1LL, work / 16));
     const auto cand = block_candidates(resident, work, dflt);
-    return pick_fastest(cand, reps, s, [&](int b) { return launch_stage(a, dtype, 0, s, kinematic, b); }, best);
+    // one RK3 step: the three stages differ in their inputs and all count
+    return pick_fastest(cand, reps, s,
+                        [&](int b) {
+                            hipError_t e = hipSuccess;
+                            for (int st = 0; st < 3 && e == hipSuccess; ++st)
+                                e = launch_stage(a[st], dtype, st, s, kinematic, b);
+                            return e;
+                        },
+                        best);
 }
 
+// `items` must send the last stage into the workspace (batch_item_fill's
+// last_to_work)
 hipError_t tune_batched(const void* items, const long long* wfirst, int nprob, long long total, int dtype, int reps,
                         hipStream_t s, int& best) {
     const long long resident = batched_resident(dtype);
@@ -130,7 +148,12 @@ hipError_t tune_batched(const void* items, const long long* wfirst, int nprob, l
     const long long dflt = std::min(resident, std::max(1LL, total / 16));
     const auto cand = block_candidates(resident, total, dflt);
     return pick_fastest(cand, reps, s,
-                        [&](int b) { return launch_stage_batched(items, wfirst, nprob, total, dtype, 0, b, s); },
+                        [&](int b) {
+                            hipError_t e = hipSuccess;
+                            for (int st = 0; st < 3 && e == hipSuccess; ++st)
+                                e = launch_stage_batched(items, wfirst, nprob, total, dtype, st, b, s);
+                            return e;
+                        },
                         best);
 }
 
