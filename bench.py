@@ -45,13 +45,15 @@ def parse():
                     help="sources of the 16-source adjoint workload to time (0 skips it)")
     ap.add_argument("--paraxial-sources", type=int, default=16,
                     help="surface sources picked from the paraxial depth march of the same medium (0 skips it)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the launch-shape search (profiling runs: keeps every timed launch at the default)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the run, copy a device buffer of this size (a plain copy kernel of known "
                          "size, to scale HBM byte counters)")
     return ap.parse_args()
 
 
-def batched_vs_sequential(nprob, nsteps, lo=128, hi=384):
+def batched_vs_sequential(nprob, nsteps, lo=128, hi=384, tune=True):
     """`nprob` independent VTI problems with per-axis sizes uniform in lo..hi:
     one graph-captured batched march of all of them against marching them
     one after another with the single-problem call (same GPU, same steps)."""
@@ -70,7 +72,8 @@ def batched_vs_sequential(nprob, nsteps, lo=128, hi=384):
     cells = sum(p.grid.ncell for p in probs)
     arr = egb.make_problem_array(solvers)
     work = egb.alloc_bytes(egb.workspace_size_batched(arr), "cuda:0")
-    blocks = egb.egb_tune_batched(arr, work, reps=6)  # launch shape for this batch (results do not depend on it)
+    # launch shape for this batch (results do not depend on it); 0 = the default
+    blocks = egb.egb_tune_batched(arr, work, reps=6) if tune else 0
     egb.egb_liouville_step_batched(arr, 1, work)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -269,7 +272,8 @@ def main():
     s.velocity()
     dt = s.dt_cfl
     s.init()
-    blocks = s.tune(reps=6)  # stage launch shape for this grid (results do not depend on it)
+    # stage launch shape for this grid (results do not depend on it)
+    blocks = egb.egb_get_blocks(s.eg, egb.EGB_TUNE_STEP) if args.no_tune else s.tune(reps=6)
     s.work_beam = egb.alloc_bytes(egb.workspace_size(s.eg, egb.EGB_OP_BEAM), dev)
     out = torch.empty((len(p.omegas), p.grid.nx, p.grid.nz, 2), dtype=torch.float32, device=dev)
     rx_d = torch.as_tensor(rx, device=dev)
@@ -332,9 +336,10 @@ def main():
     del s, out
     torch.cuda.empty_cache()
     if args.batched_steps > 0:
-        res["batched"] = batched_vs_sequential(args.batched_problems, args.batched_steps)
+        res["batched"] = batched_vs_sequential(args.batched_problems, args.batched_steps, tune=not args.no_tune)
         # many small problems: one problem alone cannot fill the chip
-        res["batched_small"] = batched_vs_sequential(256, 4 * args.batched_steps, lo=32, hi=96)
+        res["batched_small"] = batched_vs_sequential(256, 4 * args.batched_steps, lo=32, hi=96,
+                                                     tune=not args.no_tune)
         torch.cuda.empty_cache()
     if args.adjoint_sources > 0:
         res["adjoint"] = adjoint_vs_forward(args.adjoint_sources, args.rk_steps, args.n)
