@@ -62,3 +62,46 @@ def test_batched_equals_single_and_oracle(dtype):
     for name in O:
         sc = max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())
         assert rel_err(G[name], O[name], sc) < tol, name
+
+
+def test_full_size_batch_equals_single_problems():
+    """The benchmark's batch (64 independent VTI problems, every axis drawn
+    from 128..384, 1.1e9 cells) in its launch configuration: two steps of the
+    batched march, then each problem must equal its own single-problem march
+    bit for bit (compared on the GPU, one problem at a time), and the
+    smallest problem the oracle."""
+    import paper_2006_11945_amd as egb
+
+    probs = W.batch_uneven(nprob=64, nsteps=2)
+    log("full-size batch: %d problems, %.3g cells" % (len(probs), sum(p.grid.ncell for p in probs)))
+    batch = []
+    for p in probs:
+        s = egb.Solver(p, "cuda:0")
+        s.work_step = None  # the batched march brings its own workspace
+        s.velocity()
+        s.init()
+        batch.append(s)
+    arr = egb.make_problem_array(batch)
+    work = egb.alloc_bytes(egb.workspace_size_batched(arr), "cuda:0")
+    egb.egb_liouville_step_batched(arr, 2, work)
+    torch.cuda.synchronize()
+    del work
+    torch.cuda.empty_cache()
+    for i, (p, b) in enumerate(zip(probs, batch)):
+        s = egb.Solver(p, "cuda:0")
+        s.velocity()
+        assert s.dt_cfl == b.dt_cfl
+        s.init()
+        s.step(2)
+        torch.cuda.synchronize()
+        for k, v in s.planes().items():
+            assert torch.equal(v, b.planes()[k]), (i, k)
+        del s
+    small = min(range(len(probs)), key=lambda i: probs[i].grid.ncell)
+    p = probs[small]
+    log(f"  oracle on problem {small}: {p.grid.nx}x{p.grid.nz}x{p.grid.nth}")
+    o = oracle.solve(p, nsteps=2, dt=batch[small].dt_cfl)
+    G, O = gpu_planes(batch[small]), oracle_planes(o["U"])
+    for name in O:
+        sc = max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())
+        assert rel_err(G[name], O[name], sc) < 1e-5, name
