@@ -87,9 +87,13 @@ def test_paraxial_coefficients_and_surface_data(dtype, tilt):
         assert rel_err(L0[name], U0[q], sc) < tol, name
 
 
-@pytest.mark.parametrize("dtype,tilt", [("f64", False), ("f64", True), ("f32", False), ("f32", True)])
-def test_paraxial_march_parity(dtype, tilt):
-    g, med, beta = par_problem(tilt)
+@pytest.mark.parametrize("dtype,tilt,nx,nth", [("f64", False, 42, 36), ("f64", True, 42, 36), ("f32", False, 42, 36),
+                                              ("f32", True, 42, 36), ("f64", True, 200, 37), ("f32", True, 200, 37)])
+def test_paraxial_march_parity(dtype, tilt, nx, nth):
+    # 42 x 36: one partly filled x tile (every tile touches an end); 200 x 37:
+    # x tiles at 0, 64, 128, 192 (the middle two touch no end and take the
+    # plain fill) and a last theta tile of one row
+    g, med, beta = par_problem(tilt, nx=nx, nth=nth)
     o = oracle.psolve(g, med, TMAX, beta)
     log(f"paraxial march {dtype} tilt={tilt} {g.nx}x{g.nz}x{g.nth} nsub={o['nsub']}")
     P = egb().Paraxial(g, med, TMAX, DEV, dtype)

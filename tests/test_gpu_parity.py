@@ -146,6 +146,25 @@ def test_march_parity_f32(tilt):
         assert e <= 1e-4, name
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_march_parity_interior_tiles(dtype):
+    """150 z cells: three 64-cell z tiles, the middle one touching no z end
+    (its halo comes from the state alone), on a tilted heterogeneous grid."""
+    p = ragged_problem(nz=150, tilt=True, nsteps=20, dtype=dtype)
+    log(f"march {dtype} interior tiles grid={p.grid.nx}x{p.grid.nz}x{p.grid.nth} steps={p.nsteps}")
+    o = oracle.solve(p)
+    s = run_gpu(p, dtype, p.nsteps, dt=o["dt"])
+    G, O = gpu_planes(s), oracle_planes(o["U"])
+    for name in O:
+        sc = max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())
+        e = rel_err(G[name], O[name], sc)
+        log(f"  {name}: {e:.3e}")
+        assert e <= (1e-10 if dtype == "f64" else 1e-4), name
+    if dtype == "f32":
+        act = active_mask(p.grid, o["U"])
+        assert (np.abs(G["psi"] - O["psi"]) / O["psi"])[act].max() <= 1e-5
+
+
 def test_homog_iso_64_fp64_full_workload():
     """The plain FP64 workload (64^3 homogeneous isotropic, 100 steps, 20 Hz)."""
     p = W.homog_iso_64()
