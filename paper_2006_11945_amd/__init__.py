@@ -32,8 +32,8 @@ PAR_PLANES = ("X", "vartheta", "ReC", "ImC", "ReB", "ImB", "phase", "tau")   # p
 PVEL_PLANES = ("u", "w", "Stau", "A11", "A12", "A21", "A22")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2006_11945_amd/build.py` "
-                      "(or __graft_entry__.build()); there is no CPU fallback")
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2006_11945_amd/build.py`; "
+                      "there is no CPU fallback")
 
 
 class EgbGrid(ctypes.Structure):

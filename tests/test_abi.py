@@ -23,7 +23,7 @@ def declared_symbols():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        pytest.fail("libegb.so not built (run __graft_entry__.build())")
+        pytest.fail("libegb.so not built (run python paper_2006_11945_amd/build.py)")
     return ctypes.CDLL(LIB)
 
 
