@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 FLOP_WENO = 80
 FLOP_CELL_STAGE = 18 * FLOP_WENO + 6 * 6 + 3 + 17 + 30
 PEAK_FP32_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 excluded
+PEAK_HBM_GBPS = 8000.0    # HBM3E spec
 
 
 def parse():
@@ -211,9 +212,10 @@ def paraxial_leg(n, nsrc, nth=256, theta_max=None):
 STAGE_SOURCES = ("liouville.hip", "stage_common.h", "egb_device.h")
 
 
-def measured_traffic(n):
-    """HBM bytes per stage launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs, only while the kernel sources are unchanged since."""
+def measured_counters(n):
+    """The committed rocprofv3 record of the stage kernel (HBM bytes per
+    launch from FETCH_SIZE / WRITE_SIZE, VALU figures from the SQ counters),
+    only while the kernel sources are unchanged since; else None."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "k_stage_vti256_traffic.json")
@@ -222,7 +224,27 @@ def measured_traffic(n):
     rec = json.load(open(path))
     csrc = os.path.join(ROOT, "paper_2006_11945_amd", "csrc")
     src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in STAGE_SOURCES)
-    return rec["hbm_bytes_per_launch"] if hashlib.sha256(src).hexdigest() == rec["source_sha256"] else None
+    return rec if hashlib.sha256(src).hexdigest() == rec["source_sha256"] else None
+
+
+def copy_bandwidth(mib=1024, reps=5):
+    """Device-to-device copy of `mib` MiB (read + write) timed with HIP
+    events: the practical HBM ceiling next to the 8 TB/s spec."""
+    import torch
+
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbps = 2 * (mib << 20) * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbps
 
 
 def cpu_baseline(problem):
@@ -309,6 +331,9 @@ def main():
     launches = 3 * p.nsteps
     stage_ms = float(np.mean(march_ms)) / launches
     achieved = cells * FLOP_CELL_STAGE / (stage_ms * 1e-3) / 1e12
+    rec = measured_counters(args.n)
+    copy_gbps = copy_bandwidth()  # after the timed region
+    hbm_gbps = None if rec is None else rec["hbm_bytes_per_launch"] / (stage_ms * 1e-3) / 1e9
     res = {
         "metric": "phase-space cell-updates/s",
         "value": value,
@@ -327,9 +352,14 @@ def main():
                    "grid": [p.grid.nx, p.grid.nz, p.grid.nth], "rk3_steps": p.nsteps,
                    "frequencies": len(p.omegas), "receivers": 128, "psi_dtype": "f64"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(args.n),
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None if rec is None else rec["hbm_bytes_per_launch"],
                      "kernel": "k_stage (one SSP-RK3 stage)", "avg_launch_ms": stage_ms, "blocks_per_launch": blocks,
-                     "flop_per_cell_stage": FLOP_CELL_STAGE},
+                     "flop_per_cell_stage": FLOP_CELL_STAGE,
+                     # HBM side (counters x live launch time) against the spec and a measured device copy
+                     "hbm_GBps": hbm_gbps, "hbm_frac_of_8TBps": None if rec is None else hbm_gbps / PEAK_HBM_GBPS,
+                     "copy_GBps": copy_gbps, "hbm_frac_of_copy": None if rec is None else hbm_gbps / copy_gbps,
+                     "valu_instr_per_cell_stage": None if rec is None else rec.get("valu_instr_per_cell_stage"),
+                     "valu_busy": None if rec is None else rec.get("valu_busy")},
         "march_ms": float(np.mean(march_ms)),
         "march_cell_updates_per_s": cells * p.nsteps / (float(np.mean(march_ms)) * 1e-3),
     }
