@@ -146,3 +146,21 @@ def test_launch_tuning_arguments_are_validated_before_any_device_call():
                            egb.EGB_TUNE_STEP, 3, None, ctypes.byref(out)) == egb.EGB_EWORKSPACE
     assert L.egb_tune_batched(None, 0, P(256), 1 << 30, 3, None, ctypes.byref(out)) == egb.EGB_EINVAL
     assert L.egb_set_blocks_batched(None, 1, 4) == egb.EGB_EINVAL
+
+
+def test_header_compiles_as_c(tmp_path):
+    """include/egb.h is a C header: a C99 translation unit that includes it
+    (and calls nothing) compiles without a warning from the header."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "uses_egb.c"
+    src.write_text('#include "egb.h"\nint main(void) { egb_grid g; (void)g; return (int)EGB_TUNE_STEP; }\n')
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-fsyntax-only", "-D__HIP_PLATFORM_AMD__",
+                        "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include", str(src)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    assert "egb.h" not in r.stderr, r.stderr
