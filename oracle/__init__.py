@@ -57,14 +57,15 @@ def lib():
         L.oc_weno.argtypes = [P, i]; L.oc_weno.restype = d
         L.oc_march.argtypes = [i, i, i, d, d, d, d, P, d, d, d, P, P, d, i]
         L.oc_beam_sum.argtypes = [i, i, i, d, d, d, d, P, P, d, i, P, P, i, P]
-        L.oc_pbeam_sum.argtypes = [i, i, i, d, d, d, d, d, P, P, d, i, i, P, i, P]
+        L.oc_pbeam_sum.argtypes = [i, i, i, d, d, d, d, d, P, P, d, i, i, i, P, i, P]
+        L.oc_paper23_drt.argtypes = [P, d, d, P]
         L.oc_qp_polarization.argtypes = [P, d, P]
         L.oc_qp_polarization.restype = None
         L.oc_lin28.argtypes = [d, d, d, d]
         L.oc_lin28.restype = d
         L.oc_pick.argtypes = [i, i, i, d, d, d, d, P, P, i, P]
-        L.oc_pvelocity.argtypes = [i, i, i, d, d, d, P, P, P]
-        L.oc_pinit.argtypes = [i, i, d, d, d, P, d, P]
+        L.oc_pvelocity.argtypes = [i, i, i, d, d, d, i, P, P, P]
+        L.oc_pinit.argtypes = [i, i, d, d, d, P, d, i, P]
         L.oc_pmarch.argtypes = [i, i, i, d, d, d, P, i, P, P]
         L.oc_ppick.argtypes = [i, i, i, d, P, P, i, P]
         _lib = L
@@ -193,11 +194,12 @@ def ptheta(grid, theta_max: float) -> np.ndarray:
     return -theta_max + (np.arange(grid.nth) + 0.5) * dth
 
 
-def pvelocity(grid, tab: np.ndarray, theta_max: float):
-    """(pvel, rate) with rate = max(|u|/dx + |w|/dtheta); raises if V_z <= 0."""
+def pvelocity(grid, tab: np.ndarray, theta_max: float, drt: int = 0):
+    """(pvel, rate) with rate = max(|u|/dx + |w|/dtheta); raises if V_z <= 0.
+    drt = 1: the DRT coefficients of eqs. 21-23 (lateral frame, corrected)."""
     pvel = np.zeros((grid.nz, 7, grid.nth, grid.nx))
     rate = np.zeros(1)
-    rc = lib().oc_pvelocity(grid.nx, grid.nz, grid.nth, grid.dx, grid.dz, float(theta_max), _p(_c(tab)),
+    rc = lib().oc_pvelocity(grid.nx, grid.nz, grid.nth, grid.dx, grid.dz, float(theta_max), int(drt), _p(_c(tab)),
                             _p(pvel), _p(rate))
     if rc != 0:
         raise ValueError("paraxial velocity: V_z <= 0 inside (-theta_max, theta_max)")
@@ -209,9 +211,10 @@ def psubsteps(grid, rate: float, cfl: float = 0.5) -> int:
     return max(1, int(np.ceil(grid.dz * rate / cfl - 1e-12)))
 
 
-def pinit(grid, pvel: np.ndarray, theta_max: float, beta: float) -> np.ndarray:
+def pinit(grid, pvel: np.ndarray, theta_max: float, beta: float, drt: int = 0) -> np.ndarray:
     U = np.zeros((len(PAR_PLANES), grid.nth, grid.nx))
-    lib().oc_pinit(grid.nx, grid.nth, grid.x0, grid.dx, float(theta_max), _p(_c(pvel[0, 0])), float(beta), _p(U))
+    lib().oc_pinit(grid.nx, grid.nth, grid.x0, grid.dx, float(theta_max), _p(_c(pvel[0])), float(beta), int(drt),
+                   _p(U))
     return U
 
 
@@ -228,19 +231,30 @@ def pmarch(grid, pvel: np.ndarray, theta_max: float, U0: np.ndarray, nsub: int, 
     return Uall
 
 
-def pbeam_sum(grid, tab, Uall, theta_max: float, xs: float, omegas, lin: int = 0, comp: int = -1) -> np.ndarray:
+def pbeam_sum(grid, tab, Uall, theta_max: float, xs: float, omegas, lin: int = 0, comp: int = -1,
+              drt: int = 0) -> np.ndarray:
     """Green's function [nw][nx][nz] of a surface source at xs from the
     depth-march levels (row n = depth level n; row 0 left zero); comp =
-    2 i + k >= 0: the (i, k) component of the qP Green's tensor (x = 0, z = 1)."""
+    2 i + k >= 0: the (i, k) component of the qP Green's tensor (x = 0, z = 1);
+    drt = 1 for levels marched with the lateral-frame DRT of eqs. 21-23."""
     om = _c(np.atleast_1d(omegas))
     out = np.zeros((len(om), grid.nx, grid.nz, 2))
     rc = lib().oc_pbeam_sum(grid.nx, grid.nz, grid.nth, grid.x0, grid.z0, grid.dx, grid.dz, float(theta_max),
-                            _p(_c(tab)), _p(_c(Uall)), float(xs), int(lin), int(comp), _p(om), len(om), _p(out))
+                            _p(_c(tab)), _p(_c(Uall)), float(xs), int(lin), int(drt), int(comp), _p(om), len(om),
+                            _p(out))
     if rc == -3:
         raise RuntimeError("oracle beam list overflow")
     if rc != 0:
         raise MemoryError("oc_pbeam_sum")
     return out[..., 0] + 1j * out[..., 1]
+
+
+def paper23_drt(vj: np.ndarray, theta: float, u: float) -> np.ndarray:
+    """(a11, a12, a21, a22) of the lateral-frame DRT of eqs. 21-23 (per unit
+    depth) from a v-jet, the phase angle and u = dx/dz."""
+    a = np.zeros(4)
+    lib().oc_paper23_drt(_p(_c(vj)), float(theta), float(u), _p(a))
+    return a
 
 
 def qp_polarization(ms, theta: float) -> np.ndarray:
@@ -262,12 +276,12 @@ def ppick(grid, Uall: np.ndarray, xs, theta_max: float) -> np.ndarray:
     return T
 
 
-def psolve(grid, medium, theta_max: float, beta: float, xs=(), cfl: float = 0.5):
+def psolve(grid, medium, theta_max: float, beta: float, xs=(), cfl: float = 0.5, drt: int = 0):
     """Table, paraxial velocity, surface data, depth march, picks."""
     tab = medium_table(grid, medium)
-    pvel, rate = pvelocity(grid, tab, theta_max)
+    pvel, rate = pvelocity(grid, tab, theta_max, drt)
     nsub = psubsteps(grid, rate, cfl)
-    U0 = pinit(grid, pvel, theta_max, beta)
+    U0 = pinit(grid, pvel, theta_max, beta, drt)
     Uall = pmarch(grid, pvel, theta_max, U0, nsub)
     T = ppick(grid, Uall, xs, theta_max) if len(np.atleast_1d(xs)) else None
-    return {"tab": tab, "pvel": pvel, "rate": rate, "nsub": nsub, "U": Uall, "T": T}
+    return {"tab": tab, "pvel": pvel, "rate": rate, "nsub": nsub, "U": Uall, "T": T, "drt": drt}

@@ -762,7 +762,40 @@ int oc_pick(int nx, int nz, int nth, double x0, double z0, double dx, double dz,
 #define P_PH 7
 #define NPAR 8
 
-int oc_pvelocity(int nx, int nz, int nth, double dx, double dz, double theta_max, const double *tab,
+/* DRT coefficients of the depth march per unit depth, written in the
+ * lateral frame of eqs. 21-23: C = dx/dgamma at fixed z, B = dp1/dgamma,
+ *   C_z + u C_x + w C_th =  H_xp C + H_pp B,
+ *   B_z + u B_x + w B_th = -H_xx C - H_xp B,
+ * with eq. 23's substitution u1 = cos th + sin th dx/dz for anisotropic
+ * media, N = dx/dz, v the phase velocity at th and v_x, v_xx its lateral
+ * derivatives at fixed th:
+ *   H_pp = v u1^3,  H_xp = u1^2 (v_x / v) N,
+ *   H_xx = (u1 (v v_xx - 3 v_x^2) + u1^3 v_x^2) / v^3.
+ * Two corrections of the printed eqs. 22-23 make this the exact linearised
+ * depth march of an isotropic medium (h = sqrt(1/v^2 - p1^2), C' = -h_px C -
+ * h_pp B, B' = h_xx C + h_xp B): H_pp carries u1^3 (printed u1^2) and the B
+ * term of the C equation is +H_pp B (printed -H_pp B).  a[] = (a11, a12,
+ * a21, a22) in C' = a11 C + a12 B, B' = a21 C + a22 B. */
+static void paper23_drt(const double vj[10], double th, double u, double a[4])
+{
+    double v = vj[0], vx = vj[1], vxx = vj[4];
+    double u1 = cos(th) + sin(th) * u;
+    double hpp = v * u1 * u1 * u1;
+    double hxp = u1 * u1 * (vx / v) * u;
+    double hxx = (u1 * (v * vxx - 3.0 * vx * vx) + u1 * u1 * u1 * vx * vx) / (v * v * v);
+    a[0] = hxp;
+    a[1] = hpp;
+    a[2] = -hxx;
+    a[3] = -hxp;
+}
+
+int oc_paper23_drt(const double *vj, double th, double u, double *a)
+{
+    paper23_drt(vj, th, u, a);
+    return 0;
+}
+
+int oc_pvelocity(int nx, int nz, int nth, double dx, double dz, double theta_max, int drt, const double *tab,
                  double *pvel, double *rate_out)
 {
     (void)dz;
@@ -787,7 +820,13 @@ int oc_pvelocity(int nx, int nz, int nth, double dx, double dz, double theta_max
                 o[0] = V[0] / V[1];
                 o[plane] = V[2] / V[1];
                 o[2 * plane] = 1.0 / V[1];
-                for (int q = 0; q < 4; ++q) o[(3 + q) * plane] = A[q] / V[1];
+                if (drt) { /* eqs. 21-23 in the lateral frame, already per unit depth */
+                    double a[4];
+                    paper23_drt(vj, th, o[0], a);
+                    for (int q = 0; q < 4; ++q) o[(3 + q) * plane] = a[q];
+                } else {   /* the ray-normal pair of the phase-space system divided by dz/dtau */
+                    for (int q = 0; q < 4; ++q) o[(3 + q) * plane] = A[q] / V[1];
+                }
                 double r = fabs(o[0]) / dx + fabs(o[plane]) / dth;
                 if (r > rate) rate = r;
             }
@@ -796,7 +835,14 @@ int oc_pvelocity(int nx, int nz, int nth, double dx, double dz, double theta_max
     return bad ? -1 : 0;
 }
 
-int oc_pinit(int nx, int nth, double x0, double dx, double theta_max, const double *pvel0, double beta, double *U)
+/* Surface data of level 0 (eqs. 20, 24): X = x, vartheta = theta, tau = 0,
+ * C = u1 = cos theta + sin theta u and B = i eps C with the beam parameter
+ * eps = beta (the ray-normal pair: B an angle, B / C in 1/m) or, for the
+ * lateral-frame DRT of eqs. 21-23 (drt = 1, B / C a traveltime Hessian in
+ * s/m^2), eps = beta / v with v = u1 / S_tau the phase velocity (p . V = 1),
+ * i.e. B = i beta S_tau.  pvel0: the coefficient planes of level 0. */
+int oc_pinit(int nx, int nth, double x0, double dx, double theta_max, const double *pvel0, double beta, int drt,
+             double *U)
 {
     double dth = 2.0 * theta_max / nth;
     long plane = (long)nth * nx;
@@ -811,7 +857,7 @@ int oc_pinit(int nx, int nth, double x0, double dx, double theta_max, const doub
             U[P_RC * plane + c] = c0;
             U[P_IC * plane + c] = 0.0;
             U[P_RB * plane + c] = 0.0;
-            U[P_IB * plane + c] = beta * c0;
+            U[P_IB * plane + c] = drt ? beta * pvel0[2 * plane + c] : beta * c0;
             U[P_PH * plane + c] = 0.0;
         }
     }
@@ -954,8 +1000,8 @@ int oc_pmarch(int nx, int nz, int nth, double dx, double dz, double theta_max, c
  * (eqs. 31-32); comp < 0: the scalar sum.  Row 0 (the source row) is 0.
  * Output out[w][ix][n][re/im].                                             */
 int oc_pbeam_sum(int nx, int nz, int nth, double x0, double z0, double dx, double dz, double theta_max,
-                 const double *tab, const double *Uall, double xs, int lin, int comp, const double *omegas, int nw,
-                 double *out)
+                 const double *tab, const double *Uall, double xs, int lin, int drt, int comp, const double *omegas,
+                 int nw, double *out)
 {
     double dth = 2.0 * theta_max / nth, lam = dx / dth, h = 2.0 * dx;
     long plane = (long)nth * nx, lev = NPAR * plane;
@@ -1016,6 +1062,13 @@ int oc_pbeam_sum(int nx, int nz, int nth, double x0, double z0, double dx, doubl
                 double turns = nearbyint((U[P_PH * plane + c] - carg(C)) / (2.0 * M_PI));
                 double sgn = fmod(fabs(turns), 2.0) == 1.0 ? -1.0 : 1.0;
                 r.amp = sgn * csqrt(v / C) * sqrt(u1 / ss) / ss * meas;
+                if (drt) {
+                    /* lateral frame: the row Hessian is B / C itself; the lateral
+                     * displacement of a ray is its normal one over g_z, both started
+                     * at u1, so sqrt(v / C_normal) = sqrt(v / C) sqrt(g_z0 / g_z) */
+                    r.M = B / C;
+                    r.amp *= sqrt(gps[0] / gz);
+                }
                 if (comp >= 0) { /* g_i at the cell (phase angle theta) times g_k at the source (vartheta) */
                     double mr[NFLD], gr[2], gs[2];
                     for (int m = 0; m < NFLD; ++m) mr[m] = tab[(((long)i * nz + n) * NFLD + m) * NTAY];
