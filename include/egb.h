@@ -269,7 +269,23 @@ egb_status egb_adjoint_medium(const egb_grid *g, const egb_medium *m, const void
  * levels of egb_paraxial_level_bytes() each.  The grid's nth counts the
  * theta nodes of the aperture; z0 is the depth of level 0 (the surface).
  * Coefficients `pvel`: [nz][7][stride] in the grid dtype, planes
- * u = V_x/V_z, w = V_theta/V_z, S_tau = 1/V_z, A11..A22 / V_z. */
+ * u = V_x/V_z, w = V_theta/V_z, S_tau = 1/V_z, then the four DRT
+ * coefficients per unit depth (C' = a11 C + a12 B, B' = a21 C + a22 B).
+ *
+ * DRT frame (drt_variant): EGB_DRT_EXACT transports the ray-normal pair of
+ * the phase-space system (A11..A22 / V_z; B an angle).  EGB_DRT_PAPER23
+ * transports the lateral-frame pair of eqs. 21-23 (C = dx, B = dp1 at fixed
+ * depth; B / C is the row traveltime Hessian), with eq. 23's substitution
+ * u1 = cos(theta) + sin(theta) u for anisotropic media: a11 = H_xp,
+ * a12 = H_pp, a21 = -H_xx, a22 = -H_xp, H_pp = v u1^3, H_xp = u1^2 (v_x/v) u,
+ * H_xx = (u1 (v v_xx - 3 v_x^2) + u1^3 v_x^2) / v^3 (v the phase velocity,
+ * v_x, v_xx at fixed theta).  The printed eqs. 21-22 carry u1^2 in H_pp and
+ * -H_pp B in the C equation; u1^3 and +H_pp B make the variant the exact
+ * linearised depth march of an isotropic medium.  It exists to measure eq.
+ * 23's approximation against EGB_DRT_EXACT; the same drt_variant must be
+ * given to egb_paraxial_velocity, egb_paraxial_init and
+ * egb_paraxial_beam_sum. */
+enum { EGB_DRT_EXACT = 0, EGB_DRT_PAPER23 = 1 };
 size_t egb_paraxial_plane_stride(const egb_grid *g);
 size_t egb_paraxial_level_bytes(const egb_grid *g);
 size_t egb_paraxial_vel_bytes(const egb_grid *g);
@@ -285,14 +301,16 @@ egb_status egb_medium_table(const egb_grid *g, const egb_medium *m, void *coeff2
  * 0 < theta_max <= pi/2; EGB_EINVAL if V_z <= 0 at some node (rays that do
  * not go down: beyond the paraxial range of this medium).  work:
  * egb_workspace_size(g, EGB_OP_VELOCITY).  Synchronises `stream` once. */
-egb_status egb_paraxial_velocity(const egb_grid *g, const void *coeff2d, double theta_max, void *pvel,
-                                 double *rate, void *work, size_t work_bytes, hipStream_t stream);
+egb_status egb_paraxial_velocity(const egb_grid *g, const void *coeff2d, double theta_max, int32_t drt_variant,
+                                 void *pvel, double *rate, void *work, size_t work_bytes, hipStream_t stream);
 
 /* Surface data on level 0 (eqs. 20, 24 on the surface line): X = x,
- * vartheta = theta, tau = 0, C = cos(theta) + sin(theta) u, B = i beta C,
- * Phi = 0. */
-egb_status egb_paraxial_init(const egb_grid *g, const void *pvel, double theta_max, double beta, void *levels,
-                             hipStream_t stream);
+ * vartheta = theta, tau = 0, C = cos(theta) + sin(theta) u, Phi = 0, and
+ * B = i eps C with eq. 24's beam parameter read as eps = beta (1/m) for
+ * EGB_DRT_EXACT and eps = beta / v (s/m^2, B / C a traveltime Hessian) for
+ * EGB_DRT_PAPER23, i.e. B = i beta S_tau there. */
+egb_status egb_paraxial_init(const egb_grid *g, const void *pvel, double theta_max, double beta, int32_t drt_variant,
+                             void *levels, hipStream_t stream);
 
 /* March levels 0 -> nz-1: each depth interval is nsub SSP-RK3 steps of
  * dz/nsub of U_z + u U_x + w U_theta = S (S_tau = 1/V_z, S_(C,B) = A/V_z (C,
@@ -325,15 +343,20 @@ egb_status egb_paraxial_march(const egb_grid *g, const void *pvel, double theta_
  * gives G_ik of the qP Green's tensor (eqs. 31-32): every beam weighted by
  * g_i, the qP polarisation (unit eigenvector of the Christoffel matrix, eq. 4,
  * along the phase direction) at the cell, times g_k at the source for the
- * take-off angle.
+ * take-off angle.  drt_variant names the frame the levels were marched in:
+ * for EGB_DRT_PAPER23 the row Hessian is M = B/C itself and the beam carries
+ * sqrt(g_z0/g_z) (g_z, g_z0: the vertical component of the unit ray
+ * direction at the cell and at the source), which turns the lateral C into
+ * the normal one.
  * In: coeff2d (egb_medium_table), levels (egb_paraxial_march), omegas (HOST
  * float64 [nw], rad/s).  Out: out, complex [nw][nx][nz] (re, im) in the grid
  * dtype, row n = level n (row 0 is 0).  work: egb_workspace_size(g,
  * EGB_OP_PBEAM).  Synchronises `stream` once; EGB_EWORKSPACE if a level's
  * beam list overflowed. */
 egb_status egb_paraxial_beam_sum(const egb_grid *g, const void *coeff2d, const void *levels, double theta_max,
-                                 double xs, int32_t lin_variant, int32_t component, const double *omegas, int32_t nw,
-                                 void *out, void *work, size_t work_bytes, hipStream_t stream);
+                                 double xs, int32_t lin_variant, int32_t drt_variant, int32_t component,
+                                 const double *omegas, int32_t nw, void *out, void *work, size_t work_bytes,
+                                 hipStream_t stream);
 
 /* First arrivals of nsrc surface sources at every (x_i, z_n): roots in theta
  * of X - x_s between adjacent nodes whose take-off angles vartheta lie inside

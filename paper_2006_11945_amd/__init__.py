@@ -95,11 +95,11 @@ def _load():
                  "egb_beam_sum", "egb_pick_receivers"):
         getattr(L, name).restype = ctypes.c_int
     L.egb_medium_table.argtypes = [G, M, vp, vp]
-    L.egb_paraxial_velocity.argtypes = [G, vp, d, vp, dp, vp, sz, vp]
-    L.egb_paraxial_init.argtypes = [G, vp, d, d, vp, vp]
+    L.egb_paraxial_velocity.argtypes = [G, vp, d, i32, vp, dp, vp, sz, vp]
+    L.egb_paraxial_init.argtypes = [G, vp, d, d, i32, vp, vp]
     L.egb_paraxial_march.argtypes = [G, vp, d, i32, vp, vp, sz, vp]
     L.egb_paraxial_pick.argtypes = [G, vp, d, vp, i32, vp, vp]
-    L.egb_paraxial_beam_sum.argtypes = [G, vp, vp, d, d, i32, i32, dp, i32, vp, vp, sz, vp]
+    L.egb_paraxial_beam_sum.argtypes = [G, vp, vp, d, d, i32, i32, i32, dp, i32, vp, vp, sz, vp]
     for name in ("egb_medium_table", "egb_paraxial_velocity", "egb_paraxial_init", "egb_paraxial_march",
                  "egb_paraxial_pick", "egb_paraxial_beam_sum"):
         getattr(L, name).restype = ctypes.c_int
@@ -250,17 +250,20 @@ def egb_medium_table(eg, medium: "DeviceMedium", coeff2d, stream=None):
                                                      _stream(stream)))
 
 
-def egb_paraxial_velocity(eg, coeff2d, theta_max: float, pvel, work, stream=None) -> float:
+EGB_DRT_EXACT, EGB_DRT_PAPER23 = 0, 1
+
+
+def egb_paraxial_velocity(eg, coeff2d, theta_max: float, pvel, work, stream=None, drt: int = EGB_DRT_EXACT) -> float:
     rate = ctypes.c_double(0.0)
-    rc = _lib.egb_paraxial_velocity(ctypes.byref(eg), _ptr(coeff2d), float(theta_max), _ptr(pvel), ctypes.byref(rate),
-                                    _ptr(work), work.numel(), _stream(stream))
+    rc = _lib.egb_paraxial_velocity(ctypes.byref(eg), _ptr(coeff2d), float(theta_max), int(drt), _ptr(pvel),
+                                    ctypes.byref(rate), _ptr(work), work.numel(), _stream(stream))
     _check("egb_paraxial_velocity", rc)
     return rate.value
 
 
-def egb_paraxial_init(eg, pvel, theta_max: float, beta: float, levels, stream=None):
+def egb_paraxial_init(eg, pvel, theta_max: float, beta: float, levels, stream=None, drt: int = EGB_DRT_EXACT):
     _check("egb_paraxial_init", _lib.egb_paraxial_init(ctypes.byref(eg), _ptr(pvel), float(theta_max), float(beta),
-                                                       _ptr(levels), _stream(stream)))
+                                                       int(drt), _ptr(levels), _stream(stream)))
 
 
 def egb_paraxial_march(eg, pvel, theta_max: float, nsub: int, levels, work, stream=None):
@@ -276,11 +279,11 @@ def egb_paraxial_pick(eg, levels, theta_max: float, xs, T, stream=None):
 
 
 def egb_paraxial_beam_sum(eg, coeff2d, levels, theta_max: float, xs: float, lin: int, comp: int, omegas, out, work,
-                          stream=None):
+                          stream=None, drt: int = EGB_DRT_EXACT):
     om = np.ascontiguousarray(np.atleast_1d(np.asarray(omegas, dtype=np.float64)))
     rc = _lib.egb_paraxial_beam_sum(ctypes.byref(eg), _ptr(coeff2d), _ptr(levels), float(theta_max), float(xs),
-                                    int(lin), int(comp), om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(om),
-                                    _ptr(out), _ptr(work), work.numel(), _stream(stream))
+                                    int(lin), int(drt), int(comp), om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    len(om), _ptr(out), _ptr(work), work.numel(), _stream(stream))
     _check("egb_paraxial_beam_sum", rc)
 
 
@@ -470,12 +473,15 @@ def paraxial_level_views(eg, levels: torch.Tensor, n: int) -> dict:
 class Paraxial:
     """Buffers and call sequence of the paraxial depth march for one medium:
     medium table, coefficients, surface data, march, first-arrival picks of
-    any number of surface sources.  theta_max: half aperture (rad)."""
+    any number of surface sources.  theta_max: half aperture (rad); drt: the
+    DRT frame (EGB_DRT_EXACT, or EGB_DRT_PAPER23 for eqs. 21-23)."""
 
-    def __init__(self, grid, medium, theta_max: float, device="cuda", dtype: str = "f32"):
+    def __init__(self, grid, medium, theta_max: float, device="cuda", dtype: str = "f32",
+                 drt: int = EGB_DRT_EXACT):
         self.device = torch.device(device)
         self.eg = make_grid(grid, dtype)
         self.theta_max = float(theta_max)
+        self.drt = int(drt)
         self.medium = DeviceMedium.from_numpy(medium, self.device)
         eg = self.eg
         self.coeff2d = alloc_bytes(coeff2d_bytes(eg), self.device)
@@ -488,7 +494,8 @@ class Paraxial:
 
     def velocity(self, stream=None) -> float:
         egb_medium_table(self.eg, self.medium, self.coeff2d, stream)
-        self.rate = egb_paraxial_velocity(self.eg, self.coeff2d, self.theta_max, self.pvel, self.work_vel, stream)
+        self.rate = egb_paraxial_velocity(self.eg, self.coeff2d, self.theta_max, self.pvel, self.work_vel, stream,
+                                          self.drt)
         return self.rate
 
     def substeps(self, cfl: float = 0.5) -> int:
@@ -496,7 +503,7 @@ class Paraxial:
         return max(1, int(np.ceil(self.eg.dz * self.rate / cfl - 1e-12)))
 
     def init(self, beta: float, stream=None):
-        egb_paraxial_init(self.eg, self.pvel, self.theta_max, beta, self.levels, stream)
+        egb_paraxial_init(self.eg, self.pvel, self.theta_max, beta, self.levels, stream, self.drt)
 
     def march(self, nsub: Optional[int] = None, stream=None):
         egb_paraxial_march(self.eg, self.pvel, self.theta_max, self.substeps() if nsub is None else nsub,
@@ -520,7 +527,7 @@ class Paraxial:
         if out is None:
             out = torch.empty((len(om), self.eg.nx, self.eg.nz, 2), dtype=real_dtype(self.eg), device=self.device)
         egb_paraxial_beam_sum(self.eg, self.coeff2d, self.levels, self.theta_max, xs, lin, comp, om, out,
-                              self.work_beam, stream)
+                              self.work_beam, stream, self.drt)
         return out
 
     def level(self, n: int) -> dict:

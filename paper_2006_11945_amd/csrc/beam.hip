@@ -394,6 +394,14 @@ __global__ __launch_bounds__(256) void k_pbeam_compact(PBeamArgs a) {
     r.p = a.lin == EGB_LIN_PAPER28 ? lin28(sn, cs, va.V[0] / va.V[1], v) : sn / v;
     r.Mre = Mnre * hzr * hzr + 2.0 * eq * hxr * hzr + gq * hxr * hxr;
     r.Mim = Mnim * hzr * hzr;
+    if (a.drt == EGB_DRT_PAPER23) {
+        // lateral frame: the row Hessian is B / C itself, and the lateral
+        // displacement is the normal one over g_z (both started at u1), so
+        // sqrt(v / C_normal) = sqrt(v / C) sqrt(g_z0 / g_z)
+        r.Mre = BCre;
+        r.Mim = BCim;
+        w *= sqrt((vs.V[1] / sqrt(vs.V[0] * vs.V[0] + vs.V[1] * vs.V[1])) / hzr);
+    }
     r.are = w * sqre;
     r.aim = w * sqim;
     r.pad = 0.0;

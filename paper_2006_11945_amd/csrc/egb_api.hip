@@ -274,16 +274,19 @@ size_t egb_paraxial_vel_bytes(const egb_grid* g) { return grid_ok(g) ? paraxial_
 
 static bool theta_max_ok(double t) { return isfinite(t) && t > 0.0 && t <= 1.5707963267948966; }
 
-egb_status egb_paraxial_velocity(const egb_grid* g, const void* coeff2d, double theta_max, void* pvel,
-                                 double* rate_out, void* work, size_t work_bytes, hipStream_t stream) {
-    if (!grid_ok(g) || !coeff2d || !pvel || !rate_out || !work || !theta_max_ok(theta_max)) return EGB_EINVAL;
+static bool drt_ok(int32_t drt) { return drt == EGB_DRT_EXACT || drt == EGB_DRT_PAPER23; }
+
+egb_status egb_paraxial_velocity(const egb_grid* g, const void* coeff2d, double theta_max, int32_t drt_variant,
+                                 void* pvel, double* rate_out, void* work, size_t work_bytes, hipStream_t stream) {
+    if (!grid_ok(g) || !coeff2d || !pvel || !rate_out || !work || !theta_max_ok(theta_max) || !drt_ok(drt_variant))
+        return EGB_EINVAL;
     if (!aligned16(coeff2d) || !aligned16(pvel) || !aligned16(work)) return EGB_EINVAL;
     if (work_bytes < egb_workspace_size(g, EGB_OP_VELOCITY)) return EGB_EWORKSPACE;
     unsigned long long* rate = static_cast<unsigned long long*>(work);
     hipError_t e = launch_fill_u64(rate, 1, 0ull, stream);
     if (e == hipSuccess)
-        e = launch_pvelocity(grid_args(*g), g->dtype, theta_max, static_cast<const double*>(coeff2d), pvel,
-                             (long long)paraxial_stride(*g), rate, stream);
+        e = launch_pvelocity(grid_args(*g), g->dtype, theta_max, drt_variant, static_cast<const double*>(coeff2d),
+                             pvel, (long long)paraxial_stride(*g), rate, stream);
     unsigned long long bits = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&bits, rate, sizeof(bits), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -295,13 +298,14 @@ egb_status egb_paraxial_velocity(const egb_grid* g, const void* coeff2d, double 
     return EGB_OK;
 }
 
-egb_status egb_paraxial_init(const egb_grid* g, const void* pvel, double theta_max, double beta, void* levels,
-                             hipStream_t stream) {
-    if (!grid_ok(g) || !pvel || !levels || !theta_max_ok(theta_max) || !isfinite(beta) || !(beta > 0.0))
+egb_status egb_paraxial_init(const egb_grid* g, const void* pvel, double theta_max, double beta, int32_t drt_variant,
+                             void* levels, hipStream_t stream) {
+    if (!grid_ok(g) || !pvel || !levels || !theta_max_ok(theta_max) || !isfinite(beta) || !(beta > 0.0) ||
+        !drt_ok(drt_variant))
         return EGB_EINVAL;
     if (!aligned16(pvel) || !aligned16(levels)) return EGB_EINVAL;
     return hip_status(launch_pinit(g->nx, g->nth, (long long)paraxial_stride(*g), g->x0, g->dx, theta_max, beta,
-                                   g->dtype, pvel, levels, stream));
+                                   drt_variant, g->dtype, pvel, levels, stream));
 }
 
 egb_status egb_paraxial_march(const egb_grid* g, const void* pvel, double theta_max, int32_t nsub, void* levels,
@@ -354,11 +358,12 @@ egb_status egb_paraxial_march(const egb_grid* g, const void* pvel, double theta_
 }
 
 egb_status egb_paraxial_beam_sum(const egb_grid* g, const void* coeff2d, const void* levels, double theta_max,
-                                 double xs, int32_t lin_variant, int32_t component, const double* omegas, int32_t nw,
-                                 void* out, void* work, size_t work_bytes, hipStream_t stream) {
+                                 double xs, int32_t lin_variant, int32_t drt_variant, int32_t component,
+                                 const double* omegas, int32_t nw, void* out, void* work, size_t work_bytes,
+                                 hipStream_t stream) {
     if (!grid_ok(g) || !coeff2d || !levels || !theta_max_ok(theta_max) || !isfinite(xs) || !omegas || nw < 1 ||
-        !out || !work || (lin_variant != EGB_LIN_EXACT && lin_variant != EGB_LIN_PAPER28) || component < -1 ||
-        component > 3)
+        !out || !work || (lin_variant != EGB_LIN_EXACT && lin_variant != EGB_LIN_PAPER28) || !drt_ok(drt_variant) ||
+        component < -1 || component > 3)
         return EGB_EINVAL;
     if (!aligned16(coeff2d) || !aligned16(levels) || !aligned16(out) || !aligned16(work)) return EGB_EINVAL;
     for (int w = 0; w < nw; ++w)
@@ -379,6 +384,7 @@ egb_status egb_paraxial_beam_sum(const egb_grid* g, const void* coeff2d, const v
     pa.nz = g->nz;
     pa.nth = g->nth;
     pa.lin = lin_variant;
+    pa.drt = drt_variant;
     pa.comp = component;
     pa.cap = cap;
     pa.dx = g->dx;

@@ -146,10 +146,10 @@ struct PStageArgs {
     const void* Uin;
     void* Uout;
 };
-hipError_t launch_pvelocity(const GridArgs& a, int dtype, double theta_max, const double* coeff2d, void* pvel,
-                            long long P, unsigned long long* rate_bits, hipStream_t s);
-hipError_t launch_pinit(int nx, int nth, long long P, double x0, double dx, double theta_max, double beta, int dtype,
-                        const void* pvel, void* level0, hipStream_t s);
+hipError_t launch_pvelocity(const GridArgs& a, int dtype, double theta_max, int drt, const double* coeff2d,
+                            void* pvel, long long P, unsigned long long* rate_bits, hipStream_t s);
+hipError_t launch_pinit(int nx, int nth, long long P, double x0, double dx, double theta_max, double beta, int drt,
+                        int dtype, const void* pvel, void* level0, hipStream_t s);
 hipError_t launch_pstage(const PStageArgs& a, int dtype, int stage, hipStream_t s);
 hipError_t launch_ppick(int nx, int nz, int nth, double theta_max, long long P, int dtype, const void* levels,
                         size_t level_bytes, const double* xs, int nsrc, double* T, hipStream_t s);
@@ -176,6 +176,7 @@ struct PBeamArgs {
     size_t level_bytes;
     long long P;              // level plane stride (elements)
     int nx, nz, nth, lin, comp, cap;  // comp: -1 scalar, else 2 i + k of the Green's tensor
+    int drt;                  // the DRT frame the levels were marched in (EGB_DRT_*)
     double dx, dth, theta_max, xs;
     int* counts;              // [nz rows][nx columns] (columns stay 0)
     void* rows;

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void k_velocity(GridArgs a, const double* C, R
 // layout [nz][7][P] with index k nx + x.  rate: max |u|/dx + |w|/dtheta, +inf
 // where V_z <= 0 (beyond the paraxial range) or not finite.
 template <typename R>
-__global__ __launch_bounds__(256) void k_pvelocity(GridArgs a, double theta_max, const double* C, R* pvel,
+__global__ __launch_bounds__(256) void k_pvelocity(GridArgs a, double theta_max, int drt, const double* C, R* pvel,
                                                    long long P, unsigned long long* rate_bits) {
     const int ix = blockIdx.x * 64 + threadIdx.x, k = blockIdx.y * 4 + threadIdx.y, n = blockIdx.z;
     double rate = 0.0;
@@ -146,7 +146,24 @@ __global__ __launch_bounds__(256) void k_pvelocity(GridArgs a, double theta_max,
         pvel[c] = (R)u;
         pvel[P + c] = (R)w;
         pvel[2 * P + c] = (R)(1.0 / vz);
-        for (int q = 0; q < 4; ++q) pvel[(3 + q) * P + c] = (R)(r.A[q] / vz);
+        if (drt == EGB_DRT_PAPER23) {
+            // eqs. 21-23 in the lateral frame, per unit depth: u1 = cos + sin u,
+            // H_pp = v u1^3, H_xp = u1^2 (v_x / v) u,
+            // H_xx = (u1 (v v_xx - 3 v_x^2) + u1^3 v_x^2) / v^3 (v_x, v_xx at fixed theta);
+            // C' = H_xp C + H_pp B, B' = -H_xx C - H_xp B
+            double sn, cs;
+            sincos_d(th, &sn, &cs);
+            const double v = J.v, vx = J.g[0], vxx = J.h[0][0];
+            const double u1 = cs + sn * u, u13 = u1 * u1 * u1;
+            const double hxp = u1 * u1 * (vx / v) * u;
+            const double hxx = (u1 * (v * vxx - 3.0 * vx * vx) + u13 * vx * vx) / (v * v * v);
+            pvel[3 * P + c] = (R)hxp;
+            pvel[4 * P + c] = (R)(v * u13);
+            pvel[5 * P + c] = (R)(-hxx);
+            pvel[6 * P + c] = (R)(-hxp);
+        } else {  // the ray-normal pair of the phase-space system divided by dz/dtau
+            for (int q = 0; q < 4; ++q) pvel[(3 + q) * P + c] = (R)(r.A[q] / vz);
+        }
         rate = fabs(u) / a.dx + fabs(w) / dth;
         if (!(vz > 0.0) || !isfinite(rate)) rate = __longlong_as_double(0x7ff0000000000000LL);
     }
@@ -300,13 +317,13 @@ hipError_t launch_velocity(const GridArgs& a, int dtype, const double* C, void* 
     return hipGetLastError();
 }
 
-hipError_t launch_pvelocity(const GridArgs& a, int dtype, double theta_max, const double* C, void* pvel, long long P,
-                            unsigned long long* rate_bits, hipStream_t s) {
+hipError_t launch_pvelocity(const GridArgs& a, int dtype, double theta_max, int drt, const double* C, void* pvel,
+                            long long P, unsigned long long* rate_bits, hipStream_t s) {
     const dim3 grid((a.nx + 63) / 64, (a.nth + 3) / 4, a.nz), block(64, 4);
     if (dtype == EGB_F64)
-        k_pvelocity<double><<<grid, block, 0, s>>>(a, theta_max, C, (double*)pvel, P, rate_bits);
+        k_pvelocity<double><<<grid, block, 0, s>>>(a, theta_max, drt, C, (double*)pvel, P, rate_bits);
     else
-        k_pvelocity<float><<<grid, block, 0, s>>>(a, theta_max, C, (float*)pvel, P, rate_bits);
+        k_pvelocity<float><<<grid, block, 0, s>>>(a, theta_max, drt, C, (float*)pvel, P, rate_bits);
     return hipGetLastError();
 }
 

@@ -222,10 +222,12 @@ __global__ __launch_bounds__(NT) void k_pstage(PStageArgs a) {
 }
 
 // Surface data on level 0: X = x, vartheta = theta, tau = 0,
-// C = cos(theta) + sin(theta) u, B = i beta C, Phi = 0.
+// C = cos(theta) + sin(theta) u, Phi = 0, B = i eps C with eps = beta for
+// the ray-normal pair (B an angle) or beta / v for the lateral-frame pair of
+// eqs. 21-23 (B / C a traveltime Hessian; v = u1 / S_tau, so B = i beta S_tau).
 template <typename R>
 __global__ __launch_bounds__(256) void k_pinit(int nx, int nth, long long P, double x0, double dx, double theta_max,
-                                               double beta, const R* pv, R* U) {
+                                               double beta, int drt, const R* pv, R* U) {
     const int x = blockIdx.x * 64 + threadIdx.x, k = blockIdx.y * 4 + threadIdx.y;
     if (x >= nx || k >= nth) return;
     const double dth = 2.0 * theta_max / nth;
@@ -239,7 +241,7 @@ __global__ __launch_bounds__(256) void k_pinit(int nx, int nth, long long P, dou
     U[Q_RC * P + c] = (R)c0;
     U[Q_IC * P + c] = (R)0;
     U[Q_RB * P + c] = (R)0;
-    U[Q_IB * P + c] = (R)(beta * c0);
+    U[Q_IB * P + c] = (R)(drt == EGB_DRT_PAPER23 ? beta * (double)pv[2 * P + c] : beta * c0);
     U[Q_PH * P + c] = (R)0;
     reinterpret_cast<double*>(U + NPR * P)[c] = 0.0;
 }
@@ -297,14 +299,15 @@ hipError_t launch_pstage(const PStageArgs& a, int dtype, int stage, hipStream_t 
     return dtype == EGB_F64 ? pstage_t<double>(a, stage, s) : pstage_t<float>(a, stage, s);
 }
 
-hipError_t launch_pinit(int nx, int nth, long long P, double x0, double dx, double theta_max, double beta, int dtype,
-                        const void* pvel, void* level0, hipStream_t s) {
+hipError_t launch_pinit(int nx, int nth, long long P, double x0, double dx, double theta_max, double beta, int drt,
+                        int dtype, const void* pvel, void* level0, hipStream_t s) {
     const dim3 grid((nx + 63) / 64, (nth + 3) / 4), block(64, 4);
     if (dtype == EGB_F64)
-        k_pinit<double><<<grid, block, 0, s>>>(nx, nth, P, x0, dx, theta_max, beta, (const double*)pvel,
+        k_pinit<double><<<grid, block, 0, s>>>(nx, nth, P, x0, dx, theta_max, beta, drt, (const double*)pvel,
                                                (double*)level0);
     else
-        k_pinit<float><<<grid, block, 0, s>>>(nx, nth, P, x0, dx, theta_max, beta, (const float*)pvel, (float*)level0);
+        k_pinit<float><<<grid, block, 0, s>>>(nx, nth, P, x0, dx, theta_max, beta, drt, (const float*)pvel,
+                                              (float*)level0);
     return hipGetLastError();
 }
 

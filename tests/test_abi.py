@@ -164,3 +164,19 @@ def test_header_compiles_as_c(tmp_path):
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
     assert "egb.h" not in r.stderr, r.stderr
+
+
+def test_paraxial_drt_variant_is_validated():
+    import paper_2006_11945_amd as egb
+    import workloads as W
+
+    eg = egb.make_grid(W.Grid(nx=40, nz=16, nth=36, dx=10.0, dz=10.0), "f32")
+    P = ctypes.c_void_p
+    L = egb.lib()
+    rate = ctypes.c_double(0.0)
+    assert L.egb_paraxial_velocity(ctypes.byref(eg), P(256), 1.0, 2, P(256), ctypes.byref(rate), P(256), 1 << 30,
+                                   None) == egb.EGB_EINVAL
+    assert L.egb_paraxial_init(ctypes.byref(eg), P(256), 1.0, 1e-4, -1, P(256), None) == egb.EGB_EINVAL
+    om = (ctypes.c_double * 1)(100.0)
+    assert L.egb_paraxial_beam_sum(ctypes.byref(eg), P(256), P(256), 1.0, 200.0, 0, 5, -1, om, 1, P(256), P(256),
+                                   1 << 30, None) == egb.EGB_EINVAL

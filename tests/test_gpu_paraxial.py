@@ -64,13 +64,15 @@ def write_levels(P, U):
             v[name].copy_(torch.as_tensor(U[n, q]).to(v[name].dtype))
 
 
-@pytest.mark.parametrize("dtype,tilt", [("f64", False), ("f32", False), ("f64", True), ("f32", True)])
-def test_paraxial_coefficients_and_surface_data(dtype, tilt):
+@pytest.mark.parametrize("dtype,tilt,drt", [("f64", False, 0), ("f32", False, 0), ("f64", True, 0), ("f32", True, 0),
+                                            ("f64", True, 1), ("f32", True, 1)])
+def test_paraxial_coefficients_and_surface_data(dtype, tilt, drt):
+    # drt = 1: the lateral-frame DRT coefficients of eqs. 21-23 and their surface data
     g, med, beta = par_problem(tilt)
     tab = oracle.medium_table(g, med)
-    pv, rate = oracle.pvelocity(g, tab, TMAX)
-    U0 = oracle.pinit(g, pv, TMAX, beta)
-    P = egb().Paraxial(g, med, TMAX, DEV, dtype)
+    pv, rate = oracle.pvelocity(g, tab, TMAX, drt)
+    U0 = oracle.pinit(g, pv, TMAX, beta, drt)
+    P = egb().Paraxial(g, med, TMAX, DEV, dtype, drt=drt)
     r = P.velocity()
     P.init(beta)
     torch.cuda.synchronize()
@@ -87,16 +89,18 @@ def test_paraxial_coefficients_and_surface_data(dtype, tilt):
         assert rel_err(L0[name], U0[q], sc) < tol, name
 
 
-@pytest.mark.parametrize("dtype,tilt,nx,nth", [("f64", False, 42, 36), ("f64", True, 42, 36), ("f32", False, 42, 36),
-                                              ("f32", True, 42, 36), ("f64", True, 200, 37), ("f32", True, 200, 37)])
-def test_paraxial_march_parity(dtype, tilt, nx, nth):
+@pytest.mark.parametrize("dtype,tilt,nx,nth,drt", [("f64", False, 42, 36, 0), ("f64", True, 42, 36, 0),
+                                                  ("f32", False, 42, 36, 0), ("f32", True, 42, 36, 0),
+                                                  ("f64", True, 200, 37, 0), ("f32", True, 200, 37, 0),
+                                                  ("f64", True, 42, 36, 1), ("f32", True, 42, 36, 1)])
+def test_paraxial_march_parity(dtype, tilt, nx, nth, drt):
     # 42 x 36: one partly filled x tile (every tile touches an end); 200 x 37:
     # x tiles at 0, 64, 128, 192 (the middle two touch no end and take the
-    # plain fill) and a last theta tile of one row
+    # plain fill) and a last theta tile of one row; drt = 1: the DRT of eqs. 21-23
     g, med, beta = par_problem(tilt, nx=nx, nth=nth)
-    o = oracle.psolve(g, med, TMAX, beta)
-    log(f"paraxial march {dtype} tilt={tilt} {g.nx}x{g.nz}x{g.nth} nsub={o['nsub']}")
-    P = egb().Paraxial(g, med, TMAX, DEV, dtype)
+    o = oracle.psolve(g, med, TMAX, beta, drt=drt)
+    log(f"paraxial march {dtype} tilt={tilt} drt={drt} {g.nx}x{g.nz}x{g.nth} nsub={o['nsub']}")
+    P = egb().Paraxial(g, med, TMAX, DEV, dtype, drt=drt)
     P.velocity()
     assert P.substeps() == o["nsub"]
     P.init(beta)
@@ -150,7 +154,10 @@ def test_paraxial_invalid_arguments():
     L = e.lib()
     nul = ctypes.c_void_p(None)
     for t in (0.0, -0.1, 1.6, float("nan")):
-        assert L.egb_paraxial_init(ctypes.byref(P.eg), e._ptr(P.pvel), t, beta, e._ptr(P.levels), nul) == e.EGB_EINVAL
+        assert L.egb_paraxial_init(ctypes.byref(P.eg), e._ptr(P.pvel), t, beta, 0, e._ptr(P.levels),
+                                   nul) == e.EGB_EINVAL
+    assert L.egb_paraxial_init(ctypes.byref(P.eg), e._ptr(P.pvel), TMAX, beta, 2, e._ptr(P.levels),
+                               nul) == e.EGB_EINVAL  # no such DRT frame
     assert L.egb_paraxial_march(ctypes.byref(P.eg), e._ptr(P.pvel), TMAX, 0, e._ptr(P.levels), e._ptr(P.work),
                                 P.work.numel(), nul) == e.EGB_EINVAL
     assert L.egb_paraxial_march(ctypes.byref(P.eg), e._ptr(P.pvel), TMAX, 2, e._ptr(P.levels), e._ptr(P.work),
@@ -210,30 +217,31 @@ def test_paraxial_full_size_first_levels():
     assert torch.isfinite(out).all()
 
 
-@pytest.mark.parametrize("dtype,lin,comp", [("f64", 0, -1), ("f32", 0, -1), ("f32", 1, -1), ("f64", 0, 1),
-                                            ("f32", 0, 0), ("f32", 0, 2), ("f32", 0, 3)])
-def test_paraxial_beam_sum_parity(dtype, lin, comp):
+@pytest.mark.parametrize("dtype,lin,comp,drt", [("f64", 0, -1, 0), ("f32", 0, -1, 0), ("f32", 1, -1, 0),
+                                                ("f64", 0, 1, 0), ("f32", 0, 0, 0), ("f32", 0, 2, 0), ("f32", 0, 3, 0),
+                                                ("f64", 0, -1, 1), ("f32", 0, -1, 1)])
+def test_paraxial_beam_sum_parity(dtype, lin, comp, drt):
     """Green's function from the depth march (eq. 34 over Gamma = {X = x_s}),
     scalar (comp = -1) or a component of the qP Green's tensor, on identical
     input: the oracle's levels, rounded to the storage, written into the GPU
     buffer; relative L2 per frequency 1e-10 (FP64) and 1e-4 (FP32 planes:
     single-precision phase factors)."""
     g, med, beta = par_problem(tilt=True)
-    o = oracle.psolve(g, med, TMAX, beta)
+    o = oracle.psolve(g, med, TMAX, beta, drt=drt)
     U = o["U"].copy()
     if dtype == "f32":
         for q in (0, 1, 3, 4, 5, 6, 7):
             U[:, q] = U[:, q].astype(np.float32).astype(np.float64)
-    P = egb().Paraxial(g, med, TMAX, DEV, dtype)
+    P = egb().Paraxial(g, med, TMAX, DEV, dtype, drt=drt)
     P.velocity()
     write_levels(P, U)
     xs = 0.45 * g.nx * g.dx + 2.0
     om = W.hz([15.0, 40.0])
     out = P.beam(xs, om, lin=lin, comp=comp).cpu().numpy()
     G = out[..., 0] + 1j * out[..., 1]
-    Go = oracle.pbeam_sum(g, o["tab"], U, TMAX, xs, om, lin=lin, comp=comp)
+    Go = oracle.pbeam_sum(g, o["tab"], U, TMAX, xs, om, lin=lin, comp=comp, drt=drt)
     for w in range(len(om)):
         e = np.linalg.norm(G[w] - Go[w]) / np.linalg.norm(Go[w])
-        log(f"  paraxial beam {dtype} lin={lin} comp={comp} omega {om[w]:.1f}: rel L2 {e:.2e}")
+        log(f"  paraxial beam {dtype} lin={lin} comp={comp} drt={drt} omega {om[w]:.1f}: rel L2 {e:.2e}")
         assert e < (1e-10 if dtype == "f64" else 1e-4)
     assert np.linalg.norm(Go[0]) > 0
