@@ -5,7 +5,9 @@ CPU-baseline leg may import this package.  It shares no code with the HIP
 library (``paper_2006_11945_amd``) and never imports it.
 
 The arithmetic lives in ``egb_oracle.c`` (plain double-precision loops, built
-with gcc by :func:`build`); this module only marshals numpy arrays.  Plane
+with gcc by :func:`build`); this module only marshals numpy arrays.  The
+migration operators (plain sums over the Green's functions) are numpy, in
+``migration.py``.  Plane
 order of the oracle state: phi1, psi, Re C, Im C, Re B, Im B.
 """
 from __future__ import annotations
