@@ -366,6 +366,32 @@ egb_status egb_paraxial_beam_sum(const egb_grid *g, const void *coeff2d, const v
 egb_status egb_paraxial_pick(const egb_grid *g, const void *levels, double theta_max, const double *xs, int32_t nsrc,
                              double *T, hipStream_t stream);
 
+/* ---------------------------------------- Green's-function migration
+ * The application the paper ends with (section 6): imaging with the Green's
+ * functions of the depth march (eq. 34 over Gamma = {X = x_s}, eq. 35; one
+ * march serves every surface point).  The paper gives no imaging condition;
+ * these two calls are single-scattering (Born) data of a reflectivity and
+ * its exact adjoint for a real reflectivity, the image:
+ *   d[w][s][r] = omega_w^2 dx dz sum_x G[s][w][x] m[x] G[r][w][x],
+ *   I[x] = Re sum_w omega_w^2 dx dz sum_{s,r} conj(G[s][w][x])
+ *          conj(G[r][w][x]) d[w][s][r]
+ * (sources and receivers at the same ns surface points, x = ix nz + iz).
+ * G: device, complex [ns][nw][nx][nz] (re, im) in the grid dtype, i.e. the
+ * outputs of egb_paraxial_beam_sum for the ns points one after another;
+ * omegas: HOST float64 [nw] (the frequencies G was summed at, rad/s).
+ * Accumulation is float64.  1 <= ns <= 64 (EGB_EUNSUPPORTED above).
+ * Stream-ordered; nothing is allocated. */
+
+/* In: m (device float64 [nx][nz]).  Out: d (device complex128 [nw][ns][ns],
+ * (re, im)). */
+egb_status egb_born_data(const egb_grid *g, const void *G, int32_t ns, const double *omegas, int32_t nw,
+                         const double *m, double *d, hipStream_t stream);
+
+/* In: d (device complex128 [nw][ns][ns]).  Out: image (device float64
+ * [nx][nz]). */
+egb_status egb_migrate(const egb_grid *g, const void *G, int32_t ns, const double *omegas, int32_t nw,
+                       const double *d, double *image, hipStream_t stream);
+
 /* ------------------------------------------------------ launch tuning
  * Not a step of the method: the stage kernels of egb_liouville_step, its
  * kinematic variant, the reverse stages of egb_adjoint_step and

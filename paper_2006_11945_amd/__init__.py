@@ -103,6 +103,10 @@ def _load():
     for name in ("egb_medium_table", "egb_paraxial_velocity", "egb_paraxial_init", "egb_paraxial_march",
                  "egb_paraxial_pick", "egb_paraxial_beam_sum"):
         getattr(L, name).restype = ctypes.c_int
+    L.egb_born_data.argtypes = [G, vp, i32, dp, i32, vp, vp, vp]
+    L.egb_migrate.argtypes = [G, vp, i32, dp, i32, vp, vp, vp]
+    L.egb_born_data.restype = ctypes.c_int
+    L.egb_migrate.restype = ctypes.c_int
     L.egb_get_blocks.argtypes = [G, i32]; L.egb_get_blocks.restype = i32
     L.egb_set_blocks.argtypes = [G, i32, i32]
     L.egb_tune_step.argtypes = [G, vp, S, vp, vp, vp, sz, d, i32, i32, vp, ctypes.POINTER(i32)]
@@ -303,6 +307,34 @@ def workspace_size_batched(arr) -> int:
 def egb_liouville_step_batched(arr, nsteps: int, work, stream=None):
     rc = _lib.egb_liouville_step_batched(arr, len(arr), int(nsteps), _ptr(work), work.numel(), _stream(stream))
     _check("egb_liouville_step_batched", rc)
+
+
+# ------------------------------------------------- Green's-function migration
+def _host_omegas(omegas):
+    om = np.ascontiguousarray(np.atleast_1d(np.asarray(omegas, dtype=np.float64)))
+    return om, om.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def egb_born_data(eg, G, omegas, m, d=None, stream=None) -> torch.Tensor:
+    """Born data d [nw][ns][ns][re, im] (float64) of the reflectivity m
+    (float64 [nx][nz]) from the Green's functions G [ns][nw][nx][nz][re, im]."""
+    om, omp = _host_omegas(omegas)
+    ns = G.shape[0]
+    if d is None:
+        d = torch.empty((len(om), ns, ns, 2), dtype=torch.float64, device=G.device)
+    _check("egb_born_data", _lib.egb_born_data(ctypes.byref(eg), _ptr(G), ns, omp, len(om), _ptr(m), _ptr(d),
+                                               _stream(stream)))
+    return d
+
+
+def egb_migrate(eg, G, omegas, d, image=None, stream=None) -> torch.Tensor:
+    """Image [nx][nz] (float64), the adjoint of egb_born_data."""
+    om, omp = _host_omegas(omegas)
+    if image is None:
+        image = torch.empty((eg.nx, eg.nz), dtype=torch.float64, device=G.device)
+    _check("egb_migrate", _lib.egb_migrate(ctypes.byref(eg), _ptr(G), G.shape[0], omp, len(om), _ptr(d),
+                                           _ptr(image), _stream(stream)))
+    return image
 
 
 # ----------------------------------------------------------- launch tuning
@@ -529,6 +561,17 @@ class Paraxial:
         egb_paraxial_beam_sum(self.eg, self.coeff2d, self.levels, self.theta_max, xs, lin, comp, om, out,
                               self.work_beam, stream, self.drt)
         return out
+
+    def greens(self, xs_list, omegas, lin: int = EGB_LIN_EXACT, stream=None) -> torch.Tensor:
+        """Green's functions [ns][nw][nx][nz][re, im] of the surface points
+        xs_list from the one march (the input of egb_born_data / egb_migrate)."""
+        om = np.atleast_1d(np.asarray(omegas, dtype=np.float64))
+        xs_list = np.atleast_1d(np.asarray(xs_list, dtype=np.float64))
+        G = torch.empty((len(xs_list), len(om), self.eg.nx, self.eg.nz, 2), dtype=real_dtype(self.eg),
+                        device=self.device)
+        for i, xs in enumerate(xs_list):
+            self.beam(float(xs), om, lin=lin, out=G[i], stream=stream)
+        return G
 
     def level(self, n: int) -> dict:
         return paraxial_level_views(self.eg, self.levels, n)

@@ -518,6 +518,31 @@ egb_status egb_liouville_step_batched(const egb_problem* probs, int32_t nprob, i
     return hip_status(e);
 }
 
+// ------------------------------------------------------ Green's-function migration
+static egb_status migration_args(const egb_grid* g, const void* G, int32_t ns, const double* omegas, int32_t nw) {
+    if (!grid_ok(g) || !G || !aligned16(G) || ns < 1 || !omegas || nw < 1) return EGB_EINVAL;
+    if (ns > migration_max_points()) return EGB_EUNSUPPORTED;
+    for (int w = 0; w < nw; ++w)
+        if (!isfinite(omegas[w]) || !(omegas[w] > 0.0)) return EGB_EINVAL;
+    return EGB_OK;
+}
+
+egb_status egb_born_data(const egb_grid* g, const void* G, int32_t ns, const double* omegas, int32_t nw,
+                         const double* m, double* d, hipStream_t stream) {
+    const egb_status st = migration_args(g, G, ns, omegas, nw);
+    if (st != EGB_OK) return st;
+    if (!m || !d || !aligned16(m) || !aligned16(d)) return EGB_EINVAL;
+    return hip_status(launch_born_data(grid_args(*g), g->dtype, G, ns, omegas, nw, m, d, stream));
+}
+
+egb_status egb_migrate(const egb_grid* g, const void* G, int32_t ns, const double* omegas, int32_t nw,
+                       const double* d, double* image, hipStream_t stream) {
+    const egb_status st = migration_args(g, G, ns, omegas, nw);
+    if (st != EGB_OK) return st;
+    if (!d || !image || !aligned16(d) || !aligned16(image)) return EGB_EINVAL;
+    return hip_status(launch_migrate(grid_args(*g), g->dtype, G, ns, omegas, nw, d, image, stream));
+}
+
 // ------------------------------------------------------------ launch tuning
 static bool tune_op_ok(int32_t op) { return op == EGB_TUNE_STEP || op == EGB_TUNE_KINEMATIC || op == EGB_TUNE_ADJOINT; }
 

@@ -180,3 +180,19 @@ def test_paraxial_drt_variant_is_validated():
     om = (ctypes.c_double * 1)(100.0)
     assert L.egb_paraxial_beam_sum(ctypes.byref(eg), P(256), P(256), 1.0, 200.0, 0, 5, -1, om, 1, P(256), P(256),
                                    1 << 30, None) == egb.EGB_EINVAL
+
+
+def test_migration_arguments_are_validated():
+    import paper_2006_11945_amd as egb
+    import workloads as W
+
+    eg = egb.make_grid(W.Grid(nx=40, nz=16, nth=36, dx=10.0, dz=10.0), "f32")
+    P = ctypes.c_void_p
+    L = egb.lib()
+    om = (ctypes.c_double * 2)(100.0, 200.0)
+    bad = (ctypes.c_double * 2)(100.0, -1.0)
+    assert L.egb_born_data(ctypes.byref(eg), P(256), 65, om, 2, P(256), P(256), None) == egb.EGB_EUNSUPPORTED
+    assert L.egb_born_data(ctypes.byref(eg), P(256), 0, om, 2, P(256), P(256), None) == egb.EGB_EINVAL
+    assert L.egb_born_data(ctypes.byref(eg), P(256), 4, bad, 2, P(256), P(256), None) == egb.EGB_EINVAL
+    assert L.egb_migrate(ctypes.byref(eg), P(256), 4, om, 2, P(256), None, None) == egb.EGB_EINVAL
+    assert L.egb_migrate(ctypes.byref(eg), P(260), 4, om, 2, P(256), P(256), None) == egb.EGB_EINVAL
