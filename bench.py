@@ -46,6 +46,8 @@ def parse():
                     help="sources of the 16-source adjoint workload to time (0 skips it)")
     ap.add_argument("--paraxial-sources", type=int, default=16,
                     help="surface sources picked from the paraxial depth march of the same medium (0 skips it)")
+    ap.add_argument("--migration-points", type=int, default=32,
+                    help="surface points of the migration leg on the depth march (0: skip it)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape search (profiling runs: keeps every timed launch at the default)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -156,7 +158,57 @@ def adjoint_vs_forward(nsrc, nsteps, n=256):
 FLOP_PCELL_STAGE = 14 * FLOP_WENO + 7 * 2 * 2 + 17 + 7 * 4 + 7 * 3
 
 
-def paraxial_leg(n, nsrc, nth=256, theta_max=None):
+def migration_leg(P, p, npoints):
+    """Green's-function migration on the march just made: the Green's
+    functions of `npoints` surface points at the workload's frequencies (one
+    beam sum each), the Born data of a synthetic reflectivity (point
+    scatterers and a reflector segment) and its image."""
+    import numpy as np
+    import torch
+
+    import paper_2006_11945_amd as egb
+
+    g = p.grid
+    L = g.nx * g.dx
+    xs_list = np.linspace(0.1 * L, 0.9 * L, npoints)
+    m = np.zeros((g.nx, g.nz))
+    pts = [(g.nx // 2, g.nz // 2), (g.nx // 3, (2 * g.nz) // 3), ((2 * g.nx) // 3, g.nz // 3)]
+    for i, k in pts:
+        m[i, k] = 1.0
+    m[g.nx // 4:(3 * g.nx) // 4, (3 * g.nz) // 4] = 0.5
+    md = torch.as_tensor(m, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    G = P.greens(xs_list, p.omegas)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d = egb.egb_born_data(P.eg, G, p.omegas, md)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    img = egb.egb_migrate(P.eg, G, p.omegas, d)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    # complex multiply-adds of either contraction: ns^2 per image point and frequency
+    flop = 8.0 * npoints ** 2 * g.nx * g.nz * len(p.omegas)
+    im = np.abs(img.cpu().numpy())
+    bg = float(np.median(im))
+    peaks = []
+    for i, k in pts:  # the image's peak in a 21 x 21 window around each scatterer: offset, contrast
+        i0, k0 = max(i - 10, 0), max(k - 10, 0)
+        win = im[i0:i + 11, k0:k + 11]
+        a, b = np.unravel_index(np.argmax(win), win.shape)
+        peaks.append({"offset_cells": int(max(abs(i0 + a - i), abs(k0 + b - k))),
+                      "contrast": float(win.max() / max(bg, 1e-300))})
+    kr = (3 * g.nz) // 4
+    prof = im[g.nx // 4:(3 * g.nx) // 4].sum(axis=0)
+    return {"surface_points": npoints, "frequencies": len(p.omegas), "greens_s": t1 - t0,
+            "born_ms": (t2 - t1) * 1e3, "migrate_ms": (t3 - t2) * 1e3,
+            "born_fp64_TFLOPs": flop / (t2 - t1) / 1e12, "migrate_fp64_TFLOPs": flop / (t3 - t2) / 1e12,
+            "scatterers": peaks, "reflector_depth_error_cells": int(np.argmax(prof) - kr),
+            "image_finite": bool(np.isfinite(im).all())}
+
+
+def paraxial_leg(n, nsrc, nth=256, theta_max=None, migration_points=0):
     """The paraxial depth march (the paper's own formulation) on the same
     medium: 256 x 256 slice of 256 theta nodes in (-60, 60) degrees, all 256
     depth levels, first arrivals of `nsrc` surface sources from the one march,
@@ -199,6 +251,7 @@ def paraxial_leg(n, nsrc, nth=256, theta_max=None):
     return {"grid": [g.nx, g.nz, nth], "theta_max_deg": float(np.degrees(theta_max)), "substeps_per_level": nsub,
             "stage_launches": launches, "march_s": t1 - t0, "pick_s": t2 - t1, "sources": nsrc,
             "beam_sum_s": t3 - t2, "beam_frequencies": len(p.omegas), "beam_finite": bool(torch.isfinite(G).all()),
+            "migration": migration_leg(P, p, migration_points) if migration_points > 0 else None,
             "arrival_fraction": float(torch.isfinite(T).float().mean()),
             "cell_updates_per_s": cells * nsub * (g.nz - 1) / (t1 - t0),
             "roofline": {"bound": "alu", "kernel": "k_pstage (one depth-substep RK3 stage)",
@@ -375,7 +428,7 @@ def main():
         res["adjoint"] = adjoint_vs_forward(args.adjoint_sources, args.rk_steps, args.n)
         torch.cuda.empty_cache()
     if args.paraxial_sources > 0:
-        res["paraxial"] = paraxial_leg(args.n, args.paraxial_sources)
+        res["paraxial"] = paraxial_leg(args.n, args.paraxial_sources, migration_points=args.migration_points)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(W.vti_256(n=args.n, nsteps=1))
