@@ -20,7 +20,6 @@
 // lambda of the initial state.
 #include <hip/hip_runtime.h>
 #include <math.h>
-#include <stdlib.h>
 
 #include <algorithm>
 

@@ -1,7 +1,6 @@
 // C ABI of libegb: argument validation, workspace carving, launch order.
 #include <hip/hip_runtime.h>
 #include <math.h>
-#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
