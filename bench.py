@@ -316,7 +316,41 @@ def cpu_baseline(problem):
     return {"value": g.ncell / (t2 - t1), "unit": "cell-updates/s",
             "cores": int(os.environ.get("OMP_NUM_THREADS", cores)), "kind": "oracle",
             "sample": f"one SSP-RK3 step of the full {g.nx}x{g.nz}x{g.nth} grid "
-                      f"(FP64; setup {t1 - t0:.1f} s not counted, step {t2 - t1:.1f} s)"}
+                      f"(FP64; setup {t1 - t0:.1f} s not counted, step {t2 - t1:.1f} s)",
+            "cpu_model": cpu_model(), "value_1_thread": single_thread_oracle(),
+            "sample_1_thread": "one SSP-RK3 step of the same VTI recipe at 128^3, OMP_NUM_THREADS=1"}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def single_thread_oracle():
+    """The oracle on one thread (a child process: OpenMP fixes its thread
+    count when the library loads), one RK3 step of a 128^3 grid of the same
+    recipe; cell-updates/s, None if it did not run."""
+    import subprocess
+    import sys
+
+    code = ("import sys, time; sys.path.insert(0, %r)\n"
+            "import oracle, workloads as W\n"
+            "p = W.vti_256(n=128)\n"
+            "r = oracle.solve(p, nsteps=0)\n"
+            "t0 = time.perf_counter()\n"
+            "oracle.march(p.grid, r['vel'], p.source, r['U0'], r['dt'], 1)\n"
+            "print(p.grid.ncell / (time.perf_counter() - t0))\n") % ROOT
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+        return float(out.stdout.strip().splitlines()[-1]) if out.returncode == 0 else None
+    except (subprocess.SubprocessError, ValueError, IndexError):
+        return None
 
 
 def main():
@@ -356,6 +390,9 @@ def main():
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     march_ms = []
 
+    ev2 = torch.cuda.Event(enable_timing=True)
+    beam_ms = []
+
     def one_step(timed):
         s.velocity()
         s.init()
@@ -365,10 +402,13 @@ def main():
         if timed:
             ev1.record(stream)
         s.beam(p.omegas, out=out)
+        if timed:
+            ev2.record(stream)
         egb.egb_pick_receivers(s.eg, s.state, rx_d, t_pick)
         if timed:
-            ev1.synchronize()
+            ev2.synchronize()
             march_ms.append(ev0.elapsed_time(ev1))
+            beam_ms.append(ev1.elapsed_time(ev2))
 
     for _ in range(args.warmup):
         one_step(False)
@@ -413,6 +453,8 @@ def main():
                      "copy_GBps": copy_gbps, "hbm_frac_of_copy": None if rec is None else hbm_gbps / copy_gbps,
                      "valu_instr_per_cell_stage": None if rec is None else rec.get("valu_instr_per_cell_stage"),
                      "valu_busy": None if rec is None else rec.get("valu_busy")},
+        "beam_sum": {"ms": float(np.mean(beam_ms)), "frequencies": len(p.omegas),
+                     "output_point_freqs_per_s": p.grid.nx * p.grid.nz * len(p.omegas) / (np.mean(beam_ms) * 1e-3)},
         "march_ms": float(np.mean(march_ms)),
         "march_cell_updates_per_s": cells * p.nsteps / (float(np.mean(march_ms)) * 1e-3),
     }
