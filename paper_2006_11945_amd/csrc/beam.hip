@@ -180,7 +180,8 @@ __global__ __launch_bounds__(256) void k_beam_compact(BeamArgs a) {
 constexpr int WCHUNK = 16;
 struct Omegas {
     double w[WCHUNK];
-    int n, first;
+    double step;  // w[k] = w[0] + k step for every k < n when uniform
+    int n, first, uniform;
 };
 
 // Sum over one row (ROW) or column list for a chunk of frequencies.
@@ -200,11 +201,46 @@ __global__ __launch_bounds__(64) void k_beam_line(BeamArgs a, Omegas om, R* out)
 #pragma unroll
     for (int w = 0; w < WCHUNK; ++w) gre[w] = gim[w] = (R)0;
     const double two_pi = 6.283185307179586476925286766559, inv_two_pi = 1.0 / two_pi;
+    // exp(i o T) = exp(-o Im T) (cos + i sin)(o Re T), the phase reduced mod 2 pi in double
+    auto expi = [&](double o, double Tre, double Tim, R& er, R& ei) {
+        const double ph = o * Tre;
+        const double red = ph - two_pi * rint(ph * inv_two_pi);
+        R sph, cph, mag;
+        if constexpr (sizeof(R) == 4) {
+            sincosf((float)red, &sph, &cph);
+            mag = __expf(-(float)(o * Tim));
+        } else {
+            sincos(red, &sph, &cph);
+            mag = exp(-o * Tim);
+        }
+        er = mag * cph;
+        ei = mag * sph;
+    };
     for (int r = 0; r < cnt; ++r) {
         const BeamRec b = recs[r];
         const double d = pos - b.pos;
         const double Tre = b.psi + b.p * d + 0.5 * b.Mre * d * d;
         const double Tim = 0.5 * b.Mim * d * d;
+        if (om.uniform) {
+            // equally spaced frequencies: exp(i w_k T) = exp(i w_0 T) exp(i step T)^k,
+            // two exponentials per beam and output instead of one per frequency
+            R er, ei, dr, di;
+            expi(om.w[0], Tre, Tim, er, ei);
+            expi(om.step, Tre, Tim, dr, di);
+#pragma unroll
+            for (int w = 0; w < WCHUNK; ++w) {
+                if (w < om.n) {
+                    if (om.w[w] * Tim <= 16.0) {
+                        gre[w] += (R)b.are * er - (R)b.aim * ei;
+                        gim[w] += (R)b.are * ei + (R)b.aim * er;
+                    }
+                    const R nr = er * dr - ei * di;
+                    ei = er * di + ei * dr;
+                    er = nr;
+                }
+            }
+            continue;
+        }
 #pragma unroll
         for (int w = 0; w < WCHUNK; ++w) {
             if (w < om.n) {
@@ -441,6 +477,11 @@ hipError_t launch_beam_sum(const BeamArgs& a, int dtype, const double* omegas, i
         om.n = nw - w0 < WCHUNK ? nw - w0 : WCHUNK;
         om.first = w0;
         for (int w = 0; w < WCHUNK; ++w) om.w[w] = w < om.n ? omegas[w0 + w] : 0.0;
+        // equally spaced (to 1e-12 of the largest) chunks take the recurrence
+        om.step = om.n > 1 ? (om.w[om.n - 1] - om.w[0]) / (om.n - 1) : 0.0;
+        om.uniform = om.n > 1 && om.step > 0.0;
+        for (int w = 0; w < om.n && om.uniform; ++w)
+            if (fabs(om.w[w] - (om.w[0] + w * om.step)) > 1e-12 * fabs(om.w[om.n - 1])) om.uniform = 0;
         const dim3 grow((a.g.nx + 63) / 64, a.g.nz), gcol((a.g.nz + 63) / 64, a.g.nx);
         if (dtype == EGB_F64) {
             k_beam_line<double, true><<<grow, 64, 0, s>>>(a, om, (double*)out);

@@ -209,6 +209,30 @@ def test_beam_sum_parity_f32(tilt, lin):
         assert e <= 1e-4
 
 
+@pytest.mark.parametrize("hz", [[10.0, 35.0, 60.0], [10.0, 23.0, 60.0, 61.0]])
+def test_beam_sum_frequency_recurrence(hz):
+    """Equally spaced frequencies take the recurrence exp(i w_k T) =
+    exp(i w_0 T) exp(i step T)^k, others one exponential per frequency: each
+    against the oracle, and the set against the same frequencies summed one
+    by one (the direct path) on the GPU."""
+    p = ragged_problem(tilt=True, nsteps=20)
+    om = W.hz(hz)
+    o = oracle.solve(p)
+    Ur = rounded_oracle_state(o["U"], "f32")
+    s = run_gpu(p, "f32", 0)
+    egb().write_state(s.eg, s.state, oracle_planes(Ur))
+    out = s.beam(om).cpu().numpy()
+    Gb = out[..., 0] + 1j * out[..., 1]
+    Ob = oracle.beam_sum(p.grid, o["vel"], o["vaux"], p.source, Ur, om)
+    for w in range(len(om)):
+        one = s.beam(om[w:w + 1]).cpu().numpy()[0]
+        G1 = one[..., 0] + 1j * one[..., 1]
+        e = np.linalg.norm(Gb[w] - Ob[w]) / np.linalg.norm(Ob[w])
+        e1 = np.linalg.norm(Gb[w] - G1) / np.linalg.norm(G1)
+        log(f"  {hz} omega {om[w]:.1f}: vs oracle {e:.3e}, vs one by one {e1:.3e}")
+        assert e <= 1e-4 and e1 <= 1e-5
+
+
 def test_pick_parity_and_no_arrival():
     p = ragged_problem(nsteps=40)
     o = oracle.solve(p)
