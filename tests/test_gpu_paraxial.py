@@ -173,6 +173,27 @@ def test_paraxial_invalid_arguments():
     assert ex.value.status == e.EGB_EINVAL
 
 
+def test_paraxial_full_size_paper23_stays_bounded():
+    """The DRT of eqs. 21-23 marched through all 256 levels of the 256 x 256
+    heterogeneous VTI slice: every level finite, and the Green's function of
+    the central surface source finite."""
+    from dataclasses import replace
+
+    p = W.vti_256(n=256, nsteps=1)
+    g = replace(p.grid, nth=256)
+    L = g.nx * g.dx
+    P = egb().Paraxial(g, p.medium, TMAX, DEV, "f32", drt=1)
+    P.velocity()
+    P.init(1.0 / (2 * L))
+    P.march(P.substeps())
+    torch.cuda.synchronize()
+    for n in range(0, g.nz, 15):
+        G = gpu_levels(P, n)
+        assert all(np.isfinite(v).all() for v in G.values()), n
+    out = P.beam(0.5 * L, W.hz([5.0, 60.0]))
+    assert torch.isfinite(out).all()
+
+
 def test_paraxial_full_size_first_levels():
     """The 256 x 256 VTI medium with 256 theta nodes, marched through all 256
     levels in the benchmark's configuration; the first six levels are
