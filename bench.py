@@ -105,6 +105,8 @@ def adjoint_vs_forward(nsrc, nsteps, n=256):
     VTI medium: forward (kinematic march with checkpoints every 16 steps +
     pick) and backward (pick adjoint, recomputation, adjoint steps, medium
     gradient) timed separately, next to the plain full-plane forward march."""
+    from dataclasses import replace
+
     import numpy as np
     import torch
 
@@ -116,8 +118,9 @@ def adjoint_vs_forward(nsrc, nsteps, n=256):
     dev = "cuda:0"
     mk = lambda m, grad=False: [torch.tensor(np.asarray(a, dtype=np.float64), device=dev, requires_grad=grad)
                                 for a in (m.vp0, m.eps, m.delta, m.tilt)]
-    base = egb.Solver(probs[0], dev)
-    dt = base.velocity()
+    # one step for every march: within the CFL limits of the model and of the
+    # perturbed medium that makes the observed traveltimes
+    dt = min(egb.Solver(probs[0], dev).velocity(), egb.Solver(replace(probs[0], medium=true), dev).velocity())
     t_fwd = t_bwd = t_plain = 0.0
     for p in probs[:nsrc]:
         spec = {"grid": p.grid, "source": p.source, "receivers": p.receivers, "nsteps": nsteps, "vs_ratio": 0.5,

@@ -36,7 +36,7 @@ extern "C" {
 typedef enum {
     EGB_OK = 0,
     EGB_EINVAL = -1,        /* bad argument: null, size, alignment, dtype, range */
-    EGB_ECFL = -2,          /* dt not positive and finite */
+    EGB_ECFL = -2,          /* dt not positive and finite, or dt > dt_cfl (1 + 1e-12) of the velocity */
     EGB_EWORKSPACE = -3,    /* workspace too small, or a beam list overflowed it */
     EGB_EHIP = -4,          /* a HIP launch or runtime call failed */
     EGB_ENONFINITE = -5,    /* a non-finite value was produced */
@@ -117,9 +117,24 @@ size_t egb_bdata_bytes(const egb_grid *g);          /* boundary data of the marc
  *      *dt_cfl (host) = 0.5 / max(|V_x|/dx + |V_z|/dz + |V_theta|/dtheta).
  * work: egb_workspace_size(g, EGB_OP_VELOCITY) bytes.
  * Synchronises `stream` once (to return dt_cfl).  EGB_ENONFINITE if the
- * medium yields a non-finite velocity. */
+ * medium yields a non-finite velocity.  The library records dt_cfl for the
+ * buffer vel3d and this grid (host memory, process-wide, mutex-guarded, at
+ * most 4096 buffers: the least recently written record makes room): every
+ * call that marches with vel3d refuses dt > dt_cfl (1 + 1e-12) with
+ * EGB_ECFL before launching anything, and returns EGB_EINVAL for a buffer
+ * without a record for its grid. */
 egb_status egb_hamiltonian_velocity(const egb_grid *g, const egb_medium *m, void *coeff2d, void *vel3d,
                                     double *dt_cfl, void *work, size_t work_bytes, hipStream_t stream);
+
+/* The CFL limit recorded for vel3d on grid g (host out); EGB_EINVAL if there
+ * is none.  Host only: touches no device. */
+egb_status egb_velocity_dt_cfl(const egb_grid *g, const void *vel3d, double *dt_cfl);
+
+/* Record the CFL limit of a velocity buffer filled by other means (for
+ * example a copy of another buffer of the same medium): dt_cfl > 0 and
+ * finite, 0.5 / max(|V_x|/dx + |V_z|/dz + |V_theta|/dtheta) over the buffer's
+ * cells.  Host only. */
+egb_status egb_declare_velocity(const egb_grid *g, const void *vel3d, double dt_cfl);
 
 /* Point-source data (eqs. 20 and 24 read for a point source): with the medium
  * frozen at the source (bilinear in coeff2d), every cell gets
@@ -151,8 +166,10 @@ egb_status egb_boundary_data(const egb_grid *g, const void *state, void *bdata, 
  * theta periodic; cells within r0 of the source keep their values (Dirichlet
  * data).  In/out: state.  vel3d from egb_hamiltonian_velocity.
  * work: egb_workspace_size(g, EGB_OP_STEP) bytes (two RK stage buffers).
- * dt must be positive and finite (EGB_ECFL otherwise); stability needs
- * dt <= dt_cfl. */
+ * dt must be positive, finite and at most the CFL limit recorded for vel3d
+ * (egb_hamiltonian_velocity) times 1 + 1e-12: EGB_ECFL otherwise, and
+ * EGB_EINVAL if vel3d has no record for this grid; nothing is launched
+ * then. */
 egb_status egb_liouville_step(const egb_grid *g, const void *vel3d, const egb_source *src, const void *bdata,
                               void *state, void *work, size_t work_bytes, double dt, int32_t nsteps,
                               hipStream_t stream);

@@ -76,6 +76,8 @@ def _load():
     L.egb_workspace_size.argtypes = [G, i32]; L.egb_workspace_size.restype = sz
     L.egb_hamiltonian_velocity.argtypes = [G, M, vp, vp, dp, vp, sz, vp]
     L.egb_init_state.argtypes = [G, vp, S, vp, vp]
+    L.egb_velocity_dt_cfl.argtypes = [G, vp, dp]
+    L.egb_declare_velocity.argtypes = [G, vp, d]
     L.egb_boundary_data.argtypes = [G, vp, vp, vp]
     L.egb_liouville_step.argtypes = [G, vp, S, vp, vp, vp, sz, d, i32, vp]
     L.egb_beam_sum.argtypes = [G, vp, vp, S, vp, dp, i32, vp, vp, sz, vp]
@@ -92,7 +94,7 @@ def _load():
     L.egb_liouville_step_batched.argtypes = [P, i32, i32, vp, sz, vp]
     L.egb_liouville_step_batched.restype = ctypes.c_int
     for name in ("egb_hamiltonian_velocity", "egb_init_state", "egb_boundary_data", "egb_liouville_step",
-                 "egb_beam_sum", "egb_pick_receivers"):
+                 "egb_beam_sum", "egb_pick_receivers", "egb_velocity_dt_cfl", "egb_declare_velocity"):
         getattr(L, name).restype = ctypes.c_int
     L.egb_medium_table.argtypes = [G, M, vp, vp]
     L.egb_paraxial_velocity.argtypes = [G, vp, d, i32, vp, dp, vp, sz, vp]
@@ -180,6 +182,17 @@ def egb_hamiltonian_velocity(eg, medium: "DeviceMedium", coeff2d, vel3d, work, s
                                        ctypes.byref(dt), _ptr(work), work.numel(), _stream(stream))
     _check("egb_hamiltonian_velocity", rc)
     return dt.value
+
+
+def egb_velocity_dt_cfl(eg, vel3d) -> float:
+    """The CFL limit the library recorded for vel3d on this grid."""
+    dt = ctypes.c_double(0.0)
+    _check("egb_velocity_dt_cfl", _lib.egb_velocity_dt_cfl(ctypes.byref(eg), _ptr(vel3d), ctypes.byref(dt)))
+    return dt.value
+
+
+def egb_declare_velocity(eg, vel3d, dt_cfl: float):
+    _check("egb_declare_velocity", _lib.egb_declare_velocity(ctypes.byref(eg), _ptr(vel3d), float(dt_cfl)))
 
 
 def egb_init_state(eg, coeff2d, src: EgbSource, state, stream=None):

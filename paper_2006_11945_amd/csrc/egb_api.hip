@@ -4,6 +4,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "egb_internal.h"
@@ -40,6 +42,60 @@ int beam_cap_default(const egb_grid& g) { return 16 * ((g.nx > g.nz ? g.nx : g.n
 int pbeam_cap_default(const egb_grid& g) { return 16 * (g.nx + g.nth) + 64; }
 
 size_t beam_counts_bytes(const egb_grid& g) { return align256((size_t)(g.nx + g.nz) * sizeof(int)); }
+
+// CFL limits of velocity buffers.  egb_hamiltonian_velocity records the
+// limit of every buffer it fills (keyed by its address, with the grid it was
+// computed for); the marching calls look the buffer up and refuse a time
+// step above the limit.  A buffer filled by other means is declared with
+// egb_declare_velocity.  At most VEL_CAP records are kept; the least
+// recently written one makes room.
+struct VelRecord {
+    int nx, nz, nth, dtype;
+    double dx, dz, dt_cfl;
+    unsigned long long seq;
+};
+constexpr size_t VEL_CAP = 4096;
+std::mutex vel_mu;
+std::map<const void*, VelRecord>& vel_table() {
+    static std::map<const void*, VelRecord> t;
+    return t;
+}
+
+void vel_record(const egb_grid& g, const void* vel3d, double dt_cfl) {
+    static unsigned long long seq = 0;
+    std::lock_guard<std::mutex> lock(vel_mu);
+    auto& t = vel_table();
+    if (t.size() >= VEL_CAP && t.find(vel3d) == t.end()) {
+        auto old = t.begin();
+        for (auto it = t.begin(); it != t.end(); ++it)
+            if (it->second.seq < old->second.seq) old = it;
+        t.erase(old);
+    }
+    t[vel3d] = VelRecord{g.nx, g.nz, g.nth, g.dtype, g.dx, g.dz, dt_cfl, ++seq};
+}
+
+// The recorded CFL limit of vel3d for grid g; false if the buffer is unknown
+// or was recorded for another grid.
+bool vel_lookup(const egb_grid& g, const void* vel3d, double& dt_cfl) {
+    std::lock_guard<std::mutex> lock(vel_mu);
+    const auto& t = vel_table();
+    const auto it = t.find(vel3d);
+    if (it == t.end()) return false;
+    const VelRecord& r = it->second;
+    if (r.nx != g.nx || r.nz != g.nz || r.nth != g.nth || r.dtype != g.dtype || r.dx != g.dx || r.dz != g.dz)
+        return false;
+    dt_cfl = r.dt_cfl;
+    return true;
+}
+
+// dt against the limit of vel3d: EGB_ECFL for a step that is not positive
+// and finite or exceeds dt_cfl (1 + 1e-12), EGB_EINVAL for an unknown buffer.
+egb_status dt_check(const egb_grid& g, const void* vel3d, double dt) {
+    if (!(dt > 0.0) || !isfinite(dt)) return EGB_ECFL;
+    double lim = 0.0;
+    if (!vel_lookup(g, vel3d, lim)) return EGB_EINVAL;
+    return dt <= lim * (1.0 + 1e-12) ? EGB_OK : EGB_ECFL;
+}
 
 }  // namespace
 
@@ -105,6 +161,21 @@ egb_status egb_hamiltonian_velocity(const egb_grid* g, const egb_medium* m, void
     memcpy(&r, &bits, sizeof(r));
     if (!(r > 0.0) || !isfinite(r)) return EGB_ENONFINITE;
     *dt_cfl = 0.5 / r;
+    vel_record(*g, vel3d, *dt_cfl);
+    return EGB_OK;
+}
+
+egb_status egb_declare_velocity(const egb_grid* g, const void* vel3d, double dt_cfl) {
+    if (!grid_ok(g) || !vel3d || !aligned16(vel3d) || !(dt_cfl > 0.0) || !isfinite(dt_cfl)) return EGB_EINVAL;
+    vel_record(*g, vel3d, dt_cfl);
+    return EGB_OK;
+}
+
+egb_status egb_velocity_dt_cfl(const egb_grid* g, const void* vel3d, double* dt_cfl) {
+    if (!grid_ok(g) || !vel3d || !dt_cfl) return EGB_EINVAL;
+    double lim = 0.0;
+    if (!vel_lookup(*g, vel3d, lim)) return EGB_EINVAL;
+    *dt_cfl = lim;
     return EGB_OK;
 }
 
@@ -136,7 +207,8 @@ static egb_status liouville_steps(const egb_grid* g, const void* vel3d, const eg
     if (!grid_ok(g) || !vel3d || !bdata || !state || !source_ok(src) || nsteps < 0) return EGB_EINVAL;
     if (nsteps > 0 && !work) return EGB_EINVAL;
     if (!aligned16(vel3d) || !aligned16(bdata) || !aligned16(state) || (work && !aligned16(work))) return EGB_EINVAL;
-    if (!(dt > 0.0) || !isfinite(dt)) return EGB_ECFL;
+    const egb_status ds = dt_check(*g, vel3d, dt);
+    if (ds != EGB_OK) return ds;
     if (nsteps == 0) return EGB_OK;
     if (work_bytes < egb_workspace_size(g, EGB_OP_STEP)) return EGB_EWORKSPACE;
     if (!stage_fits_32bit(grid_args(*g), g->dtype)) return EGB_EUNSUPPORTED;
@@ -201,7 +273,8 @@ egb_status egb_adjoint_step(const egb_grid* g, const void* vel3d, const egb_sour
         !aligned16(bfold) || !aligned16(work))
         return EGB_EINVAL;
     if (state_n == lambda) return EGB_EINVAL;
-    if (!(dt > 0.0) || !isfinite(dt)) return EGB_ECFL;
+    const egb_status ds = dt_check(*g, vel3d, dt);
+    if (ds != EGB_OK) return ds;
     if (work_bytes < egb_workspace_size(g, EGB_OP_ADJOINT)) return EGB_EWORKSPACE;
     if (!stage_fits_32bit(grid_args(*g), g->dtype)) return EGB_EUNSUPPORTED;
     const size_t sb = align256(state_bytes(*g));
@@ -473,7 +546,8 @@ static egb_status batch_ok(const egb_problem* probs, int32_t nprob) {
         if (!grid_ok(&q.grid) || q.grid.dtype != dtype || !q.vel3d || !q.bdata || !q.state || !source_ok(&q.src))
             return EGB_EINVAL;
         if (!aligned16(q.vel3d) || !aligned16(q.bdata) || !aligned16(q.state)) return EGB_EINVAL;
-        if (!(q.dt > 0.0) || !isfinite(q.dt)) return EGB_ECFL;
+        const egb_status ds = dt_check(q.grid, q.vel3d, q.dt);
+        if (ds != EGB_OK) return ds;
         if (!stage_fits_32bit(grid_args(q.grid), dtype)) return EGB_EUNSUPPORTED;
     }
     return EGB_OK;
@@ -561,7 +635,8 @@ egb_status egb_tune_step(const egb_grid* g, const void* vel3d, const egb_source*
     if (!grid_ok(g) || !vel3d || !bdata || !state || !work || !source_ok(src) || !blocks || reps < 1) return EGB_EINVAL;
     if (op != EGB_TUNE_STEP && op != EGB_TUNE_KINEMATIC) return EGB_EINVAL;
     if (!aligned16(vel3d) || !aligned16(bdata) || !aligned16(state) || !aligned16(work)) return EGB_EINVAL;
-    if (!(dt > 0.0) || !isfinite(dt)) return EGB_ECFL;
+    const egb_status ds = dt_check(*g, vel3d, dt);
+    if (ds != EGB_OK) return ds;
     if (work_bytes < egb_workspace_size(g, EGB_OP_STEP)) return EGB_EWORKSPACE;
     if (!stage_fits_32bit(grid_args(*g), g->dtype)) return EGB_EUNSUPPORTED;
     StageArgs sa;
@@ -669,7 +744,7 @@ const char* egb_status_string(int32_t s) {
     switch (s) {
         case EGB_OK: return "ok";
         case EGB_EINVAL: return "invalid argument";
-        case EGB_ECFL: return "time step not positive and finite";
+        case EGB_ECFL: return "time step not positive and finite, or above the CFL limit of the velocity";
         case EGB_EWORKSPACE: return "workspace too small";
         case EGB_EHIP: return "HIP runtime or launch error";
         case EGB_ENONFINITE: return "non-finite value";

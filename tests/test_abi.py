@@ -59,6 +59,8 @@ def test_sizes_and_validation_without_gpu():
     assert L.egb_init_state(ctypes.byref(bad), None, ctypes.byref(src), None, None) == egb.EGB_EINVAL
     assert L.egb_init_state(None, None, None, None, None) == egb.EGB_EINVAL
     P = ctypes.c_void_p
+    # the fake velocity buffer at 256 gets a CFL limit (as egb_hamiltonian_velocity would record it)
+    assert L.egb_declare_velocity(ctypes.byref(eg), P(256), 1e-3) == egb.EGB_OK
     assert L.egb_liouville_step(ctypes.byref(eg), P(256), ctypes.byref(src), P(256), P(256), P(256), 1 << 30, -1.0,
                                 1, None) == egb.EGB_ECFL
     assert L.egb_liouville_step(ctypes.byref(eg), P(256), ctypes.byref(src), P(256), P(256), P(256), 16, 1e-3, 1,
@@ -90,6 +92,59 @@ def test_sizes_and_validation_without_gpu():
     assert egb.lib().egb_status_string(-3) == b"workspace too small"
 
 
+def test_time_step_above_the_cfl_limit_is_refused_before_any_launch():
+    """A step above the CFL limit recorded for the velocity buffer
+    (dt > dt_cfl (1 + 1e-12)) returns EGB_ECFL from every marching call,
+    a buffer without a record (or recorded for another grid) EGB_EINVAL;
+    both before any device call, so they run here without a GPU (a call
+    that passed the checks would fail at its first launch with EGB_EHIP,
+    or at the workspace check with EGB_EWORKSPACE)."""
+    import paper_2006_11945_amd as egb
+    import workloads as W
+
+    L = egb.lib()
+    P = ctypes.c_void_p
+    eg = egb.make_grid(W.Grid(nx=40, nz=72, nth=36, dx=10.0, dz=10.0), "f32")
+    other = egb.make_grid(W.Grid(nx=40, nz=72, nth=40, dx=10.0, dz=10.0), "f32")
+    src = egb.EgbSource(200.0, 300.0, 40.0, 1e-4)
+    vel, unknown = 4096 * 1024, 4096 * 2048
+    lim = 2.5e-3
+    assert L.egb_declare_velocity(ctypes.byref(eg), P(vel), lim) == egb.EGB_OK
+    out = ctypes.c_double(0.0)
+    assert L.egb_velocity_dt_cfl(ctypes.byref(eg), P(vel), ctypes.byref(out)) == egb.EGB_OK and out.value == lim
+    assert L.egb_velocity_dt_cfl(ctypes.byref(other), P(vel), ctypes.byref(out)) == egb.EGB_EINVAL
+    assert L.egb_declare_velocity(ctypes.byref(eg), P(vel + 4), lim) == egb.EGB_EINVAL  # misaligned
+    assert L.egb_declare_velocity(ctypes.byref(eg), P(vel), -1.0) == egb.EGB_EINVAL
+    over, ok_dt = lim * (1 + 1e-9), lim * (1 + 1e-13)
+
+    def step(fn, g, v, dt, work_bytes=16):
+        return fn(ctypes.byref(g), P(v), ctypes.byref(src), P(256), P(256), P(256), work_bytes, dt, 1, None)
+
+    for fn in (L.egb_liouville_step, L.egb_liouville_step_kinematic):
+        assert step(fn, eg, vel, over) == egb.EGB_ECFL
+        assert step(fn, eg, vel, ok_dt) == egb.EGB_EWORKSPACE  # the CFL check passed
+        assert step(fn, eg, unknown, ok_dt) == egb.EGB_EINVAL
+        assert step(fn, other, vel, ok_dt) == egb.EGB_EINVAL
+    adj = lambda v, dt: L.egb_adjoint_step(ctypes.byref(eg), P(v), ctypes.byref(src), P(256), P(512), P(768),
+                                           P(1024), P(1280), P(1536), 16, dt, None)
+    assert adj(vel, over) == egb.EGB_ECFL
+    assert adj(vel, ok_dt) == egb.EGB_EWORKSPACE
+    assert adj(unknown, ok_dt) == egb.EGB_EINVAL
+    b = ctypes.c_int32(0)
+    tune = lambda dt: L.egb_tune_step(ctypes.byref(eg), P(vel), ctypes.byref(src), P(256), P(256), P(256), 16, dt,
+                                      egb.EGB_TUNE_STEP, 3, None, ctypes.byref(b))
+    assert tune(over) == egb.EGB_ECFL
+    assert tune(ok_dt) == egb.EGB_EWORKSPACE
+    probs = (egb.EgbProblem * 2)()
+    probs[0] = egb.EgbProblem(eg, vel, src, 256, 256, ok_dt)
+    probs[1] = egb.EgbProblem(eg, vel, src, 256, 256, over)
+    assert L.egb_liouville_step_batched(probs, 2, 1, P(256), 16, None) == egb.EGB_ECFL
+    probs[1] = egb.EgbProblem(eg, unknown, src, 256, 256, ok_dt)
+    assert L.egb_liouville_step_batched(probs, 2, 1, P(256), 16, None) == egb.EGB_EINVAL
+    probs[1] = egb.EgbProblem(eg, vel, src, 256, 256, ok_dt)
+    assert L.egb_liouville_step_batched(probs, 2, 1, P(256), 16, None) == egb.EGB_EWORKSPACE
+
+
 def test_grids_beyond_32_bit_offsets_are_refused_before_any_launch():
     """The stage kernels address every array with 32-bit byte offsets: a
     1024^3 FP32 grid (a 30 GB state) is a valid request this build does not
@@ -102,6 +157,7 @@ def test_grids_beyond_32_bit_offsets_are_refused_before_any_launch():
     assert egb.state_bytes(eg) > 1 << 32
     src = egb.EgbSource(5000.0, 5000.0, 40.0, 1e-4)
     P = ctypes.c_void_p
+    assert egb.lib().egb_declare_velocity(ctypes.byref(eg), P(256), 1e-3) == egb.EGB_OK
     rc = egb.lib().egb_liouville_step(ctypes.byref(eg), P(256), ctypes.byref(src), P(256), P(256), P(256),
                                       1 << 62, 1e-3, 1, None)
     assert rc == egb.EGB_EUNSUPPORTED
@@ -137,6 +193,7 @@ def test_launch_tuning_arguments_are_validated_before_any_device_call():
     assert L.egb_get_blocks(ctypes.byref(eg), 9) == 0
     src = egb.EgbSource(1.0, 1.0, 1.0, 1e-4)
     out = ctypes.c_int32(0)
+    assert L.egb_declare_velocity(ctypes.byref(eg), P(256), 1e-3) == egb.EGB_OK
     args = (ctypes.byref(eg), P(256), ctypes.byref(src), P(256), P(256), P(256), 1 << 30, 1e-3)
     # the reverse stages cannot be timed without side effects: set only
     assert L.egb_tune_step(*args, egb.EGB_TUNE_ADJOINT, 3, None, ctypes.byref(out)) == egb.EGB_EINVAL
