@@ -1,16 +1,20 @@
 """Benchmark of the Eulerian Gaussian beam hot path on one MI355X.
 
-One step = one pass of the whole path over the heterogeneous-VTI workload
-(256 x 256 x 256 phase grid, 4 km square, 600 SSP-RK3 steps, beam sum over 32
-frequencies 5-60 Hz, first-arrival pick at 128 receivers), inputs resident
-in HBM:  medium table + velocity/DRT field, point-source data, the march, the
-beam superposition, the pick.
+One step = one pass of the whole path over the 2D TTI workload (512 x 512 x
+512 phase grid on a 4 km square, the VTI blob medium plus a smooth random
+tilt in [-45, 45] degrees, 1200 SSP-RK3 steps, beam sum over 64 frequencies
+5-60 Hz, first-arrival pick at 128 receivers), inputs resident in HBM:
+medium table + velocity/DRT field, point-source data, the march, the beam
+superposition, the pick.  FP32 planes, traveltime psi in FP64.
 
 Metric: phase-space cell-updates/s (nx nz nth x RK3 steps / wall time).
 The dominant kernel (the RK3 stage) is timed live with HIP events on the
 launch stream; its roofline entry counts the scheme's floating-point
-operations per cell-stage against the FP32 vector rate.  The oracle (FP64,
-C + OpenMP) is timed on the host on one full-size RK3 step.
+operations per cell-stage against the published FP32 vector peak, next to
+the issue rate without packed FP32 and the HBM floor of the state traffic.
+The oracle (FP64, C + OpenMP) is timed on the host on a window of the same
+grid.  Secondary legs: the 256^3 VTI workload, batched and adjoint marches
+against the plain solve, the paraxial depth march.
 """
 import argparse
 import json
@@ -18,6 +22,7 @@ import os
 import sys
 import time
 
+T_START = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -26,8 +31,28 @@ sys.path.insert(0, ROOT)
 # convection, sources, stage combine); see the design notes.
 FLOP_WENO = 80
 FLOP_CELL_STAGE = 18 * FLOP_WENO + 6 * 6 + 3 + 17 + 30
-PEAK_FP32_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 excluded
-PEAK_HBM_GBPS = 8000.0    # HBM3E spec
+PEAK_FP32_TFLOPS = 157.3           # published MI355X FP32 vector peak (counts packed, dual-lane FP32)
+PEAK_FP32_UNPACKED_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz: one FP32 op per lane
+PEAK_HBM_GBPS = 8000.0             # HBM3E spec
+# State bytes per cell (five FP32 planes and psi in FP64); one RK3 step must
+# at least read and write the state once: the HBM floor per cell-update.
+STATE_BYTES_PER_CELL = 5 * 4 + 8
+FLOOR_BYTES_PER_CELL_UPDATE = 2 * STATE_BYTES_PER_CELL
+
+WORKLOADS = {
+    "tti512": "2D TTI 512x512x512 (VTI blob medium + smooth tilt in [-45, 45] deg, 4 km square), "
+              "1200 RK3 steps, beam sum 64 freqs 5-60 Hz, 128 receivers",
+    "vti256": "heterogeneous VTI 256x256x256 (4 km square), 600 RK3 steps, beam sum 32 freqs 5-60 Hz, "
+              "128 receivers",
+}
+
+
+def make_workload(name, n=None, rk_steps=None):
+    import workloads as W
+
+    if name == "tti512":
+        return W.tti_512(n=512 if n is None else n, nsteps=1200 if rk_steps is None else rk_steps)
+    return W.vti_256(n=256 if n is None else n, nsteps=600 if rk_steps is None else rk_steps)
 
 
 def parse():
@@ -35,14 +60,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=256, help="grid size per axis (256 = the quoted workload)")
-    ap.add_argument("--rk-steps", type=int, default=600)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="tti512",
+                    help="the timed pass: tti512 (the quoted 512^3 TTI workload) or vti256")
+    ap.add_argument("--n", type=int, default=None, help="grid size per axis (default: the workload's own)")
+    ap.add_argument("--rk-steps", type=int, default=None, help="RK3 steps per pass (default: the workload's own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--vti-leg", type=int, default=1,
+                    help="timed passes of the 256^3 VTI workload as a secondary leg (0 skips it)")
     ap.add_argument("--batched-steps", type=int, default=10,
                     help="RK3 steps for the batched-vs-sequential comparison on the 64-problem uneven workload "
                          "(0 skips it)")
     ap.add_argument("--batched-problems", type=int, default=64)
-    ap.add_argument("--adjoint-sources", type=int, default=2,
+    ap.add_argument("--adjoint-sources", type=int, default=1,
                     help="sources of the 16-source adjoint workload to time (0 skips it)")
     ap.add_argument("--paraxial-sources", type=int, default=16,
                     help="surface sources picked from the paraxial depth march of the same medium (0 skips it)")
@@ -50,9 +79,16 @@ def parse():
                     help="surface points of the migration leg on the depth march (0: skip it)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape search (profiling runs: keeps every timed launch at the default)")
+    ap.add_argument("--time-budget-s", type=float, default=540.0,
+                    help="secondary legs that would end later than this many seconds after the start are "
+                         "skipped (and named so in the output); 0: no limit")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the run, copy a device buffer of this size (a plain copy kernel of known "
                          "size, to scale HBM byte counters)")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "SQ_DIR"), default=None,
+                    help="no GPU run: read three rocprofv3 --pmc output folders of a profiling run of this "
+                         "bench (FETCH_SIZE; WRITE_SIZE; SQ counters) and print the stage kernel's counter "
+                         "record as JSON")
     return ap.parse_args()
 
 
@@ -264,23 +300,110 @@ def paraxial_leg(n, nsrc, nth=256, theta_max=None, migration_points=0):
                          "note": "march wall time (launch gaps included) divided by the stage launches"}}
 
 
-# sources the stage kernel is built from (the traffic record names their hash)
+# sources the stage kernel is built from (the counter records name their hash)
 STAGE_SOURCES = ("liouville.hip", "stage_common.h", "egb_device.h")
 
 
-def measured_counters(n):
-    """The committed rocprofv3 record of the stage kernel (HBM bytes per
-    launch from FETCH_SIZE / WRITE_SIZE, VALU figures from the SQ counters),
-    only while the kernel sources are unchanged since; else None."""
+def stage_source_hash():
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "k_stage_vti256_traffic.json")
-    if n != 256 or not os.path.exists(path):
+    csrc = os.path.join(ROOT, "paper_2006_11945_amd", "csrc")
+    return hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in STAGE_SOURCES)).hexdigest()
+
+
+def measured_counters(workload, n):
+    """The committed rocprofv3 record of the stage kernel on this workload
+    (HBM bytes per launch from FETCH_SIZE / WRITE_SIZE, VALU figures from the
+    SQ counters), only while the kernel sources are unchanged since; else
+    None."""
+    path = os.path.join(ROOT, "profiles", f"k_stage_{workload}_traffic.json")
+    if n is not None or not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    csrc = os.path.join(ROOT, "paper_2006_11945_amd", "csrc")
-    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in STAGE_SOURCES)
-    return rec if hashlib.sha256(src).hexdigest() == rec["source_sha256"] else None
+    return rec if stage_source_hash() == rec["source_sha256"] else None
+
+
+def _counter_rows(folder):
+    """Rows of every rocprofv3 counter_collection.csv under `folder`."""
+    import csv
+    import glob
+
+    rows = []
+    for f in sorted(glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def summarize_counters(fetch_dir, write_dir, sq_dir):
+    """Counter record of the stage kernel from three --pmc runs of a
+    profiling pass of this bench (one RK3 step or more, --calibrate-copy-mib
+    1024 so that a plain copy of known size scales FETCH_SIZE / WRITE_SIZE).
+    Per dispatch the counter values of all reporting instances are summed;
+    stage launches are the k_stage dispatches (not the batched ones)."""
+    from collections import defaultdict
+
+    def per_dispatch(folder, names):
+        acc = defaultdict(lambda: defaultdict(float))
+        kern, grid = {}, {}
+        for r in _counter_rows(folder):
+            if r["Counter_Name"] not in names:
+                continue
+            d = int(r["Dispatch_Id"])
+            acc[d][r["Counter_Name"]] += float(r["Counter_Value"])
+            kern[d] = r["Kernel_Name"]
+            grid[d] = int(r.get("Grid_Size", 0) or 0)
+        return acc, kern, grid
+
+    def is_stage(name):
+        return name.startswith("void egb::(anonymous namespace)::k_stage<") or name.startswith("egb::(anonymous namespace)::k_stage<")
+
+    def stage_of(name):  # the template's second argument: the RK stage
+        inner = name[name.index("<") + 1:]
+        return int(inner.split(",")[1].strip())
+
+    def copy_kib(acc, kern, counter):
+        v = [acc[d][counter] for d in acc if "copyBuffer" in kern[d]]
+        return max(v) if v else None
+
+    cal = 1024 * 1024  # KiB of the 1 GiB calibration copy, read once and written once
+    fa, fk, _ = per_dispatch(fetch_dir, {"FETCH_SIZE"})
+    wa, wk, _ = per_dispatch(write_dir, {"WRITE_SIZE"})
+    fscale = cal / copy_kib(fa, fk, "FETCH_SIZE")
+    wscale = cal / copy_kib(wa, wk, "WRITE_SIZE")
+    per_stage = defaultdict(lambda: {"fetch": [], "write": [], "valu": [], "active": [], "gui": [], "waves": []})
+    for d, k in fk.items():
+        if is_stage(k):
+            per_stage[stage_of(k)]["fetch"].append(fa[d]["FETCH_SIZE"] * 1024 * fscale)
+    for d, k in wk.items():
+        if is_stage(k):
+            per_stage[stage_of(k)]["write"].append(wa[d]["WRITE_SIZE"] * 1024 * wscale)
+    sa, sk, _ = per_dispatch(sq_dir, {"SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVES", "GRBM_GUI_ACTIVE"})
+    inst_counts = defaultdict(int)
+    for r in _counter_rows(sq_dir):
+        if r["Counter_Name"] == "GRBM_GUI_ACTIVE":
+            inst_counts[int(r["Dispatch_Id"])] += 1
+    for d, k in sk.items():
+        if is_stage(k):
+            st = per_stage[stage_of(k)]
+            st["valu"].append(sa[d]["SQ_INSTS_VALU"])
+            st["active"].append(sa[d]["SQ_ACTIVE_INST_VALU"])
+            st["waves"].append(sa[d]["SQ_WAVES"])
+            st["gui"].append(sa[d]["GRBM_GUI_ACTIVE"] / max(inst_counts[d], 1))
+    mean = lambda v: sum(v) / len(v) if v else None
+    stages = {}
+    for k in sorted(per_stage):
+        st = per_stage[k]
+        f, w = mean(st["fetch"]), mean(st["write"])
+        stages[k] = {"fetch_bytes": f, "write_bytes": w, "hbm_bytes": None if f is None or w is None else f + w,
+                     "valu_instr": mean(st["valu"]), "valu_busy": None if not st["gui"] else
+                     mean(st["active"]) * 4 / 1024 / mean(st["gui"]), "waves": mean(st["waves"])}
+    hb = [v["hbm_bytes"] for v in stages.values() if v["hbm_bytes"] is not None]
+    return {"kernel": "k_stage<float, *, 12, false>", "source_sha256": stage_source_hash(),
+            "fetch_scale": fscale, "write_scale": wscale, "stages": stages,
+            "hbm_bytes_per_launch": mean(hb),
+            "valu_instr_per_launch": mean([v["valu_instr"] for v in stages.values() if v["valu_instr"] is not None]),
+            "valu_busy": mean([v["valu_busy"] for v in stages.values() if v["valu_busy"] is not None])}
 
 
 def copy_bandwidth(mib=1024, reps=5):
@@ -303,25 +426,49 @@ def copy_bandwidth(mib=1024, reps=5):
     return gbps
 
 
-def cpu_baseline(problem):
-    """Oracle (as it stands) on one full-size RK3 step of the same workload."""
+def window_problem(p, n, nsteps):
+    """An n x n (x, z) window of problem p around its source over all theta
+    nodes, with the same spacing and medium (the cost per cell of the whole
+    grid)."""
+    import numpy as np
+
+    import workloads as W
+
+    g = p.grid
+    i0 = min(max(int(p.source.xs / g.dx) - n // 2, 0), g.nx - n)
+    k0 = min(max(int(p.source.zs / g.dz) - n // 2, 0), g.nz - n)
+    gw = W.Grid(nx=n, nz=n, nth=g.nth, dx=g.dx, dz=g.dz, x0=g.x0 + i0 * g.dx, z0=g.z0 + k0 * g.dz)
+    cut = lambda a: np.ascontiguousarray(a[i0:i0 + n, k0:k0 + n])
+    m = p.medium
+    mw = W.Medium(vp0=cut(m.vp0), eps=cut(m.eps), delta=cut(m.delta), tilt=cut(m.tilt), vs_ratio=m.vs_ratio)
+    return W.Problem(p.name + "-window", gw, mw, p.source, nsteps, p.omegas, dtype=p.dtype)
+
+
+def cpu_baseline(key, p, window, nsteps):
+    """The oracle (as it stands) on `nsteps` RK3 steps of an n x n window of
+    the workload's grid over all its theta nodes (the whole grid when the
+    window covers it), on the host cores."""
     import oracle
 
     oracle.build(force=False)
     cores = len(os.sched_getaffinity(0))
     os.environ.setdefault("OMP_NUM_THREADS", str(cores))
+    g = p.grid
+    pw = p if window >= min(g.nx, g.nz) else window_problem(p, window, nsteps)
     t0 = time.perf_counter()
-    r = oracle.solve(problem, nsteps=0)
+    r = oracle.solve(pw, nsteps=0)
     t1 = time.perf_counter()
-    oracle.march(problem.grid, r["vel"], problem.source, r["U0"], r["dt"], 1)
+    oracle.march(pw.grid, r["vel"], pw.source, r["U0"], r["dt"], nsteps)
     t2 = time.perf_counter()
-    g = problem.grid
-    return {"value": g.ncell / (t2 - t1), "unit": "cell-updates/s",
+    gw = pw.grid
+    what = "the full grid" if pw is p else f"a {gw.nx}x{gw.nz} (x, z) window of the {g.nx}x{g.nz} grid around the source"
+    return {"value": gw.ncell * nsteps / (t2 - t1), "unit": "cell-updates/s",
             "cores": int(os.environ.get("OMP_NUM_THREADS", cores)), "kind": "oracle",
-            "sample": f"one SSP-RK3 step of the full {g.nx}x{g.nz}x{g.nth} grid "
-                      f"(FP64; setup {t1 - t0:.1f} s not counted, step {t2 - t1:.1f} s)",
-            "cpu_model": cpu_model(), "value_1_thread": single_thread_oracle(),
-            "sample_1_thread": "one SSP-RK3 step of the same VTI recipe at 128^3, OMP_NUM_THREADS=1"}
+            "sample": f"{nsteps} SSP-RK3 step(s) of {what}, all {gw.nth} theta nodes, same spacing and medium "
+                      f"(FP64; setup {t1 - t0:.1f} s not counted, march {t2 - t1:.1f} s)",
+            "cpu_model": cpu_model(), "value_1_thread": single_thread_oracle(key, min(window, g.nx) // 4),
+            "sample_1_thread": f"one SSP-RK3 step of a {min(window, g.nx) // 4}^2 (x, z) window of the same "
+                               "grid, OMP_NUM_THREADS=1"}
 
 
 def cpu_model():
@@ -334,20 +481,19 @@ def cpu_model():
     return None
 
 
-def single_thread_oracle():
+def single_thread_oracle(key, window):
     """The oracle on one thread (a child process: OpenMP fixes its thread
-    count when the library loads), one RK3 step of a 128^3 grid of the same
-    recipe; cell-updates/s, None if it did not run."""
+    count when the library loads), one RK3 step of a window of the
+    workload's grid; cell-updates/s, None if it did not run."""
     import subprocess
-    import sys
 
     code = ("import sys, time; sys.path.insert(0, %r)\n"
-            "import oracle, workloads as W\n"
-            "p = W.vti_256(n=128)\n"
+            "import bench, oracle\n"
+            "p = bench.window_problem(bench.make_workload(%r), %d, 1)\n"
             "r = oracle.solve(p, nsteps=0)\n"
             "t0 = time.perf_counter()\n"
             "oracle.march(p.grid, r['vel'], p.source, r['U0'], r['dt'], 1)\n"
-            "print(p.grid.ncell / (time.perf_counter() - t0))\n") % ROOT
+            "print(p.grid.ncell / (time.perf_counter() - t0))\n") % (ROOT, key, window)
     env = dict(os.environ, OMP_NUM_THREADS="1")
     try:
         out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
@@ -356,17 +502,96 @@ def single_thread_oracle():
         return None
 
 
+def timed_passes(egb, p, steps, warmup, tune, stream):
+    """Warm-up then `steps` timed passes of the whole path on problem p:
+    medium table and velocity, point-source data, the march, the beam sum,
+    the pick at 128 receivers.  The march and the beam sum of each timed
+    pass are bracketed by HIP events on the launch stream."""
+    import numpy as np
+    import torch
+
+    L = p.grid.nx * p.grid.dx
+    rx = np.stack([np.linspace(0.1 * L, 0.9 * L, 128), np.full(128, 0.9 * L)], axis=1)
+    dev = torch.device("cuda:0")
+    s = egb.Solver(p, dev)
+    dt = s.velocity()
+    s.init()
+    # stage launch shape for this grid (results do not depend on it)
+    blocks = s.tune(reps=6) if tune else egb.egb_get_blocks(s.eg, egb.EGB_TUNE_STEP)
+    s.work_beam = egb.alloc_bytes(egb.workspace_size(s.eg, egb.EGB_OP_BEAM), dev)
+    out = torch.empty((len(p.omegas), p.grid.nx, p.grid.nz, 2), dtype=torch.float32, device=dev)
+    rx_d = torch.as_tensor(rx, device=dev)
+    t_pick = torch.empty(128, dtype=torch.float64, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    march_ms, beam_ms = [], []
+
+    def one_pass(timed):
+        s.velocity()
+        s.init()
+        if timed:
+            ev[0].record(stream)
+        s.step(p.nsteps, dt=dt)
+        if timed:
+            ev[1].record(stream)
+        s.beam(p.omegas, out=out)
+        if timed:
+            ev[2].record(stream)
+        egb.egb_pick_receivers(s.eg, s.state, rx_d, t_pick)
+        if timed:
+            ev[2].synchronize()
+            march_ms.append(ev[0].elapsed_time(ev[1]))
+            beam_ms.append(ev[1].elapsed_time(ev[2]))
+
+    for _ in range(warmup):
+        one_pass(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        one_pass(True)
+        print(f"bench: pass {i + 1}/{steps} {march_ms[-1] + beam_ms[-1]:.0f} ms on the GPU", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    finite = bool(torch.isfinite(out).all()) and bool(torch.isfinite(t_pick).any())
+    del s, out
+    torch.cuda.empty_cache()
+    return {"ms": (t1 - t0) * 1e3 / steps, "march_ms": float(np.mean(march_ms)), "beam_ms": float(np.mean(beam_ms)),
+            "blocks": blocks, "dt": dt, "finite": finite}
+
+
+def stage_roofline(p, r, rec):
+    """Roofline entry of the stage kernel from the live launch time and the
+    committed counter record (None fields when there is none)."""
+    cells = p.grid.ncell
+    stage_ms = r["march_ms"] / (3 * p.nsteps)
+    achieved = cells * FLOP_CELL_STAGE / (stage_ms * 1e-3) / 1e12
+    traffic = None if rec is None else rec["hbm_bytes_per_launch"]
+    hbm = None if traffic is None else traffic / (stage_ms * 1e-3) / 1e9
+    valu = None if rec is None or rec.get("valu_instr_per_launch") is None else rec["valu_instr_per_launch"] / cells
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+            "kernel": "k_stage (one SSP-RK3 stage)", "avg_launch_ms": stage_ms, "blocks_per_launch": r["blocks"],
+            "flop_per_cell_stage": FLOP_CELL_STAGE,
+            # FP32 arithmetic without packed (dual-lane) instructions, which this build keeps off
+            "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS, "frac_of_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS,
+            # HBM side: counter bytes over the live launch time
+            "hbm_GBps": hbm, "hbm_frac_of_8TBps": None if hbm is None else hbm / PEAK_HBM_GBPS,
+            "traffic_bytes_per_cell_stage": None if traffic is None else traffic / cells,
+            "valu_instr_per_cell_stage": valu, "valu_busy": None if rec is None else rec.get("valu_busy")}
+
+
 def main():
     args = parse()
+    if args.summarize_counters:
+        print(json.dumps(summarize_counters(*args.summarize_counters), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is a design "
               "note, not built", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_2006_11945_amd as egb
-    import workloads as W
 
     if args.calibrate_copy_mib > 0:
         n = args.calibrate_copy_mib << 18  # float32 elements
@@ -375,61 +600,16 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    p = W.vti_256(n=args.n, nsteps=args.rk_steps)
-    L = p.grid.nx * p.grid.dx
-    rx = np.stack([np.linspace(0.1 * L, 0.9 * L, 128), np.full(128, 0.9 * L)], axis=1)
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream(dev)
-    s = egb.Solver(p, dev)
-    s.velocity()
-    dt = s.dt_cfl
-    s.init()
-    # stage launch shape for this grid (results do not depend on it)
-    blocks = egb.egb_get_blocks(s.eg, egb.EGB_TUNE_STEP) if args.no_tune else s.tune(reps=6)
-    s.work_beam = egb.alloc_bytes(egb.workspace_size(s.eg, egb.EGB_OP_BEAM), dev)
-    out = torch.empty((len(p.omegas), p.grid.nx, p.grid.nz, 2), dtype=torch.float32, device=dev)
-    rx_d = torch.as_tensor(rx, device=dev)
-    t_pick = torch.empty(128, dtype=torch.float64, device=dev)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    march_ms = []
-
-    ev2 = torch.cuda.Event(enable_timing=True)
-    beam_ms = []
-
-    def one_step(timed):
-        s.velocity()
-        s.init()
-        if timed:
-            ev0.record(stream)
-        s.step(p.nsteps, dt=dt)
-        if timed:
-            ev1.record(stream)
-        s.beam(p.omegas, out=out)
-        if timed:
-            ev2.record(stream)
-        egb.egb_pick_receivers(s.eg, s.state, rx_d, t_pick)
-        if timed:
-            ev2.synchronize()
-            march_ms.append(ev0.elapsed_time(ev1))
-            beam_ms.append(ev1.elapsed_time(ev2))
-
-    for _ in range(args.warmup):
-        one_step(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        one_step(True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
+    stream = torch.cuda.current_stream(torch.device("cuda:0"))
+    p = make_workload(args.workload, args.n, args.rk_steps)
+    r = timed_passes(egb, p, args.steps, args.warmup, not args.no_tune, stream)
     cells = p.grid.ncell
-    value = cells * p.nsteps / (ms * 1e-3)
-    launches = 3 * p.nsteps
-    stage_ms = float(np.mean(march_ms)) / launches
-    achieved = cells * FLOP_CELL_STAGE / (stage_ms * 1e-3) / 1e12
-    rec = measured_counters(args.n)
-    copy_gbps = copy_bandwidth()  # after the timed region
-    hbm_gbps = None if rec is None else rec["hbm_bytes_per_launch"] / (stage_ms * 1e-3) / 1e9
+    value = cells * p.nsteps / (r["ms"] * 1e-3)
+    rec = measured_counters(args.workload, args.n)
+    g = p.grid
+    desc = WORKLOADS[args.workload] if args.n is None and args.rk_steps is None else (
+        f"{p.name} {g.nx}x{g.nz}x{g.nth}, {p.nsteps} RK3 steps, beam sum {len(p.omegas)} freqs 5-60 Hz, "
+        "128 receivers")
     res = {
         "metric": "phase-space cell-updates/s",
         "value": value,
@@ -437,46 +617,63 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": r["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"heterogeneous VTI {p.grid.nx}x{p.grid.nz}x{p.grid.nth}, {p.nsteps} RK3 steps, "
-                               f"beam sum {len(p.omegas)} freqs 5-60 Hz, 128 receivers",
-                   "grid": [p.grid.nx, p.grid.nz, p.grid.nth], "rk3_steps": p.nsteps,
-                   "frequencies": len(p.omegas), "receivers": 128, "psi_dtype": "f64"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None if rec is None else rec["hbm_bytes_per_launch"],
-                     "kernel": "k_stage (one SSP-RK3 stage)", "avg_launch_ms": stage_ms, "blocks_per_launch": blocks,
-                     "flop_per_cell_stage": FLOP_CELL_STAGE,
-                     # HBM side (counters x live launch time) against the spec and a measured device copy
-                     "hbm_GBps": hbm_gbps, "hbm_frac_of_8TBps": None if rec is None else hbm_gbps / PEAK_HBM_GBPS,
-                     "copy_GBps": copy_gbps, "hbm_frac_of_copy": None if rec is None else hbm_gbps / copy_gbps,
-                     "valu_instr_per_cell_stage": None if rec is None else rec.get("valu_instr_per_cell_stage"),
-                     "valu_busy": None if rec is None else rec.get("valu_busy")},
-        "beam_sum": {"ms": float(np.mean(beam_ms)), "frequencies": len(p.omegas),
-                     "output_point_freqs_per_s": p.grid.nx * p.grid.nz * len(p.omegas) / (np.mean(beam_ms) * 1e-3)},
-        "march_ms": float(np.mean(march_ms)),
-        "march_cell_updates_per_s": cells * p.nsteps / (float(np.mean(march_ms)) * 1e-3),
+        "config": {"workload": desc, "grid": [g.nx, g.nz, g.nth], "rk3_steps": p.nsteps,
+                   "frequencies": len(p.omegas), "receivers": 128, "psi_dtype": "f64", "tilt": args.workload == "tti512"},
+        "roofline": stage_roofline(p, r, rec),
+        "hbm_floor": {"bytes_per_cell_update": FLOOR_BYTES_PER_CELL_UPDATE,
+                      "GBps": value * FLOOR_BYTES_PER_CELL_UPDATE / 1e9,
+                      "frac_of_8TBps": value * FLOOR_BYTES_PER_CELL_UPDATE / 1e9 / PEAK_HBM_GBPS,
+                      "note": "the state read and written once per RK3 step at the whole pass's rate"},
+        "beam_sum": {"ms": r["beam_ms"], "frequencies": len(p.omegas),
+                     "output_point_freqs_per_s": g.nx * g.nz * len(p.omegas) / (r["beam_ms"] * 1e-3)},
+        "march_ms": r["march_ms"],
+        "march_cell_updates_per_s": cells * p.nsteps / (r["march_ms"] * 1e-3),
+        "outputs_finite": r["finite"],
     }
-    del s, out
-    torch.cuda.empty_cache()
-    if args.batched_steps > 0:
+    res["roofline"]["copy_GBps"] = copy_bandwidth()  # after the timed region
+    hbm = res["roofline"]["hbm_GBps"]
+    res["roofline"]["hbm_frac_of_copy"] = None if hbm is None else hbm / res["roofline"]["copy_GBps"]
+
+    def budget_ok(name, est_s):
+        if args.time_budget_s > 0 and time.perf_counter() - T_START + est_s > args.time_budget_s:
+            res[name] = {"skipped": f"time budget ({args.time_budget_s:.0f} s after the start)"}
+            return False
+        print(f"bench: leg {name} at {time.perf_counter() - T_START:.0f} s", file=sys.stderr, flush=True)
+        return True
+
+    # secondary legs, each skipped when it would end past the time budget
+    # (rough duration estimates, seconds)
+    if not args.no_cpu_baseline and budget_ok("cpu_baseline", 40):
+        win = 256 if args.workload == "tti512" and args.n is None else 10 ** 9
+        res["cpu_baseline"] = cpu_baseline(args.workload, make_workload(args.workload, args.n, 2), win,
+                                           2 if win < 10 ** 9 else 1)
+    if args.batched_steps > 0 and budget_ok("batched", 40):
         res["batched"] = batched_vs_sequential(args.batched_problems, args.batched_steps, tune=not args.no_tune)
         # many small problems: one problem alone cannot fill the chip
         res["batched_small"] = batched_vs_sequential(256, 4 * args.batched_steps, lo=32, hi=96,
                                                      tune=not args.no_tune)
         torch.cuda.empty_cache()
-    if args.adjoint_sources > 0:
-        res["adjoint"] = adjoint_vs_forward(args.adjoint_sources, args.rk_steps, args.n)
+    if args.adjoint_sources > 0 and budget_ok("adjoint", 8 + 8 * args.adjoint_sources):
+        res["adjoint"] = adjoint_vs_forward(args.adjoint_sources, 600, 256)
         torch.cuda.empty_cache()
-    if args.paraxial_sources > 0:
-        res["paraxial"] = paraxial_leg(args.n, args.paraxial_sources, migration_points=args.migration_points)
+    if args.vti_leg > 0 and args.workload != "vti256" and budget_ok("vti256", 6 + 2 * args.vti_leg):
+        pv = make_workload("vti256")
+        rv = timed_passes(egb, pv, args.vti_leg, 1, not args.no_tune, stream)
+        vv = pv.grid.ncell * pv.nsteps / (rv["ms"] * 1e-3)
+        res["vti256"] = {"workload": WORKLOADS["vti256"], "passes": args.vti_leg, "ms_per_pass": rv["ms"],
+                         "cell_updates_per_s": vv, "march_ms": rv["march_ms"], "beam_ms": rv["beam_ms"],
+                         "roofline": stage_roofline(pv, rv, measured_counters("vti256", None)),
+                         "outputs_finite": rv["finite"]}
+    if args.paraxial_sources > 0 and budget_ok("paraxial", 12):
+        res["paraxial"] = paraxial_leg(256, args.paraxial_sources, migration_points=args.migration_points)
         torch.cuda.empty_cache()
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(W.vti_256(n=args.n, nsteps=1))
+    res["wall_s"] = time.perf_counter() - T_START
     print(json.dumps(res), flush=True)
 
 
