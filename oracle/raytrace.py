@@ -273,3 +273,48 @@ def closest_approach_fields(medium, xs, zs, x, z, th, dtau=1e-3, tmax=1.0):
     psi = (np.sin(yc[2]) * dxc + np.cos(yc[2]) * dzc) / v - tc
     shape = np.shape(x)
     return phi1.reshape(shape), psi.reshape(shape)
+
+
+class GaussianLensMedium:
+    """Isotropic v(x, z) = v0 + a exp(-|x - c|^2 / (2 sigma^2)) (a < 0: a
+    low-velocity lens that focuses rays and makes caustics behind it), with
+    the Liouville velocity of eqs. 8-9 and 12 in closed form:
+    V = (v sin, v cos, -(v_x cos - v_z sin))."""
+
+    def __init__(self, v0, a, cx, cz, sigma):
+        self.v0, self.a, self.cx, self.cz, self.sig = float(v0), float(a), float(cx), float(cz), float(sigma)
+
+    def vgrad(self, x, z):
+        e = self.a * np.exp(-((x - self.cx) ** 2 + (z - self.cz) ** 2) / (2 * self.sig ** 2))
+        return self.v0 + e, -e * (x - self.cx) / self.sig ** 2, -e * (z - self.cz) / self.sig ** 2
+
+    def velocity(self, x, z, th):
+        v, vx, vz = self.vgrad(x, z)
+        sn, cs = np.sin(th), np.cos(th)
+        return np.stack([v * sn, v * cs, -(vx * cs - vz * sn)]), v
+
+
+def fan_crossings(medium, xs, zs, take_off, z_line, dtau=1e-3, tmax=5.0):
+    """Shoot rays from the source (x_s, z_s) at the phase angles `take_off`
+    (classical Runge-Kutta steps of dtau) and return, per ray, where it
+    first crosses the depth z_line going down: x, the phase angle theta and
+    the traveltime (linear between the two steps around the crossing); NaN
+    for rays that have not crossed within tmax."""
+    th0 = np.asarray(take_off, dtype=np.float64)
+    y = np.stack([np.full_like(th0, xs), np.full_like(th0, zs), th0])
+    F = lambda q: medium.velocity(q[0], q[1], q[2])[0]
+    out = np.full((3, th0.size), np.nan)
+    done = np.zeros(th0.size, bool)
+    t = 0.0
+    for _ in range(int(np.ceil(tmax / dtau))):
+        yn = _rk4(F, y, dtau)
+        cr = (~done) & (yn[1] >= z_line) & (y[1] < z_line)
+        f = (z_line - y[1][cr]) / (yn[1][cr] - y[1][cr])
+        out[0, cr] = y[0][cr] + f * (yn[0][cr] - y[0][cr])
+        out[1, cr] = y[2][cr] + f * (yn[2][cr] - y[2][cr])
+        out[2, cr] = t + f * dtau
+        done |= cr
+        y, t = yn, t + dtau
+        if done.all():
+            break
+    return out
