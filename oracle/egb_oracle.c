@@ -591,7 +591,12 @@ int oc_beam_sum(int nx, int nz, int nth, double x0, double z0, double dx, double
             for (int iz = 0; iz < nz; ++iz) {
                 long kb = (long)k * nxz, c = kb + (long)ix * nz + iz;
                 double psi = U[S_PSI * n + c];
-                if (!(psi > 0.0)) continue;
+                /* eq. 35's gate psi > 0, taken as psi above a millionth of a
+                 * cell's traveltime: the point-source data put psi = 0 in
+                 * exact arithmetic on cells at the closest point of their ray
+                 * to the source (a source on a cell corner, diagonal phase
+                 * angles), which rounding leaves at +-1e-17 either way     */
+                if (!(psi > 1e-6 * fmin(dx, dz) / vaux[0 * n + c])) continue;
                 /* 4th-order central differences of phi1 (ghost rules as in the march) */
                 double fx = (at_x(phi, phi, nx, nz, kb, ix, iz, -2) - 8.0 * at_x(phi, phi, nx, nz, kb, ix, iz, -1) +
                              8.0 * at_x(phi, phi, nx, nz, kb, ix, iz, 1) - at_x(phi, phi, nx, nz, kb, ix, iz, 2)) / (12.0 * dx);

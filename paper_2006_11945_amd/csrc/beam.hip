@@ -12,7 +12,10 @@
 // w = cos^4 / (cos^4 + sin^4) of the ray angle for rows and 1 - w for columns.
 // Cells whose line Hessian has Im(M) <= 0 give no record: a Gaussian beam
 // decays away from its centre (the exact transport keeps Im(B conj(C)) > 0,
-// a discrete field can lose it).
+// a discrete field can lose it).  The gate psi > 0 is taken as psi above
+// 1e-6 min(dx, dz) / v: the point-source data leave psi = 0 in exact
+// arithmetic (+-1e-17 after rounding) on cells at the closest point of their
+// ray to the source, and such a cell's wide beam must not hang on rounding.
 // Pass 2 (k_beam_line): for every output cell and frequency,
 //   G += amp exp(i omega T),  T = psi + p d + M d^2 / 2,
 // skipping beams with omega Im(M) d^2 / 2 > 16, and G is scaled by i/(4 pi).
@@ -112,6 +115,10 @@ __global__ __launch_bounds__(256) void k_beam_compact(BeamArgs a) {
     double sn, cs;
     sincos_d(th, &sn, &cs);
     const double v = J.v, vx = J.g[0], vz = J.g[1], vt = J.g[2];
+    // the gate psi > 0 taken as psi above a millionth of a cell's traveltime:
+    // cells at the closest point of their ray to the source hold psi = 0 in
+    // exact arithmetic and +-1e-17 after rounding
+    if (!(psi > 1e-6 * fmin(g.dx, g.dz) / v)) return;
     const double Vt = va.V[2];
     const double sp = sqrt(va.V[0] * va.V[0] + va.V[1] * va.V[1]);
     const double hxr = va.V[0] / sp, hzr = va.V[1] / sp;  // ray direction (sin, cos of its angle)
