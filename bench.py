@@ -111,8 +111,9 @@ def batched_vs_sequential(nprob, nsteps, lo=128, hi=384, tune=True):
     cells = sum(p.grid.ncell for p in probs)
     arr = egb.make_problem_array(solvers)
     work = egb.alloc_bytes(egb.workspace_size_batched(arr), "cuda:0")
-    # launch shape for this batch (results do not depend on it); 0 = the default
-    blocks = egb.egb_tune_batched(arr, work, reps=6) if tune else 0
+    # launch (tile shape and block count) for this batch; results do not depend on it
+    blocks = egb.egb_tune_batched(arr, work, reps=3) if tune else 0
+    tile_rows, _ = egb.egb_get_launch_batched(arr)
     egb.egb_liouville_step_batched(arr, 1, work)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -131,6 +132,7 @@ def batched_vs_sequential(nprob, nsteps, lo=128, hi=384, tune=True):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     return {"problems": nprob, "sizes": [lo, hi], "cells": cells, "rk3_steps": nsteps, "tuned_blocks": blocks,
+            "tuned_tile_rows": tile_rows,
             "batched_cell_updates_per_s": cells * nsteps / t_batch,
             "sequential_cell_updates_per_s": cells * nsteps / t_seq,
             "batched_over_sequential": t_seq / t_batch}
@@ -516,8 +518,10 @@ def timed_passes(egb, p, steps, warmup, tune, stream):
     s = egb.Solver(p, dev)
     dt = s.velocity()
     s.init()
-    # stage launch shape for this grid (results do not depend on it)
-    blocks = s.tune(reps=6) if tune else egb.egb_get_blocks(s.eg, egb.EGB_TUNE_STEP)
+    # stage launch (tile shape, block count) for this grid; results do not depend on it
+    if tune:
+        s.tune(reps=6)
+    tile_rows, blocks = egb.egb_get_launch(s.eg, egb.EGB_TUNE_STEP)
     s.work_beam = egb.alloc_bytes(egb.workspace_size(s.eg, egb.EGB_OP_BEAM), dev)
     out = torch.empty((len(p.omegas), p.grid.nx, p.grid.nz, 2), dtype=torch.float32, device=dev)
     rx_d = torch.as_tensor(rx, device=dev)
@@ -556,7 +560,7 @@ def timed_passes(egb, p, steps, warmup, tune, stream):
     del s, out
     torch.cuda.empty_cache()
     return {"ms": (t1 - t0) * 1e3 / steps, "march_ms": float(np.mean(march_ms)), "beam_ms": float(np.mean(beam_ms)),
-            "blocks": blocks, "dt": dt, "finite": finite}
+            "blocks": blocks, "tile_rows": tile_rows, "dt": dt, "finite": finite}
 
 
 def stage_roofline(p, r, rec):
@@ -571,6 +575,7 @@ def stage_roofline(p, r, rec):
     return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
             "kernel": "k_stage (one SSP-RK3 stage)", "avg_launch_ms": stage_ms, "blocks_per_launch": r["blocks"],
+            "tile_theta_rows": r["tile_rows"],
             "flop_per_cell_stage": FLOP_CELL_STAGE,
             # FP32 arithmetic without packed (dual-lane) instructions, which this build keeps off
             "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS, "frac_of_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS,

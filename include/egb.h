@@ -413,31 +413,56 @@ egb_status egb_migrate(const egb_grid *g, const void *G, int32_t ns, const doubl
  * Not a step of the method: the stage kernels of egb_liouville_step, its
  * kinematic variant, the reverse stages of egb_adjoint_step and
  * egb_liouville_step_batched split the (tile, x) steps of their grids into
- * one contiguous range per block, and the number of blocks per launch
- * decides only how that work is spread over the chip; every count gives
- * bit-identical results.  By default a launch uses one round of resident
- * blocks.  The library keeps a count per (operation, grid shape(s), dtype,
- * current device), process-wide behind a mutex; these calls read it, fix it
- * or measure it.  They allocate nothing on the device. */
+ * one contiguous range per block.  A launch is a tile shape (the theta rows
+ * of a (z, theta) tile of 64 z cells, with its LDS slice and halo, and the
+ * waves per SIMD its registers are sized for) and a block count; both
+ * decide only how the work is laid out over the chip, and every launch
+ * gives bit-identical results.  By default a launch uses the first tile
+ * shape and one round of resident blocks.  The library keeps a launch per
+ * (operation, grid shape(s), dtype, current device), process-wide behind a
+ * mutex; these calls read it, fix it or measure it.  They allocate nothing
+ * on the device. */
 #define EGB_TUNE_STEP 0      /* egb_liouville_step */
 #define EGB_TUNE_KINEMATIC 1 /* egb_liouville_step_kinematic, and the stages egb_adjoint_step recomputes */
 #define EGB_TUNE_ADJOINT 2   /* the reverse stages of egb_adjoint_step */
 
-/* The count in use for `op` on grids of g's shape and dtype (0 = the
+typedef struct {
+    int32_t tile_rows; /* theta rows per tile (one of egb_tile_rows); 0 = the default shape */
+    int32_t blocks;    /* blocks per launch; 0 = one round of resident blocks */
+} egb_launch;
+
+/* The tile heights `op` supports on grids of g's dtype, the default first,
+ * into rows[] (if not NULL; at most 8); returns their number (0 for bad
+ * arguments).  FP32: 12, 8, 16 rows for EGB_TUNE_STEP (at 3, 2, 4 waves per
+ * SIMD), 16, 8, 12 for EGB_TUNE_KINEMATIC; FP64 and EGB_TUNE_ADJOINT: 8. */
+int32_t egb_tile_rows(const egb_grid *g, int32_t op, int32_t *rows);
+
+/* The block count in use for `op` on grids of g's shape and dtype (0 = the
  * default); 0 also for bad arguments. */
 int32_t egb_get_blocks(const egb_grid *g, int32_t op);
 
-/* Fix the count (blocks >= 1) or restore the default (blocks = 0).
- * EGB_EINVAL for a bad grid, op or count; EGB_EHIP without a device. */
+/* Fix the count (blocks >= 1) or restore the default (blocks = 0), keeping
+ * the tile shape.  EGB_EINVAL for a bad grid, op or count; EGB_EHIP without
+ * a device. */
 egb_status egb_set_blocks(const egb_grid *g, int32_t op, int32_t blocks);
 
+/* The launch in use (tile_rows of the shape, blocks as egb_get_blocks). */
+egb_status egb_get_launch(const egb_grid *g, int32_t op, egb_launch *out);
+
+/* Fix a launch; tile_rows must be one of egb_tile_rows (0: the default
+ * shape), blocks >= 0 (0: one round of resident blocks).  EGB_EINVAL
+ * otherwise. */
+egb_status egb_set_launch(const egb_grid *g, int32_t op, const egb_launch *l);
+
 /* The autotuner for op = EGB_TUNE_STEP or EGB_TUNE_KINEMATIC: times `reps`
- * (>= 1) RK3 steps at each candidate count (the default and 1/2 to 3 rounds
- * of resident blocks) with HIP events on `stream`, and keeps the fastest for
- * this shape (the default unless another is faster by more than 1 %),
- * returned in *blocks.  Arguments as egb_liouville_step; the timed steps
- * read `state` and write only `work` (the last stage too), so no buffer of
- * the caller changes.  Synchronises `stream`. */
+ * (>= 1) RK3 steps with HIP events on `stream`, first of every tile shape
+ * at its default block count, then of the fastest shape at the default and
+ * 1/2 to 3 rounds of resident blocks, and keeps the fastest launch for this
+ * grid shape (a candidate replaces the default only when faster by more
+ * than 1 %); *blocks receives the count (egb_get_launch the shape).
+ * Arguments as egb_liouville_step; the timed steps read `state` and write
+ * only `work` (the last stage too), so no buffer of the caller changes.
+ * Synchronises `stream`. */
 egb_status egb_tune_step(const egb_grid *g, const void *vel3d, const egb_source *src, const void *bdata,
                          const void *state, void *work, size_t work_bytes, double dt, int32_t op, int32_t reps,
                          hipStream_t stream, int32_t *blocks);
@@ -450,6 +475,10 @@ egb_status egb_tune_batched(const egb_problem *probs, int32_t nprob, void *work,
 
 /* Fix (blocks >= 1) or restore (0) the count of a batch of this shape. */
 egb_status egb_set_blocks_batched(const egb_problem *probs, int32_t nprob, int32_t blocks);
+
+/* The launch of a batch of this shape (tile heights as EGB_TUNE_STEP's). */
+egb_status egb_get_launch_batched(const egb_problem *probs, int32_t nprob, egb_launch *out);
+egb_status egb_set_launch_batched(const egb_problem *probs, int32_t nprob, const egb_launch *l);
 
 /* Human-readable text for a status code (static storage). */
 const char *egb_status_string(int32_t status);

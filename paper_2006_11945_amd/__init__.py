@@ -56,6 +56,10 @@ class EgbProblem(ctypes.Structure):
                 ("state", ctypes.c_void_p), ("dt", ctypes.c_double)]
 
 
+class EgbLaunch(ctypes.Structure):
+    _fields_ = [("tile_rows", ctypes.c_int32), ("blocks", ctypes.c_int32)]
+
+
 class EgbError(RuntimeError):
     def __init__(self, fn: str, status: int):
         super().__init__(f"{fn} failed: {status} ({_lib.egb_status_string(status).decode()})")
@@ -114,7 +118,15 @@ def _load():
     L.egb_tune_step.argtypes = [G, vp, S, vp, vp, vp, sz, d, i32, i32, vp, ctypes.POINTER(i32)]
     L.egb_tune_batched.argtypes = [P, i32, vp, sz, i32, vp, ctypes.POINTER(i32)]
     L.egb_set_blocks_batched.argtypes = [P, i32, i32]
-    for name in ("egb_set_blocks", "egb_tune_step", "egb_tune_batched", "egb_set_blocks_batched"):
+    LP = ctypes.POINTER(EgbLaunch)
+    L.egb_tile_rows.argtypes = [G, i32, ctypes.POINTER(i32)]
+    L.egb_tile_rows.restype = i32
+    L.egb_get_launch.argtypes = [G, i32, LP]
+    L.egb_set_launch.argtypes = [G, i32, LP]
+    L.egb_get_launch_batched.argtypes = [P, i32, LP]
+    L.egb_set_launch_batched.argtypes = [P, i32, LP]
+    for name in ("egb_set_blocks", "egb_tune_step", "egb_tune_batched", "egb_set_blocks_batched", "egb_get_launch",
+                 "egb_set_launch", "egb_get_launch_batched", "egb_set_launch_batched"):
         getattr(L, name).restype = ctypes.c_int
     L.egb_status_string.argtypes = [i32]; L.egb_status_string.restype = ctypes.c_char_p
     return L
@@ -380,6 +392,36 @@ def egb_tune_batched(arr, work, reps: int = 3, stream=None) -> int:
 
 def egb_set_blocks_batched(arr, blocks: int):
     _check("egb_set_blocks_batched", _lib.egb_set_blocks_batched(arr, len(arr), int(blocks)))
+
+
+def egb_tile_rows(eg, op: int) -> list:
+    """Tile heights (theta rows per tile) `op` supports on this grid's dtype, the default first."""
+    rows = (ctypes.c_int32 * 8)()
+    n = _lib.egb_tile_rows(ctypes.byref(eg), int(op), rows)
+    return [rows[i] for i in range(n)]
+
+
+def egb_get_launch(eg, op: int) -> tuple:
+    """(tile_rows, blocks) in use for `op` on this grid shape (blocks 0: the default)."""
+    l = EgbLaunch()
+    _check("egb_get_launch", _lib.egb_get_launch(ctypes.byref(eg), int(op), ctypes.byref(l)))
+    return l.tile_rows, l.blocks
+
+
+def egb_set_launch(eg, op: int, tile_rows: int, blocks: int = 0):
+    l = EgbLaunch(int(tile_rows), int(blocks))
+    _check("egb_set_launch", _lib.egb_set_launch(ctypes.byref(eg), int(op), ctypes.byref(l)))
+
+
+def egb_get_launch_batched(arr) -> tuple:
+    l = EgbLaunch()
+    _check("egb_get_launch_batched", _lib.egb_get_launch_batched(arr, len(arr), ctypes.byref(l)))
+    return l.tile_rows, l.blocks
+
+
+def egb_set_launch_batched(arr, tile_rows: int, blocks: int = 0):
+    l = EgbLaunch(int(tile_rows), int(blocks))
+    _check("egb_set_launch_batched", _lib.egb_set_launch_batched(arr, len(arr), ctypes.byref(l)))
 
 
 # ------------------------------------------------------------------ views

@@ -223,20 +223,20 @@ static egb_status liouville_steps(const egb_grid* g, const void* vel3d, const eg
     sa.xs = src->xs;
     sa.zs = src->zs;
     sa.r02 = src->r0 * src->r0;
-    const int blocks = tuned_blocks(kin ? EGB_TUNE_KINEMATIC : EGB_TUNE_STEP, grid_shape_key(*g), g->dtype);
+    const Launch L = tuned_launch(kin ? EGB_TUNE_KINEMATIC : EGB_TUNE_STEP, grid_shape_key(*g), g->dtype);
     for (int n = 0; n < nsteps; ++n) {
         sa.U0 = state;
         sa.Uin = state;
         sa.Uout = U1;
-        hipError_t e = launch_stage(sa, g->dtype, 0, stream, kin, blocks);
+        hipError_t e = launch_stage(sa, g->dtype, 0, stream, kin, L.blocks, L.shape);
         if (e != hipSuccess) return EGB_EHIP;
         sa.Uin = U1;
         sa.Uout = U2;
-        e = launch_stage(sa, g->dtype, 1, stream, kin, blocks);
+        e = launch_stage(sa, g->dtype, 1, stream, kin, L.blocks, L.shape);
         if (e != hipSuccess) return EGB_EHIP;
         sa.Uin = U2;
         sa.Uout = state;
-        e = launch_stage(sa, g->dtype, 2, stream, kin, blocks);
+        e = launch_stage(sa, g->dtype, 2, stream, kin, L.blocks, L.shape);
         if (e != hipSuccess) return EGB_EHIP;
     }
     return EGB_OK;
@@ -298,12 +298,13 @@ egb_status egb_adjoint_step(const egb_grid* g, const void* vel3d, const egb_sour
     sa.Uin = state_n;
     sa.Uout = U1;
     const unsigned long long key = grid_shape_key(*g);
-    const int kb = tuned_blocks(EGB_TUNE_KINEMATIC, key, g->dtype), ab = tuned_blocks(EGB_TUNE_ADJOINT, key, g->dtype);
-    hipError_t e = launch_stage(sa, g->dtype, 0, stream, true, kb);
+    const Launch kl = tuned_launch(EGB_TUNE_KINEMATIC, key, g->dtype);
+    const int ab = tuned_launch(EGB_TUNE_ADJOINT, key, g->dtype).blocks;
+    hipError_t e = launch_stage(sa, g->dtype, 0, stream, true, kl.blocks, kl.shape);
     if (e == hipSuccess) {
         sa.Uin = U1;
         sa.Uout = U2;
-        e = launch_stage(sa, g->dtype, 1, stream, true, kb);
+        e = launch_stage(sa, g->dtype, 1, stream, true, kl.blocks, kl.shape);
     }
     const double r02 = src->r0 * src->r0;
     // Reverse: stage 2 (input U2), stage 1 (input U1), stage 0 (input U^n).
@@ -511,7 +512,8 @@ size_t egb_workspace_size_batched(const egb_problem* probs, int32_t nprob) {
 // Validate a batch and write its item table and step offsets into the
 // workspace (item table | wfirst[] | per-problem U1, U2).
 static egb_status prepare_batch(const egb_problem* probs, int32_t nprob, void* work, size_t work_bytes,
-                                char*& d_items, long long*& d_first, long long& total, bool last_to_work = false) {
+                                char*& d_items, long long*& d_first, long long& total, bool last_to_work = false,
+                                int shape = 0) {
     const int dtype = probs[0].grid.dtype;
     if (!work || !aligned16(work)) return EGB_EINVAL;
     if (work_bytes < egb_workspace_size_batched(probs, nprob)) return EGB_EWORKSPACE;
@@ -529,7 +531,7 @@ static egb_status prepare_batch(const egb_problem* probs, int32_t nprob, void* w
         bufs += 2 * sb;
         const long long n = batch_item_fill(items.data() + (size_t)p * batch_item_bytes(), grid_args(q.grid), dtype,
                                             q.vel3d, q.bdata, q.state, U1, U2, q.dt, q.src.xs, q.src.zs,
-                                            q.src.r0 * q.src.r0, last_to_work);
+                                            q.src.r0 * q.src.r0, last_to_work, shape);
         first[p + 1] = first[p] + n;
     }
     total = first[nprob];
@@ -563,11 +565,12 @@ egb_status egb_liouville_step_batched(const egb_problem* probs, int32_t nprob, i
     char* d_items = nullptr;
     long long* d_first = nullptr;
     long long total = 0;
-    st = prepare_batch(probs, nprob, work, work_bytes, d_items, d_first, total);
+    // one round of resident blocks of the default tile over all problems'
+    // steps unless a launch is tuned or fixed for this batch
+    const Launch L = tuned_launch(TUNE_BATCHED, batch_shape_key(probs, nprob), dtype);
+    st = prepare_batch(probs, nprob, work, work_bytes, d_items, d_first, total, false, L.shape);
     if (st != EGB_OK) return st;
-    // one round of resident blocks over all problems' steps unless a count
-    // is tuned or fixed for this batch shape
-    const int grid = tuned_blocks(TUNE_BATCHED, batch_shape_key(probs, nprob), dtype);
+    const int grid = L.blocks;
     // capture the whole march in one graph on a private stream, replay on `stream`
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
@@ -578,7 +581,7 @@ egb_status egb_liouville_step_batched(const egb_problem* probs, int32_t nprob, i
         hipError_t le = hipSuccess;
         for (int n = 0; n < nsteps && le == hipSuccess; ++n)
             for (int s = 0; s < 3 && le == hipSuccess; ++s)
-                le = launch_stage_batched(d_items, d_first, nprob, total, dtype, s, grid, cs);
+                le = launch_stage_batched(d_items, d_first, nprob, total, dtype, s, grid, cs, L.shape);
         e = hipStreamEndCapture(cs, &graph);
         if (e == hipSuccess) e = le;
     }
@@ -619,14 +622,61 @@ egb_status egb_migrate(const egb_grid* g, const void* G, int32_t ns, const doubl
 // ------------------------------------------------------------ launch tuning
 static bool tune_op_ok(int32_t op) { return op == EGB_TUNE_STEP || op == EGB_TUNE_KINEMATIC || op == EGB_TUNE_ADJOINT; }
 
+// Tile heights of an operation's shapes (the reverse stages have one).
+static int op_shapes(const egb_grid* g, int32_t op, int* rows) {
+    if (op == EGB_TUNE_ADJOINT) {
+        if (rows) rows[0] = 8;
+        return 1;
+    }
+    return stage_shapes(g->dtype, op == EGB_TUNE_KINEMATIC, rows);
+}
+
 int32_t egb_get_blocks(const egb_grid* g, int32_t op) {
     if (!grid_ok(g) || !tune_op_ok(op)) return 0;
-    return tuned_blocks(op, grid_shape_key(*g), g->dtype);
+    return tuned_launch(op, grid_shape_key(*g), g->dtype).blocks;
 }
 
 egb_status egb_set_blocks(const egb_grid* g, int32_t op, int32_t blocks) {
     if (!grid_ok(g) || !tune_op_ok(op) || blocks < 0) return EGB_EINVAL;
-    return set_tuned_blocks(op, grid_shape_key(*g), g->dtype, blocks) == hipSuccess ? EGB_OK : EGB_EHIP;
+    Launch l = tuned_launch(op, grid_shape_key(*g), g->dtype);
+    l.blocks = blocks;
+    return set_tuned_launch(op, grid_shape_key(*g), g->dtype, l) == hipSuccess ? EGB_OK : EGB_EHIP;
+}
+
+int32_t egb_tile_rows(const egb_grid* g, int32_t op, int32_t* rows) {
+    if (!grid_ok(g) || !tune_op_ok(op)) return 0;
+    int r[8] = {0};
+    const int n = op_shapes(g, op, r);
+    if (rows)
+        for (int i = 0; i < n; ++i) rows[i] = r[i];
+    return n;
+}
+
+static int shape_of_rows(const int* r, int n, int32_t tile_rows) {
+    if (tile_rows == 0) return 0;
+    for (int i = 0; i < n; ++i)
+        if (r[i] == tile_rows) return i;
+    return -1;
+}
+
+egb_status egb_get_launch(const egb_grid* g, int32_t op, egb_launch* out) {
+    if (!grid_ok(g) || !tune_op_ok(op) || !out) return EGB_EINVAL;
+    int r[8] = {0};
+    op_shapes(g, op, r);
+    const Launch l = tuned_launch(op, grid_shape_key(*g), g->dtype);
+    out->tile_rows = r[l.shape];
+    out->blocks = l.blocks;
+    return EGB_OK;
+}
+
+egb_status egb_set_launch(const egb_grid* g, int32_t op, const egb_launch* l) {
+    if (!grid_ok(g) || !tune_op_ok(op) || !l || l->blocks < 0) return EGB_EINVAL;
+    int r[8] = {0};
+    const int n = op_shapes(g, op, r);
+    const int sh = shape_of_rows(r, n, l->tile_rows);
+    if (sh < 0) return EGB_EINVAL;
+    return set_tuned_launch(op, grid_shape_key(*g), g->dtype, Launch{l->blocks, sh}) == hipSuccess ? EGB_OK
+                                                                                                   : EGB_EHIP;
 }
 
 egb_status egb_tune_step(const egb_grid* g, const void* vel3d, const egb_source* src, const void* bdata,
@@ -659,13 +709,30 @@ egb_status egb_tune_step(const egb_grid* g, const void* vel3d, const egb_source*
     st[1].Uout = U2;
     st[2].Uin = U2;
     st[2].Uout = U1;
-    int best = 0;
+    Launch best{0, 0};
     hipError_t e = tune_stage(st, g->dtype, op == EGB_TUNE_KINEMATIC, reps, stream, best);
-    if (e == hipSuccess) e = set_tuned_blocks(op, grid_shape_key(*g), g->dtype, best);
+    if (e == hipSuccess) e = set_tuned_launch(op, grid_shape_key(*g), g->dtype, best);
     if (e != hipSuccess) return hip_status(e);
-    *blocks = best;
+    *blocks = best.blocks;
     return EGB_OK;
 }
+
+namespace {
+// Re-fill the device item table of a batch for a launch shape (tuning).
+struct BatchFill {
+    const egb_problem* probs;
+    int32_t nprob;
+    void* work;
+    size_t work_bytes;
+};
+hipError_t refill_batch(void* ctx, int shape, long long& total) {
+    BatchFill& f = *static_cast<BatchFill*>(ctx);
+    char* d_items = nullptr;
+    long long* d_first = nullptr;
+    const egb_status st = prepare_batch(f.probs, f.nprob, f.work, f.work_bytes, d_items, d_first, total, true, shape);
+    return st == EGB_OK ? hipSuccess : hipErrorInvalidValue;
+}
+}  // namespace
 
 egb_status egb_tune_batched(const egb_problem* probs, int32_t nprob, void* work, size_t work_bytes, int32_t reps,
                             hipStream_t stream, int32_t* blocks) {
@@ -678,11 +745,12 @@ egb_status egb_tune_batched(const egb_problem* probs, int32_t nprob, void* work,
     long long total = 0;
     st = prepare_batch(probs, nprob, work, work_bytes, d_items, d_first, total, true);
     if (st != EGB_OK) return st;
-    int best = 0;
-    hipError_t e = tune_batched(d_items, d_first, nprob, total, dtype, reps, stream, best);
-    if (e == hipSuccess) e = set_tuned_blocks(TUNE_BATCHED, batch_shape_key(probs, nprob), dtype, best);
+    BatchFill f{probs, nprob, work, work_bytes};
+    Launch best{0, 0};
+    hipError_t e = tune_batched(d_items, d_first, nprob, dtype, reps, stream, refill_batch, &f, best);
+    if (e == hipSuccess) e = set_tuned_launch(TUNE_BATCHED, batch_shape_key(probs, nprob), dtype, best);
     if (e != hipSuccess) return hip_status(e);
-    *blocks = best;
+    *blocks = best.blocks;
     return EGB_OK;
 }
 
@@ -690,7 +758,34 @@ egb_status egb_set_blocks_batched(const egb_problem* probs, int32_t nprob, int32
     egb_status st = batch_ok(probs, nprob);
     if (st != EGB_OK) return st;
     if (blocks < 0) return EGB_EINVAL;
-    return set_tuned_blocks(TUNE_BATCHED, batch_shape_key(probs, nprob), probs[0].grid.dtype, blocks) == hipSuccess
+    const int dtype = probs[0].grid.dtype;
+    Launch l = tuned_launch(TUNE_BATCHED, batch_shape_key(probs, nprob), dtype);
+    l.blocks = blocks;
+    return set_tuned_launch(TUNE_BATCHED, batch_shape_key(probs, nprob), dtype, l) == hipSuccess ? EGB_OK : EGB_EHIP;
+}
+
+egb_status egb_get_launch_batched(const egb_problem* probs, int32_t nprob, egb_launch* out) {
+    egb_status st = batch_ok(probs, nprob);
+    if (st != EGB_OK) return st;
+    if (!out) return EGB_EINVAL;
+    int r[8] = {0};
+    batched_shapes(probs[0].grid.dtype, r);
+    const Launch l = tuned_launch(TUNE_BATCHED, batch_shape_key(probs, nprob), probs[0].grid.dtype);
+    out->tile_rows = r[l.shape];
+    out->blocks = l.blocks;
+    return EGB_OK;
+}
+
+egb_status egb_set_launch_batched(const egb_problem* probs, int32_t nprob, const egb_launch* l) {
+    egb_status st = batch_ok(probs, nprob);
+    if (st != EGB_OK) return st;
+    if (!l || l->blocks < 0) return EGB_EINVAL;
+    int r[8] = {0};
+    const int n = batched_shapes(probs[0].grid.dtype, r);
+    const int sh = shape_of_rows(r, n, l->tile_rows);
+    if (sh < 0) return EGB_EINVAL;
+    return set_tuned_launch(TUNE_BATCHED, batch_shape_key(probs, nprob), probs[0].grid.dtype, Launch{l->blocks, sh}) ==
+                   hipSuccess
                ? EGB_OK
                : EGB_EHIP;
 }

@@ -82,26 +82,38 @@ struct StageArgs {
 // Blocks of `kernel` (launched with `threads` threads) that the current device
 // holds at once; 0 on a HIP error.
 int resident_blocks(const void* kernel, int threads);
+// Launch shapes of the stage kernels: theta rows per tile (and the waves per
+// SIMD their registers are sized for); shape 0 is the default.  The number
+// of shapes for (dtype, kinematic); their tile heights in tile_rows (if not
+// NULL, at least 4 entries).
+int stage_shapes(int dtype, bool kinematic, int* tile_rows);
+int batched_shapes(int dtype, int* tile_rows);
 // kinematic: march phi1 and psi only (the planes a traveltime depends on)
 // blocks <= 0: one round of resident blocks; > 0: the steps split over that many
 hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s, bool kinematic = false,
-                        int blocks = 0);
+                        int blocks = 0, int shape = 0);
 // resident blocks of the stage kernel (one round) and its (tile, x) steps on grid g
-void stage_limits(const GridArgs& g, int dtype, bool kinematic, long long& resident, long long& work);
-long long batched_resident(int dtype);
+void stage_limits(const GridArgs& g, int dtype, bool kinematic, long long& resident, long long& work, int shape = 0);
+long long batched_resident(int dtype, int shape = 0);
 
 // Launch-shape cache and autotuner (tune.hip).  Operation ids: the public
 // EGB_TUNE_* values, and TUNE_BATCHED for a batch keyed by all its grids.
 constexpr int TUNE_BATCHED = 3;
+struct Launch {
+    int blocks;  // 0: one round of resident blocks
+    int shape;   // index into the shapes of the operation (0: default)
+};
 unsigned long long grid_shape_key(const egb_grid& g);
 unsigned long long batch_shape_key(const egb_problem* p, int n);
-int tuned_blocks(int op, unsigned long long shape, int dtype);  // 0: none (the default)
-hipError_t set_tuned_blocks(int op, unsigned long long shape, int dtype, int blocks);  // blocks <= 0: forget
-// the fastest block count for the three stages a[0..2] of one RK3 step
-// (each writes only its Uout)
-hipError_t tune_stage(const StageArgs (&a)[3], int dtype, bool kinematic, int reps, hipStream_t s, int& best);
-hipError_t tune_batched(const void* items, const long long* wfirst, int nprob, long long total, int dtype, int reps,
-                        hipStream_t s, int& best);
+Launch tuned_launch(int op, unsigned long long shape, int dtype);  // {0, 0}: none (the default)
+hipError_t set_tuned_launch(int op, unsigned long long shape, int dtype, Launch l);  // {<= 0, 0}: forget
+// the fastest launch for the three stages a[0..2] of one RK3 step (each
+// writes only its Uout): every shape at its default count, then block
+// counts for the fastest shape
+hipError_t tune_stage(const StageArgs (&a)[3], int dtype, bool kinematic, int reps, hipStream_t s, Launch& best);
+// `fill(shape)` rewrites the batch items for a shape (tile counts change)
+hipError_t tune_batched(const void* items, const long long* wfirst, int nprob, int dtype, int reps, hipStream_t s,
+                        hipError_t (*fill)(void* ctx, int shape, long long& total), void* ctx, Launch& best);
 // The stage kernel addresses each array with 32-bit byte offsets.
 bool stage_fits_32bit(const GridArgs& g, int dtype);
 
@@ -109,10 +121,11 @@ bool stage_fits_32bit(const GridArgs& g, int dtype);
 size_t batch_item_bytes();
 // last_to_work: the last stage writes U1 instead of the state (timing runs)
 long long batch_item_fill(void* item, const GridArgs& g, int dtype, const void* vel, const void* bd, void* state,
-                          void* U1, void* U2, double dt, double xs, double zs, double r02, bool last_to_work = false);
+                          void* U1, void* U2, double dt, double xs, double zs, double r02, bool last_to_work = false,
+                          int shape = 0);
 // grid <= 0: one round of resident blocks
 hipError_t launch_stage_batched(const void* items, const long long* wfirst, int nprob, long long total, int dtype,
-                                int stage, int grid, hipStream_t s);
+                                int stage, int grid, hipStream_t s, int shape = 0);
 
 // Adjoint of the kinematic march (see adjoint.hip).
 // One reverse stage: lam_in (stages 1, 2) and acc_out = acc_in + ... (see

@@ -38,9 +38,6 @@
 namespace egb {
 namespace {
 
-#ifndef WAVES_PER_EU
-#define WAVES_PER_EU 3
-#endif
 constexpr int PZ = TZ + 6;   // padded LDS row
 
 // Tiles of one problem: ntz x ntk (z, theta) tiles; the batched queue also
@@ -355,8 +352,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
     }
 }
 
-template <typename R, int STAGE, int TK, bool KIN>
-__global__ __launch_bounds__(64 * TK) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
+// TK theta rows per tile (one wave each), WPE waves per SIMD the register
+// allocation is sized for (the launch shapes of the autotuner)
+template <typename R, int STAGE, int TK, bool KIN, int WPE>
+__global__ __launch_bounds__(64 * TK) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_stage(StageArgs a, TileArgs t) {
     __shared__ StageSmem<R, TK, KIN ? 1 : 5> sm;
     // The (tile, x) steps, x fastest, split into gridDim.x equal contiguous
@@ -387,8 +386,8 @@ struct BatchItem {
 
 constexpr long long MIN_STEPS = 16;  // fewest x steps worth a block's prologue
 
-template <typename R, int STAGE, int TK>
-__global__ __launch_bounds__(64 * TK) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU)))
+template <typename R, int STAGE, int TK, int WPE>
+__global__ __launch_bounds__(64 * TK) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_stage_batched(const BatchItem* __restrict__ items, const long long* __restrict__ wfirst, int nprob) {
     __shared__ StageSmem<R, TK, 5> sm;
     const long long W = wfirst[nprob];
@@ -422,7 +421,7 @@ unsigned long long bd_bytes_of(const GridArgs& g, size_t es) {
     return (unsigned long long)g.bstride * (5ull * es + 8ull);
 }
 
-template <typename R, int TK, bool KIN>
+template <typename R, int TK, bool KIN, int WPE>
 hipError_t launch_stage_t(const StageArgs& a, int stage, hipStream_t s, int blocks) {
     TileArgs t;
     t.ntz = (a.g.nz + TZ - 1) / TZ;
@@ -432,8 +431,8 @@ hipError_t launch_stage_t(const StageArgs& a, int stage, hipStream_t s, int bloc
     t.state_bytes = (unsigned)state_bytes_of(a.g, sizeof(R));
     t.vel_bytes = (unsigned)(7ull * (unsigned long long)a.g.stride * sizeof(R));
     t.bd_bytes = (unsigned)bd_bytes_of(a.g, sizeof(R));
-    const void* k = stage == 0 ? (const void*)k_stage<R, 0, TK, KIN>
-                  : stage == 1 ? (const void*)k_stage<R, 1, TK, KIN> : (const void*)k_stage<R, 2, TK, KIN>;
+    const void* k = stage == 0 ? (const void*)k_stage<R, 0, TK, KIN, WPE>
+                  : stage == 1 ? (const void*)k_stage<R, 1, TK, KIN, WPE> : (const void*)k_stage<R, 2, TK, KIN, WPE>;
     // by default one round of resident blocks, each with at least MIN_STEPS
     // x steps; `blocks` > 0 (a tuned or fixed count) splits the steps over
     // that many blocks instead (the results do not depend on the split)
@@ -445,18 +444,18 @@ hipError_t launch_stage_t(const StageArgs& a, int stage, hipStream_t s, int bloc
     t.nblocks = (int)G;
     const dim3 grid((unsigned)G), block(TZ, TK);
     switch (stage) {
-        case 0: k_stage<R, 0, TK, KIN><<<grid, block, 0, s>>>(a, t); break;
-        case 1: k_stage<R, 1, TK, KIN><<<grid, block, 0, s>>>(a, t); break;
-        default: k_stage<R, 2, TK, KIN><<<grid, block, 0, s>>>(a, t); break;
+        case 0: k_stage<R, 0, TK, KIN, WPE><<<grid, block, 0, s>>>(a, t); break;
+        case 1: k_stage<R, 1, TK, KIN, WPE><<<grid, block, 0, s>>>(a, t); break;
+        default: k_stage<R, 2, TK, KIN, WPE><<<grid, block, 0, s>>>(a, t); break;
     }
     return hipGetLastError();
 }
 
-template <typename R, int TK>
+template <typename R, int TK, int WPE>
 hipError_t launch_batched_t(const void* items, const long long* wfirst, int nprob, long long total, int stage,
                             int grid, hipStream_t s) {
-    const void* k = stage == 0 ? (const void*)k_stage_batched<R, 0, TK>
-                  : stage == 1 ? (const void*)k_stage_batched<R, 1, TK> : (const void*)k_stage_batched<R, 2, TK>;
+    const void* k = stage == 0 ? (const void*)k_stage_batched<R, 0, TK, WPE>
+                  : stage == 1 ? (const void*)k_stage_batched<R, 1, TK, WPE> : (const void*)k_stage_batched<R, 2, TK, WPE>;
     // one round of resident blocks, each with at least MIN_STEPS x steps
     long long G = grid > 0 ? grid : resident_blocks(k, 64 * TK);
     if (G <= 0) return hipErrorInvalidDeviceFunction;
@@ -465,9 +464,9 @@ hipError_t launch_batched_t(const void* items, const long long* wfirst, int npro
     const dim3 block(TZ, TK);
     const BatchItem* it = static_cast<const BatchItem*>(items);
     switch (stage) {
-        case 0: k_stage_batched<R, 0, TK><<<(unsigned)G, block, 0, s>>>(it, wfirst, nprob); break;
-        case 1: k_stage_batched<R, 1, TK><<<(unsigned)G, block, 0, s>>>(it, wfirst, nprob); break;
-        default: k_stage_batched<R, 2, TK><<<(unsigned)G, block, 0, s>>>(it, wfirst, nprob); break;
+        case 0: k_stage_batched<R, 0, TK, WPE><<<(unsigned)G, block, 0, s>>>(it, wfirst, nprob); break;
+        case 1: k_stage_batched<R, 1, TK, WPE><<<(unsigned)G, block, 0, s>>>(it, wfirst, nprob); break;
+        default: k_stage_batched<R, 2, TK, WPE><<<(unsigned)G, block, 0, s>>>(it, wfirst, nprob); break;
     }
     return hipGetLastError();
 }
@@ -495,11 +494,55 @@ int resident_blocks(const void* kernel, int threads) {
 
 size_t batch_item_bytes() { return sizeof(BatchItem); }
 
+// Launch shapes: theta rows per tile and the waves per SIMD the kernel's
+// registers are sized for.  Shape 0 is the default.  A shape changes only how
+// the (tile, x) steps are laid out over the chip: every shape gives
+// bit-identical results.
+namespace {
+struct ShapeDef {
+    int tk, wpe;
+};
+// FP32 full-plane march and batched march: 12 rows at 3 waves per SIMD (one
+// 12-wave block per CU, <= 168 VGPRs), 8 rows at 2 (one 8-wave block, no
+// register limit below 256), 16 rows at 4 (one 16-wave block, <= 128 VGPRs)
+constexpr ShapeDef SHAPES_F32[] = {{12, 3}, {8, 2}, {16, 4}};
+// FP32 kinematic march (two planes, about 100 VGPRs)
+constexpr ShapeDef SHAPES_KIN[] = {{16, 4}, {8, 4}, {12, 3}};
+// FP64 grids: 8 rows (the full-plane kernel needs about 250 VGPRs)
+constexpr ShapeDef SHAPES_F64[] = {{8, 2}};
+constexpr ShapeDef SHAPES_F64_KIN[] = {{8, 3}};
+
+template <size_t N>
+int shape_count(const ShapeDef (&)[N]) { return (int)N; }
+
+const ShapeDef* shapes_of(int dtype, bool kin, int& n) {
+    if (dtype == EGB_F64) {
+        n = kin ? shape_count(SHAPES_F64_KIN) : shape_count(SHAPES_F64);
+        return kin ? SHAPES_F64_KIN : SHAPES_F64;
+    }
+    n = kin ? shape_count(SHAPES_KIN) : shape_count(SHAPES_F32);
+    return kin ? SHAPES_KIN : SHAPES_F32;
+}
+}  // namespace
+
+int stage_shapes(int dtype, bool kinematic, int* tile_rows) {
+    int n = 0;
+    const ShapeDef* sh = shapes_of(dtype, kinematic, n);
+    if (tile_rows)
+        for (int i = 0; i < n; ++i) tile_rows[i] = sh[i].tk;
+    return n;
+}
+
+int batched_shapes(int dtype, int* tile_rows) { return stage_shapes(dtype, false, tile_rows); }
+
 // Fill the host-side item for one problem; returns its (tile, x) step count.
 long long batch_item_fill(void* item, const GridArgs& g, int dtype, const void* vel, const void* bd, void* state,
-                          void* U1, void* U2, double dt, double xs, double zs, double r02, bool last_to_work) {
+                          void* U1, void* U2, double dt, double xs, double zs, double r02, bool last_to_work,
+                          int shape) {
     BatchItem& it = *static_cast<BatchItem*>(item);
-    const int tk = dtype == EGB_F64 ? 8 : 12;
+    int n = 0;
+    const ShapeDef* sh = shapes_of(dtype, false, n);
+    const int tk = sh[shape >= 0 && shape < n ? shape : 0].tk;
     const size_t es = dtype == EGB_F64 ? 8 : 4;
     TileArgs t;
     t.ntz = (g.nz + TZ - 1) / TZ;
@@ -529,9 +572,13 @@ long long batch_item_fill(void* item, const GridArgs& g, int dtype, const void* 
 }
 
 hipError_t launch_stage_batched(const void* items, const long long* wfirst, int nprob, long long total, int dtype,
-                                int stage, int grid, hipStream_t s) {
-    if (dtype == EGB_F64) return launch_batched_t<double, 8>(items, wfirst, nprob, total, stage, grid, s);
-    return launch_batched_t<float, 12>(items, wfirst, nprob, total, stage, grid, s);
+                                int stage, int grid, hipStream_t s, int shape) {
+    if (dtype == EGB_F64) return launch_batched_t<double, 8, 2>(items, wfirst, nprob, total, stage, grid, s);
+    switch (shape) {
+        case 1: return launch_batched_t<float, 8, 2>(items, wfirst, nprob, total, stage, grid, s);
+        case 2: return launch_batched_t<float, 16, 4>(items, wfirst, nprob, total, stage, grid, s);
+        default: return launch_batched_t<float, 12, 3>(items, wfirst, nprob, total, stage, grid, s);
+    }
 }
 
 bool stage_fits_32bit(const GridArgs& g, int dtype) {
@@ -539,33 +586,59 @@ bool stage_fits_32bit(const GridArgs& g, int dtype) {
     return state_bytes_of(g, es) < (1ull << 32) && 7ull * (unsigned long long)g.stride * es < (1ull << 32);
 }
 
-hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s, bool kinematic, int blocks) {
+hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s, bool kinematic, int blocks,
+                        int shape) {
     if (dtype == EGB_F64)
-        return kinematic ? launch_stage_t<double, 8, true>(a, stage, s, blocks)
-                         : launch_stage_t<double, 8, false>(a, stage, s, blocks);
-    return kinematic ? launch_stage_t<float, 16, true>(a, stage, s, blocks)
-                     : launch_stage_t<float, 12, false>(a, stage, s, blocks);
-}
-
-template <typename R, int TK, bool KIN>
-void stage_limits_t(const GridArgs& g, long long& resident, long long& work) {
-    resident = resident_blocks((const void*)k_stage<R, 0, TK, KIN>, 64 * TK);
-    work = (long long)((g.nz + TZ - 1) / TZ) * ((g.nth + TK - 1) / TK) * g.nx;
-}
-
-void stage_limits(const GridArgs& g, int dtype, bool kinematic, long long& resident, long long& work) {
-    if (dtype == EGB_F64) {
-        if (kinematic) stage_limits_t<double, 8, true>(g, resident, work);
-        else stage_limits_t<double, 8, false>(g, resident, work);
-    } else {
-        if (kinematic) stage_limits_t<float, 16, true>(g, resident, work);
-        else stage_limits_t<float, 12, false>(g, resident, work);
+        return kinematic ? launch_stage_t<double, 8, true, 3>(a, stage, s, blocks)
+                         : launch_stage_t<double, 8, false, 2>(a, stage, s, blocks);
+    if (kinematic) {
+        switch (shape) {
+            case 1: return launch_stage_t<float, 8, true, 4>(a, stage, s, blocks);
+            case 2: return launch_stage_t<float, 12, true, 3>(a, stage, s, blocks);
+            default: return launch_stage_t<float, 16, true, 4>(a, stage, s, blocks);
+        }
+    }
+    switch (shape) {
+        case 1: return launch_stage_t<float, 8, false, 2>(a, stage, s, blocks);
+        case 2: return launch_stage_t<float, 16, false, 4>(a, stage, s, blocks);
+        default: return launch_stage_t<float, 12, false, 3>(a, stage, s, blocks);
     }
 }
 
-long long batched_resident(int dtype) {
-    return dtype == EGB_F64 ? resident_blocks((const void*)k_stage_batched<double, 0, 8>, 64 * 8)
-                            : resident_blocks((const void*)k_stage_batched<float, 0, 12>, 64 * 12);
+namespace {
+template <typename R, int TK, bool KIN, int WPE>
+void stage_limits_t(const GridArgs& g, long long& resident, long long& work) {
+    resident = resident_blocks((const void*)k_stage<R, 0, TK, KIN, WPE>, 64 * TK);
+    work = (long long)((g.nz + TZ - 1) / TZ) * ((g.nth + TK - 1) / TK) * g.nx;
+}
+}  // namespace
+
+void stage_limits(const GridArgs& g, int dtype, bool kinematic, long long& resident, long long& work, int shape) {
+    if (dtype == EGB_F64) {
+        if (kinematic) stage_limits_t<double, 8, true, 3>(g, resident, work);
+        else stage_limits_t<double, 8, false, 2>(g, resident, work);
+    } else if (kinematic) {
+        switch (shape) {
+            case 1: stage_limits_t<float, 8, true, 4>(g, resident, work); break;
+            case 2: stage_limits_t<float, 12, true, 3>(g, resident, work); break;
+            default: stage_limits_t<float, 16, true, 4>(g, resident, work); break;
+        }
+    } else {
+        switch (shape) {
+            case 1: stage_limits_t<float, 8, false, 2>(g, resident, work); break;
+            case 2: stage_limits_t<float, 16, false, 4>(g, resident, work); break;
+            default: stage_limits_t<float, 12, false, 3>(g, resident, work); break;
+        }
+    }
+}
+
+long long batched_resident(int dtype, int shape) {
+    if (dtype == EGB_F64) return resident_blocks((const void*)k_stage_batched<double, 0, 8, 2>, 64 * 8);
+    switch (shape) {
+        case 1: return resident_blocks((const void*)k_stage_batched<float, 0, 8, 2>, 64 * 8);
+        case 2: return resident_blocks((const void*)k_stage_batched<float, 0, 16, 4>, 64 * 16);
+        default: return resident_blocks((const void*)k_stage_batched<float, 0, 12, 3>, 64 * 12);
+    }
 }
 
 }  // namespace egb

@@ -205,6 +205,27 @@ def test_launch_tuning_arguments_are_validated_before_any_device_call():
     assert L.egb_set_blocks_batched(None, 1, 4) == egb.EGB_EINVAL
 
 
+def test_launch_shapes_are_listed_and_validated_without_gpu():
+    """Tile heights per operation and dtype; a tile height the operation
+    does not have, or a negative count, is refused before any device call."""
+    import paper_2006_11945_amd as egb
+    import workloads as W
+
+    g = W.Grid(nx=40, nz=72, nth=36, dx=10.0, dz=10.0)
+    e32, e64 = egb.make_grid(g, "f32"), egb.make_grid(g, "f64")
+    assert egb.egb_tile_rows(e32, egb.EGB_TUNE_STEP) == [12, 8, 16]
+    assert egb.egb_tile_rows(e32, egb.EGB_TUNE_KINEMATIC) == [16, 8, 12]
+    assert egb.egb_tile_rows(e64, egb.EGB_TUNE_STEP) == [8]
+    assert egb.egb_tile_rows(e32, egb.EGB_TUNE_ADJOINT) == [8]
+    assert egb.egb_tile_rows(e32, 7) == []
+    L = egb.lib()
+    for rows, blocks in ((10, 0), (12, -1), (16, 0)):
+        eg = e64 if rows == 16 else e32
+        l = egb.EgbLaunch(rows, blocks)
+        assert L.egb_set_launch(ctypes.byref(eg), egb.EGB_TUNE_STEP, ctypes.byref(l)) == egb.EGB_EINVAL
+    assert L.egb_get_launch(ctypes.byref(e32), egb.EGB_TUNE_STEP, None) == egb.EGB_EINVAL
+
+
 def test_header_compiles_as_c(tmp_path):
     """include/egb.h is a C header: a C99 translation unit that includes it
     (and calls nothing) compiles without a warning from the header."""

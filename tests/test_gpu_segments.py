@@ -136,3 +136,92 @@ def test_autotuned_batch_equals_default():
     for A, B in zip(*runs):
         for k in A:
             assert np.array_equal(A[k], B[k]), k
+
+
+def with_launch(grid, dtype, op, tile_rows, blocks, fn):
+    """Run fn with a fixed launch (tile shape, blocks) for op, then restore the default."""
+    import paper_2006_11945_amd as egb
+    eg = egb.make_grid(grid, dtype)
+    egb.egb_set_launch(eg, op, tile_rows, blocks)
+    assert egb.egb_get_launch(eg, op) == (tile_rows, blocks)
+    try:
+        return fn()
+    finally:
+        egb.egb_set_launch(eg, op, 0, 0)
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_march_independent_of_tile_shape(op):
+    """Every tile shape the autotuner may pick (theta rows per tile, with its
+    LDS slice, halo and waves per SIMD) gives the default march bit for bit,
+    at the default block count and at an odd one."""
+    import paper_2006_11945_amd as egb
+    p = ragged_problem(dtype="f32", tilt=True)
+    eg = egb.make_grid(p.grid, "f32")
+    rows = egb.egb_tile_rows(eg, op)
+    assert len(rows) >= 2
+
+    def march():
+        s = egb.Solver(p, DEV, "f32")
+        s.velocity()
+        s.init()
+        (s.step if op == 0 else s.step_kinematic)(6)
+        torch.cuda.synchronize()
+        return gpu_planes(s)
+
+    ref = march()
+    for tk in rows:
+        for G in (0, 19):
+            log(f"op {op}: {tk} theta rows per tile, blocks {G or 'default'}")
+            got = with_launch(p.grid, "f32", op, tk, G, march)
+            for k in ref:
+                assert np.array_equal(ref[k], got[k]), (tk, G, k)
+
+
+def test_batch_independent_of_tile_shape():
+    import paper_2006_11945_amd as egb
+    from tests.test_gpu_batched import small_batch
+    probs = small_batch("f32", seeds=(7, 8, 9))
+    runs = []
+    rows = None
+    for tk in (None, 12, 8, 16):
+        ss = []
+        for p in probs:
+            s = egb.Solver(p, DEV, "f32")
+            s.velocity()
+            s.init()
+            ss.append(s)
+        arr = egb.make_problem_array(ss)
+        work = egb.alloc_bytes(egb.workspace_size_batched(arr), DEV)
+        if rows is None:
+            rows = egb.egb_tile_rows(ss[0].eg, 0)
+        if tk is not None:
+            assert tk in rows
+            egb.egb_set_launch_batched(arr, tk, 0)
+            assert egb.egb_get_launch_batched(arr) == (tk, 0)
+        try:
+            egb.egb_liouville_step_batched(arr, 5, work)
+        finally:
+            egb.egb_set_launch_batched(arr, 0, 0)
+        torch.cuda.synchronize()
+        runs.append([gpu_planes(s) for s in ss])
+        log(f"batch with {tk or 'default'} theta rows per tile")
+    for other in runs[1:]:
+        for A, B in zip(runs[0], other):
+            for k in A:
+                assert np.array_equal(A[k], B[k]), k
+
+
+def test_tuned_launch_shape_is_reported():
+    import paper_2006_11945_amd as egb
+    p = ragged_problem(dtype="f32", tilt=True)
+    s = egb.Solver(p, DEV, "f32")
+    s.velocity()
+    s.init()
+    try:
+        b = s.tune(op=0, reps=2)
+        tk, blocks = egb.egb_get_launch(s.eg, 0)
+        log(f"tuned: {tk} theta rows per tile, {blocks} blocks")
+        assert blocks == b and tk in egb.egb_tile_rows(s.eg, 0)
+    finally:
+        egb.egb_set_launch(s.eg, 0, 0, 0)
