@@ -187,6 +187,24 @@ egb_status egb_beam_sum(const egb_grid *g, const void *coeff2d, const void *vel3
                         const void *state, const double *omegas, int32_t nw, void *out, void *work,
                         size_t work_bytes, hipStream_t stream);
 
+/* egb_beam_sum for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and results, with the scratch (line counts and beam record
+ * lists) in a fixed array of egb_beam_scratch_bytes() = 128 MiB that the
+ * library holds on every device it runs on until the process ends.  The
+ * caller passes inputs and outputs as for egb_beam_sum; nothing is
+ * allocated on the device or the host.  Each line list holds as many
+ * records as fit in the array: EGB_EUNSUPPORTED (nothing launched) when
+ * fewer than 256 records per line would fit (nx + nz above about 8000),
+ * EGB_EWORKSPACE after the call when a line held more records than fit
+ * (egb_beam_sum with a larger workspace then serves the grid).  All calls on
+ * one device share its array: calls that overlap on one device (other host
+ * threads, other streams) race and must not be made; the counts are cleared
+ * by a kernel at the start of every call.  Synchronises `stream` once. */
+size_t egb_beam_scratch_bytes(void);
+egb_status egb_beam_sum_noalloc(const egb_grid *g, const void *coeff2d, const void *vel3d, const egb_source *src,
+                                const void *state, const double *omegas, int32_t nw, void *out, hipStream_t stream);
+
 /* One problem of a batched march (independent source, own grid and dt). */
 typedef struct {
     egb_grid grid;

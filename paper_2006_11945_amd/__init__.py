@@ -85,6 +85,10 @@ def _load():
     L.egb_boundary_data.argtypes = [G, vp, vp, vp]
     L.egb_liouville_step.argtypes = [G, vp, S, vp, vp, vp, sz, d, i32, vp]
     L.egb_beam_sum.argtypes = [G, vp, vp, S, vp, dp, i32, vp, vp, sz, vp]
+    L.egb_beam_sum_noalloc.argtypes = [G, vp, vp, S, vp, dp, i32, vp, vp]
+    L.egb_beam_sum_noalloc.restype = ctypes.c_int
+    L.egb_beam_scratch_bytes.argtypes = []
+    L.egb_beam_scratch_bytes.restype = sz
     L.egb_pick_receivers.argtypes = [G, vp, vp, i32, vp, vp]
     L.egb_gvel_bytes.argtypes = [G]; L.egb_gvel_bytes.restype = sz
     L.egb_liouville_step_kinematic.argtypes = [G, vp, S, vp, vp, vp, sz, d, i32, vp]
@@ -229,6 +233,15 @@ def egb_beam_sum(eg, coeff2d, vel3d, src: EgbSource, state, omegas, out, work, s
                            om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(om), _ptr(out), _ptr(work),
                            work.numel(), _stream(stream))
     _check("egb_beam_sum", rc)
+
+
+def egb_beam_sum_noalloc(eg, coeff2d, vel3d, src: EgbSource, state, omegas, out, stream=None):
+    """egb_beam_sum with the library's fixed per-device scratch (no workspace)."""
+    om = np.ascontiguousarray(np.atleast_1d(np.asarray(omegas, dtype=np.float64)))
+    rc = _lib.egb_beam_sum_noalloc(ctypes.byref(eg), _ptr(coeff2d), _ptr(vel3d), ctypes.byref(src), _ptr(state),
+                                   om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(om), _ptr(out),
+                                   _stream(stream))
+    _check("egb_beam_sum_noalloc", rc)
 
 
 def egb_pick_receivers(eg, state, rx, t_out, stream=None):

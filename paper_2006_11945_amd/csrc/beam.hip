@@ -296,6 +296,17 @@ __global__ void k_fill_i32(int* p, int n) {
     if (i < n) p[i] = 0;
 }
 
+// *out = max(p[0 .. n)), one block of 256 threads
+__global__ __launch_bounds__(256) void k_max_i32(const int* p, int n, int* out) {
+    __shared__ int part[4];
+    int m = 0;
+    for (int i = threadIdx.x; i < n; i += 256) m = max(m, p[i]);
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = max(max(part[0], part[1]), max(part[2], part[3]));
+}
+
 // qP polarisation (eqs. 4, 31-32) for table values m = (a11, a33, a13 + a55,
 // a55, nu) and phase angle theta: the unit eigenvector of the 2x2
 // Christoffel matrix for the larger eigenvalue, found in the symmetry frame
@@ -475,6 +486,11 @@ hipError_t launch_beam_compact(const BeamArgs& a, int dtype, hipStream_t s) {
         k_beam_compact<double><<<grid, block, 0, s>>>(a);
     else
         k_beam_compact<float><<<grid, block, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_i32(const int* p, int n, int* out, hipStream_t s) {
+    k_max_i32<<<1, 256, 0, s>>>(p, n, out);
     return hipGetLastError();
 }
 

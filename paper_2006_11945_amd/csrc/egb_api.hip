@@ -41,7 +41,8 @@ int beam_cap_default(const egb_grid& g) { return 16 * ((g.nx > g.nz ? g.nx : g.n
 // ... per depth level of the paraxial beam sum.
 int pbeam_cap_default(const egb_grid& g) { return 16 * (g.nx + g.nth) + 64; }
 
-size_t beam_counts_bytes(const egb_grid& g) { return align256((size_t)(g.nx + g.nz) * sizeof(int)); }
+// Line counts of the beam lists, then one int for their maximum.
+size_t beam_counts_bytes(const egb_grid& g) { return align256((size_t)(g.nx + g.nz + 1) * sizeof(int)); }
 
 // CFL limits of velocity buffers.  egb_hamiltonian_velocity records the
 // limit of every buffer it fills (keyed by its address, with the grid it was
@@ -95,6 +96,34 @@ egb_status dt_check(const egb_grid& g, const void* vel3d, double dt) {
     double lim = 0.0;
     if (!vel_lookup(g, vel3d, lim)) return EGB_EINVAL;
     return dt <= lim * (1.0 + 1e-12) ? EGB_OK : EGB_ECFL;
+}
+
+// Fixed scratch of egb_beam_sum_noalloc (the line counts and the beam
+// record lists), one copy per device, held until the process ends.  Host
+// code never uses the array's name as an address: the device address comes
+// from hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t BEAM_SCRATCH_BYTES = (size_t)128 << 20;
+constexpr size_t BEAM_SCRATCH_MIN_CAP = 256;
+constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[BEAM_SCRATCH_BYTES];
+std::mutex scratch_mu;
+void* scratch_dev[MAX_DEVICES] = {};
+
+hipError_t beam_scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        scratch_dev[dev] = p;
+    }
+    *out = scratch_dev[dev];
+    return hipSuccess;
 }
 
 }  // namespace
@@ -790,15 +819,21 @@ egb_status egb_set_launch_batched(const egb_problem* probs, int32_t nprob, const
                : EGB_EHIP;
 }
 
-egb_status egb_beam_sum(const egb_grid* g, const void* coeff2d, const void* vel3d, const egb_source* src,
-                        const void* state, const double* omegas, int32_t nw, void* out, void* work,
-                        size_t work_bytes, hipStream_t stream) {
-    if (!grid_ok(g) || !coeff2d || !vel3d || !state || !omegas || nw < 1 || !out || !work || !source_ok(src))
+static egb_status beam_sum_checks(const egb_grid* g, const void* coeff2d, const void* vel3d, const egb_source* src,
+                                  const void* state, const double* omegas, int32_t nw, const void* out) {
+    if (!grid_ok(g) || !coeff2d || !vel3d || !state || !omegas || nw < 1 || !out || !source_ok(src))
         return EGB_EINVAL;
-    if (!aligned16(coeff2d) || !aligned16(vel3d) || !aligned16(state) || !aligned16(out) || !aligned16(work))
-        return EGB_EINVAL;
+    if (!aligned16(coeff2d) || !aligned16(vel3d) || !aligned16(state) || !aligned16(out)) return EGB_EINVAL;
     for (int w = 0; w < nw; ++w)
         if (!isfinite(omegas[w]) || !(omegas[w] > 0.0)) return EGB_EINVAL;
+    return EGB_OK;
+}
+
+// The beam sum on a checked request with `work_bytes` of scratch at `work`:
+// record lists of as many records per line as fit.
+static egb_status beam_sum_run(const egb_grid* g, const void* coeff2d, const void* vel3d, const egb_source* src,
+                               const void* state, const double* omegas, int32_t nw, void* out, void* work,
+                               size_t work_bytes, hipStream_t stream) {
     const size_t cb = beam_counts_bytes(*g);
     const size_t per = (size_t)(g->nx + g->nz) * beam_record_bytes();
     if (work_bytes < cb + per) return EGB_EWORKSPACE;
@@ -818,14 +853,37 @@ egb_status egb_beam_sum(const egb_grid* g, const void* coeff2d, const void* vel3
     ba.cols = w + cb + (size_t)g->nz * cap * beam_record_bytes();
     hipError_t e = launch_beam_compact(ba, g->dtype, stream);
     if (e == hipSuccess) e = launch_beam_sum(ba, g->dtype, omegas, nw, out, stream);
-    std::vector<int> counts(g->nx + g->nz);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(counts.data(), ba.counts, counts.size() * sizeof(int), hipMemcpyDeviceToHost, stream);
+    // the longest list (a device reduction into the slot after the counts)
+    const int nl = g->nx + g->nz;
+    int longest = 0;
+    if (e == hipSuccess) e = launch_max_i32(ba.counts, nl, ba.counts + nl, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&longest, ba.counts + nl, sizeof(int), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return EGB_EHIP;
-    for (int c : counts)
-        if (c > cap) return EGB_EWORKSPACE;
-    return EGB_OK;
+    return longest > cap ? EGB_EWORKSPACE : EGB_OK;
+}
+
+egb_status egb_beam_sum(const egb_grid* g, const void* coeff2d, const void* vel3d, const egb_source* src,
+                        const void* state, const double* omegas, int32_t nw, void* out, void* work,
+                        size_t work_bytes, hipStream_t stream) {
+    const egb_status st = beam_sum_checks(g, coeff2d, vel3d, src, state, omegas, nw, out);
+    if (st != EGB_OK) return st;
+    if (!work || !aligned16(work)) return EGB_EINVAL;
+    return beam_sum_run(g, coeff2d, vel3d, src, state, omegas, nw, out, work, work_bytes, stream);
+}
+
+size_t egb_beam_scratch_bytes(void) { return BEAM_SCRATCH_BYTES; }
+
+egb_status egb_beam_sum_noalloc(const egb_grid* g, const void* coeff2d, const void* vel3d, const egb_source* src,
+                                const void* state, const double* omegas, int32_t nw, void* out, hipStream_t stream) {
+    const egb_status st = beam_sum_checks(g, coeff2d, vel3d, src, state, omegas, nw, out);
+    if (st != EGB_OK) return st;
+    // the fixed scratch must hold the line counts and at least BEAM_SCRATCH_MIN_CAP records per line
+    const size_t need = beam_counts_bytes(*g) + (size_t)(g->nx + g->nz) * BEAM_SCRATCH_MIN_CAP * beam_record_bytes();
+    if (need > BEAM_SCRATCH_BYTES) return EGB_EUNSUPPORTED;
+    void* ptr = nullptr;
+    if (beam_scratch_address(&ptr) != hipSuccess) return EGB_EHIP;
+    return beam_sum_run(g, coeff2d, vel3d, src, state, omegas, nw, out, ptr, BEAM_SCRATCH_BYTES, stream);
 }
 
 egb_status egb_pick_receivers(const egb_grid* g, const void* state, const double* rx, int32_t nr, double* t_out,

@@ -203,6 +203,8 @@ hipError_t launch_born_data(const GridArgs& g, int dtype, const void* G, int ns,
 hipError_t launch_migrate(const GridArgs& g, int dtype, const void* G, int ns, const double* omegas, int nw,
                           const double* d, double* image, hipStream_t s);
 hipError_t launch_beam_sum(const BeamArgs& a, int dtype, const double* omegas, int nw, void* out, hipStream_t s);
+// *out = max(p[0 .. n)) (one block)
+hipError_t launch_max_i32(const int* p, int n, int* out, hipStream_t s);
 size_t beam_record_bytes();
 
 }  // namespace egb
