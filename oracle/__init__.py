@@ -8,7 +8,9 @@ The arithmetic lives in ``egb_oracle.c`` (plain double-precision loops, built
 with gcc by :func:`build`); this module only marshals numpy arrays.  The
 migration operators (plain sums over the Green's functions) are numpy, in
 ``migration.py``.  Plane
-order of the oracle state: phi1, psi, Re C, Im C, Re B, Im B.
+order of the oracle state: phi1, psi, Re C, Im C, Re B, Im B, and the
+continuous phase of C (the KMAH phase, which decides the branch of
+sqrt(1/C) in the beam sum).
 """
 from __future__ import annotations
 
@@ -22,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "egb_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-PLANES = ("phi1", "psi", "ReC", "ImC", "ReB", "ImB")
+PLANES = ("phi1", "psi", "ReC", "ImC", "ReB", "ImB", "phase")
 PAR_PLANES = ("X", "vt", "tau", "ReC", "ImC", "ReB", "ImB", "phase")  # paraxial depth march
 VEL_PLANES = ("Vx", "Vz", "Vt", "A11", "A12", "A21", "A22")
 NFLD, NTAY = 5, 6
@@ -57,6 +59,7 @@ def lib():
         L.oc_velocity.argtypes = [i, i, i, d, d, P, P, P, P]
         L.oc_init_state.argtypes = [i, i, i, d, d, d, d, P, d, d, d, P]
         L.oc_weno.argtypes = [P, i]; L.oc_weno.restype = d
+        L.oc_upwind5.argtypes = [P, i]; L.oc_upwind5.restype = d
         L.oc_march.argtypes = [i, i, i, d, d, d, d, P, d, d, d, P, P, d, i]
         L.oc_beam_sum.argtypes = [i, i, i, d, d, d, d, P, P, d, i, P, P, i, P]
         L.oc_pbeam_sum.argtypes = [i, i, i, d, d, d, d, d, P, P, d, i, i, i, P, i, P]
@@ -130,7 +133,7 @@ def velocity(grid, tab: np.ndarray):
 
 
 def init_state(grid, tab: np.ndarray, source) -> np.ndarray:
-    U = np.zeros((6, grid.nth, grid.nx, grid.nz))
+    U = np.zeros((len(PLANES), grid.nth, grid.nx, grid.nz))
     lib().oc_init_state(grid.nx, grid.nz, grid.nth, grid.x0, grid.z0, grid.dx, grid.dz, _p(_c(tab)),
                         source.xs, source.zs, source.beta, _p(U))
     return U

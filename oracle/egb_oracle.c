@@ -30,8 +30,10 @@
 
 #define NFLD 5 /* medium fields: a11, a33, b = a13 + a55, a55, tilt nu */
 #define NTAY 6 /* per field: f, f_x, f_z, f_xx, f_xz, f_zz             */
-#define NSTATE 6
-enum { S_PHI = 0, S_PSI = 1, S_RC = 2, S_IC = 3, S_RB = 4, S_IB = 5 };
+#define NSTATE 7
+/* S_PH: the continuous phase of C along the ray (the KMAH phase); it only
+ * decides the branch of sqrt(1/C) in the beam sum */
+enum { S_PHI = 0, S_PSI = 1, S_RC = 2, S_IC = 3, S_RB = 4, S_IB = 5, S_PH = 6 };
 
 /* ------------------------------------------------------------------------ */
 /* 4th-order finite differences on a uniform line (central inside, one-sided
@@ -386,6 +388,8 @@ int oc_init_state(int nx, int nz, int nth, double x0, double z0, double dx, doub
                 U[S_IC * n + c] = s * beta * A12 * psi;
                 U[S_RB * n + c] = 0.0;
                 U[S_IB * n + c] = beta * s;
+                /* arg C of the data: C = s (1 + i beta A12 psi), s > 0 */
+                U[S_PH * n + c] = atan(beta * A12 * psi);
             }
     }
     return 0;
@@ -422,6 +426,24 @@ double oc_weno(const double *u, int minus)
     double e = 1e-6 * mx;
     double a0 = 0.1 / pow(e + s0, 2), a1 = 0.6 / pow(e + s1, 2), a2 = 0.3 / pow(e + s2, 2);
     return am * ((a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2));
+}
+
+/* The upwind derivative of the WENO5 stencils with their linear weights
+ * d = (0.1, 0.6, 0.3) (the fifth-order linear upwind scheme), undivided:
+ * q0 = v1/3 - 7v2/6 + 11v3/6, q1 = -v2/6 + 5v3/6 + v4/3,
+ * q2 = v3/3 + 5v4/6 - v5/6, D = 0.1 q0 + 0.6 q1 + 0.3 q2, with v the
+ * one-sided differences as in oc_weno.  Used for the phase plane, which is
+ * smooth in phase space (it has no fronts for nonlinear weights to guard)
+ * and only has to stay well within pi of the ray's phase.                 */
+double oc_upwind5(const double *u, int minus)
+{
+    double v[5];
+    for (int m = 0; m < 5; ++m)
+        v[m] = minus ? u[m + 1] - u[m] : u[6 - m] - u[5 - m];
+    double q0 = v[0] / 3.0 - 7.0 * v[1] / 6.0 + 11.0 * v[2] / 6.0;
+    double q1 = -v[1] / 6.0 + 5.0 * v[2] / 6.0 + v[3] / 3.0;
+    double q2 = v[2] / 3.0 + 5.0 * v[3] / 6.0 - v[4] / 6.0;
+    return 0.1 * q0 + 0.6 * q1 + 0.3 * q2;
 }
 
 /* Value of plane u at (k, ix + m, iz) / (k, ix, iz + m) with ghosts: outside
@@ -469,16 +491,17 @@ static void rhs(int nx, int nz, int nth, double dx, double dz, const double *vel
                 double Lf[NSTATE];
                 for (int f = 0; f < NSTATE; ++f) {
                     const double *u = U + f * n, *ub = Ub + f * n;
+                    double (*D)(const double *, int) = f == S_PH ? oc_upwind5 : oc_weno;
                     double w[7];
                     for (int m = -3; m <= 3; ++m) w[m + 3] = at_x(u, ub, nx, nz, (long)k * nxz, ix, iz, m);
-                    double Dx = oc_weno(w, cx >= 0.0);
+                    double Dx = D(w, cx >= 0.0);
                     for (int m = -3; m <= 3; ++m) w[m + 3] = at_z(u, ub, nz, (long)k * nxz + (long)ix * nz, iz, m);
-                    double Dz = oc_weno(w, cz >= 0.0);
+                    double Dz = D(w, cz >= 0.0);
                     for (int m = -3; m <= 3; ++m) {
                         int kk = ((k + m) % nth + nth) % nth;
                         w[m + 3] = u[(long)kk * nxz + (long)ix * nz + iz];
                     }
-                    double Dt = oc_weno(w, ct >= 0.0);
+                    double Dt = D(w, ct >= 0.0);
                     Lf[f] = -(cx * Dx + cz * Dz + ct * Dt);
                 }
                 double A11 = vel[3 * n + c], A12 = vel[4 * n + c], A21 = vel[5 * n + c], A22 = vel[6 * n + c];
@@ -487,6 +510,12 @@ static void rhs(int nx, int nz, int nth, double dx, double dz, const double *vel
                 Lf[S_RB] += A21 * U[S_RC * n + c] + A22 * U[S_RB * n + c];
                 Lf[S_IC] += A11 * U[S_IC * n + c] + A12 * U[S_IB * n + c];
                 Lf[S_IB] += A21 * U[S_IC * n + c] + A22 * U[S_IB * n + c];
+                /* continuous phase of C: d(log C)/dtau = A11 + A12 B / C with A
+                 * real, so dPhi/dtau = A12 Im(B / C)                          */
+                {
+                    double rc = U[S_RC * n + c], ic = U[S_IC * n + c], rb = U[S_RB * n + c], ib = U[S_IB * n + c];
+                    Lf[S_PH] += A12 * (ib * rc - rb * ic) / (rc * rc + ic * ic);
+                }
                 for (int f = 0; f < NSTATE; ++f) L[f * n + c] = Lf[f];
             }
 }
@@ -626,7 +655,11 @@ int oc_beam_sum(int nx, int nz, int nth, double x0, double z0, double dx, double
                 double q[2] = {-vx / (v * nv), -vz / (v * nv)};
                 double gq = gx * q[0] + gz * q[1], gpq = gp[0] * q[0] + gp[1] * q[1];
                 double complex Mn = (gp_pth * B + gp_dxp_gp * C) / C;
-                double complex amp0 = csqrt(v / C);
+                /* sqrt(v / C) on the ray's branch: the principal root times
+                 * (-1)^k, k the full turns between the continuous phase Phi
+                 * and arg C (Phi = arg C + 2 pi k)                           */
+                int kmah = (int)lround((U[S_PH * n + c] - carg(C)) / (2.0 * M_PI));
+                double complex amp0 = csqrt(v / C) * ((kmah & 1) ? -1.0 : 1.0);
                 double c4 = pow(gz, 4), s4 = pow(gx, 4), wrow = c4 / (c4 + s4);
                 if (arow && fabs(gz) > 1e-4) {
                     double ds = dn * gx / gz, px = dn / gz, pt = dtp + ds * Vt / nv;

@@ -293,6 +293,35 @@ class GaussianLensMedium:
         sn, cs = np.sin(th), np.cos(th)
         return np.stack([v * sn, v * cs, -(vx * cs - vz * sn)]), v
 
+    def table(self, x, z, fs=0.5):
+        """The five fields and their derivatives at one point (for trace()):
+        isotropic, a11 = a33 = v^2, a55 = (fs v)^2, a13 + a55 = a33 - a55."""
+        v, vx, vz = self.vgrad(x, z)
+        e = self.a * np.exp(-((x - self.cx) ** 2 + (z - self.cz) ** 2) / (2 * self.sig ** 2))
+        s2 = self.sig ** 2
+        vxx = e * ((x - self.cx) ** 2 / s2 - 1.0) / s2
+        vzz = e * ((z - self.cz) ** 2 / s2 - 1.0) / s2
+        vxz = e * (x - self.cx) * (z - self.cz) / s2 ** 2
+        sq = np.array([v * v, 2 * v * vx, 2 * v * vz, 2 * (vx * vx + v * vxx), 2 * (vx * vz + v * vxz),
+                       2 * (vz * vz + v * vzz)])
+        t = np.zeros((5, 6))
+        for f, k in enumerate((1.0, 1.0, 1.0 - fs * fs, fs * fs)):
+            t[f] = k * sq
+        return t
+
+
+def continuous_phase_of_c(medium, y0, tau, beta, s=1.0, n=400):
+    """The continuous phase of the ray-normal DRT amplitude C along the ray
+    from the source point y0 = (x_s, z_s, take-off angle) for time tau:
+    (C, B)(0) = (s, i beta s) (the point-source data at the source), carried
+    by d(C, B)/dtau = A (C, B) (real A, so the propagator of the two real
+    unit starts gives C), arg C unwrapped over n samples."""
+    sol1 = trace(medium, y0, tau, with_drt=True, d0=(1.0, 0.0), dense=True)
+    sol2 = trace(medium, y0, tau, with_drt=True, d0=(0.0, 1.0), dense=True)
+    t = np.linspace(0.0, tau, n)
+    C = s * (sol1.sol(t)[3] + 1j * beta * sol2.sol(t)[3])
+    return float(np.unwrap(np.angle(C))[-1])
+
 
 def fan_crossings(medium, xs, zs, take_off, z_line, dtau=1e-3, tmax=5.0):
     """Shoot rays from the source (x_s, z_s) at the phase angles `take_off`

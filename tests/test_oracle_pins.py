@@ -331,9 +331,13 @@ def test_homogeneous_point_source_data_is_steady(eps, delta, tilt):
     p.grid.nth = 20
     p.medium = W.homogeneous(p.grid, 2000.0, eps, delta, tilt)
     r = oracle.solve(p, nsteps=6)
-    scale = np.abs(r["U0"]).max(axis=(1, 2, 3))
+    U, U0 = r["U"][:6], r["U0"][:6]
+    scale = np.abs(U0).max(axis=(1, 2, 3))
     scale[4] = scale[5]  # Re B vanishes identically; its natural scale is |B| = beta s
-    assert (np.abs(r["U"] - r["U0"]).max(axis=(1, 2, 3)) / scale).max() < 1e-12
+    assert (np.abs(U - U0).max(axis=(1, 2, 3)) / scale).max() < 1e-12
+    # the phase plane: its data arctan(beta A12 psi) is not linear in x, z, so
+    # the scheme keeps it to its truncation error, far inside pi
+    assert np.abs(r["U"][6] - r["U0"][6]).max() < 1e-3
 
 
 def _pick_tol(grid, t):
@@ -491,3 +495,17 @@ def test_beam_sum_lin28_variant_ab():
         errs.append(np.linalg.norm((G - H)[m]) / np.linalg.norm(H[m]))
     assert errs[0] < 0.03, errs
     assert errs[1] > 5 * errs[0], errs
+
+
+def test_phase_plane_follows_arg_c_in_a_homogeneous_medium():
+    """The continuous phase of C carried by the march equals arg C where no
+    caustic is crossed: in the homogeneous workload (64^3, 100 steps) the two
+    agree to the scheme's error (measured 2.3e-5 rad; the data's phase,
+    arctan(beta A12 psi), is extended into the edge ghosts linearly, which is
+    exact for the other planes but not for it)."""
+    p = W.homog_iso_64()
+    r = oracle.solve(p)
+    U = r["U"]
+    d = np.abs(U[6] - np.angle(U[2] + 1j * U[3]))
+    assert d.max() < 1e-4
+    assert np.abs(U[6]).max() > 0.3  # the phase does vary (beta A12 psi up to ~0.35)
