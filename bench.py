@@ -27,16 +27,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Floating-point operations of the scheme per cell and RK stage, counted from
-# its definition (WENO5-JS in Hamilton-Jacobi form on 6 planes x 3 axes,
-# convection, sources, stage combine); see the design notes.
+# its definition: WENO5-JS in Hamilton-Jacobi form on 6 planes (phi1, C, B,
+# psi) x 3 axes, the linear fifth-order upwind derivative of the phase plane
+# on 3 axes, convection (7 planes x 3 axes, a multiply-add each), sources
+# (psi 3, A (C, B) 17, A12 Im(B / C) 9), stage combine (7 planes x 5).
 FLOP_WENO = 80
-FLOP_CELL_STAGE = 18 * FLOP_WENO + 6 * 6 + 3 + 17 + 30
+FLOP_UPWIND5 = 15
+FLOP_CELL_STAGE = 18 * FLOP_WENO + 3 * FLOP_UPWIND5 + 7 * 6 + 3 + 17 + 9 + 7 * 5
 PEAK_FP32_TFLOPS = 157.3           # published MI355X FP32 vector peak (counts packed, dual-lane FP32)
 PEAK_FP32_UNPACKED_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz: one FP32 op per lane
 PEAK_HBM_GBPS = 8000.0             # HBM3E spec
-# State bytes per cell (five FP32 planes and psi in FP64); one RK3 step must
+# State bytes per cell (six FP32 planes and psi in FP64); one RK3 step must
 # at least read and write the state once: the HBM floor per cell-update.
-STATE_BYTES_PER_CELL = 5 * 4 + 8
+STATE_BYTES_PER_CELL = 6 * 4 + 8
 FLOOR_BYTES_PER_CELL_UPDATE = 2 * STATE_BYTES_PER_CELL
 
 WORKLOADS = {

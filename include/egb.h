@@ -43,7 +43,7 @@ typedef enum {
     EGB_EUNSUPPORTED = -6   /* valid request this build does not implement */
 } egb_status;
 
-/* Arithmetic type of the phase-space planes.  EGB_F32: five planes in float,
+/* Arithmetic type of the phase-space planes.  EGB_F32: six planes in float,
  * traveltime psi in double (FP64 traveltime accumulation); EGB_F64: all
  * planes in double. */
 typedef enum { EGB_F32 = 0, EGB_F64 = 1 } egb_dtype;
@@ -51,8 +51,14 @@ typedef enum { EGB_F32 = 0, EGB_F64 = 1 } egb_dtype;
 /* State planes (order in memory).  phi1: ray-family level set, the signed
  * miss distance of the ray from the source (X - x_s of eqs. 19-20, 35);
  * (C, B): complex dynamic ray tracing pair of eq. 21 in the ray-normal frame;
- * psi: traveltime (tau of eq. 19). */
-enum { EGB_PHI1 = 0, EGB_RE_C = 1, EGB_IM_C = 2, EGB_RE_B = 3, EGB_IM_B = 4, EGB_PSI = 5, EGB_NSTATE = 6 };
+ * phase: arg C continued along the ray (its Liouville equation follows from
+ * eq. 21: d(arg C)/dtau = A12 Im(B / C)), which picks the branch of
+ * sqrt(1 / C) in the beam amplitude past caustics (the KMAH index: the
+ * number of full turns between it and the principal arg C);
+ * psi: traveltime (tau of eq. 19).  The planes before EGB_PSI are in the grid
+ * dtype, psi is double. */
+enum { EGB_PHI1 = 0, EGB_RE_C = 1, EGB_IM_C = 2, EGB_RE_B = 3, EGB_IM_B = 4, EGB_PHASE = 5, EGB_PSI = 6,
+       EGB_NSTATE = 7 };
 
 /* Velocity planes (order in memory): the Liouville velocity V = (dx/dtau,
  * dz/dtau, dtheta/dtau) of eqs. 8, 9, 12 and the 2x2 ray-normal dynamic ray
@@ -140,7 +146,8 @@ egb_status egb_declare_velocity(const egb_grid *g, const void *vel3d, double dt_
  * frozen at the source (bilinear in coeff2d), every cell gets
  * phi1 = (x - xs).g_perp(theta), psi = p(theta).(x - xs),
  * C = s (1 + i beta A12 psi), B = i beta s, s = (sqrt(v)/W)^(2/3),
- * W = a33/v^2 (the beam weight of eqs. 31-33 redone in 2D).
+ * W = a33/v^2 (the beam weight of eqs. 31-33 redone in 2D),
+ * phase = arg C = atan(beta A12 psi) (s > 0).
  * Out: state (egb_state_bytes). */
 egb_status egb_init_state(const egb_grid *g, const void *coeff2d, const egb_source *src, void *state,
                           hipStream_t stream);
@@ -153,23 +160,29 @@ egb_status egb_init_state(const egb_grid *g, const void *coeff2d, const egb_sour
  * eqs. 16-21 leave open: the point-source data is the solution of the
  * homogeneous problem, so it is what enters through the edges).
  * In: state holding the point-source data (egb_init_state).
- * Out: bdata, egb_bdata_bytes(g) bytes.  Layout per plane (five planes in the
- * grid dtype, then psi in double, each padded to egb_bdata_plane_stride()
+ * Out: bdata, egb_bdata_bytes(g) bytes.  Layout per plane (the six planes
+ * before EGB_PSI in the grid dtype, then psi in double, each padded to egb_bdata_plane_stride()
  * elements): x ghosts [theta][6][nz], then z ghosts [theta][nx][6], ghost
  * slots 0..2 at positions -3..-1 and 3..5 at n, n+1, n+2 of the line. */
 size_t egb_bdata_plane_stride(const egb_grid *g);
 egb_status egb_boundary_data(const egb_grid *g, const void *state, void *bdata, hipStream_t stream);
 
 /* nsteps SSP-RK3 pseudo-time steps of U_t + V.grad U = S(U) (eqs. 16, 19, 21
- * multiplied by dz/dtau): WENO5 Hamilton-Jacobi upwind derivatives, sources
- * S_psi = 1, S_(C,B) = A (C, B); ghosts: x, z from bdata (egb_boundary_data),
+ * multiplied by dz/dtau): WENO5 Hamilton-Jacobi upwind derivatives (for the
+ * phase plane the fifth-order linear upwind derivative, the WENO5 stencils
+ * at their linear weights), sources S_psi = 1, S_(C,B) = A (C, B),
+ * S_phase = A12 Im(B / C); ghosts: x, z from bdata (egb_boundary_data),
  * theta periodic; cells within r0 of the source keep their values (Dirichlet
  * data).  In/out: state.  vel3d from egb_hamiltonian_velocity.
  * work: egb_workspace_size(g, EGB_OP_STEP) bytes (two RK stage buffers).
  * dt must be positive, finite and at most the CFL limit recorded for vel3d
  * (egb_hamiltonian_velocity) times 1 + 1e-12: EGB_ECFL otherwise, and
  * EGB_EINVAL if vel3d has no record for this grid; nothing is launched
- * then. */
+ * then.  EGB_EUNSUPPORTED (nothing launched) for grids beyond the kernels'
+ * 32-bit buffer offsets: the velocity planes, the grid-dtype state planes
+ * and the psi plane must each stay below 4 GiB (FP32: up to about 153 M
+ * cells, 512^3 included; FP64: about 76 M); the same limit holds for every
+ * march below. */
 egb_status egb_liouville_step(const egb_grid *g, const void *vel3d, const egb_source *src, const void *bdata,
                               void *state, void *work, size_t work_bytes, double dt, int32_t nsteps,
                               hipStream_t stream);
@@ -178,7 +191,9 @@ egb_status egb_liouville_step(const egb_grid *g, const void *vel3d, const egb_so
  * output cell (x0, z0) and frequency omega:
  *   G = (i/4pi) [ sum_row w A dtheta exp(i omega T) + sum_col (1-w) A dtheta exp(i omega T) ]
  * over the phase cells of the same row / column on Gamma = {phi1 = 0, psi > 0}
- * (smoothed delta of width 2 dx), T = psi + p1 (x0 - x) + M (x0 - x)^2 / 2.
+ * (smoothed delta of width 2 dx), T = psi + p1 (x0 - x) + M (x0 - x)^2 / 2,
+ * A = sqrt(v / C) on the ray's branch: the principal root times (-1)^k, k
+ * the nearest whole number of turns in (phase - arg C) / 2 pi.
  * In: omegas (HOST float64 [nw], rad/s).  Out: out, complex [nw][nx][nz]
  * interleaved (re, im) in the grid dtype (complex64 / complex128).
  * work: egb_workspace_size(g, EGB_OP_BEAM).  Synchronises `stream` once;

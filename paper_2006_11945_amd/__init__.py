@@ -24,9 +24,9 @@ LIB_PATH = os.path.join(HERE, "libegb.so")
 
 EGB_OK, EGB_EINVAL, EGB_ECFL, EGB_EWORKSPACE, EGB_EHIP, EGB_ENONFINITE, EGB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 EGB_F32, EGB_F64 = 0, 1
-EGB_PHI1, EGB_RE_C, EGB_IM_C, EGB_RE_B, EGB_IM_B, EGB_PSI = range(6)
+EGB_PHI1, EGB_RE_C, EGB_IM_C, EGB_RE_B, EGB_IM_B, EGB_PHASE, EGB_PSI = range(7)
 EGB_OP_VELOCITY, EGB_OP_STEP, EGB_OP_BEAM, EGB_OP_ADJOINT, EGB_OP_PARAXIAL, EGB_OP_PBEAM = range(6)
-STATE_PLANES = ("phi1", "ReC", "ImC", "ReB", "ImB", "psi")
+STATE_PLANES = ("phi1", "ReC", "ImC", "ReB", "ImB", "phase", "psi")
 VEL_PLANES = ("Vx", "Vz", "Vt", "A11", "A12", "A21", "A22")
 PAR_PLANES = ("X", "vartheta", "ReC", "ImC", "ReB", "ImB", "phase", "tau")   # paraxial level planes, in memory order
 PVEL_PLANES = ("u", "w", "Stau", "A11", "A12", "A21", "A22")

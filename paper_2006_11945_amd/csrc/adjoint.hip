@@ -80,7 +80,11 @@ struct AdjStageArgs {
     void* lam_in;        // stages 1, 2: lambda of the stage input
     void* gvel;          // [3][stride] of R, accumulated
     double dt, xs, zs, r02;
-    unsigned state_bytes, vel_bytes, gvel_bytes, bd_bytes;
+    // descriptor extents: plane phi1 of the state-layout buffers and of the
+    // boundary data, and their psi planes under descriptors of their own
+    // (base + psi_off / bpsi_off), each below 4 GiB
+    unsigned state_bytes, psi_bytes, vel_bytes, gvel_bytes, bd_bytes, bpsi_bytes;
+    unsigned long long psi_off, bpsi_off;
     int ntz, ntk;
 };
 
@@ -162,14 +166,16 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
     const bool zin = iz < g.nz;
     const bool valid = zin && kraw < g.nth;  // own cell written by this tile
     const int izc = min(iz, g.nz - 1);
-    const unsigned nxz = (unsigned)g.nxz, SP = (unsigned)g.stride * ES, PSI = 5u * SP;
+    const unsigned nxz = (unsigned)g.nxz, SP = (unsigned)g.stride * ES;
     const unsigned kb = (unsigned)k * nxz;
     const auto rUi = make_rsrc(a.Uin, a.state_bytes);
     const auto rL = make_rsrc(a.lam, a.state_bytes);
     const auto rV = make_rsrc(a.vel, a.vel_bytes);
     const auto rG = make_rsrc(a.gvel, a.gvel_bytes);
     const auto rB = make_rsrc(a.bd, a.bd_bytes);
-    const unsigned BSP = (unsigned)g.bstride * ES;  // boundary data: bytes per R plane
+    const auto pUi = make_rsrc(static_cast<const char*>(a.Uin) + a.psi_off, a.psi_bytes);
+    const auto pL = make_rsrc(static_cast<const char*>(a.lam) + a.psi_off, a.psi_bytes);
+    const auto pB = make_rsrc(static_cast<const char*>(a.bd) + a.bpsi_off, a.bpsi_bytes);
     const unsigned XG = (unsigned)k * 6u * (unsigned)g.nz + (unsigned)izc;  // x ghost slot 0 of the column
     const unsigned ZG = (unsigned)g.nth * 6u * (unsigned)g.nz;            // first z ghost
     const double cbdt = cb * a.dt;
@@ -220,11 +226,11 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
     auto x_value = [&](int p, R& v, double& vp) {
         const bool gh = p < 0 || p >= g.nx;  // block-uniform
         const auto r = gh ? rB : rUi;
-        const unsigned sp = gh ? BSP : SP;
+        const auto rp = gh ? pB : pUi;
         const unsigned o = gh ? XG + (unsigned)(min(max(p < 0 ? p + 3 : p - g.nx + 3, 0), 5) * g.nz)
                               : kb + (unsigned)(p * g.nz + izc);
         v = bload<R>(r, o * ES, 0);
-        vp = bload<double>(r, o * 8u, 5u * sp);
+        vp = bload<double>(rp, o * 8u, 0);
     };
     R qv[7];
     double qp[7];
@@ -245,7 +251,7 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
         const int xc = min(max(x, 0), g.nx - 1);
         const unsigned c = kb + (unsigned)(xc * g.nz + izc);
         l0 = bload<R>(rL, c * ES, 0);
-        l1 = bload<double>(rL, c * 8u, PSI);
+        l1 = bload<double>(pL, c * 8u, 0);
         vx = bload<R>(rV, c * ES, EGB_VX * SP);
         vz = bload<R>(rV, c * ES, EGB_VZ * SP);
         vt = bload<R>(rV, c * ES, EGB_VT * SP);
@@ -272,11 +278,11 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
             vcell(tid + r * NT, vb, vm, vbd);
             const unsigned o = vb + xo;
             vv[r] = bload<R>(rUi, o * ES, 0);
-            vp[r] = bload<double>(rUi, o * 8u, PSI);
+            vp[r] = bload<double>(pUi, o * 8u, 0);
             if (z_end) {  // the boundary-data value, kept by ghost cells
                 const unsigned o1 = vbd + (unsigned)(x * 6);
                 vv1[r] = bload<R>(rB, o1 * ES, 0);
-                vp1[r] = bload<double>(rB, o1 * 8u, 5u * BSP);
+                vp1[r] = bload<double>(pB, o1 * 8u, 0);
             }
         }
     };
@@ -298,7 +304,7 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
             hcell(tid + r * NT, tl, zl, real, hc);
             const unsigned c = (hc + xo) * ES, c8 = (hc + xo) * 8u;
             nhm0[r] = bload<R>(rL, c, 0);
-            nhm1[r] = bload<double>(rL, c8, PSI);
+            nhm1[r] = bload<double>(pL, c8, 0);
             nhvel[r] = bload<R>(rV, c + (unsigned)(tid + r * NT < 6 * TZ ? EGB_VT : EGB_VZ) * SP, 0);
             nhlive[r] = real && !in_ball(x, tzi * TZ + zl);
         }
@@ -350,13 +356,14 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
         const bool out = valid && xt >= x0 && xt < x1;
         const unsigned co = kb + (unsigned)(min(max(xt, 0), g.nx - 1) * g.nz + izc);
         const R ol0 = bload<R>(rL, co * ES, 0);
-        const double ol1 = bload<double>(rL, co * 8u, PSI);
+        const double ol1 = bload<double>(pL, co * 8u, 0);
         R oa0 = (R)0;
         double oa1 = 0.0;
         if constexpr (STAGE != 2) {
             const auto rAi = make_rsrc(a.acc_in, a.state_bytes);
+            const auto pAi = make_rsrc(static_cast<const char*>(a.acc_in) + a.psi_off, a.psi_bytes);
             oa0 = bload<R>(rAi, co * ES, 0);
-            oa1 = bload<double>(rAi, co * 8u, PSI);
+            oa1 = bload<double>(pAi, co * 8u, 0);
         }
         const bool wlive = __any(cm0 != (R)0 || cm1 != 0.0);  // wave-uniform
         // (straight-line: the store is guarded, the address is clamped)
@@ -488,9 +495,10 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
             const R add0 = ball ? l0 : (R)ca * l0;
             const double add1 = ball ? l1 : ca * l1;
             const auto rAo = make_rsrc(a.acc_out, a.state_bytes);
+            const auto pAo = make_rsrc(static_cast<char*>(a.acc_out) + a.psi_off, a.psi_bytes);
             if constexpr (STAGE == 2) {
                 bstore(add0, rAo, c * ES, 0);
-                bstore(add1, rAo, c * 8u, PSI);
+                bstore(add1, pAo, c * 8u, 0);
             } else {
                 R o0 = oa0 + add0;
                 double o1 = oa1 + add1;
@@ -499,12 +507,13 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
                     o1 += (double)a1[0];
                 }
                 bstore(o0, rAo, c * ES, 0);
-                bstore(o1, rAo, c * 8u, PSI);
+                bstore(o1, pAo, c * 8u, 0);
             }
             if constexpr (STAGE != 0) {
                 const auto rLi = make_rsrc(a.lam_in, a.state_bytes);
+                const auto pLi = make_rsrc(static_cast<char*>(a.lam_in) + a.psi_off, a.psi_bytes);
                 bstore(a0[0], rLi, c * ES, 0);
-                bstore((double)a1[0], rLi, c * 8u, PSI);
+                bstore((double)a1[0], pLi, c * 8u, 0);
             }
         }
         // shift
@@ -562,9 +571,9 @@ __global__ __launch_bounds__(256) void k_pick_adjoint(GridArgs a, const char* st
     __shared__ double val[256][16];
     __shared__ int has[256];
     const R* phi = reinterpret_cast<const R*>(state);
-    const double* psi = reinterpret_cast<const double*>(phi + 5 * a.stride);
+    const double* psi = reinterpret_cast<const double*>(phi + EGB_PSI * a.stride);
     R* lphi = reinterpret_cast<R*>(lam);
-    double* lpsi = reinterpret_cast<double*>(lphi + 5 * a.stride);
+    double* lpsi = reinterpret_cast<double*>(lphi + EGB_PSI * a.stride);
     for (int base = 0; base < nr; base += 256) {
         const int r = base + (int)threadIdx.x;
         has[threadIdx.x] = 0;
@@ -692,7 +701,7 @@ __global__ __launch_bounds__(256) void k_adj_source(GridArgs a, const double* C,
                                                     const double* bfold, double* gms) {
     const int k = blockIdx.x;
     const R* lphi = reinterpret_cast<const R*>(lam0);
-    const double* lpsi = reinterpret_cast<const double*>(lphi + 5 * a.stride);
+    const double* lpsi = reinterpret_cast<const double*>(lphi + EGB_PSI * a.stride);
     double s[4] = {0, 0, 0, 0};
     for (long long cz = threadIdx.x; cz < a.nxz; cz += blockDim.x) {
         const int ix = (int)(cz / a.nz), iz = (int)(cz % a.nz);
@@ -863,10 +872,14 @@ hipError_t launch_adjoint_stage(const GridArgs& g, int dtype, int stage, const v
     a.xs = xs;
     a.zs = zs;
     a.r02 = r02;
-    a.state_bytes = (unsigned)(S * (5 * es + 8));
+    a.state_bytes = (unsigned)(S * es);  // plane phi1
+    a.psi_off = (unsigned long long)EGB_PSI * S * es;
+    a.psi_bytes = (unsigned)(S * 8);
     a.vel_bytes = (unsigned)(7 * S * es);
     a.gvel_bytes = (unsigned)(3 * S * es);
-    a.bd_bytes = (unsigned)((unsigned long long)g.bstride * (5 * es + 8));
+    a.bd_bytes = (unsigned)((unsigned long long)g.bstride * es);
+    a.bpsi_off = (unsigned long long)EGB_PSI * g.bstride * es;
+    a.bpsi_bytes = (unsigned)((unsigned long long)g.bstride * 8);
     a.ntz = a.ntk = 0;
     return dtype == EGB_F64 ? adj_stage_t<double, 4>(a, stage, s, blocks) : adj_stage_t<float, 8>(a, stage, s, blocks);
 }

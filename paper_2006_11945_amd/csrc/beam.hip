@@ -9,7 +9,10 @@
 //   pos (x or z of the cell), psi, p (p1 or p3 of eq. 7, or eq. 28's
 //   coefficient for the lin=paper28 variant), M (traveltime Hessian along
 //   the line, complex) and amp = w sqrt(v / C) dtheta (complex),
-// w = cos^4 / (cos^4 + sin^4) of the ray angle for rows and 1 - w for columns.
+// w = cos^4 / (cos^4 + sin^4) of the ray angle for rows and 1 - w for columns,
+// and sqrt(v / C) on the branch the ray carries: the principal root times
+// (-1)^k, k the nearest whole number of turns between the phase plane (arg C
+// continued along the ray) and the principal arg C.
 // Cells whose line Hessian has Im(M) <= 0 give no record: a Gaussian beam
 // decays away from its centre (the exact transport keeps Im(B conj(C)) > 0,
 // a discrete field can lose it).  The gate psi > 0 is taken as psi above
@@ -80,7 +83,7 @@ __global__ __launch_bounds__(256) void k_beam_compact(BeamArgs a) {
     if (iz >= g.nz || ix >= g.nx) return;
     const long long S = g.stride, kb = (long long)k * g.nxz, c = kb + (long long)ix * g.nz + iz;
     const R* U = reinterpret_cast<const R*>(a.U);
-    const double psi = reinterpret_cast<const double*>(U + 5 * S)[c];
+    const double psi = reinterpret_cast<const double*>(U + EGB_PSI * S)[c];
     if (!(psi > 0.0)) return;
     const R* phi = U + EGB_PHI1 * S;
     const double fx = cd4(phi + kb + iz, g.nz, g.nx, ix, g.dx);
@@ -136,12 +139,20 @@ __global__ __launch_bounds__(256) void k_beam_compact(BeamArgs a) {
     const double den = reC * reC + imC * imC;
     const double BCre = (reB * reC + imB * imC) / den, BCim = (imB * reC - reB * imC) / den;
     const double Mnre = e_pth * BCre + e_dxp_e, Mnim = e_pth * BCim;
-    // sqrt(v / C), principal branch
+    // sqrt(v / C): the principal root, times (-1)^k on the ray's branch, k the
+    // whole turns between the continued phase of C and its principal arg
     const double vCre = v * reC / den, vCim = -v * imC / den;
     const double mod = sqrt(vCre * vCre + vCim * vCim);
     double sqre = sqrt(0.5 * (mod + vCre));
     double sqim = sqrt(0.5 * fmax(mod - vCre, 0.0));
     sqim = vCim < 0.0 ? -sqim : sqim;
+    {
+        const double turns = rint(((double)U[EGB_PHASE * S + c] - atan2(imC, reC)) / 6.283185307179586476925286766559);
+        if (fmod(fabs(turns), 2.0) == 1.0) {
+            sqre = -sqre;
+            sqim = -sqim;
+        }
+    }
     const double c4 = hzr * hzr * hzr * hzr, s4 = hxr * hxr * hxr * hxr, wrow = c4 / (c4 + s4);
     const double dn = imC, dtp = imB;
     BeamRec* rows = reinterpret_cast<BeamRec*>(a.rows);

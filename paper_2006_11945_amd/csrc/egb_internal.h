@@ -16,20 +16,21 @@ inline size_t plane_stride(const egb_grid& g) {
 }
 inline size_t real_size(const egb_grid& g) { return g.dtype == EGB_F64 ? 8 : 4; }
 
-// Byte offset of state plane p: planes 0..4 in the grid dtype, psi in double.
+// Byte offset of state plane p: planes before EGB_PSI in the grid dtype, psi
+// in double.
 inline size_t state_plane_offset(const egb_grid& g, int p) {
     return (size_t)p * plane_stride(g) * real_size(g);
 }
 inline size_t state_bytes(const egb_grid& g) { return state_plane_offset(g, EGB_PSI) + plane_stride(g) * 8; }
 
 // Boundary data: per plane, x ghosts [theta][6][nz] then z ghosts
-// [theta][nx][6], padded to 64 elements; five planes in the grid dtype, psi
-// in double.
+// [theta][nx][6], padded to 64 elements; the state's planes before EGB_PSI in
+// the grid dtype, psi in double.
 inline size_t bdata_stride(const egb_grid& g) {
     size_t n = (size_t)g.nth * 6 * ((size_t)g.nx + (size_t)g.nz);
     return (n + 63) / 64 * 64;
 }
-inline size_t bdata_bytes(const egb_grid& g) { return bdata_stride(g) * (5 * real_size(g) + 8); }
+inline size_t bdata_bytes(const egb_grid& g) { return bdata_stride(g) * (EGB_PSI * real_size(g) + 8); }
 // Adjoint boundary accumulator (float64): [2 planes: phi1, psi][theta] x
 // ([2 ends][3 sources][2 weights][nz] then [nx][2 ends][3 sources][2 weights]).
 inline size_t bfold_bytes(const egb_grid& g) { return (size_t)2 * g.nth * 12 * ((size_t)g.nx + g.nz) * 8; }

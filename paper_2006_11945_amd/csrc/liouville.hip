@@ -3,14 +3,16 @@
 // For every phase cell (x, z, theta) and state plane f:
 //   L_f = -(V_x D_x + V_z D_z + V_theta D_theta) U_f + S_f,
 //   S_phi1 = 0, S_psi = 1, S_(C,B) = A (C, B)          (eqs. 16, 19, 21 x dz/dtau)
+//   S_phase = A12 Im(B / C)                  (arg C continued along the ray)
 // with D the WENO5 Hamilton-Jacobi derivative on the upwind side (D- for a
-// velocity component >= 0, D+ otherwise), then
+// velocity component >= 0, D+ otherwise; for the phase plane the linear
+// fifth-order upwind derivative), then
 //   Uout = ca U0 + cb (Uin + dt L(Uin)),  (ca, cb) = (0,1), (3/4,1/4), (1/3,2/3),
 // and cells inside the source ball copy U0.  Ghosts: x, z from the boundary
 // data (fixed values: the point-source data extended linearly beyond each
 // end), theta periodic.
 //
-// Precision: planes phi1, C, B in R (float or double); psi is stored and
+// Precision: planes phi1, C, B, phase in R (float or double); psi is stored and
 // combined in double, its WENO differences are formed in double and the
 // derivative is evaluated in R.
 //
@@ -42,9 +44,14 @@ constexpr int PZ = TZ + 6;   // padded LDS row
 
 // Tiles of one problem: ntz x ntk (z, theta) tiles; the batched queue also
 // splits x into nxc chunks of kx; nblocks is the launch's block count.
+// Buffer extents for the raw buffer descriptors: the grid-dtype planes of the
+// state and of the boundary data, and their psi planes, each under its own
+// descriptor (base + psi_off / bpsi_off), so that each extent stays below
+// 4 GiB where the whole state would not (512^3 FP32: 3 GiB + 1 GiB).
 struct TileArgs {
     int ntz, ntk, nxc, kx, nblocks;
-    unsigned state_bytes, vel_bytes, bd_bytes;
+    unsigned state_bytes, psi_bytes, vel_bytes, bd_bytes, bpsi_bytes;
+    unsigned long long psi_off, bpsi_off;
 };
 
 template <typename R, int TK, int NP>
@@ -58,6 +65,14 @@ struct StageSmem {
     static constexpr int PB = PLANE * (int)sizeof(W);        // bytes per plane
     W w[2 * BUF];
 };
+
+// Upwind derivative of plane f from its six upwind-ordered values: WENO5,
+// or the linear fifth-order scheme for the phase plane (f is a constant
+// after unrolling).
+template <typename R, typename T>
+__device__ __forceinline__ R deriv(int f, T u0, T u1, T u2, T u3, T u4, T u5) {
+    return f == EGB_PHASE ? upwind5_up<R>(u0, u1, u2, u3, u4, u5) : weno_up<R>(u0, u1, u2, u3, u4, u5);
+}
 
 // Store the NP plane values and psi of one cell at word index i.
 template <typename R, int TK, int NP>
@@ -95,8 +110,8 @@ __device__ __forceinline__ void lds_put(StageSmem<R, TK, NP>& sm, int i, const R
 // load an in-domain column and write nothing.
 template <typename R, int STAGE, int TK, bool KIN>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t, int tile, int x0, int x1,
-                                           StageSmem<R, TK, KIN ? 1 : 5>& sm) {
-    constexpr int NP = KIN ? 1 : 5;  // R planes marched
+                                           StageSmem<R, TK, KIN ? 1 : EGB_PSI>& sm) {
+    constexpr int NP = KIN ? 1 : EGB_PSI;  // R planes marched
     using S = StageSmem<R, TK, NP>;
     constexpr int WS = (int)sizeof(typename S::W);
     constexpr int NHALO = 6 * TZ + 6 * TK;
@@ -123,8 +138,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
     const auto rUo = make_rsrc(a.Uout, t.state_bytes);
     const auto rV = make_rsrc(a.vel, t.vel_bytes);
     const auto rB = make_rsrc(a.bd, t.bd_bytes);
+    // the psi planes
+    const auto pUi = make_rsrc(static_cast<const char*>(a.Uin) + t.psi_off, t.psi_bytes);
+    const auto pU0 = make_rsrc(static_cast<const char*>(a.U0) + t.psi_off, t.psi_bytes);
+    const auto pUo = make_rsrc(static_cast<char*>(a.Uout) + t.psi_off, t.psi_bytes);
+    const auto pB = make_rsrc(static_cast<const char*>(a.bd) + t.bpsi_off, t.bpsi_bytes);
     const unsigned SP = SS * ES;         // bytes per R plane
-    const unsigned PSI = 5u * SP;        // byte offset of the psi plane
     const unsigned BSP = (unsigned)g.bstride * ES;  // boundary data: bytes per R plane
     const unsigned XG = (unsigned)k * 6u * (unsigned)g.nz + (unsigned)izc;  // x ghost slot 0 of the column
     const unsigned ZG = (unsigned)g.nth * 6u * (unsigned)g.nz;            // first z ghost
@@ -168,12 +187,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
     auto x_entry = [&](int p, R (&v)[NP], double& vp) {
         const bool gh = p < 0 || p >= g.nx;  // block-uniform
         const auto r = gh ? rB : rUi;
+        const auto rp = gh ? pB : pUi;
         const unsigned sp = gh ? BSP : SP;
         const unsigned o = gh ? XG + (unsigned)(min(p < 0 ? p + 3 : p - g.nx + 3, 5) * g.nz)
                               : kb + (unsigned)(p * g.nz + izc);
 #pragma unroll
         for (int f = 0; f < NP; ++f) v[f] = bload<R>(r, o * ES, f * sp);
-        vp = bload<double>(r, o * 8u, 5u * sp);
+        vp = bload<double>(rp, o * 8u, 0);
     };
     R q[NP][7];
     double qp[7];
@@ -192,12 +212,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
         const unsigned o0 = hkb + (unsigned)(xs * g.nz) + (unsigned)hz0;
 #pragma unroll
         for (int f = 0; f < NP; ++f) hr0[f] = bload<R>(rUi, o0 * ES, f * SP);
-        hq0 = bload<double>(rUi, o0 * 8u, PSI);
+        hq0 = bload<double>(pUi, o0 * 8u, 0);
         if (z_end) {
             const unsigned o1 = hbo + (unsigned)(xs * 6);
 #pragma unroll
             for (int f = 0; f < NP; ++f) hr1[f] = bload<R>(rB, o1 * ES, f * BSP);
-            hq1 = bload<double>(rB, o1 * 8u, 5u * BSP);
+            hq1 = bload<double>(pB, o1 * 8u, 0);
         }
     };
     halo_load(x0);
@@ -273,7 +293,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
             if constexpr (STAGE != 0) {
 #pragma unroll
                 for (int f = 0; f < NP; ++f) u0[f] = bload<R>(rU0, cR, f * SP);
-                p0 = bload<double>(rU0, c8, PSI);
+                p0 = bload<double>(pU0, c8, 0);
             } else {
 #pragma unroll
                 for (int f = 0; f < NP; ++f) u0[f] = q[f][3];
@@ -295,8 +315,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
                 constexpr int D = decltype(dir)::value;
 #pragma unroll
                 for (int f = 0; f < NP; ++f)
-                    acc[f] -= gx * weno_up<R>(upw<D>(q[f], 0, mx), upw<D>(q[f], 1, mx), upw<D>(q[f], 2, mx),
-                                              q[f][3], upw<D>(q[f], 4, mx), upw<D>(q[f], 5, mx));
+                    acc[f] -= gx * deriv<R>(f, upw<D>(q[f], 0, mx), upw<D>(q[f], 1, mx), upw<D>(q[f], 2, mx),
+                                            q[f][3], upw<D>(q[f], 4, mx), upw<D>(q[f], 5, mx));
                 convp = gx * weno_up<R>(upw<D>(qp, 0, mx), upw<D>(qp, 1, mx), upw<D>(qp, 2, mx), qp[3],
                                         upw<D>(qp, 4, mx), upw<D>(qp, 5, mx));
             };
@@ -310,8 +330,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
                 const int a4 = meB + step, a5 = meB + 2 * step;
 #pragma unroll
                 for (int f = 0; f < NP; ++f)
-                    acc[f] -= gR * weno_up<R>(lds_r<R>(sm, a0, f), lds_r<R>(sm, a1, f), lds_r<R>(sm, a2, f), q[f][3],
-                                              lds_r<R>(sm, a4, f), lds_r<R>(sm, a5, f));
+                    acc[f] -= gR * deriv<R>(f, lds_r<R>(sm, a0, f), lds_r<R>(sm, a1, f), lds_r<R>(sm, a2, f), q[f][3],
+                                            lds_r<R>(sm, a4, f), lds_r<R>(sm, a5, f));
                 convp += gR * weno_up<R>(lds_psi<NP>(sm, a0), lds_psi<NP>(sm, a1), lds_psi<NP>(sm, a2), qp[3],
                                          lds_psi<NP>(sm, a4), lds_psi<NP>(sm, a5));
             };
@@ -324,6 +344,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
                 acc[EGB_RE_B] += A21 * q[EGB_RE_C][3] + A22 * q[EGB_RE_B][3];
                 acc[EGB_IM_C] += A11 * q[EGB_IM_C][3] + A12 * q[EGB_IM_B][3];
                 acc[EGB_IM_B] += A21 * q[EGB_IM_C][3] + A22 * q[EGB_IM_B][3];
+                const R rc = q[EGB_RE_C][3], ic = q[EGB_IM_C][3], rb = q[EGB_RE_B][3], ib = q[EGB_IM_B][3];
+                acc[EGB_PHASE] += A12 * ((ib * rc - rb * ic) / (rc * rc + ic * ic));
             }
             if constexpr (STAGE != 0) {
 #pragma unroll
@@ -333,7 +355,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
             if (valid) {
 #pragma unroll
                 for (int f = 0; f < NP; ++f) bstore(ball ? u0[f] : acc[f], rUo, cR, f * SP);
-                bstore(ball ? p0 : accp, rUo, c8, PSI);
+                bstore(ball ? p0 : accp, pUo, c8, 0);
             }
         }
         // shift the queue
@@ -357,7 +379,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
 template <typename R, int STAGE, int TK, bool KIN, int WPE>
 __global__ __launch_bounds__(64 * TK) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_stage(StageArgs a, TileArgs t) {
-    __shared__ StageSmem<R, TK, KIN ? 1 : 5> sm;
+    __shared__ StageSmem<R, TK, KIN ? 1 : EGB_PSI> sm;
     // The (tile, x) steps, x fastest, split into gridDim.x equal contiguous
     // ranges (the grid is what the chip holds at once, so every block runs in
     // one round); a range crossing a tile boundary is two segments.
@@ -389,7 +411,7 @@ constexpr long long MIN_STEPS = 16;  // fewest x steps worth a block's prologue
 template <typename R, int STAGE, int TK, int WPE>
 __global__ __launch_bounds__(64 * TK) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_stage_batched(const BatchItem* __restrict__ items, const long long* __restrict__ wfirst, int nprob) {
-    __shared__ StageSmem<R, TK, 5> sm;
+    __shared__ StageSmem<R, TK, EGB_PSI> sm;
     const long long W = wfirst[nprob];
     const long long b = xcd_remap(blockIdx.x, gridDim.x);
     long long w = W * b / gridDim.x;
@@ -414,11 +436,15 @@ void k_stage_batched(const BatchItem* __restrict__ items, const long long* __res
     }
 }
 
-unsigned long long state_bytes_of(const GridArgs& g, size_t es) {
-    return (unsigned long long)g.stride * (5ull * es + 8ull);
-}
-unsigned long long bd_bytes_of(const GridArgs& g, size_t es) {
-    return (unsigned long long)g.bstride * (5ull * es + 8ull);
+// Descriptor extents of one grid (see TileArgs).
+void set_extents(TileArgs& t, const GridArgs& g, size_t es) {
+    t.state_bytes = (unsigned)((unsigned long long)EGB_PSI * g.stride * es);
+    t.psi_off = (unsigned long long)EGB_PSI * g.stride * es;
+    t.psi_bytes = (unsigned)(g.stride * 8ull);
+    t.vel_bytes = (unsigned)(7ull * (unsigned long long)g.stride * es);
+    t.bd_bytes = (unsigned)((unsigned long long)EGB_PSI * g.bstride * es);
+    t.bpsi_off = (unsigned long long)EGB_PSI * g.bstride * es;
+    t.bpsi_bytes = (unsigned)(g.bstride * 8ull);
 }
 
 template <typename R, int TK, bool KIN, int WPE>
@@ -428,9 +454,7 @@ hipError_t launch_stage_t(const StageArgs& a, int stage, hipStream_t s, int bloc
     t.ntk = (a.g.nth + TK - 1) / TK;
     t.kx = a.g.nx;
     t.nxc = 1;
-    t.state_bytes = (unsigned)state_bytes_of(a.g, sizeof(R));
-    t.vel_bytes = (unsigned)(7ull * (unsigned long long)a.g.stride * sizeof(R));
-    t.bd_bytes = (unsigned)bd_bytes_of(a.g, sizeof(R));
+    set_extents(t, a.g, sizeof(R));
     const void* k = stage == 0 ? (const void*)k_stage<R, 0, TK, KIN, WPE>
                   : stage == 1 ? (const void*)k_stage<R, 1, TK, KIN, WPE> : (const void*)k_stage<R, 2, TK, KIN, WPE>;
     // by default one round of resident blocks, each with at least MIN_STEPS
@@ -550,9 +574,7 @@ long long batch_item_fill(void* item, const GridArgs& g, int dtype, const void* 
     t.kx = g.nx;
     t.nxc = 1;
     t.nblocks = 0;
-    t.state_bytes = (unsigned)state_bytes_of(g, es);
-    t.vel_bytes = (unsigned)(7ull * (unsigned long long)g.stride * es);
-    t.bd_bytes = (unsigned)bd_bytes_of(g, es);
+    set_extents(t, g, es);
     it.t = t;
     void* in[3] = {state, U1, U2};
     void* out[3] = {U1, U2, last_to_work ? U1 : state};  // U1 is free again in the last stage
@@ -581,9 +603,12 @@ hipError_t launch_stage_batched(const void* items, const long long* wfirst, int 
     }
 }
 
+// Every descriptor extent (and so every byte offset inside it) below 4 GiB:
+// the velocity planes (7 per cell) are the largest.
 bool stage_fits_32bit(const GridArgs& g, int dtype) {
-    const size_t es = dtype == EGB_F64 ? 8 : 4;
-    return state_bytes_of(g, es) < (1ull << 32) && 7ull * (unsigned long long)g.stride * es < (1ull << 32);
+    const unsigned long long es = dtype == EGB_F64 ? 8 : 4, lim = 1ull << 32;
+    const unsigned long long S = (unsigned long long)g.stride, B = (unsigned long long)g.bstride;
+    return 7ull * S * es < lim && EGB_PSI * S * es < lim && S * 8ull < lim && EGB_PSI * B * es < lim && B * 8ull < lim;
 }
 
 hipError_t launch_stage(const StageArgs& a, int dtype, int stage, hipStream_t s, bool kinematic, int blocks,

@@ -205,12 +205,13 @@ __global__ __launch_bounds__(256) void k_init_state(GridArgs a, const double* C,
     const double psi = (sn * ddx + cs * ddz) / v;
     const long long c = (long long)k * a.nxz + (long long)ix * a.nz + iz;
     R* P = reinterpret_cast<R*>(state);
-    double* Ps = reinterpret_cast<double*>(P + 5 * a.stride);
+    double* Ps = reinterpret_cast<double*>(P + EGB_PSI * a.stride);
     P[EGB_PHI1 * a.stride + c] = (R)(ddx * ex + ddz * ez);
     P[EGB_RE_C * a.stride + c] = (R)s;
     P[EGB_IM_C * a.stride + c] = (R)(s * src.beta * r.A[1] * psi);
     P[EGB_RE_B * a.stride + c] = (R)0;
     P[EGB_IM_B * a.stride + c] = (R)(src.beta * s);
+    P[EGB_PHASE * a.stride + c] = (R)atan(src.beta * r.A[1] * psi);  // arg C, s > 0
     Ps[c] = psi;
 }
 
@@ -243,10 +244,10 @@ __global__ __launch_bounds__(256) void k_boundary_data(GridArgs a, const char* s
     const long long e = gi < 3 ? c0 : c0 + (long long)(len - 1) * step;
     const long long e1 = gi < 3 ? c0 + step : c0 + (long long)(len - 2) * step;
     const R* P = reinterpret_cast<const R*>(state);
-    const double* Ps = reinterpret_cast<const double*>(P + 5 * a.stride);
+    const double* Ps = reinterpret_cast<const double*>(P + EGB_PSI * a.stride);
     R* B = reinterpret_cast<R*>(bd);
-    double* Bs = reinterpret_cast<double*>(B + 5 * a.bstride);
-    for (int f = 0; f < 5; ++f)
+    double* Bs = reinterpret_cast<double*>(B + EGB_PSI * a.bstride);
+    for (int f = 0; f < EGB_PSI; ++f)
         B[f * a.bstride + i] = (R)((m + 1) * (double)P[f * a.stride + e] - m * (double)P[f * a.stride + e1]);
     Bs[i] = (m + 1) * Ps[e] - m * Ps[e1];
 }
@@ -263,7 +264,7 @@ __global__ void k_pick(GridArgs a, const char* state, const double* rx, int nr, 
     const double tx = fmin(fmax(fx - ix, 0.0), 1.0), tz = fmin(fmax(fz - iz, 0.0), 1.0);
     const double w00 = (1 - tx) * (1 - tz), w10 = tx * (1 - tz), w01 = (1 - tx) * tz, w11 = tx * tz;
     const R* phi = reinterpret_cast<const R*>(state);
-    const double* psi = reinterpret_cast<const double*>(phi + 5 * a.stride);
+    const double* psi = reinterpret_cast<const double*>(phi + EGB_PSI * a.stride);
     const long long o = (long long)ix * a.nz + iz;
     auto interp_phi = [&](int k) {
         const R* p = phi + (long long)k * a.nxz + o;

@@ -35,6 +35,16 @@ __device__ __forceinline__ R weno_up(T u0, T u1, T u2, T u3, T u4, T u5) {
     return weno5<R>((R)(u1 - u0), (R)(u2 - u1), (R)(u3 - u2), (R)(u4 - u3), (R)(u5 - u4));
 }
 
+// The fifth-order linear upwind derivative of the same six values: the three
+// WENO5 candidate stencils combined with their linear weights (0.1, 0.6,
+// 0.3), which in the differences d_k = u_k - u_(k-1) is
+//   (2 d1 - 13 d2 + 47 d3 + 27 d4 - 3 d5) / 60.
+template <typename R, typename T>
+__device__ __forceinline__ R upwind5_up(T u0, T u1, T u2, T u3, T u4, T u5) {
+    const R d1 = (R)(u1 - u0), d2 = (R)(u2 - u1), d3 = (R)(u3 - u2), d4 = (R)(u4 - u3), d5 = (R)(u5 - u4);
+    return ((R)2 * d1 - (R)13 * d2 + (R)47 * d3 + (R)27 * d4 - (R)3 * d5) * (R)(1.0 / 60.0);
+}
+
 // Value m of the upwind-ordered x stencil from the column queue q (q[3] is
 // the cell): DIR 0 = every lane upwinds from -x, 1 = every lane from +x,
 // 2 = per lane (`minus`).

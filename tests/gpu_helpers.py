@@ -4,11 +4,11 @@ import numpy as np
 
 import oracle
 
-ORACLE_TO_GPU = {"phi1": 0, "psi": 1, "ReC": 2, "ImC": 3, "ReB": 4, "ImB": 5}
+ORACLE_TO_GPU = {"phi1": 0, "psi": 1, "ReC": 2, "ImC": 3, "ReB": 4, "ImB": 5, "phase": 6}
 
 
 def oracle_planes(U):
-    """Oracle state [6][nth][nx][nz] -> dict by plane name."""
+    """Oracle state [7][nth][nx][nz] -> dict by plane name."""
     return {name: U[i] for name, i in ORACLE_TO_GPU.items()}
 
 
@@ -25,6 +25,15 @@ def rounded_oracle_state(U, dtype):
             if name != "psi":
                 out[i] = U[i].astype(np.float32).astype(np.float64)
     return out
+
+
+def plane_scale(O, name):
+    """Scale of the error of state plane `name`: the larger of its own and
+    Im B's maximum (C and B share the beam's scale), pi for the phase plane
+    (its errors are angles)."""
+    if name == "phase":
+        return np.pi
+    return max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())
 
 
 def rel_err(a, b, scale=None):

@@ -44,13 +44,14 @@ def test_sizes_and_validation_without_gpu():
     n = 40 * 72 * 36
     st = egb.plane_stride(eg)
     assert st >= n and st % 64 == 0
-    assert egb.state_bytes(eg) == 5 * st * 4 + st * 8
-    assert egb.state_plane_offset(eg, egb.EGB_PSI) == 5 * st * 4
+    assert egb.state_bytes(eg) == 6 * st * 4 + st * 8
+    assert egb.state_plane_offset(eg, egb.EGB_PHASE) == 5 * st * 4
+    assert egb.state_plane_offset(eg, egb.EGB_PSI) == 6 * st * 4
     assert egb.vel3d_bytes(eg) == 7 * st * 4
     assert egb.coeff2d_bytes(eg) == 30 * 40 * 72 * 8
     assert egb.workspace_size(eg, egb.EGB_OP_STEP) >= 2 * egb.state_bytes(eg)
     eg64 = egb.make_grid(g, "f64")
-    assert egb.state_bytes(eg64) == 6 * st * 8
+    assert egb.state_bytes(eg64) == 7 * st * 8
     # invalid grids give zero sizes and EINVAL before any device work
     bad = egb.EgbGrid(4, 72, 36, 0, 0.0, 0.0, 10.0, 10.0)
     assert egb.state_bytes(bad) == 0
@@ -75,8 +76,8 @@ def test_sizes_and_validation_without_gpu():
     assert L.egb_boundary_data(ctypes.byref(eg), None, P(256), None) == egb.EGB_EINVAL
     bs = egb.bdata_plane_stride(eg)
     assert bs >= 36 * 6 * (40 + 72) and bs % 64 == 0
-    assert egb.bdata_bytes(eg) == 5 * bs * 4 + bs * 8
-    assert egb.bdata_bytes(eg64) == 6 * bs * 8
+    assert egb.bdata_bytes(eg) == 6 * bs * 4 + bs * 8
+    assert egb.bdata_bytes(eg64) == 7 * bs * 8
     assert egb.bfold_bytes(eg) == 2 * 36 * 12 * (40 + 72) * 8
     badlin = egb.EgbSource(1.0, 1.0, 1.0, 1e-4, 7)  # no such linear-phase variant
     assert L.egb_init_state(ctypes.byref(eg), ctypes.c_void_p(256), ctypes.byref(badlin), ctypes.c_void_p(256),

@@ -6,7 +6,7 @@ import torch
 
 import oracle
 import workloads as W
-from tests.gpu_helpers import gpu_planes, log, oracle_planes, rel_err
+from tests.gpu_helpers import gpu_planes, log, oracle_planes, rel_err, plane_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -60,7 +60,7 @@ def test_batched_equals_single_and_oracle(dtype):
     G, O = gpu_planes(batch[0]), oracle_planes(o["U"])
     tol = 1e-10 if dtype == "f64" else 1e-5
     for name in O:
-        sc = max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())
+        sc = plane_scale(O, name)
         assert rel_err(G[name], O[name], sc) < tol, name
 
 
@@ -103,5 +103,5 @@ def test_full_size_batch_equals_single_problems():
     o = oracle.solve(p, nsteps=2, dt=batch[small].dt_cfl)
     G, O = gpu_planes(batch[small]), oracle_planes(o["U"])
     for name in O:
-        sc = max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())
+        sc = plane_scale(O, name)
         assert rel_err(G[name], O[name], sc) < 1e-5, name

@@ -36,7 +36,7 @@ import torch
 import oracle
 import workloads as W
 from tests.conftest import progress
-from tests.gpu_helpers import gpu_planes, oracle_planes, rel_err
+from tests.gpu_helpers import gpu_planes, oracle_planes, rel_err, plane_scale
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -92,7 +92,7 @@ def full_length(p, label):
     prel = lambda t: (np.abs(t - t_or)[ok] / t_or[ok]).max()
 
     # FP64: the oracle's arithmetic
-    e64 = {name: rel_err(G64[name], O[name], max(np.abs(O[name]).max(), np.abs(O["ImB"]).max() if name != "psi" else 0))
+    e64 = {name: rel_err(G64[name], O[name], np.abs(O[name]).max() if name == "psi" else plane_scale(O, name))
            for name in O}
     w64 = wrel(W64)
     progress(f"[{label}] FP64 planes " + " ".join(f"{k} {v:.1e}" for k, v in e64.items()) +
@@ -108,8 +108,8 @@ def full_length(p, label):
     dpsi = np.abs(G32["psi"] - O["psi"])
     trel = (dpsi[far] / O["psi"][far]).max()
     tabs = dpsi[act].max() / O["psi"][act].max()
-    errs = {name: rel_err(G32[name], O[name], max(np.abs(O[name]).max(), np.abs(O["ImB"]).max()))
-            for name in ("phi1", "ReC", "ImC", "ReB", "ImB")}
+    errs = {name: rel_err(G32[name], O[name], plane_scale(O, name))
+            for name in ("phi1", "ReC", "ImC", "ReB", "ImB", "phase")}
     w32 = wrel(W32)
     progress(f"[{label}] FP32 psi rel {trel:.2e} over {far.sum()} active cells beyond 2 r0, abs/max {tabs:.2e}; "
              + " ".join(f"{k} {v:.1e}" for k, v in errs.items()))

@@ -15,7 +15,7 @@ import torch
 
 import oracle
 import workloads as W
-from tests.gpu_helpers import ORACLE_TO_GPU, gpu_planes, log, oracle_planes, rel_err, rounded_oracle_state
+from tests.gpu_helpers import ORACLE_TO_GPU, gpu_planes, log, oracle_planes, rel_err, rounded_oracle_state, plane_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -85,7 +85,7 @@ def test_table_velocity_init(dtype, tilt):
     G, O = gpu_planes(s), oracle_planes(o["U0"])
     for name in ORACLE_TO_GPU:
         t_ = 1e-12 if (dtype == "f64" or name == "psi") else 2e-6
-        assert rel_err(G[name], O[name], max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())) < t_, name
+        assert rel_err(G[name], O[name], plane_scale(O, name)) < t_, name
 
 
 def boundary_views(eg, bdata):
@@ -98,7 +98,7 @@ def boundary_views(eg, bdata):
     es = torch.empty((), dtype=rd).element_size()
     out = {}
     for p, name in enumerate(e.STATE_PLANES):
-        dt, off = (torch.float64, 5 * bs * es) if p == e.EGB_PSI else (rd, p * bs * es)
+        dt, off = (torch.float64, e.EGB_PSI * bs * es) if p == e.EGB_PSI else (rd, p * bs * es)
         flat = bdata[off:off + bs * torch.empty((), dtype=dt).element_size()].view(dt).double().cpu().numpy()
         out[name] = (flat[:nxg].reshape(eg.nth, 6, eg.nz), flat[nxg:nxg + nzg].reshape(eg.nth, eg.nx, 6))
     return out
@@ -139,8 +139,8 @@ def test_march_parity_f32(tilt):
     trel = (np.abs(G["psi"] - O["psi"]) / O["psi"])[act].max()
     log(f"  psi max rel err over {act.sum()} active cells: {trel:.3e}")
     assert trel <= 1e-5
-    for name in ("phi1", "ReC", "ImC", "ReB", "ImB"):
-        sc = max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())
+    for name in ("phi1", "ReC", "ImC", "ReB", "ImB", "phase"):
+        sc = plane_scale(O, name)
         e = rel_err(G[name], O[name], sc)
         log(f"  {name}: {e:.3e}")
         assert e <= 1e-4, name
@@ -156,7 +156,7 @@ def test_march_parity_interior_tiles(dtype):
     s = run_gpu(p, dtype, p.nsteps, dt=o["dt"])
     G, O = gpu_planes(s), oracle_planes(o["U"])
     for name in O:
-        sc = max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())
+        sc = plane_scale(O, name)
         e = rel_err(G[name], O[name], sc)
         log(f"  {name}: {e:.3e}")
         assert e <= (1e-10 if dtype == "f64" else 1e-4), name
@@ -173,7 +173,7 @@ def test_homog_iso_64_fp64_full_workload():
     s = run_gpu(p, "f64", p.nsteps, dt=o["dt"])
     G, O = gpu_planes(s), oracle_planes(o["U"])
     for name in ORACLE_TO_GPU:
-        sc = max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())
+        sc = plane_scale(O, name)
         assert rel_err(G[name], O[name], sc) < 1e-10, name
     out = s.beam(p.omegas).cpu().numpy()
     Gb = out[..., 0] + 1j * out[..., 1]
@@ -268,7 +268,7 @@ def test_minimum_grid_and_zero_steps():
     torch.cuda.synchronize()
     G, O = gpu_planes(s), oracle_planes(o["U"])
     for name in ORACLE_TO_GPU:
-        sc = max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())
+        sc = plane_scale(O, name)
         assert rel_err(G[name], O[name], sc) < 1e-10, name
 
 
@@ -283,8 +283,8 @@ def test_vti_256_full_size_one_step():
     rel = np.abs(G["psi"] - O["psi"]) / np.maximum(np.abs(O["psi"]), 1e-3)
     log(f"  psi max rel err (|psi| >= 1e-3 floor): {rel.max():.3e}")
     assert rel.max() <= 1e-5
-    for name in ("phi1", "ReC", "ImC", "ReB", "ImB"):
-        sc = max(np.abs(O[name]).max(), np.abs(O["ImB"]).max())
+    for name in ("phi1", "ReC", "ImC", "ReB", "ImB", "phase"):
+        sc = plane_scale(O, name)
         e = rel_err(G[name], O[name], sc)
         log(f"  {name}: {e:.3e}")
         assert e <= 1e-5, name
@@ -327,7 +327,7 @@ def test_tti_512_full_size_window():
         if name == "psi":
             worst[name] = float((np.abs(G - R) / np.maximum(np.abs(R), 1e-3)).max())
         else:
-            worst[name] = rel_err(G, R, max(np.abs(R).max(), np.abs(O["ImB"][inner]).max()))
+            worst[name] = rel_err(G, R, np.pi if name == "phase" else max(np.abs(R).max(), np.abs(O["ImB"][inner]).max()))
     log("  " + " ".join(f"{k}: {v:.2e}" for k, v in worst.items()))
     assert worst.pop("psi") <= 1e-5
     for name, e in worst.items():
