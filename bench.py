@@ -37,6 +37,7 @@ FLOP_CELL_STAGE = 18 * FLOP_WENO + 3 * FLOP_UPWIND5 + 7 * 6 + 3 + 17 + 9 + 7 * 5
 PEAK_FP32_TFLOPS = 157.3           # published MI355X FP32 vector peak (counts packed, dual-lane FP32)
 PEAK_FP32_UNPACKED_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz: one FP32 op per lane
 PEAK_HBM_GBPS = 8000.0             # HBM3E spec
+XCDS = 8                           # accelerator dies (each with its own L2 and cycle counter)
 # State bytes per cell (six FP32 planes and psi in FP64); one RK3 step must
 # at least read and write the state once: the HBM floor per cell-update.
 STATE_BYTES_PER_CELL = 6 * 4 + 8
@@ -384,10 +385,14 @@ def summarize_counters(fetch_dir, write_dir, sq_dir):
         if is_stage(k):
             per_stage[stage_of(k)]["write"].append(wa[d]["WRITE_SIZE"] * 1024 * wscale)
     sa, sk, _ = per_dispatch(sq_dir, {"SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVES", "GRBM_GUI_ACTIVE"})
+    # GRBM_GUI_ACTIVE counts the cycles of each XCD: rocprofv3 either lists
+    # the 8 instances per dispatch or gives one row with their sum; the
+    # device's busy cycles are their mean either way
     inst_counts = defaultdict(int)
     for r in _counter_rows(sq_dir):
         if r["Counter_Name"] == "GRBM_GUI_ACTIVE":
             inst_counts[int(r["Dispatch_Id"])] += 1
+    inst_counts = {d: (XCDS if n == 1 else n) for d, n in inst_counts.items()}
     for d, k in sk.items():
         if is_stage(k):
             st = per_stage[stage_of(k)]
@@ -574,7 +579,8 @@ def stage_roofline(p, r, rec):
     achieved = cells * FLOP_CELL_STAGE / (stage_ms * 1e-3) / 1e12
     traffic = None if rec is None else rec["hbm_bytes_per_launch"]
     hbm = None if traffic is None else traffic / (stage_ms * 1e-3) / 1e9
-    valu = None if rec is None or rec.get("valu_instr_per_launch") is None else rec["valu_instr_per_launch"] / cells
+    # SQ_INSTS_VALU counts wave instructions; a wave updates 64 cells (one per lane)
+    valu = None if rec is None or rec.get("valu_instr_per_launch") is None else rec["valu_instr_per_launch"] * 64 / cells
     return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
             "kernel": "k_stage (one SSP-RK3 stage)", "avg_launch_ms": stage_ms, "blocks_per_launch": r["blocks"],
