@@ -196,6 +196,9 @@ egb_status egb_liouville_step(const egb_grid *g, const void *vel3d, const egb_so
  * the nearest whole number of turns in (phase - arg C) / 2 pi.
  * In: omegas (HOST float64 [nw], rad/s).  Out: out, complex [nw][nx][nz]
  * interleaved (re, im) in the grid dtype (complex64 / complex128).
+ * Each row and column sums its beams in the order of their phase cells
+ * (theta, then the position along the line), so the result is the same bit
+ * for bit on every call, whatever order the beams were collected in.
  * work: egb_workspace_size(g, EGB_OP_BEAM).  Synchronises `stream` once;
  * EGB_EWORKSPACE if a per-row/column beam list overflowed. */
 egb_status egb_beam_sum(const egb_grid *g, const void *coeff2d, const void *vel3d, const egb_source *src,
@@ -204,8 +207,8 @@ egb_status egb_beam_sum(const egb_grid *g, const void *coeff2d, const void *vel3
 
 /* egb_beam_sum for callers that cannot allocate (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
- * kernels and results, with the scratch (line counts and beam record
- * lists) in a fixed array of egb_beam_scratch_bytes() = 128 MiB that the
+ * kernels and results, with the scratch (line counts, beam record lists
+ * and their order) in a fixed array of egb_beam_scratch_bytes() = 128 MiB that the
  * library holds on every device it runs on until the process ends.  The
  * caller passes inputs and outputs as for egb_beam_sum; nothing is
  * allocated on the device or the host.  Each line list holds as many

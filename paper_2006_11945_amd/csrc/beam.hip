@@ -32,8 +32,11 @@
 
 namespace egb {
 
+// key: the record's source cell along its line (theta row times the line
+// length plus the position), unique within a line; it fixes the order of
+// the sum (see k_beam_order)
 struct BeamRec {
-    double psi, pos, p, Mre, Mim, are, aim, pad;
+    double psi, pos, p, Mre, Mim, are, aim, key;
 };
 
 size_t beam_record_bytes() { return sizeof(BeamRec); }
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(256) void k_beam_compact(BeamArgs a) {
         r.Mim = Mnim * hzr * hzr;
         r.are = w * sqre;
         r.aim = w * sqim;
-        r.pad = 0.0;
+        r.key = (double)((long long)k * g.nx + ix);
         if (r.Mim > 0.0) {  // a Gaussian beam decays away from its centre
             const int slot = atomicAdd(&a.counts[iz], 1);
             if (slot < a.cap) rows[(long long)iz * a.cap + slot] = r;
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(256) void k_beam_compact(BeamArgs a) {
         r.Mim = Mnim * hxr * hxr;
         r.are = w * sqre;
         r.aim = w * sqim;
-        r.pad = 0.0;
+        r.key = (double)((long long)k * g.nz + iz);
         if (r.Mim > 0.0) {
             const int slot = atomicAdd(&a.counts[g.nz + ix], 1);
             if (slot < a.cap) cols[(long long)ix * a.cap + slot] = r;
@@ -215,6 +218,7 @@ __global__ __launch_bounds__(64) void k_beam_line(BeamArgs a, Omegas om, R* out)
     const double pos = ROW ? g.x0 + (j + 0.5) * g.dx : g.z0 + (j + 0.5) * g.dz;
     const int cnt = min(a.counts[ROW ? line : g.nz + line], a.cap);
     const BeamRec* recs = reinterpret_cast<const BeamRec*>(ROW ? a.rows : a.cols) + (long long)line * a.cap;
+    const int* ord = a.order + ((ROW ? 0LL : (long long)g.nz) + line) * a.cap;
     R gre[WCHUNK], gim[WCHUNK];
 #pragma unroll
     for (int w = 0; w < WCHUNK; ++w) gre[w] = gim[w] = (R)0;
@@ -235,7 +239,7 @@ __global__ __launch_bounds__(64) void k_beam_line(BeamArgs a, Omegas om, R* out)
         ei = mag * sph;
     };
     for (int r = 0; r < cnt; ++r) {
-        const BeamRec b = recs[r];
+        const BeamRec b = recs[ord[r]];  // in key order: the sum does not depend on the append order
         const double d = pos - b.pos;
         const double Tre = b.psi + b.p * d + 0.5 * b.Mre * d * d;
         const double Tim = 0.5 * b.Mim * d * d;
@@ -299,6 +303,33 @@ __global__ __launch_bounds__(64) void k_beam_line(BeamArgs a, Omegas om, R* out)
             out[o] += -gim[w] * s;
             out[o + 1] += gre[w] * s;
         }
+    }
+}
+
+// The order of one line's records by key: record r goes to position
+// #{s : key_s < key_r} (keys are unique within a line), so every run sums a
+// line in the same order whatever order the compaction's atomic appends took.
+// grid: (ORDER_BLOCKS, lines), 256 threads; the keys of the line pass through
+// LDS 256 at a time.
+constexpr int ORDER_BLOCKS = 16;
+template <bool ROW>
+__global__ __launch_bounds__(256) void k_beam_order(BeamArgs a) {
+    __shared__ double ks[256];
+    const int line = blockIdx.y;
+    const int cnt = min(a.counts[ROW ? line : a.g.nz + line], a.cap);
+    const BeamRec* recs = reinterpret_cast<const BeamRec*>(ROW ? a.rows : a.cols) + (long long)line * a.cap;
+    int* ord = a.order + ((ROW ? 0LL : (long long)a.g.nz) + line) * a.cap;
+    for (int r0 = blockIdx.x * 256; r0 < cnt; r0 += gridDim.x * 256) {  // block-uniform
+        const int r = r0 + (int)threadIdx.x;
+        const double kr = r < cnt ? recs[r].key : 0.0;
+        int rank = 0;
+        for (int s0 = 0; s0 < cnt; s0 += 256) {
+            __syncthreads();
+            ks[threadIdx.x] = s0 + (int)threadIdx.x < cnt ? recs[s0 + threadIdx.x].key : INFINITY;
+            __syncthreads();
+            for (int j = 0; j < 256; ++j) rank += ks[j] < kr;
+        }
+        if (r < cnt) ord[rank] = r;
     }
 }
 
@@ -469,7 +500,7 @@ __global__ __launch_bounds__(256) void k_pbeam_compact(PBeamArgs a) {
     }
     r.are = w * sqre;
     r.aim = w * sqim;
-    r.pad = 0.0;
+    r.key = (double)c;
     if (!(r.Mim > 0.0)) return;  // not a Gaussian beam (grows away from its centre)
     const int slot = atomicAdd(&a.counts[n], 1);
     if (slot < a.cap) reinterpret_cast<BeamRec*>(a.rows)[(long long)n * a.cap + slot] = r;
@@ -506,6 +537,8 @@ hipError_t launch_max_i32(const int* p, int n, int* out, hipStream_t s) {
 }
 
 hipError_t launch_beam_sum(const BeamArgs& a, int dtype, const double* omegas, int nw, void* out, hipStream_t s) {
+    k_beam_order<true><<<dim3(ORDER_BLOCKS, a.g.nz), 256, 0, s>>>(a);
+    k_beam_order<false><<<dim3(ORDER_BLOCKS, a.g.nx), 256, 0, s>>>(a);
     for (int w0 = 0; w0 < nw; w0 += WCHUNK) {
         Omegas om;
         om.n = nw - w0 < WCHUNK ? nw - w0 : WCHUNK;

@@ -155,9 +155,9 @@ size_t egb_workspace_size(const egb_grid* g, int32_t op) {
         case EGB_OP_VELOCITY: return 256;
         case EGB_OP_STEP: return 2 * align256(state_bytes(*g));
         case EGB_OP_BEAM:
-            return beam_counts_bytes(*g) + (size_t)(g->nx + g->nz) * beam_cap_default(*g) * beam_record_bytes();
+            return beam_counts_bytes(*g) + (size_t)(g->nx + g->nz) * beam_cap_default(*g) * beam_slot_bytes();
         case EGB_OP_PARAXIAL: return 2 * align256(paraxial_level_bytes(*g));
-        case EGB_OP_PBEAM: return beam_counts_bytes(*g) + (size_t)g->nz * pbeam_cap_default(*g) * beam_record_bytes();
+        case EGB_OP_PBEAM: return beam_counts_bytes(*g) + (size_t)g->nz * pbeam_cap_default(*g) * beam_slot_bytes();
         case EGB_OP_ADJOINT: {
             const size_t step = 5 * align256(state_bytes(*g));
             const size_t med = align256((size_t)15 * g->nx * g->nz * sizeof(double)) +
@@ -471,7 +471,7 @@ egb_status egb_paraxial_beam_sum(const egb_grid* g, const void* coeff2d, const v
     for (int w = 0; w < nw; ++w)
         if (!isfinite(omegas[w]) || !(omegas[w] > 0.0)) return EGB_EINVAL;
     const size_t cb = beam_counts_bytes(*g);
-    const size_t per = (size_t)g->nz * beam_record_bytes();
+    const size_t per = (size_t)g->nz * beam_slot_bytes();
     if (work_bytes < cb + per) return EGB_EWORKSPACE;
     const size_t capz = (work_bytes - cb) / per;
     const int cap = capz > (size_t)(1 << 30) ? (1 << 30) : (int)capz;
@@ -507,6 +507,7 @@ egb_status egb_paraxial_beam_sum(const egb_grid* g, const void* coeff2d, const v
     ba.counts = pa.counts;
     ba.rows = pa.rows;
     ba.cols = pa.rows;
+    ba.order = reinterpret_cast<int*>(w + cb + (size_t)g->nz * cap * beam_record_bytes());
     hipError_t e = launch_pbeam_compact(pa, g->dtype, stream);
     if (e == hipSuccess) e = launch_beam_sum(ba, g->dtype, omegas, nw, out, stream);
     std::vector<int> counts(g->nz);
@@ -835,7 +836,7 @@ static egb_status beam_sum_run(const egb_grid* g, const void* coeff2d, const voi
                                const void* state, const double* omegas, int32_t nw, void* out, void* work,
                                size_t work_bytes, hipStream_t stream) {
     const size_t cb = beam_counts_bytes(*g);
-    const size_t per = (size_t)(g->nx + g->nz) * beam_record_bytes();
+    const size_t per = (size_t)(g->nx + g->nz) * beam_slot_bytes();
     if (work_bytes < cb + per) return EGB_EWORKSPACE;
     const size_t capz = (work_bytes - cb) / per;
     const int cap = capz > (size_t)(1 << 30) ? (1 << 30) : (int)capz;
@@ -851,6 +852,7 @@ static egb_status beam_sum_run(const egb_grid* g, const void* coeff2d, const voi
     ba.counts = reinterpret_cast<int*>(w);
     ba.rows = w + cb;
     ba.cols = w + cb + (size_t)g->nz * cap * beam_record_bytes();
+    ba.order = reinterpret_cast<int*>(w + cb + (size_t)(g->nx + g->nz) * cap * beam_record_bytes());
     hipError_t e = launch_beam_compact(ba, g->dtype, stream);
     if (e == hipSuccess) e = launch_beam_sum(ba, g->dtype, omegas, nw, out, stream);
     // the longest list (a device reduction into the slot after the counts)
@@ -879,7 +881,7 @@ egb_status egb_beam_sum_noalloc(const egb_grid* g, const void* coeff2d, const vo
     const egb_status st = beam_sum_checks(g, coeff2d, vel3d, src, state, omegas, nw, out);
     if (st != EGB_OK) return st;
     // the fixed scratch must hold the line counts and at least BEAM_SCRATCH_MIN_CAP records per line
-    const size_t need = beam_counts_bytes(*g) + (size_t)(g->nx + g->nz) * BEAM_SCRATCH_MIN_CAP * beam_record_bytes();
+    const size_t need = beam_counts_bytes(*g) + (size_t)(g->nx + g->nz) * BEAM_SCRATCH_MIN_CAP * beam_slot_bytes();
     if (need > BEAM_SCRATCH_BYTES) return EGB_EUNSUPPORTED;
     void* ptr = nullptr;
     if (beam_scratch_address(&ptr) != hipSuccess) return EGB_EHIP;

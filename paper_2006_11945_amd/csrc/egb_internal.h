@@ -180,6 +180,7 @@ struct BeamArgs {
     int* counts;      // [nz rows][nx cols]
     void* rows;       // row records
     void* cols;       // column records
+    int* order;       // per line, cap entries: the record indices in the order of their keys
 };
 hipError_t launch_beam_compact(const BeamArgs& a, int dtype, hipStream_t s);
 // Beam records of the depth march (rows = levels; see beam.hip).
@@ -207,5 +208,7 @@ hipError_t launch_beam_sum(const BeamArgs& a, int dtype, const double* omegas, i
 // *out = max(p[0 .. n)) (one block)
 hipError_t launch_max_i32(const int* p, int n, int* out, hipStream_t s);
 size_t beam_record_bytes();
+// bytes per record slot of a line list: the record and its entry in the line's order
+inline size_t beam_slot_bytes() { return beam_record_bytes() + sizeof(int); }
 
 }  // namespace egb
