@@ -144,8 +144,8 @@ def batched_vs_sequential(nprob, nsteps, lo=128, hi=384, tune=True):
 
 def adjoint_vs_forward(nsrc, nsteps, n=256):
     """Traveltime misfit at 128 receivers for `nsrc` of the 16 sources on the
-    VTI medium: forward (kinematic march with checkpoints every 16 steps +
-    pick) and backward (pick adjoint, recomputation, adjoint steps, medium
+    VTI medium: forward (kinematic march keeping the states the backward
+    sweep needs + pick) and backward (pick adjoint, recomputation, adjoint steps, medium
     gradient) timed separately, next to the plain full-plane forward march."""
     from dataclasses import replace
 
@@ -163,10 +163,16 @@ def adjoint_vs_forward(nsrc, nsteps, n=256):
     # one step for every march: within the CFL limits of the model and of the
     # perturbed medium that makes the observed traveltimes
     dt = min(egb.Solver(probs[0], dev).velocity(), egb.Solver(replace(probs[0], medium=true), dev).velocity())
+    # every step's phi1 and psi resident in HBM (FP32 phi1 + FP64 psi per cell
+    # and step) when that takes at most half of the free memory, else a
+    # checkpoint every 16 steps and the segments recomputed
+    g0 = probs[0].grid
+    need = nsteps * g0.nx * g0.nz * g0.nth * (4 + 8)
+    K = 0 if need <= 0.5 * torch.cuda.mem_get_info(dev)[0] else 16
     t_fwd = t_bwd = t_plain = 0.0
     for p in probs[:nsrc]:
         spec = {"grid": p.grid, "source": p.source, "receivers": p.receivers, "nsteps": nsteps, "vs_ratio": 0.5,
-                "dtype": "f32", "checkpoint_every": 16, "dt": dt}
+                "dtype": "f32", "checkpoint_every": K, "dt": dt}
         with torch.no_grad():
             t_obs = egb.traveltime(*mk(true), spec)
         ts = mk(p.medium, True)
@@ -193,7 +199,9 @@ def adjoint_vs_forward(nsrc, nsteps, n=256):
         del s, ts, t, J
         torch.cuda.empty_cache()
     cu = probs[0].grid.ncell * nsteps * nsrc
-    return {"sources": nsrc, "rk3_steps": nsteps, "receivers": 128, "checkpoint_every": 16,
+    return {"sources": nsrc, "rk3_steps": nsteps, "receivers": 128,
+            "states_kept": "every step's phi1 and psi resident" if K == 0 else f"a checkpoint every {K} steps",
+            "archive_GB": need / 1e9 if K == 0 else 0.0,
             "forward_s": t_fwd, "backward_s": t_bwd, "plain_forward_s": t_plain,
             "backward_cell_updates_per_s": cu / t_bwd, "backward_over_plain_forward": t_bwd / t_plain}
 

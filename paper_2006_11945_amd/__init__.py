@@ -656,15 +656,24 @@ class TravelTime(torch.autograd.Function):
     the gridded medium (vp0, eps, delta, tilt; float64 device tensors [nx][nz]).
 
     forward: medium table and velocity, point-source data, ``nsteps``
-    kinematic RK3 steps (phi1, psi) keeping a state every ``checkpoint_every``
-    steps, then the pick.  backward: the pick adjoint, then segment by segment
-    in reverse the forward states are recomputed from the checkpoint and the
-    adjoint step is applied, and finally the medium gradient.  The time step
-    is fixed (the CFL step of the forward medium unless ``spec['dt']`` is set).
+    kinematic RK3 steps (phi1, psi), then the pick.  The states the backward
+    sweep needs are kept in one of two ways:
+    * ``checkpoint_every`` = K > 0: a whole state every K steps; the backward
+      sweep recomputes each segment from its checkpoint;
+    * K = 0: the two planes the adjoint reads (phi1, psi) of every step's
+      state, resident in device memory (12 B per cell and step in FP32:
+      121 GB for 600 steps at 256^3, which HBM of 288 GB holds), so nothing
+      is recomputed but the two inner stages of each step;
+    * K = "auto" (the default): 0 when the archive takes at most half of the
+      free device memory, else 16.
+    backward: the pick adjoint, then step by step in reverse the adjoint
+    step, and finally the medium gradient.  The gradient is the same bit for
+    bit for every K.  The time step is fixed (the CFL step of the forward
+    medium unless ``spec['dt']`` is set).
 
     spec: grid (nx, nz, nth, x0, z0, dx, dz), source (xs, zs, r0, beta),
     receivers (numpy [nr][2]), nsteps, vs_ratio, dtype ("f32" / "f64"),
-    checkpoint_every (default 16), dt (optional).
+    checkpoint_every (default "auto"), dt (optional).
     """
 
     @staticmethod
@@ -684,11 +693,26 @@ class TravelTime(torch.autograd.Function):
         bdata = alloc_bytes(bdata_bytes(eg), dev)
         egb_boundary_data(eg, state, bdata)
         work = alloc_bytes(workspace_size(eg, EGB_OP_STEP), dev)
-        K = int(spec.get("checkpoint_every", 16))
         nsteps = int(spec["nsteps"])
-        ckpts = []
+        views = state_views(eg, state)
+        K = spec.get("checkpoint_every", "auto")
+        if not any(ctx.needs_input_grad[:4]):
+            K = nsteps  # no backward sweep will run: only the start is kept
+        elif K == "auto":
+            need = nsteps * (views["phi1"].numel() * views["phi1"].element_size() +
+                             views["psi"].numel() * views["psi"].element_size())
+            K = 0 if need <= 0.5 * torch.cuda.mem_get_info(dev)[0] else 16
+        K = int(K)
+        ckpts, arch = [], None
+        if K == 0:  # phi1 and psi of every step's state, resident
+            arch = (torch.empty((nsteps,) + tuple(views["phi1"].shape), dtype=views["phi1"].dtype, device=dev),
+                    torch.empty((nsteps,) + tuple(views["psi"].shape), dtype=views["psi"].dtype, device=dev))
+            for i in range(nsteps):
+                arch[0][i].copy_(views["phi1"])
+                arch[1][i].copy_(views["psi"])
+                egb_liouville_step_kinematic(eg, vel3d, src, bdata, state, work, dt, 1)
         done = 0
-        while done < nsteps:
+        while K > 0 and done < nsteps:
             ckpts.append((done, state.clone()))
             n = min(K, nsteps - done)
             egb_liouville_step_kinematic(eg, vel3d, src, bdata, state, work, dt, n)
@@ -697,7 +721,7 @@ class TravelTime(torch.autograd.Function):
         t = torch.empty(rx.shape[0], dtype=torch.float64, device=dev)
         egb_pick_receivers(eg, state, rx, t)
         ctx.egb = dict(eg=eg, src=src, med=med, coeff2d=coeff2d, vel3d=vel3d, bdata=bdata, dt=dt, K=K, nsteps=nsteps,
-                       ckpts=ckpts, final=state, rx=rx, work=work)
+                       ckpts=ckpts, arch=arch, final=state, rx=rx, work=work)
         return t
 
     @staticmethod
@@ -710,6 +734,13 @@ class TravelTime(torch.autograd.Function):
         tb = torch.nan_to_num(tbar.detach().to(torch.float64).contiguous(), nan=0.0)
         egb_pick_adjoint(eg, d["final"], d["rx"], tb, lam)
         wadj = alloc_bytes(workspace_size(eg, EGB_OP_ADJOINT), dev)
+        if d["arch"] is not None:  # every step's phi1 and psi are resident
+            st = d["final"].clone()
+            v = state_views(eg, st)
+            for i in reversed(range(d["nsteps"])):
+                v["phi1"].copy_(d["arch"][0][i])
+                v["psi"].copy_(d["arch"][1][i])
+                egb_adjoint_step(eg, d["vel3d"], src, d["bdata"], st, lam, gvel, bfold, wadj, d["dt"])
         for start, ck in reversed(d["ckpts"]):
             n = min(d["K"], d["nsteps"] - start)
             states = [ck]

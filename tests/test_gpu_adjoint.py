@@ -100,7 +100,12 @@ def test_adjoint_checkpoint_interval_does_not_change_gradient():
                                                  dt=r["dt"])["U"], rx)
     _, g1, _ = gpu_gradient(p, rx, t_obs, "f64", r["dt"], K=1)
     _, g2, _ = gpu_gradient(p, rx, t_obs, "f64", r["dt"], K=4)
-    for a, b in zip(g1, g2):
+    _, g0, _ = gpu_gradient(p, rx, t_obs, "f64", r["dt"], K=0)  # every step's phi1 and psi resident
+    _, g32a, _ = gpu_gradient(p, rx, t_obs, "f32", r["dt"], K=0)
+    _, g32b, _ = gpu_gradient(p, rx, t_obs, "f32", r["dt"], K=3)
+    for a, b, c in zip(g1, g2, g0):
+        assert np.array_equal(a, b) and np.array_equal(a, c)
+    for a, b in zip(g32a, g32b):
         assert np.array_equal(a, b)
 
 
