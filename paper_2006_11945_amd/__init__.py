@@ -752,6 +752,7 @@ class TravelTime(torch.autograd.Function):
                 egb_adjoint_step(eg, d["vel3d"], src, d["bdata"], st, lam, gvel, bfold, wadj, d["dt"])
         grad = torch.empty((4, eg.nx, eg.nz), dtype=torch.float64, device=dev)
         egb_adjoint_medium(eg, d["med"], d["coeff2d"], src, gvel, lam, bfold, grad, wadj)
+        d["arch"], d["ckpts"] = None, []  # the kept states are not needed again
         return grad[0], grad[1], grad[2], grad[3], None
 
 
