@@ -132,6 +132,15 @@ __device__ __forceinline__ void fold_weights(const C (&d)[NSLOT], int s, int n, 
     }
 }
 
+// *p += v as one atomic add whose old value is not returned: the kernels add
+// to an entry of g_V or of the boundary buffer from one thread per launch
+// (so the sums are deterministic), and an add in memory needs no wait for a
+// load, which in a loop with loads in flight would wait for all of them.
+template <typename T>
+__device__ __forceinline__ void add_to(T* p, T v) {
+    (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Index of a boundary-sensitivity entry: plane p (0 phi1, 1 psi), theta k,
 // line end e (0 near, 1 far), source s (0..2 counted from that end, inward),
 // weight w (0 end cell, 1 its neighbour); x lines by z, z lines by x.
@@ -171,7 +180,6 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
     const auto rUi = make_rsrc(a.Uin, a.state_bytes);
     const auto rL = make_rsrc(a.lam, a.state_bytes);
     const auto rV = make_rsrc(a.vel, a.vel_bytes);
-    const auto rG = make_rsrc(a.gvel, a.gvel_bytes);
     const auto rB = make_rsrc(a.bd, a.bd_bytes);
     const auto pUi = make_rsrc(static_cast<const char*>(a.Uin) + a.psi_off, a.psi_bytes);
     const auto pL = make_rsrc(static_cast<const char*>(a.lam) + a.psi_off, a.psi_bytes);
@@ -366,8 +374,6 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
             oa1 = bload<double>(pAi, co * 8u, 0);
         }
         const bool wlive = __any(cm0 != (R)0 || cm1 != 0.0);  // wave-uniform
-        // (straight-line: the store is guarded, the address is clamped)
-        const R gv0 = bload<R>(rG, cR, 0), gv1 = bload<R>(rG, cR, SP), gv2 = bload<R>(rG, cR, 2u * SP);
         // the next core slice's values and halo, one step ahead: their latency
         // hides behind this step's rows (the registers of this slice's values
         // are free once it is in LDS)
@@ -397,7 +403,7 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
             if (xfold && valid) {
                 const int e = xs < 3 ? 0 : 1, sidx = e == 0 ? xs : g.nx - 1 - xs;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) a.bfold[bfold_x(g, q >> 1, k, e, sidx, q & 1, iz)] += f[q];
+                for (int q = 0; q < 4; ++q) add_to(&a.bfold[bfold_x(g, q >> 1, k, e, sidx, q & 1, iz)], f[q]);
             }
             // d(-cb dt V_x D_x U / dx)/dV_x with D_x U = sign * W_up / dx
             gsx = (R)(plus ? -kx : kx) * (cm0 * W0 + (R)cm1 * W1);
@@ -432,7 +438,7 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
                     fold_weights(d, zg, g.nz, f[2], f[3]);
                     const int e = zg < 3 ? 0 : 1, sidx = e == 0 ? zg : g.nz - 1 - zg;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) a.bfold[bfold_z(g, q >> 1, k, xs, e, sidx, q & 1)] += f[q];
+                    for (int q = 0; q < 4; ++q) add_to(&a.bfold[bfold_z(g, q >> 1, k, xs, e, sidx, q & 1)], f[q]);
                 }
 #pragma unroll
                 for (int j = 0; j < NSLOT; ++j) dst[(NSLOT + j) * stride] = d[j];
@@ -468,9 +474,10 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
                 }
             }
             if (valid && wlive) {
-                bstore(gv0 + gsx, rG, cR, 0);
-                bstore(gv1 + (R)(-kz) * Wz, rG, cR, SP);
-                bstore(gv2 + (R)(-kt) * Wt, rG, cR, 2u * SP);
+                R* gv = reinterpret_cast<R*>(static_cast<char*>(a.gvel) + cR);
+                add_to(gv, gsx);
+                add_to(gv + g.stride, (R)(-kz) * Wz);
+                add_to(gv + 2 * g.stride, (R)(-kt) * Wt);
             }
             __syncthreads();
             // sum the slots aimed at the own cell
