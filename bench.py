@@ -146,7 +146,9 @@ def adjoint_vs_forward(nsrc, nsteps, n=256):
     """Traveltime misfit at 128 receivers for `nsrc` of the 16 sources on the
     VTI medium: forward (kinematic march keeping the states the backward
     sweep needs + pick) and backward (pick adjoint, recomputation, adjoint steps, medium
-    gradient) timed separately, next to the plain full-plane forward march."""
+    gradient) timed separately on each source's second call, next to the plain
+    full-plane forward march; the first call's forward, which allocates the
+    state archive, is reported apart."""
     from dataclasses import replace
 
     import numpy as np
@@ -169,25 +171,34 @@ def adjoint_vs_forward(nsrc, nsteps, n=256):
     g0 = probs[0].grid
     need = nsteps * g0.nx * g0.nz * g0.nth * (4 + 8)
     K = 0 if need <= 0.5 * torch.cuda.mem_get_info(dev)[0] else 16
-    t_fwd = t_bwd = t_plain = 0.0
+    t_fwd = t_bwd = t_plain = t_first = 0.0
     for p in probs[:nsrc]:
         spec = {"grid": p.grid, "source": p.source, "receivers": p.receivers, "nsteps": nsteps, "vs_ratio": 0.5,
                 "dtype": "f32", "checkpoint_every": K, "dt": dt}
         with torch.no_grad():
             t_obs = egb.traveltime(*mk(true), spec)
         ts = mk(p.medium, True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        t = egb.traveltime(*ts, spec)
-        ok = ~(torch.isnan(t) | torch.isnan(t_obs))
-        J = torch.sum((t[ok] - t_obs[ok]) ** 2)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        J.backward()
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        t_fwd += t1 - t0
-        t_bwd += t2 - t1
+        # two calls: the first allocates the state archive (and pays for the
+        # device's first touch of memory that earlier legs released); torch's
+        # caching allocator keeps it for the second, which is the one timed,
+        # as in an inversion loop over sources and iterations
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t = egb.traveltime(*ts, spec)
+            ok = ~(torch.isnan(t) | torch.isnan(t_obs))
+            J = torch.sum((t[ok] - t_obs[ok]) ** 2)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            J.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if rep == 0:
+                t_first += t1 - t0
+            else:
+                t_fwd += t1 - t0
+                t_bwd += t2 - t1
+            del t, J
         s = egb.Solver(p, dev)
         s.velocity()
         s.init()
@@ -196,13 +207,13 @@ def adjoint_vs_forward(nsrc, nsteps, n=256):
         s.step(nsteps, dt=dt)
         torch.cuda.synchronize()
         t_plain += time.perf_counter() - t3
-        del s, ts, t, J
+        del s, ts
         torch.cuda.empty_cache()
     cu = probs[0].grid.ncell * nsteps * nsrc
     return {"sources": nsrc, "rk3_steps": nsteps, "receivers": 128,
             "states_kept": "every step's phi1 and psi resident" if K == 0 else f"a checkpoint every {K} steps",
             "archive_GB": need / 1e9 if K == 0 else 0.0,
-            "forward_s": t_fwd, "backward_s": t_bwd, "plain_forward_s": t_plain,
+            "forward_s": t_fwd, "backward_s": t_bwd, "plain_forward_s": t_plain, "first_call_forward_s": t_first,
             "backward_cell_updates_per_s": cu / t_bwd, "backward_over_plain_forward": t_bwd / t_plain}
 
 
@@ -686,7 +697,7 @@ def main():
         res["batched_small"] = batched_vs_sequential(256, 4 * args.batched_steps, lo=32, hi=96,
                                                      tune=not args.no_tune)
         torch.cuda.empty_cache()
-    if args.adjoint_sources > 0 and budget_ok("adjoint", 8 + 8 * args.adjoint_sources):
+    if args.adjoint_sources > 0 and budget_ok("adjoint", 8 + 16 * args.adjoint_sources):
         res["adjoint"] = adjoint_vs_forward(args.adjoint_sources, 600, 256)
         torch.cuda.empty_cache()
     if args.vti_leg > 0 and args.workload != "vti256" and budget_ok("vti256", 6 + 2 * args.vti_leg):
