@@ -605,7 +605,7 @@ def stage_roofline(p, r, rec):
             "kernel": "k_stage (one SSP-RK3 stage)", "avg_launch_ms": stage_ms, "blocks_per_launch": r["blocks"],
             "tile_theta_rows": r["tile_rows"],
             "flop_per_cell_stage": FLOP_CELL_STAGE,
-            # FP32 arithmetic without packed (dual-lane) instructions, which this build keeps off
+            # FP32 arithmetic without packed (dual-lane) instructions, which the library is compiled without
             "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS, "frac_of_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS,
             # HBM side: counter bytes over the live launch time
             "hbm_GBps": hbm, "hbm_frac_of_8TBps": None if hbm is None else hbm / PEAK_HBM_GBPS,

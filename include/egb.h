@@ -40,7 +40,7 @@ typedef enum {
     EGB_EWORKSPACE = -3,    /* workspace too small, or a beam list overflowed it */
     EGB_EHIP = -4,          /* a HIP launch or runtime call failed */
     EGB_ENONFINITE = -5,    /* a non-finite value was produced */
-    EGB_EUNSUPPORTED = -6   /* valid request this build does not implement */
+    EGB_EUNSUPPORTED = -6   /* valid request the library does not implement */
 } egb_status;
 
 /* Arithmetic type of the phase-space planes.  EGB_F32: six planes in float,

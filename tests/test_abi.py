@@ -148,7 +148,7 @@ def test_time_step_above_the_cfl_limit_is_refused_before_any_launch():
 
 def test_grids_beyond_32_bit_offsets_are_refused_before_any_launch():
     """The stage kernels address every array with 32-bit byte offsets: a
-    1024^3 FP32 grid (a 30 GB state) is a valid request this build does not
+    1024^3 FP32 grid (a 30 GB state) is a valid request the library does not
     implement.  Host-side validation only (fake aligned device pointers)."""
     import paper_2006_11945_amd as egb
     import workloads as W
