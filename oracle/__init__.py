@@ -62,6 +62,7 @@ def lib():
         L.oc_upwind5.argtypes = [P, i]; L.oc_upwind5.restype = d
         L.oc_march.argtypes = [i, i, i, d, d, d, d, P, d, d, d, P, P, d, i]
         L.oc_beam_sum.argtypes = [i, i, i, d, d, d, d, P, P, d, i, P, P, i, P]
+        L.oc_beam_sum_at.argtypes = [i, i, i, d, d, d, d, P, P, d, i, P, P, i, ctypes.POINTER(i), i, P]
         L.oc_pbeam_sum.argtypes = [i, i, i, d, d, d, d, d, P, P, d, i, i, i, P, i, P]
         L.oc_paper23_drt.argtypes = [P, d, d, P]
         L.oc_qp_polarization.argtypes = [P, d, P]
@@ -163,6 +164,22 @@ def beam_sum(grid, vel, vaux, source, U, omegas, lin: int = 0) -> np.ndarray:
     out = np.zeros((len(om), grid.nx, grid.nz, 2))
     rc = lib().oc_beam_sum(grid.nx, grid.nz, grid.nth, grid.x0, grid.z0, grid.dx, grid.dz, _p(_c(vel)),
                            _p(_c(vaux)), source.beta, int(lin), _p(_c(U)), _p(om), len(om), _p(out))
+    if rc == -3:
+        raise RuntimeError("oracle beam list overflow")
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def beam_sum_at(grid, vel, vaux, source, U, omegas, points, lin: int = 0) -> np.ndarray:
+    """The same Green's function at the output cells points[j] = (ix, iz)
+    only: complex [nw][npts] (the beams are those of the whole state)."""
+    om = _c(np.atleast_1d(omegas))
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.int32).reshape(-1, 2))
+    out = np.zeros((len(om), len(pts), 2))
+    rc = lib().oc_beam_sum_at(grid.nx, grid.nz, grid.nth, grid.x0, grid.z0, grid.dx, grid.dz, _p(_c(vel)),
+                              _p(_c(vaux)), source.beta, int(lin), _p(_c(U)), _p(om), len(om),
+                              pts.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(pts), _p(out))
+    if rc == -1:
+        raise ValueError("output cell outside the grid")
     if rc == -3:
         raise RuntimeError("oracle beam list overflow")
     return out[..., 0] + 1j * out[..., 1]

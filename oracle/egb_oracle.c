@@ -601,19 +601,25 @@ double oc_lin28(double s, double c, double u, double v)
 
 static double delta_h(double d, double h) { return fabs(d) < h ? (1.0 + cos(M_PI * d / h)) / (2.0 * h) : 0.0; }
 
-int oc_beam_sum(int nx, int nz, int nth, double x0, double z0, double dx, double dz, const double *vel,
-                const double *vaux, double beta, int lin, const double *U, const double *omegas, int nw, double *out)
+/* The beams of the state, as per-row and per-column lists of records. */
+typedef struct { beamrec *rows, *cols; int *nrow, *ncol; int cap; } beamlists;
+
+static void free_beams(beamlists *bl) { free(bl->rows); free(bl->cols); free(bl->nrow); free(bl->ncol); }
+
+/* 0, -2 (no memory) or -3 (a line holds more beams than the list's room) */
+static int beam_lists(int nx, int nz, int nth, double x0, double z0, double dx, double dz, const double *vel,
+                      const double *vaux, double beta, int lin, const double *U, beamlists *bl)
 {
     long n = (long)nth * nx * nz, nxz = (long)nx * nz;
     double dth = 2.0 * M_PI / nth, lx = dx / dth, lz = dz / dth, hx = 2.0 * dx, hz = 2.0 * dz;
     const double *phi = U + S_PHI * n;
-    /* per-row and per-column lists of beam records */
     int cap = 8 * (nx + nz + nth) + 64;
     beamrec *rows = (beamrec *)malloc(sizeof(beamrec) * (long)nz * cap);
     beamrec *cols = (beamrec *)malloc(sizeof(beamrec) * (long)nx * cap);
     int *nrow = (int *)calloc(nz, sizeof(int)), *ncol = (int *)calloc(nx, sizeof(int));
     int overflow = 0;
-    if (!rows || !cols || !nrow || !ncol) { free(rows); free(cols); free(nrow); free(ncol); return -2; }
+    bl->rows = rows; bl->cols = cols; bl->nrow = nrow; bl->ncol = ncol; bl->cap = cap;
+    if (!rows || !cols || !nrow || !ncol) { free_beams(bl); return -2; }
     for (int k = 0; k < nth; ++k) {
         double th = k * dth, sn = sin(th), cs = cos(th);
         for (int ix = 0; ix < nx; ++ix)
@@ -689,36 +695,72 @@ int oc_beam_sum(int nx, int nz, int nth, double x0, double z0, double dx, double
                 }
             }
     }
-    const double complex W = I / (4.0 * M_PI);
+    return overflow ? -3 : 0;
+}
+
+/* G at the output cell (ix, iz) and frequency om: the beams of row iz, then
+ * those of column ix, times W = i / (4 pi).                               */
+static double complex beam_point(const beamlists *bl, int ix, int iz, double x0, double z0, double dx, double dz,
+                                 double om)
+{
+    double xo = x0 + (ix + 0.5) * dx, zo = z0 + (iz + 0.5) * dz;
+    double complex G = 0.0;
+    for (int r = 0; r < bl->nrow[iz]; ++r) {
+        const beamrec *b = &bl->rows[(long)iz * bl->cap + r];
+        double d = xo - b->pos;
+        double complex T = b->psi + b->p * d + 0.5 * b->M * d * d;
+        if (0.5 * om * cimag(b->M) * d * d > 16.0) continue;
+        G += b->amp * cexp(I * om * T);
+    }
+    for (int r = 0; r < bl->ncol[ix]; ++r) {
+        const beamrec *b = &bl->cols[(long)ix * bl->cap + r];
+        double d = zo - b->pos;
+        double complex T = b->psi + b->p * d + 0.5 * b->M * d * d;
+        if (0.5 * om * cimag(b->M) * d * d > 16.0) continue;
+        G += b->amp * cexp(I * om * T);
+    }
+    return G * (I / (4.0 * M_PI));
+}
+
+int oc_beam_sum(int nx, int nz, int nth, double x0, double z0, double dx, double dz, const double *vel,
+                const double *vaux, double beta, int lin, const double *U, const double *omegas, int nw, double *out)
+{
+    beamlists bl;
+    int rc = beam_lists(nx, nz, nth, x0, z0, dx, dz, vel, vaux, beta, lin, U, &bl);
+    if (rc == -2) return rc;
 #pragma omp parallel for collapse(2) schedule(static)
     for (int w = 0; w < nw; ++w)
-        for (int ix = 0; ix < nx; ++ix) {
-            double om = omegas[w];
+        for (int ix = 0; ix < nx; ++ix)
             for (int iz = 0; iz < nz; ++iz) {
-                double xo = x0 + (ix + 0.5) * dx, zo = z0 + (iz + 0.5) * dz;
-                double complex G = 0.0;
-                for (int r = 0; r < nrow[iz]; ++r) {
-                    const beamrec *b = &rows[(long)iz * cap + r];
-                    double d = xo - b->pos;
-                    double complex T = b->psi + b->p * d + 0.5 * b->M * d * d;
-                    if (0.5 * om * cimag(b->M) * d * d > 16.0) continue;
-                    G += b->amp * cexp(I * om * T);
-                }
-                for (int r = 0; r < ncol[ix]; ++r) {
-                    const beamrec *b = &cols[(long)ix * cap + r];
-                    double d = zo - b->pos;
-                    double complex T = b->psi + b->p * d + 0.5 * b->M * d * d;
-                    if (0.5 * om * cimag(b->M) * d * d > 16.0) continue;
-                    G += b->amp * cexp(I * om * T);
-                }
-                G *= W;
+                double complex G = beam_point(&bl, ix, iz, x0, z0, dx, dz, omegas[w]);
                 long o = (((long)w * nx + ix) * nz + iz) * 2;
                 out[o] = creal(G);
                 out[o + 1] = cimag(G);
             }
+    free_beams(&bl);
+    return rc;
+}
+
+/* The same sum at npts output cells pts[j] = (ix, iz) only; out[w][j][re/im]. */
+int oc_beam_sum_at(int nx, int nz, int nth, double x0, double z0, double dx, double dz, const double *vel,
+                   const double *vaux, double beta, int lin, const double *U, const double *omegas, int nw,
+                   const int *pts, int npts, double *out)
+{
+    for (int j = 0; j < npts; ++j)
+        if (pts[2 * j] < 0 || pts[2 * j] >= nx || pts[2 * j + 1] < 0 || pts[2 * j + 1] >= nz) return -1;
+    beamlists bl;
+    int rc = beam_lists(nx, nz, nth, x0, z0, dx, dz, vel, vaux, beta, lin, U, &bl);
+    if (rc == -2) return rc;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int w = 0; w < nw; ++w)
+        for (int j = 0; j < npts; ++j) {
+            double complex G = beam_point(&bl, pts[2 * j], pts[2 * j + 1], x0, z0, dx, dz, omegas[w]);
+            long o = ((long)w * npts + j) * 2;
+            out[o] = creal(G);
+            out[o + 1] = cimag(G);
         }
-    free(rows); free(cols); free(nrow); free(ncol);
-    return overflow ? -3 : 0;
+    free_beams(&bl);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */

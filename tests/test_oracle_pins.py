@@ -509,3 +509,21 @@ def test_phase_plane_follows_arg_c_in_a_homogeneous_medium():
     d = np.abs(U[6] - np.angle(U[2] + 1j * U[3]))
     assert d.max() < 1e-4
     assert np.abs(U[6]).max() > 0.3  # the phase does vary (beta A12 psi up to ~0.35)
+
+
+def test_beam_sum_at_sampled_cells_is_the_whole_grid_sum_there():
+    """The oracle's sampled-output entry (used at sizes where the whole sum is
+    out of reach) evaluates the same records and the same per-cell sum: its
+    values equal the whole-grid sum's at those cells, bit for bit, on a
+    heterogeneous TTI state after a few steps; cells outside the grid are
+    refused."""
+    p = W.tti_512(n=40, nsteps=3, nw=5)
+    r = oracle.solve(p)
+    G = oracle.beam_sum(p.grid, r["vel"], r["vaux"], p.source, r["U"], p.omegas)
+    pts = [(0, 0), (39, 39), (20, 20), (3, 31), (31, 3), (20, 0)]
+    Ga = oracle.beam_sum_at(p.grid, r["vel"], r["vaux"], p.source, r["U"], p.omegas, pts)
+    assert np.abs(G).max() > 0
+    for j, (ix, iz) in enumerate(pts):
+        assert np.array_equal(Ga[:, j], G[:, ix, iz])
+    with pytest.raises(ValueError):
+        oracle.beam_sum_at(p.grid, r["vel"], r["vaux"], p.source, r["U"], p.omegas, [(40, 0)])
