@@ -312,6 +312,47 @@ def test_vti_256_full_size_one_step():
         assert e <= 1e-5, name
 
 
+def test_tti_512_full_size_beam_sum_sampled():
+    """The beam sum at the 512^3 TTI workload's full size and in the
+    benchmark's configuration (all 512 theta nodes, 64 equally spaced
+    frequencies 5-60 Hz, so the line sums take the frequency recurrence):
+    the GPU's own point-source data (FP32 planes, FP64 psi) summed on the
+    GPU, against the oracle's FP64 data and beam sum evaluated one output
+    cell at a time on 288 sampled cells (random cells, the grid's corners and
+    the row and column through the source).  Relative L2 over the sampled
+    cells <= 1e-4 per frequency (FP32 wavefield tolerance); every GPU output
+    finite."""
+    p = W.tti_512()
+    g = p.grid
+    log(f"TTI 512^3 beam sum, {len(p.omegas)} frequencies, oracle on sampled output cells")
+    s = egb().Solver(p, DEV, "f32")
+    s.velocity()
+    s.init()
+    Gd = s.beam(p.omegas)
+    assert bool(torch.isfinite(Gd).all())
+    rng = np.random.default_rng(5120)
+    isx, isz = int(p.source.xs / g.dx - g.x0 / g.dx), int(p.source.zs / g.dz - g.z0 / g.dz)
+    pts = [(int(a), int(b)) for a, b in zip(rng.integers(0, g.nx, 224), rng.integers(0, g.nz, 224))]
+    pts += [(0, 0), (0, g.nz - 1), (g.nx - 1, 0), (g.nx - 1, g.nz - 1)]
+    pts += [(isx, int(z)) for z in np.linspace(0, g.nz - 1, 30).astype(int)]
+    pts += [(int(x), isz) for x in np.linspace(0, g.nx - 1, 30).astype(int)]
+    idx = torch.as_tensor(np.asarray(pts), device=DEV)
+    Gs = Gd[:, idx[:, 0], idx[:, 1]].double().cpu().numpy()
+    G = Gs[..., 0] + 1j * Gs[..., 1]
+    del Gd, s
+    torch.cuda.empty_cache()
+    tab = oracle.medium_table(g, p.medium)
+    vel, vaux, _ = oracle.velocity(g, tab)
+    U0 = oracle.init_state(g, tab, p.source)
+    O = oracle.beam_sum_at(g, vel, vaux, p.source, U0, p.omegas, pts)
+    del vel, vaux, U0
+    err = np.linalg.norm(G - O, axis=1) / np.linalg.norm(O, axis=1)
+    log(f"  {len(pts)} cells: rel L2 per frequency max {err.max():.2e} (median {np.median(err):.2e}), "
+        f"|G| max {np.abs(O).max():.3e}")
+    assert np.all(np.abs(O).max(axis=1) > 0)
+    assert err.max() <= 1e-4
+
+
 def test_tti_512_full_size_window():
     """The 512^3 TTI workload (smooth random tilt) in the benchmark's launch
     configuration: one SSP-RK3 step of the whole grid on the GPU, compared
