@@ -225,3 +225,46 @@ def test_tuned_launch_shape_is_reported():
         assert blocks == b and tk in egb.egb_tile_rows(s.eg, 0)
     finally:
         egb.egb_set_launch(s.eg, 0, 0, 0)
+
+
+def test_tti_512_full_size_march_independent_of_launch_shape():
+    """At the 512^3 TTI workload's full size: the launch shape the autotuner
+    picks (as the benchmark does), and other tile shapes and block counts,
+    give bit-identical states after 3 RK3 steps (all seven planes), with
+    every value finite."""
+    import paper_2006_11945_amd as egb
+    import workloads as W
+    p = W.tti_512(nsteps=3)
+    eg = egb.make_grid(p.grid, "f32")
+    rows = egb.egb_tile_rows(eg, 0)
+
+    def march(shape):
+        s = egb.Solver(p, DEV, "f32")
+        s.velocity()
+        s.init()
+        try:
+            if shape == "tuned":
+                s.tune(op=0, reps=1)
+            else:
+                egb.egb_set_launch(s.eg, 0, *shape)
+            used = egb.egb_get_launch(s.eg, 0)
+            s.step(p.nsteps)
+        finally:
+            egb.egb_set_launch(s.eg, 0, 0, 0)
+        torch.cuda.synchronize()
+        out = {k: v.clone() for k, v in s.planes().items()}
+        del s
+        torch.cuda.empty_cache()
+        return used, out
+
+    used, ref = march("tuned")
+    log(f"TTI 512^3: tuned launch {used[0]} theta rows per tile, {used[1]} blocks")
+    for k, v in ref.items():
+        assert bool(torch.isfinite(v).all()), k
+    shapes = [(r, b) for r, b in ((rows[0], 97), (rows[-1], 4096)) if (r, b) != tuple(used)]
+    for shape in shapes:
+        got_used, got = march(shape)
+        log(f"  {got_used[0]} theta rows per tile, {got_used[1]} blocks")
+        for k in ref:
+            assert torch.equal(ref[k], got[k]), (shape, k)
+        del got
