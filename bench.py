@@ -246,12 +246,19 @@ def migration_leg(P, p, npoints):
     G = P.greens(xs_list, p.omegas)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    d = egb.egb_born_data(P.eg, G, p.omegas, md)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    # the two contractions once untimed (buffers, first launches), then timed
+    work = egb.alloc_bytes(max(egb.egb_born_workspace_size(P.eg, npoints, len(p.omegas)), 256), "cuda:0")
+    d = egb.egb_born_data(P.eg, G, p.omegas, md, work=work)
     img = egb.egb_migrate(P.eg, G, p.omegas, d)
     torch.cuda.synchronize()
+    t1b = time.perf_counter()
+    egb.egb_born_data(P.eg, G, p.omegas, md, d=d, work=work)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    egb.egb_migrate(P.eg, G, p.omegas, d, image=img)
+    torch.cuda.synchronize()
     t3 = time.perf_counter()
+    tg, t1 = t1 - t0, t1b
     # complex multiply-adds of either contraction: ns^2 per image point and frequency
     flop = 8.0 * npoints ** 2 * g.nx * g.nz * len(p.omegas)
     im = np.abs(img.cpu().numpy())
@@ -265,7 +272,7 @@ def migration_leg(P, p, npoints):
                       "contrast": float(win.max() / max(bg, 1e-300))})
     kr = (3 * g.nz) // 4
     prof = im[g.nx // 4:(3 * g.nx) // 4].sum(axis=0)
-    return {"surface_points": npoints, "frequencies": len(p.omegas), "greens_s": t1 - t0,
+    return {"surface_points": npoints, "frequencies": len(p.omegas), "greens_s": tg,
             "born_ms": (t2 - t1) * 1e3, "migrate_ms": (t3 - t2) * 1e3,
             "born_fp64_TFLOPs": flop / (t2 - t1) / 1e12, "migrate_fp64_TFLOPs": flop / (t3 - t2) / 1e12,
             "scatterers": peaks, "reflector_depth_error_cells": int(np.argmax(prof) - kr),

@@ -432,13 +432,21 @@ egb_status egb_paraxial_pick(const egb_grid *g, const void *levels, double theta
  * G: device, complex [ns][nw][nx][nz] (re, im) in the grid dtype, i.e. the
  * outputs of egb_paraxial_beam_sum for the ns points one after another;
  * omegas: HOST float64 [nw] (the frequencies G was summed at, rad/s).
- * Accumulation is float64.  1 <= ns <= 64 (EGB_EUNSUPPORTED above).
- * Stream-ordered; nothing is allocated. */
+ * Accumulation is float64.  1 <= ns <= 64 and nw <= 65535
+ * (EGB_EUNSUPPORTED above).  Stream-ordered; nothing is allocated. */
+
+/* Bytes of the workspace egb_born_data needs for this grid, ns points and nw
+ * frequencies (the partial sums of its split over image points); 0 on bad
+ * arguments. */
+size_t egb_born_workspace_size(const egb_grid *g, int32_t ns, int32_t nw);
 
 /* In: m (device float64 [nx][nz]).  Out: d (device complex128 [nw][ns][ns],
- * (re, im)). */
+ * (re, im)).  work: device, 16-byte aligned, at least
+ * egb_born_workspace_size(g, ns, nw) bytes (EGB_EWORKSPACE otherwise),
+ * overwritten.  The partial sums are added in a fixed order: the same
+ * inputs give the same bits on every call. */
 egb_status egb_born_data(const egb_grid *g, const void *G, int32_t ns, const double *omegas, int32_t nw,
-                         const double *m, double *d, hipStream_t stream);
+                         const double *m, double *d, void *work, size_t work_bytes, hipStream_t stream);
 
 /* In: d (device complex128 [nw][ns][ns]).  Out: image (device float64
  * [nx][nz]). */

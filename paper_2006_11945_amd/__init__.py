@@ -113,7 +113,9 @@ def _load():
     for name in ("egb_medium_table", "egb_paraxial_velocity", "egb_paraxial_init", "egb_paraxial_march",
                  "egb_paraxial_pick", "egb_paraxial_beam_sum"):
         getattr(L, name).restype = ctypes.c_int
-    L.egb_born_data.argtypes = [G, vp, i32, dp, i32, vp, vp, vp]
+    L.egb_born_data.argtypes = [G, vp, i32, dp, i32, vp, vp, vp, sz, vp]
+    L.egb_born_workspace_size.argtypes = [G, i32, i32]
+    L.egb_born_workspace_size.restype = ctypes.c_size_t
     L.egb_migrate.argtypes = [G, vp, i32, dp, i32, vp, vp, vp]
     L.egb_born_data.restype = ctypes.c_int
     L.egb_migrate.restype = ctypes.c_int
@@ -353,15 +355,23 @@ def _host_omegas(omegas):
     return om, om.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def egb_born_data(eg, G, omegas, m, d=None, stream=None) -> torch.Tensor:
+def egb_born_workspace_size(eg, ns: int, nw: int) -> int:
+    return int(_lib.egb_born_workspace_size(ctypes.byref(eg), int(ns), int(nw)))
+
+
+def egb_born_data(eg, G, omegas, m, d=None, work=None, stream=None) -> torch.Tensor:
     """Born data d [nw][ns][ns][re, im] (float64) of the reflectivity m
-    (float64 [nx][nz]) from the Green's functions G [ns][nw][nx][nz][re, im]."""
+    (float64 [nx][nz]) from the Green's functions G [ns][nw][nx][nz][re, im];
+    `work` (bytes, egb_born_workspace_size) is allocated when not given."""
     om, omp = _host_omegas(omegas)
     ns = G.shape[0]
     if d is None:
         d = torch.empty((len(om), ns, ns, 2), dtype=torch.float64, device=G.device)
+    nb = egb_born_workspace_size(eg, ns, len(om))
+    if work is None:
+        work = alloc_bytes(max(nb, 256), G.device)
     _check("egb_born_data", _lib.egb_born_data(ctypes.byref(eg), _ptr(G), ns, omp, len(om), _ptr(m), _ptr(d),
-                                               _stream(stream)))
+                                               _ptr(work), work.numel() * work.element_size(), _stream(stream)))
     return d
 
 

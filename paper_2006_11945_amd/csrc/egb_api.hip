@@ -627,18 +627,24 @@ egb_status egb_liouville_step_batched(const egb_problem* probs, int32_t nprob, i
 // ------------------------------------------------------ Green's-function migration
 static egb_status migration_args(const egb_grid* g, const void* G, int32_t ns, const double* omegas, int32_t nw) {
     if (!grid_ok(g) || !G || !aligned16(G) || ns < 1 || !omegas || nw < 1) return EGB_EINVAL;
-    if (ns > migration_max_points()) return EGB_EUNSUPPORTED;
+    if (ns > migration_max_points() || nw > 65535) return EGB_EUNSUPPORTED;
     for (int w = 0; w < nw; ++w)
         if (!isfinite(omegas[w]) || !(omegas[w] > 0.0)) return EGB_EINVAL;
     return EGB_OK;
 }
 
+size_t egb_born_workspace_size(const egb_grid* g, int32_t ns, int32_t nw) {
+    if (!grid_ok(g) || ns < 1 || ns > migration_max_points() || nw < 1 || nw > 65535) return 0;
+    return born_workspace_bytes((long long)g->nx * g->nz, ns, nw);
+}
+
 egb_status egb_born_data(const egb_grid* g, const void* G, int32_t ns, const double* omegas, int32_t nw,
-                         const double* m, double* d, hipStream_t stream) {
+                         const double* m, double* d, void* work, size_t work_bytes, hipStream_t stream) {
     const egb_status st = migration_args(g, G, ns, omegas, nw);
     if (st != EGB_OK) return st;
-    if (!m || !d || !aligned16(m) || !aligned16(d)) return EGB_EINVAL;
-    return hip_status(launch_born_data(grid_args(*g), g->dtype, G, ns, omegas, nw, m, d, stream));
+    if (!m || !d || !aligned16(m) || !aligned16(d) || !work || !aligned16(work)) return EGB_EINVAL;
+    if (work_bytes < egb_born_workspace_size(g, ns, nw)) return EGB_EWORKSPACE;
+    return hip_status(launch_born_data(grid_args(*g), g->dtype, G, ns, omegas, nw, m, d, work, stream));
 }
 
 egb_status egb_migrate(const egb_grid* g, const void* G, int32_t ns, const double* omegas, int32_t nw,

@@ -200,8 +200,9 @@ hipError_t launch_pbeam_compact(const PBeamArgs& a, int dtype, hipStream_t s);
 
 // Green's-function migration (migration.hip)
 int migration_max_points();
+size_t born_workspace_bytes(long long npt, int ns, int nw);
 hipError_t launch_born_data(const GridArgs& g, int dtype, const void* G, int ns, const double* omegas, int nw,
-                            const double* m, double* d, hipStream_t s);
+                            const double* m, double* d, void* work, hipStream_t s);
 hipError_t launch_migrate(const GridArgs& g, int dtype, const void* G, int ns, const double* omegas, int nw,
                           const double* d, double* image, hipStream_t s);
 hipError_t launch_beam_sum(const BeamArgs& a, int dtype, const double* omegas, int nw, void* out, hipStream_t s);

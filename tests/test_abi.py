@@ -270,8 +270,15 @@ def test_migration_arguments_are_validated():
     L = egb.lib()
     om = (ctypes.c_double * 2)(100.0, 200.0)
     bad = (ctypes.c_double * 2)(100.0, -1.0)
-    assert L.egb_born_data(ctypes.byref(eg), P(256), 65, om, 2, P(256), P(256), None) == egb.EGB_EUNSUPPORTED
-    assert L.egb_born_data(ctypes.byref(eg), P(256), 0, om, 2, P(256), P(256), None) == egb.EGB_EINVAL
-    assert L.egb_born_data(ctypes.byref(eg), P(256), 4, bad, 2, P(256), P(256), None) == egb.EGB_EINVAL
+    big = 1 << 40
+    assert L.egb_born_data(ctypes.byref(eg), P(256), 65, om, 2, P(256), P(256), P(256), big, None) == egb.EGB_EUNSUPPORTED
+    assert L.egb_born_data(ctypes.byref(eg), P(256), 0, om, 2, P(256), P(256), P(256), big, None) == egb.EGB_EINVAL
+    assert L.egb_born_data(ctypes.byref(eg), P(256), 4, bad, 2, P(256), P(256), P(256), big, None) == egb.EGB_EINVAL
+    assert L.egb_born_data(ctypes.byref(eg), P(256), 4, om, 2, P(256), P(256), None, big, None) == egb.EGB_EINVAL
+    # the workspace: partial sums of the split over image points
+    nb = egb.egb_born_workspace_size(eg, 4, 2)
+    assert nb > 0 and nb % (4 * 4 * 2 * 2 * 8) == 0
+    assert egb.egb_born_workspace_size(eg, 65, 2) == 0 and egb.egb_born_workspace_size(eg, 4, 0) == 0
+    assert L.egb_born_data(ctypes.byref(eg), P(256), 4, om, 2, P(256), P(256), P(256), nb - 1, None) == egb.EGB_EWORKSPACE
     assert L.egb_migrate(ctypes.byref(eg), P(256), 4, om, 2, P(256), None, None) == egb.EGB_EINVAL
     assert L.egb_migrate(ctypes.byref(eg), P(260), 4, om, 2, P(256), P(256), None) == egb.EGB_EINVAL
