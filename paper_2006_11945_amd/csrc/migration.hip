@@ -6,16 +6,16 @@
 //   image      I[x] = Re sum_w omega_w^2 dA sum_{s,r} conj(G[s][w][x])
 //                     conj(G[r][w][x]) d[w][s][r],
 // the adjoint of the data for a real reflectivity m (dA = dx dz).  Both are
-// complex contractions over ns x ns x (nx nz) per frequency with FP64
-// accumulation on the vector units (FP64 matrix cores run no faster than the
-// vector units on this chip, and the operands arrive as the grid dtype).
-// The Born data is a long reduction over image points with a small output
-// (ns x ns per frequency): the points are split over blocks, each block
-// stages a chunk of the Green's functions in LDS and every lane keeps a 4 x 4
-// register tile of the output, and the partial sums (caller's workspace) are
-// added in a fixed order, so the result does not depend on timing.  The
-// image keeps, per image point, the ns sums over receivers in registers
-// while the data matrix is read from LDS by the whole wavefront at once.
+// complex contractions over ns x ns x (nx nz) per frequency, computed in FP64
+// on the matrix cores (v_mfma_f64_16x16x4f64; the Green's functions are
+// converted from the grid dtype as they are staged).  The Born data is a
+// long reduction over image points with a small output (ns x ns per
+// frequency): the points are split over blocks, each block stages chunks of
+// the Green's functions in LDS (the next chunk loaded into registers while
+// the current one is multiplied), and the partial sums (caller's workspace)
+// are added in a fixed order, so the result does not depend on timing.  The
+// image forms Y = d conj(g) for 64 image points per wavefront, then
+// Re conj(g)^T Y per point.
 #include <hip/hip_runtime.h>
 
 #include "egb_internal.h"
@@ -28,7 +28,7 @@ constexpr int MG_WCH = 32;    // frequencies per launch
 constexpr int BO = 32;        // Born: output tile of 32 sources x 32 receivers per block
 constexpr int BKC = 64;       // Born: image points per LDS chunk (16 per wavefront)
 constexpr int BORN_BLOCKS = 2048;  // Born: blocks aimed at per launch (points split to reach it)
-constexpr int MS = 32;        // image kernel: surface points held per image point
+constexpr int MS = 32;        // image kernel on the matrix cores: up to 32 surface points
 
 struct MigW {
     double w2[MG_WCH];  // omega^2 dA of this chunk's frequencies
@@ -40,94 +40,118 @@ __device__ __forceinline__ double2 gval(const R* G, long long off) {
     return make_double2((double)G[2 * off], (double)G[2 * off + 1]);
 }
 
-// Partial Born sums: block (split p, frequency w, output tile), 4
-// wavefronts.  The block's image points [p kc, (p + 1) kc) run through LDS in
-// chunks of BKC (the tile's source rows times m, and its receiver rows);
-// wavefront q takes points 16 q .. 16 q + 15 of each chunk and lane (ls, lr)
-// the outputs s = s0 + ls + 8 i, r = r0 + lr + 8 j (i, j < 4).  The four
-// wavefronts' sums are added in order through LDS and the tile is written
-// to part[p][w][s][r] (complex).
+// Partial Born sums on the matrix cores: block (split p, frequency w,
+// output tile), 4 wavefronts.  The block's image points [p kc, (p + 1) kc)
+// run through LDS in chunks of BKC (the tile's 32 source rows times m, and
+// its 32 receiver rows); wavefront q takes points 16 q .. 16 q + 15 of each
+// chunk, 4 at a time, as the K = 4 of v_mfma_f64_16x16x4f64 (A[i][k] in lane
+// i + 16 k, B[k][j] in lane j + 16 k, C[i][j] in lane j + 16 (i % 4), item
+// i / 4).  The complex tile is 2 x 2 blocks of 16 x 16, real and imaginary
+// parts apart: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br (four products per
+// block).  The four wavefronts' sums are added in order through LDS and the
+// tile is written to part[p][w][s][r] (complex).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 template <typename R>
-__global__ __launch_bounds__(256) void k_born_part(const R* G, const double* m, int ns, int nw, long long npt,
+__global__ __launch_bounds__(256, 2) void k_born_part(const R* G, const double* m, int ns, int nw, long long npt,
                                                    long long kc, double* part) {
-    constexpr int ROW = BKC + 1;  // padded LDS row (double2): the 8 rows a read touches hit distinct banks
+    constexpr int ROW = BKC + 1;  // padded LDS row (double2)
     __shared__ double2 sm[2 * BO * ROW];
     double2* As = sm;
     double2* Bs = sm + BO * ROW;
-    const int t = threadIdx.x, wave = t >> 6, lane = t & 63, ls = lane >> 3, lr = lane & 7;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
     const int p = blockIdx.x, w = blockIdx.y;
     const int nt = (ns + BO - 1) / BO;
     const int s0 = (int)(blockIdx.z / nt) * BO, r0 = (int)(blockIdx.z % nt) * BO;
     const long long xa = (long long)p * kc, xb = xa + kc < npt ? xa + kc : npt;
-    double are[4][4], aim[4][4];
+    v4d cre[2][2], cim[2][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) are[i][j] = aim[i][j] = 0.0;
-    for (long long x0 = xa; x0 < xb; x0 += BKC) {
-        // thread t stages point c = t % 64 of the rows t / 64 + 4 q
-        const int c = t & 63;
+        for (int b = 0; b < 2; ++b) {
+            cre[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+            cim[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+        }
+    // thread t stages point c = t % 64 of the rows t / 64 + 4 q; the values of
+    // the next chunk are loaded into registers while this one is multiplied.
+    // A diagonal tile (the same source and receiver rows) loads each row once.
+    const int c = t & 63;
+    const bool diag = s0 == r0;  // block-uniform
+    R ga[BO / 4][2], gb[BO / 4][2];
+    double mx = 0.0;
+    auto fetch = [&](long long x0) {
         const long long x = x0 + c;
         const bool xin = x < xb;
-        const double mx = xin ? m[x] : 0.0;
+        mx = xin ? m[x] : 0.0;
 #pragma unroll
         for (int q = 0; q < BO / 4; ++q) {
             const int row = (t >> 6) + 4 * q;
             const int sr = s0 + row, rr = r0 + row;
-            double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+            ga[q][0] = ga[q][1] = gb[q][0] = gb[q][1] = (R)0;
             if (xin && sr < ns) {
-                a = gval(G, ((long long)sr * nw + w) * npt + x);
-                a.x *= mx;
-                a.y *= mx;
+                const long long o = ((long long)sr * nw + w) * npt + x;
+                ga[q][0] = G[2 * o];
+                ga[q][1] = G[2 * o + 1];
             }
-            if (xin && rr < ns) b = gval(G, ((long long)rr * nw + w) * npt + x);
-            As[row * ROW + c] = a;
-            Bs[row * ROW + c] = b;
+            if (!diag && xin && rr < ns) {
+                const long long o = ((long long)rr * nw + w) * npt + x;
+                gb[q][0] = G[2 * o];
+                gb[q][1] = G[2 * o + 1];
+            }
+        }
+    };
+    if (xa < xb) fetch(xa);
+    for (long long x0 = xa; x0 < xb; x0 += BKC) {
+#pragma unroll
+        for (int q = 0; q < BO / 4; ++q) {
+            const int row = (t >> 6) + 4 * q;
+            const double2 g = make_double2((double)ga[q][0], (double)ga[q][1]);
+            As[row * ROW + c] = make_double2(g.x * mx, g.y * mx);
+            Bs[row * ROW + c] = diag ? g : make_double2((double)gb[q][0], (double)gb[q][1]);
         }
         __syncthreads();
-        const int k0 = wave * (BKC / 4);
-#pragma unroll 2
-        for (int k = k0; k < k0 + BKC / 4; ++k) {
-            double2 a[4], b[4];
+        if (x0 + BKC < xb) fetch(x0 + BKC);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                a[i] = As[(ls + 8 * i) * ROW + k];
-                b[i] = Bs[(lr + 8 * i) * ROW + k];
-            }
+        for (int q = 0; q < BKC / 16; ++q) {
+            const int k = wave * (BKC / 4) + 4 * q + lk;
+            const double2 a[2] = {As[li * ROW + k], As[(16 + li) * ROW + k]};
+            const double2 b[2] = {Bs[li * ROW + k], Bs[(16 + li) * ROW + k]};
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int ts = 0; ts < 2; ++ts)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    are[i][j] = fma(a[i].x, b[j].x, fma(-a[i].y, b[j].y, are[i][j]));
-                    aim[i][j] = fma(a[i].x, b[j].y, fma(a[i].y, b[j].x, aim[i][j]));
+                for (int tr = 0; tr < 2; ++tr) {
+                    cre[ts][tr] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ts].x, b[tr].x, cre[ts][tr], 0, 0, 0);
+                    cre[ts][tr] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[ts].y, b[tr].y, cre[ts][tr], 0, 0, 0);
+                    cim[ts][tr] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ts].x, b[tr].y, cim[ts][tr], 0, 0, 0);
+                    cim[ts][tr] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ts].y, b[tr].x, cim[ts][tr], 0, 0, 0);
                 }
         }
         __syncthreads();
     }
     // the wavefronts' sums through LDS (the staging buffer, free after the
-    // loop's last barrier), added in wavefront order
-    double2* red = sm;  // [wave][entry i * 4 + j][lane]
+    // loop's last barrier), added in wavefront order; entry e = ((ts 2 + tr)
+    // 2 + part) 4 + item
+    double* red = reinterpret_cast<double*>(sm);  // [wave][e][lane], 4 x 32 x 64
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int ts = 0; ts < 2; ++ts)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) red[(wave * 16 + i * 4 + j) * 64 + lane] = make_double2(are[i][j], aim[i][j]);
+        for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int e = ((ts * 2 + tr) * 2) * 4 + v;
+                red[(wave * 32 + e) * 64 + lane] = cre[ts][tr][v];
+                red[(wave * 32 + e + 4) * 64 + lane] = cim[ts][tr][v];
+            }
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int idx = t + 256 * e, entry = idx >> 6, ln = idx & 63;
-        const int s = s0 + (ln >> 3) + 8 * (entry >> 2), r = r0 + (ln & 7) + 8 * (entry & 3);
-        double2 v = red[entry * 64 + ln];
+    for (int e2 = 0; e2 < 8; ++e2) {
+        const int idx = t + 256 * e2, e = idx >> 6, ln = idx & 63;
+        const int v = e & 3, part_im = (e >> 2) & 1, tr = (e >> 3) & 1, ts = e >> 4;
+        const int s = s0 + ts * 16 + (ln >> 4) + 4 * v, r = r0 + tr * 16 + (ln & 15);
+        double sum = red[e * 64 + ln];
 #pragma unroll
-        for (int q = 1; q < 4; ++q) {
-            const double2 u = red[(q * 16 + entry) * 64 + ln];
-            v.x += u.x;
-            v.y += u.y;
-        }
-        if (s < ns && r < ns) {
-            const long long o = ((((long long)p * nw + w) * ns + s) * ns + r) * 2;
-            part[o] = v.x;
-            part[o + 1] = v.y;
-        }
+        for (int q = 1; q < 4; ++q) sum += red[(q * 32 + e) * 64 + ln];
+        if (s < ns && r < ns) part[((((long long)p * nw + w) * ns + s) * ns + r) * 2 + part_im] = sum;
     }
 }
 
@@ -202,24 +226,28 @@ __global__ __launch_bounds__(256) void k_migrate(const R* G, const double* d, in
     }
 }
 
-// I[x] for 64 image points per block and ns <= MS surface points: wavefront
-// q takes the chunk's frequencies q, q + 4, ...; per frequency it stages the
-// data matrix (zero-padded to MS x MS) in its own LDS region, lane x forms
-// y_s = sum_r d[s][r] conj(g_r) for all s at once (r outer, the MS sums in
-// registers, d[s][r] read by the whole wavefront from one address) and adds
-// Re sum_s conj(g_s) y_s; the four wavefronts' sums are added in order.
-// accumulate: add to the image (later frequency chunks), else overwrite it.
+// I[x] for 64 image points per block and ns <= MS surface points, on the
+// matrix cores: wavefront q takes the chunk's frequencies q, q + 4, ...; per
+// frequency it stages the data matrix (zero-padded to MS x MS) in its own LDS
+// region and forms Y = d conj(g) over its 64 points (s x x, K = r) with
+// v_mfma_f64_16x16x4f64: A = d[s][r] (2 tiles of 16 s), B = conj(g_r(x))
+// read from the Green's functions (4 tiles of 16 x), Re Y += dr gr + di gi,
+// Im Y += di gr - dr gi.  Lane (j, i) then holds Y for x = 16 tx + j and
+// s = 16 ts + i + 4 v and adds Re conj(g_s) Y; the four lanes of one x are
+// added by cross-lane exchange and the four wavefronts through LDS, both in
+// a fixed order.  accumulate: add to the image (later frequency chunks),
+// else overwrite it.
 template <typename R>
-__global__ __launch_bounds__(256) void k_migrate_regs(const R* G, const double* d, int ns, int nw, long long npt,
-                                                      MigW wc, int accumulate, double* img) {
-    __shared__ double2 Ds[4][MS * MS];
+__global__ __launch_bounds__(256, 2) void k_migrate_mfma(const R* G, const double* d, int ns, int nw, long long npt,
+                                                         MigW wc, int accumulate, double* img) {
+    constexpr int DR = MS + 1;  // padded LDS row (double2) of the data matrix
+    __shared__ double2 Ds[4][MS * DR];
     __shared__ double part[4][64];
-    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-    const long long x = (long long)blockIdx.x * 64 + lane;
-    const bool xin = x < npt;
-    const long long xc = xin ? x : npt - 1;  // lanes past the end read a valid point and write nothing
-    double acc = 0.0;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63, lj = lane & 15, lq = lane >> 4;
+    const long long xb0 = (long long)blockIdx.x * 64;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};  // per x tile: x = xb0 + 16 tx + lj
     const int nit = (wc.n + 3) / 4;
+    const int nks = (ns + 3) / 4;  // K steps of 4 receivers
     for (int it = 0; it < nit; ++it) {
         const int wl = wave + 4 * it;
         const bool has = wl < wc.n;  // wavefront-uniform
@@ -232,53 +260,87 @@ __global__ __launch_bounds__(256) void k_migrate_regs(const R* G, const double* 
                     const long long o = (((long long)w * ns + sr) * ns + rr) * 2;
                     v = make_double2(d[o], d[o + 1]);
                 }
-                Ds[wave][i] = v;
+                Ds[wave][sr * DR + rr] = v;
             }
         }
         __syncthreads();
         if (has) {
-            double yre[MS], yim[MS];
+            v4d yre[2][4], yim[2][4];
 #pragma unroll
-            for (int sr = 0; sr < MS; ++sr) yre[sr] = yim[sr] = 0.0;
-            // g_r two receivers ahead of its use (raw values, converted at use)
-            const long long gofs = (long long)w * npt + xc, gstep = (long long)nw * npt;
-            R p0x = G[2 * gofs], p0y = G[2 * gofs + 1];
-            R p1x = (R)0, p1y = (R)0;
-            if (ns > 1) {
-                p1x = G[2 * (gofs + gstep)];
-                p1y = G[2 * (gofs + gstep) + 1];
-            }
-            for (int rr = 0; rr < ns; ++rr) {
-                const double2 g = make_double2((double)p0x, (double)p0y);  // conj(g_r) = (g.x, -g.y)
-                p0x = p1x;
-                p0y = p1y;
-                if (rr + 2 < ns) {
-                    const long long o = gofs + (long long)(rr + 2) * gstep;
-                    p1x = G[2 * o];
-                    p1y = G[2 * o + 1];
-                }
+            for (int ts = 0; ts < 2; ++ts)
 #pragma unroll
-                for (int sr = 0; sr < MS; ++sr) {
-                    const double2 dv = Ds[wave][sr * MS + rr];
-                    yre[sr] = fma(dv.x, g.x, fma(dv.y, g.y, yre[sr]));
-                    yim[sr] = fma(dv.y, g.x, fma(-dv.x, g.y, yim[sr]));
+                for (int tx = 0; tx < 4; ++tx) {
+                    yre[ts][tx] = (v4d){0.0, 0.0, 0.0, 0.0};
+                    yim[ts][tx] = (v4d){0.0, 0.0, 0.0, 0.0};
                 }
-            }
-            double aw = 0.0;  // Re sum_s conj(g_s) y_s
+            // B operands one K step ahead (raw values, converted at use)
+            R bn[4][2];
+            auto fetch_b = [&](int ks) {
+                const int rr = 4 * ks + lq;
 #pragma unroll
-            for (int sr = 0; sr < MS; ++sr) {
-                if (sr < ns) {
-                    const double2 g = gval(G, ((long long)sr * nw + w) * npt + xc);
-                    aw = fma(g.x, yre[sr], fma(g.y, yim[sr], aw));
+                for (int tx = 0; tx < 4; ++tx) {
+                    const long long x = xb0 + 16 * tx + lj;
+                    bn[tx][0] = bn[tx][1] = (R)0;
+                    if (rr < ns && x < npt) {
+                        const long long o = ((long long)rr * nw + w) * npt + x;
+                        bn[tx][0] = G[2 * o];
+                        bn[tx][1] = G[2 * o + 1];
+                    }
                 }
+            };
+            fetch_b(0);
+            for (int ks = 0; ks < nks; ++ks) {
+                const int rr = 4 * ks + lq;
+                const double2 a[2] = {Ds[wave][lj * DR + rr], Ds[wave][(16 + lj) * DR + rr]};
+                double2 b[4];
+#pragma unroll
+                for (int tx = 0; tx < 4; ++tx) b[tx] = make_double2((double)bn[tx][0], (double)bn[tx][1]);
+                if (ks + 1 < nks) fetch_b(ks + 1);
+#pragma unroll
+                for (int ts = 0; ts < 2; ++ts)
+#pragma unroll
+                    for (int tx = 0; tx < 4; ++tx) {
+                        yre[ts][tx] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ts].x, b[tx].x, yre[ts][tx], 0, 0, 0);
+                        yre[ts][tx] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ts].y, b[tx].y, yre[ts][tx], 0, 0, 0);
+                        yim[ts][tx] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ts].y, b[tx].x, yim[ts][tx], 0, 0, 0);
+                        yim[ts][tx] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[ts].x, b[tx].y, yim[ts][tx], 0, 0, 0);
+                    }
             }
-            acc = fma(wc.w2[wl], aw, acc);
+            // Re sum_s conj(g_s) Y_s over this lane's sources, per x tile
+#pragma unroll
+            for (int tx = 0; tx < 4; ++tx) {
+                const long long x = xb0 + 16 * tx + lj;
+                double aw = 0.0;
+#pragma unroll
+                for (int ts = 0; ts < 2; ++ts)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int sr = 16 * ts + lq + 4 * v;
+                        if (sr < ns && x < npt) {
+                            const double2 g = gval(G, ((long long)sr * nw + w) * npt + x);
+                            aw = fma(g.x, yre[ts][tx][v], fma(g.y, yim[ts][tx][v], aw));
+                        }
+                    }
+                acc[tx] = fma(wc.w2[wl], aw, acc[tx]);
+            }
         }
         __syncthreads();
     }
-    part[wave][lane] = acc;
+    // the four lanes of each x (lq = 0..3), then the four wavefronts
+#pragma unroll
+    for (int tx = 0; tx < 4; ++tx) {
+        const double a1 = __shfl_xor(acc[tx], 16);
+        const double s01 = lq & 1 ? a1 + acc[tx] : acc[tx] + a1;  // (lane lq even) + (lq odd)
+        const double s23 = __shfl_xor(s01, 32);
+        acc[tx] = lq & 2 ? s23 + s01 : s01 + s23;
+    }
+    if (lq == 0) {
+#pragma unroll
+        for (int tx = 0; tx < 4; ++tx) part[wave][16 * tx + lj] = acc[tx];
+    }
     __syncthreads();
-    if (wave == 0 && xin) {
+    const long long x = xb0 + lane;
+    if (wave == 0 && x < npt) {
         const double sum = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
         img[x] = accumulate ? img[x] + sum : sum;
     }
@@ -344,13 +406,13 @@ hipError_t launch_migrate(const GridArgs& g, int dtype, const void* G, int ns, c
     for (int first = 0; first < nw; first += MG_WCH) {
         const MigW wc = chunk_of(omegas, first, nw, dA);
         const int acc = first > 0;
-        if (ns <= MS) {  // the sums over receivers in registers
+        if (ns <= MS) {  // on the matrix cores
             const unsigned blocks = (unsigned)((npt + 63) / 64);
             if (dtype == EGB_F64)
-                k_migrate_regs<double><<<blocks, 256, 0, s>>>(static_cast<const double*>(G), d, ns, nw, npt, wc, acc,
+                k_migrate_mfma<double><<<blocks, 256, 0, s>>>(static_cast<const double*>(G), d, ns, nw, npt, wc, acc,
                                                              image);
             else
-                k_migrate_regs<float><<<blocks, 256, 0, s>>>(static_cast<const float*>(G), d, ns, nw, npt, wc, acc,
+                k_migrate_mfma<float><<<blocks, 256, 0, s>>>(static_cast<const float*>(G), d, ns, nw, npt, wc, acc,
                                                             image);
         } else if (dtype == EGB_F64) {
             const unsigned blocks = (unsigned)((npt + 31) / 32);
