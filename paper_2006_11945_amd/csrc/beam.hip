@@ -201,6 +201,7 @@ __global__ __launch_bounds__(256) void k_beam_compact(BeamArgs a) {
 constexpr int WCHUNK = 16;
 struct Omegas {
     double w[WCHUNK];
+    float tcut[WCHUNK];  // 16 / w[k] rounded to float: the window test of the FP32 recurrence
     double step;  // w[k] = w[0] + k step for every k < n when uniform
     int n, first, uniform;
 };
@@ -208,7 +209,7 @@ struct Omegas {
 // Sum over one row (ROW) or column list for a chunk of frequencies.
 // block: 64 lanes = 64 consecutive output cells along the line; grid.x: chunks
 // along the line, grid.y: the line index.
-template <typename R, bool ROW>
+template <typename R, bool ROW, bool FULL>
 __global__ __launch_bounds__(64) void k_beam_line(BeamArgs a, Omegas om, R* out) {
     const GridArgs& g = a.g;
     const int line = blockIdx.y;
@@ -238,11 +239,44 @@ __global__ __launch_bounds__(64) void k_beam_line(BeamArgs a, Omegas om, R* out)
         er = mag * cph;
         ei = mag * sph;
     };
+    // the line's records in key order (the sum does not depend on the append
+    // order), 64 at a time through LDS: lane l gathers record r0 + l, then
+    // every lane reads each record from one LDS address
+    __shared__ BeamRec srec[64];
     for (int r = 0; r < cnt; ++r) {
-        const BeamRec b = recs[ord[r]];  // in key order: the sum does not depend on the append order
+        if (r % 64 == 0) {
+            __syncthreads();  // the previous chunk's reads are done
+            if (r + (int)threadIdx.x < cnt) srec[threadIdx.x] = recs[ord[r + threadIdx.x]];
+            __syncthreads();
+        }
+        const BeamRec b = srec[r % 64];
         const double d = pos - b.pos;
         const double Tre = b.psi + b.p * d + 0.5 * b.Mre * d * d;
         const double Tim = 0.5 * b.Mim * d * d;
+        if (sizeof(R) == 4 && om.uniform) {
+            // FP32, equally spaced frequencies: z_k = A exp(i w_k T) =
+            // z_0 exp(i step T)^k, one complex rotation and one add per
+            // frequency; a term enters while Im T <= 16 / w_k (float test:
+            // a term at the edge of the window is e^-16 of its beam)
+            R er, ei, dr, di;
+            expi(om.w[0], Tre, Tim, er, ei);
+            expi(om.step, Tre, Tim, dr, di);
+            R zr = (R)b.are * er - (R)b.aim * ei, zi = (R)b.are * ei + (R)b.aim * er;
+            const float tf = (float)Tim;
+#pragma unroll
+            for (int w = 0; w < WCHUNK; ++w) {
+                if (FULL || w < om.n) {  // FULL: a chunk of WCHUNK frequencies
+                    if (tf <= om.tcut[w]) {
+                        gre[w] += zr;
+                        gim[w] += zi;
+                    }
+                    const R nr = zr * dr - zi * di, ni = zr * di + zi * dr;
+                    zr = nr;
+                    zi = ni;
+                }
+            }
+            continue;
+        }
         if (om.uniform) {
             // equally spaced frequencies: exp(i w_k T) = exp(i w_0 T) exp(i step T)^k,
             // two exponentials per beam and output instead of one per frequency
@@ -544,6 +578,7 @@ hipError_t launch_beam_sum(const BeamArgs& a, int dtype, const double* omegas, i
         om.n = nw - w0 < WCHUNK ? nw - w0 : WCHUNK;
         om.first = w0;
         for (int w = 0; w < WCHUNK; ++w) om.w[w] = w < om.n ? omegas[w0 + w] : 0.0;
+        for (int w = 0; w < WCHUNK; ++w) om.tcut[w] = w < om.n ? (float)(16.0 / om.w[w]) : 0.0f;
         // equally spaced (to 1e-12 of the largest) chunks take the recurrence
         om.step = om.n > 1 ? (om.w[om.n - 1] - om.w[0]) / (om.n - 1) : 0.0;
         om.uniform = om.n > 1 && om.step > 0.0;
@@ -551,11 +586,14 @@ hipError_t launch_beam_sum(const BeamArgs& a, int dtype, const double* omegas, i
             if (fabs(om.w[w] - (om.w[0] + w * om.step)) > 1e-12 * fabs(om.w[om.n - 1])) om.uniform = 0;
         const dim3 grow((a.g.nx + 63) / 64, a.g.nz), gcol((a.g.nz + 63) / 64, a.g.nx);
         if (dtype == EGB_F64) {
-            k_beam_line<double, true><<<grow, 64, 0, s>>>(a, om, (double*)out);
-            k_beam_line<double, false><<<gcol, 64, 0, s>>>(a, om, (double*)out);
+            k_beam_line<double, true, false><<<grow, 64, 0, s>>>(a, om, (double*)out);
+            k_beam_line<double, false, false><<<gcol, 64, 0, s>>>(a, om, (double*)out);
+        } else if (om.n == WCHUNK) {
+            k_beam_line<float, true, true><<<grow, 64, 0, s>>>(a, om, (float*)out);
+            k_beam_line<float, false, true><<<gcol, 64, 0, s>>>(a, om, (float*)out);
         } else {
-            k_beam_line<float, true><<<grow, 64, 0, s>>>(a, om, (float*)out);
-            k_beam_line<float, false><<<gcol, 64, 0, s>>>(a, om, (float*)out);
+            k_beam_line<float, true, false><<<grow, 64, 0, s>>>(a, om, (float*)out);
+            k_beam_line<float, false, false><<<gcol, 64, 0, s>>>(a, om, (float*)out);
         }
     }
     return hipGetLastError();
