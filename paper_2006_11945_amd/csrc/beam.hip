@@ -198,7 +198,8 @@ __global__ __launch_bounds__(256) void k_beam_compact(BeamArgs a) {
     }
 }
 
-constexpr int WCHUNK = 16;
+constexpr int WCHUNK = 32;  // frequencies per launch of the FP32 recurrence (equally spaced, full chunk)
+constexpr int WGEN = 16;    // frequencies per launch otherwise
 struct Omegas {
     double w[WCHUNK];
     float tcut[WCHUNK];  // 16 / w[k] rounded to float: the window test of the FP32 recurrence
@@ -206,11 +207,14 @@ struct Omegas {
     int n, first, uniform;
 };
 
-// Sum over one row (ROW) or column list for a chunk of frequencies.
+// Sum over one row (ROW) or column list for a chunk of NCH frequencies.
 // block: 64 lanes = 64 consecutive output cells along the line; grid.x: chunks
-// along the line, grid.y: the line index.
-template <typename R, bool ROW, bool FULL>
+// along the line, grid.y: the line index.  FAST: FP32, NCH equally spaced
+// frequencies (the recurrence of the weighted term); otherwise up to NCH
+// frequencies, equally spaced or not.
+template <typename R, bool ROW, int NCH, bool FAST>
 __global__ __launch_bounds__(64) void k_beam_line(BeamArgs a, Omegas om, R* out) {
+    static_assert(!FAST || sizeof(R) == 4, "the fast recurrence is the FP32 one");
     const GridArgs& g = a.g;
     const int line = blockIdx.y;
     const int j = blockIdx.x * 64 + threadIdx.x;  // position along the line
@@ -220,9 +224,9 @@ __global__ __launch_bounds__(64) void k_beam_line(BeamArgs a, Omegas om, R* out)
     const int cnt = min(a.counts[ROW ? line : g.nz + line], a.cap);
     const BeamRec* recs = reinterpret_cast<const BeamRec*>(ROW ? a.rows : a.cols) + (long long)line * a.cap;
     const int* ord = a.order + ((ROW ? 0LL : (long long)g.nz) + line) * a.cap;
-    R gre[WCHUNK], gim[WCHUNK];
+    R gre[NCH], gim[NCH];
 #pragma unroll
-    for (int w = 0; w < WCHUNK; ++w) gre[w] = gim[w] = (R)0;
+    for (int w = 0; w < NCH; ++w) gre[w] = gim[w] = (R)0;
     const double two_pi = 6.283185307179586476925286766559, inv_two_pi = 1.0 / two_pi;
     // exp(i o T) = exp(-o Im T) (cos + i sin)(o Re T), the phase reduced mod 2 pi in double
     auto expi = [&](double o, double Tre, double Tim, R& er, R& ei) {
@@ -253,7 +257,7 @@ __global__ __launch_bounds__(64) void k_beam_line(BeamArgs a, Omegas om, R* out)
         const double d = pos - b.pos;
         const double Tre = b.psi + b.p * d + 0.5 * b.Mre * d * d;
         const double Tim = 0.5 * b.Mim * d * d;
-        if (sizeof(R) == 4 && om.uniform) {
+        if constexpr (FAST) {
             // FP32, equally spaced frequencies: z_k = A exp(i w_k T) =
             // z_0 exp(i step T)^k, one complex rotation and one add per
             // frequency; a term enters while Im T <= 16 / w_k (float test:
@@ -264,27 +268,24 @@ __global__ __launch_bounds__(64) void k_beam_line(BeamArgs a, Omegas om, R* out)
             R zr = (R)b.are * er - (R)b.aim * ei, zi = (R)b.are * ei + (R)b.aim * er;
             const float tf = (float)Tim;
 #pragma unroll
-            for (int w = 0; w < WCHUNK; ++w) {
-                if (FULL || w < om.n) {  // FULL: a chunk of WCHUNK frequencies
-                    if (tf <= om.tcut[w]) {
-                        gre[w] += zr;
-                        gim[w] += zi;
-                    }
-                    const R nr = zr * dr - zi * di, ni = zr * di + zi * dr;
-                    zr = nr;
-                    zi = ni;
+            for (int w = 0; w < NCH; ++w) {
+                if (tf <= om.tcut[w]) {
+                    gre[w] += zr;
+                    gim[w] += zi;
                 }
+                const R nr = zr * dr - zi * di, ni = zr * di + zi * dr;
+                zr = nr;
+                zi = ni;
             }
             continue;
-        }
-        if (om.uniform) {
+        } else if (om.uniform) {
             // equally spaced frequencies: exp(i w_k T) = exp(i w_0 T) exp(i step T)^k,
             // two exponentials per beam and output instead of one per frequency
             R er, ei, dr, di;
             expi(om.w[0], Tre, Tim, er, ei);
             expi(om.step, Tre, Tim, dr, di);
 #pragma unroll
-            for (int w = 0; w < WCHUNK; ++w) {
+            for (int w = 0; w < NCH; ++w) {
                 if (w < om.n) {
                     if (om.w[w] * Tim <= 16.0) {
                         gre[w] += (R)b.are * er - (R)b.aim * ei;
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(64) void k_beam_line(BeamArgs a, Omegas om, R* out)
             continue;
         }
 #pragma unroll
-        for (int w = 0; w < WCHUNK; ++w) {
+        for (int w = 0; w < NCH; ++w) {
             if (w < om.n) {
                 const double o = om.w[w];
                 const double decay = o * Tim;
@@ -328,14 +329,17 @@ __global__ __launch_bounds__(64) void k_beam_line(BeamArgs a, Omegas om, R* out)
     const int ix = ROW ? j : line, iz = ROW ? line : j;
     // W = i / (4 pi): (gre + i gim) * i / (4 pi) = (-gim + i gre) / (4 pi)
     const R s = (R)(1.0 / (4.0 * M_PI));
-    for (int w = 0; w < om.n; ++w) {
-        const long long o = (((long long)(om.first + w) * g.nx + ix) * g.nz + iz) * 2;
-        if (ROW) {
-            out[o] = -gim[w] * s;
-            out[o + 1] = gre[w] * s;
-        } else {
-            out[o] += -gim[w] * s;
-            out[o + 1] += gre[w] * s;
+#pragma unroll
+    for (int w = 0; w < NCH; ++w) {
+        if (w < om.n) {
+            const long long o = (((long long)(om.first + w) * g.nx + ix) * g.nz + iz) * 2;
+            if (ROW) {
+                out[o] = -gim[w] * s;
+                out[o + 1] = gre[w] * s;
+            } else {
+                out[o] += -gim[w] * s;
+                out[o + 1] += gre[w] * s;
+            }
         }
     }
 }
@@ -573,28 +577,39 @@ hipError_t launch_max_i32(const int* p, int n, int* out, hipStream_t s) {
 hipError_t launch_beam_sum(const BeamArgs& a, int dtype, const double* omegas, int nw, void* out, hipStream_t s) {
     k_beam_order<true><<<dim3(ORDER_BLOCKS, a.g.nz), 256, 0, s>>>(a);
     k_beam_order<false><<<dim3(ORDER_BLOCKS, a.g.nx), 256, 0, s>>>(a);
-    for (int w0 = 0; w0 < nw; w0 += WCHUNK) {
+    // a chunk of equally spaced frequencies (to 1e-12 of the largest)
+    auto chunk = [&](int w0, int n) {
         Omegas om;
-        om.n = nw - w0 < WCHUNK ? nw - w0 : WCHUNK;
+        om.n = n;
         om.first = w0;
         for (int w = 0; w < WCHUNK; ++w) om.w[w] = w < om.n ? omegas[w0 + w] : 0.0;
         for (int w = 0; w < WCHUNK; ++w) om.tcut[w] = w < om.n ? (float)(16.0 / om.w[w]) : 0.0f;
-        // equally spaced (to 1e-12 of the largest) chunks take the recurrence
         om.step = om.n > 1 ? (om.w[om.n - 1] - om.w[0]) / (om.n - 1) : 0.0;
         om.uniform = om.n > 1 && om.step > 0.0;
         for (int w = 0; w < om.n && om.uniform; ++w)
             if (fabs(om.w[w] - (om.w[0] + w * om.step)) > 1e-12 * fabs(om.w[om.n - 1])) om.uniform = 0;
-        const dim3 grow((a.g.nx + 63) / 64, a.g.nz), gcol((a.g.nz + 63) / 64, a.g.nx);
-        if (dtype == EGB_F64) {
-            k_beam_line<double, true, false><<<grow, 64, 0, s>>>(a, om, (double*)out);
-            k_beam_line<double, false, false><<<gcol, 64, 0, s>>>(a, om, (double*)out);
-        } else if (om.n == WCHUNK) {
-            k_beam_line<float, true, true><<<grow, 64, 0, s>>>(a, om, (float*)out);
-            k_beam_line<float, false, true><<<gcol, 64, 0, s>>>(a, om, (float*)out);
-        } else {
-            k_beam_line<float, true, false><<<grow, 64, 0, s>>>(a, om, (float*)out);
-            k_beam_line<float, false, false><<<gcol, 64, 0, s>>>(a, om, (float*)out);
+        return om;
+    };
+    const dim3 grow((a.g.nx + 63) / 64, a.g.nz), gcol((a.g.nz + 63) / 64, a.g.nx);
+    for (int w0 = 0; w0 < nw;) {
+        if (dtype == EGB_F32 && nw - w0 >= WCHUNK) {
+            const Omegas om = chunk(w0, WCHUNK);
+            if (om.uniform) {  // FP32 recurrence over a full chunk
+                k_beam_line<float, true, WCHUNK, true><<<grow, 64, 0, s>>>(a, om, (float*)out);
+                k_beam_line<float, false, WCHUNK, true><<<gcol, 64, 0, s>>>(a, om, (float*)out);
+                w0 += WCHUNK;
+                continue;
+            }
         }
+        const Omegas om = chunk(w0, nw - w0 < WGEN ? nw - w0 : WGEN);
+        if (dtype == EGB_F64) {
+            k_beam_line<double, true, WGEN, false><<<grow, 64, 0, s>>>(a, om, (double*)out);
+            k_beam_line<double, false, WGEN, false><<<gcol, 64, 0, s>>>(a, om, (double*)out);
+        } else {
+            k_beam_line<float, true, WGEN, false><<<grow, 64, 0, s>>>(a, om, (float*)out);
+            k_beam_line<float, false, WGEN, false><<<gcol, 64, 0, s>>>(a, om, (float*)out);
+        }
+        w0 += om.n;
     }
     return hipGetLastError();
 }
