@@ -430,9 +430,7 @@ __device__ __forceinline__ void qp_polarization(const double (&m)[NF], double th
 // the depth march starts a beam with C(0) = u1 = cos + sin u, the point-source
 // data with C(0) = s, both for the medium frozen at the source.
 template <typename R>
-__global__ __launch_bounds__(256) void k_pbeam_compact(PBeamArgs a) {
-    const int ix = blockIdx.x * 64 + threadIdx.x, k = blockIdx.y * 4 + threadIdx.y, n = blockIdx.z + 1;
-    if (ix >= a.nx || k >= a.nth || n >= a.nz) return;
+__device__ __forceinline__ void pbeam_cell(const PBeamArgs& a, int ix, int k, int n, bool record) {
     const long long P = a.P, c = (long long)k * a.nx + ix;
     const R* L = reinterpret_cast<const R*>(static_cast<const char*>(a.levels) + (size_t)n * a.level_bytes);
     const double tau = reinterpret_cast<const double*>(L + 7 * P)[c];
@@ -450,6 +448,10 @@ __global__ __launch_bounds__(256) void k_pbeam_compact(PBeamArgs a) {
     if (!(fabs(d) < h)) return;
     const double vt0 = (double)T[c];  // take-off angle; outside the aperture: edge data, not a ray
     if (!(fabs(vt0) < a.theta_max)) return;
+    if (!record) {  // the gate only: the cell is a beam candidate of the block
+        a.cand[atomicAdd(a.ncand, 1)] = k * a.nx + ix;
+        return;
+    }
     const double meas = delta_h(d, h) * fabs(Xx * Tt - Xt * Tx) / gX * a.dx * a.dth;
     // local phase-velocity jet and ray direction at (x, z_n, theta)
     MediumPoint M;
@@ -544,13 +546,38 @@ __global__ __launch_bounds__(256) void k_pbeam_compact(PBeamArgs a) {
     if (slot < a.cap) reinterpret_cast<BeamRec*>(a.rows)[(long long)n * a.cap + slot] = r;
 }
 
+// Block: 64 x 8 cells (x, theta) of level n.  Every thread evaluates the gate
+// of its cell and the block's candidates are gathered in LDS; then one thread
+// per candidate forms the record, so the long FP64 path runs on full
+// wavefronts instead of once in every wavefront that holds a candidate (a
+// few cells per theta row lie near Gamma).  The append order does not
+// matter: the line sums take the records in key order.
+template <typename R>
+__global__ __launch_bounds__(512) void k_pbeam_compact(PBeamArgs a) {
+    __shared__ int cand[512];
+    __shared__ int ncand;
+    const int tid = threadIdx.y * 64 + threadIdx.x;
+    const int ix = blockIdx.x * 64 + threadIdx.x, k = blockIdx.y * 8 + threadIdx.y, n = blockIdx.z + 1;
+    if (tid == 0) ncand = 0;
+    __syncthreads();
+    PBeamArgs g = a;
+    g.cand = cand;
+    g.ncand = &ncand;
+    if (ix < a.nx && k < a.nth && n < a.nz) pbeam_cell<R>(g, ix, k, n, false);
+    __syncthreads();
+    if (tid < ncand) {
+        const int c = cand[tid];
+        pbeam_cell<R>(a, c % a.nx, c / a.nx, n, true);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_pbeam_compact(const PBeamArgs& a, int dtype, hipStream_t s) {
     const int nl = a.g.nz + a.g.nx;
     k_fill_i32<<<(nl + 255) / 256, 256, 0, s>>>(a.counts, nl);
     if (a.nz < 2) return hipGetLastError();
-    const dim3 grid((a.nx + 63) / 64, (a.nth + 3) / 4, a.nz - 1), block(64, 4);
+    const dim3 grid((a.nx + 63) / 64, (a.nth + 7) / 8, a.nz - 1), block(64, 8);
     if (dtype == EGB_F64)
         k_pbeam_compact<double><<<grid, block, 0, s>>>(a);
     else

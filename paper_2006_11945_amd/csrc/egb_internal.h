@@ -195,6 +195,8 @@ struct PBeamArgs {
     double dx, dth, theta_max, xs;
     int* counts;              // [nz rows][nx columns] (columns stay 0)
     void* rows;
+    int* cand;                // inside the compaction kernel: its block's candidates (LDS)
+    int* ncand;
 };
 hipError_t launch_pbeam_compact(const PBeamArgs& a, int dtype, hipStream_t s);
 
