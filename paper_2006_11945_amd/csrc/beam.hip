@@ -603,7 +603,7 @@ hipError_t launch_max_i32(const int* p, int n, int* out, hipStream_t s) {
 
 hipError_t launch_beam_sum(const BeamArgs& a, int dtype, const double* omegas, int nw, void* out, hipStream_t s) {
     k_beam_order<true><<<dim3(ORDER_BLOCKS, a.g.nz), 256, 0, s>>>(a);
-    k_beam_order<false><<<dim3(ORDER_BLOCKS, a.g.nx), 256, 0, s>>>(a);
+    if (!a.rows_only) k_beam_order<false><<<dim3(ORDER_BLOCKS, a.g.nx), 256, 0, s>>>(a);
     // a chunk of equally spaced frequencies (to 1e-12 of the largest)
     auto chunk = [&](int w0, int n) {
         Omegas om;
@@ -623,7 +623,7 @@ hipError_t launch_beam_sum(const BeamArgs& a, int dtype, const double* omegas, i
             const Omegas om = chunk(w0, WCHUNK);
             if (om.uniform) {  // FP32 recurrence over a full chunk
                 k_beam_line<float, true, WCHUNK, true><<<grow, 64, 0, s>>>(a, om, (float*)out);
-                k_beam_line<float, false, WCHUNK, true><<<gcol, 64, 0, s>>>(a, om, (float*)out);
+                if (!a.rows_only) k_beam_line<float, false, WCHUNK, true><<<gcol, 64, 0, s>>>(a, om, (float*)out);
                 w0 += WCHUNK;
                 continue;
             }
@@ -631,10 +631,10 @@ hipError_t launch_beam_sum(const BeamArgs& a, int dtype, const double* omegas, i
         const Omegas om = chunk(w0, nw - w0 < WGEN ? nw - w0 : WGEN);
         if (dtype == EGB_F64) {
             k_beam_line<double, true, WGEN, false><<<grow, 64, 0, s>>>(a, om, (double*)out);
-            k_beam_line<double, false, WGEN, false><<<gcol, 64, 0, s>>>(a, om, (double*)out);
+            if (!a.rows_only) k_beam_line<double, false, WGEN, false><<<gcol, 64, 0, s>>>(a, om, (double*)out);
         } else {
             k_beam_line<float, true, WGEN, false><<<grow, 64, 0, s>>>(a, om, (float*)out);
-            k_beam_line<float, false, WGEN, false><<<gcol, 64, 0, s>>>(a, om, (float*)out);
+            if (!a.rows_only) k_beam_line<float, false, WGEN, false><<<gcol, 64, 0, s>>>(a, om, (float*)out);
         }
         w0 += om.n;
     }

@@ -507,6 +507,7 @@ egb_status egb_paraxial_beam_sum(const egb_grid* g, const void* coeff2d, const v
     ba.counts = pa.counts;
     ba.rows = pa.rows;
     ba.cols = pa.rows;
+    ba.rows_only = 1;
     ba.order = reinterpret_cast<int*>(w + cb + (size_t)g->nz * cap * beam_record_bytes());
     hipError_t e = launch_pbeam_compact(pa, g->dtype, stream);
     if (e == hipSuccess) e = launch_beam_sum(ba, g->dtype, omegas, nw, out, stream);

@@ -181,6 +181,7 @@ struct BeamArgs {
     void* rows;       // row records
     void* cols;       // column records
     int* order;       // per line, cap entries: the record indices in the order of their keys
+    int rows_only = 0;  // the column lists are empty (the depth march's sums): no column pass
 };
 hipError_t launch_beam_compact(const BeamArgs& a, int dtype, hipStream_t s);
 // Beam records of the depth march (rows = levels; see beam.hip).
