@@ -275,6 +275,8 @@ def test_migration_arguments_are_validated():
     assert L.egb_born_data(ctypes.byref(eg), P(256), 0, om, 2, P(256), P(256), P(256), big, None) == egb.EGB_EINVAL
     assert L.egb_born_data(ctypes.byref(eg), P(256), 4, bad, 2, P(256), P(256), P(256), big, None) == egb.EGB_EINVAL
     assert L.egb_born_data(ctypes.byref(eg), P(256), 4, om, 2, P(256), P(256), None, big, None) == egb.EGB_EINVAL
+    # frequencies are a grid dimension of the split kernel: at most 65535
+    assert L.egb_born_data(ctypes.byref(eg), P(256), 4, om, 70000, P(256), P(256), P(256), big, None) == egb.EGB_EUNSUPPORTED
     # the workspace: partial sums of the split over image points
     nb = egb.egb_born_workspace_size(eg, 4, 2)
     assert nb > 0 and nb % (4 * 4 * 2 * 2 * 8) == 0

@@ -34,9 +34,10 @@ def egb():
 @pytest.mark.parametrize("dtype,ns,nw,nx,nz", [("f64", 5, 3, 23, 19), ("f32", 37, 35, 40, 33),
                                              ("f32", 64, 4, 64, 64), ("f64", 1, 1, 9, 8)])
 def test_born_data_and_image_parity(dtype, ns, nw, nx, nz):
-    """Seeded random Green's functions: ragged source tiles (37 of 16-wide
-    tiles), more frequencies than one launch takes (35 > 32), the maximum of
-    64 surface points, a single point and frequency."""
+    """Seeded random Green's functions: ragged source tiles (37 points: two
+    32-wide tiles, the image on its general path), more frequencies than one
+    launch takes (35 > 32), the maximum of 64 surface points, a single point
+    and frequency.  A second call gives the same bits."""
     e = egb()
     rng = np.random.default_rng(1000 * ns + nw)
     g = W.Grid(nx=nx, nz=nz, nth=8, dx=12.5, dz=10.0)
@@ -53,9 +54,13 @@ def test_born_data_and_image_parity(dtype, ns, nw, nx, nz):
     err = np.abs(dg - do).max() / np.abs(do).max()
     log(f"born {dtype} ns={ns} nw={nw} {nx}x{nz}: {err:.2e}")
     assert err < 1e-11
+    # the split over image points adds its partial sums in a fixed order
+    assert torch.equal(d, e.egb_born_data(eg, G, om, torch.as_tensor(m, device=DEV)))
     # the image of arbitrary data (not only Born data)
     dr = rng.standard_normal((nw, ns, ns, 2))
-    img = e.egb_migrate(eg, G, om, torch.as_tensor(dr, device=DEV)).cpu().numpy()
+    img_t = e.egb_migrate(eg, G, om, torch.as_tensor(dr, device=DEV))
+    assert torch.equal(img_t, e.egb_migrate(eg, G, om, torch.as_tensor(dr, device=DEV)))
+    img = img_t.cpu().numpy()
     io = MG.migrate(Gc, dr[..., 0] + 1j * dr[..., 1], om, g.dx * g.dz)
     err = np.abs(img - io).max() / np.abs(io).max()
     log(f"image {dtype}: {err:.2e}")
