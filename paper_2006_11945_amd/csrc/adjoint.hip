@@ -480,15 +480,22 @@ __device__ __forceinline__ void adj_tile(const AdjStageArgs& a, int tile, int x0
                 add_to(gv + 2 * g.stride, (R)(-kt) * Wt);
             }
             __syncthreads();
-            // sum the slots aimed at the own cell
-            double t0 = 0.0, t1 = 0.0;
+            // sum the slots aimed at the own cell (all 28 reads issued
+            // before the sums, which keep their order)
+            R sz0[NSLOT], st0[NSLOT], sz1[NSLOT], st1[NSLOT];
 #pragma unroll
             for (int j = 0; j < NSLOT; ++j) {
                 const int zsrc = tz - (j - 3), tsrc = tk - (j - 3);
-                t0 += (double)sm.cz[j * S::ZPL + tk * S::CZW + zsrc + 3] +
-                      (double)sm.ct[j * S::TPL + (tsrc + 3) * TZ + tz];
-                t1 += (double)sm.cz[(NSLOT + j) * S::ZPL + tk * S::CZW + zsrc + 3] +
-                      (double)sm.ct[(NSLOT + j) * S::TPL + (tsrc + 3) * TZ + tz];
+                sz0[j] = sm.cz[j * S::ZPL + tk * S::CZW + zsrc + 3];
+                st0[j] = sm.ct[j * S::TPL + (tsrc + 3) * TZ + tz];
+                sz1[j] = sm.cz[(NSLOT + j) * S::ZPL + tk * S::CZW + zsrc + 3];
+                st1[j] = sm.ct[(NSLOT + j) * S::TPL + (tsrc + 3) * TZ + tz];
+            }
+            double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+            for (int j = 0; j < NSLOT; ++j) {
+                t0 += (double)sz0[j] + (double)st0[j];
+                t1 += (double)sz1[j] + (double)st1[j];
             }
             a0[3] += (R)(t0 + cb * (double)cm0);
             a1[3] += (R)(t1 + cb * cm1);
