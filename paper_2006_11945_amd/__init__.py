@@ -745,12 +745,32 @@ class TravelTime(torch.autograd.Function):
         egb_pick_adjoint(eg, d["final"], d["rx"], tb, lam)
         wadj = alloc_bytes(workspace_size(eg, EGB_OP_ADJOINT), dev)
         if d["arch"] is not None:  # every step's phi1 and psi are resident
-            st = d["final"].clone()
-            v = state_views(eg, st)
-            for i in reversed(range(d["nsteps"])):
-                v["phi1"].copy_(d["arch"][0][i])
-                v["psi"].copy_(d["arch"][1][i])
-                egb_adjoint_step(eg, d["vel3d"], src, d["bdata"], st, lam, gvel, bfold, wadj, d["dt"])
+            # two state buffers: step i - 1's planes are copied into one on a
+            # side stream while the adjoint step of i reads the other
+            main = torch.cuda.current_stream(dev)
+            side = torch.cuda.Stream(dev)
+            st = [d["final"].clone(), d["final"].clone()]
+            views = [state_views(eg, b) for b in st]
+            ready = [torch.cuda.Event(), torch.cuda.Event()]
+            done = [torch.cuda.Event(), torch.cuda.Event()]
+
+            def stage(i, b):
+                side.wait_event(done[b])  # the step that last read buffer b has ended
+                with torch.cuda.stream(side):
+                    views[b]["phi1"].copy_(d["arch"][0][i])
+                    views[b]["psi"].copy_(d["arch"][1][i])
+                ready[b].record(side)
+
+            n = d["nsteps"]
+            if n > 0:
+                stage(n - 1, 0)
+            for k, i in enumerate(reversed(range(n))):
+                b = k % 2
+                if i > 0:
+                    stage(i - 1, 1 - b)
+                main.wait_event(ready[b])
+                egb_adjoint_step(eg, d["vel3d"], src, d["bdata"], st[b], lam, gvel, bfold, wadj, d["dt"])
+                done[b].record(main)
         for start, ck in reversed(d["ckpts"]):
             n = min(d["K"], d["nsteps"] - start)
             states = [ck]
