@@ -196,31 +196,21 @@ __device__ inline VelA velocity_and_drt(const VJet& J, double theta) {
 //                                      u = (3 s2 - s1, s2 + s3, s4 - 3 s3),
 //   omega_k proportional to d_k / (eps + beta_k)^2,  d = (0.1, 0.6, 0.3),
 // which is the textbook form (q_k - v3 = r_k / 6) with fewer operations.
-// The weights use b_k = 4 (eps + beta_k) 2^(-2e), 2^e ~ max|v|, computed
-// from s_j 2^(-e) (exact power-of-two scaling): every intermediate stays
-// within [1e-6, 1e5] whatever the scale of v, and the weights over the common
-// denominator b0^2 b1^2 b2^2 need a single reciprocal.  All differences zero
-// gives W = 0 (eps is then taken with max|v| 2^(-e) = 1/2, which keeps the
-// denominator positive).
+// With b_k = 4 (eps + beta_k) the weights relative to omega_0 are
+// (1, 6 (b0/b1)^2, 3 (b0/b2)^2): every b_k lies between 4 eps and a few tens
+// of max v^2, so each ratio lies within about 1e-7 .. 1e7 whatever the scale
+// of v (no rescaling), at the cost of three reciprocals.  eps is kept at
+// least the smallest normal number, so that all differences zero give W = 0.
 template <typename R>
 __device__ __forceinline__ R weno5(R v1, R v2, R v3, R v4, R v5) {
     constexpr bool F = sizeof(R) == 4;
     const R m = fmax(fmax(fmax(fmax(fabs(v1), fabs(v2)), fabs(v3)), fabs(v4)), fabs(v5));
-    int e;
-    R mm;
-    if constexpr (F) {
-        e = __builtin_amdgcn_frexp_expf(m);
-        mm = fmaxf(__builtin_amdgcn_frexp_mantf(m), 0.5f);
-    } else {
-        e = __builtin_amdgcn_frexp_exp(m);
-        mm = fmax(__builtin_amdgcn_frexp_mant(m), 0.5);
-    }
-    auto sc = [&](R x) {
-        if constexpr (F) return __builtin_amdgcn_ldexpf(x, -e);
-        else return __builtin_amdgcn_ldexp(x, -e);
+    auto rcp = [](R x) {
+        if constexpr (F) return __builtin_amdgcn_rcpf(x);
+        else return (R)1 / x;
     };
-    const R eps4 = ((R)4e-6 * mm) * mm;
-    const R s1 = sc(v2 - v1), s2 = sc(v3 - v2), s3 = sc(v4 - v3), s4 = sc(v5 - v4);
+    const R eps4 = fmax(((R)4e-6 * m) * m, F ? (R)1.17549435e-38 : (R)2.2250738585072014e-308);
+    const R s1 = v2 - v1, s2 = v3 - v2, s3 = v4 - v3, s4 = v5 - v4;
     const R t0 = s2 - s1, u0 = (R)3 * s2 - s1;
     const R t1 = s3 - s2, u1 = s2 + s3;
     const R t2 = s4 - s3, u2 = s4 - (R)3 * s3;
@@ -228,16 +218,12 @@ __device__ __forceinline__ R weno5(R v1, R v2, R v3, R v4, R v5) {
     const R b0 = (c13 * t0) * t0 + (u0 * u0 + eps4);
     const R b1 = (c13 * t1) * t1 + (u1 * u1 + eps4);
     const R b2 = (c13 * t2) * t2 + (u2 * u2 + eps4);
-    // weights over the common denominator: (1, 6, 3) x products of the other two b^2
-    const R G = ((R)3 * b0) * b0, E1 = b1 * b1, E2 = b2 * b2;
-    const R w0 = E1 * E2, w2 = G * E1, H = G * E2, w1 = H + H;
+    const R q1 = b0 * rcp(b1), q2 = b0 * rcp(b2);
+    const R w1 = ((R)6 * q1) * q1, w2 = ((R)3 * q2) * q2;
     const R r0 = (R)5 * s2 - (R)2 * s1, r1 = s2 + (R)2 * s3, r2 = (R)4 * s3 - s4;
-    const R num = w0 * r0 + w1 * r1 + w2 * r2;
-    const R den = (w0 + w1) + w2;
-    R r;
-    if constexpr (F) r = __builtin_amdgcn_ldexpf(num * __builtin_amdgcn_rcpf(den), e);
-    else r = __builtin_amdgcn_ldexp(num / den, e);
-    return v3 + r * (R)(1.0 / 6.0);
+    const R num = r0 + w1 * r1 + w2 * r2;
+    const R den = ((R)1 + w1) + w2;
+    return v3 + (num * rcp(den)) * (R)(1.0 / 6.0);
 }
 
 // WENO5 value (undivided) and its gradient g[k] = dW/dv_{k+1}, by reverse-mode
