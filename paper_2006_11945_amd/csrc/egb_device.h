@@ -227,13 +227,14 @@ __device__ __forceinline__ R weno5(R v1, R v2, R v3, R v4, R v5) {
 }
 
 // WENO5 value (undivided) and its gradient g[k] = dW/dv_{k+1}, by reverse-mode
-// differentiation of the formula above.  W is positively 1-homogeneous in v,
-// so the gradient is that of the power-of-two normalised differences a:
-// with omega_k = w_k / D, Rb = sum omega_k r_k and W' = a3 + Rb / 6,
-//   dW'/db_k = -omega_k (r_k - Rb) / (3 b_k)   (b_k enters squared in w),
-//   dW'/dr_k = omega_k / 6,  dW'/deps4 = sum_k dW'/db_k,
-// then back through t, u, r, s to a; eps4 = 4e-6 a_J^2 for the first entry J
-// of largest magnitude.  When all differences vanish W and the gradient are 0.
+// differentiation of the formula above (the same weights relative to
+// omega_0, no rescaling): with omega_k = w_k / D, Rb = sum omega_k r_k and
+// W = v3 + Rb / 6,
+//   dW/db_k = -omega_k (r_k - Rb) / (3 b_k)   (b_k enters squared in w),
+//   dW/dr_k = omega_k / 6,  dW/deps4 = sum_k dW/db_k,
+// then back through t, u, r, s to v; eps4 = 4e-6 v_J^2 for the first entry J
+// of largest magnitude (its floor, the smallest normal number, has no
+// derivative).  When all differences vanish W and the gradient are 0.
 template <typename R>
 __device__ __forceinline__ R weno5_grad(R v1, R v2, R v3, R v4, R v5, R (&g)[5]) {
     constexpr bool F = sizeof(R) == 4;
@@ -241,21 +242,14 @@ __device__ __forceinline__ R weno5_grad(R v1, R v2, R v3, R v4, R v5, R (&g)[5])
     // first entry of largest magnitude (its index and value)
     const int J = fabs(v1) == m ? 0 : fabs(v2) == m ? 1 : fabs(v3) == m ? 2 : fabs(v4) == m ? 3 : 4;
     const R vJ = J == 0 ? v1 : J == 1 ? v2 : J == 2 ? v3 : J == 3 ? v4 : v5;
-    int e;
-    if constexpr (F) e = __builtin_amdgcn_frexp_expf(m);
-    else e = __builtin_amdgcn_frexp_exp(m);
-    auto sc = [&](R x) {
-        if constexpr (F) return __builtin_amdgcn_ldexpf(x, -e);
-        else return __builtin_amdgcn_ldexp(x, -e);
-    };
     auto rcp = [](R x) {
         if constexpr (F) return __builtin_amdgcn_rcpf(x);
         else return (R)1 / x;
     };
-    const R a1 = sc(v1), a2 = sc(v2), a3 = sc(v3), a4 = sc(v4), a5 = sc(v5), aJ = sc(vJ);
-    // aJ^2 lies in [1/4, 1) unless all differences vanish (then 1/4 keeps D > 0)
-    const R eps4 = (R)4e-6 * fmax(aJ * aJ, (R)0.25);
-    const R s1 = a2 - a1, s2 = a3 - a2, s3 = a4 - a3, s4 = a5 - a4;
+    constexpr R tiny = F ? (R)1.17549435e-38 : (R)2.2250738585072014e-308;
+    const R e4 = ((R)4e-6 * m) * m;
+    const R eps4 = fmax(e4, tiny);
+    const R s1 = v2 - v1, s2 = v3 - v2, s3 = v4 - v3, s4 = v5 - v4;
     const R t0 = s2 - s1, u0 = (R)3 * s2 - s1;
     const R t1 = s3 - s2, u1 = s2 + s3;
     const R t2 = s4 - s3, u2 = s4 - (R)3 * s3;
@@ -263,15 +257,16 @@ __device__ __forceinline__ R weno5_grad(R v1, R v2, R v3, R v4, R v5, R (&g)[5])
     const R b0 = (c13 * t0) * t0 + (u0 * u0 + eps4);
     const R b1 = (c13 * t1) * t1 + (u1 * u1 + eps4);
     const R b2 = (c13 * t2) * t2 + (u2 * u2 + eps4);
-    const R G = ((R)3 * b0) * b0, E1 = b1 * b1, E2 = b2 * b2;
-    const R w0 = E1 * E2, w2 = G * E1, H = G * E2, w1 = H + H;
-    const R rD = rcp((w0 + w1) + w2);
-    const R o0 = w0 * rD, o1 = w1 * rD, o2 = w2 * rD;
+    const R rb0 = rcp(b0), rb1 = rcp(b1), rb2 = rcp(b2);
+    const R q1 = b0 * rb1, q2 = b0 * rb2;
+    const R w1 = ((R)6 * q1) * q1, w2 = ((R)3 * q2) * q2;
+    const R rD = rcp(((R)1 + w1) + w2);
+    const R o0 = rD, o1 = w1 * rD, o2 = w2 * rD;
     const R r0 = (R)5 * s2 - (R)2 * s1, r1 = s2 + (R)2 * s3, r2 = (R)4 * s3 - s4;
     const R Rb = o0 * r0 + o1 * r1 + o2 * r2;
-    const R W = a3 + Rb * (R)(1.0 / 6.0);
-    // backward: beta_k = omega_k (r_k - Rb) / b_k, dW'/db_k = -beta_k / 3
-    const R be0 = o0 * (r0 - Rb) * rcp(b0), be1 = o1 * (r1 - Rb) * rcp(b1), be2 = o2 * (r2 - Rb) * rcp(b2);
+    const R W = v3 + Rb * (R)(1.0 / 6.0);
+    // backward: beta_k = omega_k (r_k - Rb) / b_k, dW/db_k = -beta_k / 3
+    const R be0 = o0 * (r0 - Rb) * rb0, be1 = o1 * (r1 - Rb) * rb1, be2 = o2 * (r2 - Rb) * rb2;
     constexpr R kt = (R)(-2.0 * 13.0 / 9.0), ku = (R)(-2.0 / 3.0);  // d b / d t = 2 c t, d b / d u = 2 u
     const R tb0 = kt * t0 * be0, tb1 = kt * t1 * be1, tb2 = kt * t2 * be2;
     const R ub0 = ku * u0 * be0, ub1 = ku * u1 * be1, ub2 = ku * u2 * be2;
@@ -280,15 +275,14 @@ __device__ __forceinline__ R weno5_grad(R v1, R v2, R v3, R v4, R v5, R (&g)[5])
     const R s2b = tb0 + (R)3 * ub0 - tb1 + ub1 + (o0 * (R)5 + o1) * (R)(1.0 / 6.0);
     const R s3b = tb1 + ub1 - tb2 - (R)3 * ub2 + (o1 + o2 * (R)2) * (R)(1.0 / 3.0);
     const R s4b = tb2 + ub2 - o2 * (R)(1.0 / 6.0);
-    const R ej = epsb * (R)8e-6 * aJ;
+    const R ej = e4 >= tiny ? epsb * (R)8e-6 * vJ : (R)0;
     const bool ok = m > (R)0;
     g[0] = ok ? -s1b + (J == 0 ? ej : (R)0) : (R)0;
     g[1] = ok ? s1b - s2b + (J == 1 ? ej : (R)0) : (R)0;
     g[2] = ok ? (R)1 + s2b - s3b + (J == 2 ? ej : (R)0) : (R)0;
     g[3] = ok ? s3b - s4b + (J == 3 ? ej : (R)0) : (R)0;
     g[4] = ok ? s4b + (J == 4 ? ej : (R)0) : (R)0;
-    if constexpr (F) return ok ? __builtin_amdgcn_ldexpf(W, e) : (R)0;
-    else return ok ? __builtin_amdgcn_ldexp(W, e) : (R)0;
+    return ok ? W : (R)0;
 }
 
 // ------------------------------------------------------------ dual numbers
