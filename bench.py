@@ -142,7 +142,7 @@ def batched_vs_sequential(nprob, nsteps, lo=128, hi=384, tune=True):
             "batched_over_sequential": t_seq / t_batch}
 
 
-def adjoint_vs_forward(nsrc, nsteps, n=256):
+def adjoint_vs_forward(nsrc, nsteps, n=256, tune=True):
     """Traveltime misfit at 128 receivers for `nsrc` of the 16 sources on the
     VTI medium: forward (kinematic march keeping the states the backward
     sweep needs + pick) and backward (pick adjoint, recomputation, adjoint steps, medium
@@ -169,6 +169,16 @@ def adjoint_vs_forward(nsrc, nsteps, n=256):
     # and step) when that takes at most half of the free memory, else a
     # checkpoint every 16 steps and the segments recomputed
     g0 = probs[0].grid
+    tuned = None
+    if tune:  # launch shapes of the grid's full-plane and kinematic stages (the library keeps them per grid shape)
+        s = egb.Solver(probs[0], dev)
+        s.velocity()
+        s.init()
+        tuned = {}
+        for name, op in (("full_plane", egb.EGB_TUNE_STEP), ("kinematic", egb.EGB_TUNE_KINEMATIC)):
+            s.tune(op=op, reps=2)
+            tuned[name] = egb.egb_get_launch(s.eg, op)
+        del s
     need = nsteps * g0.nx * g0.nz * g0.nth * (4 + 8)
     K = 0 if need <= 0.5 * torch.cuda.mem_get_info(dev)[0] else 16
     t_fwd = t_bwd = t_plain = t_first = 0.0
@@ -210,7 +220,7 @@ def adjoint_vs_forward(nsrc, nsteps, n=256):
         del s, ts
         torch.cuda.empty_cache()
     cu = probs[0].grid.ncell * nsteps * nsrc
-    return {"sources": nsrc, "rk3_steps": nsteps, "receivers": 128,
+    return {"sources": nsrc, "rk3_steps": nsteps, "receivers": 128, "tuned_launch": tuned,
             "states_kept": "every step's phi1 and psi resident" if K == 0 else f"a checkpoint every {K} steps",
             "archive_GB": need / 1e9 if K == 0 else 0.0,
             "forward_s": t_fwd, "backward_s": t_bwd, "plain_forward_s": t_plain, "first_call_forward_s": t_first,
@@ -705,7 +715,7 @@ def main():
                                                      tune=not args.no_tune)
         torch.cuda.empty_cache()
     if args.adjoint_sources > 0 and budget_ok("adjoint", 8 + 16 * args.adjoint_sources):
-        res["adjoint"] = adjoint_vs_forward(args.adjoint_sources, 600, 256)
+        res["adjoint"] = adjoint_vs_forward(args.adjoint_sources, 600, 256, tune=not args.no_tune)
         torch.cuda.empty_cache()
     if args.vti_leg > 0 and args.workload != "vti256" and budget_ok("vti256", 6 + 2 * args.vti_leg):
         pv = make_workload("vti256")
