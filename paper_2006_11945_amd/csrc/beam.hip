@@ -22,8 +22,12 @@
 // Pass 2 (k_beam_line): for every output cell and frequency,
 //   G += amp exp(i omega T),  T = psi + p d + M d^2 / 2,
 // skipping beams with omega Im(M) d^2 / 2 > 16, and G is scaled by i/(4 pi).
-// A wavefront owns one row (or column) and walks its record list with
-// uniform loads; lanes span the output cells of that line.
+// A wavefront owns 64 output cells of one row (or column) and walks the
+// line's records in key order, gathered 64 at a time into LDS and read by
+// all lanes from one address; equally spaced frequencies rotate the term by
+// exp(i step T) from one frequency to the next (chunks of 32 in FP32, else
+// 16 per launch).  The depth march's beams (rows only) go through the
+// same line sums after k_pbeam_compact.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
