@@ -32,12 +32,14 @@ def egb():
 
 
 @pytest.mark.parametrize("dtype,ns,nw,nx,nz", [("f64", 5, 3, 23, 19), ("f32", 37, 35, 40, 33),
-                                             ("f32", 64, 4, 64, 64), ("f64", 1, 1, 9, 8)])
+                                             ("f32", 64, 4, 64, 64), ("f64", 1, 1, 9, 8), ("f32", 32, 33, 48, 40)])
 def test_born_data_and_image_parity(dtype, ns, nw, nx, nz):
     """Seeded random Green's functions: ragged source tiles (37 points: two
     32-wide tiles, the image on its general path), more frequencies than one
     launch takes (35 > 32), the maximum of 64 surface points, a single point
-    and frequency.  A second call gives the same bits."""
+    and frequency, exactly one full 32 x 32 tile (both contractions on the
+    matrix cores with every lane's tile entries in use).  A second call gives
+    the same bits."""
     e = egb()
     rng = np.random.default_rng(1000 * ns + nw)
     g = W.Grid(nx=nx, nz=nz, nth=8, dx=12.5, dz=10.0)
