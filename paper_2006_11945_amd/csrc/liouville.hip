@@ -239,15 +239,28 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
         cvt = bload<R>(rV, cR, EGB_VT * SP);
     }
 
+    // The queue is a ring over each round of seven x steps: in step RT of a
+    // round, entry j (position x - 3 + j) sits in q[.][(j + RT) % 7], so
+    // advancing the queue writes only the new entry x + 4 (into the slot of
+    // x - 3) instead of moving six entries per plane.
     int buf = 0;
-    for (int x = x0; x < x1; ++x, buf ^= 1) {
+    auto step = [&](const int x, auto rot) {
+        constexpr int RT = decltype(rot)::value;
+        R qx[NP][7];
+        double qpx[7];
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+#pragma unroll
+            for (int f = 0; f < NP; ++f) qx[f][j] = q[f][(j + RT) % 7];
+            qpx[j] = qp[(j + RT) % 7];
+        }
         const int wb = buf * S::BUF;
         // slice x into LDS: own column from the queue, halo from its loads
         if (zin) {
             R own[NP];
 #pragma unroll
-            for (int f = 0; f < NP; ++f) own[f] = q[f][3];
-            lds_put(sm, wb + me, own, qp[3]);
+            for (int f = 0; f < NP; ++f) own[f] = qx[f][3];
+            lds_put(sm, wb + me, own, qpx[3]);
         }
         if (has_halo) {
             R hv[NP];
@@ -296,8 +309,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
                 p0 = bload<double>(pU0, c8, 0);
             } else {
 #pragma unroll
-                for (int f = 0; f < NP; ++f) u0[f] = q[f][3];
-                p0 = qp[3];
+                for (int f = 0; f < NP; ++f) u0[f] = qx[f][3];
+                p0 = qpx[3];
             }
             if constexpr (!KIN) {
 #pragma unroll
@@ -308,17 +321,17 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
             // the double psi once
             R acc[NP], convp;
 #pragma unroll
-            for (int f = 0; f < NP; ++f) acc[f] = (R)cb * q[f][3];
-            double accp = cb * qp[3] + cdt;
+            for (int f = 0; f < NP; ++f) acc[f] = (R)cb * qx[f][3];
+            double accp = cb * qpx[3] + cdt;
             // x: upwind stencil from the register queue
             auto xpart = [&](auto dir) {
                 constexpr int D = decltype(dir)::value;
 #pragma unroll
                 for (int f = 0; f < NP; ++f)
-                    acc[f] -= gx * deriv<R>(f, upw<D>(q[f], 0, mx), upw<D>(q[f], 1, mx), upw<D>(q[f], 2, mx),
-                                            q[f][3], upw<D>(q[f], 4, mx), upw<D>(q[f], 5, mx));
-                convp = gx * weno_up<R>(upw<D>(qp, 0, mx), upw<D>(qp, 1, mx), upw<D>(qp, 2, mx), qp[3],
-                                        upw<D>(qp, 4, mx), upw<D>(qp, 5, mx));
+                    acc[f] -= gx * deriv<R>(f, upw<D>(qx[f], 0, mx), upw<D>(qx[f], 1, mx), upw<D>(qx[f], 2, mx),
+                                            qx[f][3], upw<D>(qx[f], 4, mx), upw<D>(qx[f], 5, mx));
+                convp = gx * weno_up<R>(upw<D>(qpx, 0, mx), upw<D>(qpx, 1, mx), upw<D>(qpx, 2, mx), qpx[3],
+                                        upw<D>(qpx, 4, mx), upw<D>(qpx, 5, mx));
             };
             if (__all(mx)) xpart(std::integral_constant<int, 0>{});
             else if (!__any(mx)) xpart(std::integral_constant<int, 1>{});
@@ -330,9 +343,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
                 const int a4 = meB + step, a5 = meB + 2 * step;
 #pragma unroll
                 for (int f = 0; f < NP; ++f)
-                    acc[f] -= gR * deriv<R>(f, lds_r<R>(sm, a0, f), lds_r<R>(sm, a1, f), lds_r<R>(sm, a2, f), q[f][3],
+                    acc[f] -= gR * deriv<R>(f, lds_r<R>(sm, a0, f), lds_r<R>(sm, a1, f), lds_r<R>(sm, a2, f), qx[f][3],
                                             lds_r<R>(sm, a4, f), lds_r<R>(sm, a5, f));
-                convp += gR * weno_up<R>(lds_psi<NP>(sm, a0), lds_psi<NP>(sm, a1), lds_psi<NP>(sm, a2), qp[3],
+                convp += gR * weno_up<R>(lds_psi<NP>(sm, a0), lds_psi<NP>(sm, a1), lds_psi<NP>(sm, a2), qpx[3],
                                          lds_psi<NP>(sm, a4), lds_psi<NP>(sm, a5));
             };
             lpart(mz ? WS : -WS, gz);
@@ -340,12 +353,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
             accp -= (double)convp;
             if constexpr (!KIN) {
                 const R A11 = cdtr * Am[0], A12 = cdtr * Am[1], A21 = cdtr * Am[2], A22 = cdtr * Am[3];
-                acc[EGB_RE_C] += A11 * q[EGB_RE_C][3] + A12 * q[EGB_RE_B][3];
-                acc[EGB_RE_B] += A21 * q[EGB_RE_C][3] + A22 * q[EGB_RE_B][3];
-                acc[EGB_IM_C] += A11 * q[EGB_IM_C][3] + A12 * q[EGB_IM_B][3];
-                acc[EGB_IM_B] += A21 * q[EGB_IM_C][3] + A22 * q[EGB_IM_B][3];
-                const R rc = q[EGB_RE_C][3], ic = q[EGB_IM_C][3], rb = q[EGB_RE_B][3], ib = q[EGB_IM_B][3];
-                acc[EGB_PHASE] += A12 * ((ib * rc - rb * ic) / (rc * rc + ic * ic));
+                // the products are fused explicitly, so that the rounding
+                // does not depend on how the compiler contracts them
+                const R rc = qx[EGB_RE_C][3], ic = qx[EGB_IM_C][3], rb = qx[EGB_RE_B][3], ib = qx[EGB_IM_B][3];
+                acc[EGB_RE_C] += fma(A11, rc, A12 * rb);
+                acc[EGB_RE_B] += fma(A21, rc, A22 * rb);
+                acc[EGB_IM_C] += fma(A11, ic, A12 * ib);
+                acc[EGB_IM_B] += fma(A21, ic, A22 * ib);
+                acc[EGB_PHASE] += A12 * (fma(rc, ib, -(rb * ic)) / fma(ic, ic, rc * rc));
             }
             if constexpr (STAGE != 0) {
 #pragma unroll
@@ -358,19 +373,32 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
                 bstore(ball ? p0 : accp, pUo, c8, 0);
             }
         }
-        // shift the queue
+        // advance the queue: entry x + 4 takes the slot of x - 3
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-#pragma unroll
-            for (int f = 0; f < NP; ++f) q[f][j] = q[f][j + 1];
-            qp[j] = qp[j + 1];
-        }
-#pragma unroll
-        for (int f = 0; f < NP; ++f) q[f][6] = qn[f];
-        qp[6] = qpn;
+        for (int f = 0; f < NP; ++f) q[f][RT] = qn[f];
+        qp[RT] = qpn;
         cvx = nvx;
         cvz = nvz;
         cvt = nvt;
+        buf ^= 1;
+        // keep each step's schedule to itself (as in a rolled loop), so that
+        // the register use stays that of one step
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    for (int x = x0; x < x1; x += 7) {
+        step(x, std::integral_constant<int, 0>{});
+        if (x + 1 >= x1) break;
+        step(x + 1, std::integral_constant<int, 1>{});
+        if (x + 2 >= x1) break;
+        step(x + 2, std::integral_constant<int, 2>{});
+        if (x + 3 >= x1) break;
+        step(x + 3, std::integral_constant<int, 3>{});
+        if (x + 4 >= x1) break;
+        step(x + 4, std::integral_constant<int, 4>{});
+        if (x + 5 >= x1) break;
+        step(x + 5, std::integral_constant<int, 5>{});
+        if (x + 6 >= x1) break;
+        step(x + 6, std::integral_constant<int, 6>{});
     }
 }
 
