@@ -18,12 +18,13 @@
 //
 // Work decomposition.  A block owns a (z, theta) tile of 64 x TK cells and
 // walks a chunk of x.  Each thread keeps the seven x-neighbours of its own
-// (theta, z) column in registers (a queue shifted once per x step), so the
-// x-stencil costs no extra memory traffic.  The current x slice of the
-// tile, with a 3-cell halo in z (ghosts from the boundary data) and in theta
-// (periodic), sits in LDS (double buffered, one barrier per x step); the z-
-// and theta-stencils read it at immediate offsets.  Blocks are numbered so
-// that consecutive tiles land on the same XCD (shared L2 for the theta halo).
+// (theta, z) column in registers (a ring that takes one new entry per x
+// step), so the x-stencil costs no extra memory traffic.  The current x
+// slice of the tile, with a 3-cell halo in z (ghosts from the boundary data)
+// and in theta (periodic), sits in LDS (double buffered, one barrier per x
+// step); the z- and theta-stencils read it at immediate offsets.  Blocks are
+// numbered so that consecutive tiles land on the same XCD (shared L2 for the
+// theta halo).
 #include <hip/hip_runtime.h>
 #include <stdlib.h>
 
@@ -180,10 +181,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileArgs& t
     }
     const bool z_end = tzi == 0 || tzi == t.ntz - 1 || (tzi + 1) * TZ + 3 > g.nz;  // block-uniform
 
-    // queue of the column's x-neighbours: q[f][j] at x - 3 + j, from the
-    // state inside the grid and from the boundary data beyond either end
-    // (position p: slot p + 3 before x = 0, p - nx + 3 past nx - 1; a slot
-    // past nx + 2 is never used and clamped)
+    // queue of the column's x-neighbours (at x = x0: q[f][j] at x0 - 3 + j;
+    // a ring afterwards, see the x loop), entries from the state inside the
+    // grid and from the boundary data beyond either end (position p: slot
+    // p + 3 before x = 0, p - nx + 3 past nx - 1; a slot past nx + 2 is
+    // never used and clamped)
     auto x_entry = [&](int p, R (&v)[NP], double& vp) {
         const bool gh = p < 0 || p >= g.nx;  // block-uniform
         const auto r = gh ? rB : rUi;
